@@ -1,0 +1,2 @@
+"""FP64 CPU oracle (test infrastructure only; never imported by the GPU product path)."""
+from .gp_oracle import *  # noqa: F401,F403
