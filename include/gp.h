@@ -1,0 +1,145 @@
+/*
+ * gp.h -- C ABI of libgpdbec: one split-step semi-implicit Crank-Nicolson time step
+ * of the dipolar Gross-Pitaevskii equation on an AMD Instinct MI355X (gfx950).
+ *
+ * Method (Loncar et al., CPC, arXiv:1601.04640, program summary "Nature of problem"
+ * and "Solution method"; function roles from "Summary of revisions"):
+ *   the GP equation with contact and dipolar interactions in a harmonic anisotropic
+ *   trap, in 2D (x-y or x-z plane) or 3D, propagated in imaginary time (stationary
+ *   states) or real time (dynamics) by split-step Crank-Nicolson; the dipolar
+ *   potential is a momentum-space product (convolution theorem).  One step is
+ *     n = |psi|^2;  Phi = F^-1[U(k) F[n]]                      (calcpsidd2)
+ *     psi <- psi exp(-eps dt (V + g_c n + g_dd Phi))            (calcnu)
+ *     CN sweeps along x, y, z, A = eps dt/(4 h^2), Dirichlet    (calclux/y/z)
+ *     imaginary time: psi <- psi/sqrt(sum|psi|^2 dV)           (calcnorm)
+ *   with eps = 1 (imaginary time) or i (real time), and norm, energy, chemical
+ *   potential and rms sizes reduced in FP64 (calcnorm, calcmuen, calcrms).
+ *   U(k) = (3 kz^2/k^2 - 1) b(kR) in 3D (dipoles along z, spherical cutoff R);
+ *   quasi-2D kernels are its transverse Gaussian averages; g_c = g in 3D and
+ *   g/(sqrt(2 pi) d) in 2D with d = 1/sqrt(omega_perp).
+ *
+ * Layout: every grid is stored x fastest.  3D index (k*ny + j)*nx + i, 2D XY
+ *   j*nx + i, 2D XZ k*nx + i.  Complex values are interleaved (re, im).  Grid
+ *   coordinates are x_i = (i - n/2) h; the first and last point of every axis are
+ *   Dirichlet boundary points (zero).
+ *
+ * Memory ownership: the caller allocates one device workspace of at least
+ *   gp_workspace_bytes() bytes (256-byte aligned) and owns the HIP stream; the library
+ *   allocates no device memory, owns only the host-side context, and never frees
+ *   the workspace.  All device work of a context is enqueued on its stream.
+ *
+ * Precision: GP_FP64 keeps every field in double.  GP_FP32_MIXED keeps psi, V, the
+ *   spectrum, the kernel table and all bulk arithmetic (FFT, multiply, phase, CN) in
+ *   float; norm/energy/mu/rms reductions and the imaginary-time renormalisation
+ *   factor are accumulated and computed in double.
+ *
+ * Errors: every call returns a gp_status; no call prints, throws or aborts.  Steps
+ *   are asynchronous: a non-finite norm detected on the device sets a sticky flag
+ *   that the next synchronous call (gp_energy, gp_get_psi to host, gp_sync,
+ *   gp_history) reports as GP_E_NONFINITE.  A context is not thread-safe; distinct
+ *   contexts may be used from distinct threads.
+ */
+#ifndef GPDBEC_GP_H
+#define GPDBEC_GP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int gp_status;
+#define GP_OK            0
+#define GP_E_ARG        -1  /* bad pointer, non-positive dt/h, bad enum, workspace too small */
+#define GP_E_SIZE       -2  /* an axis is odd, < 8, > 512, or has a prime factor other than 2, 3, 5 */
+#define GP_E_DEVICE     -3  /* a HIP runtime call or kernel launch failed */
+#define GP_E_NONFINITE  -4  /* the wave function became NaN/Inf (or its norm underflowed to 0) */
+#define GP_E_STATE      -5  /* call out of order (e.g. stepping before gp_set_psi) */
+#define GP_E_NOMEM      -6  /* host-side allocation failed */
+
+typedef enum { GP_3D = 0, GP_2D_XY = 1, GP_2D_XZ = 2 } gp_geom;
+typedef enum { GP_FP64 = 0, GP_FP32_MIXED = 1 } gp_prec;
+
+/* Problem parameters.  In 2D XY the grid is (ny, nx) and nz, dz are ignored; lambda is
+ * the frozen transverse frequency (d = 1/sqrt(lambda)).  In 2D XZ the grid is (nz, nx)
+ * and ny, dy are ignored; nu is the frozen transverse frequency (d = 1/sqrt(nu)).
+ * cutoff_R <= 0 disables the spherical cutoff (3D only).  The trap is
+ * V = (gamma^2 x^2 + nu^2 y^2 + lambda^2 z^2)/2 restricted to the plane in 2D, unless
+ * replaced by gp_set_potential. */
+typedef struct gp_params {
+  int geom;                 /* gp_geom */
+  int nx, ny, nz;
+  double dx, dy, dz;
+  double dt;                /* > 0; the sign of time is set by the step call */
+  double gamma, nu, lambda; /* trap frequencies along x, y, z */
+  double g, gdd;            /* contact and dipolar couplings (3D units) */
+  double cutoff_R;
+  int prec;                 /* gp_prec */
+} gp_params;
+
+/* FP64 observables of one wave function.  rms[] = (x, y, z); the frozen axis of a 2D
+ * geometry reports 0.  e_int and e_dd already contain the 1/2; mu doubles them. */
+typedef struct gp_observables {
+  double norm, mu, energy, e_kin, e_pot, e_int, e_dd;
+  double rms[3];
+} gp_observables;
+
+typedef struct gp_ctx gp_ctx;
+
+/* Bytes of device workspace a context with these parameters needs.  Validates params
+ * exactly as gp_init does. */
+gp_status gp_workspace_bytes(const gp_params* params, size_t* bytes);
+
+/* Create a context.  dev_workspace: device pointer, >= gp_workspace_bytes, 256-byte
+ * aligned, owned by the caller and kept alive until gp_destroy.  hip_stream: a
+ * hipStream_t (NULL = the null stream).  Builds the FFT twiddles, the kernel table
+ * U(k)/N, the CN factor tables and the harmonic V on the device; psi is unset. */
+gp_status gp_init(const gp_params* params, void* dev_workspace, size_t ws_bytes,
+                  void* hip_stream, gp_ctx** out);
+gp_status gp_destroy(gp_ctx* ctx);
+const char* gp_status_string(gp_status status);
+
+/* Wave function I/O.  on_device = 0: host buffer of interleaved complex double.
+ * on_device = 1: device buffer of interleaved complex in the context precision
+ * (double for GP_FP64, float for GP_FP32_MIXED).  set: boundary points are zeroed;
+ * the input is otherwise used as is (not renormalised).  get to host synchronises. */
+gp_status gp_set_psi(gp_ctx* ctx, const void* psi, int on_device);
+gp_status gp_get_psi(gp_ctx* ctx, void* psi, int on_device);
+
+/* Replace the trap by an arbitrary real grid V (host: double; device: context
+ * precision), same layout as psi. */
+gp_status gp_set_potential(gp_ctx* ctx, const void* V, int on_device);
+
+/* Change the couplings (e.g. a quench g -> g').  Takes effect for later steps. */
+gp_status gp_set_couplings(gp_ctx* ctx, double g, double gdd);
+
+/* nsteps >= 0 steps in imaginary time (with renormalisation) / real time.
+ * Asynchronous.  Each step also reduces the FP64 observables of the state it starts
+ * from (kept in a history ring, see gp_history). */
+gp_status gp_step_imag(gp_ctx* ctx, int nsteps);
+gp_status gp_step_real(gp_ctx* ctx, int nsteps);
+
+/* Observables of the current psi (computes Phi of this psi).  Synchronous. */
+gp_status gp_energy(gp_ctx* ctx, gp_observables* out);
+
+/* Phi = F^-1[U F[|psi|^2]] of the current psi, WITHOUT the g_dd factor.
+ * on_device = 0: host buffer of double; 1: device buffer in context precision. */
+gp_status gp_dipolar_potential(gp_ctx* ctx, void* phi, int on_device);
+
+/* Observables of the states the most recent steps started from, oldest first.
+ * Copies min(max_records, available) records (at most gp_history_capacity()) to host
+ * memory; *count receives the number copied.  Synchronous. */
+gp_status gp_history(gp_ctx* ctx, gp_observables* out, int max_records, int* count);
+int gp_history_capacity(void);
+
+/* Wait for the context's stream; reports the sticky non-finite flag. */
+gp_status gp_sync(gp_ctx* ctx);
+
+/* Text of the HIP error behind the calling thread's most recent GP_E_DEVICE ("" if none).
+ * The pointer stays valid until the thread's next failing call. */
+const char* gp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GPDBEC_GP_H */

@@ -1,0 +1,294 @@
+"""Thin ctypes binding of libgpdbec (include/gp.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP kernels.
+PyTorch supplies the device workspace and the HIP stream.  If the shared library is
+missing this module raises; there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgpdbec.so")
+
+GP_OK = 0
+GP_E_ARG = -1
+GP_E_SIZE = -2
+GP_E_DEVICE = -3
+GP_E_NONFINITE = -4
+GP_E_STATE = -5
+GP_E_NOMEM = -6
+
+GP_3D, GP_2D_XY, GP_2D_XZ = 0, 1, 2
+GP_FP64, GP_FP32_MIXED = 0, 1
+GEOM = {"3d": GP_3D, "2dxy": GP_2D_XY, "2dxz": GP_2D_XZ}
+PREC = {"fp64": GP_FP64, "fp32": GP_FP32_MIXED}
+
+
+class gp_params(ctypes.Structure):
+    _fields_ = [
+        ("geom", ctypes.c_int),
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("gamma", ctypes.c_double), ("nu", ctypes.c_double), ("lambda_", ctypes.c_double),
+        ("g", ctypes.c_double), ("gdd", ctypes.c_double),
+        ("cutoff_R", ctypes.c_double),
+        ("prec", ctypes.c_int),
+    ]
+
+
+class gp_observables(ctypes.Structure):
+    _fields_ = [
+        ("norm", ctypes.c_double), ("mu", ctypes.c_double), ("energy", ctypes.c_double),
+        ("e_kin", ctypes.c_double), ("e_pot", ctypes.c_double), ("e_int", ctypes.c_double),
+        ("e_dd", ctypes.c_double), ("rms", ctypes.c_double * 3),
+    ]
+
+    def as_dict(self):
+        return {"norm": self.norm, "mu": self.mu, "energy": self.energy,
+                "e_kin": self.e_kin, "e_pot": self.e_pot, "e_int": self.e_int,
+                "e_dd": self.e_dd, "rms": tuple(self.rms)}
+
+
+# name -> (restype, argtypes), mirroring include/gp.h
+_P = ctypes.c_void_p
+_SIGS = {
+    "gp_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(gp_params), ctypes.POINTER(ctypes.c_size_t)]),
+    "gp_init": (ctypes.c_int, [ctypes.POINTER(gp_params), _P, ctypes.c_size_t, _P,
+                               ctypes.POINTER(_P)]),
+    "gp_destroy": (ctypes.c_int, [_P]),
+    "gp_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "gp_set_psi": (ctypes.c_int, [_P, _P, ctypes.c_int]),
+    "gp_get_psi": (ctypes.c_int, [_P, _P, ctypes.c_int]),
+    "gp_set_potential": (ctypes.c_int, [_P, _P, ctypes.c_int]),
+    "gp_set_couplings": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double]),
+    "gp_step_imag": (ctypes.c_int, [_P, ctypes.c_int]),
+    "gp_step_real": (ctypes.c_int, [_P, ctypes.c_int]),
+    "gp_energy": (ctypes.c_int, [_P, ctypes.POINTER(gp_observables)]),
+    "gp_dipolar_potential": (ctypes.c_int, [_P, _P, ctypes.c_int]),
+    "gp_history": (ctypes.c_int, [_P, ctypes.POINTER(gp_observables), ctypes.c_int,
+                                  ctypes.POINTER(ctypes.c_int)]),
+    "gp_history_capacity": (ctypes.c_int, []),
+    "gp_sync": (ctypes.c_int, [_P]),
+    "gp_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libgpdbec.so and declare its signatures.  Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libgpdbec.so not found at {path}: build it with "
+                           "`python -c 'import __graft_entry__ as g; g.build()'`")
+    # torch ships its own HIP runtime with the same soname as the system one; loading
+    # torch first makes the library bind to that runtime, so device pointers and
+    # streams created by torch are valid in the library (one runtime per process).
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class GPError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        lib = load()
+        msg = lib.gp_status_string(status).decode()
+        if status == GP_E_DEVICE:
+            msg += ": " + lib.gp_last_error().decode()
+        super().__init__(f"{where}: {msg} ({status})")
+
+
+def _check(status, where):
+    if status != GP_OK:
+        raise GPError(status, where)
+
+
+def make_params(geom, nx, ny=1, nz=1, dx=0.1, dy=0.1, dz=0.1, dt=1e-3, gamma=1.0, nu=1.0,
+                lam=1.0, g=0.0, gdd=0.0, R=0.0, prec="fp64", **_ignored):
+    p = gp_params()
+    p.geom = GEOM[geom] if isinstance(geom, str) else int(geom)
+    p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
+    p.dx, p.dy, p.dz = float(dx), float(dy), float(dz)
+    p.dt = float(dt)
+    p.gamma, p.nu, p.lambda_ = float(gamma), float(nu), float(lam)
+    p.g, p.gdd = float(g), float(gdd)
+    p.cutoff_R = float(R)
+    p.prec = PREC[prec] if isinstance(prec, str) else int(prec)
+    return p
+
+
+# ------------------------------------------------------- same-name thin wrappers
+def gp_workspace_bytes(params: gp_params) -> int:
+    n = ctypes.c_size_t(0)
+    _check(load().gp_workspace_bytes(ctypes.byref(params), ctypes.byref(n)), "gp_workspace_bytes")
+    return n.value
+
+
+def gp_init(params: gp_params, workspace_ptr: int, ws_bytes: int, stream_ptr: int) -> int:
+    ctx = _P()
+    _check(load().gp_init(ctypes.byref(params), _P(workspace_ptr), ws_bytes, _P(stream_ptr),
+                          ctypes.byref(ctx)), "gp_init")
+    return ctx.value
+
+
+def gp_destroy(ctx: int):
+    _check(load().gp_destroy(_P(ctx)), "gp_destroy")
+
+
+def gp_set_psi(ctx: int, ptr: int, on_device: int):
+    _check(load().gp_set_psi(_P(ctx), _P(ptr), on_device), "gp_set_psi")
+
+
+def gp_get_psi(ctx: int, ptr: int, on_device: int):
+    _check(load().gp_get_psi(_P(ctx), _P(ptr), on_device), "gp_get_psi")
+
+
+def gp_set_potential(ctx: int, ptr: int, on_device: int):
+    _check(load().gp_set_potential(_P(ctx), _P(ptr), on_device), "gp_set_potential")
+
+
+def gp_set_couplings(ctx: int, g: float, gdd: float):
+    _check(load().gp_set_couplings(_P(ctx), g, gdd), "gp_set_couplings")
+
+
+def gp_step_imag(ctx: int, nsteps: int):
+    _check(load().gp_step_imag(_P(ctx), nsteps), "gp_step_imag")
+
+
+def gp_step_real(ctx: int, nsteps: int):
+    _check(load().gp_step_real(_P(ctx), nsteps), "gp_step_real")
+
+
+def gp_energy(ctx: int) -> dict:
+    ob = gp_observables()
+    _check(load().gp_energy(_P(ctx), ctypes.byref(ob)), "gp_energy")
+    return ob.as_dict()
+
+
+def gp_dipolar_potential(ctx: int, ptr: int, on_device: int):
+    _check(load().gp_dipolar_potential(_P(ctx), _P(ptr), on_device), "gp_dipolar_potential")
+
+
+def gp_history(ctx: int, max_records: int) -> list:
+    arr = (gp_observables * max(1, max_records))()
+    cnt = ctypes.c_int(0)
+    _check(load().gp_history(_P(ctx), arr, max_records, ctypes.byref(cnt)), "gp_history")
+    return [arr[i].as_dict() for i in range(cnt.value)]
+
+
+def gp_sync(ctx: int):
+    _check(load().gp_sync(_P(ctx)), "gp_sync")
+
+
+# ------------------------------------------------------------ convenience class
+class Solver:
+    """One context on one device: owns a torch workspace tensor and uses a torch stream.
+
+    params: dict with the keys of `make_params` (geom, nx, ny, nz, dx, dy, dz, dt, gamma,
+    nu, lam, g, gdd, R); prec: "fp64" or "fp32" (FP32 bulk, FP64 reductions)."""
+
+    def __init__(self, params: dict, prec: str = "fp64", device: str = "cuda:0", stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.params = dict(params)
+        self.prec = prec
+        self.p = make_params(**{**params, "prec": prec})
+        self.shape = _shape(params)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ws_bytes = gp_workspace_bytes(self.p)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        self._ws_ptr = (base + 255) & ~255
+        self.ctx = gp_init(self.p, self._ws_ptr, self.ws_bytes, self.stream.cuda_stream)
+        self.cdtype = torch.complex128 if prec == "fp64" else torch.complex64
+        self.rdtype = torch.float64 if prec == "fp64" else torch.float32
+
+    def close(self):
+        if self.ctx:
+            gp_destroy(self.ctx)
+            self.ctx = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --- state
+    def set_psi(self, psi):
+        if isinstance(psi, np.ndarray):
+            a = np.ascontiguousarray(psi, dtype=np.complex128)
+            assert a.shape == self.shape, (a.shape, self.shape)
+            gp_set_psi(self.ctx, a.ctypes.data, 0)
+        else:
+            t = psi.to(device=self.device, dtype=self.cdtype).contiguous()
+            assert tuple(t.shape) == self.shape
+            gp_set_psi(self.ctx, t.data_ptr(), 1)
+            self.stream.synchronize()
+
+    def get_psi(self) -> np.ndarray:
+        out = np.empty(self.shape, dtype=np.complex128)
+        gp_get_psi(self.ctx, out.ctypes.data, 0)
+        return out
+
+    def get_psi_device(self):
+        t = self.torch.empty(self.shape, dtype=self.cdtype, device=self.device)
+        gp_get_psi(self.ctx, t.data_ptr(), 1)
+        return t
+
+    def set_potential(self, V):
+        if isinstance(V, np.ndarray):
+            a = np.ascontiguousarray(V, dtype=np.float64)
+            assert a.shape == self.shape
+            gp_set_potential(self.ctx, a.ctypes.data, 0)
+        else:
+            t = V.to(device=self.device, dtype=self.rdtype).contiguous()
+            gp_set_potential(self.ctx, t.data_ptr(), 1)
+            self.stream.synchronize()
+
+    def set_couplings(self, g, gdd):
+        gp_set_couplings(self.ctx, g, gdd)
+
+    # --- method
+    def step_imag(self, n: int):
+        gp_step_imag(self.ctx, n)
+
+    def step_real(self, n: int):
+        gp_step_real(self.ctx, n)
+
+    def energy(self) -> dict:
+        return gp_energy(self.ctx)
+
+    def dipolar_potential(self) -> np.ndarray:
+        out = np.empty(self.shape, dtype=np.float64)
+        gp_dipolar_potential(self.ctx, out.ctypes.data, 0)
+        return out
+
+    def history(self, n: int) -> list:
+        return gp_history(self.ctx, n)
+
+    def sync(self):
+        gp_sync(self.ctx)
+
+
+def _shape(params):
+    g = params["geom"]
+    if g == "3d":
+        return (params["nz"], params["ny"], params["nx"])
+    if g == "2dxy":
+        return (params["ny"], params["nx"])
+    return (params["nz"], params["nx"])

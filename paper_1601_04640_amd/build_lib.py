@@ -1,0 +1,67 @@
+"""Build libgpdbec.so (HIP, gfx950) in-tree: one object per (precision, pass family)
+plus the C-ABI translation unit, compiled in parallel with hipcc, linked shared."""
+from __future__ import annotations
+
+import concurrent.futures
+import os
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(PKG, "csrc")
+BUILD = os.path.join(PKG, "_build")
+LIB = os.path.join(PKG, "libgpdbec.so")
+ARCH = os.environ.get("GPDBEC_ARCH", "gfx950")
+
+HIPCC = "/opt/rocm/bin/hipcc"
+FLAGS = [
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+    # packed FP32 instructions are kept out of the generated code
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wno-unused-command-line-argument",
+]
+
+
+def _jobs():
+    jobs = []
+    for real in ("float", "double"):
+        for fam in (0, 1, 2):
+            obj = os.path.join(BUILD, f"inst_{real}_{fam}.o")
+            cmd = [HIPCC, *FLAGS, f"-DGP_REAL={real}", f"-DGP_FAMILY={fam}", "-c",
+                   os.path.join(CSRC, "gp_inst.hip"), "-o", obj]
+            jobs.append((obj, cmd))
+    obj = os.path.join(BUILD, "capi.o")
+    jobs.append((obj, [HIPCC, *FLAGS, "-c", os.path.join(CSRC, "gp_capi.hip"), "-o", obj]))
+    return jobs
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l
+                    and "not a recognized feature" not in l)
+    return r.returncode, err
+
+
+def build(verbose: bool = True) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    jobs = _jobs()
+    workers = min(len(jobs), max(1, min(os.cpu_count() or 1, 8)))
+    with concurrent.futures.ThreadPoolExecutor(workers) as ex:
+        results = list(ex.map(lambda j: (j[0], _run(j[1])), jobs))
+    failed = [(o, e) for o, (rc, e) in results if rc != 0]
+    if failed:
+        msg = "\n\n".join(f"{o}:\n{e}" for o, e in failed)
+        raise RuntimeError(f"hipcc failed:\n{msg}")
+    tmp = LIB + ".tmp"
+    rc, err = _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp,
+                    *[o for o, _ in jobs]])
+    if rc != 0:
+        raise RuntimeError(f"link failed:\n{err}")
+    os.replace(tmp, LIB)
+    if verbose:
+        print(f"built {LIB}", file=sys.stderr)
+    return LIB
+
+
+if __name__ == "__main__":
+    build()

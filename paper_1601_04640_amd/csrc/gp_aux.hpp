@@ -1,0 +1,285 @@
+// Set-up, I/O and reduction kernels: FFT twiddles, Crank-Nicolson factor tables, the
+// dipolar kernel table U(k)/N, the harmonic trap, wave-function conversion with the
+// Dirichlet boundary, and the FP64 finalisation of one step's partial sums.
+#pragma once
+#include "gp_device.hpp"
+
+namespace gpdbec {
+
+// tw[k] = exp(-2 pi i k/N), evaluated in FP64 and rounded to T.
+template <typename T>
+__global__ void k_twiddles(cpx<T>* tw, int N) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  double s, c;
+  sincospi(2.0 * (double)k / (double)N, &s, &c);
+  tw[k] = cpx<T>{(T)c, (T)(-s)};
+}
+
+// Thomas factors of (1 + 2A) u_i - A (u_{i-1} + u_{i+1}) with Dirichlet ends, for
+// A = Ar (imaginary time) and A = i Ar (real time), evaluated sequentially in FP64:
+//   m_1 = 1/b,  m_i = 1/(b - a c_{i-1}),  c_i = a m_i,  g_i = -c_i = A m_i,
+// with a = -A, b = 1 + 2A; m = g = 0 on the two boundary rows.
+struct zd {
+  double re, im;
+};
+__device__ inline zd zmul(zd a, zd b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ inline zd zsub(zd a, zd b) { return {a.re - b.re, a.im - b.im}; }
+__device__ inline zd zinv(zd a) {
+  const double d = a.re * a.re + a.im * a.im;
+  return {a.re / d, -a.im / d};
+}
+template <typename T>
+__global__ void k_cn_tables(cpx<T>* m_im, cpx<T>* g_im, cpx<T>* m_re, cpx<T>* g_re, int N,
+                            double Ar) {
+  if (blockIdx.x != 0 || threadIdx.x > 1) return;
+  const bool real_time = threadIdx.x == 1;
+  cpx<T>* mt = real_time ? m_re : m_im;
+  cpx<T>* gt = real_time ? g_re : g_im;
+  const zd A = real_time ? zd{0.0, Ar} : zd{Ar, 0.0};
+  const zd a = {-A.re, -A.im};
+  const zd b = {1.0 + 2.0 * A.re, 2.0 * A.im};
+  zd c = {0.0, 0.0};
+  mt[0] = cpx<T>{0, 0};
+  gt[0] = cpx<T>{0, 0};
+  for (int i = 1; i <= N - 2; ++i) {
+    const zd m = zinv(zsub(b, zmul(a, c)));
+    c = zmul(a, m);
+    mt[i] = cpx<T>{(T)m.re, (T)m.im};
+    gt[i] = cpx<T>{(T)(-c.re), (T)(-c.im)};
+  }
+  mt[N - 1] = cpx<T>{0, 0};
+  gt[N - 1] = cpx<T>{0, 0};
+}
+
+// Spherical-cutoff factor b(s) = 1 + 3 cos s/s^2 - 3 sin s/s^3 (s = kR); for s < 1 the
+// alternating series sum_{k>=2} (-1)^k 6k s^(2k-2)/(2k+1)! avoids the cancellation.
+__device__ inline double cutoff_b(double s) {
+  if (s < 1.0) {
+    const double s2 = s * s;
+    double term = s2 / 10.0;  // k = 2
+    double acc = term;
+    for (int k = 2; k < 15; ++k) {
+      term *= -s2 * (double)(k + 1) / ((double)k * (2.0 * k + 2.0) * (2.0 * k + 3.0));
+      acc += term;
+    }
+    return acc;
+  }
+  double sn, cs;
+  sincos(s, &sn, &cs);
+  return 1.0 + 3.0 * cs / (s * s) - 3.0 * sn / (s * s * s);
+}
+
+struct KernelGeom {
+  int geom;          // 0: 3D, 1: 2D XY, 2: 2D XZ
+  int n0, n1, n2;    // grid axes (x fastest)
+  double h0, h1, h2;
+  double R;          // 3D cutoff radius (<= 0: none)
+  double d;          // 2D transverse width
+};
+
+// ktab[(kx*n2 + k2)*n1 + k1] = U(k)/(n0 n1 n2), kx = 0..n0/2, in FP64 rounded to T.
+//  3D:  U = (3 kz^2/k^2 - 1) b(kR), U(0) = 0   (axis 1 = y, axis 2 = z)
+//  XY:  U = [2 - 3 sqrt(pi) xi erfcx(xi)]/(sqrt(2 pi) d),  xi = q d/sqrt 2
+//  XZ:  U = [-1 + 3 sqrt(pi) (kz^2/q^2) xi erfcx(xi)]/(sqrt(2 pi) d)   (axis 1 = z)
+template <typename T>
+__global__ void k_kernel_table(T* ktab, KernelGeom kg) {
+  const int H = kg.n0 / 2 + 1;
+  const size_t total = (size_t)H * kg.n1 * kg.n2;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int k1 = (int)(idx % kg.n1);
+  const int k2 = (int)((idx / kg.n1) % kg.n2);
+  const int kx = (int)(idx / ((size_t)kg.n1 * kg.n2));
+  const double pi = 3.14159265358979323846;
+  const double qx = 2.0 * pi * kx / (kg.n0 * kg.h0);
+  const int m1 = (k1 < kg.n1 / 2) ? k1 : k1 - kg.n1;
+  const int m2 = (k2 < kg.n2 / 2) ? k2 : k2 - kg.n2;
+  const double q1 = 2.0 * pi * m1 / (kg.n1 * kg.h1);
+  const double q2 = (kg.n2 > 1) ? 2.0 * pi * m2 / (kg.n2 * kg.h2) : 0.0;
+  double u;
+  if (kg.geom == 0) {
+    const double k2s = qx * qx + q1 * q1 + q2 * q2;
+    if (k2s == 0.0) {
+      u = 0.0;
+    } else {
+      u = 3.0 * q2 * q2 / k2s - 1.0;
+      if (kg.R > 0.0) u *= cutoff_b(sqrt(k2s) * kg.R);
+    }
+  } else {
+    const double pref = 1.0 / (sqrt(2.0 * pi) * kg.d);
+    const double qq = qx * qx + q1 * q1;
+    const double q = sqrt(qq);
+    const double xi = q * kg.d / sqrt(2.0);
+    const double ex = 3.0 * sqrt(pi) * xi * erfcx(xi);
+    if (kg.geom == 1) {
+      u = pref * (2.0 - ex);
+    } else {
+      const double ratio = (qq > 0.0) ? q1 * q1 / qq : 0.0;
+      u = pref * (-1.0 + ratio * ex);
+    }
+  }
+  ktab[idx] = (T)(u / ((double)kg.n0 * (double)kg.n1 * (double)kg.n2));
+}
+
+// Harmonic trap V = (w0^2 a0^2 + w1^2 a1^2 + w2^2 a2^2)/2 with a = (idx - n/2) h.
+template <typename T>
+__global__ void k_harmonic(T* V, int n0, int n1, int n2, double h0, double h1, double h2,
+                           double w0, double w1, double w2) {
+  const size_t total = (size_t)n0 * n1 * n2;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int i = (int)(idx % n0);
+  const int j = (int)((idx / n0) % n1);
+  const int k = (int)(idx / ((size_t)n0 * n1));
+  const double x = (i - n0 / 2) * h0, y = (j - n1 / 2) * h1, z = (k - n2 / 2) * h2;
+  V[idx] = (T)(0.5 * (w0 * w0 * x * x + w1 * w1 * y * y + w2 * w2 * z * z));
+}
+
+__device__ inline bool on_boundary(size_t idx, int n0, int n1, int n2) {
+  const int i = (int)(idx % n0);
+  const int j = (int)((idx / n0) % n1);
+  const int k = (int)(idx / ((size_t)n0 * n1));
+  return i == 0 || i == n0 - 1 || j == 0 || j == n1 - 1 || (n2 > 1 && (k == 0 || k == n2 - 1));
+}
+
+// psi[off + e] = src[e] (converted), boundary points zeroed.
+template <typename T, typename S>
+__global__ void k_psi_in(cpx<T>* psi, const cpx<S>* src, size_t off, size_t cnt, int n0, int n1,
+                         int n2) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= cnt) return;
+  const size_t idx = off + e;
+  const cpx<S> v = src[e];
+  psi[idx] = on_boundary(idx, n0, n1, n2) ? cpx<T>{0, 0} : cpx<T>{(T)v.re, (T)v.im};
+}
+
+// dst[e] = scale * psi[off + e] (converted).
+template <typename T, typename D>
+__global__ void k_psi_out(cpx<D>* dst, const cpx<T>* psi, const double* scale, size_t off,
+                          size_t cnt) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= cnt) return;
+  const double s = *scale;
+  const cpx<T> v = psi[off + e];
+  dst[e] = cpx<D>{(D)(s * (double)v.re), (D)(s * (double)v.im)};
+}
+
+template <typename D, typename S>
+__global__ void k_real_convert(D* dst, const S* src, size_t cnt) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < cnt) dst[e] = (D)src[e];
+}
+
+// --------------------------------------------------------------- finalisation
+enum : int { FIN_IMAG = 0, FIN_REAL = 1, FIN_OBSERVE = 2, FIN_EKZ = 3 };
+constexpr int kRecord = 10;  // norm, mu, energy, e_kin, e_pot, e_int, e_dd, rms x/y/z
+
+struct FinArgs {
+  const double* p_x;   // 2 per block: sum |dx psi|^2, sum |d1 psi|^2 (unscaled)
+  int nb_x;
+  const double* p_nl;  // 7 per block: n, V n, n^2, Phi n, x^2 n, a1^2 n, a2^2 n (scaled)
+  int nb_nl;
+  const double* p_col; // 2 per block: |u|^2, |d2 u|^2 (new state / unscaled input)
+  int nb_col;
+  double dV, h0, h1, h2, gc, gdd;
+  int geom;            // 0: 3D, 1: XY, 2: XZ
+  double* scale;
+  double* ekz;         // pending z-kinetic energy of the stored state (3D)
+  int* flags;
+  double* ring;
+  int* ring_pos;
+  int ring_cap;
+  double* obs;         // FIN_OBSERVE output record
+};
+
+// One block of kThreads.  Sums every partial field over blocks in a fixed order.
+__global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a, int mode) {
+  __shared__ double red[11 * kThreads];
+  const int tid = threadIdx.x;
+  double v[11];
+#pragma unroll
+  for (int k = 0; k < 11; ++k) v[k] = 0.0;
+  if (mode != FIN_EKZ) {
+    for (int b = tid; b < a.nb_x; b += kThreads) {
+      v[0] += a.p_x[2 * b];
+      v[1] += a.p_x[2 * b + 1];
+    }
+    for (int b = tid; b < a.nb_nl; b += kThreads) {
+#pragma unroll
+      for (int k = 0; k < 7; ++k) v[2 + k] += a.p_nl[7 * b + k];
+    }
+  }
+  if (mode != FIN_OBSERVE || a.geom == 0) {
+    for (int b = tid; b < a.nb_col; b += kThreads) {
+      v[9] += a.p_col[2 * b];
+      v[10] += a.p_col[2 * b + 1];
+    }
+  }
+  block_sum<11>(v, red);
+  if (tid != 0) return;
+  const double s = *a.scale;
+  const double s2 = s * s;
+  if (mode == FIN_EKZ) {
+    *a.ekz = 0.5 * s2 * v[10] / (a.h2 * a.h2) * a.dV;
+    return;
+  }
+  const double dV = a.dV;
+  double rec[kRecord];
+  const double norm = v[2] * dV;
+  double ekin = 0.5 * s2 * (v[0] / (a.h0 * a.h0) + v[1] / (a.h1 * a.h1)) * dV;
+  if (a.geom == 0) {
+    ekin += (mode == FIN_OBSERVE) ? 0.5 * s2 * v[10] / (a.h2 * a.h2) * dV : *a.ekz;
+  }
+  const double epot = v[3] * dV;
+  const double eint = 0.5 * a.gc * v[4] * dV;
+  const double edd = 0.5 * a.gdd * v[5] * dV;
+  rec[0] = norm;
+  rec[1] = ekin + epot + 2.0 * eint + 2.0 * edd;
+  rec[2] = ekin + epot + eint + edd;
+  rec[3] = ekin;
+  rec[4] = epot;
+  rec[5] = eint;
+  rec[6] = edd;
+  const double r0 = sqrt(v[6] * dV / norm), r1 = sqrt(v[7] * dV / norm), r2 = sqrt(v[8] * dV / norm);
+  rec[7] = r0;
+  rec[8] = (a.geom == 2) ? 0.0 : r1;
+  rec[9] = (a.geom == 0) ? r2 : (a.geom == 2 ? r1 : 0.0);
+  double* dst;
+  if (mode == FIN_OBSERVE) {
+    dst = a.obs;
+  } else {
+    const int pos = *a.ring_pos;
+    dst = a.ring + (size_t)(pos % a.ring_cap) * kRecord;
+    *a.ring_pos = pos + 1;
+  }
+#pragma unroll
+  for (int k = 0; k < kRecord; ++k) dst[k] = rec[k];
+  if (!isfinite(norm)) *a.flags |= 1;
+  if (mode == FIN_OBSERVE) return;
+  // new state: imaginary time renormalises, real time keeps the physical values
+  const double nout = v[9] * dV;
+  if (!isfinite(nout) || !(nout > 0.0)) {
+    *a.flags |= 1;
+    *a.scale = 1.0;
+    return;
+  }
+  const double sn = (mode == FIN_IMAG) ? 1.0 / sqrt(nout) : 1.0;
+  *a.scale = sn;
+  if (a.geom == 0) *a.ekz = 0.5 * sn * sn * v[10] / (a.h2 * a.h2) * dV;
+}
+
+__global__ void k_reset_state(double* scale, double* ekz, int* flags, int* ring_pos) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    *scale = 1.0;
+    *ekz = 0.0;
+    *flags = 0;
+    *ring_pos = 0;
+  }
+}
+
+__global__ void k_set_scale_one(double* scale) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *scale = 1.0;
+}
+
+}  // namespace gpdbec

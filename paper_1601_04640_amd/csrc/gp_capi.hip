@@ -1,0 +1,623 @@
+// C ABI of libgpdbec (see include/gp.h): context set-up, workspace carving, state I/O
+// and the per-step pass schedule on the caller's HIP stream.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "../../include/gp.h"
+#include "gp_aux.hpp"
+#include "gp_kernels.hpp"
+#include "gp_launch.hpp"
+
+using namespace gpdbec;
+
+namespace {
+
+constexpr int kRingCap = 4096;
+
+bool size_ok(int n) {
+  switch (n) {
+#define X(N) case N:
+    GP_FOR_SIZES(X)
+#undef X
+    return true;
+    default:
+      return false;
+  }
+}
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct Layout {
+  int n0, n1, n2;       // grid axes, x fastest
+  double h0, h1, h2;
+  size_t npts, nspec;   // grid points, half-spectrum values
+  size_t esz;           // bytes of one real value
+  int nb_x, nb_col, nb_colobs;
+  // byte offsets inside the workspace
+  size_t o_psi, o_V, o_spec, o_ktab, o_tw[3], o_cn[3][4], o_px, o_pnl, o_pcol, o_scalars,
+      o_ring, o_obs, o_io, total;
+};
+
+struct Scalars {  // device-side scalars (one 256-byte block)
+  double scale;
+  double ekz;
+  double obs_pad;
+  int flags;
+  int ring_pos;
+};
+
+gp_status validate(const gp_params* p) {
+  if (!p) return GP_E_ARG;
+  if (p->geom < GP_3D || p->geom > GP_2D_XZ) return GP_E_ARG;
+  if (p->prec != GP_FP64 && p->prec != GP_FP32_MIXED) return GP_E_ARG;
+  if (!(p->dt > 0) || !isfinite(p->dt)) return GP_E_ARG;
+  if (!(p->dx > 0) || !isfinite(p->dx)) return GP_E_ARG;
+  if (!isfinite(p->g) || !isfinite(p->gdd) || !isfinite(p->gamma) || !isfinite(p->nu) ||
+      !isfinite(p->lambda) || !isfinite(p->cutoff_R))
+    return GP_E_ARG;
+  if (!size_ok(p->nx)) return GP_E_SIZE;
+  if (p->geom == GP_3D) {
+    if (!(p->dy > 0) || !(p->dz > 0)) return GP_E_ARG;
+    if (!size_ok(p->ny) || !size_ok(p->nz)) return GP_E_SIZE;
+  } else if (p->geom == GP_2D_XY) {
+    if (!(p->dy > 0) || !(p->lambda > 0)) return GP_E_ARG;
+    if (!size_ok(p->ny)) return GP_E_SIZE;
+  } else {
+    if (!(p->dz > 0) || !(p->nu > 0)) return GP_E_ARG;
+    if (!size_ok(p->nz)) return GP_E_SIZE;
+  }
+  return GP_OK;
+}
+
+int tj_of(bool fp64, int n) { return fp64 ? Launch<double>::tj(n) : Launch<float>::tj(n); }
+int tc_of(bool fp64, int n) { return fp64 ? Launch<double>::tc(n) : Launch<float>::tc(n); }
+
+Layout make_layout(const gp_params* p) {
+  Layout L{};
+  const bool fp64 = p->prec == GP_FP64;
+  L.n0 = p->nx;
+  L.h0 = p->dx;
+  if (p->geom == GP_3D) {
+    L.n1 = p->ny; L.h1 = p->dy; L.n2 = p->nz; L.h2 = p->dz;
+  } else if (p->geom == GP_2D_XY) {
+    L.n1 = p->ny; L.h1 = p->dy; L.n2 = 1; L.h2 = 1.0;
+  } else {
+    L.n1 = p->nz; L.h1 = p->dz; L.n2 = 1; L.h2 = 1.0;
+  }
+  L.esz = fp64 ? 8 : 4;
+  L.npts = (size_t)L.n0 * L.n1 * L.n2;
+  const int H = L.n0 / 2 + 1;
+  L.nspec = (size_t)H * L.n1 * L.n2;
+  const int tj = tj_of(fp64, L.n0);
+  L.nb_x = ((L.n1 + tj - 1) / tj) * L.n2;
+  if (p->geom == GP_3D) {
+    const int tcz = tc_of(fp64, L.n2);
+    L.nb_col = ((L.n0 + tcz - 1) / tcz) * L.n1;   // z sweep / z observe
+  } else {
+    const int tcy = tc_of(fp64, L.n1);
+    L.nb_col = ((L.n0 + tcy - 1) / tcy) * L.n2;   // y sweep (last pass in 2D)
+  }
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t r = o;
+    o += align_up(bytes);
+    return r;
+  };
+  L.o_psi = take(2 * L.esz * L.npts);
+  L.o_V = take(L.esz * L.npts);
+  L.o_spec = take(2 * L.esz * L.nspec);
+  L.o_ktab = take(L.esz * L.nspec);
+  const int ns[3] = {L.n0, L.n1, L.n2};
+  for (int a = 0; a < 3; ++a) {
+    L.o_tw[a] = take(2 * L.esz * ns[a]);
+    for (int t = 0; t < 4; ++t) L.o_cn[a][t] = take(2 * L.esz * ns[a]);
+  }
+  L.o_px = take(sizeof(double) * 2 * L.nb_x);
+  L.o_pnl = take(sizeof(double) * 7 * L.nb_x);
+  L.o_pcol = take(sizeof(double) * 2 * L.nb_col);
+  L.o_scalars = take(sizeof(Scalars));
+  L.o_ring = take(sizeof(double) * kRecord * kRingCap);
+  L.o_obs = take(sizeof(double) * kRecord);
+  L.o_io = take(16 * L.npts);
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+struct gp_ctx {
+  gp_params p;
+  Layout L;
+  hipStream_t st;
+  char* ws;
+  bool fp64;
+  bool psi_set;
+  bool ekz_valid;
+  double gc;
+  template <typename X>
+  X* at(size_t off) const { return reinterpret_cast<X*>(ws + off); }
+  Scalars* sc() const { return at<Scalars>(L.o_scalars); }
+};
+
+namespace {
+
+thread_local char g_last_error[256] = "";
+
+gp_status dev(hipError_t e) {
+  if (e == hipSuccess) return GP_OK;
+  snprintf(g_last_error, sizeof(g_last_error), "%s (%d)", hipGetErrorString(e), (int)e);
+  return GP_E_DEVICE;
+}
+
+// Discard an error left in HIP's per-thread slot by earlier, unrelated runtime calls, so
+// that a launch check reports only this library's launches.
+void clear_stale_error() { (void)hipGetLastError(); }
+#define GP_TRY(expr)                     \
+  do {                                   \
+    const gp_status _s = (expr);         \
+    if (_s != GP_OK) return _s;          \
+  } while (0)
+#define GP_HIP(expr) GP_TRY(dev(expr))
+
+unsigned blocks_for(size_t n, int per = kThreads) { return (unsigned)((n + per - 1) / per); }
+
+double d_perp(const gp_params& p) {
+  return p.geom == GP_2D_XY ? 1.0 / sqrt(p.lambda) : 1.0 / sqrt(p.nu);
+}
+
+double contact(const gp_params& p) {
+  if (p.geom == GP_3D) return p.g;
+  return p.g / (sqrt(2.0 * M_PI) * d_perp(p));
+}
+
+StepScalars scalars_for(const gp_ctx* c, int axis) {
+  StepScalars s{};
+  const double h[3] = {c->L.h0, c->L.h1, c->L.h2};
+  s.dt = c->p.dt;
+  s.gc = c->gc;
+  s.gdd = c->p.gdd;
+  s.Ar = c->p.dt / (4.0 * h[axis] * h[axis]);
+  s.h0 = c->L.h0;
+  s.h1 = c->L.h1;
+  s.h2 = c->L.h2;
+  return s;
+}
+
+FinArgs fin_args(const gp_ctx* c) {
+  FinArgs a{};
+  a.p_x = c->at<double>(c->L.o_px);
+  a.nb_x = c->L.nb_x;
+  a.p_nl = c->at<double>(c->L.o_pnl);
+  a.nb_nl = c->L.nb_x;
+  a.p_col = c->at<double>(c->L.o_pcol);
+  a.nb_col = c->L.nb_col;
+  a.dV = c->L.h0 * c->L.h1 * (c->p.geom == GP_3D ? c->L.h2 : 1.0);
+  a.h0 = c->L.h0;
+  a.h1 = c->L.h1;
+  a.h2 = c->L.h2;
+  a.gc = c->gc;
+  a.gdd = c->p.gdd;
+  a.geom = c->p.geom;
+  Scalars* s = c->sc();
+  a.scale = &s->scale;
+  a.ekz = &s->ekz;
+  a.flags = &s->flags;
+  a.ring = c->at<double>(c->L.o_ring);
+  a.ring_pos = &s->ring_pos;
+  a.ring_cap = kRingCap;
+  a.obs = c->at<double>(c->L.o_obs);
+  return a;
+}
+
+// ------------------------------------------------------------- pass schedule
+template <typename T>
+struct Passes {
+  static cpx<T>* psi(gp_ctx* c) { return c->at<cpx<T>>(c->L.o_psi); }
+  static cpx<T>* spec(gp_ctx* c) { return c->at<cpx<T>>(c->L.o_spec); }
+  static const cpx<T>* tw(gp_ctx* c, int a) { return c->at<cpx<T>>(c->L.o_tw[a]); }
+  static const cpx<T>* cn(gp_ctx* c, int a, int k) { return c->at<cpx<T>>(c->L.o_cn[a][k]); }
+
+  // density -> spectrum -> U(k) product -> back to the x-half spectrum
+  static gp_status convolution(gp_ctx* c) {
+    const Layout& L = c->L;
+    const int H = L.n0 / 2 + 1;
+    GP_HIP(Launch<T>::r2c_x(L.n0, L.nb_x, c->st, psi(c), &c->sc()->scale, spec(c), tw(c, 0),
+                            c->at<double>(L.o_px), L.n1, L.n2));
+    if (c->p.geom == GP_3D) {
+      const int nl = H * L.n2;
+      const int lb = c->fp64 ? Launch<double>::lb(L.n1) : Launch<float>::lb(L.n1);
+      const int tc = tc_of(c->fp64, L.n2);
+      GP_HIP(Launch<T>::fft_line(L.n1, false, (nl + lb - 1) / lb, c->st, spec(c), tw(c, 1), nl));
+      GP_HIP(Launch<T>::conv_col(L.n2, ((L.n1 + tc - 1) / tc) * H, c->st, spec(c),
+                                 c->at<T>(L.o_ktab), tw(c, 2), L.n1));
+      GP_HIP(Launch<T>::fft_line(L.n1, true, (nl + lb - 1) / lb, c->st, spec(c), tw(c, 1), nl));
+    } else {
+      const int lb = c->fp64 ? Launch<double>::lb(L.n1) : Launch<float>::lb(L.n1);
+      GP_HIP(Launch<T>::conv_line(L.n1, (H + lb - 1) / lb, c->st, spec(c), c->at<T>(L.o_ktab),
+                                  tw(c, 1), H));
+    }
+    return GP_OK;
+  }
+
+  // z-difference sums of the stored state (3D), for the kinetic energy
+  static gp_status z_observe(gp_ctx* c) {
+    const Layout& L = c->L;
+    return dev(Launch<T>::cn_col(L.n2, MODE_OBSERVE, true, L.nb_col, c->st, psi(c), nullptr,
+                                 nullptr, 0.0, c->at<double>(L.o_pcol), L.n0,
+                                 (size_t)L.n0 * L.n1, (size_t)L.n0));
+  }
+
+  static gp_status step(gp_ctx* c, bool imag) {
+    const Layout& L = c->L;
+    const int mode = imag ? MODE_IMAG : MODE_REAL;
+    const int k = imag ? 0 : 2;  // table pair: (m, g) imaginary or real time
+    GP_TRY(convolution(c));
+    const StepScalars sx = scalars_for(c, 0);
+    GP_HIP(Launch<T>::c2r_nl_cnx(L.n0, mode, L.nb_x, c->st, psi(c), c->at<T>(L.o_V),
+                                 &c->sc()->scale, spec(c), tw(c, 0), cn(c, 0, k), cn(c, 0, k + 1),
+                                 sx, c->at<double>(L.o_pnl), nullptr, L.n1, L.n2));
+    const int tcy = tc_of(c->fp64, L.n1);
+    const double Ay = scalars_for(c, 1).Ar;
+    if (c->p.geom == GP_3D) {
+      GP_HIP(Launch<T>::cn_col(L.n1, mode, false, ((L.n0 + tcy - 1) / tcy) * L.n2, c->st, psi(c),
+                               cn(c, 1, k), cn(c, 1, k + 1), Ay, nullptr, L.n0, (size_t)L.n0,
+                               (size_t)L.n0 * L.n1));
+      const double Az = scalars_for(c, 2).Ar;
+      GP_HIP(Launch<T>::cn_col(L.n2, mode, true, L.nb_col, c->st, psi(c), cn(c, 2, k),
+                               cn(c, 2, k + 1), Az, c->at<double>(L.o_pcol), L.n0,
+                               (size_t)L.n0 * L.n1, (size_t)L.n0));
+    } else {
+      GP_HIP(Launch<T>::cn_col(L.n1, mode, true, L.nb_col, c->st, psi(c), cn(c, 1, k),
+                               cn(c, 1, k + 1), Ay, c->at<double>(L.o_pcol), L.n0, (size_t)L.n0,
+                               (size_t)L.n0 * L.n1));
+    }
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, c->st, fin_args(c),
+                       imag ? (int)FIN_IMAG : (int)FIN_REAL);
+    GP_HIP(hipGetLastError());
+    return GP_OK;
+  }
+
+  static gp_status observe(gp_ctx* c) {
+    const Layout& L = c->L;
+    GP_TRY(convolution(c));
+    const StepScalars sx = scalars_for(c, 0);
+    GP_HIP(Launch<T>::c2r_nl_cnx(L.n0, MODE_OBSERVE, L.nb_x, c->st, psi(c), c->at<T>(L.o_V),
+                                 &c->sc()->scale, spec(c), tw(c, 0), nullptr, nullptr, sx,
+                                 c->at<double>(L.o_pnl), nullptr, L.n1, L.n2));
+    if (c->p.geom == GP_3D) GP_TRY(z_observe(c));
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, c->st, fin_args(c),
+                       (int)FIN_OBSERVE);
+    GP_HIP(hipGetLastError());
+    return GP_OK;
+  }
+
+  static gp_status phi(gp_ctx* c, T* out) {
+    const Layout& L = c->L;
+    GP_TRY(convolution(c));
+    const StepScalars sx = scalars_for(c, 0);
+    GP_HIP(Launch<T>::c2r_nl_cnx(L.n0, MODE_PHI, L.nb_x, c->st, psi(c), c->at<T>(L.o_V),
+                                 &c->sc()->scale, spec(c), tw(c, 0), nullptr, nullptr, sx,
+                                 c->at<double>(L.o_pnl), out, L.n1, L.n2));
+    return GP_OK;
+  }
+
+  static gp_status init_tables(gp_ctx* c) {
+    const Layout& L = c->L;
+    const int ns[3] = {L.n0, L.n1, L.n2};
+    const double hs[3] = {L.h0, L.h1, L.h2};
+    const int naxes = (c->p.geom == GP_3D) ? 3 : 2;
+    for (int a = 0; a < naxes; ++a) {
+      hipLaunchKernelGGL(k_twiddles<T>, dim3(blocks_for(ns[a])), dim3(kThreads), 0, c->st,
+                         c->at<cpx<T>>(L.o_tw[a]), ns[a]);
+      const double Ar = c->p.dt / (4.0 * hs[a] * hs[a]);
+      hipLaunchKernelGGL(k_cn_tables<T>, dim3(1), dim3(64), 0, c->st,
+                         c->at<cpx<T>>(L.o_cn[a][0]), c->at<cpx<T>>(L.o_cn[a][1]),
+                         c->at<cpx<T>>(L.o_cn[a][2]), c->at<cpx<T>>(L.o_cn[a][3]), ns[a], Ar);
+    }
+    KernelGeom kg{};
+    kg.geom = c->p.geom;
+    kg.n0 = L.n0;
+    kg.n1 = L.n1;
+    kg.n2 = L.n2;
+    kg.h0 = L.h0;
+    kg.h1 = L.h1;
+    kg.h2 = L.h2;
+    kg.R = c->p.cutoff_R;
+    kg.d = (c->p.geom == GP_3D) ? 0.0 : d_perp(c->p);
+    hipLaunchKernelGGL(k_kernel_table<T>, dim3(blocks_for(L.nspec)), dim3(kThreads), 0, c->st,
+                       c->at<T>(L.o_ktab), kg);
+    double w0 = c->p.gamma, w1, w2 = 0.0;
+    if (c->p.geom == GP_3D) {
+      w1 = c->p.nu;
+      w2 = c->p.lambda;
+    } else if (c->p.geom == GP_2D_XY) {
+      w1 = c->p.nu;
+    } else {
+      w1 = c->p.lambda;
+    }
+    hipLaunchKernelGGL(k_harmonic<T>, dim3(blocks_for(L.npts)), dim3(kThreads), 0, c->st,
+                       c->at<T>(L.o_V), L.n0, L.n1, L.n2, L.h0, L.h1, L.h2, w0, w1, w2);
+    Scalars* s = c->sc();
+    hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, c->st, &s->scale, &s->ekz, &s->flags,
+                       &s->ring_pos);
+    return dev(hipGetLastError());
+  }
+
+  // host FP64 or device T input, chunked through the io staging area
+  static gp_status set_psi(gp_ctx* c, const void* src, int on_device) {
+    const Layout& L = c->L;
+    if (on_device) {
+      hipLaunchKernelGGL((k_psi_in<T, T>), dim3(blocks_for(L.npts)), dim3(kThreads), 0, c->st,
+                         psi(c), reinterpret_cast<const cpx<T>*>(src), (size_t)0, L.npts, L.n0,
+                         L.n1, L.n2);
+      GP_HIP(hipGetLastError());
+    } else {
+      cpx<double>* io = c->at<cpx<double>>(L.o_io);
+      GP_HIP(hipMemcpyAsync(io, src, 16 * L.npts, hipMemcpyHostToDevice, c->st));
+      hipLaunchKernelGGL((k_psi_in<T, double>), dim3(blocks_for(L.npts)), dim3(kThreads), 0,
+                         c->st, psi(c), io, (size_t)0, L.npts, L.n0, L.n1, L.n2);
+      GP_HIP(hipGetLastError());
+      GP_HIP(hipStreamSynchronize(c->st));
+    }
+    hipLaunchKernelGGL(k_set_scale_one, dim3(1), dim3(64), 0, c->st, &c->sc()->scale);
+    return dev(hipGetLastError());
+  }
+
+  static gp_status get_psi(gp_ctx* c, void* dst, int on_device) {
+    const Layout& L = c->L;
+    if (on_device) {
+      hipLaunchKernelGGL((k_psi_out<T, T>), dim3(blocks_for(L.npts)), dim3(kThreads), 0, c->st,
+                         reinterpret_cast<cpx<T>*>(dst), psi(c), &c->sc()->scale, (size_t)0,
+                         L.npts);
+      return dev(hipGetLastError());
+    }
+    cpx<double>* io = c->at<cpx<double>>(L.o_io);
+    hipLaunchKernelGGL((k_psi_out<T, double>), dim3(blocks_for(L.npts)), dim3(kThreads), 0,
+                       c->st, io, psi(c), &c->sc()->scale, (size_t)0, L.npts);
+    GP_HIP(hipGetLastError());
+    GP_HIP(hipMemcpyAsync(dst, io, 16 * L.npts, hipMemcpyDeviceToHost, c->st));
+    GP_HIP(hipStreamSynchronize(c->st));
+    return GP_OK;
+  }
+
+  static gp_status set_potential(gp_ctx* c, const void* src, int on_device) {
+    const Layout& L = c->L;
+    if (on_device) {
+      GP_HIP(hipMemcpyAsync(c->at<T>(L.o_V), src, L.esz * L.npts, hipMemcpyDeviceToDevice, c->st));
+      return GP_OK;
+    }
+    double* io = c->at<double>(L.o_io);
+    GP_HIP(hipMemcpyAsync(io, src, 8 * L.npts, hipMemcpyHostToDevice, c->st));
+    hipLaunchKernelGGL((k_real_convert<T, double>), dim3(blocks_for(L.npts)), dim3(kThreads), 0,
+                       c->st, c->at<T>(L.o_V), io, L.npts);
+    GP_HIP(hipGetLastError());
+    GP_HIP(hipStreamSynchronize(c->st));
+    return GP_OK;
+  }
+
+  static gp_status dipolar(gp_ctx* c, void* dst, int on_device) {
+    const Layout& L = c->L;
+    if (on_device) return phi(c, reinterpret_cast<T*>(dst));
+    T* tmp = c->at<T>(L.o_io);
+    GP_TRY(phi(c, tmp));
+    double* outd = c->at<double>(L.o_io + 8 * L.npts);
+    hipLaunchKernelGGL((k_real_convert<double, T>), dim3(blocks_for(L.npts)), dim3(kThreads), 0,
+                       c->st, outd, tmp, L.npts);
+    GP_HIP(hipGetLastError());
+    GP_HIP(hipMemcpyAsync(dst, outd, 8 * L.npts, hipMemcpyDeviceToHost, c->st));
+    GP_HIP(hipStreamSynchronize(c->st));
+    return GP_OK;
+  }
+};
+
+gp_status check_flags(gp_ctx* c) {
+  int flags = 0;
+  GP_HIP(hipMemcpyAsync(&flags, &c->sc()->flags, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  GP_HIP(hipStreamSynchronize(c->st));
+  return (flags & 1) ? GP_E_NONFINITE : GP_OK;
+}
+
+gp_status run_steps(gp_ctx* c, int nsteps, bool imag) {
+  if (!c) return GP_E_ARG;
+  clear_stale_error();
+  if (nsteps < 0) return GP_E_ARG;
+  if (!c->psi_set) return GP_E_STATE;
+  if (c->p.geom == GP_3D && !c->ekz_valid) {
+    if (c->fp64) {
+      GP_TRY(Passes<double>::z_observe(c));
+    } else {
+      GP_TRY(Passes<float>::z_observe(c));
+    }
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, c->st, fin_args(c), (int)FIN_EKZ);
+    GP_HIP(hipGetLastError());
+    c->ekz_valid = true;
+  }
+  for (int s = 0; s < nsteps; ++s) {
+    if (c->fp64) {
+      GP_TRY(Passes<double>::step(c, imag));
+    } else {
+      GP_TRY(Passes<float>::step(c, imag));
+    }
+  }
+  return GP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gp_status gp_workspace_bytes(const gp_params* params, size_t* bytes) {
+  if (!bytes) return GP_E_ARG;
+  GP_TRY(validate(params));
+  *bytes = make_layout(params).total;
+  return GP_OK;
+}
+
+gp_status gp_init(const gp_params* params, void* dev_workspace, size_t ws_bytes, void* hip_stream,
+                  gp_ctx** out) {
+  clear_stale_error();
+  if (!out || !dev_workspace) return GP_E_ARG;
+  *out = nullptr;
+  GP_TRY(validate(params));
+  const Layout L = make_layout(params);
+  if (ws_bytes < L.total) return GP_E_ARG;
+  if ((reinterpret_cast<uintptr_t>(dev_workspace) & 255) != 0) return GP_E_ARG;
+  gp_ctx* c = new (std::nothrow) gp_ctx();
+  if (!c) return GP_E_NOMEM;
+  c->p = *params;
+  c->L = L;
+  c->st = reinterpret_cast<hipStream_t>(hip_stream);
+  c->ws = reinterpret_cast<char*>(dev_workspace);
+  c->fp64 = params->prec == GP_FP64;
+  c->psi_set = false;
+  c->ekz_valid = false;
+  c->gc = contact(c->p);
+  const gp_status s = c->fp64 ? Passes<double>::init_tables(c) : Passes<float>::init_tables(c);
+  if (s != GP_OK) {
+    delete c;
+    return s;
+  }
+  *out = c;
+  return GP_OK;
+}
+
+gp_status gp_destroy(gp_ctx* ctx) {
+  if (!ctx) return GP_E_ARG;
+  const hipError_t e = hipStreamSynchronize(ctx->st);
+  delete ctx;
+  return dev(e);
+}
+
+const char* gp_status_string(gp_status s) {
+  switch (s) {
+    case GP_OK: return "ok";
+    case GP_E_ARG: return "invalid argument";
+    case GP_E_SIZE: return "unsupported grid size (even 8..512, factors 2, 3, 5 with 3 and 5 at most once)";
+    case GP_E_DEVICE: return "HIP runtime error";
+    case GP_E_NONFINITE: return "wave function became non-finite";
+    case GP_E_STATE: return "call out of order (set psi first)";
+    case GP_E_NOMEM: return "host allocation failed";
+    default: return "unknown status";
+  }
+}
+
+gp_status gp_set_psi(gp_ctx* c, const void* psi, int on_device) {
+  clear_stale_error();
+  if (!c || !psi) return GP_E_ARG;
+  GP_TRY(c->fp64 ? Passes<double>::set_psi(c, psi, on_device)
+                 : Passes<float>::set_psi(c, psi, on_device));
+  c->psi_set = true;
+  c->ekz_valid = false;
+  return GP_OK;
+}
+
+gp_status gp_get_psi(gp_ctx* c, void* psi, int on_device) {
+  clear_stale_error();
+  if (!c || !psi) return GP_E_ARG;
+  if (!c->psi_set) return GP_E_STATE;
+  GP_TRY(c->fp64 ? Passes<double>::get_psi(c, psi, on_device)
+                 : Passes<float>::get_psi(c, psi, on_device));
+  return on_device ? GP_OK : check_flags(c);
+}
+
+gp_status gp_set_potential(gp_ctx* c, const void* V, int on_device) {
+  clear_stale_error();
+  if (!c || !V) return GP_E_ARG;
+  return c->fp64 ? Passes<double>::set_potential(c, V, on_device)
+                 : Passes<float>::set_potential(c, V, on_device);
+}
+
+gp_status gp_set_couplings(gp_ctx* c, double g, double gdd) {
+  if (!c || !isfinite(g) || !isfinite(gdd)) return GP_E_ARG;
+  c->p.g = g;
+  c->p.gdd = gdd;
+  c->gc = contact(c->p);
+  return GP_OK;
+}
+
+gp_status gp_step_imag(gp_ctx* c, int nsteps) { return run_steps(c, nsteps, true); }
+gp_status gp_step_real(gp_ctx* c, int nsteps) { return run_steps(c, nsteps, false); }
+
+gp_status gp_energy(gp_ctx* c, gp_observables* out) {
+  clear_stale_error();
+  if (!c || !out) return GP_E_ARG;
+  if (!c->psi_set) return GP_E_STATE;
+  GP_TRY(c->fp64 ? Passes<double>::observe(c) : Passes<float>::observe(c));
+  double rec[kRecord];
+  GP_HIP(hipMemcpyAsync(rec, c->at<double>(c->L.o_obs), sizeof(rec), hipMemcpyDeviceToHost, c->st));
+  GP_HIP(hipStreamSynchronize(c->st));
+  out->norm = rec[0];
+  out->mu = rec[1];
+  out->energy = rec[2];
+  out->e_kin = rec[3];
+  out->e_pot = rec[4];
+  out->e_int = rec[5];
+  out->e_dd = rec[6];
+  out->rms[0] = rec[7];
+  out->rms[1] = rec[8];
+  out->rms[2] = rec[9];
+  return check_flags(c);
+}
+
+gp_status gp_dipolar_potential(gp_ctx* c, void* phi, int on_device) {
+  clear_stale_error();
+  if (!c || !phi) return GP_E_ARG;
+  if (!c->psi_set) return GP_E_STATE;
+  return c->fp64 ? Passes<double>::dipolar(c, phi, on_device)
+                 : Passes<float>::dipolar(c, phi, on_device);
+}
+
+int gp_history_capacity(void) { return kRingCap; }
+
+const char* gp_last_error(void) { return g_last_error; }
+
+gp_status gp_history(gp_ctx* c, gp_observables* out, int max_records, int* count) {
+  clear_stale_error();
+  if (!c || !count || max_records < 0 || (max_records > 0 && !out)) return GP_E_ARG;
+  int pos = 0;
+  GP_HIP(hipMemcpyAsync(&pos, &c->sc()->ring_pos, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  GP_HIP(hipStreamSynchronize(c->st));
+  int avail = pos < kRingCap ? pos : kRingCap;
+  int n = avail < max_records ? avail : max_records;
+  if (n > 0) {
+    double* ring = new (std::nothrow) double[(size_t)kRecord * kRingCap];
+    if (!ring) return GP_E_NOMEM;
+    const hipError_t e = hipMemcpyAsync(ring, c->at<double>(c->L.o_ring),
+                                        sizeof(double) * kRecord * kRingCap,
+                                        hipMemcpyDeviceToHost, c->st);
+    const hipError_t e2 = (e == hipSuccess) ? hipStreamSynchronize(c->st) : e;
+    if (e2 != hipSuccess) {
+      delete[] ring;
+      return GP_E_DEVICE;
+    }
+    for (int r = 0; r < n; ++r) {
+      const double* rec = ring + (size_t)((pos - n + r) % kRingCap) * kRecord;
+      out[r].norm = rec[0];
+      out[r].mu = rec[1];
+      out[r].energy = rec[2];
+      out[r].e_kin = rec[3];
+      out[r].e_pot = rec[4];
+      out[r].e_int = rec[5];
+      out[r].e_dd = rec[6];
+      out[r].rms[0] = rec[7];
+      out[r].rms[1] = rec[8];
+      out[r].rms[2] = rec[9];
+    }
+    delete[] ring;
+  }
+  *count = n;
+  return check_flags(c);
+}
+
+gp_status gp_sync(gp_ctx* c) {
+  clear_stale_error();
+  if (!c) return GP_E_ARG;
+  return check_flags(c);
+}
+
+}  // extern "C"

@@ -1,0 +1,355 @@
+// Device building blocks for the dipolar GP split-step Crank-Nicolson step on gfx950:
+//   * cpx<T>            interleaved complex value (float or double)
+//   * LdsFFT            batched mixed-radix (2, 3, 4, 5) Stockham FFT of lines held in LDS
+//   * cn_solve_lines    constant-coefficient tridiagonal Crank-Nicolson solves of lines in
+//                       LDS, several lanes per line, exact chunked scan of the two Thomas
+//                       recurrences across the lanes (wave shuffles)
+//   * block_sum         deterministic FP64 block reductions
+// All kernels run with 256 threads per block (4 wave64s).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gpdbec {
+
+constexpr int kThreads = 256;
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cpx {
+  T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> mk(T r, T i) { return cpx<T>{r, i}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> operator*(cpx<T> a, cpx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> scl(cpx<T> a, T s) { return {a.re * s, a.im * s}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> conjg(cpx<T> a) { return {a.re, -a.im}; }
+// multiply by -i (forward) or +i (inverse)
+template <typename T, bool INV>
+__device__ __forceinline__ cpx<T> mul_mi(cpx<T> a) {
+  return INV ? cpx<T>{-a.im, a.re} : cpx<T>{a.im, -a.re};
+}
+
+// |a|^2 with the operands widened to double first (reductions accumulate in FP64).
+template <typename T>
+__device__ __forceinline__ double abs2_d(cpx<T> a) {
+  const double r = (double)a.re, i = (double)a.im;
+  return r * r + i * i;
+}
+template <typename T>
+__device__ __forceinline__ double absdiff2_d(cpx<T> a, cpx<T> b) {
+  const double r = (double)a.re - (double)b.re, i = (double)a.im - (double)b.im;
+  return r * r + i * i;
+}
+
+// ------------------------------------------------------------------ radix plan
+struct RadixPlan {
+  int n;
+  int r[16];
+};
+constexpr RadixPlan make_plan(int N) {
+  RadixPlan p{0, {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
+  int m = N;
+  while (m % 4 == 0) { p.r[p.n++] = 4; m /= 4; }
+  while (m % 2 == 0) { p.r[p.n++] = 2; m /= 2; }
+  while (m % 3 == 0) { p.r[p.n++] = 3; m /= 3; }
+  while (m % 5 == 0) { p.r[p.n++] = 5; m /= 5; }
+  return p;
+}
+constexpr bool plan_ok(int N) {
+  int m = N;
+  while (m % 2 == 0) m /= 2;
+  while (m % 3 == 0) m /= 3;
+  while (m % 5 == 0) m /= 5;
+  return m == 1;
+}
+constexpr int plan_span(int N, int s) {  // product of the radices before stage s
+  RadixPlan p = make_plan(N);
+  int L = 1;
+  for (int i = 0; i < s; ++i) L *= p.r[i];
+  return L;
+}
+
+// -------------------------------------------------------------- small DFTs
+template <typename T, bool INV>
+__device__ __forceinline__ void dft2(cpx<T>* x) {
+  const cpx<T> a = x[0], b = x[1];
+  x[0] = a + b;
+  x[1] = a - b;
+}
+template <typename T, bool INV>
+__device__ __forceinline__ void dft4(cpx<T>* x) {
+  const cpx<T> s02 = x[0] + x[2], d02 = x[0] - x[2];
+  const cpx<T> s13 = x[1] + x[3], d13 = mul_mi<T, INV>(x[1] - x[3]);
+  x[0] = s02 + s13;
+  x[2] = s02 - s13;
+  x[1] = d02 + d13;
+  x[3] = d02 - d13;
+}
+template <typename T, bool INV>
+__device__ __forceinline__ void dft3(cpx<T>* x) {
+  // W3 = exp(-2 pi i/3) = -1/2 - i sqrt(3)/2 (forward)
+  const T h = (T)0.5;
+  const T s = INV ? (T)-0.86602540378443864676 : (T)0.86602540378443864676;
+  const cpx<T> t1 = x[1] + x[2], t2 = x[1] - x[2];
+  const cpx<T> m = x[0] - scl(t1, h);
+  const cpx<T> r = {s * t2.im, -s * t2.re};  // -i s t2
+  x[0] = x[0] + t1;
+  x[1] = m + r;
+  x[2] = m - r;
+}
+template <typename T, bool INV>
+__device__ __forceinline__ void dft5(cpx<T>* x) {
+  const T c1 = (T)0.30901699437494742410, c2 = (T)-0.80901699437494742410;
+  const T s1 = INV ? (T)-0.95105651629515357212 : (T)0.95105651629515357212;
+  const T s2 = INV ? (T)-0.58778525229247312917 : (T)0.58778525229247312917;
+  const cpx<T> t1 = x[1] + x[4], t2 = x[2] + x[3];
+  const cpx<T> t3 = x[1] - x[4], t4 = x[2] - x[3];
+  const cpx<T> a1 = x[0] + scl(t1, c1) + scl(t2, c2);
+  const cpx<T> a2 = x[0] + scl(t1, c2) + scl(t2, c1);
+  const cpx<T> u1 = scl(t3, s1) + scl(t4, s2);   // multiplied by -i below
+  const cpx<T> u2 = scl(t3, s2) - scl(t4, s1);
+  const cpx<T> b1 = {u1.im, -u1.re};
+  const cpx<T> b2 = {u2.im, -u2.re};
+  x[0] = x[0] + t1 + t2;
+  x[1] = a1 + b1;
+  x[4] = a1 - b1;
+  x[2] = a2 + b2;
+  x[3] = a2 - b2;
+}
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dft(cpx<T>* x) {
+  if constexpr (R == 2) dft2<T, INV>(x);
+  else if constexpr (R == 3) dft3<T, INV>(x);
+  else if constexpr (R == 4) dft4<T, INV>(x);
+  else dft5<T, INV>(x);
+}
+
+// --------------------------------------------------------------- LDS FFT
+// NL lines of length N live in LDS; element (line l, index i) at buf[l*LS + i*ES].
+// tw[k] = exp(-2 pi i k/N), k < N, in LDS.  LINE_FAST selects which of (line,
+// butterfly) varies fastest across threads: true for column tiles (LS = 1), false for
+// contiguous rows (ES = 1), so that neighbouring lanes touch neighbouring addresses.
+// Every thread of the block must call run(); it synchronises the block internally and
+// returns after a final barrier.  Forward: unnormalised exp(-i...); INV: exp(+i...).
+template <typename T, int N, int NL, int LS, int ES, bool LINE_FAST>
+struct LdsFFT {
+  static constexpr RadixPlan P = make_plan(N);
+  static_assert(plan_ok(N), "FFT length must factor into 2, 3, 5");
+
+  template <int S, bool INV>
+  __device__ static __forceinline__ void stage(cpx<T>* buf, const cpx<T>* tw) {
+    if constexpr (S < P.n) {
+      constexpr int R = P.r[S];
+      constexpr int L = plan_span(N, S);
+      constexpr int NB = N / R;                 // butterflies per line
+      constexpr int TOT = NL * NB;
+      constexpr int IT = (TOT + kThreads - 1) / kThreads;
+      constexpr int TWS = N / (L * R);
+      cpx<T> v[IT][R];
+      const int tid = threadIdx.x;
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int u = tid + it * kThreads;
+        if (TOT % kThreads == 0 || u < TOT) {
+          const int l = LINE_FAST ? (u % NL) : (u / NB);
+          const int t = LINE_FAST ? (u / NL) : (u % NB);
+          const int j = t % L;
+          cpx<T>* base = buf + l * LS;
+#pragma unroll
+          for (int m = 0; m < R; ++m) v[it][m] = base[(t + m * NB) * ES];
+          if (L > 1) {
+#pragma unroll
+            for (int m = 1; m < R; ++m) {
+              cpx<T> w = tw[j * m * TWS];
+              if (INV) w.im = -w.im;
+              v[it][m] = v[it][m] * w;
+            }
+          }
+          dft<T, R, INV>(v[it]);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int u = tid + it * kThreads;
+        if (TOT % kThreads == 0 || u < TOT) {
+          const int l = LINE_FAST ? (u % NL) : (u / NB);
+          const int t = LINE_FAST ? (u / NL) : (u % NB);
+          const int j = t % L;
+          cpx<T>* base = buf + l * LS;
+          const int o = (t - j) * R + j;
+#pragma unroll
+          for (int m = 0; m < R; ++m) base[(o + m * L) * ES] = v[it][m];
+        }
+      }
+      __syncthreads();
+      stage<S + 1, INV>(buf, tw);
+    }
+  }
+
+  template <bool INV>
+  __device__ static void run(cpx<T>* buf, const cpx<T>* tw) {
+    stage<0, INV>(buf, tw);
+  }
+};
+
+// ---------------------------------------------------- Crank-Nicolson line solves
+// Chunk-padded position of element i for a line split into chunks of S elements: one
+// spare slot after every chunk keeps the P lanes of a line on distinct LDS banks.
+template <int S>
+__device__ __forceinline__ int cpad(int i) { return i + i / S; }
+
+template <typename T>
+__device__ __forceinline__ cpx<T> shfl_up_c(cpx<T> v, int off, int width) {
+  return {__shfl_up(v.re, off, width), __shfl_up(v.im, off, width)};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> shfl_down_c(cpx<T> v, int off, int width) {
+  return {__shfl_down(v.re, off, width), __shfl_down(v.im, off, width)};
+}
+
+// Solve, for NL lines of N points (two Dirichlet end points included) held in LDS at
+// buf[l*LS + cpad<S>(i)*ES] with S = ceil(N/P):
+//     -A u_{i-1} + (1+2A) u_i - A u_{i+1} = A p_{i-1} + (1-2A) p_i + A p_{i+1},  0 < i < N-1,
+//     u_0 = u_{N-1} = 0,
+// and overwrite the line with u.  Thomas elimination with the data-independent factors
+// precomputed per axis: m_i = 1/(b - a c_{i-1}) and g_i = A m_i (= -c_i), so that
+//     forward   d_i = m_i r_i + g_i d_{i-1}
+//     backward  u_i = d_i + g_i u_{i+1}
+// (m = g = 0 on the two boundary rows makes them u = 0).  Each recurrence is an affine
+// map per chunk, composed across the P lanes of a line by a Hillis-Steele scan of
+// (gain, offset) pairs through wave shuffles, then re-run with the exact carry-in.
+// P divides 64, so one line never spans two waves.  Every thread must call this.
+template <typename T, int N, int NL, int LS, int ES, int P>
+__device__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt, const cpx<T>* gt,
+                               cpx<T> A, cpx<T> B) {
+  static_assert(64 % P == 0 && NL * P == kThreads, "lanes per line");
+  constexpr int S = (N + P - 1) / P;
+  const int tid = threadIdx.x;
+  const int l = tid / P, q = tid % P;
+  const int lo = q * S;
+  cpx<T>* line = buf + l * LS;
+  cpx<T> r[S];
+  // right-hand side of the explicit half
+#pragma unroll
+  for (int e = 0; e < S; ++e) {
+    const int i = lo + e;
+    r[e] = cpx<T>{0, 0};
+    if (i >= 1 && i <= N - 2) {
+      const cpx<T> pm = line[cpad<S>(i - 1) * ES];
+      const cpx<T> p0 = line[cpad<S>(i) * ES];
+      const cpx<T> pp = line[cpad<S>(i + 1) * ES];
+      r[e] = A * (pm + pp) + B * p0;
+    }
+  }
+  // forward recurrence: local affine map (G, D): d_out = G d_in + D
+  cpx<T> G = {1, 0}, D = {0, 0};
+#pragma unroll
+  for (int e = 0; e < S; ++e) {
+    const int i = lo + e;
+    if (i < N) {
+      const cpx<T> m = mt[i], g = gt[i];
+      D = m * r[e] + g * D;
+      G = g * G;
+    }
+  }
+  cpx<T> din = {0, 0};
+  if constexpr (P > 1) {
+#pragma unroll
+    for (int off = 1; off < P; off <<= 1) {
+      const cpx<T> Gp = shfl_up_c(G, off, P), Dp = shfl_up_c(D, off, P);
+      if (q >= off) {
+        D = G * Dp + D;
+        G = G * Gp;
+      }
+    }
+    din = shfl_up_c(D, 1, P);
+    if (q == 0) din = cpx<T>{0, 0};
+  }
+  {
+    cpx<T> d = din;
+#pragma unroll
+    for (int e = 0; e < S; ++e) {
+      const int i = lo + e;
+      if (i < N) {
+        d = mt[i] * r[e] + gt[i] * d;
+        r[e] = d;
+      }
+    }
+  }
+  // backward recurrence: local map u_lo = G u_in + X, u_in = u at the next chunk start
+  G = cpx<T>{1, 0};
+  cpx<T> X = {0, 0};
+#pragma unroll
+  for (int e = S - 1; e >= 0; --e) {
+    const int i = lo + e;
+    if (i < N) {
+      const cpx<T> g = gt[i];
+      X = r[e] + g * X;
+      G = g * G;
+    }
+  }
+  cpx<T> xin = {0, 0};
+  if constexpr (P > 1) {
+#pragma unroll
+    for (int off = 1; off < P; off <<= 1) {
+      const cpx<T> Gn = shfl_down_c(G, off, P), Xn = shfl_down_c(X, off, P);
+      if (q + off < P) {
+        X = G * Xn + X;
+        G = G * Gn;
+      }
+    }
+    xin = shfl_down_c(X, 1, P);
+    if (q == P - 1) xin = cpx<T>{0, 0};
+  }
+  {
+    cpx<T> x = xin;
+#pragma unroll
+    for (int e = S - 1; e >= 0; --e) {
+      const int i = lo + e;
+      if (i < N) {
+        x = r[e] + gt[i] * x;
+        r[e] = x;
+      }
+    }
+  }
+  __syncthreads();  // every lane has read its neighbours
+#pragma unroll
+  for (int e = 0; e < S; ++e) {
+    const int i = lo + e;
+    if (i < N) line[cpad<S>(i) * ES] = r[e];
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------- reductions
+// Deterministic FP64 block sum of NV values per thread; result valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* red /* LDS kThreads*NV */) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) red[k * kThreads + tid] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) red[k * kThreads + tid] += red[k * kThreads + tid + s];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = red[k * kThreads];
+}
+
+}  // namespace gpdbec

@@ -1,0 +1,375 @@
+// Pass kernels of one split-step Crank-Nicolson step (templated on precision and on the
+// line length of the axis they work along).
+//
+// Grid: (n2, n1, n0) with x = axis 0 fastest; 3D: n1 = ny, n2 = nz; 2D: n1 = ny (XY) or
+// nz (XZ), n2 = 1.  psi is stored "lazily scaled": the physical wave function is
+// scale * psi, with scale an FP64 device scalar (1 except after an imaginary-time step,
+// whose renormalisation factor is applied by the next pass that reads psi).
+//
+// Spectrum of the density (after the x real-to-complex transform) is stored
+// kx-plane-major, spec[(kx*n2 + k2)*n1 + k1], kx = 0..n0/2, so that the y lines are
+// contiguous, the z lines are strided by n1, and one x line of the spectrum is a set
+// of n0/2+1 contiguous runs over k1 (coalesced when a block owns several k1).
+//
+// Pass order of one 3D step (2D: r2c_x, conv_line, c2r_nl_cnx, cn_col(last), finalize):
+//   r2c_x        n = s^2|psi|^2, x-R2C (two real lines packed per complex FFT);
+//                kinetic x/y difference sums of the incoming state
+//   fft_line     y FFT (forward)
+//   conv_col     z FFT, multiply by U(k)/N, inverse z FFT
+//   fft_line     y FFT (inverse)
+//   c2r_nl_cnx   x-C2R -> Phi; norm/V/contact/dipolar/rms sums of the incoming state;
+//                psi <- psi exp(-eps dt theta); CN sweep along x
+//   cn_col       CN sweep along y
+//   cn_col       CN sweep along z; norm and z-kinetic sums of the new state
+//   finalize     FP64 totals, observables record, renormalisation factor
+#pragma once
+#include "gp_device.hpp"
+
+namespace gpdbec {
+
+// Lines per block for passes along x, columns per block for strided passes.
+template <typename T, int N>
+struct Tiles {
+  // x lines per block (even): 16, or 8 when a line of complex T exceeds 4 KiB (LDS)
+  static constexpr int TJ = (N * 2 * (int)sizeof(T) > 4096) ? 8 : 16;
+  static constexpr int PX = kThreads / TJ;          // lanes per x line in the CN solve
+  static constexpr int TC = (sizeof(T) == 8 && N > 256) ? 8 : 16;  // columns per block
+  static constexpr int PC = kThreads / TC;
+  static constexpr int LB = (2048 / N) < 1 ? 1 : (2048 / N);        // contiguous lines
+};
+
+struct StepScalars {
+  double dt;        // time step
+  double gc;        // contact coupling (2D: includes 1/(sqrt(2 pi) d))
+  double gdd;       // dipolar coupling
+  double Ar;        // dt/(4 dx^2): A = Ar (imaginary) or i Ar (real time)
+  double h0, h1, h2;  // spacings along axes 0, 1, 2
+};
+
+enum : int { MODE_IMAG = 0, MODE_REAL = 1, MODE_OBSERVE = 2, MODE_PHI = 3 };
+
+// ---------------------------------------------------------------- pass: r2c_x
+// grid: ceil(n1/TJ) * n2 blocks.  partials[b*2 + {0,1}] = sum |dx psi|^2, sum |dy psi|^2
+// of the stored psi (unscaled), the y difference reaching one line past the tile.
+template <typename T, int N0>
+__global__ __launch_bounds__(kThreads) void k_r2c_x(const cpx<T>* __restrict__ psi,
+                                                    const double* __restrict__ scale,
+                                                    cpx<T>* __restrict__ spec,
+                                                    const cpx<T>* __restrict__ tw0,
+                                                    double* __restrict__ partials, int n1, int n2) {
+  using TL = Tiles<T, N0>;
+  constexpr int TJ = TL::TJ, NP = TJ / 2, H = N0 / 2 + 1, LSZ = N0 + 1;
+  __shared__ cpx<T> Z[NP * LSZ];
+  __shared__ cpx<T> W[N0];
+  __shared__ double red[2 * kThreads];
+  const int tid = threadIdx.x;
+  const int nt1 = (n1 + TJ - 1) / TJ;
+  const int k2 = blockIdx.x / nt1;
+  const int j0 = (blockIdx.x % nt1) * TJ;
+  const double s = *scale;
+  const T s2 = (T)(s * s);
+  for (int i = tid; i < N0; i += kThreads) W[i] = tw0[i];
+  double sums[2] = {0.0, 0.0};
+  for (int u = tid; u < TJ * N0; u += kThreads) {
+    const int jl = u / N0, i = u % N0;
+    const int j = j0 + jl;
+    T nv = 0;
+    if (j < n1) {
+      const cpx<T>* line = psi + ((size_t)k2 * n1 + j) * N0;
+      const cpx<T> a = line[i];
+      nv = s2 * (a.re * a.re + a.im * a.im);
+      if (i + 1 < N0) sums[0] += absdiff2_d(line[i + 1], a);
+      if (j + 1 < n1) sums[1] += absdiff2_d(line[i + N0], a);
+    }
+    T* zc = reinterpret_cast<T*>(&Z[(jl >> 1) * LSZ + i]);
+    zc[jl & 1] = nv;
+  }
+  __syncthreads();
+  LdsFFT<T, N0, NP, LSZ, 1, false>::template run<false>(Z, W);
+  // untangle the two real lines of each pair and store kx = 0..N0/2
+  for (int u = tid; u < H * NP; u += kThreads) {
+    const int p = u % NP, kx = u / NP;
+    const int j = j0 + 2 * p;
+    if (j >= n1) continue;
+    const cpx<T> zk = Z[p * LSZ + kx];
+    const cpx<T> zm = Z[p * LSZ + ((N0 - kx) % N0)];
+    const T hf = (T)0.5;
+    cpx<T> a = {hf * (zk.re + zm.re), hf * (zk.im - zm.im)};
+    cpx<T> b = {hf * (zk.im + zm.im), hf * (zm.re - zk.re)};
+    cpx<T>* o = spec + ((size_t)kx * n2 + k2) * n1 + j;
+    o[0] = a;
+    o[1] = b;  // n1 is even, so line j+1 exists whenever line j does
+  }
+  block_sum<2>(sums, red);
+  if (tid == 0) {
+    partials[blockIdx.x * 2 + 0] = sums[0];
+    partials[blockIdx.x * 2 + 1] = sums[1];
+  }
+}
+
+// -------------------------------------------------------------- pass: fft_line
+// FFT of contiguous lines of length N (count nlines), LB lines per block.
+template <typename T, int N, bool INV>
+__global__ __launch_bounds__(kThreads) void k_fft_line(cpx<T>* __restrict__ data,
+                                                       const cpx<T>* __restrict__ tw, int nlines) {
+  constexpr int LB = Tiles<T, N>::LB, LSZ = N + 1;
+  __shared__ cpx<T> B[LB * LSZ];
+  __shared__ cpx<T> W[N];
+  const int tid = threadIdx.x;
+  const int l0 = blockIdx.x * LB;
+  for (int i = tid; i < N; i += kThreads) W[i] = tw[i];
+  for (int u = tid; u < LB * N; u += kThreads) {
+    const int l = u / N, i = u % N;
+    B[l * LSZ + i] = (l0 + l < nlines) ? data[(size_t)(l0 + l) * N + i] : cpx<T>{0, 0};
+  }
+  __syncthreads();
+  LdsFFT<T, N, LB, LSZ, 1, false>::template run<INV>(B, W);
+  for (int u = tid; u < LB * N; u += kThreads) {
+    const int l = u / N, i = u % N;
+    if (l0 + l < nlines) data[(size_t)(l0 + l) * N + i] = B[l * LSZ + i];
+  }
+}
+
+// FFT -> multiply by the kernel table -> inverse FFT of contiguous lines (2D: y lines).
+template <typename T, int N>
+__global__ __launch_bounds__(kThreads) void k_conv_line(cpx<T>* __restrict__ data,
+                                                        const T* __restrict__ ktab,
+                                                        const cpx<T>* __restrict__ tw, int nlines) {
+  constexpr int LB = Tiles<T, N>::LB, LSZ = N + 1;
+  __shared__ cpx<T> B[LB * LSZ];
+  __shared__ cpx<T> W[N];
+  const int tid = threadIdx.x;
+  const int l0 = blockIdx.x * LB;
+  for (int i = tid; i < N; i += kThreads) W[i] = tw[i];
+  for (int u = tid; u < LB * N; u += kThreads) {
+    const int l = u / N, i = u % N;
+    B[l * LSZ + i] = (l0 + l < nlines) ? data[(size_t)(l0 + l) * N + i] : cpx<T>{0, 0};
+  }
+  __syncthreads();
+  LdsFFT<T, N, LB, LSZ, 1, false>::template run<false>(B, W);
+  for (int u = tid; u < LB * N; u += kThreads) {
+    const int l = u / N, i = u % N;
+    const T k = (l0 + l < nlines) ? ktab[(size_t)(l0 + l) * N + i] : (T)0;
+    B[l * LSZ + i] = scl(B[l * LSZ + i], k);
+  }
+  __syncthreads();
+  LdsFFT<T, N, LB, LSZ, 1, false>::template run<true>(B, W);
+  for (int u = tid; u < LB * N; u += kThreads) {
+    const int l = u / N, i = u % N;
+    if (l0 + l < nlines) data[(size_t)(l0 + l) * N + i] = B[l * LSZ + i];
+  }
+}
+
+// --------------------------------------------------------------- pass: conv_col
+// 3D z pass on the spectrum: lines along k2 (stride n1) inside each kx plane; a block
+// owns TC consecutive k1 of one kx plane.  grid: ceil(n1/TC) * H blocks.
+template <typename T, int N2>
+__global__ __launch_bounds__(kThreads) void k_conv_col(cpx<T>* __restrict__ spec,
+                                                       const T* __restrict__ ktab,
+                                                       const cpx<T>* __restrict__ tw2, int n1) {
+  constexpr int TC = Tiles<T, N2>::TC, RS = TC + 1;
+  __shared__ cpx<T> B[N2 * RS];
+  __shared__ cpx<T> W[N2];
+  const int tid = threadIdx.x;
+  const int nt = (n1 + TC - 1) / TC;
+  const int kx = blockIdx.x / nt;
+  const int c0 = (blockIdx.x % nt) * TC;
+  for (int i = tid; i < N2; i += kThreads) W[i] = tw2[i];
+  const size_t plane = (size_t)kx * N2 * n1;
+  for (int u = tid; u < N2 * TC; u += kThreads) {
+    const int c = u % TC, r = u / TC;
+    B[r * RS + c] = (c0 + c < n1) ? spec[plane + (size_t)r * n1 + c0 + c] : cpx<T>{0, 0};
+  }
+  __syncthreads();
+  LdsFFT<T, N2, TC, 1, RS, true>::template run<false>(B, W);
+  for (int u = tid; u < N2 * TC; u += kThreads) {
+    const int c = u % TC, r = u / TC;
+    const T k = (c0 + c < n1) ? ktab[plane + (size_t)r * n1 + c0 + c] : (T)0;
+    B[r * RS + c] = scl(B[r * RS + c], k);
+  }
+  __syncthreads();
+  LdsFFT<T, N2, TC, 1, RS, true>::template run<true>(B, W);
+  for (int u = tid; u < N2 * TC; u += kThreads) {
+    const int c = u % TC, r = u / TC;
+    if (c0 + c < n1) spec[plane + (size_t)r * n1 + c0 + c] = B[r * RS + c];
+  }
+}
+
+// ------------------------------------------------------------ pass: c2r_nl_cnx
+// grid: ceil(n1/TJ) * n2 blocks.  MODE_IMAG / MODE_REAL: full step pass (writes psi).
+// MODE_OBSERVE: sums only.  MODE_PHI: writes Phi (without g_dd) to phi_out.
+// partials[b*7 + ...] = sum n, sum V n, sum n^2, sum Phi n, sum x^2 n, sum y^2 n, sum z^2 n
+// of the incoming (scaled) state; axis coordinates (idx - n/2) h.
+template <typename T, int N0, int MODE>
+__global__ __launch_bounds__(kThreads) void k_c2r_nl_cnx(
+    cpx<T>* __restrict__ psi, const T* __restrict__ V, const double* __restrict__ scale,
+    const cpx<T>* __restrict__ spec, const cpx<T>* __restrict__ tw0,
+    const cpx<T>* __restrict__ cnm, const cpx<T>* __restrict__ cng, StepScalars sc,
+    double* __restrict__ partials, T* __restrict__ phi_out, int n1, int n2) {
+  using TL = Tiles<T, N0>;
+  constexpr int TJ = TL::TJ, NP = TJ / 2, H = N0 / 2 + 1, LSZ = N0 + 1;
+  constexpr int PX = TL::PX, SX = (N0 + PX - 1) / PX, LSP = N0 + (N0 + SX - 1) / SX;
+  constexpr bool STEP = (MODE == MODE_IMAG || MODE == MODE_REAL);
+  __shared__ cpx<T> Z[NP * LSZ];
+  __shared__ cpx<T> PS[STEP ? TJ * LSP : 1];
+  __shared__ cpx<T> W[N0];
+  __shared__ cpx<T> MT[STEP ? N0 : 1], GT[STEP ? N0 : 1];
+  __shared__ double red[7 * kThreads];
+  const int tid = threadIdx.x;
+  const int nt1 = (n1 + TJ - 1) / TJ;
+  const int k2 = blockIdx.x / nt1;
+  const int j0 = (blockIdx.x % nt1) * TJ;
+  const double s = *scale;
+  for (int i = tid; i < N0; i += kThreads) {
+    W[i] = tw0[i];
+    if constexpr (STEP) {
+      MT[i] = cnm[i];
+      GT[i] = cng[i];
+    }
+  }
+  // gather the Hermitian half spectrum of each line pair into a full complex line
+  for (int u = tid; u < H * NP; u += kThreads) {
+    const int p = u % NP, kx = u / NP;
+    const int j = j0 + 2 * p;
+    cpx<T> a = {0, 0}, b = {0, 0};
+    if (j < n1) {
+      const cpx<T>* o = spec + ((size_t)kx * n2 + k2) * n1 + j;
+      a = o[0];
+      b = o[1];
+    }
+    cpx<T>* z = Z + p * LSZ;
+    if (kx == 0 || kx == N0 / 2) {
+      z[kx] = cpx<T>{a.re, b.re};
+    } else {
+      z[kx] = cpx<T>{a.re - b.im, a.im + b.re};
+      z[N0 - kx] = cpx<T>{a.re + b.im, b.re - a.im};
+    }
+  }
+  __syncthreads();
+  LdsFFT<T, N0, NP, LSZ, 1, false>::template run<true>(Z, W);
+
+  double sums[7] = {0, 0, 0, 0, 0, 0, 0};
+  const T ts = (T)s;
+  const double h0 = sc.h0, h1 = sc.h1, h2 = sc.h2;
+  for (int u = tid; u < TJ * N0; u += kThreads) {
+    const int jl = u / N0, i = u % N0;
+    const int j = j0 + jl;
+    if (j >= n1) {
+      if constexpr (STEP) PS[jl * LSP + cpad<SX>(i)] = cpx<T>{0, 0};
+      continue;
+    }
+    const size_t g = ((size_t)k2 * n1 + j) * N0 + i;
+    const T phi = reinterpret_cast<const T*>(&Z[(jl >> 1) * LSZ + i])[jl & 1];
+    if constexpr (MODE == MODE_PHI) {
+      phi_out[g] = phi;
+      continue;
+    }
+    cpx<T> p = psi[g];
+    p = scl(p, ts);
+    const T v = V[g];
+    const double nd = abs2_d(p);
+    const double xc = (i - N0 / 2) * h0, yc = (j - n1 / 2) * h1, zc = (k2 - n2 / 2) * h2;
+    sums[0] += nd;
+    sums[1] += (double)v * nd;
+    sums[2] += nd * nd;
+    sums[3] += (double)phi * nd;
+    sums[4] += xc * xc * nd;
+    sums[5] += yc * yc * nd;
+    sums[6] += zc * zc * nd;
+    if constexpr (STEP) {
+      const T n = p.re * p.re + p.im * p.im;
+      const T th = (T)sc.dt * (v + (T)sc.gc * n + (T)sc.gdd * phi);
+      cpx<T> f;
+      if constexpr (MODE == MODE_IMAG) {
+        f = cpx<T>{exp(-th), (T)0};
+      } else {
+        f = cpx<T>{cos(th), -sin(th)};
+      }
+      PS[jl * LSP + cpad<SX>(i)] = p * f;
+    }
+  }
+  if constexpr (MODE != MODE_PHI) {
+    block_sum<7>(sums, red);
+    if (tid == 0) {
+#pragma unroll
+      for (int k = 0; k < 7; ++k) partials[blockIdx.x * 7 + k] = sums[k];
+    }
+  }
+  if constexpr (STEP) {
+    __syncthreads();
+    const cpx<T> A = (MODE == MODE_IMAG) ? cpx<T>{(T)sc.Ar, 0} : cpx<T>{0, (T)sc.Ar};
+    const cpx<T> B = (MODE == MODE_IMAG) ? cpx<T>{(T)(1.0 - 2.0 * sc.Ar), 0}
+                                         : cpx<T>{(T)1, (T)(-2.0 * sc.Ar)};
+    cn_solve_lines<T, N0, TJ, LSP, 1, PX>(PS, MT, GT, A, B);
+    for (int u = tid; u < TJ * N0; u += kThreads) {
+      const int jl = u / N0, i = u % N0;
+      const int j = j0 + jl;
+      if (j < n1) psi[((size_t)k2 * n1 + j) * N0 + i] = PS[jl * LSP + cpad<SX>(i)];
+    }
+  }
+}
+
+// ----------------------------------------------------------------- pass: cn_col
+// CN sweep along a strided axis: lines of length N with element stride `estride`;
+// a block owns TC consecutive x columns (x0..x0+TC-1) of one "outer" index.
+//   y sweep (3D/2D): estride = n0, outer = k2 (n_outer = n2), base = k2*n1*n0
+//   z sweep (3D):    estride = n0*n1, outer = k1 (n_outer = n1), base = k1*n0
+// SUMS: also partials[b*2+{0,1}] = sum |u|^2, sum |u_{i+1}-u_i|^2 along the line of the
+// result (MODE_OBSERVE: of the stored input, nothing written; sums unscaled).
+// grid: ceil(n0/TC) * n_outer blocks.
+template <typename T, int N, int MODE, bool SUMS>
+__global__ __launch_bounds__(kThreads) void k_cn_col(cpx<T>* __restrict__ psi,
+                                                     const cpx<T>* __restrict__ cnm,
+                                                     const cpx<T>* __restrict__ cng,
+                                                     double Ar, double* __restrict__ partials,
+                                                     int n0, size_t estride, size_t ostride) {
+  using TL = Tiles<T, N>;
+  constexpr int TC = TL::TC, PC = TL::PC, SC = (N + PC - 1) / PC, RS = TC + 1;
+  constexpr int NR = N + (N + SC - 1) / SC;  // padded rows
+  constexpr bool SOLVE = (MODE == MODE_IMAG || MODE == MODE_REAL);
+  __shared__ cpx<T> B[NR * RS];
+  __shared__ cpx<T> MT[SOLVE ? N : 1], GT[SOLVE ? N : 1];
+  __shared__ double red[2 * kThreads];
+  const int tid = threadIdx.x;
+  const int nt = (n0 + TC - 1) / TC;
+  const int outer = blockIdx.x / nt;
+  const int x0 = (blockIdx.x % nt) * TC;
+  cpx<T>* base = psi + (size_t)outer * ostride + x0;
+  if constexpr (SOLVE) {
+    for (int i = tid; i < N; i += kThreads) {
+      MT[i] = cnm[i];
+      GT[i] = cng[i];
+    }
+  }
+  for (int u = tid; u < N * TC; u += kThreads) {
+    const int c = u % TC, r = u / TC;
+    B[cpad<SC>(r) * RS + c] = (x0 + c < n0) ? base[(size_t)r * estride + c] : cpx<T>{0, 0};
+  }
+  __syncthreads();
+  if constexpr (SOLVE) {
+    const cpx<T> A = (MODE == MODE_IMAG) ? cpx<T>{(T)Ar, 0} : cpx<T>{0, (T)Ar};
+    const cpx<T> Bc = (MODE == MODE_IMAG) ? cpx<T>{(T)(1.0 - 2.0 * Ar), 0}
+                                          : cpx<T>{(T)1, (T)(-2.0 * Ar)};
+    cn_solve_lines<T, N, TC, 1, RS, PC>(B, MT, GT, A, Bc);
+  }
+  double sums[2] = {0.0, 0.0};
+  for (int u = tid; u < N * TC; u += kThreads) {
+    const int c = u % TC, r = u / TC;
+    if (x0 + c >= n0) continue;
+    const cpx<T> v = B[cpad<SC>(r) * RS + c];
+    if constexpr (SOLVE) base[(size_t)r * estride + c] = v;
+    if constexpr (SUMS) {
+      sums[0] += abs2_d(v);
+      if (r + 1 < N) sums[1] += absdiff2_d(B[cpad<SC>(r + 1) * RS + c], v);
+    }
+  }
+  if constexpr (SUMS) {
+    block_sum<2>(sums, red);
+    if (tid == 0) {
+      partials[blockIdx.x * 2 + 0] = sums[0];
+      partials[blockIdx.x * 2 + 1] = sums[1];
+    }
+  }
+}
+
+}  // namespace gpdbec

@@ -1,0 +1,69 @@
+// Host-side launchers: map a runtime line length onto the compile-time specialised
+// pass kernels.  Supported line lengths (every axis): even N = 2^a 3^b 5^c with
+// b, c <= 1 and 8 <= N <= 512.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+#include "gp_device.hpp"
+
+#define GP_FOR_SIZES(X) \
+  X(8) X(10) X(12) X(16) X(20) X(24) X(30) X(32) X(40) X(48) X(60) X(64) X(80) X(96) X(120) \
+  X(128) X(160) X(192) X(240) X(256) X(320) X(384) X(480) X(512)
+
+namespace gpdbec {
+
+struct StepScalars;
+
+bool size_supported(int n);
+
+template <typename T>
+struct Launch {
+  // tile geometry of the pass kernels for line length n
+  static int tj(int n);  // x lines per block
+  static int tc(int n);  // columns per block (strided passes)
+  static int lb(int n);  // contiguous lines per block
+
+  static hipError_t r2c_x(int n0, int blocks, hipStream_t st, const cpx<T>* psi,
+                          const double* scale, cpx<T>* spec, const cpx<T>* tw0, double* part,
+                          int n1, int n2);
+  static hipError_t fft_line(int n, bool inv, int blocks, hipStream_t st, cpx<T>* data,
+                             const cpx<T>* tw, int nlines);
+  static hipError_t conv_line(int n, int blocks, hipStream_t st, cpx<T>* data, const T* ktab,
+                              const cpx<T>* tw, int nlines);
+  static hipError_t conv_col(int n2, int blocks, hipStream_t st, cpx<T>* spec, const T* ktab,
+                             const cpx<T>* tw2, int n1);
+  static hipError_t c2r_nl_cnx(int n0, int mode, int blocks, hipStream_t st, cpx<T>* psi,
+                               const T* V, const double* scale, const cpx<T>* spec,
+                               const cpx<T>* tw0, const cpx<T>* cnm, const cpx<T>* cng,
+                               const StepScalars& sc, double* part, T* phi_out, int n1, int n2);
+  static hipError_t cn_col(int n, int mode, bool sums, int blocks, hipStream_t st, cpx<T>* psi,
+                           const cpx<T>* cnm, const cpx<T>* cng, double Ar, double* part, int n0,
+                           size_t estride, size_t ostride);
+};
+
+// The members are defined (explicitly specialised) per precision in gp_inst.hip.
+#define GP_DECLARE_LAUNCH(T)                                                                  \
+  template <> int Launch<T>::tj(int);                                                         \
+  template <> int Launch<T>::tc(int);                                                         \
+  template <> int Launch<T>::lb(int);                                                         \
+  template <> hipError_t Launch<T>::r2c_x(int, int, hipStream_t, const cpx<T>*, const double*, \
+                                          cpx<T>*, const cpx<T>*, double*, int, int);          \
+  template <> hipError_t Launch<T>::fft_line(int, bool, int, hipStream_t, cpx<T>*,             \
+                                             const cpx<T>*, int);                              \
+  template <> hipError_t Launch<T>::conv_line(int, int, hipStream_t, cpx<T>*, const T*,       \
+                                              const cpx<T>*, int);                             \
+  template <> hipError_t Launch<T>::conv_col(int, int, hipStream_t, cpx<T>*, const T*,        \
+                                             const cpx<T>*, int);                              \
+  template <> hipError_t Launch<T>::c2r_nl_cnx(int, int, int, hipStream_t, cpx<T>*, const T*, \
+                                               const double*, const cpx<T>*, const cpx<T>*,    \
+                                               const cpx<T>*, const cpx<T>*,                   \
+                                               const StepScalars&, double*, T*, int, int);     \
+  template <> hipError_t Launch<T>::cn_col(int, int, bool, int, hipStream_t, cpx<T>*,         \
+                                           const cpx<T>*, const cpx<T>*, double, double*, int, \
+                                           size_t, size_t);
+GP_DECLARE_LAUNCH(float)
+GP_DECLARE_LAUNCH(double)
+#undef GP_DECLARE_LAUNCH
+
+}  // namespace gpdbec

@@ -1,0 +1,43 @@
+"""Helpers shared by the GPU parity tests: oracle parameters from a workload dict, relative
+errors, and a case banner printed (and flushed) before every GPU step."""
+import sys
+
+import numpy as np
+
+import oracle as O
+
+FP64_PSI_TOL = 1e-10     # rel-L2 of psi, FP64 mode
+FP32_PSI_TOL = 2e-5      # rel-L2 of psi, FP32 mode (FP64 reductions)
+FP64_E_TOL = 1e-12       # relative energy / mu, FP64 mode
+FP32_E_TOL = 1e-6        # relative energy / mu, FP32 mode
+
+
+def banner(*parts):
+    print("[gpu case]", *parts, flush=True)
+    sys.stdout.flush()
+
+
+def oparams(w):
+    keys = ("geom", "nx", "ny", "nz", "dx", "dy", "dz", "dt", "gamma", "nu", "lam", "g", "gdd", "R")
+    return O.Params(**{k: w[k] for k in keys if k in w})
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+def obs_close(got, ref, tol, keys=("norm", "energy", "mu", "e_kin", "e_pot", "e_int", "e_dd")):
+    bad = {}
+    scale = max(abs(ref["energy"]), abs(ref["mu"]), 1.0)
+    for k in keys:
+        # each part is compared relative to the total energy scale (parts can be ~0)
+        if abs(got[k] - ref[k]) > tol * max(abs(ref[k]), scale * 1e-3):
+            bad[k] = (got[k], ref[k])
+    for a in range(3):
+        if abs(got["rms"][a] - ref["rms"][a]) > tol * max(abs(ref["rms"][a]), 1e-3):
+            bad[f"rms{a}"] = (got["rms"][a], ref["rms"][a])
+    return bad

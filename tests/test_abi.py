@@ -1,0 +1,97 @@
+"""Host-only checks of the C-ABI library: it loads, exports every symbol the header
+declares, and validates parameters (no device work, runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1601_04640_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "gp.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(gp_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_function():
+    lib = B.load()
+    names = header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    # the binding declares exactly the header's functions
+    assert sorted(B._SIGS) == names
+
+
+def test_struct_layouts_match_header():
+    assert ctypes.sizeof(B.gp_observables) == 10 * 8
+    # int geom, 3 ints, 10 doubles, int prec (with padding)
+    assert B.gp_params.dx.offset == 16
+    assert B.gp_params.prec.offset == 16 + 10 * 8
+
+
+def test_status_strings():
+    lib = B.load()
+    for s in (0, -1, -2, -3, -4, -5, -6):
+        assert len(lib.gp_status_string(s)) > 0
+
+
+def ws(**kw):
+    base = dict(geom="3d", nx=16, ny=16, nz=16, dx=0.2, dy=0.2, dz=0.2, dt=1e-3)
+    base.update(kw)
+    return B.gp_workspace_bytes(B.make_params(**base))
+
+
+@pytest.mark.parametrize("n", [7, 9, 14, 6, 4, 514, 1024, 22, 26, 36, 90, 0, -8])
+def test_unsupported_sizes_rejected(n):
+    with pytest.raises(B.GPError) as e:
+        ws(nx=n)
+    assert e.value.status == B.GP_E_SIZE
+    with pytest.raises(B.GPError) as e:
+        ws(nz=n)
+    assert e.value.status == B.GP_E_SIZE
+
+
+@pytest.mark.parametrize("n", [8, 10, 12, 16, 20, 24, 30, 32, 40, 48, 60, 64, 80, 96, 120,
+                               128, 160, 192, 240, 256, 320, 384, 480, 512])
+def test_supported_sizes_accepted(n):
+    assert ws(nx=n, ny=8, nz=8) > 0
+
+
+@pytest.mark.parametrize("kw", [dict(dt=0.0), dict(dt=-1e-3), dict(dx=0.0), dict(dy=-0.1),
+                                dict(geom=7), dict(prec=5), dict(g=float("nan")),
+                                dict(geom="2dxy", lam=0.0), dict(geom="2dxz", nu=-1.0)])
+def test_bad_arguments_rejected(kw):
+    with pytest.raises(B.GPError) as e:
+        ws(**kw)
+    assert e.value.status == B.GP_E_ARG
+
+
+def test_2d_ignores_unused_axis():
+    a = ws(geom="2dxy", nx=64, ny=32, nz=7)       # nz ignored in XY
+    b = ws(geom="2dxz", nx=64, ny=3, nz=32)        # ny ignored in XZ
+    assert a == b
+
+
+def test_workspace_scales_with_precision_and_size():
+    assert ws(prec="fp64") > ws(prec="fp32")
+    assert ws(nx=32) > ws(nx=16)
+
+
+def test_null_arguments_rejected():
+    lib = B.load()
+    n = ctypes.c_size_t(0)
+    assert lib.gp_workspace_bytes(None, ctypes.byref(n)) == B.GP_E_ARG
+    p = B.make_params("3d", 16, 16, 16)
+    assert lib.gp_workspace_bytes(ctypes.byref(p), None) == B.GP_E_ARG
+    ctx = ctypes.c_void_p()
+    assert lib.gp_init(ctypes.byref(p), None, 0, None, ctypes.byref(ctx)) == B.GP_E_ARG
+    for fn in ("gp_step_imag", "gp_step_real"):
+        assert getattr(lib, fn)(None, 1) == B.GP_E_ARG
+    assert lib.gp_destroy(None) == B.GP_E_ARG
+    assert lib.gp_sync(None) == B.GP_E_ARG
+    assert lib.gp_history_capacity() >= 1000

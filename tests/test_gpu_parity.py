@@ -1,0 +1,172 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on the same seeded
+inputs.  Sizes are chosen so the oracle finishes in seconds while spanning several tiles
+with ragged tails (x lines are processed 16 (or 8) per block, strided columns 16 (or 8)
+per block).  Tolerances: psi rel-L2 <= 1e-10 (FP64) / 2e-5 (FP32); energy and mu
+relative <= 1e-12 (FP64) / 1e-6 (FP32)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1601_04640_amd import inputs as I
+from tests.gpu_util import (FP32_E_TOL, FP32_PSI_TOL, FP64_E_TOL, FP64_PSI_TOL, banner,
+                            obs_close, oparams, rel, rel_l2)
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    # 3D: ragged x-line tiles (ny = 20, 40 not multiples of 16), ragged column tiles
+    "3d_24x20x16": dict(geom="3d", nx=24, ny=20, nz=16, dx=0.35, dy=0.4, dz=0.45, dt=0.002,
+                        gamma=1.0, nu=1.3, lam=2.0, g=25.0, gdd=8.0, R=2.8),
+    "3d_40x30x48": dict(geom="3d", nx=40, ny=30, nz=48, dx=0.3, dy=0.35, dz=0.25, dt=0.001,
+                        gamma=1.0, nu=1.1, lam=1.8, g=30.0, gdd=12.0, R=5.0),
+    "3d_64x48x20": dict(geom="3d", nx=64, ny=48, nz=20, dx=0.25, dy=0.3, dz=0.5, dt=0.002,
+                        gamma=1.0, nu=1.0, lam=2.0, g=20.0, gdd=6.0, R=0.0),
+    "2dxy_48x40": dict(geom="2dxy", nx=48, ny=40, nz=1, dx=0.25, dy=0.3, dz=1.0, dt=0.002,
+                       gamma=1.0, nu=1.5, lam=4.0, g=30.0, gdd=10.0, R=0.0),
+    "2dxz_30x64": dict(geom="2dxz", nx=30, ny=1, nz=64, dx=0.4, dy=1.0, dz=0.2, dt=0.001,
+                       gamma=1.0, nu=4.0, lam=2.5, g=20.0, gdd=15.0, R=0.0),
+    "2dxy_120x96": dict(geom="2dxy", nx=120, ny=96, nz=1, dx=0.15, dy=0.15, dz=1.0, dt=0.001,
+                        gamma=1.0, nu=1.2, lam=4.0, g=40.0, gdd=20.0, R=0.0),
+}
+
+
+def start_state(w, seed, noise=True):
+    shape_axes = {"3d": (0.8, 1.0, 1.1), "2dxy": (0.9, 1.1), "2dxz": (0.8, 1.0)}[w["geom"]]
+    return I.gaussian(w["geom"], w["nx"], w["ny"], w["nz"], w["dx"], w["dy"], w["dz"],
+                      widths=shape_axes, amp_noise=0.05 if noise else 0.0,
+                      phase_noise=0.02 if noise else 0.0, seed=seed)
+
+
+def make_solver(w, prec):
+    from paper_1601_04640_amd.binding import Solver
+    return Solver(w, prec=prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_dipolar_potential(name, prec, gpu_lib):
+    w = CASES[name]
+    banner("dipolar_potential", name, prec)
+    psi = start_state(w, 101)
+    s = make_solver(w, prec)
+    s.set_psi(psi)
+    got = s.dipolar_potential()
+    ref = O.dipolar_potential(np.abs(psi) ** 2, oparams(w))
+    err = rel_l2(got, ref)
+    assert err <= (1e-12 if prec == "fp64" else 2e-6), err
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_energy_observables(name, prec, gpu_lib):
+    w = CASES[name]
+    banner("energy", name, prec)
+    psi = start_state(w, 102)
+    s = make_solver(w, prec)
+    s.set_psi(psi)
+    got = s.energy()
+    ref = O.observables(psi, oparams(w))
+    bad = obs_close(got, ref, FP64_E_TOL if prec == "fp64" else FP32_E_TOL)
+    assert not bad, bad
+    s.close()
+
+
+@pytest.mark.parametrize("imag", [True, False])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_steps_match_oracle(name, prec, imag, gpu_lib):
+    w = CASES[name]
+    nsteps = 12
+    banner("steps", name, prec, "imag" if imag else "real", nsteps)
+    psi0 = start_state(w, 103)
+    p = oparams(w)
+    s = make_solver(w, prec)
+    s.set_psi(psi0)
+    s.step_imag(nsteps) if imag else s.step_real(nsteps)
+    got = s.get_psi()
+    ref, hist = O.run(psi0, p, imag, nsteps, record=True)
+    err = rel_l2(got, ref)
+    assert err <= (FP64_PSI_TOL if prec == "fp64" else FP32_PSI_TOL), err
+    # per-step records: observables of the state each step started from
+    recs = s.history(nsteps)
+    assert len(recs) == nsteps
+    tol = FP64_E_TOL if prec == "fp64" else FP32_E_TOL
+    for k, (g_, r_) in enumerate(zip(recs, hist)):
+        bad = obs_close(g_, r_, tol * 10)
+        assert not bad, (k, bad)
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_set_potential_and_quench(prec, gpu_lib):
+    """Arbitrary grid V through gp_set_potential, then a coupling quench."""
+    w = CASES["2dxy_48x40"]
+    banner("set_potential+quench", prec)
+    p = oparams(w)
+    V = O.harmonic_potential(p) + 0.3 * I.smooth_random_field(p.shape(), p.spacings(), 1.0, 7)
+    psi0 = start_state(w, 104)
+    s = make_solver(w, prec)
+    s.set_psi(psi0)
+    s.set_potential(V)
+    s.step_imag(5)
+    s.set_couplings(12.0, 3.0)
+    s.step_real(7)
+    got = s.get_psi()
+    ref = O.run(psi0, p, True, 5, V=V)
+    p2 = oparams({**w, "g": 12.0, "gdd": 3.0})
+    ref = O.run(ref, p2, False, 7, V=V)
+    err = rel_l2(got, ref)
+    assert err <= (FP64_PSI_TOL if prec == "fp64" else FP32_PSI_TOL), err
+    s.close()
+
+
+def test_device_io_roundtrip(gpu_lib):
+    import torch
+    w = CASES["3d_24x20x16"]
+    banner("device io roundtrip")
+    psi = start_state(w, 105)
+    for prec in ("fp64", "fp32"):
+        s = make_solver(w, prec)
+        t = torch.from_numpy(psi).to("cuda:0")
+        s.set_psi(t)
+        back = s.get_psi_device().cpu().numpy()
+        tol = 1e-15 if prec == "fp64" else 1e-7
+        assert rel_l2(back.astype(np.complex128), psi) < tol
+        s.close()
+
+
+def test_state_and_nonfinite_errors(gpu_lib):
+    from paper_1601_04640_amd import binding as B
+    w = CASES["2dxy_48x40"]
+    banner("state errors / nonfinite flag")
+    s = make_solver(w, "fp64")
+    with pytest.raises(B.GPError) as e:
+        s.step_real(1)
+    assert e.value.status == B.GP_E_STATE
+    with pytest.raises(B.GPError) as e:
+        s.energy()
+    assert e.value.status == B.GP_E_STATE
+    psi = start_state(w, 106)
+    psi[10, 10] = np.nan
+    s.set_psi(psi)
+    s.step_imag(2)
+    with pytest.raises(B.GPError) as e:
+        s.sync()
+    assert e.value.status == B.GP_E_NONFINITE
+    s.close()
+
+
+def test_zero_steps_and_boundary_zeroing(gpu_lib):
+    w = CASES["3d_24x20x16"]
+    banner("zero steps / boundary")
+    rng = np.random.default_rng(3)
+    psi = rng.standard_normal((16, 20, 24)) + 1j * rng.standard_normal((16, 20, 24))
+    s = make_solver(w, "fp64")
+    s.set_psi(psi)
+    s.step_real(0)
+    got = s.get_psi()
+    assert np.array_equal(got, O.zero_boundary(psi))
+    s.close()
