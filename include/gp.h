@@ -135,6 +135,26 @@ int gp_history_capacity(void);
 /* Wait for the context's stream; reports the sticky non-finite flag. */
 gp_status gp_sync(gp_ctx* ctx);
 
+/* Optional per-pass timing (profiling and benchmarks).  With a non-zero mask, every
+ * launch of a selected pass (bit 1 << gp_pass) is bracketed by HIP events recorded on
+ * the context's stream; gp_timing_read synchronises, returns the summed durations (ms)
+ * and launch counts of every pass since the last enable, and keeps timing on.  Mask 0
+ * turns timing off.  Events are host-side objects; no device memory is allocated. */
+typedef enum {
+  GP_PASS_R2C_X = 0,      /* |psi|^2, x real-to-complex FFT, x/y kinetic sums      */
+  GP_PASS_FFT_Y_FWD = 1,  /* 3D: forward y FFT of the half spectrum                */
+  GP_PASS_CONV_Z = 2,     /* 3D: z FFT, U(k)/N product, inverse z FFT              */
+  GP_PASS_FFT_Y_INV = 3,  /* 3D: inverse y FFT                                     */
+  GP_PASS_CONV_Y = 4,     /* 2D: y FFT, U(k)/N product, inverse y FFT              */
+  GP_PASS_C2R_NL_CNX = 5, /* x C2R -> Phi, observables sums, phase, CN sweep x     */
+  GP_PASS_CN_Y = 6,       /* CN sweep y (2D: with the new-state norm sum)          */
+  GP_PASS_CN_Z = 7,       /* 3D: CN sweep z with new-state norm / z-kinetic sums   */
+  GP_PASS_FINALIZE = 8,   /* FP64 totals, observables record, renormalisation      */
+  GP_PASS_COUNT = 9
+} gp_pass;
+gp_status gp_timing_enable(gp_ctx* ctx, unsigned pass_mask);
+gp_status gp_timing_read(gp_ctx* ctx, double* total_ms, int* launches);
+
 /* Text of the HIP error behind the calling thread's most recent GP_E_DEVICE ("" if none).
  * The pointer stays valid until the thread's next failing call. */
 const char* gp_last_error(void);

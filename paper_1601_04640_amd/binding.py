@@ -75,7 +75,13 @@ _SIGS = {
     "gp_history_capacity": (ctypes.c_int, []),
     "gp_sync": (ctypes.c_int, [_P]),
     "gp_last_error": (ctypes.c_char_p, []),
+    "gp_timing_enable": (ctypes.c_int, [_P, ctypes.c_uint]),
+    "gp_timing_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_int)]),
 }
+
+PASS_NAMES = ("r2c_x", "fft_y_fwd", "conv_z", "fft_y_inv", "conv_y", "c2r_nl_cnx", "cn_y",
+              "cn_z", "finalize")
 
 _lib = None
 
@@ -193,6 +199,18 @@ def gp_sync(ctx: int):
     _check(load().gp_sync(_P(ctx)), "gp_sync")
 
 
+def gp_timing_enable(ctx: int, mask: int):
+    _check(load().gp_timing_enable(_P(ctx), mask), "gp_timing_enable")
+
+
+def gp_timing_read(ctx: int) -> dict:
+    n = len(PASS_NAMES)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int * n)()
+    _check(load().gp_timing_read(_P(ctx), ms, cnt), "gp_timing_read")
+    return {PASS_NAMES[i]: (ms[i], cnt[i]) for i in range(n)}
+
+
 # ------------------------------------------------------------ convenience class
 class Solver:
     """One context on one device: owns a torch workspace tensor and uses a torch stream.
@@ -283,6 +301,15 @@ class Solver:
 
     def sync(self):
         gp_sync(self.ctx)
+
+    def timing_enable(self, passes=()):
+        mask = 0
+        for p in passes:
+            mask |= 1 << PASS_NAMES.index(p)
+        gp_timing_enable(self.ctx, mask)
+
+    def timing_read(self) -> dict:
+        return gp_timing_read(self.ctx)
 
 
 def _shape(params):

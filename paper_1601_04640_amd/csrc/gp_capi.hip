@@ -7,6 +7,8 @@
 #include <string.h>
 
 #include <new>
+#include <utility>
+#include <vector>
 
 #include "../../include/gp.h"
 #include "gp_aux.hpp"
@@ -131,6 +133,10 @@ Layout make_layout(const gp_params* p) {
 }  // namespace
 
 struct gp_ctx {
+  // optional per-pass timing: event pairs recorded around selected pass launches
+  unsigned tmask = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[GP_PASS_COUNT];
+  std::vector<hipEvent_t> tpool;
   gp_params p;
   Layout L;
   hipStream_t st;
@@ -163,6 +169,38 @@ void clear_stale_error() { (void)hipGetLastError(); }
     if (_s != GP_OK) return _s;          \
   } while (0)
 #define GP_HIP(expr) GP_TRY(dev(expr))
+
+hipEvent_t take_event(gp_ctx* c) {
+  if (!c->tpool.empty()) {
+    hipEvent_t e = c->tpool.back();
+    c->tpool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Records the start event of a timed pass; returns false when timing is off.
+gp_status pass_begin(gp_ctx* c, int pass) {
+  if (!(c->tmask & (1u << pass))) return GP_OK;
+  hipEvent_t a = take_event(c), b = take_event(c);
+  if (!a || !b) return GP_E_DEVICE;
+  c->tev[pass].emplace_back(a, b);
+  return dev(hipEventRecord(a, c->st));
+}
+
+gp_status pass_end(gp_ctx* c, int pass) {
+  if (!(c->tmask & (1u << pass))) return GP_OK;
+  return dev(hipEventRecord(c->tev[pass].back().second, c->st));
+}
+
+#define GP_PASS(c, id, expr)        \
+  do {                              \
+    GP_TRY(pass_begin((c), (id)));  \
+    GP_HIP(expr);                   \
+    GP_TRY(pass_end((c), (id)));    \
+  } while (0)
 
 unsigned blocks_for(size_t n, int per = kThreads) { return (unsigned)((n + per - 1) / per); }
 
@@ -226,20 +264,25 @@ struct Passes {
   static gp_status convolution(gp_ctx* c) {
     const Layout& L = c->L;
     const int H = L.n0 / 2 + 1;
-    GP_HIP(Launch<T>::r2c_x(L.n0, L.nb_x, c->st, psi(c), &c->sc()->scale, spec(c), tw(c, 0),
-                            c->at<double>(L.o_px), L.n1, L.n2));
+    GP_PASS(c, GP_PASS_R2C_X,
+            Launch<T>::r2c_x(L.n0, L.nb_x, c->st, psi(c), &c->sc()->scale, spec(c), tw(c, 0),
+                             c->at<double>(L.o_px), L.n1, L.n2));
     if (c->p.geom == GP_3D) {
       const int nl = H * L.n2;
       const int lb = c->fp64 ? Launch<double>::lb(L.n1) : Launch<float>::lb(L.n1);
       const int tc = tc_of(c->fp64, L.n2);
-      GP_HIP(Launch<T>::fft_line(L.n1, false, (nl + lb - 1) / lb, c->st, spec(c), tw(c, 1), nl));
-      GP_HIP(Launch<T>::conv_col(L.n2, ((L.n1 + tc - 1) / tc) * H, c->st, spec(c),
-                                 c->at<T>(L.o_ktab), tw(c, 2), L.n1));
-      GP_HIP(Launch<T>::fft_line(L.n1, true, (nl + lb - 1) / lb, c->st, spec(c), tw(c, 1), nl));
+      GP_PASS(c, GP_PASS_FFT_Y_FWD,
+              Launch<T>::fft_line(L.n1, false, (nl + lb - 1) / lb, c->st, spec(c), tw(c, 1), nl));
+      GP_PASS(c, GP_PASS_CONV_Z,
+              Launch<T>::conv_col(L.n2, ((L.n1 + tc - 1) / tc) * H, c->st, spec(c),
+                                  c->at<T>(L.o_ktab), tw(c, 2), L.n1));
+      GP_PASS(c, GP_PASS_FFT_Y_INV,
+              Launch<T>::fft_line(L.n1, true, (nl + lb - 1) / lb, c->st, spec(c), tw(c, 1), nl));
     } else {
       const int lb = c->fp64 ? Launch<double>::lb(L.n1) : Launch<float>::lb(L.n1);
-      GP_HIP(Launch<T>::conv_line(L.n1, (H + lb - 1) / lb, c->st, spec(c), c->at<T>(L.o_ktab),
-                                  tw(c, 1), H));
+      GP_PASS(c, GP_PASS_CONV_Y,
+              Launch<T>::conv_line(L.n1, (H + lb - 1) / lb, c->st, spec(c), c->at<T>(L.o_ktab),
+                                   tw(c, 1), H));
     }
     return GP_OK;
   }
@@ -258,27 +301,34 @@ struct Passes {
     const int k = imag ? 0 : 2;  // table pair: (m, g) imaginary or real time
     GP_TRY(convolution(c));
     const StepScalars sx = scalars_for(c, 0);
-    GP_HIP(Launch<T>::c2r_nl_cnx(L.n0, mode, L.nb_x, c->st, psi(c), c->at<T>(L.o_V),
-                                 &c->sc()->scale, spec(c), tw(c, 0), cn(c, 0, k), cn(c, 0, k + 1),
-                                 sx, c->at<double>(L.o_pnl), nullptr, L.n1, L.n2));
+    GP_PASS(c, GP_PASS_C2R_NL_CNX,
+            Launch<T>::c2r_nl_cnx(L.n0, mode, L.nb_x, c->st, psi(c), c->at<T>(L.o_V),
+                                  &c->sc()->scale, spec(c), tw(c, 0), cn(c, 0, k),
+                                  cn(c, 0, k + 1), sx, c->at<double>(L.o_pnl), nullptr, L.n1,
+                                  L.n2));
     const int tcy = tc_of(c->fp64, L.n1);
     const double Ay = scalars_for(c, 1).Ar;
     if (c->p.geom == GP_3D) {
-      GP_HIP(Launch<T>::cn_col(L.n1, mode, false, ((L.n0 + tcy - 1) / tcy) * L.n2, c->st, psi(c),
-                               cn(c, 1, k), cn(c, 1, k + 1), Ay, nullptr, L.n0, (size_t)L.n0,
-                               (size_t)L.n0 * L.n1));
+      GP_PASS(c, GP_PASS_CN_Y,
+              Launch<T>::cn_col(L.n1, mode, false, ((L.n0 + tcy - 1) / tcy) * L.n2, c->st,
+                                psi(c), cn(c, 1, k), cn(c, 1, k + 1), Ay, nullptr, L.n0,
+                                (size_t)L.n0, (size_t)L.n0 * L.n1));
       const double Az = scalars_for(c, 2).Ar;
-      GP_HIP(Launch<T>::cn_col(L.n2, mode, true, L.nb_col, c->st, psi(c), cn(c, 2, k),
-                               cn(c, 2, k + 1), Az, c->at<double>(L.o_pcol), L.n0,
-                               (size_t)L.n0 * L.n1, (size_t)L.n0));
+      GP_PASS(c, GP_PASS_CN_Z,
+              Launch<T>::cn_col(L.n2, mode, true, L.nb_col, c->st, psi(c), cn(c, 2, k),
+                                cn(c, 2, k + 1), Az, c->at<double>(L.o_pcol), L.n0,
+                                (size_t)L.n0 * L.n1, (size_t)L.n0));
     } else {
-      GP_HIP(Launch<T>::cn_col(L.n1, mode, true, L.nb_col, c->st, psi(c), cn(c, 1, k),
-                               cn(c, 1, k + 1), Ay, c->at<double>(L.o_pcol), L.n0, (size_t)L.n0,
-                               (size_t)L.n0 * L.n1));
+      GP_PASS(c, GP_PASS_CN_Y,
+              Launch<T>::cn_col(L.n1, mode, true, L.nb_col, c->st, psi(c), cn(c, 1, k),
+                                cn(c, 1, k + 1), Ay, c->at<double>(L.o_pcol), L.n0,
+                                (size_t)L.n0, (size_t)L.n0 * L.n1));
     }
+    GP_TRY(pass_begin(c, GP_PASS_FINALIZE));
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, c->st, fin_args(c),
                        imag ? (int)FIN_IMAG : (int)FIN_REAL);
     GP_HIP(hipGetLastError());
+    GP_TRY(pass_end(c, GP_PASS_FINALIZE));
     return GP_OK;
   }
 
@@ -489,6 +539,13 @@ gp_status gp_init(const gp_params* params, void* dev_workspace, size_t ws_bytes,
 gp_status gp_destroy(gp_ctx* ctx) {
   if (!ctx) return GP_E_ARG;
   const hipError_t e = hipStreamSynchronize(ctx->st);
+  for (int k = 0; k < GP_PASS_COUNT; ++k) {
+    for (auto& ev : ctx->tev[k]) {
+      hipEventDestroy(ev.first);
+      hipEventDestroy(ev.second);
+    }
+  }
+  for (auto ev : ctx->tpool) hipEventDestroy(ev);
   delete ctx;
   return dev(e);
 }
@@ -575,6 +632,38 @@ gp_status gp_dipolar_potential(gp_ctx* c, void* phi, int on_device) {
 int gp_history_capacity(void) { return kRingCap; }
 
 const char* gp_last_error(void) { return g_last_error; }
+
+gp_status gp_timing_enable(gp_ctx* c, unsigned mask) {
+  if (!c) return GP_E_ARG;
+  clear_stale_error();
+  GP_HIP(hipStreamSynchronize(c->st));
+  for (int k = 0; k < GP_PASS_COUNT; ++k) {
+    for (auto& e : c->tev[k]) {
+      c->tpool.push_back(e.first);
+      c->tpool.push_back(e.second);
+    }
+    c->tev[k].clear();
+  }
+  c->tmask = mask & ((1u << GP_PASS_COUNT) - 1);
+  return GP_OK;
+}
+
+gp_status gp_timing_read(gp_ctx* c, double* total_ms, int* launches) {
+  if (!c || !total_ms || !launches) return GP_E_ARG;
+  clear_stale_error();
+  GP_HIP(hipStreamSynchronize(c->st));
+  for (int k = 0; k < GP_PASS_COUNT; ++k) {
+    double acc = 0.0;
+    for (auto& e : c->tev[k]) {
+      float ms = 0.f;
+      GP_HIP(hipEventElapsedTime(&ms, e.first, e.second));
+      acc += ms;
+    }
+    total_ms[k] = acc;
+    launches[k] = (int)c->tev[k].size();
+  }
+  return GP_OK;
+}
 
 gp_status gp_history(gp_ctx* c, gp_observables* out, int max_records, int* count) {
   clear_stale_error();
