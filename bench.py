@@ -94,38 +94,58 @@ def ground_state(imag_steps):
     return psi, abs(mu[1]["mu"] - mu[0]["mu"])
 
 
-def time_gpu(prec, psi_start, steps, warmup):
+def time_gpu(workload, prec, psi_start, steps, warmup):
+    """Two live timed regions of `steps` full steps from the same start, on the solver's
+    stream: (1) steps replayed from captured HIP graphs, no instrumentation -> value;
+    (2) the same steps launched directly with HIP events around every launch of the
+    dominant pass -> its mean launch time for the roofline."""
     import torch
     from paper_1601_04640_amd import inputs as I
     from paper_1601_04640_amd.binding import Solver
-    w = I.WORKLOADS[WORKLOAD]
+    w = I.WORKLOADS[workload]
     s = Solver(w, prec=prec)
     s.set_psi(psi_start)
     s.step_real(warmup)
     s.sync()
-    s.set_psi(psi_start)                 # every timed run starts the quench afresh
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    # timed region: `steps` full steps on the solver's stream (torch's current stream)
-    s.timing_enable([DOMINANT])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(s.stream)
-    s.step_real(steps)
-    ev1.record(s.stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
-    timing = s.timing_read()
-    s.timing_enable([])
-    hist = s.history(steps)
-    psi = s.get_psi()
-    npts = w["nx"] * w["ny"] * w["nz"]
-    nspec = (w["nx"] // 2 + 1) * w["ny"] * w["nz"]
+    res = {}
+    for region in ("graph", "events"):
+        s.set_psi(psi_start)                 # every timed run starts afresh
+        if region == "events":
+            s.timing_enable([DOMINANT])
+        else:
+            s.timing_enable([])
+            s.use_graphs(True)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record(s.stream)
+        s.step_real(steps)
+        ev1.record(s.stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        res[region] = dict(wall=wall, gpu_ms=ev0.elapsed_time(ev1))
+        if region == "events":
+            res["timing"] = s.timing_read()
+            s.timing_enable([])
+        else:
+            res["hist"] = s.history(steps)
+            res["psi"] = s.get_psi()
+    res["npts"] = w["nx"] * w["ny"] * w["nz"]
+    res["nspec"] = (w["nx"] // 2 + 1) * w["ny"] * w["nz"]
     s.close()
-    return dict(wall=wall, gpu_ms=gpu_ms, timing=timing, hist=hist, psi=psi, npts=npts,
-                nspec=nspec)
+    return res
+
+
+def roofline(r, esz):
+    tot_ms, nl = r["timing"][DOMINANT]
+    avg_ms = tot_ms / max(nl, 1)
+    alg = pass_bytes(DOMINANT, r["npts"], r["nspec"], esz)
+    achieved = alg / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "kernel": DOMINANT,
+            "avg_launch_ms": round(avg_ms, 5), "launches": nl,
+            "algorithmic_bytes_per_launch": alg}
 
 
 def cpu_baseline(budget_s=15.0):
@@ -165,6 +185,8 @@ def main():
     ap.add_argument("--imag-steps", type=int, default=6000,
                     help="imaginary-time relaxation before the quench (untimed)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-large", action="store_true", help="skip the 256^3 workload")
+    ap.add_argument("--large-steps", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the "
@@ -176,29 +198,21 @@ def main():
     psi_g, dmu = ground_state(args.imag_steps)
     print(f"[bench] FP64 ground state: {args.imag_steps} imaginary steps, |dmu| = {dmu:.2e}",
           file=sys.stderr, flush=True)
-    r32 = time_gpu("fp32", psi_g, args.steps, args.warmup)
-    print(f"[bench] fp32 done: {r32['gpu_ms'] / args.steps:.4f} ms/step", file=sys.stderr,
-          flush=True)
-    r64 = time_gpu("fp64", psi_g, args.steps, args.warmup)
-    print(f"[bench] fp64 done: {r64['gpu_ms'] / args.steps:.4f} ms/step", file=sys.stderr,
-          flush=True)
+    r32 = time_gpu(WORKLOAD, "fp32", psi_g, args.steps, args.warmup)
+    print(f"[bench] fp32 done: {r32['graph']['gpu_ms'] / args.steps:.4f} ms/step",
+          file=sys.stderr, flush=True)
+    r64 = time_gpu(WORKLOAD, "fp64", psi_g, args.steps, args.warmup)
+    print(f"[bench] fp64 done: {r64['graph']['gpu_ms'] / args.steps:.4f} ms/step",
+          file=sys.stderr, flush=True)
     npts = r32["npts"]
-    ms32 = r32["wall"] * 1e3 / args.steps
-    ms64 = r64["wall"] * 1e3 / args.steps
-    value = npts * args.steps / r32["wall"]
+    ms32 = r32["graph"]["wall"] * 1e3 / args.steps
+    ms64 = r64["graph"]["wall"] * 1e3 / args.steps
+    value = npts * args.steps / r32["graph"]["wall"]
     err = float(np.linalg.norm(r32["psi"] - r64["psi"]) / np.linalg.norm(r64["psi"]))
     e32 = r32["hist"][-1]["energy"]
     e64 = r64["hist"][-1]["energy"]
-
-    tot_ms, nl = r32["timing"][DOMINANT]
-    avg_ms = tot_ms / max(nl, 1)
-    alg = pass_bytes(DOMINANT, npts, r32["nspec"], 4)
-    achieved = alg / (avg_ms * 1e-3) / 1e9
-    traffic = read_traffic(DOMINANT, WORKLOAD, "fp32")
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic, "kernel": DOMINANT, "avg_launch_ms": round(avg_ms, 5),
-            "algorithmic_bytes_per_launch": alg}
+    roof = roofline(r32, 4)
+    roof["traffic"] = read_traffic(DOMINANT, WORKLOAD, "fp32")
     line = {
         "metric": METRIC,
         "value": value,
@@ -214,18 +228,33 @@ def main():
         "reductions_dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{WORKLOAD} real-time quench g 20->15, g_dd 6, trap (1,1,2), "
-                               "dx 0.2, dt 0.001, from the imaginary-time ground state",
+                               "dx 0.2, dt 0.001, from the FP64 imaginary-time ground state",
                    "grid": [128, 96, 80], "points": npts},
         "roofline": roof,
-        "fp64": {"value": npts * args.steps / r64["wall"], "ms_per_step": ms64},
+        "fp64": {"value": npts * args.steps / r64["graph"]["wall"], "ms_per_step": ms64,
+                 "roofline": roofline(r64, 8)},
         "fp32_vs_fp64": {"psi_rel_l2_after_steps": err,
                          "energy_rel": abs(e32 - e64) / abs(e64),
                          "note": "same FP64 ground state, same quench; FP64 path matches "
                                  "the FP64 oracle to <= 1e-10 in the parity tests"},
         "ground_state": {"imag_steps": args.imag_steps, "dt": 0.002, "last_abs_dmu": dmu},
-        "gpu_event_ms_per_step": {"fp32": r32["gpu_ms"] / args.steps,
-                                  "fp64": r64["gpu_ms"] / args.steps},
+        "gpu_event_ms_per_step": {"fp32": r32["graph"]["gpu_ms"] / args.steps,
+                                  "fp64": r64["graph"]["gpu_ms"] / args.steps,
+                                  "fp32_direct_launch_with_events":
+                                      r32["events"]["gpu_ms"] / args.steps},
     }
+    if not args.no_large:
+        from paper_1601_04640_amd import inputs as I
+        psi5 = I.psi0_real3d_256()
+        big = {}
+        for prec, esz in (("fp32", 4), ("fp64", 8)):
+            r = time_gpu("real3d_256", prec, psi5, args.large_steps, 5)
+            big[prec] = {"value": r["npts"] * args.large_steps / r["graph"]["wall"],
+                         "ms_per_step": r["graph"]["wall"] * 1e3 / args.large_steps,
+                         "roofline": roofline(r, esz)}
+            print(f"[bench] real3d_256 {prec}: {big[prec]['ms_per_step']:.4f} ms/step",
+                  file=sys.stderr, flush=True)
+        line["real3d_256"] = big
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline()

@@ -135,6 +135,11 @@ int gp_history_capacity(void);
 /* Wait for the context's stream; reports the sticky non-finite flag. */
 gp_status gp_sync(gp_ctx* ctx);
 
+/* Step loops of at least 8 steps replay a captured HIP graph of 8 steps (captured once
+ * per time direction, re-captured after gp_set_couplings); enable = 0 launches every
+ * pass directly.  Default: enabled.  Timing (below) always launches directly. */
+gp_status gp_use_graphs(gp_ctx* ctx, int enable);
+
 /* Optional per-pass timing (profiling and benchmarks).  With a non-zero mask, every
  * launch of a selected pass (bit 1 << gp_pass) is bracketed by HIP events recorded on
  * the context's stream; gp_timing_read synchronises, returns the summed durations (ms)
@@ -149,7 +154,8 @@ typedef enum {
   GP_PASS_C2R_NL_CNX = 5, /* x C2R -> Phi, observables sums, phase, CN sweep x     */
   GP_PASS_CN_Y = 6,       /* CN sweep y (2D: with the new-state norm sum)          */
   GP_PASS_CN_Z = 7,       /* 3D: CN sweep z with new-state norm / z-kinetic sums   */
-  GP_PASS_FINALIZE = 8,   /* FP64 totals, observables record, renormalisation      */
+  GP_PASS_FINALIZE = 8,   /* standalone FP64 finalisation (2D observables only; in  */
+                          /* steps it runs in the last block of the last CN pass)   */
   GP_PASS_COUNT = 9
 } gp_pass;
 gp_status gp_timing_enable(gp_ctx* ctx, unsigned pass_mask);

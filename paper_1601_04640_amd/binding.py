@@ -75,6 +75,7 @@ _SIGS = {
     "gp_history_capacity": (ctypes.c_int, []),
     "gp_sync": (ctypes.c_int, [_P]),
     "gp_last_error": (ctypes.c_char_p, []),
+    "gp_use_graphs": (ctypes.c_int, [_P, ctypes.c_int]),
     "gp_timing_enable": (ctypes.c_int, [_P, ctypes.c_uint]),
     "gp_timing_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_int)]),
@@ -199,6 +200,10 @@ def gp_sync(ctx: int):
     _check(load().gp_sync(_P(ctx)), "gp_sync")
 
 
+def gp_use_graphs(ctx: int, enable: bool):
+    _check(load().gp_use_graphs(_P(ctx), int(bool(enable))), "gp_use_graphs")
+
+
 def gp_timing_enable(ctx: int, mask: int):
     _check(load().gp_timing_enable(_P(ctx), mask), "gp_timing_enable")
 
@@ -301,6 +306,9 @@ class Solver:
 
     def sync(self):
         gp_sync(self.ctx)
+
+    def use_graphs(self, enable: bool):
+        gp_use_graphs(self.ctx, enable)
 
     def timing_enable(self, passes=()):
         mask = 0

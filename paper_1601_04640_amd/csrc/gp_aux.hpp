@@ -3,6 +3,7 @@
 // Dirichlet boundary, and the FP64 finalisation of one step's partial sums.
 #pragma once
 #include "gp_device.hpp"
+#include "gp_finalize.hpp"
 
 namespace gpdbec {
 
@@ -171,110 +172,20 @@ __global__ void k_real_convert(D* dst, const S* src, size_t cnt) {
   if (e < cnt) dst[e] = (D)src[e];
 }
 
-// --------------------------------------------------------------- finalisation
-enum : int { FIN_IMAG = 0, FIN_REAL = 1, FIN_OBSERVE = 2, FIN_EKZ = 3 };
-constexpr int kRecord = 10;  // norm, mu, energy, e_kin, e_pot, e_int, e_dd, rms x/y/z
-
-struct FinArgs {
-  const double* p_x;   // 2 per block: sum |dx psi|^2, sum |d1 psi|^2 (unscaled)
-  int nb_x;
-  const double* p_nl;  // 7 per block: n, V n, n^2, Phi n, x^2 n, a1^2 n, a2^2 n (scaled)
-  int nb_nl;
-  const double* p_col; // 2 per block: |u|^2, |d2 u|^2 (new state / unscaled input)
-  int nb_col;
-  double dV, h0, h1, h2, gc, gdd;
-  int geom;            // 0: 3D, 1: XY, 2: XZ
-  double* scale;
-  double* ekz;         // pending z-kinetic energy of the stored state (3D)
-  int* flags;
-  double* ring;
-  int* ring_pos;
-  int ring_cap;
-  double* obs;         // FIN_OBSERVE output record
-};
-
-// One block of kThreads.  Sums every partial field over blocks in a fixed order.
+// ------------------------------------------------------------------ finalisation
+// Standalone finalize (used where no column pass ends the sequence: 2D observables).
 __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a, int mode) {
-  __shared__ double red[11 * kThreads];
-  const int tid = threadIdx.x;
-  double v[11];
-#pragma unroll
-  for (int k = 0; k < 11; ++k) v[k] = 0.0;
-  if (mode != FIN_EKZ) {
-    for (int b = tid; b < a.nb_x; b += kThreads) {
-      v[0] += a.p_x[2 * b];
-      v[1] += a.p_x[2 * b + 1];
-    }
-    for (int b = tid; b < a.nb_nl; b += kThreads) {
-#pragma unroll
-      for (int k = 0; k < 7; ++k) v[2 + k] += a.p_nl[7 * b + k];
-    }
-  }
-  if (mode != FIN_OBSERVE || a.geom == 0) {
-    for (int b = tid; b < a.nb_col; b += kThreads) {
-      v[9] += a.p_col[2 * b];
-      v[10] += a.p_col[2 * b + 1];
-    }
-  }
-  block_sum<11>(v, red);
-  if (tid != 0) return;
-  const double s = *a.scale;
-  const double s2 = s * s;
-  if (mode == FIN_EKZ) {
-    *a.ekz = 0.5 * s2 * v[10] / (a.h2 * a.h2) * a.dV;
-    return;
-  }
-  const double dV = a.dV;
-  double rec[kRecord];
-  const double norm = v[2] * dV;
-  double ekin = 0.5 * s2 * (v[0] / (a.h0 * a.h0) + v[1] / (a.h1 * a.h1)) * dV;
-  if (a.geom == 0) {
-    ekin += (mode == FIN_OBSERVE) ? 0.5 * s2 * v[10] / (a.h2 * a.h2) * dV : *a.ekz;
-  }
-  const double epot = v[3] * dV;
-  const double eint = 0.5 * a.gc * v[4] * dV;
-  const double edd = 0.5 * a.gdd * v[5] * dV;
-  rec[0] = norm;
-  rec[1] = ekin + epot + 2.0 * eint + 2.0 * edd;
-  rec[2] = ekin + epot + eint + edd;
-  rec[3] = ekin;
-  rec[4] = epot;
-  rec[5] = eint;
-  rec[6] = edd;
-  const double r0 = sqrt(v[6] * dV / norm), r1 = sqrt(v[7] * dV / norm), r2 = sqrt(v[8] * dV / norm);
-  rec[7] = r0;
-  rec[8] = (a.geom == 2) ? 0.0 : r1;
-  rec[9] = (a.geom == 0) ? r2 : (a.geom == 2 ? r1 : 0.0);
-  double* dst;
-  if (mode == FIN_OBSERVE) {
-    dst = a.obs;
-  } else {
-    const int pos = *a.ring_pos;
-    dst = a.ring + (size_t)(pos % a.ring_cap) * kRecord;
-    *a.ring_pos = pos + 1;
-  }
-#pragma unroll
-  for (int k = 0; k < kRecord; ++k) dst[k] = rec[k];
-  if (!isfinite(norm)) *a.flags |= 1;
-  if (mode == FIN_OBSERVE) return;
-  // new state: imaginary time renormalises, real time keeps the physical values
-  const double nout = v[9] * dV;
-  if (!isfinite(nout) || !(nout > 0.0)) {
-    *a.flags |= 1;
-    *a.scale = 1.0;
-    return;
-  }
-  const double sn = (mode == FIN_IMAG) ? 1.0 / sqrt(nout) : 1.0;
-  *a.scale = sn;
-  if (a.geom == 0) *a.ekz = 0.5 * sn * sn * v[10] / (a.h2 * a.h2) * dV;
+  finalize_block(a, mode);
 }
 
-__global__ void k_reset_state(double* scale, double* ekz, int* flags, int* ring_pos) {
+__global__ void k_reset_state(double* scale, double* ekz, int* flags, int* ring_pos,
+                              unsigned* counter) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     *scale = 1.0;
     *ekz = 0.0;
     *flags = 0;
     *ring_pos = 0;
+    *counter = 0u;
   }
 }
 

@@ -20,6 +20,7 @@ using namespace gpdbec;
 namespace {
 
 constexpr int kRingCap = 4096;
+constexpr int kGraphSteps = 8;  // steps per captured graph
 
 bool size_ok(int n) {
   switch (n) {
@@ -51,6 +52,7 @@ struct Scalars {  // device-side scalars (one 256-byte block)
   double obs_pad;
   int flags;
   int ring_pos;
+  unsigned counter;  // arrival tickets of the fused finalisation
 };
 
 gp_status validate(const gp_params* p) {
@@ -133,6 +135,10 @@ Layout make_layout(const gp_params* p) {
 }  // namespace
 
 struct gp_ctx {
+  // step loop replay: kGraphSteps steps captured once per time direction
+  bool use_graphs = true;
+  hipStream_t cap_st = nullptr;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};  // [imaginary, real]
   // optional per-pass timing: event pairs recorded around selected pass launches
   unsigned tmask = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[GP_PASS_COUNT];
@@ -287,17 +293,20 @@ struct Passes {
     return GP_OK;
   }
 
-  // z-difference sums of the stored state (3D), for the kinetic energy
-  static gp_status z_observe(gp_ctx* c) {
+  // z-difference sums of the stored state (3D), for the kinetic energy; the last block
+  // finalises with fin_mode (FIN_EKZ: pending z-kinetic part; FIN_OBSERVE: full record)
+  static gp_status z_observe(gp_ctx* c, int fin_mode) {
     const Layout& L = c->L;
     return dev(Launch<T>::cn_col(L.n2, MODE_OBSERVE, true, L.nb_col, c->st, psi(c), nullptr,
                                  nullptr, 0.0, c->at<double>(L.o_pcol), L.n0,
-                                 (size_t)L.n0 * L.n1, (size_t)L.n0));
+                                 (size_t)L.n0 * L.n1, (size_t)L.n0, &c->sc()->counter,
+                                 fin_args(c), fin_mode));
   }
 
   static gp_status step(gp_ctx* c, bool imag) {
     const Layout& L = c->L;
     const int mode = imag ? MODE_IMAG : MODE_REAL;
+    const int fin = imag ? (int)FIN_IMAG : (int)FIN_REAL;
     const int k = imag ? 0 : 2;  // table pair: (m, g) imaginary or real time
     GP_TRY(convolution(c));
     const StepScalars sx = scalars_for(c, 0);
@@ -312,23 +321,20 @@ struct Passes {
       GP_PASS(c, GP_PASS_CN_Y,
               Launch<T>::cn_col(L.n1, mode, false, ((L.n0 + tcy - 1) / tcy) * L.n2, c->st,
                                 psi(c), cn(c, 1, k), cn(c, 1, k + 1), Ay, nullptr, L.n0,
-                                (size_t)L.n0, (size_t)L.n0 * L.n1));
+                                (size_t)L.n0, (size_t)L.n0 * L.n1, nullptr, FinArgs{}, 0));
       const double Az = scalars_for(c, 2).Ar;
       GP_PASS(c, GP_PASS_CN_Z,
               Launch<T>::cn_col(L.n2, mode, true, L.nb_col, c->st, psi(c), cn(c, 2, k),
                                 cn(c, 2, k + 1), Az, c->at<double>(L.o_pcol), L.n0,
-                                (size_t)L.n0 * L.n1, (size_t)L.n0));
+                                (size_t)L.n0 * L.n1, (size_t)L.n0, &c->sc()->counter,
+                                fin_args(c), fin));
     } else {
       GP_PASS(c, GP_PASS_CN_Y,
               Launch<T>::cn_col(L.n1, mode, true, L.nb_col, c->st, psi(c), cn(c, 1, k),
                                 cn(c, 1, k + 1), Ay, c->at<double>(L.o_pcol), L.n0,
-                                (size_t)L.n0, (size_t)L.n0 * L.n1));
+                                (size_t)L.n0, (size_t)L.n0 * L.n1, &c->sc()->counter,
+                                fin_args(c), fin));
     }
-    GP_TRY(pass_begin(c, GP_PASS_FINALIZE));
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, c->st, fin_args(c),
-                       imag ? (int)FIN_IMAG : (int)FIN_REAL);
-    GP_HIP(hipGetLastError());
-    GP_TRY(pass_end(c, GP_PASS_FINALIZE));
     return GP_OK;
   }
 
@@ -339,7 +345,7 @@ struct Passes {
     GP_HIP(Launch<T>::c2r_nl_cnx(L.n0, MODE_OBSERVE, L.nb_x, c->st, psi(c), c->at<T>(L.o_V),
                                  &c->sc()->scale, spec(c), tw(c, 0), nullptr, nullptr, sx,
                                  c->at<double>(L.o_pnl), nullptr, L.n1, L.n2));
-    if (c->p.geom == GP_3D) GP_TRY(z_observe(c));
+    if (c->p.geom == GP_3D) return z_observe(c, FIN_OBSERVE);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, c->st, fin_args(c),
                        (int)FIN_OBSERVE);
     GP_HIP(hipGetLastError());
@@ -394,7 +400,7 @@ struct Passes {
                        c->at<T>(L.o_V), L.n0, L.n1, L.n2, L.h0, L.h1, L.h2, w0, w1, w2);
     Scalars* s = c->sc();
     hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, c->st, &s->scale, &s->ekz, &s->flags,
-                       &s->ring_pos);
+                       &s->ring_pos, &s->counter);
     return dev(hipGetLastError());
   }
 
@@ -472,6 +478,43 @@ gp_status check_flags(gp_ctx* c) {
   return (flags & 1) ? GP_E_NONFINITE : GP_OK;
 }
 
+void drop_graphs(gp_ctx* c) {
+  for (auto& g : c->gexec) {
+    if (g) hipGraphExecDestroy(g);
+    g = nullptr;
+  }
+}
+
+gp_status one_step(gp_ctx* c, bool imag) {
+  return c->fp64 ? Passes<double>::step(c, imag) : Passes<float>::step(c, imag);
+}
+
+// Capture kGraphSteps steps on a private stream (the caller's stream may be the null
+// stream, which cannot be captured); the graph is launched on the caller's stream.
+gp_status build_graph(gp_ctx* c, bool imag) {
+  if (!c->cap_st) GP_HIP(hipStreamCreateWithFlags(&c->cap_st, hipStreamNonBlocking));
+  const hipStream_t user = c->st;
+  c->st = c->cap_st;
+  hipGraph_t g = nullptr;
+  gp_status s = dev(hipStreamBeginCapture(c->cap_st, hipStreamCaptureModeThreadLocal));
+  if (s == GP_OK) {
+    for (int i = 0; i < kGraphSteps && s == GP_OK; ++i) s = one_step(c, imag);
+    const gp_status e = dev(hipStreamEndCapture(c->cap_st, &g));
+    if (s == GP_OK) s = e;
+  }
+  c->st = user;
+  if (s != GP_OK) {
+    if (g) hipGraphDestroy(g);
+    return s;
+  }
+  hipGraphExec_t ex = nullptr;
+  s = dev(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+  hipGraphDestroy(g);
+  if (s != GP_OK) return s;
+  c->gexec[imag ? 0 : 1] = ex;
+  return GP_OK;
+}
+
 gp_status run_steps(gp_ctx* c, int nsteps, bool imag) {
   if (!c) return GP_E_ARG;
   clear_stale_error();
@@ -479,21 +522,20 @@ gp_status run_steps(gp_ctx* c, int nsteps, bool imag) {
   if (!c->psi_set) return GP_E_STATE;
   if (c->p.geom == GP_3D && !c->ekz_valid) {
     if (c->fp64) {
-      GP_TRY(Passes<double>::z_observe(c));
+      GP_TRY(Passes<double>::z_observe(c, FIN_EKZ));
     } else {
-      GP_TRY(Passes<float>::z_observe(c));
+      GP_TRY(Passes<float>::z_observe(c, FIN_EKZ));
     }
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, c->st, fin_args(c), (int)FIN_EKZ);
-    GP_HIP(hipGetLastError());
     c->ekz_valid = true;
   }
-  for (int s = 0; s < nsteps; ++s) {
-    if (c->fp64) {
-      GP_TRY(Passes<double>::step(c, imag));
-    } else {
-      GP_TRY(Passes<float>::step(c, imag));
-    }
+  int done = 0;
+  if (c->use_graphs && c->tmask == 0 && nsteps >= kGraphSteps) {
+    const int gi = imag ? 0 : 1;
+    if (!c->gexec[gi]) GP_TRY(build_graph(c, imag));
+    for (; nsteps - done >= kGraphSteps; done += kGraphSteps)
+      GP_HIP(hipGraphLaunch(c->gexec[gi], c->st));
   }
+  for (; done < nsteps; ++done) GP_TRY(one_step(c, imag));
   return GP_OK;
 }
 
@@ -546,6 +588,8 @@ gp_status gp_destroy(gp_ctx* ctx) {
     }
   }
   for (auto ev : ctx->tpool) hipEventDestroy(ev);
+  drop_graphs(ctx);
+  if (ctx->cap_st) hipStreamDestroy(ctx->cap_st);
   delete ctx;
   return dev(e);
 }
@@ -594,6 +638,7 @@ gp_status gp_set_couplings(gp_ctx* c, double g, double gdd) {
   c->p.g = g;
   c->p.gdd = gdd;
   c->gc = contact(c->p);
+  drop_graphs(c);  // the couplings are launch arguments of the captured kernels
   return GP_OK;
 }
 
@@ -632,6 +677,12 @@ gp_status gp_dipolar_potential(gp_ctx* c, void* phi, int on_device) {
 int gp_history_capacity(void) { return kRingCap; }
 
 const char* gp_last_error(void) { return g_last_error; }
+
+gp_status gp_use_graphs(gp_ctx* c, int enable) {
+  if (!c) return GP_E_ARG;
+  c->use_graphs = enable != 0;
+  return GP_OK;
+}
 
 gp_status gp_timing_enable(gp_ctx* c, unsigned mask) {
   if (!c) return GP_E_ARG;

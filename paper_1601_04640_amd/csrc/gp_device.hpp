@@ -334,22 +334,31 @@ __device__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt, const cpx<T>* gt,
 
 // ------------------------------------------------------------- reductions
 // Deterministic FP64 block sum of NV values per thread; result valid in thread 0.
+// Butterfly reduction inside each wave64 (shuffles), then the kThreads/64 wave totals
+// are added in wave order: one barrier, fixed summation order.
+constexpr int kWaves = kThreads / 64;
 template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double* red /* LDS kThreads*NV */) {
-  const int tid = threadIdx.x;
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* red /* LDS NV*kWaves */) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int k = 0; k < NV; ++k) red[k * kThreads + tid] = v[k];
-  __syncthreads();
+  for (int k = 0; k < NV; ++k) {
 #pragma unroll
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
-    if (tid < s) {
-#pragma unroll
-      for (int k = 0; k < NV; ++k) red[k * kThreads + tid] += red[k * kThreads + tid + s];
-    }
-    __syncthreads();
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
   }
+  if (lane == 0) {
 #pragma unroll
-  for (int k = 0; k < NV; ++k) v[k] = red[k * kThreads];
+    for (int k = 0; k < NV; ++k) red[k * kWaves + wave] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double acc = red[k * kWaves];
+#pragma unroll
+      for (int w = 1; w < kWaves; ++w) acc += red[k * kWaves + w];
+      v[k] = acc;
+    }
+  }
 }
 
 }  // namespace gpdbec

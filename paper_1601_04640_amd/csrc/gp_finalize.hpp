@@ -1,0 +1,137 @@
+// FP64 finalisation of one step's partial sums: totals in a fixed order, the
+// observables record of the state the step started from, and the new renormalisation
+// factor.  Runs on one block, either as a kernel of its own or inside the last block of
+// the step's final column pass ("last block done": every block publishes its partials,
+// then takes a ticket from a device counter; the block that draws the last ticket
+// finalises and re-arms the counter).
+#pragma once
+#include "gp_device.hpp"
+
+namespace gpdbec {
+
+enum : int { FIN_IMAG = 0, FIN_REAL = 1, FIN_OBSERVE = 2, FIN_EKZ = 3 };
+constexpr int kRecord = 10;  // norm, mu, energy, e_kin, e_pot, e_int, e_dd, rms x/y/z
+
+struct FinArgs {
+  const double* p_x;   // 2 per block: sum |dx psi|^2, sum |d1 psi|^2 (unscaled)
+  int nb_x;
+  const double* p_nl;  // 7 per block: n, V n, n^2, Phi n, x^2 n, a1^2 n, a2^2 n (scaled)
+  int nb_nl;
+  const double* p_col; // 2 per block: |u|^2, |d2 u|^2 (new state / unscaled input)
+  int nb_col;
+  double dV, h0, h1, h2, gc, gdd;
+  int geom;            // 0: 3D, 1: XY, 2: XZ
+  double* scale;
+  double* ekz;         // pending z-kinetic energy of the stored state (3D)
+  int* flags;
+  double* ring;
+  int* ring_pos;
+  int ring_cap;
+  double* obs;         // FIN_OBSERVE output record
+};
+
+// Partial sums written by other blocks of the running kernel are read with relaxed
+// device-scope atomic loads, which bypass the per-XCD L2.
+__device__ __forceinline__ double coherent_load(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// All threads of one block must call this.
+__device__ inline void finalize_block(const FinArgs& a, int mode) {
+  __shared__ double red[11 * kWaves];
+  const int tid = threadIdx.x;
+  double v[11];
+#pragma unroll
+  for (int k = 0; k < 11; ++k) v[k] = 0.0;
+  if (mode != FIN_EKZ) {
+    for (int b = tid; b < a.nb_x; b += kThreads) {
+      v[0] += a.p_x[2 * b];
+      v[1] += a.p_x[2 * b + 1];
+    }
+    for (int b = tid; b < a.nb_nl; b += kThreads) {
+#pragma unroll
+      for (int k = 0; k < 7; ++k) v[2 + k] += a.p_nl[7 * b + k];
+    }
+  }
+  if (mode != FIN_OBSERVE || a.geom == 0) {
+    for (int b = tid; b < a.nb_col; b += kThreads) {
+      v[9] += coherent_load(a.p_col + 2 * b);
+      v[10] += coherent_load(a.p_col + 2 * b + 1);
+    }
+  }
+  block_sum<11>(v, red);
+  if (tid != 0) return;
+  const double s = *a.scale;
+  const double s2 = s * s;
+  if (mode == FIN_EKZ) {
+    *a.ekz = 0.5 * s2 * v[10] / (a.h2 * a.h2) * a.dV;
+    return;
+  }
+  const double dV = a.dV;
+  double rec[kRecord];
+  const double norm = v[2] * dV;
+  double ekin = 0.5 * s2 * (v[0] / (a.h0 * a.h0) + v[1] / (a.h1 * a.h1)) * dV;
+  if (a.geom == 0) {
+    ekin += (mode == FIN_OBSERVE) ? 0.5 * s2 * v[10] / (a.h2 * a.h2) * dV : *a.ekz;
+  }
+  const double epot = v[3] * dV;
+  const double eint = 0.5 * a.gc * v[4] * dV;
+  const double edd = 0.5 * a.gdd * v[5] * dV;
+  rec[0] = norm;
+  rec[1] = ekin + epot + 2.0 * eint + 2.0 * edd;
+  rec[2] = ekin + epot + eint + edd;
+  rec[3] = ekin;
+  rec[4] = epot;
+  rec[5] = eint;
+  rec[6] = edd;
+  const double r0 = sqrt(v[6] * dV / norm), r1 = sqrt(v[7] * dV / norm), r2 = sqrt(v[8] * dV / norm);
+  rec[7] = r0;
+  rec[8] = (a.geom == 2) ? 0.0 : r1;
+  rec[9] = (a.geom == 0) ? r2 : (a.geom == 2 ? r1 : 0.0);
+  double* dst;
+  if (mode == FIN_OBSERVE) {
+    dst = a.obs;
+  } else {
+    const int pos = *a.ring_pos;
+    dst = a.ring + (size_t)(pos % a.ring_cap) * kRecord;
+    *a.ring_pos = pos + 1;
+  }
+#pragma unroll
+  for (int k = 0; k < kRecord; ++k) dst[k] = rec[k];
+  if (!isfinite(norm)) *a.flags |= 1;
+  if (mode == FIN_OBSERVE) return;
+  // new state: imaginary time renormalises, real time keeps the physical values
+  const double nout = v[9] * dV;
+  if (!isfinite(nout) || !(nout > 0.0)) {
+    *a.flags |= 1;
+    *a.scale = 1.0;
+    return;
+  }
+  const double sn = (mode == FIN_IMAG) ? 1.0 / sqrt(nout) : 1.0;
+  *a.scale = sn;
+  if (a.geom == 0) *a.ekz = 0.5 * sn * sn * v[10] / (a.h2 * a.h2) * dV;
+}
+
+// Called by every thread of every block of a column pass after its partial sums are in
+// `sums` (thread 0).  Publishes them; the last block to arrive runs finalize_block.
+__device__ inline void publish_and_finalize(const double (&sums)[2], double* partials,
+                                            unsigned* counter, const FinArgs& fa, int mode) {
+  __shared__ int is_last;
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(partials + blockIdx.x * 2 + 0, sums[0], __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(partials + blockIdx.x * 2 + 1, sums[1], __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+    const unsigned t = atomicAdd(counter, 1u);
+    is_last = (t == gridDim.x - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (is_last) {
+    __threadfence();
+    finalize_block(fa, mode);
+    if (threadIdx.x == 0) atomicExch(counter, 0u);
+  }
+}
+
+}  // namespace gpdbec

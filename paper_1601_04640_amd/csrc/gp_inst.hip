@@ -127,9 +127,11 @@ hipError_t Launch<T>::conv_col(int n2, int blocks, hipStream_t st, cpx<T>* spec,
 template <>
 hipError_t Launch<T>::cn_col(int n, int mode, bool sums, int blocks, hipStream_t st,
                              cpx<T>* psi, const cpx<T>* cnm, const cpx<T>* cng, double Ar,
-                             double* part, int n0, size_t estride, size_t ostride) {
-#define CN(N, M, S) \
-  GP_LAUNCH((k_cn_col<T, N, M, S>), blocks, st, psi, cnm, cng, Ar, part, n0, estride, ostride)
+                             double* part, int n0, size_t estride, size_t ostride,
+                             unsigned* counter, const FinArgs& fa, int fin_mode) {
+#define CN(N, M, S)                                                                        \
+  GP_LAUNCH((k_cn_col<T, N, M, S>), blocks, st, psi, cnm, cng, Ar, part, n0, estride, ostride, \
+            counter, fa, fin_mode)
   switch (n) {
 #define X(N)                                        \
   case N:                                           \

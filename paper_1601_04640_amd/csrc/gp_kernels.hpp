@@ -24,6 +24,7 @@
 //   finalize     FP64 totals, observables record, renormalisation factor
 #pragma once
 #include "gp_device.hpp"
+#include "gp_finalize.hpp"
 
 namespace gpdbec {
 
@@ -48,6 +49,14 @@ struct StepScalars {
 
 enum : int { MODE_IMAG = 0, MODE_REAL = 1, MODE_OBSERVE = 2, MODE_PHI = 3 };
 
+// Global-memory phases are statically unrolled over ITERS = ceil(elements/kThreads)
+// so that every load of a thread is issued before the first one is consumed.
+template <int TOTAL>
+struct Iters {
+  static constexpr int N = (TOTAL + kThreads - 1) / kThreads;
+  __device__ static __forceinline__ bool valid(int u) { return TOTAL % kThreads == 0 || u < TOTAL; }
+};
+
 // ---------------------------------------------------------------- pass: r2c_x
 // grid: ceil(n1/TJ) * n2 blocks.  partials[b*2 + {0,1}] = sum |dx psi|^2, sum |dy psi|^2
 // of the stored psi (unscaled), the y difference reaching one line past the tile.
@@ -59,51 +68,105 @@ __global__ __launch_bounds__(kThreads) void k_r2c_x(const cpx<T>* __restrict__ p
                                                     double* __restrict__ partials, int n1, int n2) {
   using TL = Tiles<T, N0>;
   constexpr int TJ = TL::TJ, NP = TJ / 2, H = N0 / 2 + 1, LSZ = N0 + 1;
+  using IT = Iters<TJ * N0>;
   __shared__ cpx<T> Z[NP * LSZ];
   __shared__ cpx<T> W[N0];
-  __shared__ double red[2 * kThreads];
+  __shared__ double red[2 * kWaves];
   const int tid = threadIdx.x;
   const int nt1 = (n1 + TJ - 1) / TJ;
   const int k2 = blockIdx.x / nt1;
   const int j0 = (blockIdx.x % nt1) * TJ;
+  const cpx<T>* plane = psi + (size_t)k2 * n1 * N0;
+  // all loads first: the point, its x neighbour and its y neighbour (mostly cache hits)
+  cpx<T> a[IT::N], bx[IT::N], by[IT::N];
+#pragma unroll
+  for (int it = 0; it < IT::N; ++it) {
+    const int u = tid + it * kThreads;
+    const int jl = u / N0, i = u % N0, j = j0 + jl;
+    const cpx<T> z = {0, 0};
+    const bool in = IT::valid(u) && j < n1;
+    // clamped indices keep every load in bounds; at the last point of an axis the
+    // neighbour is the point itself (zero difference), outside the grid all are zero
+    const int jc = min(j, n1 - 1);
+    const cpx<T>* line = plane + (size_t)jc * N0;
+    const cpx<T> l0 = line[i];
+    const cpx<T> l1 = line[min(i + 1, N0 - 1)];
+    const cpx<T> l2 = plane[(size_t)min(jc + 1, n1 - 1) * N0 + i];
+    a[it] = in ? l0 : z;
+    bx[it] = in ? l1 : z;
+    by[it] = in ? l2 : z;
+  }
+  for (int i = tid; i < N0; i += kThreads) W[i] = tw0[i];
   const double s = *scale;
   const T s2 = (T)(s * s);
-  for (int i = tid; i < N0; i += kThreads) W[i] = tw0[i];
   double sums[2] = {0.0, 0.0};
-  for (int u = tid; u < TJ * N0; u += kThreads) {
+#pragma unroll
+  for (int it = 0; it < IT::N; ++it) {
+    const int u = tid + it * kThreads;
+    if (!IT::valid(u)) continue;
     const int jl = u / N0, i = u % N0;
-    const int j = j0 + jl;
-    T nv = 0;
-    if (j < n1) {
-      const cpx<T>* line = psi + ((size_t)k2 * n1 + j) * N0;
-      const cpx<T> a = line[i];
-      nv = s2 * (a.re * a.re + a.im * a.im);
-      if (i + 1 < N0) sums[0] += absdiff2_d(line[i + 1], a);
-      if (j + 1 < n1) sums[1] += absdiff2_d(line[i + N0], a);
-    }
-    T* zc = reinterpret_cast<T*>(&Z[(jl >> 1) * LSZ + i]);
-    zc[jl & 1] = nv;
+    sums[0] += absdiff2_d(bx[it], a[it]);
+    sums[1] += absdiff2_d(by[it], a[it]);
+    const T nv = s2 * (a[it].re * a[it].re + a[it].im * a[it].im);
+    cpx<T>& zc = Z[(jl >> 1) * LSZ + i];
+    if (jl & 1) zc.im = nv;
+    else zc.re = nv;
   }
   __syncthreads();
   LdsFFT<T, N0, NP, LSZ, 1, false>::template run<false>(Z, W);
   // untangle the two real lines of each pair and store kx = 0..N0/2
-  for (int u = tid; u < H * NP; u += kThreads) {
+  using IH = Iters<H * NP>;
+#pragma unroll
+  for (int it = 0; it < IH::N; ++it) {
+    const int u = tid + it * kThreads;
+    if (!IH::valid(u)) continue;
     const int p = u % NP, kx = u / NP;
     const int j = j0 + 2 * p;
     if (j >= n1) continue;
     const cpx<T> zk = Z[p * LSZ + kx];
     const cpx<T> zm = Z[p * LSZ + ((N0 - kx) % N0)];
     const T hf = (T)0.5;
-    cpx<T> a = {hf * (zk.re + zm.re), hf * (zk.im - zm.im)};
-    cpx<T> b = {hf * (zk.im + zm.im), hf * (zm.re - zk.re)};
+    const cpx<T> ra = {hf * (zk.re + zm.re), hf * (zk.im - zm.im)};
+    const cpx<T> rb = {hf * (zk.im + zm.im), hf * (zm.re - zk.re)};
     cpx<T>* o = spec + ((size_t)kx * n2 + k2) * n1 + j;
-    o[0] = a;
-    o[1] = b;  // n1 is even, so line j+1 exists whenever line j does
+    o[0] = ra;
+    o[1] = rb;  // n1 is even, so line j+1 exists whenever line j does
   }
   block_sum<2>(sums, red);
   if (tid == 0) {
     partials[blockIdx.x * 2 + 0] = sums[0];
     partials[blockIdx.x * 2 + 1] = sums[1];
+  }
+}
+
+// Loads LB contiguous lines of length N into LDS rows of stride N + 1.
+template <typename T, int N, int LB>
+__device__ __forceinline__ void load_lines(cpx<T>* B, const cpx<T>* __restrict__ data, int l0,
+                                           int nlines) {
+  using IT = Iters<LB * N>;
+  cpx<T> v[IT::N];
+#pragma unroll
+  for (int it = 0; it < IT::N; ++it) {
+    const int u = threadIdx.x + it * kThreads;
+    const int l = u / N, i = u % N;
+    v[it] = (IT::valid(u) && l0 + l < nlines) ? data[(size_t)(l0 + l) * N + i] : cpx<T>{0, 0};
+  }
+#pragma unroll
+  for (int it = 0; it < IT::N; ++it) {
+    const int u = threadIdx.x + it * kThreads;
+    if (IT::valid(u)) B[(u / N) * (N + 1) + u % N] = v[it];
+  }
+}
+
+template <typename T, int N, int LB>
+__device__ __forceinline__ void store_lines(const cpx<T>* B, cpx<T>* __restrict__ data, int l0,
+                                            int nlines) {
+  using IT = Iters<LB * N>;
+#pragma unroll
+  for (int it = 0; it < IT::N; ++it) {
+    const int u = threadIdx.x + it * kThreads;
+    const int l = u / N, i = u % N;
+    if (IT::valid(u) && l0 + l < nlines) data[(size_t)(l0 + l) * N + i] = B[l * (N + 1) + i];
   }
 }
 
@@ -115,19 +178,12 @@ __global__ __launch_bounds__(kThreads) void k_fft_line(cpx<T>* __restrict__ data
   constexpr int LB = Tiles<T, N>::LB, LSZ = N + 1;
   __shared__ cpx<T> B[LB * LSZ];
   __shared__ cpx<T> W[N];
-  const int tid = threadIdx.x;
   const int l0 = blockIdx.x * LB;
-  for (int i = tid; i < N; i += kThreads) W[i] = tw[i];
-  for (int u = tid; u < LB * N; u += kThreads) {
-    const int l = u / N, i = u % N;
-    B[l * LSZ + i] = (l0 + l < nlines) ? data[(size_t)(l0 + l) * N + i] : cpx<T>{0, 0};
-  }
+  load_lines<T, N, LB>(B, data, l0, nlines);
+  for (int i = threadIdx.x; i < N; i += kThreads) W[i] = tw[i];
   __syncthreads();
   LdsFFT<T, N, LB, LSZ, 1, false>::template run<INV>(B, W);
-  for (int u = tid; u < LB * N; u += kThreads) {
-    const int l = u / N, i = u % N;
-    if (l0 + l < nlines) data[(size_t)(l0 + l) * N + i] = B[l * LSZ + i];
-  }
+  store_lines<T, N, LB>(B, data, l0, nlines);
 }
 
 // FFT -> multiply by the kernel table -> inverse FFT of contiguous lines (2D: y lines).
@@ -136,28 +192,33 @@ __global__ __launch_bounds__(kThreads) void k_conv_line(cpx<T>* __restrict__ dat
                                                         const T* __restrict__ ktab,
                                                         const cpx<T>* __restrict__ tw, int nlines) {
   constexpr int LB = Tiles<T, N>::LB, LSZ = N + 1;
+  using IT = Iters<LB * N>;
   __shared__ cpx<T> B[LB * LSZ];
   __shared__ cpx<T> W[N];
   const int tid = threadIdx.x;
   const int l0 = blockIdx.x * LB;
-  for (int i = tid; i < N; i += kThreads) W[i] = tw[i];
-  for (int u = tid; u < LB * N; u += kThreads) {
+  load_lines<T, N, LB>(B, data, l0, nlines);
+  T kv[IT::N];  // kernel values: loaded now, used after the forward FFT
+#pragma unroll
+  for (int it = 0; it < IT::N; ++it) {
+    const int u = tid + it * kThreads;
     const int l = u / N, i = u % N;
-    B[l * LSZ + i] = (l0 + l < nlines) ? data[(size_t)(l0 + l) * N + i] : cpx<T>{0, 0};
+    kv[it] = (IT::valid(u) && l0 + l < nlines) ? ktab[(size_t)(l0 + l) * N + i] : (T)0;
   }
+  for (int i = tid; i < N; i += kThreads) W[i] = tw[i];
   __syncthreads();
   LdsFFT<T, N, LB, LSZ, 1, false>::template run<false>(B, W);
-  for (int u = tid; u < LB * N; u += kThreads) {
-    const int l = u / N, i = u % N;
-    const T k = (l0 + l < nlines) ? ktab[(size_t)(l0 + l) * N + i] : (T)0;
-    B[l * LSZ + i] = scl(B[l * LSZ + i], k);
+#pragma unroll
+  for (int it = 0; it < IT::N; ++it) {
+    const int u = tid + it * kThreads;
+    if (IT::valid(u)) {
+      cpx<T>& e = B[(u / N) * LSZ + u % N];
+      e = scl(e, kv[it]);
+    }
   }
   __syncthreads();
   LdsFFT<T, N, LB, LSZ, 1, false>::template run<true>(B, W);
-  for (int u = tid; u < LB * N; u += kThreads) {
-    const int l = u / N, i = u % N;
-    if (l0 + l < nlines) data[(size_t)(l0 + l) * N + i] = B[l * LSZ + i];
-  }
+  store_lines<T, N, LB>(B, data, l0, nlines);
 }
 
 // --------------------------------------------------------------- pass: conv_col
@@ -168,30 +229,48 @@ __global__ __launch_bounds__(kThreads) void k_conv_col(cpx<T>* __restrict__ spec
                                                        const T* __restrict__ ktab,
                                                        const cpx<T>* __restrict__ tw2, int n1) {
   constexpr int TC = Tiles<T, N2>::TC, RS = TC + 1;
+  using IT = Iters<N2 * TC>;
   __shared__ cpx<T> B[N2 * RS];
   __shared__ cpx<T> W[N2];
   const int tid = threadIdx.x;
   const int nt = (n1 + TC - 1) / TC;
   const int kx = blockIdx.x / nt;
   const int c0 = (blockIdx.x % nt) * TC;
-  for (int i = tid; i < N2; i += kThreads) W[i] = tw2[i];
   const size_t plane = (size_t)kx * N2 * n1;
-  for (int u = tid; u < N2 * TC; u += kThreads) {
+  cpx<T> v[IT::N];
+  T kv[IT::N];
+#pragma unroll
+  for (int it = 0; it < IT::N; ++it) {
+    const int u = tid + it * kThreads;
     const int c = u % TC, r = u / TC;
-    B[r * RS + c] = (c0 + c < n1) ? spec[plane + (size_t)r * n1 + c0 + c] : cpx<T>{0, 0};
+    const bool in = IT::valid(u) && c0 + c < n1;
+    const size_t g = plane + (size_t)r * n1 + c0 + c;
+    v[it] = in ? spec[g] : cpx<T>{0, 0};
+    kv[it] = in ? ktab[g] : (T)0;
+  }
+  for (int i = tid; i < N2; i += kThreads) W[i] = tw2[i];
+#pragma unroll
+  for (int it = 0; it < IT::N; ++it) {
+    const int u = tid + it * kThreads;
+    if (IT::valid(u)) B[(u / TC) * RS + u % TC] = v[it];
   }
   __syncthreads();
   LdsFFT<T, N2, TC, 1, RS, true>::template run<false>(B, W);
-  for (int u = tid; u < N2 * TC; u += kThreads) {
-    const int c = u % TC, r = u / TC;
-    const T k = (c0 + c < n1) ? ktab[plane + (size_t)r * n1 + c0 + c] : (T)0;
-    B[r * RS + c] = scl(B[r * RS + c], k);
+#pragma unroll
+  for (int it = 0; it < IT::N; ++it) {
+    const int u = tid + it * kThreads;
+    if (IT::valid(u)) {
+      cpx<T>& e = B[(u / TC) * RS + u % TC];
+      e = scl(e, kv[it]);
+    }
   }
   __syncthreads();
   LdsFFT<T, N2, TC, 1, RS, true>::template run<true>(B, W);
-  for (int u = tid; u < N2 * TC; u += kThreads) {
+#pragma unroll
+  for (int it = 0; it < IT::N; ++it) {
+    const int u = tid + it * kThreads;
     const int c = u % TC, r = u / TC;
-    if (c0 + c < n1) spec[plane + (size_t)r * n1 + c0 + c] = B[r * RS + c];
+    if (IT::valid(u) && c0 + c < n1) spec[plane + (size_t)r * n1 + c0 + c] = B[r * RS + c];
   }
 }
 
@@ -210,16 +289,42 @@ __global__ __launch_bounds__(kThreads) void k_c2r_nl_cnx(
   constexpr int TJ = TL::TJ, NP = TJ / 2, H = N0 / 2 + 1, LSZ = N0 + 1;
   constexpr int PX = TL::PX, SX = (N0 + PX - 1) / PX, LSP = N0 + (N0 + SX - 1) / SX;
   constexpr bool STEP = (MODE == MODE_IMAG || MODE == MODE_REAL);
+  constexpr bool NEEDPSI = (MODE != MODE_PHI);
+  using IT = Iters<TJ * N0>;
+  using IH = Iters<H * NP>;
   __shared__ cpx<T> Z[NP * LSZ];
   __shared__ cpx<T> PS[STEP ? TJ * LSP : 1];
   __shared__ cpx<T> W[N0];
   __shared__ cpx<T> MT[STEP ? N0 : 1], GT[STEP ? N0 : 1];
-  __shared__ double red[7 * kThreads];
+  __shared__ double red[7 * kWaves];
   const int tid = threadIdx.x;
   const int nt1 = (n1 + TJ - 1) / TJ;
   const int k2 = blockIdx.x / nt1;
   const int j0 = (blockIdx.x % nt1) * TJ;
-  const double s = *scale;
+  const size_t pbase = ((size_t)k2 * n1 + j0) * N0;  // first point of the tile
+  // issue every global load of the block up front: spectrum pairs, psi and V tiles
+  cpx<T> sa[IH::N], sb[IH::N];
+#pragma unroll
+  for (int it = 0; it < IH::N; ++it) {
+    const int u = tid + it * kThreads;
+    const int p = u % NP, kx = u / NP;
+    const int j = j0 + 2 * p;
+    const bool in = IH::valid(u) && j < n1;
+    const cpx<T>* o = spec + ((size_t)kx * n2 + k2) * n1 + j;
+    sa[it] = in ? o[0] : cpx<T>{0, 0};
+    sb[it] = in ? o[1] : cpx<T>{0, 0};
+  }
+  cpx<T> pv[NEEDPSI ? IT::N : 1];
+  T vv[NEEDPSI ? IT::N : 1];
+  if constexpr (NEEDPSI) {
+#pragma unroll
+    for (int it = 0; it < IT::N; ++it) {
+      const int u = tid + it * kThreads;
+      const bool in = IT::valid(u) && j0 + u / N0 < n1;
+      pv[it] = in ? psi[pbase + u] : cpx<T>{0, 0};
+      vv[it] = in ? V[pbase + u] : (T)0;
+    }
+  }
   for (int i = tid; i < N0; i += kThreads) {
     W[i] = tw0[i];
     if constexpr (STEP) {
@@ -227,16 +332,13 @@ __global__ __launch_bounds__(kThreads) void k_c2r_nl_cnx(
       GT[i] = cng[i];
     }
   }
-  // gather the Hermitian half spectrum of each line pair into a full complex line
-  for (int u = tid; u < H * NP; u += kThreads) {
+  // the Hermitian half spectrum of each line pair -> a full complex line
+#pragma unroll
+  for (int it = 0; it < IH::N; ++it) {
+    const int u = tid + it * kThreads;
+    if (!IH::valid(u)) continue;
     const int p = u % NP, kx = u / NP;
-    const int j = j0 + 2 * p;
-    cpx<T> a = {0, 0}, b = {0, 0};
-    if (j < n1) {
-      const cpx<T>* o = spec + ((size_t)kx * n2 + k2) * n1 + j;
-      a = o[0];
-      b = o[1];
-    }
+    const cpx<T> a = sa[it], b = sb[it];
     cpx<T>* z = Z + p * LSZ;
     if (kx == 0 || kx == N0 / 2) {
       z[kx] = cpx<T>{a.re, b.re};
@@ -248,63 +350,71 @@ __global__ __launch_bounds__(kThreads) void k_c2r_nl_cnx(
   __syncthreads();
   LdsFFT<T, N0, NP, LSZ, 1, false>::template run<true>(Z, W);
 
-  double sums[7] = {0, 0, 0, 0, 0, 0, 0};
-  const T ts = (T)s;
-  const double h0 = sc.h0, h1 = sc.h1, h2 = sc.h2;
-  for (int u = tid; u < TJ * N0; u += kThreads) {
-    const int jl = u / N0, i = u % N0;
-    const int j = j0 + jl;
-    if (j >= n1) {
-      if constexpr (STEP) PS[jl * LSP + cpad<SX>(i)] = cpx<T>{0, 0};
-      continue;
+  if constexpr (MODE == MODE_PHI) {
+#pragma unroll
+    for (int it = 0; it < IT::N; ++it) {
+      const int u = tid + it * kThreads;
+      const int jl = u / N0, i = u % N0;
+      if (IT::valid(u) && j0 + jl < n1)
+        phi_out[pbase + u] = reinterpret_cast<const T*>(&Z[(jl >> 1) * LSZ + i])[jl & 1];
     }
-    const size_t g = ((size_t)k2 * n1 + j) * N0 + i;
-    const T phi = reinterpret_cast<const T*>(&Z[(jl >> 1) * LSZ + i])[jl & 1];
-    if constexpr (MODE == MODE_PHI) {
-      phi_out[g] = phi;
-      continue;
-    }
-    cpx<T> p = psi[g];
-    p = scl(p, ts);
-    const T v = V[g];
-    const double nd = abs2_d(p);
-    const double xc = (i - N0 / 2) * h0, yc = (j - n1 / 2) * h1, zc = (k2 - n2 / 2) * h2;
-    sums[0] += nd;
-    sums[1] += (double)v * nd;
-    sums[2] += nd * nd;
-    sums[3] += (double)phi * nd;
-    sums[4] += xc * xc * nd;
-    sums[5] += yc * yc * nd;
-    sums[6] += zc * zc * nd;
-    if constexpr (STEP) {
-      const T n = p.re * p.re + p.im * p.im;
-      const T th = (T)sc.dt * (v + (T)sc.gc * n + (T)sc.gdd * phi);
-      cpx<T> f;
-      if constexpr (MODE == MODE_IMAG) {
-        f = cpx<T>{exp(-th), (T)0};
-      } else {
-        f = cpx<T>{cos(th), -sin(th)};
+    return;
+  } else {
+    double sums[7] = {0, 0, 0, 0, 0, 0, 0};
+    const T ts = (T)(*scale);
+    const double h0 = sc.h0, h1 = sc.h1, h2 = sc.h2;
+    const double zc = (k2 - n2 / 2) * h2;
+#pragma unroll
+    for (int it = 0; it < IT::N; ++it) {
+      const int u = tid + it * kThreads;
+      if (!IT::valid(u)) continue;
+      const int jl = u / N0, i = u % N0;
+      const int j = j0 + jl;
+      if (j >= n1) {
+        if constexpr (STEP) PS[jl * LSP + cpad<SX>(i)] = cpx<T>{0, 0};
+        continue;
       }
-      PS[jl * LSP + cpad<SX>(i)] = p * f;
+      const T phi = reinterpret_cast<const T*>(&Z[(jl >> 1) * LSZ + i])[jl & 1];
+      const cpx<T> p = scl(pv[it], ts);
+      const T v = vv[it];
+      const double nd = abs2_d(p);
+      const double xc = (i - N0 / 2) * h0, yc = (j - n1 / 2) * h1;
+      sums[0] += nd;
+      sums[1] += (double)v * nd;
+      sums[2] += nd * nd;
+      sums[3] += (double)phi * nd;
+      sums[4] += xc * xc * nd;
+      sums[5] += yc * yc * nd;
+      sums[6] += zc * zc * nd;
+      if constexpr (STEP) {
+        const T n = p.re * p.re + p.im * p.im;
+        const T th = (T)sc.dt * (v + (T)sc.gc * n + (T)sc.gdd * phi);
+        cpx<T> f;
+        if constexpr (MODE == MODE_IMAG) {
+          f = cpx<T>{exp(-th), (T)0};
+        } else {
+          f = cpx<T>{cos(th), -sin(th)};
+        }
+        PS[jl * LSP + cpad<SX>(i)] = p * f;
+      }
     }
-  }
-  if constexpr (MODE != MODE_PHI) {
     block_sum<7>(sums, red);
     if (tid == 0) {
 #pragma unroll
       for (int k = 0; k < 7; ++k) partials[blockIdx.x * 7 + k] = sums[k];
     }
-  }
-  if constexpr (STEP) {
-    __syncthreads();
-    const cpx<T> A = (MODE == MODE_IMAG) ? cpx<T>{(T)sc.Ar, 0} : cpx<T>{0, (T)sc.Ar};
-    const cpx<T> B = (MODE == MODE_IMAG) ? cpx<T>{(T)(1.0 - 2.0 * sc.Ar), 0}
-                                         : cpx<T>{(T)1, (T)(-2.0 * sc.Ar)};
-    cn_solve_lines<T, N0, TJ, LSP, 1, PX>(PS, MT, GT, A, B);
-    for (int u = tid; u < TJ * N0; u += kThreads) {
-      const int jl = u / N0, i = u % N0;
-      const int j = j0 + jl;
-      if (j < n1) psi[((size_t)k2 * n1 + j) * N0 + i] = PS[jl * LSP + cpad<SX>(i)];
+    if constexpr (STEP) {
+      __syncthreads();
+      const cpx<T> A = (MODE == MODE_IMAG) ? cpx<T>{(T)sc.Ar, 0} : cpx<T>{0, (T)sc.Ar};
+      const cpx<T> B = (MODE == MODE_IMAG) ? cpx<T>{(T)(1.0 - 2.0 * sc.Ar), 0}
+                                           : cpx<T>{(T)1, (T)(-2.0 * sc.Ar)};
+      cn_solve_lines<T, N0, TJ, LSP, 1, PX>(PS, MT, GT, A, B);
+#pragma unroll
+      for (int it = 0; it < IT::N; ++it) {
+        const int u = tid + it * kThreads;
+        const int jl = u / N0, i = u % N0;
+        if (IT::valid(u) && j0 + jl < n1) psi[pbase + u] = PS[jl * LSP + cpad<SX>(i)];
+      }
     }
   }
 }
@@ -315,35 +425,47 @@ __global__ __launch_bounds__(kThreads) void k_c2r_nl_cnx(
 //   y sweep (3D/2D): estride = n0, outer = k2 (n_outer = n2), base = k2*n1*n0
 //   z sweep (3D):    estride = n0*n1, outer = k1 (n_outer = n1), base = k1*n0
 // SUMS: also partials[b*2+{0,1}] = sum |u|^2, sum |u_{i+1}-u_i|^2 along the line of the
-// result (MODE_OBSERVE: of the stored input, nothing written; sums unscaled).
+// result (MODE_OBSERVE: of the stored input, nothing written; sums unscaled), and the
+// last block to finish runs the step's FP64 finalisation (fin_mode, FinArgs).
 // grid: ceil(n0/TC) * n_outer blocks.
 template <typename T, int N, int MODE, bool SUMS>
 __global__ __launch_bounds__(kThreads) void k_cn_col(cpx<T>* __restrict__ psi,
                                                      const cpx<T>* __restrict__ cnm,
                                                      const cpx<T>* __restrict__ cng,
                                                      double Ar, double* __restrict__ partials,
-                                                     int n0, size_t estride, size_t ostride) {
+                                                     int n0, size_t estride, size_t ostride,
+                                                     unsigned* counter, FinArgs fa,
+                                                     int fin_mode) {
   using TL = Tiles<T, N>;
   constexpr int TC = TL::TC, PC = TL::PC, SC = (N + PC - 1) / PC, RS = TC + 1;
   constexpr int NR = N + (N + SC - 1) / SC;  // padded rows
   constexpr bool SOLVE = (MODE == MODE_IMAG || MODE == MODE_REAL);
+  using IT = Iters<N * TC>;
   __shared__ cpx<T> B[NR * RS];
   __shared__ cpx<T> MT[SOLVE ? N : 1], GT[SOLVE ? N : 1];
-  __shared__ double red[2 * kThreads];
+  __shared__ double red[2 * kWaves];
   const int tid = threadIdx.x;
   const int nt = (n0 + TC - 1) / TC;
   const int outer = blockIdx.x / nt;
   const int x0 = (blockIdx.x % nt) * TC;
   cpx<T>* base = psi + (size_t)outer * ostride + x0;
+  cpx<T> v[IT::N];
+#pragma unroll
+  for (int it = 0; it < IT::N; ++it) {
+    const int u = tid + it * kThreads;
+    const int c = u % TC, r = u / TC;
+    v[it] = (IT::valid(u) && x0 + c < n0) ? base[(size_t)r * estride + c] : cpx<T>{0, 0};
+  }
   if constexpr (SOLVE) {
     for (int i = tid; i < N; i += kThreads) {
       MT[i] = cnm[i];
       GT[i] = cng[i];
     }
   }
-  for (int u = tid; u < N * TC; u += kThreads) {
-    const int c = u % TC, r = u / TC;
-    B[cpad<SC>(r) * RS + c] = (x0 + c < n0) ? base[(size_t)r * estride + c] : cpx<T>{0, 0};
+#pragma unroll
+  for (int it = 0; it < IT::N; ++it) {
+    const int u = tid + it * kThreads;
+    if (IT::valid(u)) B[cpad<SC>(u / TC) * RS + u % TC] = v[it];
   }
   __syncthreads();
   if constexpr (SOLVE) {
@@ -353,22 +475,21 @@ __global__ __launch_bounds__(kThreads) void k_cn_col(cpx<T>* __restrict__ psi,
     cn_solve_lines<T, N, TC, 1, RS, PC>(B, MT, GT, A, Bc);
   }
   double sums[2] = {0.0, 0.0};
-  for (int u = tid; u < N * TC; u += kThreads) {
+#pragma unroll
+  for (int it = 0; it < IT::N; ++it) {
+    const int u = tid + it * kThreads;
     const int c = u % TC, r = u / TC;
-    if (x0 + c >= n0) continue;
-    const cpx<T> v = B[cpad<SC>(r) * RS + c];
-    if constexpr (SOLVE) base[(size_t)r * estride + c] = v;
+    if (!IT::valid(u) || x0 + c >= n0) continue;
+    const cpx<T> val = B[cpad<SC>(r) * RS + c];
+    if constexpr (SOLVE) base[(size_t)r * estride + c] = val;
     if constexpr (SUMS) {
-      sums[0] += abs2_d(v);
-      if (r + 1 < N) sums[1] += absdiff2_d(B[cpad<SC>(r + 1) * RS + c], v);
+      sums[0] += abs2_d(val);
+      if (r + 1 < N) sums[1] += absdiff2_d(B[cpad<SC>(r + 1) * RS + c], val);
     }
   }
   if constexpr (SUMS) {
     block_sum<2>(sums, red);
-    if (tid == 0) {
-      partials[blockIdx.x * 2 + 0] = sums[0];
-      partials[blockIdx.x * 2 + 1] = sums[1];
-    }
+    publish_and_finalize(sums, partials, counter, fa, fin_mode);
   }
 }
 

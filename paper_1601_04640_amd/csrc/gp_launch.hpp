@@ -6,6 +6,7 @@
 #include <stddef.h>
 
 #include "gp_device.hpp"
+#include "gp_finalize.hpp"
 
 #define GP_FOR_SIZES(X) \
   X(8) X(10) X(12) X(16) X(20) X(24) X(30) X(32) X(40) X(48) X(60) X(64) X(80) X(96) X(120) \
@@ -39,7 +40,8 @@ struct Launch {
                                const StepScalars& sc, double* part, T* phi_out, int n1, int n2);
   static hipError_t cn_col(int n, int mode, bool sums, int blocks, hipStream_t st, cpx<T>* psi,
                            const cpx<T>* cnm, const cpx<T>* cng, double Ar, double* part, int n0,
-                           size_t estride, size_t ostride);
+                           size_t estride, size_t ostride, unsigned* counter,
+                           const FinArgs& fa, int fin_mode);
 };
 
 // The members are defined (explicitly specialised) per precision in gp_inst.hip.
@@ -61,7 +63,7 @@ struct Launch {
                                                const StepScalars&, double*, T*, int, int);     \
   template <> hipError_t Launch<T>::cn_col(int, int, bool, int, hipStream_t, cpx<T>*,         \
                                            const cpx<T>*, const cpx<T>*, double, double*, int, \
-                                           size_t, size_t);
+                                           size_t, size_t, unsigned*, const FinArgs&, int);
 GP_DECLARE_LAUNCH(float)
 GP_DECLARE_LAUNCH(double)
 #undef GP_DECLARE_LAUNCH

@@ -111,13 +111,15 @@ def test_set_potential_and_quench(prec, gpu_lib):
     s = make_solver(w, prec)
     s.set_psi(psi0)
     s.set_potential(V)
-    s.step_imag(5)
-    s.set_couplings(12.0, 3.0)
-    s.step_real(7)
+    s.step_imag(10)
+    s.step_real(9)
+    s.set_couplings(12.0, 3.0)      # captured graphs must pick up the new couplings
+    s.step_real(9)
     got = s.get_psi()
-    ref = O.run(psi0, p, True, 5, V=V)
+    ref = O.run(psi0, p, True, 10, V=V)
+    ref = O.run(ref, p, False, 9, V=V)
     p2 = oparams({**w, "g": 12.0, "gdd": 3.0})
-    ref = O.run(ref, p2, False, 7, V=V)
+    ref = O.run(ref, p2, False, 9, V=V)
     err = rel_l2(got, ref)
     assert err <= (FP64_PSI_TOL if prec == "fp64" else FP32_PSI_TOL), err
     s.close()
@@ -169,4 +171,43 @@ def test_zero_steps_and_boundary_zeroing(gpu_lib):
     s.step_real(0)
     got = s.get_psi()
     assert np.array_equal(got, O.zero_boundary(psi))
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_graph_replay_equals_direct_launches(prec, gpu_lib):
+    """Steps replayed from captured HIP graphs are bitwise equal to direct launches, for
+    every replay, with host synchronisation and eager work between replays."""
+    w = CASES["3d_40x30x48"]
+    banner("graph vs direct", prec)
+    psi0 = start_state(w, 107)
+    runs = []
+    for graphs in (True, False):
+        s = make_solver(w, prec)
+        s.use_graphs(graphs)
+        s.set_psi(psi0)
+        states = []
+        s.step_imag(16)                       # two replays of the imaginary-time graph
+        states.append(s.get_psi())
+        for _ in range(3):                    # three separate replays of the real-time graph
+            s.step_real(8)
+            states.append(s.get_psi())        # synchronises; eager copy kernel in between
+            states.append(s.dipolar_potential())
+        runs.append((states, s.history(40)))
+        s.close()
+    for a, b in zip(runs[0][0], runs[1][0]):
+        assert np.array_equal(a, b)
+    assert runs[0][1] == runs[1][1]
+
+
+def test_timing_counts_launches(gpu_lib):
+    w = CASES["3d_24x20x16"]
+    banner("timing")
+    s = make_solver(w, "fp32")
+    s.set_psi(start_state(w, 108))
+    s.timing_enable(["c2r_nl_cnx", "cn_z"])
+    s.step_real(10)
+    t = s.timing_read()
+    assert t["c2r_nl_cnx"][1] == 10 and t["cn_z"][1] == 10 and t["r2c_x"][1] == 0
+    assert t["c2r_nl_cnx"][0] > 0
     s.close()
