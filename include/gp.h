@@ -119,6 +119,23 @@ gp_status gp_set_couplings(gp_ctx* ctx, double g, double gdd);
 gp_status gp_step_imag(gp_ctx* ctx, int nsteps);
 gp_status gp_step_real(gp_ctx* ctx, int nsteps);
 
+/* Backpropagation through one real-time step (gp_step_real with nsteps = 1).
+ * All pointers are device pointers.  psi_n: the forward state at the START of the step
+ * (interleaved complex, context precision, physical values).  lam: in: the costate
+ * dL/d conj(psi) at the end of the step; out: at its start (context precision, in
+ * place).  gradV: double grid (psi layout), accumulated += dL/dV of this step.
+ * grad_g, grad_gdd: one double each, accumulated += dL/dg (3D units; the quasi-2D
+ * contact factor 1/(sqrt(2 pi) d) is applied) and += dL/dg_dd.  With the convention
+ * dL = 2 Re sum conj(lam) dpsi:
+ *   lam_a = C_x(-dt) C_y(-dt) C_z(-dt) lam     (adjoint CN sweeps)
+ *   mu = exp(+i dt theta) lam_a,  s = 2 dt Im(conj(mu) psi_n),  theta of psi_n
+ *   dL/dV += s, dL/dg_c += sum s n, dL/dg_dd += sum s Phi
+ *   lam_n = mu + (g_c s + g_dd F^-1[U F[s]]) psi_n
+ * Uses the context's workspace (spectrum, scratch field) and couplings/potential; the
+ * context's own psi is left unchanged.  Asynchronous on the context's stream. */
+gp_status gp_step_real_adjoint(gp_ctx* ctx, const void* psi_n, void* lam, double* gradV,
+                               double* grad_g, double* grad_gdd);
+
 /* Observables of the current psi (computes Phi of this psi).  Synchronous. */
 gp_status gp_energy(gp_ctx* ctx, gp_observables* out);
 

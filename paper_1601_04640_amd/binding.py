@@ -76,6 +76,7 @@ _SIGS = {
     "gp_sync": (ctypes.c_int, [_P]),
     "gp_last_error": (ctypes.c_char_p, []),
     "gp_use_graphs": (ctypes.c_int, [_P, ctypes.c_int]),
+    "gp_step_real_adjoint": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "gp_timing_enable": (ctypes.c_int, [_P, ctypes.c_uint]),
     "gp_timing_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_int)]),
@@ -177,6 +178,12 @@ def gp_step_imag(ctx: int, nsteps: int):
 
 def gp_step_real(ctx: int, nsteps: int):
     _check(load().gp_step_real(_P(ctx), nsteps), "gp_step_real")
+
+
+def gp_step_real_adjoint(ctx: int, psi_n: int, lam: int, gradV: int, grad_g: int,
+                         grad_gdd: int):
+    _check(load().gp_step_real_adjoint(_P(ctx), _P(psi_n), _P(lam), _P(gradV), _P(grad_g),
+                                       _P(grad_gdd)), "gp_step_real_adjoint")
 
 
 def gp_energy(ctx: int) -> dict:

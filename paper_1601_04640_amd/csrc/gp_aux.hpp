@@ -30,14 +30,15 @@ __device__ inline zd zinv(zd a) {
   const double d = a.re * a.re + a.im * a.im;
   return {a.re / d, -a.im / d};
 }
+// Third set: A = -i Ar, the adjoint sweep of a real-time step (conjugate factors).
 template <typename T>
-__global__ void k_cn_tables(cpx<T>* m_im, cpx<T>* g_im, cpx<T>* m_re, cpx<T>* g_re, int N,
-                            double Ar) {
-  if (blockIdx.x != 0 || threadIdx.x > 1) return;
-  const bool real_time = threadIdx.x == 1;
-  cpx<T>* mt = real_time ? m_re : m_im;
-  cpx<T>* gt = real_time ? g_re : g_im;
-  const zd A = real_time ? zd{0.0, Ar} : zd{Ar, 0.0};
+__global__ void k_cn_tables(cpx<T>* m_im, cpx<T>* g_im, cpx<T>* m_re, cpx<T>* g_re,
+                            cpx<T>* m_adj, cpx<T>* g_adj, int N, double Ar) {
+  if (blockIdx.x != 0 || threadIdx.x > 2) return;
+  const int set = threadIdx.x;
+  cpx<T>* mt = set == 0 ? m_im : (set == 1 ? m_re : m_adj);
+  cpx<T>* gt = set == 0 ? g_im : (set == 1 ? g_re : g_adj);
+  const zd A = set == 0 ? zd{Ar, 0.0} : (set == 1 ? zd{0.0, Ar} : zd{0.0, -Ar});
   const zd a = {-A.re, -A.im};
   const zd b = {1.0 + 2.0 * A.re, 2.0 * A.im};
   zd c = {0.0, 0.0};
@@ -178,10 +179,29 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a, int mode) {
   finalize_block(a, mode);
 }
 
-__global__ void k_reset_state(double* scale, double* ekz, int* flags, int* ring_pos,
-                              unsigned* counter) {
+// dL/dg += cfac * sum(s n), dL/dg_dd += sum(s Phi) over the k_adj_x partials (one block,
+// fixed summation order).
+__global__ __launch_bounds__(kThreads) void k_adj_reduce(const double* __restrict__ partials,
+                                                         int nb, double cfac, double* grad_g,
+                                                         double* grad_gdd) {
+  __shared__ double red[2 * kWaves];
+  double v[2] = {0.0, 0.0};
+  for (int b = threadIdx.x; b < nb; b += kThreads) {
+    v[0] += partials[2 * b];
+    v[1] += partials[2 * b + 1];
+  }
+  block_sum<2>(v, red);
+  if (threadIdx.x == 0) {
+    *grad_g += cfac * v[0];
+    *grad_gdd += v[1];
+  }
+}
+
+__global__ void k_reset_state(double* scale, double* one, double* ekz, int* flags,
+                              int* ring_pos, unsigned* counter) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     *scale = 1.0;
+    *one = 1.0;
     *ekz = 0.0;
     *flags = 0;
     *ring_pos = 0;

@@ -42,12 +42,13 @@ struct Layout {
   size_t esz;           // bytes of one real value
   int nb_x, nb_col, nb_colobs;
   // byte offsets inside the workspace
-  size_t o_psi, o_V, o_spec, o_ktab, o_tw[3], o_cn[3][4], o_px, o_pnl, o_pcol, o_scalars,
-      o_ring, o_obs, o_io, total;
+  size_t o_psi, o_V, o_spec, o_ktab, o_tw[3], o_cn[3][6], o_px, o_pnl, o_pcol, o_padj, o_sfield,
+      o_scalars, o_ring, o_obs, o_io, total;
 };
 
 struct Scalars {  // device-side scalars (one 256-byte block)
   double scale;
+  double one;        // constant 1 (scale of an externally supplied psi)
   double ekz;
   double obs_pad;
   int flags;
@@ -119,11 +120,13 @@ Layout make_layout(const gp_params* p) {
   const int ns[3] = {L.n0, L.n1, L.n2};
   for (int a = 0; a < 3; ++a) {
     L.o_tw[a] = take(2 * L.esz * ns[a]);
-    for (int t = 0; t < 4; ++t) L.o_cn[a][t] = take(2 * L.esz * ns[a]);
+    for (int t = 0; t < 6; ++t) L.o_cn[a][t] = take(2 * L.esz * ns[a]);
   }
   L.o_px = take(sizeof(double) * 2 * L.nb_x);
   L.o_pnl = take(sizeof(double) * 7 * L.nb_x);
   L.o_pcol = take(sizeof(double) * 2 * L.nb_col);
+  L.o_padj = take(sizeof(double) * 2 * L.nb_x);
+  L.o_sfield = take(L.esz * L.npts);
   L.o_scalars = take(sizeof(Scalars));
   L.o_ring = take(sizeof(double) * kRecord * kRingCap);
   L.o_obs = take(sizeof(double) * kRecord);
@@ -266,13 +269,10 @@ struct Passes {
   static const cpx<T>* tw(gp_ctx* c, int a) { return c->at<cpx<T>>(c->L.o_tw[a]); }
   static const cpx<T>* cn(gp_ctx* c, int a, int k) { return c->at<cpx<T>>(c->L.o_cn[a][k]); }
 
-  // density -> spectrum -> U(k) product -> back to the x-half spectrum
-  static gp_status convolution(gp_ctx* c) {
+  // y/z transforms of the x-half spectrum, U(k)/N product, inverse y/z transforms
+  static gp_status spectrum_passes(gp_ctx* c) {
     const Layout& L = c->L;
     const int H = L.n0 / 2 + 1;
-    GP_PASS(c, GP_PASS_R2C_X,
-            Launch<T>::r2c_x(L.n0, L.nb_x, c->st, psi(c), &c->sc()->scale, spec(c), tw(c, 0),
-                             c->at<double>(L.o_px), L.n1, L.n2));
     if (c->p.geom == GP_3D) {
       const int nl = H * L.n2;
       const int lb = c->fp64 ? Launch<double>::lb(L.n1) : Launch<float>::lb(L.n1);
@@ -291,6 +291,46 @@ struct Passes {
                                    tw(c, 1), H));
     }
     return GP_OK;
+  }
+
+  // density of `src` (times scale^2) -> spectrum -> U(k) product -> x-half spectrum
+  static gp_status convolution(gp_ctx* c, const cpx<T>* src, const double* scale) {
+    const Layout& L = c->L;
+    GP_PASS(c, GP_PASS_R2C_X,
+            Launch<T>::r2c_x(L.n0, L.nb_x, c->st, src, scale, spec(c), tw(c, 0),
+                             c->at<double>(L.o_px), L.n1, L.n2));
+    return spectrum_passes(c);
+  }
+  static gp_status convolution(gp_ctx* c) { return convolution(c, psi(c), &c->sc()->scale); }
+
+  // Backpropagation through one real-time step (see gp_step_real_adjoint).
+  static gp_status adjoint(gp_ctx* c, const cpx<T>* psin, cpx<T>* lam, double* gradV,
+                           double* grad_g, double* grad_gdd) {
+    const Layout& L = c->L;
+    const int tcy = tc_of(c->fp64, L.n1);
+    const int nb_y = ((L.n0 + tcy - 1) / tcy) * L.n2;
+    if (c->p.geom == GP_3D) {
+      GP_HIP(Launch<T>::cn_col(L.n2, MODE_ADJ, false, L.nb_col, c->st, lam, cn(c, 2, 4),
+                               cn(c, 2, 5), scalars_for(c, 2).Ar, nullptr, L.n0,
+                               (size_t)L.n0 * L.n1, (size_t)L.n0, nullptr, FinArgs{}, 0));
+    }
+    GP_HIP(Launch<T>::cn_col(L.n1, MODE_ADJ, false, nb_y, c->st, lam, cn(c, 1, 4), cn(c, 1, 5),
+                             scalars_for(c, 1).Ar, nullptr, L.n0, (size_t)L.n0,
+                             (size_t)L.n0 * L.n1, nullptr, FinArgs{}, 0));
+    GP_TRY(convolution(c, psin, &c->sc()->one));
+    const StepScalars sx = scalars_for(c, 0);
+    T* sf = c->at<T>(L.o_sfield);
+    double* pa = c->at<double>(L.o_padj);
+    GP_HIP(Launch<T>::adj_x(L.n0, L.nb_x, c->st, lam, psin, c->at<T>(L.o_V), spec(c), tw(c, 0),
+                            cn(c, 0, 4), cn(c, 0, 5), sx, sf, gradV, pa, L.n1, L.n2));
+    GP_HIP(Launch<T>::r2c_real(L.n0, L.nb_x, c->st, sf, spec(c), tw(c, 0), L.n1, L.n2));
+    GP_TRY(spectrum_passes(c));
+    GP_HIP(Launch<T>::adj_fin(L.n0, L.nb_x, c->st, lam, psin, sf, spec(c), tw(c, 0), sx, L.n1,
+                              L.n2));
+    const double cfac = (c->p.geom == GP_3D) ? 1.0 : 1.0 / (sqrt(2.0 * M_PI) * d_perp(c->p));
+    hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(kThreads), 0, c->st, pa, L.nb_x, cfac,
+                       grad_g, grad_gdd);
+    return dev(hipGetLastError());
   }
 
   // z-difference sums of the stored state (3D), for the kinetic energy; the last block
@@ -373,7 +413,8 @@ struct Passes {
       const double Ar = c->p.dt / (4.0 * hs[a] * hs[a]);
       hipLaunchKernelGGL(k_cn_tables<T>, dim3(1), dim3(64), 0, c->st,
                          c->at<cpx<T>>(L.o_cn[a][0]), c->at<cpx<T>>(L.o_cn[a][1]),
-                         c->at<cpx<T>>(L.o_cn[a][2]), c->at<cpx<T>>(L.o_cn[a][3]), ns[a], Ar);
+                         c->at<cpx<T>>(L.o_cn[a][2]), c->at<cpx<T>>(L.o_cn[a][3]),
+                         c->at<cpx<T>>(L.o_cn[a][4]), c->at<cpx<T>>(L.o_cn[a][5]), ns[a], Ar);
     }
     KernelGeom kg{};
     kg.geom = c->p.geom;
@@ -399,8 +440,8 @@ struct Passes {
     hipLaunchKernelGGL(k_harmonic<T>, dim3(blocks_for(L.npts)), dim3(kThreads), 0, c->st,
                        c->at<T>(L.o_V), L.n0, L.n1, L.n2, L.h0, L.h1, L.h2, w0, w1, w2);
     Scalars* s = c->sc();
-    hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, c->st, &s->scale, &s->ekz, &s->flags,
-                       &s->ring_pos, &s->counter);
+    hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, c->st, &s->scale, &s->one, &s->ekz,
+                       &s->flags, &s->ring_pos, &s->counter);
     return dev(hipGetLastError());
   }
 
@@ -643,6 +684,18 @@ gp_status gp_set_couplings(gp_ctx* c, double g, double gdd) {
 }
 
 gp_status gp_step_imag(gp_ctx* c, int nsteps) { return run_steps(c, nsteps, true); }
+
+gp_status gp_step_real_adjoint(gp_ctx* c, const void* psi_n, void* lam, double* gradV,
+                               double* grad_g, double* grad_gdd) {
+  if (!c || !psi_n || !lam || !gradV || !grad_g || !grad_gdd) return GP_E_ARG;
+  clear_stale_error();
+  if (c->fp64) {
+    return Passes<double>::adjoint(c, reinterpret_cast<const cpx<double>*>(psi_n),
+                                   reinterpret_cast<cpx<double>*>(lam), gradV, grad_g, grad_gdd);
+  }
+  return Passes<float>::adjoint(c, reinterpret_cast<const cpx<float>*>(psi_n),
+                                reinterpret_cast<cpx<float>*>(lam), gradV, grad_g, grad_gdd);
+}
 gp_status gp_step_real(gp_ctx* c, int nsteps) { return run_steps(c, nsteps, false); }
 
 gp_status gp_energy(gp_ctx* c, gp_observables* out) {

@@ -68,6 +68,58 @@ hipError_t Launch<T>::c2r_nl_cnx(int n0, int mode, int blocks, hipStream_t st, c
 #undef CASE_MODE
   return hipGetLastError();
 }
+
+template <>
+hipError_t Launch<T>::r2c_real(int n0, int blocks, hipStream_t st, const T* f, cpx<T>* spec,
+                               const cpx<T>* tw0, int n1, int n2) {
+  switch (n0) {
+#define X(N)                                                                 \
+  case N:                                                                    \
+    GP_LAUNCH((k_r2c_real<T, N>), blocks, st, f, spec, tw0, n1, n2);         \
+    break;
+    GP_FOR_SIZES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <>
+hipError_t Launch<T>::adj_x(int n0, int blocks, hipStream_t st, cpx<T>* lam, const cpx<T>* psin,
+                            const T* V, const cpx<T>* spec, const cpx<T>* tw0,
+                            const cpx<T>* cnm, const cpx<T>* cng, const StepScalars& sc,
+                            T* sfield, double* gradV, double* part, int n1, int n2) {
+  switch (n0) {
+#define X(N)                                                                          \
+  case N:                                                                             \
+    GP_LAUNCH((k_adj_x<T, N>), blocks, st, lam, psin, V, spec, tw0, cnm, cng, sc,    \
+              sfield, gradV, part, n1, n2);                                           \
+    break;
+    GP_FOR_SIZES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <>
+hipError_t Launch<T>::adj_fin(int n0, int blocks, hipStream_t st, cpx<T>* lam,
+                              const cpx<T>* psin, const T* sfield, const cpx<T>* spec,
+                              const cpx<T>* tw0, const StepScalars& sc, int n1, int n2) {
+  switch (n0) {
+#define X(N)                                                                              \
+  case N:                                                                                 \
+    GP_LAUNCH((k_adj_fin<T, N>), blocks, st, lam, psin, sfield, spec, tw0, sc, n1, n2);  \
+    break;
+    GP_FOR_SIZES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
 #endif
 
 #if GP_FAMILY == 1
@@ -137,6 +189,8 @@ hipError_t Launch<T>::cn_col(int n, int mode, bool sums, int blocks, hipStream_t
   case N:                                           \
     if (mode == MODE_OBSERVE) {                     \
       CN(N, MODE_OBSERVE, true);                    \
+    } else if (mode == MODE_ADJ) {                  \
+      CN(N, MODE_ADJ, false);                       \
     } else if (mode == MODE_IMAG) {                 \
       if (sums) CN(N, MODE_IMAG, true);             \
       else CN(N, MODE_IMAG, false);                 \

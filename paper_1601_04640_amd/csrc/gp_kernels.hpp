@@ -47,7 +47,8 @@ struct StepScalars {
   double h0, h1, h2;  // spacings along axes 0, 1, 2
 };
 
-enum : int { MODE_IMAG = 0, MODE_REAL = 1, MODE_OBSERVE = 2, MODE_PHI = 3 };
+// MODE_ADJ: the adjoint sweep of a real-time step (A -> conj(A) = -i Ar).
+enum : int { MODE_IMAG = 0, MODE_REAL = 1, MODE_OBSERVE = 2, MODE_PHI = 3, MODE_ADJ = 4 };
 
 // Global-memory phases are statically unrolled over ITERS = ceil(elements/kThreads)
 // so that every load of a thread is issued before the first one is consumed.
@@ -439,7 +440,7 @@ __global__ __launch_bounds__(kThreads) void k_cn_col(cpx<T>* __restrict__ psi,
   using TL = Tiles<T, N>;
   constexpr int TC = TL::TC, PC = TL::PC, SC = (N + PC - 1) / PC, RS = TC + 1;
   constexpr int NR = N + (N + SC - 1) / SC;  // padded rows
-  constexpr bool SOLVE = (MODE == MODE_IMAG || MODE == MODE_REAL);
+  constexpr bool SOLVE = (MODE == MODE_IMAG || MODE == MODE_REAL || MODE == MODE_ADJ);
   using IT = Iters<N * TC>;
   __shared__ cpx<T> B[NR * RS];
   __shared__ cpx<T> MT[SOLVE ? N : 1], GT[SOLVE ? N : 1];
@@ -469,9 +470,12 @@ __global__ __launch_bounds__(kThreads) void k_cn_col(cpx<T>* __restrict__ psi,
   }
   __syncthreads();
   if constexpr (SOLVE) {
-    const cpx<T> A = (MODE == MODE_IMAG) ? cpx<T>{(T)Ar, 0} : cpx<T>{0, (T)Ar};
+    // A = Ar (imaginary time), i Ar (real time), -i Ar (adjoint); Bc = 1 - 2A
+    const cpx<T> A = (MODE == MODE_IMAG) ? cpx<T>{(T)Ar, 0}
+                     : (MODE == MODE_REAL) ? cpx<T>{0, (T)Ar} : cpx<T>{0, (T)(-Ar)};
     const cpx<T> Bc = (MODE == MODE_IMAG) ? cpx<T>{(T)(1.0 - 2.0 * Ar), 0}
-                                          : cpx<T>{(T)1, (T)(-2.0 * Ar)};
+                      : (MODE == MODE_REAL) ? cpx<T>{(T)1, (T)(-2.0 * Ar)}
+                                            : cpx<T>{(T)1, (T)(2.0 * Ar)};
     cn_solve_lines<T, N, TC, 1, RS, PC>(B, MT, GT, A, Bc);
   }
   double sums[2] = {0.0, 0.0};
@@ -490,6 +494,238 @@ __global__ __launch_bounds__(kThreads) void k_cn_col(cpx<T>* __restrict__ psi,
   if constexpr (SUMS) {
     block_sum<2>(sums, red);
     publish_and_finalize(sums, partials, counter, fa, fin_mode);
+  }
+}
+
+}  // namespace gpdbec
+
+// ========================================================= adjoint (real time)
+// Backpropagation through one real-time step (costate lambda = dL/d conj(psi)):
+//   lambda_a = C_x(-dt) C_y(-dt) C_z(-dt) lambda      (adjoint of each CN factor)
+//   mu = exp(+i dt theta) lambda_a,  theta = V + g_c n + g_dd Phi  (of psi_n)
+//   s  = 2 dt Im(conj(mu) psi_n);   dL/dV += s;  sums s n, s Phi -> dL/dg_c, dL/dg_dd
+//   lambda_n = mu + (g_c s + g_dd K s) psi_n,  K s = F^-1[U F[s]]
+namespace gpdbec {
+
+// Real-to-complex x pass of a real field f (the adjoint's second convolution input).
+// grid: ceil(n1/TJ) * n2 blocks; writes the same kx-plane-major half spectrum.
+template <typename T, int N0>
+__global__ __launch_bounds__(kThreads) void k_r2c_real(const T* __restrict__ f,
+                                                       cpx<T>* __restrict__ spec,
+                                                       const cpx<T>* __restrict__ tw0, int n1,
+                                                       int n2) {
+  using TL = Tiles<T, N0>;
+  constexpr int TJ = TL::TJ, NP = TJ / 2, H = N0 / 2 + 1, LSZ = N0 + 1;
+  using IT = Iters<TJ * N0>;
+  using IH = Iters<H * NP>;
+  __shared__ cpx<T> Z[NP * LSZ];
+  __shared__ cpx<T> W[N0];
+  const int tid = threadIdx.x;
+  const int nt1 = (n1 + TJ - 1) / TJ;
+  const int k2 = blockIdx.x / nt1;
+  const int j0 = (blockIdx.x % nt1) * TJ;
+  const size_t pbase = ((size_t)k2 * n1 + j0) * N0;
+  T fv[IT::N];
+#pragma unroll
+  for (int it = 0; it < IT::N; ++it) {
+    const int u = tid + it * kThreads;
+    fv[it] = (IT::valid(u) && j0 + u / N0 < n1) ? f[pbase + u] : (T)0;
+  }
+  for (int i = tid; i < N0; i += kThreads) W[i] = tw0[i];
+#pragma unroll
+  for (int it = 0; it < IT::N; ++it) {
+    const int u = tid + it * kThreads;
+    if (!IT::valid(u)) continue;
+    const int jl = u / N0, i = u % N0;
+    cpx<T>& zc = Z[(jl >> 1) * LSZ + i];
+    if (jl & 1) zc.im = fv[it];
+    else zc.re = fv[it];
+  }
+  __syncthreads();
+  LdsFFT<T, N0, NP, LSZ, 1, false>::template run<false>(Z, W);
+#pragma unroll
+  for (int it = 0; it < IH::N; ++it) {
+    const int u = tid + it * kThreads;
+    if (!IH::valid(u)) continue;
+    const int p = u % NP, kx = u / NP;
+    const int j = j0 + 2 * p;
+    if (j >= n1) continue;
+    const cpx<T> zk = Z[p * LSZ + kx];
+    const cpx<T> zm = Z[p * LSZ + ((N0 - kx) % N0)];
+    const T hf = (T)0.5;
+    cpx<T>* o = spec + ((size_t)kx * n2 + k2) * n1 + j;
+    o[0] = cpx<T>{hf * (zk.re + zm.re), hf * (zk.im - zm.im)};
+    o[1] = cpx<T>{hf * (zk.im + zm.im), hf * (zm.re - zk.re)};
+  }
+}
+
+// Gathers the Hermitian half spectrum of the tile's line pairs into full complex lines
+// (issued loads first) and runs the inverse x FFT: afterwards line jl of the tile holds
+// the real field in component (jl & 1) of Z[(jl >> 1) * (N0 + 1) + i].
+template <typename T, int N0, int NP>
+__device__ __forceinline__ void c2r_tile(cpx<T>* Z, const cpx<T>* W,
+                                         const cpx<T>* __restrict__ spec, int j0, int k2,
+                                         int n1, int n2, const cpx<T> (&sa)[Iters<(N0 / 2 + 1) * NP>::N],
+                                         const cpx<T> (&sb)[Iters<(N0 / 2 + 1) * NP>::N]) {
+  constexpr int LSZ = N0 + 1, H = N0 / 2 + 1;
+  using IH = Iters<H * NP>;
+#pragma unroll
+  for (int it = 0; it < IH::N; ++it) {
+    const int u = threadIdx.x + it * kThreads;
+    if (!IH::valid(u)) continue;
+    const int p = u % NP, kx = u / NP;
+    const cpx<T> a = sa[it], b = sb[it];
+    cpx<T>* z = Z + p * LSZ;
+    if (kx == 0 || kx == N0 / 2) {
+      z[kx] = cpx<T>{a.re, b.re};
+    } else {
+      z[kx] = cpx<T>{a.re - b.im, a.im + b.re};
+      z[N0 - kx] = cpx<T>{a.re + b.im, b.re - a.im};
+    }
+  }
+  __syncthreads();
+  LdsFFT<T, N0, NP, LSZ, 1, false>::template run<true>(Z, W);
+}
+
+template <typename T, int N0, int NP>
+__device__ __forceinline__ void load_spec_pairs(const cpx<T>* __restrict__ spec, int j0, int k2,
+                                                int n1, int n2,
+                                                cpx<T> (&sa)[Iters<(N0 / 2 + 1) * NP>::N],
+                                                cpx<T> (&sb)[Iters<(N0 / 2 + 1) * NP>::N]) {
+  using IH = Iters<(N0 / 2 + 1) * NP>;
+#pragma unroll
+  for (int it = 0; it < IH::N; ++it) {
+    const int u = threadIdx.x + it * kThreads;
+    const int p = u % NP, kx = u / NP;
+    const int j = j0 + 2 * p;
+    const bool in = IH::valid(u) && j < n1;
+    const cpx<T>* o = spec + ((size_t)kx * n2 + k2) * n1 + j;
+    sa[it] = in ? o[0] : cpx<T>{0, 0};
+    sb[it] = in ? o[1] : cpx<T>{0, 0};
+  }
+}
+
+// Adjoint x pass: lambda_a = C_x(-dt) lambda (conj tables), Phi of psi_n from the
+// spectrum, mu = exp(i dt theta) lambda_a -> lam, s -> sfield, gradV += s (FP64),
+// partials[b*2 + {0,1}] = sum s n, sum s Phi.  grid: ceil(n1/TJ) * n2 blocks.
+template <typename T, int N0>
+__global__ __launch_bounds__(kThreads) void k_adj_x(
+    cpx<T>* __restrict__ lam, const cpx<T>* __restrict__ psin, const T* __restrict__ V,
+    const cpx<T>* __restrict__ spec, const cpx<T>* __restrict__ tw0,
+    const cpx<T>* __restrict__ cnm, const cpx<T>* __restrict__ cng, StepScalars sc,
+    T* __restrict__ sfield, double* __restrict__ gradV, double* __restrict__ partials, int n1,
+    int n2) {
+  using TL = Tiles<T, N0>;
+  constexpr int TJ = TL::TJ, NP = TJ / 2, LSZ = N0 + 1;
+  constexpr int PX = TL::PX, SX = (N0 + PX - 1) / PX, LSP = N0 + (N0 + SX - 1) / SX;
+  using IT = Iters<TJ * N0>;
+  using IH = Iters<(N0 / 2 + 1) * NP>;
+  __shared__ cpx<T> Z[NP * LSZ];
+  __shared__ cpx<T> PS[TJ * LSP];
+  __shared__ cpx<T> W[N0];
+  __shared__ cpx<T> MT[N0], GT[N0];
+  __shared__ double red[2 * kWaves];
+  const int tid = threadIdx.x;
+  const int nt1 = (n1 + TJ - 1) / TJ;
+  const int k2 = blockIdx.x / nt1;
+  const int j0 = (blockIdx.x % nt1) * TJ;
+  const size_t pbase = ((size_t)k2 * n1 + j0) * N0;
+  cpx<T> sa[IH::N], sb[IH::N];
+  load_spec_pairs<T, N0, NP>(spec, j0, k2, n1, n2, sa, sb);
+  cpx<T> lv[IT::N], pv[IT::N];
+  T vv[IT::N];
+#pragma unroll
+  for (int it = 0; it < IT::N; ++it) {
+    const int u = tid + it * kThreads;
+    const bool in = IT::valid(u) && j0 + u / N0 < n1;
+    lv[it] = in ? lam[pbase + u] : cpx<T>{0, 0};
+    pv[it] = in ? psin[pbase + u] : cpx<T>{0, 0};
+    vv[it] = in ? V[pbase + u] : (T)0;
+  }
+  for (int i = tid; i < N0; i += kThreads) {
+    W[i] = tw0[i];
+    MT[i] = cnm[i];
+    GT[i] = cng[i];
+  }
+#pragma unroll
+  for (int it = 0; it < IT::N; ++it) {
+    const int u = tid + it * kThreads;
+    if (IT::valid(u)) PS[(u / N0) * LSP + cpad<SX>(u % N0)] = lv[it];
+  }
+  c2r_tile<T, N0, NP>(Z, W, spec, j0, k2, n1, n2, sa, sb);  // ends with a barrier
+  const cpx<T> A = {0, (T)(-sc.Ar)};
+  const cpx<T> B = {(T)1, (T)(2.0 * sc.Ar)};
+  cn_solve_lines<T, N0, TJ, LSP, 1, PX>(PS, MT, GT, A, B);
+  double sums[2] = {0.0, 0.0};
+  const T dt = (T)sc.dt;
+#pragma unroll
+  for (int it = 0; it < IT::N; ++it) {
+    const int u = tid + it * kThreads;
+    if (!IT::valid(u)) continue;
+    const int jl = u / N0, i = u % N0;
+    if (j0 + jl >= n1) continue;
+    const T phi = (jl & 1) ? Z[(jl >> 1) * LSZ + i].im : Z[(jl >> 1) * LSZ + i].re;
+    const cpx<T> p = pv[it];
+    const T n = p.re * p.re + p.im * p.im;
+    const T th = dt * (vv[it] + (T)sc.gc * n + (T)sc.gdd * phi);
+    const cpx<T> la = PS[jl * LSP + cpad<SX>(i)];
+    const cpx<T> mu = la * cpx<T>{cos(th), sin(th)};
+    const T s = (T)2 * dt * (mu.re * p.im - mu.im * p.re);
+    lam[pbase + u] = mu;
+    sfield[pbase + u] = s;
+    gradV[pbase + u] += (double)s;
+    sums[0] += (double)s * (double)n;
+    sums[1] += (double)s * (double)phi;
+  }
+  block_sum<2>(sums, red);
+  if (tid == 0) {
+    partials[blockIdx.x * 2 + 0] = sums[0];
+    partials[blockIdx.x * 2 + 1] = sums[1];
+  }
+}
+
+// Adjoint closing x pass: K s from the spectrum; lambda = mu + (g_c s + g_dd K s) psi_n.
+template <typename T, int N0>
+__global__ __launch_bounds__(kThreads) void k_adj_fin(cpx<T>* __restrict__ lam,
+                                                      const cpx<T>* __restrict__ psin,
+                                                      const T* __restrict__ sfield,
+                                                      const cpx<T>* __restrict__ spec,
+                                                      const cpx<T>* __restrict__ tw0,
+                                                      StepScalars sc, int n1, int n2) {
+  using TL = Tiles<T, N0>;
+  constexpr int TJ = TL::TJ, NP = TJ / 2, LSZ = N0 + 1;
+  using IT = Iters<TJ * N0>;
+  using IH = Iters<(N0 / 2 + 1) * NP>;
+  __shared__ cpx<T> Z[NP * LSZ];
+  __shared__ cpx<T> W[N0];
+  const int tid = threadIdx.x;
+  const int nt1 = (n1 + TJ - 1) / TJ;
+  const int k2 = blockIdx.x / nt1;
+  const int j0 = (blockIdx.x % nt1) * TJ;
+  const size_t pbase = ((size_t)k2 * n1 + j0) * N0;
+  cpx<T> sa[IH::N], sb[IH::N];
+  load_spec_pairs<T, N0, NP>(spec, j0, k2, n1, n2, sa, sb);
+  cpx<T> mv[IT::N], pv[IT::N];
+  T sv[IT::N];
+#pragma unroll
+  for (int it = 0; it < IT::N; ++it) {
+    const int u = tid + it * kThreads;
+    const bool in = IT::valid(u) && j0 + u / N0 < n1;
+    mv[it] = in ? lam[pbase + u] : cpx<T>{0, 0};
+    pv[it] = in ? psin[pbase + u] : cpx<T>{0, 0};
+    sv[it] = in ? sfield[pbase + u] : (T)0;
+  }
+  for (int i = tid; i < N0; i += kThreads) W[i] = tw0[i];
+  c2r_tile<T, N0, NP>(Z, W, spec, j0, k2, n1, n2, sa, sb);
+#pragma unroll
+  for (int it = 0; it < IT::N; ++it) {
+    const int u = tid + it * kThreads;
+    if (!IT::valid(u)) continue;
+    const int jl = u / N0, i = u % N0;
+    if (j0 + jl >= n1) continue;
+    const T ks = (jl & 1) ? Z[(jl >> 1) * LSZ + i].im : Z[(jl >> 1) * LSZ + i].re;
+    const T w = (T)sc.gc * sv[it] + (T)sc.gdd * ks;
+    lam[pbase + u] = mv[it] + scl(pv[it], w);
   }
 }
 
