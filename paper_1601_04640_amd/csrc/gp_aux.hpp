@@ -198,14 +198,13 @@ __global__ __launch_bounds__(kThreads) void k_adj_reduce(const double* __restric
 }
 
 __global__ void k_reset_state(double* scale, double* one, double* ekz, int* flags,
-                              int* ring_pos, unsigned* counter) {
+                              int* ring_pos) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     *scale = 1.0;
     *one = 1.0;
     *ekz = 0.0;
     *flags = 0;
     *ring_pos = 0;
-    *counter = 0u;
   }
 }
 

@@ -53,7 +53,6 @@ struct Scalars {  // device-side scalars (one 256-byte block)
   double obs_pad;
   int flags;
   int ring_pos;
-  unsigned counter;  // arrival tickets of the fused finalisation
 };
 
 gp_status validate(const gp_params* p) {
@@ -311,18 +310,18 @@ struct Passes {
     const int nb_y = ((L.n0 + tcy - 1) / tcy) * L.n2;
     if (c->p.geom == GP_3D) {
       GP_HIP(Launch<T>::cn_col(L.n2, MODE_ADJ, false, L.nb_col, c->st, lam, cn(c, 2, 4),
-                               cn(c, 2, 5), scalars_for(c, 2).Ar, nullptr, L.n0,
-                               (size_t)L.n0 * L.n1, (size_t)L.n0, nullptr, FinArgs{}, 0));
+                               scalars_for(c, 2).Ar, nullptr, L.n0, (size_t)L.n0 * L.n1,
+                               (size_t)L.n0));
     }
-    GP_HIP(Launch<T>::cn_col(L.n1, MODE_ADJ, false, nb_y, c->st, lam, cn(c, 1, 4), cn(c, 1, 5),
+    GP_HIP(Launch<T>::cn_col(L.n1, MODE_ADJ, false, nb_y, c->st, lam, cn(c, 1, 4),
                              scalars_for(c, 1).Ar, nullptr, L.n0, (size_t)L.n0,
-                             (size_t)L.n0 * L.n1, nullptr, FinArgs{}, 0));
+                             (size_t)L.n0 * L.n1));
     GP_TRY(convolution(c, psin, &c->sc()->one));
     const StepScalars sx = scalars_for(c, 0);
     T* sf = c->at<T>(L.o_sfield);
     double* pa = c->at<double>(L.o_padj);
     GP_HIP(Launch<T>::adj_x(L.n0, L.nb_x, c->st, lam, psin, c->at<T>(L.o_V), spec(c), tw(c, 0),
-                            cn(c, 0, 4), cn(c, 0, 5), sx, sf, gradV, pa, L.n1, L.n2));
+                            cn(c, 0, 4), sx, sf, gradV, pa, L.n1, L.n2));
     GP_HIP(Launch<T>::r2c_real(L.n0, L.nb_x, c->st, sf, spec(c), tw(c, 0), L.n1, L.n2));
     GP_TRY(spectrum_passes(c));
     GP_HIP(Launch<T>::adj_fin(L.n0, L.nb_x, c->st, lam, psin, sf, spec(c), tw(c, 0), sx, L.n1,
@@ -333,49 +332,55 @@ struct Passes {
     return dev(hipGetLastError());
   }
 
-  // z-difference sums of the stored state (3D), for the kinetic energy; the last block
-  // finalises with fin_mode (FIN_EKZ: pending z-kinetic part; FIN_OBSERVE: full record)
+  // FP64 finalisation of the partial sums (fin_mode: FIN_IMAG/REAL after a step,
+  // FIN_OBSERVE for gp_energy, FIN_EKZ for the pending z-kinetic part)
+  static gp_status finalize(gp_ctx* c, int fin_mode) {
+    GP_TRY(pass_begin(c, GP_PASS_FINALIZE));
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, c->st, fin_args(c), fin_mode);
+    GP_HIP(hipGetLastError());
+    return pass_end(c, GP_PASS_FINALIZE);
+  }
+
+  // z-difference sums of the stored state (3D), for the kinetic energy, then finalise
+  // with fin_mode (FIN_EKZ: pending z-kinetic part; FIN_OBSERVE: full record)
   static gp_status z_observe(gp_ctx* c, int fin_mode) {
     const Layout& L = c->L;
-    return dev(Launch<T>::cn_col(L.n2, MODE_OBSERVE, true, L.nb_col, c->st, psi(c), nullptr,
-                                 nullptr, 0.0, c->at<double>(L.o_pcol), L.n0,
-                                 (size_t)L.n0 * L.n1, (size_t)L.n0, &c->sc()->counter,
-                                 fin_args(c), fin_mode));
+    GP_HIP(Launch<T>::cn_col(L.n2, MODE_OBSERVE, true, L.nb_col, c->st, psi(c), nullptr, 0.0,
+                             c->at<double>(L.o_pcol), L.n0, (size_t)L.n0 * L.n1,
+                             (size_t)L.n0));
+    return finalize(c, fin_mode);
   }
 
   static gp_status step(gp_ctx* c, bool imag) {
     const Layout& L = c->L;
     const int mode = imag ? MODE_IMAG : MODE_REAL;
     const int fin = imag ? (int)FIN_IMAG : (int)FIN_REAL;
-    const int k = imag ? 0 : 2;  // table pair: (m, g) imaginary or real time
+    const int k = imag ? 0 : 2;  // factor table: imaginary or real time
     GP_TRY(convolution(c));
     const StepScalars sx = scalars_for(c, 0);
     GP_PASS(c, GP_PASS_C2R_NL_CNX,
             Launch<T>::c2r_nl_cnx(L.n0, mode, L.nb_x, c->st, psi(c), c->at<T>(L.o_V),
-                                  &c->sc()->scale, spec(c), tw(c, 0), cn(c, 0, k),
-                                  cn(c, 0, k + 1), sx, c->at<double>(L.o_pnl), nullptr, L.n1,
-                                  L.n2));
+                                  &c->sc()->scale, spec(c), tw(c, 0), cn(c, 0, k), sx,
+                                  c->at<double>(L.o_pnl), nullptr, L.n1, L.n2));
     const int tcy = tc_of(c->fp64, L.n1);
     const double Ay = scalars_for(c, 1).Ar;
     if (c->p.geom == GP_3D) {
       GP_PASS(c, GP_PASS_CN_Y,
               Launch<T>::cn_col(L.n1, mode, false, ((L.n0 + tcy - 1) / tcy) * L.n2, c->st,
-                                psi(c), cn(c, 1, k), cn(c, 1, k + 1), Ay, nullptr, L.n0,
-                                (size_t)L.n0, (size_t)L.n0 * L.n1, nullptr, FinArgs{}, 0));
+                                psi(c), cn(c, 1, k), Ay, nullptr, L.n0, (size_t)L.n0,
+                                (size_t)L.n0 * L.n1));
       const double Az = scalars_for(c, 2).Ar;
       GP_PASS(c, GP_PASS_CN_Z,
-              Launch<T>::cn_col(L.n2, mode, true, L.nb_col, c->st, psi(c), cn(c, 2, k),
-                                cn(c, 2, k + 1), Az, c->at<double>(L.o_pcol), L.n0,
-                                (size_t)L.n0 * L.n1, (size_t)L.n0, &c->sc()->counter,
-                                fin_args(c), fin));
+              Launch<T>::cn_col(L.n2, mode, true, L.nb_col, c->st, psi(c), cn(c, 2, k), Az,
+                                c->at<double>(L.o_pcol), L.n0, (size_t)L.n0 * L.n1,
+                                (size_t)L.n0));
     } else {
       GP_PASS(c, GP_PASS_CN_Y,
-              Launch<T>::cn_col(L.n1, mode, true, L.nb_col, c->st, psi(c), cn(c, 1, k),
-                                cn(c, 1, k + 1), Ay, c->at<double>(L.o_pcol), L.n0,
-                                (size_t)L.n0, (size_t)L.n0 * L.n1, &c->sc()->counter,
-                                fin_args(c), fin));
+              Launch<T>::cn_col(L.n1, mode, true, L.nb_col, c->st, psi(c), cn(c, 1, k), Ay,
+                                c->at<double>(L.o_pcol), L.n0, (size_t)L.n0,
+                                (size_t)L.n0 * L.n1));
     }
-    return GP_OK;
+    return finalize(c, fin);
   }
 
   static gp_status observe(gp_ctx* c) {
@@ -383,13 +388,10 @@ struct Passes {
     GP_TRY(convolution(c));
     const StepScalars sx = scalars_for(c, 0);
     GP_HIP(Launch<T>::c2r_nl_cnx(L.n0, MODE_OBSERVE, L.nb_x, c->st, psi(c), c->at<T>(L.o_V),
-                                 &c->sc()->scale, spec(c), tw(c, 0), nullptr, nullptr, sx,
+                                 &c->sc()->scale, spec(c), tw(c, 0), nullptr, sx,
                                  c->at<double>(L.o_pnl), nullptr, L.n1, L.n2));
     if (c->p.geom == GP_3D) return z_observe(c, FIN_OBSERVE);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, c->st, fin_args(c),
-                       (int)FIN_OBSERVE);
-    GP_HIP(hipGetLastError());
-    return GP_OK;
+    return finalize(c, FIN_OBSERVE);
   }
 
   static gp_status phi(gp_ctx* c, T* out) {
@@ -397,7 +399,7 @@ struct Passes {
     GP_TRY(convolution(c));
     const StepScalars sx = scalars_for(c, 0);
     GP_HIP(Launch<T>::c2r_nl_cnx(L.n0, MODE_PHI, L.nb_x, c->st, psi(c), c->at<T>(L.o_V),
-                                 &c->sc()->scale, spec(c), tw(c, 0), nullptr, nullptr, sx,
+                                 &c->sc()->scale, spec(c), tw(c, 0), nullptr, sx,
                                  c->at<double>(L.o_pnl), out, L.n1, L.n2));
     return GP_OK;
   }
@@ -441,7 +443,7 @@ struct Passes {
                        c->at<T>(L.o_V), L.n0, L.n1, L.n2, L.h0, L.h1, L.h2, w0, w1, w2);
     Scalars* s = c->sc();
     hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, c->st, &s->scale, &s->one, &s->ekz,
-                       &s->flags, &s->ring_pos, &s->counter);
+                       &s->flags, &s->ring_pos);
     return dev(hipGetLastError());
   }
 

@@ -226,40 +226,57 @@ __device__ __forceinline__ cpx<T> shfl_down_c(cpx<T> v, int off, int width) {
 // precomputed per axis: m_i = 1/(b - a c_{i-1}) and g_i = A m_i (= -c_i), so that
 //     forward   d_i = m_i r_i + g_i d_{i-1}
 //     backward  u_i = d_i + g_i u_{i+1}
-// (m = g = 0 on the two boundary rows makes them u = 0).  Each recurrence is an affine
-// map per chunk, composed across the P lanes of a line by a Hillis-Steele scan of
-// (gain, offset) pairs through wave shuffles, then re-run with the exact carry-in.
-// P divides 64, so one line never spans two waves.  Every thread must call this.
+// (m = 0 on the two boundary rows makes them u = 0).  Each recurrence is an affine map
+// per chunk, composed across the P lanes of a line by a Hillis-Steele scan of (gain,
+// offset) pairs through wave shuffles, then re-run with the exact carry-in.  P divides
+// 64, so one line never spans two waves.  mt holds m_i in LDS at cpad<S>(i) (the same
+// chunk padding as the data, so the P lanes of a line read distinct banks); each lane
+// reads its chunk, its two neighbours and its m_i once into registers.  Every thread
+// must call this; it ends with a block barrier.
 template <typename T, int N, int NL, int LS, int ES, int P>
-__device__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt, const cpx<T>* gt,
-                               cpx<T> A, cpx<T> B) {
+__device__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt, cpx<T> A, cpx<T> B) {
   static_assert(64 % P == 0 && NL * P == kThreads, "lanes per line");
   constexpr int S = (N + P - 1) / P;
   const int tid = threadIdx.x;
   const int l = tid / P, q = tid % P;
   const int lo = q * S;
   cpx<T>* line = buf + l * LS;
-  cpx<T> r[S];
-  // right-hand side of the explicit half
+  cpx<T> r[S], m[S];
+  const cpx<T> zero = {0, 0};
+  // chunk, its left/right neighbours and the chunk's factors, read once (indices are
+  // clamped into the line so every read is unconditional; out-of-line values -> 0)
+  const cpx<T> tl = line[cpad<S>(min(max(lo - 1, 0), N - 1)) * ES];
+  const cpx<T> tr = line[cpad<S>(min(lo + S, N - 1)) * ES];
+  const cpx<T> pl = (lo >= 1 && lo - 1 < N) ? tl : zero;
+  const cpx<T> pr = (lo + S < N) ? tr : zero;
 #pragma unroll
   for (int e = 0; e < S; ++e) {
     const int i = lo + e;
-    r[e] = cpx<T>{0, 0};
-    if (i >= 1 && i <= N - 2) {
-      const cpx<T> pm = line[cpad<S>(i - 1) * ES];
-      const cpx<T> p0 = line[cpad<S>(i) * ES];
-      const cpx<T> pp = line[cpad<S>(i + 1) * ES];
-      r[e] = A * (pm + pp) + B * p0;
+    const int ic = min(i, N - 1);
+    const cpx<T> tv = line[cpad<S>(ic) * ES];
+    const cpx<T> tm = mt[cpad<S>(ic)];
+    r[e] = (i < N) ? tv : zero;
+    m[e] = (i < N) ? tm : zero;
+  }
+  // right-hand side of the explicit half (in place: r[e] becomes rhs_e)
+  {
+    cpx<T> prev = pl;
+#pragma unroll
+    for (int e = 0; e < S; ++e) {
+      const int i = lo + e;
+      const cpx<T> cur = r[e];
+      const cpx<T> next = (e + 1 < S) ? r[e + 1] : pr;
+      r[e] = (i >= 1 && i <= N - 2) ? A * (prev + next) + B * cur : zero;
+      prev = cur;
     }
   }
   // forward recurrence: local affine map (G, D): d_out = G d_in + D
   cpx<T> G = {1, 0}, D = {0, 0};
 #pragma unroll
   for (int e = 0; e < S; ++e) {
-    const int i = lo + e;
-    if (i < N) {
-      const cpx<T> m = mt[i], g = gt[i];
-      D = m * r[e] + g * D;
+    if (lo + e < N) {
+      const cpx<T> g = A * m[e];
+      D = m[e] * r[e] + g * D;
       G = g * G;
     }
   }
@@ -280,9 +297,8 @@ __device__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt, const cpx<T>* gt,
     cpx<T> d = din;
 #pragma unroll
     for (int e = 0; e < S; ++e) {
-      const int i = lo + e;
-      if (i < N) {
-        d = mt[i] * r[e] + gt[i] * d;
+      if (lo + e < N) {
+        d = m[e] * r[e] + (A * m[e]) * d;
         r[e] = d;
       }
     }
@@ -292,9 +308,8 @@ __device__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt, const cpx<T>* gt,
   cpx<T> X = {0, 0};
 #pragma unroll
   for (int e = S - 1; e >= 0; --e) {
-    const int i = lo + e;
-    if (i < N) {
-      const cpx<T> g = gt[i];
+    if (lo + e < N) {
+      const cpx<T> g = A * m[e];
       X = r[e] + g * X;
       G = g * G;
     }
@@ -316,9 +331,8 @@ __device__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt, const cpx<T>* gt,
     cpx<T> x = xin;
 #pragma unroll
     for (int e = S - 1; e >= 0; --e) {
-      const int i = lo + e;
-      if (i < N) {
-        x = r[e] + gt[i] * x;
+      if (lo + e < N) {
+        x = r[e] + (A * m[e]) * x;
         r[e] = x;
       }
     }
@@ -330,6 +344,18 @@ __device__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt, const cpx<T>* gt,
     if (i < N) line[cpad<S>(i) * ES] = r[e];
   }
   __syncthreads();
+}
+
+// Stores the factor table m (N entries) in LDS at the chunk-padded positions used by
+// cn_solve_lines with P lanes per line.
+template <typename T, int N, int P>
+__device__ __forceinline__ void load_cn_table(cpx<T>* mt, const cpx<T>* __restrict__ m) {
+  constexpr int S = (N + P - 1) / P;
+  for (int i = threadIdx.x; i < N; i += kThreads) mt[cpad<S>(i)] = m[i];
+}
+template <int N, int P>
+constexpr int cn_table_len() {
+  return N + (N + (N + P - 1) / P - 1) / ((N + P - 1) / P);
 }
 
 // ------------------------------------------------------------- reductions

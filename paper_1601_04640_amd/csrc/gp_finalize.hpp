@@ -1,9 +1,7 @@
 // FP64 finalisation of one step's partial sums: totals in a fixed order, the
 // observables record of the state the step started from, and the new renormalisation
-// factor.  Runs on one block, either as a kernel of its own or inside the last block of
-// the step's final column pass ("last block done": every block publishes its partials,
-// then takes a ticket from a device counter; the block that draws the last ticket
-// finalises and re-arms the counter).
+// factor.  Runs on one block after the step's last pass (one block per instance in the
+// batched ensemble).
 #pragma once
 #include "gp_device.hpp"
 
@@ -30,12 +28,6 @@ struct FinArgs {
   double* obs;         // FIN_OBSERVE output record
 };
 
-// Partial sums written by other blocks of the running kernel are read with relaxed
-// device-scope atomic loads, which bypass the per-XCD L2.
-__device__ __forceinline__ double coherent_load(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // All threads of one block must call this.
 __device__ inline void finalize_block(const FinArgs& a, int mode) {
   __shared__ double red[11 * kWaves];
@@ -55,8 +47,8 @@ __device__ inline void finalize_block(const FinArgs& a, int mode) {
   }
   if (mode != FIN_OBSERVE || a.geom == 0) {
     for (int b = tid; b < a.nb_col; b += kThreads) {
-      v[9] += coherent_load(a.p_col + 2 * b);
-      v[10] += coherent_load(a.p_col + 2 * b + 1);
+      v[9] += a.p_col[2 * b];
+      v[10] += a.p_col[2 * b + 1];
     }
   }
   block_sum<11>(v, red);
@@ -110,28 +102,6 @@ __device__ inline void finalize_block(const FinArgs& a, int mode) {
   const double sn = (mode == FIN_IMAG) ? 1.0 / sqrt(nout) : 1.0;
   *a.scale = sn;
   if (a.geom == 0) *a.ekz = 0.5 * sn * sn * v[10] / (a.h2 * a.h2) * dV;
-}
-
-// Called by every thread of every block of a column pass after its partial sums are in
-// `sums` (thread 0).  Publishes them; the last block to arrive runs finalize_block.
-__device__ inline void publish_and_finalize(const double (&sums)[2], double* partials,
-                                            unsigned* counter, const FinArgs& fa, int mode) {
-  __shared__ int is_last;
-  if (threadIdx.x == 0) {
-    __hip_atomic_store(partials + blockIdx.x * 2 + 0, sums[0], __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(partials + blockIdx.x * 2 + 1, sums[1], __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-    const unsigned t = atomicAdd(counter, 1u);
-    is_last = (t == gridDim.x - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (is_last) {
-    __threadfence();
-    finalize_block(fa, mode);
-    if (threadIdx.x == 0) atomicExch(counter, 0u);
-  }
 }
 
 }  // namespace gpdbec

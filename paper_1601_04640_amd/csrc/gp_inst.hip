@@ -40,13 +40,12 @@ hipError_t Launch<T>::r2c_x(int n0, int blocks, hipStream_t st, const cpx<T>* ps
 template <>
 hipError_t Launch<T>::c2r_nl_cnx(int n0, int mode, int blocks, hipStream_t st, cpx<T>* psi,
                                  const T* V, const double* scale, const cpx<T>* spec,
-                                 const cpx<T>* tw0, const cpx<T>* cnm, const cpx<T>* cng,
-                                 const StepScalars& sc, double* part, T* phi_out, int n1,
-                                 int n2) {
+                                 const cpx<T>* tw0, const cpx<T>* cnm, const StepScalars& sc,
+                                 double* part, T* phi_out, int n1, int n2) {
 #define CASE_MODE(N, M)                                                                      \
   case M:                                                                                    \
-    GP_LAUNCH((k_c2r_nl_cnx<T, N, M>), blocks, st, psi, V, scale, spec, tw0, cnm, cng, sc,  \
-              part, phi_out, n1, n2);                                                        \
+    GP_LAUNCH((k_c2r_nl_cnx<T, N, M>), blocks, st, psi, V, scale, spec, tw0, cnm, sc, part, \
+              phi_out, n1, n2);                                                              \
     break;
   switch (n0) {
 #define X(N)                               \
@@ -88,13 +87,13 @@ hipError_t Launch<T>::r2c_real(int n0, int blocks, hipStream_t st, const T* f, c
 template <>
 hipError_t Launch<T>::adj_x(int n0, int blocks, hipStream_t st, cpx<T>* lam, const cpx<T>* psin,
                             const T* V, const cpx<T>* spec, const cpx<T>* tw0,
-                            const cpx<T>* cnm, const cpx<T>* cng, const StepScalars& sc,
-                            T* sfield, double* gradV, double* part, int n1, int n2) {
+                            const cpx<T>* cnm, const StepScalars& sc, T* sfield, double* gradV,
+                            double* part, int n1, int n2) {
   switch (n0) {
 #define X(N)                                                                          \
   case N:                                                                             \
-    GP_LAUNCH((k_adj_x<T, N>), blocks, st, lam, psin, V, spec, tw0, cnm, cng, sc,    \
-              sfield, gradV, part, n1, n2);                                           \
+    GP_LAUNCH((k_adj_x<T, N>), blocks, st, lam, psin, V, spec, tw0, cnm, sc, sfield, \
+              gradV, part, n1, n2);                                                   \
     break;
     GP_FOR_SIZES(X)
 #undef X
@@ -178,12 +177,10 @@ hipError_t Launch<T>::conv_col(int n2, int blocks, hipStream_t st, cpx<T>* spec,
 #if GP_FAMILY == 2
 template <>
 hipError_t Launch<T>::cn_col(int n, int mode, bool sums, int blocks, hipStream_t st,
-                             cpx<T>* psi, const cpx<T>* cnm, const cpx<T>* cng, double Ar,
-                             double* part, int n0, size_t estride, size_t ostride,
-                             unsigned* counter, const FinArgs& fa, int fin_mode) {
-#define CN(N, M, S)                                                                        \
-  GP_LAUNCH((k_cn_col<T, N, M, S>), blocks, st, psi, cnm, cng, Ar, part, n0, estride, ostride, \
-            counter, fa, fin_mode)
+                             cpx<T>* psi, const cpx<T>* cnm, double Ar, double* part, int n0,
+                             size_t estride, size_t ostride) {
+#define CN(N, M, S) \
+  GP_LAUNCH((k_cn_col<T, N, M, S>), blocks, st, psi, cnm, Ar, part, n0, estride, ostride)
   switch (n) {
 #define X(N)                                        \
   case N:                                           \

@@ -9,9 +9,9 @@
 // Spectrum of the density (after the x real-to-complex transform) is stored
 // kx-plane-major, spec[(kx*n2 + k2)*n1 + k1], kx = 0..n0/2, so that the y lines are
 // contiguous, the z lines are strided by n1, and one x line of the spectrum is a set
-// of n0/2+1 contiguous runs over k1 (coalesced when a block owns several k1).
+// of n0/2+1 contiguous runs over k1 (coalesced when a tile owns several k1).
 //
-// Pass order of one 3D step (2D: r2c_x, conv_line, c2r_nl_cnx, cn_col(last), finalize):
+// Pass order of one 3D step (2D: r2c_x, conv_line, c2r_nl_cnx, cn_col, finalize):
 //   r2c_x        n = s^2|psi|^2, x-R2C (two real lines packed per complex FFT);
 //                kinetic x/y difference sums of the incoming state
 //   fft_line     y FFT (forward)
@@ -22,19 +22,26 @@
 //   cn_col       CN sweep along y
 //   cn_col       CN sweep along z; norm and z-kinetic sums of the new state
 //   finalize     FP64 totals, observables record, renormalisation factor
+//
+// Every pass is a __device__ body working on one tile (index `bid`) with its LDS carved
+// from a byte pointer, so the same body serves a single-grid kernel (one block per tile)
+// and a persistent multi-instance kernel (blocks looping over tiles of many grids).
+// lds_bytes<T, N, pass>() gives the bytes a body needs.
 #pragma once
 #include "gp_device.hpp"
 #include "gp_finalize.hpp"
 
 namespace gpdbec {
 
-// Lines per block for passes along x, columns per block for strided passes.
+// Lines per tile for passes along x, columns per tile for strided passes.
 template <typename T, int N>
 struct Tiles {
-  // x lines per block (even): 16, or 8 when a line of complex T exceeds 4 KiB (LDS)
-  static constexpr int TJ = (N * 2 * (int)sizeof(T) > 4096) ? 8 : 16;
+  // x lines per tile (even): 16, or 8 (32 lanes per line, half the register chunk of
+  // the CN solve) when a line of complex T reaches 4 KiB
+  static constexpr int TJ = (N * 2 * (int)sizeof(T) >= 4096) ? 8 : 16;
   static constexpr int PX = kThreads / TJ;          // lanes per x line in the CN solve
-  static constexpr int TC = (sizeof(T) == 8 && N > 256) ? 8 : 16;  // columns per block
+  // columns per tile: 16, or 8 when the 16-lane chunk would exceed the register budget
+  static constexpr int TC = ((N + 15) / 16 > (sizeof(T) == 8 ? 16 : 24)) ? 8 : 16;
   static constexpr int PC = kThreads / TC;
   static constexpr int LB = (2048 / N) < 1 ? 1 : (2048 / N);        // contiguous lines
 };
@@ -50,6 +57,21 @@ struct StepScalars {
 // MODE_ADJ: the adjoint sweep of a real-time step (A -> conj(A) = -i Ar).
 enum : int { MODE_IMAG = 0, MODE_REAL = 1, MODE_OBSERVE = 2, MODE_PHI = 3, MODE_ADJ = 4 };
 
+// Coefficients of one CN sweep: A and B = 1 - 2A.
+template <typename T, int MODE>
+__device__ __forceinline__ void cn_coeffs(double Ar, cpx<T>& A, cpx<T>& B) {
+  if constexpr (MODE == MODE_IMAG) {
+    A = cpx<T>{(T)Ar, 0};
+    B = cpx<T>{(T)(1.0 - 2.0 * Ar), 0};
+  } else if constexpr (MODE == MODE_REAL) {
+    A = cpx<T>{0, (T)Ar};
+    B = cpx<T>{(T)1, (T)(-2.0 * Ar)};
+  } else {
+    A = cpx<T>{0, (T)(-Ar)};
+    B = cpx<T>{(T)1, (T)(2.0 * Ar)};
+  }
+}
+
 // Global-memory phases are statically unrolled over ITERS = ceil(elements/kThreads)
 // so that every load of a thread is issued before the first one is consumed.
 template <int TOTAL>
@@ -58,25 +80,81 @@ struct Iters {
   __device__ static __forceinline__ bool valid(int u) { return TOTAL % kThreads == 0 || u < TOTAL; }
 };
 
-// ---------------------------------------------------------------- pass: r2c_x
-// grid: ceil(n1/TJ) * n2 blocks.  partials[b*2 + {0,1}] = sum |dx psi|^2, sum |dy psi|^2
-// of the stored psi (unscaled), the y difference reaching one line past the tile.
+// ------------------------------------------------------------------ LDS carving
+constexpr size_t a16(size_t b) { return (b + 15) & ~(size_t)15; }
+struct Carve {
+  char* p;
+  template <typename X>
+  __device__ __forceinline__ X* take(size_t n) {
+    X* r = reinterpret_cast<X*>(p);
+    p += a16(n * sizeof(X));
+    return r;
+  }
+};
+
+// Geometry of an x-line tile (TJ lines of N0 points; NP packed complex pairs).
 template <typename T, int N0>
-__global__ __launch_bounds__(kThreads) void k_r2c_x(const cpx<T>* __restrict__ psi,
-                                                    const double* __restrict__ scale,
-                                                    cpx<T>* __restrict__ spec,
-                                                    const cpx<T>* __restrict__ tw0,
-                                                    double* __restrict__ partials, int n1, int n2) {
-  using TL = Tiles<T, N0>;
-  constexpr int TJ = TL::TJ, NP = TJ / 2, H = N0 / 2 + 1, LSZ = N0 + 1;
+struct XT {
+  static constexpr int TJ = Tiles<T, N0>::TJ, NP = TJ / 2, H = N0 / 2 + 1, LSZ = N0 + 1;
+  static constexpr int PX = Tiles<T, N0>::PX, SX = (N0 + PX - 1) / PX;
+  static constexpr int LSP = N0 + (N0 + SX - 1) / SX;  // chunk-padded line for CN
+  static constexpr size_t C = sizeof(cpx<T>);
+  static constexpr size_t Z = a16(NP * LSZ * C), W = a16(N0 * C), PS = a16(TJ * LSP * C),
+                          MT = a16(cn_table_len<N0, PX>() * C),
+                          RED = a16(8 * kWaves * sizeof(double));
+};
+
+// Geometry of a strided-column CN tile (TC columns of N points).
+template <typename T, int N>
+struct CT {
+  static constexpr int TC = Tiles<T, N>::TC, PC = Tiles<T, N>::PC, SC = (N + PC - 1) / PC;
+  static constexpr int RS = TC + 1, NR = N + (N + SC - 1) / SC;  // padded rows
+  static constexpr size_t C = sizeof(cpx<T>);
+  static constexpr size_t B = a16(NR * RS * C), MT = a16(cn_table_len<N, PC>() * C),
+                          RED = a16(8 * kWaves * sizeof(double));
+};
+
+// -------------------------------------------------------------------- LDS sizes
+enum : int { P_R2C = 0, P_R2C_REAL, P_FFT_LINE, P_CONV_LINE, P_CONV_COL, P_C2R_STEP, P_C2R_OBS,
+             P_CN_COL, P_ADJ_X, P_ADJ_FIN };
+template <typename T, int N, int PASS>
+constexpr size_t lds_bytes() {
+  using X = XT<T, N>;
+  constexpr size_t C = sizeof(cpx<T>);
+  constexpr int LB = Tiles<T, N>::LB, TC = Tiles<T, N>::TC;
+  if (PASS == P_R2C) return X::Z + X::W + X::RED;
+  if (PASS == P_R2C_REAL) return X::Z + X::W;
+  if (PASS == P_FFT_LINE || PASS == P_CONV_LINE) return a16(LB * (N + 1) * C) + a16(N * C);
+  if (PASS == P_CONV_COL) return a16(N * (TC + 1) * C) + a16(N * C);
+  if (PASS == P_C2R_STEP || PASS == P_ADJ_X) return X::Z + X::PS + X::W + X::MT + X::RED;
+  if (PASS == P_C2R_OBS) return X::Z + X::W + X::RED;
+  if (PASS == P_CN_COL) return CT<T, N>::B + CT<T, N>::MT + CT<T, N>::RED;
+  if (PASS == P_ADJ_FIN) return X::Z + X::W;
+  return 0;
+}
+
+// ================================================================ pass bodies
+// ---------------------------------------------------------------- r2c_x
+// tiles: ceil(n1/TJ) * n2.  partials[bid*2 + {0,1}] = sum |dx psi|^2, sum |dy psi|^2 of
+// the stored psi (unscaled), the y difference reaching one line past the tile.
+template <typename T, int N0>
+__device__ __forceinline__ void r2c_x_body(const cpx<T>* __restrict__ psi,
+                                           const double* __restrict__ scale,
+                                           cpx<T>* __restrict__ spec,
+                                           const cpx<T>* __restrict__ tw0,
+                                           double* __restrict__ partials, int n1, int n2, int bid,
+                                           char* lds) {
+  using X = XT<T, N0>;
+  constexpr int TJ = X::TJ, NP = X::NP, H = X::H, LSZ = X::LSZ;
   using IT = Iters<TJ * N0>;
-  __shared__ cpx<T> Z[NP * LSZ];
-  __shared__ cpx<T> W[N0];
-  __shared__ double red[2 * kWaves];
+  Carve cv{lds};
+  cpx<T>* Z = cv.take<cpx<T>>(NP * LSZ);
+  cpx<T>* W = cv.take<cpx<T>>(N0);
+  double* red = cv.take<double>(8 * kWaves);
   const int tid = threadIdx.x;
   const int nt1 = (n1 + TJ - 1) / TJ;
-  const int k2 = blockIdx.x / nt1;
-  const int j0 = (blockIdx.x % nt1) * TJ;
+  const int k2 = bid / nt1;
+  const int j0 = (bid % nt1) * TJ;
   const cpx<T>* plane = psi + (size_t)k2 * n1 * N0;
   // all loads first: the point, its x neighbour and its y neighbour (mostly cache hits)
   cpx<T> a[IT::N], bx[IT::N], by[IT::N];
@@ -127,16 +205,65 @@ __global__ __launch_bounds__(kThreads) void k_r2c_x(const cpx<T>* __restrict__ p
     const cpx<T> zk = Z[p * LSZ + kx];
     const cpx<T> zm = Z[p * LSZ + ((N0 - kx) % N0)];
     const T hf = (T)0.5;
-    const cpx<T> ra = {hf * (zk.re + zm.re), hf * (zk.im - zm.im)};
-    const cpx<T> rb = {hf * (zk.im + zm.im), hf * (zm.re - zk.re)};
     cpx<T>* o = spec + ((size_t)kx * n2 + k2) * n1 + j;
-    o[0] = ra;
-    o[1] = rb;  // n1 is even, so line j+1 exists whenever line j does
+    o[0] = cpx<T>{hf * (zk.re + zm.re), hf * (zk.im - zm.im)};
+    o[1] = cpx<T>{hf * (zk.im + zm.im), hf * (zm.re - zk.re)};  // n1 even: line j+1 exists
   }
   block_sum<2>(sums, red);
   if (tid == 0) {
-    partials[blockIdx.x * 2 + 0] = sums[0];
-    partials[blockIdx.x * 2 + 1] = sums[1];
+    partials[bid * 2 + 0] = sums[0];
+    partials[bid * 2 + 1] = sums[1];
+  }
+}
+
+// Real-to-complex x pass of a real field f (the adjoint's second convolution input).
+template <typename T, int N0>
+__device__ __forceinline__ void r2c_real_body(const T* __restrict__ f, cpx<T>* __restrict__ spec,
+                                              const cpx<T>* __restrict__ tw0, int n1, int n2,
+                                              int bid, char* lds) {
+  using X = XT<T, N0>;
+  constexpr int TJ = X::TJ, NP = X::NP, H = X::H, LSZ = X::LSZ;
+  using IT = Iters<TJ * N0>;
+  using IH = Iters<H * NP>;
+  Carve cv{lds};
+  cpx<T>* Z = cv.take<cpx<T>>(NP * LSZ);
+  cpx<T>* W = cv.take<cpx<T>>(N0);
+  const int tid = threadIdx.x;
+  const int nt1 = (n1 + TJ - 1) / TJ;
+  const int k2 = bid / nt1;
+  const int j0 = (bid % nt1) * TJ;
+  const size_t pbase = ((size_t)k2 * n1 + j0) * N0;
+  T fv[IT::N];
+#pragma unroll
+  for (int it = 0; it < IT::N; ++it) {
+    const int u = tid + it * kThreads;
+    fv[it] = (IT::valid(u) && j0 + u / N0 < n1) ? f[pbase + u] : (T)0;
+  }
+  for (int i = tid; i < N0; i += kThreads) W[i] = tw0[i];
+#pragma unroll
+  for (int it = 0; it < IT::N; ++it) {
+    const int u = tid + it * kThreads;
+    if (!IT::valid(u)) continue;
+    const int jl = u / N0, i = u % N0;
+    cpx<T>& zc = Z[(jl >> 1) * LSZ + i];
+    if (jl & 1) zc.im = fv[it];
+    else zc.re = fv[it];
+  }
+  __syncthreads();
+  LdsFFT<T, N0, NP, LSZ, 1, false>::template run<false>(Z, W);
+#pragma unroll
+  for (int it = 0; it < IH::N; ++it) {
+    const int u = tid + it * kThreads;
+    if (!IH::valid(u)) continue;
+    const int p = u % NP, kx = u / NP;
+    const int j = j0 + 2 * p;
+    if (j >= n1) continue;
+    const cpx<T> zk = Z[p * LSZ + kx];
+    const cpx<T> zm = Z[p * LSZ + ((N0 - kx) % N0)];
+    const T hf = (T)0.5;
+    cpx<T>* o = spec + ((size_t)kx * n2 + k2) * n1 + j;
+    o[0] = cpx<T>{hf * (zk.re + zm.re), hf * (zk.im - zm.im)};
+    o[1] = cpx<T>{hf * (zk.im + zm.im), hf * (zm.re - zk.re)};
   }
 }
 
@@ -171,15 +298,17 @@ __device__ __forceinline__ void store_lines(const cpx<T>* B, cpx<T>* __restrict_
   }
 }
 
-// -------------------------------------------------------------- pass: fft_line
-// FFT of contiguous lines of length N (count nlines), LB lines per block.
+// ------------------------------------------------------------------ fft_line
+// FFT of contiguous lines of length N (count nlines), LB lines per tile.
 template <typename T, int N, bool INV>
-__global__ __launch_bounds__(kThreads) void k_fft_line(cpx<T>* __restrict__ data,
-                                                       const cpx<T>* __restrict__ tw, int nlines) {
+__device__ __forceinline__ void fft_line_body(cpx<T>* __restrict__ data,
+                                              const cpx<T>* __restrict__ tw, int nlines, int bid,
+                                              char* lds) {
   constexpr int LB = Tiles<T, N>::LB, LSZ = N + 1;
-  __shared__ cpx<T> B[LB * LSZ];
-  __shared__ cpx<T> W[N];
-  const int l0 = blockIdx.x * LB;
+  Carve cv{lds};
+  cpx<T>* B = cv.take<cpx<T>>(LB * LSZ);
+  cpx<T>* W = cv.take<cpx<T>>(N);
+  const int l0 = bid * LB;
   load_lines<T, N, LB>(B, data, l0, nlines);
   for (int i = threadIdx.x; i < N; i += kThreads) W[i] = tw[i];
   __syncthreads();
@@ -189,15 +318,17 @@ __global__ __launch_bounds__(kThreads) void k_fft_line(cpx<T>* __restrict__ data
 
 // FFT -> multiply by the kernel table -> inverse FFT of contiguous lines (2D: y lines).
 template <typename T, int N>
-__global__ __launch_bounds__(kThreads) void k_conv_line(cpx<T>* __restrict__ data,
-                                                        const T* __restrict__ ktab,
-                                                        const cpx<T>* __restrict__ tw, int nlines) {
+__device__ __forceinline__ void conv_line_body(cpx<T>* __restrict__ data,
+                                               const T* __restrict__ ktab,
+                                               const cpx<T>* __restrict__ tw, int nlines, int bid,
+                                               char* lds) {
   constexpr int LB = Tiles<T, N>::LB, LSZ = N + 1;
   using IT = Iters<LB * N>;
-  __shared__ cpx<T> B[LB * LSZ];
-  __shared__ cpx<T> W[N];
+  Carve cv{lds};
+  cpx<T>* B = cv.take<cpx<T>>(LB * LSZ);
+  cpx<T>* W = cv.take<cpx<T>>(N);
   const int tid = threadIdx.x;
-  const int l0 = blockIdx.x * LB;
+  const int l0 = bid * LB;
   load_lines<T, N, LB>(B, data, l0, nlines);
   T kv[IT::N];  // kernel values: loaded now, used after the forward FFT
 #pragma unroll
@@ -222,21 +353,23 @@ __global__ __launch_bounds__(kThreads) void k_conv_line(cpx<T>* __restrict__ dat
   store_lines<T, N, LB>(B, data, l0, nlines);
 }
 
-// --------------------------------------------------------------- pass: conv_col
-// 3D z pass on the spectrum: lines along k2 (stride n1) inside each kx plane; a block
-// owns TC consecutive k1 of one kx plane.  grid: ceil(n1/TC) * H blocks.
+// ------------------------------------------------------------------ conv_col
+// 3D z pass on the spectrum: lines along k2 (stride n1) inside each kx plane; a tile is
+// TC consecutive k1 of one kx plane.  tiles: ceil(n1/TC) * H.
 template <typename T, int N2>
-__global__ __launch_bounds__(kThreads) void k_conv_col(cpx<T>* __restrict__ spec,
-                                                       const T* __restrict__ ktab,
-                                                       const cpx<T>* __restrict__ tw2, int n1) {
+__device__ __forceinline__ void conv_col_body(cpx<T>* __restrict__ spec,
+                                              const T* __restrict__ ktab,
+                                              const cpx<T>* __restrict__ tw2, int n1, int bid,
+                                              char* lds) {
   constexpr int TC = Tiles<T, N2>::TC, RS = TC + 1;
   using IT = Iters<N2 * TC>;
-  __shared__ cpx<T> B[N2 * RS];
-  __shared__ cpx<T> W[N2];
+  Carve cv{lds};
+  cpx<T>* B = cv.take<cpx<T>>(N2 * RS);
+  cpx<T>* W = cv.take<cpx<T>>(N2);
   const int tid = threadIdx.x;
   const int nt = (n1 + TC - 1) / TC;
-  const int kx = blockIdx.x / nt;
-  const int c0 = (blockIdx.x % nt) * TC;
+  const int kx = bid / nt;
+  const int c0 = (bid % nt) * TC;
   const size_t plane = (size_t)kx * N2 * n1;
   cpx<T> v[IT::N];
   T kv[IT::N];
@@ -275,39 +408,16 @@ __global__ __launch_bounds__(kThreads) void k_conv_col(cpx<T>* __restrict__ spec
   }
 }
 
-// ------------------------------------------------------------ pass: c2r_nl_cnx
-// grid: ceil(n1/TJ) * n2 blocks.  MODE_IMAG / MODE_REAL: full step pass (writes psi).
-// MODE_OBSERVE: sums only.  MODE_PHI: writes Phi (without g_dd) to phi_out.
-// partials[b*7 + ...] = sum n, sum V n, sum n^2, sum Phi n, sum x^2 n, sum y^2 n, sum z^2 n
-// of the incoming (scaled) state; axis coordinates (idx - n/2) h.
-template <typename T, int N0, int MODE>
-__global__ __launch_bounds__(kThreads) void k_c2r_nl_cnx(
-    cpx<T>* __restrict__ psi, const T* __restrict__ V, const double* __restrict__ scale,
-    const cpx<T>* __restrict__ spec, const cpx<T>* __restrict__ tw0,
-    const cpx<T>* __restrict__ cnm, const cpx<T>* __restrict__ cng, StepScalars sc,
-    double* __restrict__ partials, T* __restrict__ phi_out, int n1, int n2) {
-  using TL = Tiles<T, N0>;
-  constexpr int TJ = TL::TJ, NP = TJ / 2, H = N0 / 2 + 1, LSZ = N0 + 1;
-  constexpr int PX = TL::PX, SX = (N0 + PX - 1) / PX, LSP = N0 + (N0 + SX - 1) / SX;
-  constexpr bool STEP = (MODE == MODE_IMAG || MODE == MODE_REAL);
-  constexpr bool NEEDPSI = (MODE != MODE_PHI);
-  using IT = Iters<TJ * N0>;
-  using IH = Iters<H * NP>;
-  __shared__ cpx<T> Z[NP * LSZ];
-  __shared__ cpx<T> PS[STEP ? TJ * LSP : 1];
-  __shared__ cpx<T> W[N0];
-  __shared__ cpx<T> MT[STEP ? N0 : 1], GT[STEP ? N0 : 1];
-  __shared__ double red[7 * kWaves];
-  const int tid = threadIdx.x;
-  const int nt1 = (n1 + TJ - 1) / TJ;
-  const int k2 = blockIdx.x / nt1;
-  const int j0 = (blockIdx.x % nt1) * TJ;
-  const size_t pbase = ((size_t)k2 * n1 + j0) * N0;  // first point of the tile
-  // issue every global load of the block up front: spectrum pairs, psi and V tiles
-  cpx<T> sa[IH::N], sb[IH::N];
+// ------------------------------------------------- spectrum of a line pair tile
+template <typename T, int N0, int NP>
+__device__ __forceinline__ void load_spec_pairs(const cpx<T>* __restrict__ spec, int j0, int k2,
+                                                int n1, int n2,
+                                                cpx<T> (&sa)[Iters<(N0 / 2 + 1) * NP>::N],
+                                                cpx<T> (&sb)[Iters<(N0 / 2 + 1) * NP>::N]) {
+  using IH = Iters<(N0 / 2 + 1) * NP>;
 #pragma unroll
   for (int it = 0; it < IH::N; ++it) {
-    const int u = tid + it * kThreads;
+    const int u = threadIdx.x + it * kThreads;
     const int p = u % NP, kx = u / NP;
     const int j = j0 + 2 * p;
     const bool in = IH::valid(u) && j < n1;
@@ -315,28 +425,20 @@ __global__ __launch_bounds__(kThreads) void k_c2r_nl_cnx(
     sa[it] = in ? o[0] : cpx<T>{0, 0};
     sb[it] = in ? o[1] : cpx<T>{0, 0};
   }
-  cpx<T> pv[NEEDPSI ? IT::N : 1];
-  T vv[NEEDPSI ? IT::N : 1];
-  if constexpr (NEEDPSI) {
-#pragma unroll
-    for (int it = 0; it < IT::N; ++it) {
-      const int u = tid + it * kThreads;
-      const bool in = IT::valid(u) && j0 + u / N0 < n1;
-      pv[it] = in ? psi[pbase + u] : cpx<T>{0, 0};
-      vv[it] = in ? V[pbase + u] : (T)0;
-    }
-  }
-  for (int i = tid; i < N0; i += kThreads) {
-    W[i] = tw0[i];
-    if constexpr (STEP) {
-      MT[i] = cnm[i];
-      GT[i] = cng[i];
-    }
-  }
-  // the Hermitian half spectrum of each line pair -> a full complex line
+}
+
+// Hermitian half spectra of the tile's line pairs -> full complex lines -> inverse x
+// FFT: line jl of the tile then holds its real field in component (jl & 1) of
+// Z[(jl >> 1) * (N0 + 1) + i].  Every thread must call this (block barriers inside).
+template <typename T, int N0, int NP>
+__device__ __forceinline__ void c2r_tile(cpx<T>* Z, const cpx<T>* W,
+                                         const cpx<T> (&sa)[Iters<(N0 / 2 + 1) * NP>::N],
+                                         const cpx<T> (&sb)[Iters<(N0 / 2 + 1) * NP>::N]) {
+  constexpr int LSZ = N0 + 1, H = N0 / 2 + 1;
+  using IH = Iters<H * NP>;
 #pragma unroll
   for (int it = 0; it < IH::N; ++it) {
-    const int u = tid + it * kThreads;
+    const int u = threadIdx.x + it * kThreads;
     if (!IH::valid(u)) continue;
     const int p = u % NP, kx = u / NP;
     const cpx<T> a = sa[it], b = sb[it];
@@ -350,16 +452,67 @@ __global__ __launch_bounds__(kThreads) void k_c2r_nl_cnx(
   }
   __syncthreads();
   LdsFFT<T, N0, NP, LSZ, 1, false>::template run<true>(Z, W);
+}
+
+template <typename T>
+__device__ __forceinline__ T tile_real(const cpx<T>* Z, int LSZ, int jl, int i) {
+  const cpx<T> z = Z[(jl >> 1) * LSZ + i];
+  return (jl & 1) ? z.im : z.re;
+}
+
+// ------------------------------------------------------------------ c2r_nl_cnx
+// tiles: ceil(n1/TJ) * n2.  MODE_IMAG / MODE_REAL: full step pass (writes psi).
+// MODE_OBSERVE: sums only.  MODE_PHI: writes Phi (without g_dd) to phi_out.
+// partials[bid*7 + ...] = sum n, sum V n, sum n^2, sum Phi n, sum x^2 n, sum y^2 n,
+// sum z^2 n of the incoming (scaled) state; axis coordinates (idx - n/2) h.
+template <typename T, int N0, int MODE>
+__device__ __forceinline__ void c2r_nl_cnx_body(
+    cpx<T>* __restrict__ psi, const T* __restrict__ V, const double* __restrict__ scale,
+    const cpx<T>* __restrict__ spec, const cpx<T>* __restrict__ tw0,
+    const cpx<T>* __restrict__ cnm, const StepScalars& sc, double* __restrict__ partials,
+    T* __restrict__ phi_out, int n1, int n2, int bid, char* lds) {
+  using X = XT<T, N0>;
+  constexpr int TJ = X::TJ, NP = X::NP, LSZ = X::LSZ, PX = X::PX, SX = X::SX, LSP = X::LSP;
+  constexpr bool STEP = (MODE == MODE_IMAG || MODE == MODE_REAL);
+  constexpr bool NEEDPSI = (MODE != MODE_PHI);
+  using IT = Iters<TJ * N0>;
+  using IH = Iters<(N0 / 2 + 1) * NP>;
+  Carve cv{lds};
+  cpx<T>* Z = cv.take<cpx<T>>(NP * LSZ);
+  cpx<T>* PS = STEP ? cv.take<cpx<T>>(TJ * LSP) : nullptr;
+  cpx<T>* W = cv.take<cpx<T>>(N0);
+  cpx<T>* MT = STEP ? cv.take<cpx<T>>(cn_table_len<N0, PX>()) : nullptr;
+  double* red = cv.take<double>(8 * kWaves);
+  const int tid = threadIdx.x;
+  const int nt1 = (n1 + TJ - 1) / TJ;
+  const int k2 = bid / nt1;
+  const int j0 = (bid % nt1) * TJ;
+  const size_t pbase = ((size_t)k2 * n1 + j0) * N0;  // first point of the tile
+  // issue every global load of the tile up front: spectrum pairs, psi and V
+  cpx<T> sa[IH::N], sb[IH::N];
+  load_spec_pairs<T, N0, NP>(spec, j0, k2, n1, n2, sa, sb);
+  cpx<T> pv[NEEDPSI ? IT::N : 1];
+  T vv[NEEDPSI ? IT::N : 1];
+  if constexpr (NEEDPSI) {
+#pragma unroll
+    for (int it = 0; it < IT::N; ++it) {
+      const int u = tid + it * kThreads;
+      const bool in = IT::valid(u) && j0 + u / N0 < n1;
+      pv[it] = in ? psi[pbase + u] : cpx<T>{0, 0};
+      vv[it] = in ? V[pbase + u] : (T)0;
+    }
+  }
+  for (int i = tid; i < N0; i += kThreads) W[i] = tw0[i];
+  if constexpr (STEP) load_cn_table<T, N0, PX>(MT, cnm);
+  c2r_tile<T, N0, NP>(Z, W, sa, sb);
 
   if constexpr (MODE == MODE_PHI) {
 #pragma unroll
     for (int it = 0; it < IT::N; ++it) {
       const int u = tid + it * kThreads;
       const int jl = u / N0, i = u % N0;
-      if (IT::valid(u) && j0 + jl < n1)
-        phi_out[pbase + u] = reinterpret_cast<const T*>(&Z[(jl >> 1) * LSZ + i])[jl & 1];
+      if (IT::valid(u) && j0 + jl < n1) phi_out[pbase + u] = tile_real(Z, LSZ, jl, i);
     }
-    return;
   } else {
     double sums[7] = {0, 0, 0, 0, 0, 0, 0};
     const T ts = (T)(*scale);
@@ -375,7 +528,7 @@ __global__ __launch_bounds__(kThreads) void k_c2r_nl_cnx(
         if constexpr (STEP) PS[jl * LSP + cpad<SX>(i)] = cpx<T>{0, 0};
         continue;
       }
-      const T phi = reinterpret_cast<const T*>(&Z[(jl >> 1) * LSZ + i])[jl & 1];
+      const T phi = tile_real(Z, LSZ, jl, i);
       const cpx<T> p = scl(pv[it], ts);
       const T v = vv[it];
       const double nd = abs2_d(p);
@@ -402,14 +555,13 @@ __global__ __launch_bounds__(kThreads) void k_c2r_nl_cnx(
     block_sum<7>(sums, red);
     if (tid == 0) {
 #pragma unroll
-      for (int k = 0; k < 7; ++k) partials[blockIdx.x * 7 + k] = sums[k];
+      for (int k = 0; k < 7; ++k) partials[bid * 7 + k] = sums[k];
     }
     if constexpr (STEP) {
       __syncthreads();
-      const cpx<T> A = (MODE == MODE_IMAG) ? cpx<T>{(T)sc.Ar, 0} : cpx<T>{0, (T)sc.Ar};
-      const cpx<T> B = (MODE == MODE_IMAG) ? cpx<T>{(T)(1.0 - 2.0 * sc.Ar), 0}
-                                           : cpx<T>{(T)1, (T)(-2.0 * sc.Ar)};
-      cn_solve_lines<T, N0, TJ, LSP, 1, PX>(PS, MT, GT, A, B);
+      cpx<T> A, B;
+      cn_coeffs<T, MODE>(sc.Ar, A, B);
+      cn_solve_lines<T, N0, TJ, LSP, 1, PX>(PS, MT, A, B);
 #pragma unroll
       for (int it = 0; it < IT::N; ++it) {
         const int u = tid + it * kThreads;
@@ -420,35 +572,31 @@ __global__ __launch_bounds__(kThreads) void k_c2r_nl_cnx(
   }
 }
 
-// ----------------------------------------------------------------- pass: cn_col
-// CN sweep along a strided axis: lines of length N with element stride `estride`;
-// a block owns TC consecutive x columns (x0..x0+TC-1) of one "outer" index.
-//   y sweep (3D/2D): estride = n0, outer = k2 (n_outer = n2), base = k2*n1*n0
-//   z sweep (3D):    estride = n0*n1, outer = k1 (n_outer = n1), base = k1*n0
-// SUMS: also partials[b*2+{0,1}] = sum |u|^2, sum |u_{i+1}-u_i|^2 along the line of the
-// result (MODE_OBSERVE: of the stored input, nothing written; sums unscaled), and the
-// last block to finish runs the step's FP64 finalisation (fin_mode, FinArgs).
-// grid: ceil(n0/TC) * n_outer blocks.
+// --------------------------------------------------------------------- cn_col
+// CN sweep along a strided axis: lines of length N with element stride `estride`; a
+// tile is TC consecutive x columns (x0..x0+TC-1) of one "outer" index.
+//   y sweep (3D/2D): estride = n0, outer = k2 (n_outer = n2), ostride = n1*n0
+//   z sweep (3D):    estride = n0*n1, outer = k1 (n_outer = n1), ostride = n0
+// SUMS: also partials[bid*2+{0,1}] = sum |u|^2, sum |u_{i+1}-u_i|^2 along the line of
+// the result (MODE_OBSERVE: of the stored input, nothing written; sums unscaled).
+// tiles: ceil(n0/TC) * n_outer.
 template <typename T, int N, int MODE, bool SUMS>
-__global__ __launch_bounds__(kThreads) void k_cn_col(cpx<T>* __restrict__ psi,
-                                                     const cpx<T>* __restrict__ cnm,
-                                                     const cpx<T>* __restrict__ cng,
-                                                     double Ar, double* __restrict__ partials,
-                                                     int n0, size_t estride, size_t ostride,
-                                                     unsigned* counter, FinArgs fa,
-                                                     int fin_mode) {
-  using TL = Tiles<T, N>;
-  constexpr int TC = TL::TC, PC = TL::PC, SC = (N + PC - 1) / PC, RS = TC + 1;
-  constexpr int NR = N + (N + SC - 1) / SC;  // padded rows
+__device__ __forceinline__ void cn_col_body(cpx<T>* __restrict__ psi,
+                                            const cpx<T>* __restrict__ cnm, double Ar,
+                                            double* __restrict__ partials, int n0,
+                                            size_t estride, size_t ostride, int bid, char* lds) {
+  using G = CT<T, N>;
+  constexpr int TC = G::TC, PC = G::PC, SC = G::SC, RS = G::RS;
   constexpr bool SOLVE = (MODE == MODE_IMAG || MODE == MODE_REAL || MODE == MODE_ADJ);
   using IT = Iters<N * TC>;
-  __shared__ cpx<T> B[NR * RS];
-  __shared__ cpx<T> MT[SOLVE ? N : 1], GT[SOLVE ? N : 1];
-  __shared__ double red[2 * kWaves];
+  Carve cv{lds};
+  cpx<T>* B = cv.take<cpx<T>>(G::NR * RS);
+  cpx<T>* MT = cv.take<cpx<T>>(cn_table_len<N, PC>());
+  double* red = cv.take<double>(8 * kWaves);
   const int tid = threadIdx.x;
   const int nt = (n0 + TC - 1) / TC;
-  const int outer = blockIdx.x / nt;
-  const int x0 = (blockIdx.x % nt) * TC;
+  const int outer = bid / nt;
+  const int x0 = (bid % nt) * TC;
   cpx<T>* base = psi + (size_t)outer * ostride + x0;
   cpx<T> v[IT::N];
 #pragma unroll
@@ -457,12 +605,7 @@ __global__ __launch_bounds__(kThreads) void k_cn_col(cpx<T>* __restrict__ psi,
     const int c = u % TC, r = u / TC;
     v[it] = (IT::valid(u) && x0 + c < n0) ? base[(size_t)r * estride + c] : cpx<T>{0, 0};
   }
-  if constexpr (SOLVE) {
-    for (int i = tid; i < N; i += kThreads) {
-      MT[i] = cnm[i];
-      GT[i] = cng[i];
-    }
-  }
+  if constexpr (SOLVE) load_cn_table<T, N, PC>(MT, cnm);
 #pragma unroll
   for (int it = 0; it < IT::N; ++it) {
     const int u = tid + it * kThreads;
@@ -470,13 +613,9 @@ __global__ __launch_bounds__(kThreads) void k_cn_col(cpx<T>* __restrict__ psi,
   }
   __syncthreads();
   if constexpr (SOLVE) {
-    // A = Ar (imaginary time), i Ar (real time), -i Ar (adjoint); Bc = 1 - 2A
-    const cpx<T> A = (MODE == MODE_IMAG) ? cpx<T>{(T)Ar, 0}
-                     : (MODE == MODE_REAL) ? cpx<T>{0, (T)Ar} : cpx<T>{0, (T)(-Ar)};
-    const cpx<T> Bc = (MODE == MODE_IMAG) ? cpx<T>{(T)(1.0 - 2.0 * Ar), 0}
-                      : (MODE == MODE_REAL) ? cpx<T>{(T)1, (T)(-2.0 * Ar)}
-                                            : cpx<T>{(T)1, (T)(2.0 * Ar)};
-    cn_solve_lines<T, N, TC, 1, RS, PC>(B, MT, GT, A, Bc);
+    cpx<T> A, Bc;
+    cn_coeffs<T, MODE>(Ar, A, Bc);
+    cn_solve_lines<T, N, TC, 1, RS, PC>(B, MT, A, Bc);
   }
   double sums[2] = {0.0, 0.0};
 #pragma unroll
@@ -493,142 +632,44 @@ __global__ __launch_bounds__(kThreads) void k_cn_col(cpx<T>* __restrict__ psi,
   }
   if constexpr (SUMS) {
     block_sum<2>(sums, red);
-    publish_and_finalize(sums, partials, counter, fa, fin_mode);
+    if (tid == 0) {
+      partials[bid * 2 + 0] = sums[0];
+      partials[bid * 2 + 1] = sums[1];
+    }
   }
 }
 
-}  // namespace gpdbec
-
-// ========================================================= adjoint (real time)
+// ============================================================ adjoint bodies
 // Backpropagation through one real-time step (costate lambda = dL/d conj(psi)):
 //   lambda_a = C_x(-dt) C_y(-dt) C_z(-dt) lambda      (adjoint of each CN factor)
 //   mu = exp(+i dt theta) lambda_a,  theta = V + g_c n + g_dd Phi  (of psi_n)
 //   s  = 2 dt Im(conj(mu) psi_n);   dL/dV += s;  sums s n, s Phi -> dL/dg_c, dL/dg_dd
 //   lambda_n = mu + (g_c s + g_dd K s) psi_n,  K s = F^-1[U F[s]]
-namespace gpdbec {
 
-// Real-to-complex x pass of a real field f (the adjoint's second convolution input).
-// grid: ceil(n1/TJ) * n2 blocks; writes the same kx-plane-major half spectrum.
+// Adjoint x pass: lambda_a = C_x(-dt) lambda (conjugate factors), Phi of psi_n from the
+// spectrum, mu -> lam, s -> sfield, gradV += s (FP64), partials[bid*2 + {0,1}] =
+// sum s n, sum s Phi.  tiles: ceil(n1/TJ) * n2.
 template <typename T, int N0>
-__global__ __launch_bounds__(kThreads) void k_r2c_real(const T* __restrict__ f,
-                                                       cpx<T>* __restrict__ spec,
-                                                       const cpx<T>* __restrict__ tw0, int n1,
-                                                       int n2) {
-  using TL = Tiles<T, N0>;
-  constexpr int TJ = TL::TJ, NP = TJ / 2, H = N0 / 2 + 1, LSZ = N0 + 1;
-  using IT = Iters<TJ * N0>;
-  using IH = Iters<H * NP>;
-  __shared__ cpx<T> Z[NP * LSZ];
-  __shared__ cpx<T> W[N0];
-  const int tid = threadIdx.x;
-  const int nt1 = (n1 + TJ - 1) / TJ;
-  const int k2 = blockIdx.x / nt1;
-  const int j0 = (blockIdx.x % nt1) * TJ;
-  const size_t pbase = ((size_t)k2 * n1 + j0) * N0;
-  T fv[IT::N];
-#pragma unroll
-  for (int it = 0; it < IT::N; ++it) {
-    const int u = tid + it * kThreads;
-    fv[it] = (IT::valid(u) && j0 + u / N0 < n1) ? f[pbase + u] : (T)0;
-  }
-  for (int i = tid; i < N0; i += kThreads) W[i] = tw0[i];
-#pragma unroll
-  for (int it = 0; it < IT::N; ++it) {
-    const int u = tid + it * kThreads;
-    if (!IT::valid(u)) continue;
-    const int jl = u / N0, i = u % N0;
-    cpx<T>& zc = Z[(jl >> 1) * LSZ + i];
-    if (jl & 1) zc.im = fv[it];
-    else zc.re = fv[it];
-  }
-  __syncthreads();
-  LdsFFT<T, N0, NP, LSZ, 1, false>::template run<false>(Z, W);
-#pragma unroll
-  for (int it = 0; it < IH::N; ++it) {
-    const int u = tid + it * kThreads;
-    if (!IH::valid(u)) continue;
-    const int p = u % NP, kx = u / NP;
-    const int j = j0 + 2 * p;
-    if (j >= n1) continue;
-    const cpx<T> zk = Z[p * LSZ + kx];
-    const cpx<T> zm = Z[p * LSZ + ((N0 - kx) % N0)];
-    const T hf = (T)0.5;
-    cpx<T>* o = spec + ((size_t)kx * n2 + k2) * n1 + j;
-    o[0] = cpx<T>{hf * (zk.re + zm.re), hf * (zk.im - zm.im)};
-    o[1] = cpx<T>{hf * (zk.im + zm.im), hf * (zm.re - zk.re)};
-  }
-}
-
-// Gathers the Hermitian half spectrum of the tile's line pairs into full complex lines
-// (issued loads first) and runs the inverse x FFT: afterwards line jl of the tile holds
-// the real field in component (jl & 1) of Z[(jl >> 1) * (N0 + 1) + i].
-template <typename T, int N0, int NP>
-__device__ __forceinline__ void c2r_tile(cpx<T>* Z, const cpx<T>* W,
-                                         const cpx<T>* __restrict__ spec, int j0, int k2,
-                                         int n1, int n2, const cpx<T> (&sa)[Iters<(N0 / 2 + 1) * NP>::N],
-                                         const cpx<T> (&sb)[Iters<(N0 / 2 + 1) * NP>::N]) {
-  constexpr int LSZ = N0 + 1, H = N0 / 2 + 1;
-  using IH = Iters<H * NP>;
-#pragma unroll
-  for (int it = 0; it < IH::N; ++it) {
-    const int u = threadIdx.x + it * kThreads;
-    if (!IH::valid(u)) continue;
-    const int p = u % NP, kx = u / NP;
-    const cpx<T> a = sa[it], b = sb[it];
-    cpx<T>* z = Z + p * LSZ;
-    if (kx == 0 || kx == N0 / 2) {
-      z[kx] = cpx<T>{a.re, b.re};
-    } else {
-      z[kx] = cpx<T>{a.re - b.im, a.im + b.re};
-      z[N0 - kx] = cpx<T>{a.re + b.im, b.re - a.im};
-    }
-  }
-  __syncthreads();
-  LdsFFT<T, N0, NP, LSZ, 1, false>::template run<true>(Z, W);
-}
-
-template <typename T, int N0, int NP>
-__device__ __forceinline__ void load_spec_pairs(const cpx<T>* __restrict__ spec, int j0, int k2,
-                                                int n1, int n2,
-                                                cpx<T> (&sa)[Iters<(N0 / 2 + 1) * NP>::N],
-                                                cpx<T> (&sb)[Iters<(N0 / 2 + 1) * NP>::N]) {
-  using IH = Iters<(N0 / 2 + 1) * NP>;
-#pragma unroll
-  for (int it = 0; it < IH::N; ++it) {
-    const int u = threadIdx.x + it * kThreads;
-    const int p = u % NP, kx = u / NP;
-    const int j = j0 + 2 * p;
-    const bool in = IH::valid(u) && j < n1;
-    const cpx<T>* o = spec + ((size_t)kx * n2 + k2) * n1 + j;
-    sa[it] = in ? o[0] : cpx<T>{0, 0};
-    sb[it] = in ? o[1] : cpx<T>{0, 0};
-  }
-}
-
-// Adjoint x pass: lambda_a = C_x(-dt) lambda (conj tables), Phi of psi_n from the
-// spectrum, mu = exp(i dt theta) lambda_a -> lam, s -> sfield, gradV += s (FP64),
-// partials[b*2 + {0,1}] = sum s n, sum s Phi.  grid: ceil(n1/TJ) * n2 blocks.
-template <typename T, int N0>
-__global__ __launch_bounds__(kThreads) void k_adj_x(
+__device__ __forceinline__ void adj_x_body(
     cpx<T>* __restrict__ lam, const cpx<T>* __restrict__ psin, const T* __restrict__ V,
     const cpx<T>* __restrict__ spec, const cpx<T>* __restrict__ tw0,
-    const cpx<T>* __restrict__ cnm, const cpx<T>* __restrict__ cng, StepScalars sc,
-    T* __restrict__ sfield, double* __restrict__ gradV, double* __restrict__ partials, int n1,
-    int n2) {
-  using TL = Tiles<T, N0>;
-  constexpr int TJ = TL::TJ, NP = TJ / 2, LSZ = N0 + 1;
-  constexpr int PX = TL::PX, SX = (N0 + PX - 1) / PX, LSP = N0 + (N0 + SX - 1) / SX;
+    const cpx<T>* __restrict__ cnm, const StepScalars& sc, T* __restrict__ sfield,
+    double* __restrict__ gradV, double* __restrict__ partials, int n1, int n2, int bid,
+    char* lds) {
+  using X = XT<T, N0>;
+  constexpr int TJ = X::TJ, NP = X::NP, LSZ = X::LSZ, PX = X::PX, SX = X::SX, LSP = X::LSP;
   using IT = Iters<TJ * N0>;
   using IH = Iters<(N0 / 2 + 1) * NP>;
-  __shared__ cpx<T> Z[NP * LSZ];
-  __shared__ cpx<T> PS[TJ * LSP];
-  __shared__ cpx<T> W[N0];
-  __shared__ cpx<T> MT[N0], GT[N0];
-  __shared__ double red[2 * kWaves];
+  Carve cv{lds};
+  cpx<T>* Z = cv.take<cpx<T>>(NP * LSZ);
+  cpx<T>* PS = cv.take<cpx<T>>(TJ * LSP);
+  cpx<T>* W = cv.take<cpx<T>>(N0);
+  cpx<T>* MT = cv.take<cpx<T>>(cn_table_len<N0, PX>());
+  double* red = cv.take<double>(8 * kWaves);
   const int tid = threadIdx.x;
   const int nt1 = (n1 + TJ - 1) / TJ;
-  const int k2 = blockIdx.x / nt1;
-  const int j0 = (blockIdx.x % nt1) * TJ;
+  const int k2 = bid / nt1;
+  const int j0 = (bid % nt1) * TJ;
   const size_t pbase = ((size_t)k2 * n1 + j0) * N0;
   cpx<T> sa[IH::N], sb[IH::N];
   load_spec_pairs<T, N0, NP>(spec, j0, k2, n1, n2, sa, sb);
@@ -642,20 +683,17 @@ __global__ __launch_bounds__(kThreads) void k_adj_x(
     pv[it] = in ? psin[pbase + u] : cpx<T>{0, 0};
     vv[it] = in ? V[pbase + u] : (T)0;
   }
-  for (int i = tid; i < N0; i += kThreads) {
-    W[i] = tw0[i];
-    MT[i] = cnm[i];
-    GT[i] = cng[i];
-  }
+  for (int i = tid; i < N0; i += kThreads) W[i] = tw0[i];
+  load_cn_table<T, N0, PX>(MT, cnm);
 #pragma unroll
   for (int it = 0; it < IT::N; ++it) {
     const int u = tid + it * kThreads;
     if (IT::valid(u)) PS[(u / N0) * LSP + cpad<SX>(u % N0)] = lv[it];
   }
-  c2r_tile<T, N0, NP>(Z, W, spec, j0, k2, n1, n2, sa, sb);  // ends with a barrier
-  const cpx<T> A = {0, (T)(-sc.Ar)};
-  const cpx<T> B = {(T)1, (T)(2.0 * sc.Ar)};
-  cn_solve_lines<T, N0, TJ, LSP, 1, PX>(PS, MT, GT, A, B);
+  c2r_tile<T, N0, NP>(Z, W, sa, sb);  // ends with a barrier
+  cpx<T> A, Bc;
+  cn_coeffs<T, MODE_ADJ>(sc.Ar, A, Bc);
+  cn_solve_lines<T, N0, TJ, LSP, 1, PX>(PS, MT, A, Bc);
   double sums[2] = {0.0, 0.0};
   const T dt = (T)sc.dt;
 #pragma unroll
@@ -664,7 +702,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_x(
     if (!IT::valid(u)) continue;
     const int jl = u / N0, i = u % N0;
     if (j0 + jl >= n1) continue;
-    const T phi = (jl & 1) ? Z[(jl >> 1) * LSZ + i].im : Z[(jl >> 1) * LSZ + i].re;
+    const T phi = tile_real(Z, LSZ, jl, i);
     const cpx<T> p = pv[it];
     const T n = p.re * p.re + p.im * p.im;
     const T th = dt * (vv[it] + (T)sc.gc * n + (T)sc.gdd * phi);
@@ -679,29 +717,31 @@ __global__ __launch_bounds__(kThreads) void k_adj_x(
   }
   block_sum<2>(sums, red);
   if (tid == 0) {
-    partials[blockIdx.x * 2 + 0] = sums[0];
-    partials[blockIdx.x * 2 + 1] = sums[1];
+    partials[bid * 2 + 0] = sums[0];
+    partials[bid * 2 + 1] = sums[1];
   }
 }
 
 // Adjoint closing x pass: K s from the spectrum; lambda = mu + (g_c s + g_dd K s) psi_n.
 template <typename T, int N0>
-__global__ __launch_bounds__(kThreads) void k_adj_fin(cpx<T>* __restrict__ lam,
-                                                      const cpx<T>* __restrict__ psin,
-                                                      const T* __restrict__ sfield,
-                                                      const cpx<T>* __restrict__ spec,
-                                                      const cpx<T>* __restrict__ tw0,
-                                                      StepScalars sc, int n1, int n2) {
-  using TL = Tiles<T, N0>;
-  constexpr int TJ = TL::TJ, NP = TJ / 2, LSZ = N0 + 1;
+__device__ __forceinline__ void adj_fin_body(cpx<T>* __restrict__ lam,
+                                             const cpx<T>* __restrict__ psin,
+                                             const T* __restrict__ sfield,
+                                             const cpx<T>* __restrict__ spec,
+                                             const cpx<T>* __restrict__ tw0,
+                                             const StepScalars& sc, int n1, int n2, int bid,
+                                             char* lds) {
+  using X = XT<T, N0>;
+  constexpr int TJ = X::TJ, NP = X::NP, LSZ = X::LSZ;
   using IT = Iters<TJ * N0>;
   using IH = Iters<(N0 / 2 + 1) * NP>;
-  __shared__ cpx<T> Z[NP * LSZ];
-  __shared__ cpx<T> W[N0];
+  Carve cv{lds};
+  cpx<T>* Z = cv.take<cpx<T>>(NP * LSZ);
+  cpx<T>* W = cv.take<cpx<T>>(N0);
   const int tid = threadIdx.x;
   const int nt1 = (n1 + TJ - 1) / TJ;
-  const int k2 = blockIdx.x / nt1;
-  const int j0 = (blockIdx.x % nt1) * TJ;
+  const int k2 = bid / nt1;
+  const int j0 = (bid % nt1) * TJ;
   const size_t pbase = ((size_t)k2 * n1 + j0) * N0;
   cpx<T> sa[IH::N], sb[IH::N];
   load_spec_pairs<T, N0, NP>(spec, j0, k2, n1, n2, sa, sb);
@@ -716,17 +756,106 @@ __global__ __launch_bounds__(kThreads) void k_adj_fin(cpx<T>* __restrict__ lam,
     sv[it] = in ? sfield[pbase + u] : (T)0;
   }
   for (int i = tid; i < N0; i += kThreads) W[i] = tw0[i];
-  c2r_tile<T, N0, NP>(Z, W, spec, j0, k2, n1, n2, sa, sb);
+  c2r_tile<T, N0, NP>(Z, W, sa, sb);
 #pragma unroll
   for (int it = 0; it < IT::N; ++it) {
     const int u = tid + it * kThreads;
     if (!IT::valid(u)) continue;
     const int jl = u / N0, i = u % N0;
     if (j0 + jl >= n1) continue;
-    const T ks = (jl & 1) ? Z[(jl >> 1) * LSZ + i].im : Z[(jl >> 1) * LSZ + i].re;
-    const T w = (T)sc.gc * sv[it] + (T)sc.gdd * ks;
+    const T w = (T)sc.gc * sv[it] + (T)sc.gdd * tile_real(Z, LSZ, jl, i);
     lam[pbase + u] = mv[it] + scl(pv[it], w);
   }
 }
+
+// ========================================================= single-grid kernels
+// One block per tile; static LDS sized for the pass.
+#define GP_LDS(T, N, PASS) __shared__ __attribute__((aligned(16))) char lds[lds_bytes<T, N, PASS>()]
+
+template <typename T, int N0>
+__global__ __launch_bounds__(kThreads) void k_r2c_x(const cpx<T>* __restrict__ psi,
+                                                    const double* __restrict__ scale,
+                                                    cpx<T>* __restrict__ spec,
+                                                    const cpx<T>* __restrict__ tw0,
+                                                    double* __restrict__ partials, int n1, int n2) {
+  GP_LDS(T, N0, P_R2C);
+  r2c_x_body<T, N0>(psi, scale, spec, tw0, partials, n1, n2, blockIdx.x, lds);
+}
+
+template <typename T, int N0>
+__global__ __launch_bounds__(kThreads) void k_r2c_real(const T* __restrict__ f,
+                                                       cpx<T>* __restrict__ spec,
+                                                       const cpx<T>* __restrict__ tw0, int n1,
+                                                       int n2) {
+  GP_LDS(T, N0, P_R2C_REAL);
+  r2c_real_body<T, N0>(f, spec, tw0, n1, n2, blockIdx.x, lds);
+}
+
+template <typename T, int N, bool INV>
+__global__ __launch_bounds__(kThreads) void k_fft_line(cpx<T>* __restrict__ data,
+                                                       const cpx<T>* __restrict__ tw, int nlines) {
+  GP_LDS(T, N, P_FFT_LINE);
+  fft_line_body<T, N, INV>(data, tw, nlines, blockIdx.x, lds);
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(kThreads) void k_conv_line(cpx<T>* __restrict__ data,
+                                                        const T* __restrict__ ktab,
+                                                        const cpx<T>* __restrict__ tw, int nlines) {
+  GP_LDS(T, N, P_CONV_LINE);
+  conv_line_body<T, N>(data, ktab, tw, nlines, blockIdx.x, lds);
+}
+
+template <typename T, int N2>
+__global__ __launch_bounds__(kThreads) void k_conv_col(cpx<T>* __restrict__ spec,
+                                                       const T* __restrict__ ktab,
+                                                       const cpx<T>* __restrict__ tw2, int n1) {
+  GP_LDS(T, N2, P_CONV_COL);
+  conv_col_body<T, N2>(spec, ktab, tw2, n1, blockIdx.x, lds);
+}
+
+template <typename T, int N0, int MODE>
+__global__ __launch_bounds__(kThreads) void k_c2r_nl_cnx(
+    cpx<T>* __restrict__ psi, const T* __restrict__ V, const double* __restrict__ scale,
+    const cpx<T>* __restrict__ spec, const cpx<T>* __restrict__ tw0,
+    const cpx<T>* __restrict__ cnm, StepScalars sc, double* __restrict__ partials,
+    T* __restrict__ phi_out, int n1, int n2) {
+  GP_LDS(T, N0, ((MODE == MODE_IMAG || MODE == MODE_REAL) ? P_C2R_STEP : P_C2R_OBS));
+  c2r_nl_cnx_body<T, N0, MODE>(psi, V, scale, spec, tw0, cnm, sc, partials, phi_out, n1, n2,
+                               blockIdx.x, lds);
+}
+
+template <typename T, int N, int MODE, bool SUMS>
+__global__ __launch_bounds__(kThreads) void k_cn_col(cpx<T>* __restrict__ psi,
+                                                     const cpx<T>* __restrict__ cnm,
+                                                     double Ar, double* __restrict__ partials,
+                                                     int n0, size_t estride, size_t ostride) {
+  GP_LDS(T, N, P_CN_COL);
+  cn_col_body<T, N, MODE, SUMS>(psi, cnm, Ar, partials, n0, estride, ostride, blockIdx.x, lds);
+}
+
+template <typename T, int N0>
+__global__ __launch_bounds__(kThreads) void k_adj_x(
+    cpx<T>* __restrict__ lam, const cpx<T>* __restrict__ psin, const T* __restrict__ V,
+    const cpx<T>* __restrict__ spec, const cpx<T>* __restrict__ tw0,
+    const cpx<T>* __restrict__ cnm, StepScalars sc, T* __restrict__ sfield,
+    double* __restrict__ gradV, double* __restrict__ partials, int n1, int n2) {
+  GP_LDS(T, N0, P_ADJ_X);
+  adj_x_body<T, N0>(lam, psin, V, spec, tw0, cnm, sc, sfield, gradV, partials, n1, n2,
+                    blockIdx.x, lds);
+}
+
+template <typename T, int N0>
+__global__ __launch_bounds__(kThreads) void k_adj_fin(cpx<T>* __restrict__ lam,
+                                                      const cpx<T>* __restrict__ psin,
+                                                      const T* __restrict__ sfield,
+                                                      const cpx<T>* __restrict__ spec,
+                                                      const cpx<T>* __restrict__ tw0,
+                                                      StepScalars sc, int n1, int n2) {
+  GP_LDS(T, N0, P_ADJ_FIN);
+  adj_fin_body<T, N0>(lam, psin, sfield, spec, tw0, sc, n1, n2, blockIdx.x, lds);
+}
+
+#undef GP_LDS
 
 }  // namespace gpdbec

@@ -36,22 +36,21 @@ struct Launch {
                              const cpx<T>* tw2, int n1);
   static hipError_t c2r_nl_cnx(int n0, int mode, int blocks, hipStream_t st, cpx<T>* psi,
                                const T* V, const double* scale, const cpx<T>* spec,
-                               const cpx<T>* tw0, const cpx<T>* cnm, const cpx<T>* cng,
-                               const StepScalars& sc, double* part, T* phi_out, int n1, int n2);
+                               const cpx<T>* tw0, const cpx<T>* cnm, const StepScalars& sc,
+                               double* part, T* phi_out, int n1, int n2);
   // adjoint x passes
   static hipError_t r2c_real(int n0, int blocks, hipStream_t st, const T* f, cpx<T>* spec,
                              const cpx<T>* tw0, int n1, int n2);
   static hipError_t adj_x(int n0, int blocks, hipStream_t st, cpx<T>* lam, const cpx<T>* psin,
                           const T* V, const cpx<T>* spec, const cpx<T>* tw0, const cpx<T>* cnm,
-                          const cpx<T>* cng, const StepScalars& sc, T* sfield, double* gradV,
-                          double* part, int n1, int n2);
+                          const StepScalars& sc, T* sfield, double* gradV, double* part, int n1,
+                          int n2);
   static hipError_t adj_fin(int n0, int blocks, hipStream_t st, cpx<T>* lam,
                             const cpx<T>* psin, const T* sfield, const cpx<T>* spec,
                             const cpx<T>* tw0, const StepScalars& sc, int n1, int n2);
   static hipError_t cn_col(int n, int mode, bool sums, int blocks, hipStream_t st, cpx<T>* psi,
-                           const cpx<T>* cnm, const cpx<T>* cng, double Ar, double* part, int n0,
-                           size_t estride, size_t ostride, unsigned* counter,
-                           const FinArgs& fa, int fin_mode);
+                           const cpx<T>* cnm, double Ar, double* part, int n0, size_t estride,
+                           size_t ostride);
 };
 
 // The members are defined (explicitly specialised) per precision in gp_inst.hip.
@@ -69,20 +68,19 @@ struct Launch {
                                              const cpx<T>*, int);                              \
   template <> hipError_t Launch<T>::c2r_nl_cnx(int, int, int, hipStream_t, cpx<T>*, const T*, \
                                                const double*, const cpx<T>*, const cpx<T>*,    \
-                                               const cpx<T>*, const cpx<T>*,                   \
-                                               const StepScalars&, double*, T*, int, int);     \
+                                               const cpx<T>*, const StepScalars&, double*, T*, \
+                                               int, int);                                      \
   template <> hipError_t Launch<T>::r2c_real(int, int, hipStream_t, const T*, cpx<T>*,        \
                                              const cpx<T>*, int, int);                          \
   template <> hipError_t Launch<T>::adj_x(int, int, hipStream_t, cpx<T>*, const cpx<T>*,       \
                                           const T*, const cpx<T>*, const cpx<T>*,               \
-                                          const cpx<T>*, const cpx<T>*, const StepScalars&,     \
-                                          T*, double*, double*, int, int);                      \
+                                          const cpx<T>*, const StepScalars&, T*, double*,       \
+                                          double*, int, int);                                   \
   template <> hipError_t Launch<T>::adj_fin(int, int, hipStream_t, cpx<T>*, const cpx<T>*,     \
                                             const T*, const cpx<T>*, const cpx<T>*,             \
                                             const StepScalars&, int, int);                      \
   template <> hipError_t Launch<T>::cn_col(int, int, bool, int, hipStream_t, cpx<T>*,         \
-                                           const cpx<T>*, const cpx<T>*, double, double*, int, \
-                                           size_t, size_t, unsigned*, const FinArgs&, int);
+                                           const cpx<T>*, double, double*, int, size_t, size_t);
 GP_DECLARE_LAUNCH(float)
 GP_DECLARE_LAUNCH(double)
 #undef GP_DECLARE_LAUNCH
