@@ -171,12 +171,42 @@ typedef enum {
   GP_PASS_C2R_NL_CNX = 5, /* x C2R -> Phi, observables sums, phase, CN sweep x     */
   GP_PASS_CN_Y = 6,       /* CN sweep y (2D: with the new-state norm sum)          */
   GP_PASS_CN_Z = 7,       /* 3D: CN sweep z with new-state norm / z-kinetic sums   */
-  GP_PASS_FINALIZE = 8,   /* standalone FP64 finalisation (2D observables only; in  */
-                          /* steps it runs in the last block of the last CN pass)   */
+  GP_PASS_FINALIZE = 8,   /* single-block FP64 finalisation of the block partials   */
+                          /* (norm, observables, next lazy scale, history record)   */
   GP_PASS_COUNT = 9
 } gp_pass;
 gp_status gp_timing_enable(gp_ctx* ctx, unsigned pass_mask);
 gp_status gp_timing_read(gp_ctx* ctx, double* total_ms, int* launches);
+
+/* ------------------------------------------------------------ batched ensemble
+ * Many independent quasi-2D instances (GP_2D_XY / GP_2D_XZ, any mix) of uneven sizes
+ * and parameters, stepped together: each pass of a step is one persistent launch per
+ * size class (lines <= 256 points, and 384/512) over a work list of (instance, tile)
+ * items from every instance, sorted by decreasing instance size; one FP64 finalisation
+ * block per instance.  Steps replay a captured HIP graph (8 steps) when nsteps >= 8.
+ * All instances share one precision; every axis must be one of 32, 48, 64, 96, 128, 192,
+ * 256, 384, 512 (else GP_E_SIZE).  The caller-owned workspace holds one single-grid
+ * workspace per instance plus descriptors and work lists. */
+typedef struct gp_batch gp_batch;
+gp_status gp_batch_workspace_bytes(const gp_params* params, int count, size_t* bytes);
+gp_status gp_batch_init(const gp_params* params, int count, void* dev_workspace,
+                        size_t ws_bytes, void* hip_stream, gp_batch** out);
+gp_status gp_batch_destroy(gp_batch* batch);
+/* The single-grid context of instance idx (owned by the batch; NULL if out of range):
+ * use it for gp_set_psi / gp_get_psi / gp_energy / gp_history of that instance. */
+gp_ctx* gp_batch_context(gp_batch* batch, int idx);
+/* nsteps imaginary- / real-time steps of every instance (all psi must be set). */
+gp_status gp_batch_step_imag(gp_batch* batch, int nsteps);
+gp_status gp_batch_step_real(gp_batch* batch, int nsteps);
+/* Observables of every instance's current psi (count records).  Synchronous. */
+gp_status gp_batch_energy(gp_batch* batch, gp_observables* out);
+/* Launch plan (autotuner interface).  items/blocks: arrays of 4 passes x 2 size classes
+ * (r2c, conv, c2r, cn; class 0 = lines <= 256): work items and persistent blocks.
+ * gp_batch_set_blocks sets the persistent block count of one (pass, class); 0 restores
+ * the default (min(items, 1024)). */
+gp_status gp_batch_plan(gp_batch* batch, int* items, int* blocks);
+gp_status gp_batch_set_blocks(gp_batch* batch, int pass, int size_class, int blocks);
+gp_status gp_batch_use_graphs(gp_batch* batch, int enable);
 
 /* Text of the HIP error behind the calling thread's most recent GP_E_DEVICE ("" if none).
  * The pointer stays valid until the thread's next failing call. */

@@ -76,6 +76,18 @@ _SIGS = {
     "gp_sync": (ctypes.c_int, [_P]),
     "gp_last_error": (ctypes.c_char_p, []),
     "gp_use_graphs": (ctypes.c_int, [_P, ctypes.c_int]),
+    "gp_batch_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(gp_params), ctypes.c_int,
+                                                ctypes.POINTER(ctypes.c_size_t)]),
+    "gp_batch_init": (ctypes.c_int, [ctypes.POINTER(gp_params), ctypes.c_int, _P, ctypes.c_size_t,
+                                     _P, ctypes.POINTER(_P)]),
+    "gp_batch_destroy": (ctypes.c_int, [_P]),
+    "gp_batch_context": (_P, [_P, ctypes.c_int]),
+    "gp_batch_step_imag": (ctypes.c_int, [_P, ctypes.c_int]),
+    "gp_batch_step_real": (ctypes.c_int, [_P, ctypes.c_int]),
+    "gp_batch_energy": (ctypes.c_int, [_P, ctypes.POINTER(gp_observables)]),
+    "gp_batch_plan": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "gp_batch_set_blocks": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "gp_batch_use_graphs": (ctypes.c_int, [_P, ctypes.c_int]),
     "gp_step_real_adjoint": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "gp_timing_enable": (ctypes.c_int, [_P, ctypes.c_uint]),
     "gp_timing_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
@@ -334,3 +346,91 @@ def _shape(params):
     if g == "2dxy":
         return (params["ny"], params["nx"])
     return (params["nz"], params["nx"])
+
+
+# ------------------------------------------------------------------ batched ensemble
+BATCH_PASSES = ("r2c_x", "conv_y", "c2r_nl_cnx", "cn_y")
+BATCH_CLASSES = 2
+
+
+class Batch:
+    """Many independent quasi-2D instances stepped together (gp_batch_*): one persistent
+    launch per pass and size class.  params_list: dicts as for Solver (geom 2dxy/2dxz)."""
+
+    def __init__(self, params_list, prec="fp32", device="cuda:0", stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.prec = prec
+        self.count = len(params_list)
+        arr = (gp_params * self.count)()
+        for i, p in enumerate(params_list):
+            arr[i] = make_params(**{**p, "prec": prec})
+        self._arr = arr
+        self.shapes = [_shape(p) for p in params_list]
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        lib = load()
+        n = ctypes.c_size_t(0)
+        _check(lib.gp_batch_workspace_bytes(arr, self.count, ctypes.byref(n)),
+               "gp_batch_workspace_bytes")
+        self.ws_bytes = n.value
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self.ws.data_ptr() + 255) & ~255
+        h = _P()
+        _check(lib.gp_batch_init(arr, self.count, _P(ptr), self.ws_bytes,
+                                 _P(self.stream.cuda_stream), ctypes.byref(h)), "gp_batch_init")
+        self.handle = h.value
+        self.ctxs = [lib.gp_batch_context(_P(self.handle), i) for i in range(self.count)]
+
+    def close(self):
+        if self.handle:
+            _check(load().gp_batch_destroy(_P(self.handle)), "gp_batch_destroy")
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_psi(self, idx, psi):
+        a = np.ascontiguousarray(psi, dtype=np.complex128)
+        assert a.shape == self.shapes[idx]
+        gp_set_psi(self.ctxs[idx], a.ctypes.data, 0)
+
+    def get_psi(self, idx):
+        out = np.empty(self.shapes[idx], dtype=np.complex128)
+        gp_get_psi(self.ctxs[idx], out.ctypes.data, 0)
+        return out
+
+    def step_imag(self, n):
+        _check(load().gp_batch_step_imag(_P(self.handle), n), "gp_batch_step_imag")
+
+    def step_real(self, n):
+        _check(load().gp_batch_step_real(_P(self.handle), n), "gp_batch_step_real")
+
+    def energy(self):
+        arr = (gp_observables * self.count)()
+        _check(load().gp_batch_energy(_P(self.handle), arr), "gp_batch_energy")
+        return [arr[i].as_dict() for i in range(self.count)]
+
+    def history(self, idx, n):
+        return gp_history(self.ctxs[idx], n)
+
+    def plan(self):
+        k = len(BATCH_PASSES) * BATCH_CLASSES
+        items = (ctypes.c_int * k)()
+        blocks = (ctypes.c_int * k)()
+        _check(load().gp_batch_plan(_P(self.handle), items, blocks), "gp_batch_plan")
+        return {(BATCH_PASSES[i // BATCH_CLASSES], i % BATCH_CLASSES): (items[i], blocks[i])
+                for i in range(k)}
+
+    def set_blocks(self, pass_name, size_class, blocks):
+        _check(load().gp_batch_set_blocks(_P(self.handle), BATCH_PASSES.index(pass_name),
+                                          size_class, blocks), "gp_batch_set_blocks")
+
+    def use_graphs(self, enable):
+        _check(load().gp_batch_use_graphs(_P(self.handle), int(bool(enable))), "gp_batch_use_graphs")
+
+    def points(self):
+        return int(sum(int(np.prod(s)) for s in self.shapes))

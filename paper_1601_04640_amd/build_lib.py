@@ -30,6 +30,10 @@ def _jobs():
             cmd = [HIPCC, *FLAGS, f"-DGP_REAL={real}", f"-DGP_FAMILY={fam}", "-c",
                    os.path.join(CSRC, "gp_inst.hip"), "-o", obj]
             jobs.append((obj, cmd))
+    for real in ("float", "double"):
+        obj = os.path.join(BUILD, f"batch_{real}.o")
+        jobs.append((obj, [HIPCC, *FLAGS, f"-DGP_REAL={real}", "-c",
+                           os.path.join(CSRC, "gp_batch_inst.hip"), "-o", obj]))
     obj = os.path.join(BUILD, "capi.o")
     jobs.append((obj, [HIPCC, *FLAGS, "-c", os.path.join(CSRC, "gp_capi.hip"), "-o", obj]))
     return jobs

@@ -8,10 +8,12 @@
 
 #include <new>
 #include <utility>
+#include <algorithm>
 #include <vector>
 
 #include "../../include/gp.h"
 #include "gp_aux.hpp"
+#include "gp_batch_launch.hpp"
 #include "gp_kernels.hpp"
 #include "gp_launch.hpp"
 
@@ -584,6 +586,246 @@ gp_status run_steps(gp_ctx* c, int nsteps, bool imag) {
 
 }  // namespace
 
+// =============================================================== batched ensemble
+struct gp_batch {
+  int count = 0;
+  bool fp64 = false;
+  hipStream_t st = nullptr;
+  std::vector<gp_ctx*> inst;
+  std::vector<gp_params> params;
+  char* ws = nullptr;
+  void* desc = nullptr;                       // device BDesc<T>[count]
+  WorkItem* work[BP_COUNT][kBatchClasses] = {};
+  int nwork[BP_COUNT][kBatchClasses] = {};
+  size_t lds[BP_COUNT][kBatchClasses][3] = {};  // [pass][class][mode imag/real/observe]
+  int grid[BP_COUNT][kBatchClasses] = {};
+  bool use_graphs = true;
+  hipStream_t cap_st = nullptr;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  std::vector<double> cpl;                    // (g, g_dd) per instance in the descriptors
+};
+
+namespace {
+
+constexpr int kBatchDefaultGrid = 1024;
+
+gp_status batch_validate(const gp_params* arr, int count) {
+  if (!arr || count <= 0) return GP_E_ARG;
+  for (int i = 0; i < count; ++i) {
+    GP_TRY(validate(&arr[i]));
+    if (arr[i].geom == GP_3D) return GP_E_ARG;
+    if (arr[i].prec != arr[0].prec) return GP_E_ARG;
+    const int n1 = arr[i].geom == GP_2D_XY ? arr[i].ny : arr[i].nz;
+    const bool ok = arr[i].prec == GP_FP64
+                        ? (batch_size_ok<double>(arr[i].nx) && batch_size_ok<double>(n1))
+                        : (batch_size_ok<float>(arr[i].nx) && batch_size_ok<float>(n1));
+    if (!ok) return GP_E_SIZE;
+  }
+  return GP_OK;
+}
+
+// Workspace: descriptors, work lists, then one single-grid workspace per instance.
+struct BatchLayout {
+  size_t o_desc, o_work, o_inst0, total;
+  std::vector<size_t> o_inst;
+  int total_items;
+};
+
+template <typename T>
+int batch_items(const gp_params* arr, int count) {
+  int tot = 0;
+  for (int i = 0; i < count; ++i) {
+    const int n1 = arr[i].geom == GP_2D_XY ? arr[i].ny : arr[i].nz;
+    int nbx, nbc, nbcol;
+    batch_tiles<T>(arr[i].nx, n1, &nbx, &nbc, &nbcol);
+    tot += 2 * nbx + nbc + nbcol;
+  }
+  return tot;
+}
+
+BatchLayout batch_layout(const gp_params* arr, int count) {
+  BatchLayout B{};
+  const bool fp64 = arr[0].prec == GP_FP64;
+  const size_t dsz = fp64 ? sizeof(BDesc<double>) : sizeof(BDesc<float>);
+  B.total_items = fp64 ? batch_items<double>(arr, count) : batch_items<float>(arr, count);
+  size_t o = 0;
+  B.o_desc = o;
+  o += align_up(dsz * count);
+  B.o_work = o;
+  o += align_up(sizeof(WorkItem) * (size_t)B.total_items);
+  for (int i = 0; i < count; ++i) {
+    B.o_inst.push_back(o);
+    o += align_up(make_layout(&arr[i]).total);
+  }
+  B.total = o;
+  return B;
+}
+
+void batch_drop_graphs(gp_batch* b) {
+  for (auto& g : b->gexec) {
+    if (g) hipGraphExecDestroy(g);
+    g = nullptr;
+  }
+}
+
+// Per-instance descriptors (pointers into the instance workspaces, step scalars and
+// couplings); rewritten when an instance's couplings change.
+template <typename T>
+gp_status batch_write_desc(gp_batch* b) {
+  std::vector<BDesc<T>> D(b->count);
+  b->cpl.assign(2 * (size_t)b->count, 0.0);
+  for (int i = 0; i < b->count; ++i) {
+    gp_ctx* c = b->inst[i];
+    const Layout& L = c->L;
+    BDesc<T>& d = D[i];
+    d.psi = c->at<cpx<T>>(L.o_psi);
+    d.V = c->at<T>(L.o_V);
+    d.spec = c->at<cpx<T>>(L.o_spec);
+    d.ktab = c->at<T>(L.o_ktab);
+    d.tw0 = c->at<cpx<T>>(L.o_tw[0]);
+    d.tw1 = c->at<cpx<T>>(L.o_tw[1]);
+    d.cn0[0] = c->at<cpx<T>>(L.o_cn[0][0]);
+    d.cn0[1] = c->at<cpx<T>>(L.o_cn[0][2]);
+    d.cn1[0] = c->at<cpx<T>>(L.o_cn[1][0]);
+    d.cn1[1] = c->at<cpx<T>>(L.o_cn[1][2]);
+    d.p_x = c->at<double>(L.o_px);
+    d.p_nl = c->at<double>(L.o_pnl);
+    d.p_col = c->at<double>(L.o_pcol);
+    d.scale = &c->sc()->scale;
+    d.sc = scalars_for(c, 0);
+    d.Ar1 = scalars_for(c, 1).Ar;
+    d.n0 = L.n0;
+    d.n1 = L.n1;
+    d.fa = fin_args(c);
+    b->cpl[2 * i] = c->p.g;
+    b->cpl[2 * i + 1] = c->p.gdd;
+  }
+  GP_HIP(hipMemcpyAsync(b->desc, D.data(), sizeof(BDesc<T>) * b->count, hipMemcpyHostToDevice,
+                        b->st));
+  return dev(hipStreamSynchronize(b->st));
+}
+
+template <typename T>
+gp_status batch_build(gp_batch* b, const BatchLayout& BL) {
+  GP_TRY(batch_write_desc<T>(b));
+  std::vector<int> n0(b->count), n1(b->count);
+  for (int i = 0; i < b->count; ++i) {
+    n0[i] = b->inst[i]->L.n0;
+    n1[i] = b->inst[i]->L.n1;
+  }
+  // work lists per (pass, class): instances by decreasing size, then their tiles
+  std::vector<int> order(b->count);
+  for (int i = 0; i < b->count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return (size_t)n0[x] * n1[x] > (size_t)n0[y] * n1[y];
+  });
+  std::vector<WorkItem> lists[BP_COUNT][kBatchClasses];
+  for (int i : order) {
+    int nbx, nbc, nbcol;
+    batch_tiles<T>(n0[i], n1[i], &nbx, &nbc, &nbcol);
+    const int c0 = batch_class(n0[i]), c1 = batch_class(n1[i]);
+    for (int t = 0; t < nbx; ++t) lists[BP_R2C][c0].push_back({i, t});
+    for (int t = 0; t < nbc; ++t) lists[BP_CONV][c1].push_back({i, t});
+    for (int t = 0; t < nbx; ++t) lists[BP_C2R][c0].push_back({i, t});
+    for (int t = 0; t < nbcol; ++t) lists[BP_CN][c1].push_back({i, t});
+    const int modes[3] = {MODE_IMAG, MODE_REAL, MODE_OBSERVE};
+    for (int m = 0; m < 3; ++m) {
+      size_t* L0 = b->lds[BP_R2C][c0];
+      L0[m] = std::max(L0[m], batch_lds<T>(BP_R2C, n0[i], modes[m]));
+      size_t* L1 = b->lds[BP_CONV][c1];
+      L1[m] = std::max(L1[m], batch_lds<T>(BP_CONV, n1[i], modes[m]));
+      size_t* L2 = b->lds[BP_C2R][c0];
+      L2[m] = std::max(L2[m], batch_lds<T>(BP_C2R, n0[i], modes[m]));
+      size_t* L3 = b->lds[BP_CN][c1];
+      L3[m] = std::max(L3[m], batch_lds<T>(BP_CN, n1[i], modes[m]));
+    }
+  }
+  WorkItem* dev_work = reinterpret_cast<WorkItem*>(b->ws + BL.o_work);
+  size_t off = 0;
+  for (int p = 0; p < BP_COUNT; ++p) {
+    for (int k = 0; k < kBatchClasses; ++k) {
+      b->work[p][k] = dev_work + off;
+      b->nwork[p][k] = (int)lists[p][k].size();
+      b->grid[p][k] = std::min(b->nwork[p][k], kBatchDefaultGrid);
+      if (!lists[p][k].empty())
+        GP_HIP(hipMemcpyAsync(dev_work + off, lists[p][k].data(),
+                              sizeof(WorkItem) * lists[p][k].size(), hipMemcpyHostToDevice,
+                              b->st));
+      off += lists[p][k].size();
+      for (int m = 0; m < 3; ++m)
+        if (b->lds[p][k][m] > 0) GP_HIP(batch_reserve_lds<T>(p, m, k, b->lds[p][k][m]));
+    }
+  }
+  GP_HIP(hipStreamSynchronize(b->st));
+  return GP_OK;
+}
+
+template <typename T>
+gp_status batch_step(gp_batch* b, hipStream_t st, bool imag) {
+  const int mode = imag ? MODE_IMAG : MODE_REAL;
+  const int mi = imag ? 0 : 1;
+  const BDesc<T>* D = reinterpret_cast<const BDesc<T>*>(b->desc);
+  const int passes[4] = {BP_R2C, BP_CONV, BP_C2R, BP_CN};
+  for (int p : passes) {
+    for (int k = 0; k < kBatchClasses; ++k) {
+      GP_HIP(batch_launch<T>(p, mode, k, b->grid[p][k], b->lds[p][k][mi], st, D, b->work[p][k],
+                             b->nwork[p][k]));
+    }
+  }
+  return dev(batch_finalize<T>(b->count, imag ? (int)FIN_IMAG : (int)FIN_REAL, st, D));
+}
+
+gp_status batch_one_step(gp_batch* b, hipStream_t st, bool imag) {
+  return b->fp64 ? batch_step<double>(b, st, imag) : batch_step<float>(b, st, imag);
+}
+
+gp_status batch_build_graph(gp_batch* b, bool imag) {
+  if (!b->cap_st) GP_HIP(hipStreamCreateWithFlags(&b->cap_st, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  gp_status s = dev(hipStreamBeginCapture(b->cap_st, hipStreamCaptureModeThreadLocal));
+  if (s == GP_OK) {
+    for (int i = 0; i < kGraphSteps && s == GP_OK; ++i) s = batch_one_step(b, b->cap_st, imag);
+    const gp_status e = dev(hipStreamEndCapture(b->cap_st, &g));
+    if (s == GP_OK) s = e;
+  }
+  if (s != GP_OK) {
+    if (g) hipGraphDestroy(g);
+    return s;
+  }
+  hipGraphExec_t ex = nullptr;
+  s = dev(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+  hipGraphDestroy(g);
+  if (s != GP_OK) return s;
+  b->gexec[imag ? 0 : 1] = ex;
+  return GP_OK;
+}
+
+gp_status batch_run(gp_batch* b, int nsteps, bool imag) {
+  if (!b || nsteps < 0) return GP_E_ARG;
+  clear_stale_error();
+  bool stale = false;
+  for (int i = 0; i < b->count; ++i) {
+    const gp_ctx* c = b->inst[i];
+    if (!c->psi_set) return GP_E_STATE;
+    stale |= c->p.g != b->cpl[2 * i] || c->p.gdd != b->cpl[2 * i + 1];
+  }
+  if (stale) {  // gp_set_couplings on an instance context since the descriptors were written
+    batch_drop_graphs(b);
+    GP_TRY(b->fp64 ? batch_write_desc<double>(b) : batch_write_desc<float>(b));
+  }
+  int done = 0;
+  if (b->use_graphs && nsteps >= kGraphSteps) {
+    const int gi = imag ? 0 : 1;
+    if (!b->gexec[gi]) GP_TRY(batch_build_graph(b, imag));
+    for (; nsteps - done >= kGraphSteps; done += kGraphSteps)
+      GP_HIP(hipGraphLaunch(b->gexec[gi], b->st));
+  }
+  for (; done < nsteps; ++done) GP_TRY(batch_one_step(b, b->st, imag));
+  return GP_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 gp_status gp_workspace_bytes(const gp_params* params, size_t* bytes) {
@@ -807,6 +1049,94 @@ gp_status gp_history(gp_ctx* c, gp_observables* out, int max_records, int* count
   }
   *count = n;
   return check_flags(c);
+}
+
+gp_status gp_batch_workspace_bytes(const gp_params* params, int count, size_t* bytes) {
+  if (!bytes) return GP_E_ARG;
+  GP_TRY(batch_validate(params, count));
+  *bytes = batch_layout(params, count).total;
+  return GP_OK;
+}
+
+gp_status gp_batch_init(const gp_params* params, int count, void* dev_workspace, size_t ws_bytes,
+                        void* hip_stream, gp_batch** out) {
+  if (!out || !dev_workspace) return GP_E_ARG;
+  *out = nullptr;
+  clear_stale_error();
+  GP_TRY(batch_validate(params, count));
+  const BatchLayout BL = batch_layout(params, count);
+  if (ws_bytes < BL.total) return GP_E_ARG;
+  if ((reinterpret_cast<uintptr_t>(dev_workspace) & 255) != 0) return GP_E_ARG;
+  gp_batch* b = new (std::nothrow) gp_batch();
+  if (!b) return GP_E_NOMEM;
+  b->count = count;
+  b->fp64 = params[0].prec == GP_FP64;
+  b->st = reinterpret_cast<hipStream_t>(hip_stream);
+  b->ws = reinterpret_cast<char*>(dev_workspace);
+  b->desc = b->ws + BL.o_desc;
+  b->params.assign(params, params + count);
+  gp_status s = GP_OK;
+  for (int i = 0; i < count && s == GP_OK; ++i) {
+    gp_ctx* c = nullptr;
+    s = gp_init(&params[i], b->ws + BL.o_inst[i], make_layout(&params[i]).total, hip_stream, &c);
+    if (s == GP_OK) b->inst.push_back(c);
+  }
+  if (s == GP_OK) s = b->fp64 ? batch_build<double>(b, BL) : batch_build<float>(b, BL);
+  if (s != GP_OK) {
+    gp_batch_destroy(b);
+    return s;
+  }
+  *out = b;
+  return GP_OK;
+}
+
+gp_status gp_batch_destroy(gp_batch* b) {
+  if (!b) return GP_E_ARG;
+  const hipError_t e = hipStreamSynchronize(b->st);
+  batch_drop_graphs(b);
+  if (b->cap_st) hipStreamDestroy(b->cap_st);
+  for (gp_ctx* c : b->inst) gp_destroy(c);
+  delete b;
+  return dev(e);
+}
+
+gp_ctx* gp_batch_context(gp_batch* b, int idx) {
+  if (!b || idx < 0 || idx >= b->count) return nullptr;
+  return b->inst[idx];
+}
+
+gp_status gp_batch_step_imag(gp_batch* b, int nsteps) { return batch_run(b, nsteps, true); }
+gp_status gp_batch_step_real(gp_batch* b, int nsteps) { return batch_run(b, nsteps, false); }
+
+gp_status gp_batch_energy(gp_batch* b, gp_observables* out) {
+  if (!b || !out) return GP_E_ARG;
+  for (int i = 0; i < b->count; ++i) GP_TRY(gp_energy(b->inst[i], &out[i]));
+  return GP_OK;
+}
+
+gp_status gp_batch_plan(gp_batch* b, int* items, int* blocks) {
+  if (!b || !items || !blocks) return GP_E_ARG;
+  for (int p = 0; p < BP_COUNT; ++p)
+    for (int k = 0; k < kBatchClasses; ++k) {
+      items[p * kBatchClasses + k] = b->nwork[p][k];
+      blocks[p * kBatchClasses + k] = b->grid[p][k];
+    }
+  return GP_OK;
+}
+
+gp_status gp_batch_set_blocks(gp_batch* b, int pass, int size_class, int blocks) {
+  if (!b || pass < 0 || pass >= BP_COUNT || size_class < 0 || size_class >= kBatchClasses)
+    return GP_E_ARG;
+  const int n = b->nwork[pass][size_class];
+  b->grid[pass][size_class] = blocks <= 0 ? std::min(n, kBatchDefaultGrid) : std::min(blocks, n);
+  batch_drop_graphs(b);  // the grid sizes are captured launch parameters
+  return GP_OK;
+}
+
+gp_status gp_batch_use_graphs(gp_batch* b, int enable) {
+  if (!b) return GP_E_ARG;
+  b->use_graphs = enable != 0;
+  return GP_OK;
 }
 
 gp_status gp_sync(gp_ctx* c) {

@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace gpdbec {
 
 constexpr int kThreads = 256;
@@ -222,8 +224,10 @@ __device__ __forceinline__ cpx<T> shfl_down_c(cpx<T> v, int off, int width) {
 // buf[l*LS + cpad<S>(i)*ES] with S = ceil(N/P):
 //     -A u_{i-1} + (1+2A) u_i - A u_{i+1} = A p_{i-1} + (1-2A) p_i + A p_{i+1},  0 < i < N-1,
 //     u_0 = u_{N-1} = 0,
-// and overwrite the line with u.  Thomas elimination with the data-independent factors
-// precomputed per axis: m_i = 1/(b - a c_{i-1}) and g_i = A m_i (= -c_i), so that
+// and overwrite the line with u.  A = a (IMAG_A false: imaginary-time step, all factors
+// real) or A = i a (IMAG_A true: real-time step, a > 0, or its adjoint, a < 0).
+// Thomas elimination with the data-independent factors precomputed per axis:
+// m_i = 1/(b - a c_{i-1}) and g_i = A m_i (= -c_i), so that
 //     forward   d_i = m_i r_i + g_i d_{i-1}
 //     backward  u_i = d_i + g_i u_{i+1}
 // (m = 0 on the two boundary rows makes them u = 0).  Each recurrence is an affine map
@@ -233,15 +237,62 @@ __device__ __forceinline__ cpx<T> shfl_down_c(cpx<T> v, int off, int width) {
 // chunk padding as the data, so the P lanes of a line read distinct banks); each lane
 // reads its chunk, its two neighbours and its m_i once into registers.  Every thread
 // must call this; it ends with a block barrier.
-template <typename T, int N, int NL, int LS, int ES, int P>
-__device__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt, cpx<T> A, cpx<T> B) {
+// Gains g = A m of the recurrences: complex when A = i a, real when A = a (then m is
+// real too).  mulg(g, x) = g x for a complex x; gg(g, h) = g h.
+template <typename T>
+__device__ __forceinline__ cpx<T> mulg(cpx<T> g, cpx<T> x) { return g * x; }
+template <typename T>
+__device__ __forceinline__ cpx<T> mulg(T g, cpx<T> x) { return {g * x.re, g * x.im}; }
+template <typename T>
+__device__ __forceinline__ T shfl_up_g(T v, int off, int w) { return __shfl_up(v, off, w); }
+template <typename T>
+__device__ __forceinline__ cpx<T> shfl_up_g(cpx<T> v, int off, int w) { return shfl_up_c(v, off, w); }
+template <typename T>
+__device__ __forceinline__ T shfl_down_g(T v, int off, int w) { return __shfl_down(v, off, w); }
+template <typename T>
+__device__ __forceinline__ cpx<T> shfl_down_g(cpx<T> v, int off, int w) { return shfl_down_c(v, off, w); }
+
+template <typename T, bool IMAG_A>
+struct CnArith {
+  using G = typename std::conditional<IMAG_A, cpx<T>, T>::type;
+  T a;
+  static __device__ __forceinline__ G one() {
+    if constexpr (IMAG_A) return cpx<T>{1, 0};
+    else return (T)1;
+  }
+  // A x
+  __device__ __forceinline__ cpx<T> mulA(cpx<T> x) const {
+    return IMAG_A ? cpx<T>{-a * x.im, a * x.re} : cpx<T>{a * x.re, a * x.im};
+  }
+  // g = A m
+  __device__ __forceinline__ G gain(cpx<T> m) const {
+    if constexpr (IMAG_A) return cpx<T>{-a * m.im, a * m.re};
+    else return a * m.re;
+  }
+  // m x
+  __device__ __forceinline__ cpx<T> mulm(cpx<T> m, cpx<T> x) const {
+    return IMAG_A ? m * x : cpx<T>{m.re * x.re, m.re * x.im};
+  }
+  // rhs = A (p_{i-1} + p_{i+1}) + (1 - 2A) p_i
+  __device__ __forceinline__ cpx<T> rhs(cpx<T> pm, cpx<T> p0, cpx<T> pp) const {
+    const cpx<T> s = {pm.re + pp.re - (T)2 * p0.re, pm.im + pp.im - (T)2 * p0.im};
+    return p0 + mulA(s);
+  }
+};
+
+template <typename T, int N, int NL, int LS, int ES, int P, bool IMAG_A>
+__device__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt, T a) {
   static_assert(64 % P == 0 && NL * P == kThreads, "lanes per line");
   constexpr int S = (N + P - 1) / P;
+  using AR = CnArith<T, IMAG_A>;
+  using GT = typename AR::G;
+  const AR ar{a};
   const int tid = threadIdx.x;
   const int l = tid / P, q = tid % P;
   const int lo = q * S;
   cpx<T>* line = buf + l * LS;
-  cpx<T> r[S], m[S];
+  cpx<T> r[S];
+  GT g[S];
   const cpx<T> zero = {0, 0};
   // chunk, its left/right neighbours and the chunk's factors, read once (indices are
   // clamped into the line so every read is unconditional; out-of-line values -> 0)
@@ -251,43 +302,44 @@ __device__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt, cpx<T> A, cpx<T> B
   const cpx<T> pr = (lo + S < N) ? tr : zero;
 #pragma unroll
   for (int e = 0; e < S; ++e) {
-    const int i = lo + e;
-    const int ic = min(i, N - 1);
-    const cpx<T> tv = line[cpad<S>(ic) * ES];
-    const cpx<T> tm = mt[cpad<S>(ic)];
-    r[e] = (i < N) ? tv : zero;
-    m[e] = (i < N) ? tm : zero;
+    const int ic = min(lo + e, N - 1);
+    r[e] = line[cpad<S>(ic) * ES];
   }
-  // right-hand side of the explicit half (in place: r[e] becomes rhs_e)
+  // r <- m * rhs (0 outside the interior rows), g = A m (0 on the boundary rows)
   {
     cpx<T> prev = pl;
 #pragma unroll
     for (int e = 0; e < S; ++e) {
       const int i = lo + e;
+      const cpx<T> tm = mt[cpad<S>(min(i, N - 1))];
+      const cpx<T> m = (i < N) ? tm : zero;
       const cpx<T> cur = r[e];
       const cpx<T> next = (e + 1 < S) ? r[e + 1] : pr;
-      r[e] = (i >= 1 && i <= N - 2) ? A * (prev + next) + B * cur : zero;
+      const cpx<T> rh = (i >= 1 && i <= N - 2) ? ar.rhs(prev, cur, next) : zero;
       prev = cur;
+      r[e] = ar.mulm(m, rh);
+      g[e] = ar.gain(m);
     }
   }
-  // forward recurrence: local affine map (G, D): d_out = G d_in + D
-  cpx<T> G = {1, 0}, D = {0, 0};
+  // forward recurrence d_i = (m r)_i + g_i d_{i-1}: local affine map (G, D)
+  GT Gn = AR::one();
+  cpx<T> D = {0, 0};
 #pragma unroll
   for (int e = 0; e < S; ++e) {
     if (lo + e < N) {
-      const cpx<T> g = A * m[e];
-      D = m[e] * r[e] + g * D;
-      G = g * G;
+      D = r[e] + mulg(g[e], D);
+      Gn = g[e] * Gn;
     }
   }
   cpx<T> din = {0, 0};
   if constexpr (P > 1) {
 #pragma unroll
     for (int off = 1; off < P; off <<= 1) {
-      const cpx<T> Gp = shfl_up_c(G, off, P), Dp = shfl_up_c(D, off, P);
+      const GT Gp = shfl_up_g(Gn, off, P);
+      const cpx<T> Dp = shfl_up_c(D, off, P);
       if (q >= off) {
-        D = G * Dp + D;
-        G = G * Gp;
+        D = mulg(Gn, Dp) + D;
+        Gn = Gn * Gp;
       }
     }
     din = shfl_up_c(D, 1, P);
@@ -298,30 +350,30 @@ __device__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt, cpx<T> A, cpx<T> B
 #pragma unroll
     for (int e = 0; e < S; ++e) {
       if (lo + e < N) {
-        d = m[e] * r[e] + (A * m[e]) * d;
+        d = r[e] + mulg(g[e], d);
         r[e] = d;
       }
     }
   }
   // backward recurrence: local map u_lo = G u_in + X, u_in = u at the next chunk start
-  G = cpx<T>{1, 0};
+  Gn = AR::one();
   cpx<T> X = {0, 0};
 #pragma unroll
   for (int e = S - 1; e >= 0; --e) {
     if (lo + e < N) {
-      const cpx<T> g = A * m[e];
-      X = r[e] + g * X;
-      G = g * G;
+      X = r[e] + mulg(g[e], X);
+      Gn = g[e] * Gn;
     }
   }
   cpx<T> xin = {0, 0};
   if constexpr (P > 1) {
 #pragma unroll
     for (int off = 1; off < P; off <<= 1) {
-      const cpx<T> Gn = shfl_down_c(G, off, P), Xn = shfl_down_c(X, off, P);
+      const GT Gq = shfl_down_g(Gn, off, P);
+      const cpx<T> Xn = shfl_down_c(X, off, P);
       if (q + off < P) {
-        X = G * Xn + X;
-        G = G * Gn;
+        X = mulg(Gn, Xn) + X;
+        Gn = Gn * Gq;
       }
     }
     xin = shfl_down_c(X, 1, P);
@@ -332,7 +384,7 @@ __device__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt, cpx<T> A, cpx<T> B
 #pragma unroll
     for (int e = S - 1; e >= 0; --e) {
       if (lo + e < N) {
-        x = r[e] + (A * m[e]) * x;
+        x = r[e] + mulg(g[e], x);
         r[e] = x;
       }
     }
@@ -344,6 +396,46 @@ __device__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt, cpx<T> A, cpx<T> B
     if (i < N) line[cpad<S>(i) * ES] = r[e];
   }
   __syncthreads();
+}
+
+// exp(-i x) as (cos x, sin x): Taylor series in Horner form for |x| <= pi/4 (truncation
+// below 1e-9 relative in float, 1e-19 in double), the library sincos beyond.
+__device__ __forceinline__ void sincos_phase(float x, float& s, float& c) {
+  if (fabsf(x) <= 0.78539816339744831f) {
+    const float x2 = x * x;
+    s = x * (1.f + x2 * (-1.f / 6.f + x2 * (1.f / 120.f + x2 * (-1.f / 5040.f + x2 * (1.f / 362880.f)))));
+    c = 1.f + x2 * (-0.5f + x2 * (1.f / 24.f + x2 * (-1.f / 720.f + x2 * (1.f / 40320.f +
+        x2 * (-1.f / 3628800.f)))));
+  } else {
+    sincosf(x, &s, &c);
+  }
+}
+__device__ __forceinline__ void sincos_phase(double x, double& s, double& c) {
+  if (fabs(x) <= 0.78539816339744831) {
+    const double x2 = x * x;
+    // sum_{k=0}^{8} (-1)^k x^(2k+1)/(2k+1)!  and  sum_{k=0}^{9} (-1)^k x^(2k)/(2k)!
+    double ps = 1.0 / 355687428096000.0;            // 1/17!
+    ps = -1.0 / 1307674368000.0 + x2 * ps;           // 1/15!
+    ps = 1.0 / 6227020800.0 + x2 * ps;               // 1/13!
+    ps = -1.0 / 39916800.0 + x2 * ps;                // 1/11!
+    ps = 1.0 / 362880.0 + x2 * ps;                   // 1/9!
+    ps = -1.0 / 5040.0 + x2 * ps;
+    ps = 1.0 / 120.0 + x2 * ps;
+    ps = -1.0 / 6.0 + x2 * ps;
+    s = x * (1.0 + x2 * ps);
+    double pc = -1.0 / 6402373705728000.0;           // 1/18!
+    pc = 1.0 / 20922789888000.0 + x2 * pc;           // 1/16!
+    pc = -1.0 / 87178291200.0 + x2 * pc;             // 1/14!
+    pc = 1.0 / 479001600.0 + x2 * pc;                // 1/12!
+    pc = -1.0 / 3628800.0 + x2 * pc;                 // 1/10!
+    pc = 1.0 / 40320.0 + x2 * pc;
+    pc = -1.0 / 720.0 + x2 * pc;
+    pc = 1.0 / 24.0 + x2 * pc;
+    pc = -0.5 + x2 * pc;
+    c = 1.0 + x2 * pc;
+  } else {
+    sincos(x, &s, &c);
+  }
 }
 
 // Stores the factor table m (N entries) in LDS at the chunk-padded positions used by

@@ -35,22 +35,29 @@ __device__ inline void finalize_block(const FinArgs& a, int mode) {
   double v[11];
 #pragma unroll
   for (int k = 0; k < 11; ++k) v[k] = 0.0;
-  if (mode != FIN_EKZ) {
-    for (int b = tid; b < a.nb_x; b += kThreads) {
-      v[0] += a.p_x[2 * b];
-      v[1] += a.p_x[2 * b + 1];
-    }
-    for (int b = tid; b < a.nb_nl; b += kThreads) {
+  // blocks are summed in a fixed order; 4 slots per iteration keep 4 loads in flight
+  auto acc = [&](const double* p, int nb, int stride, int k0, int nk) {
+    for (int b0 = tid; b0 < nb; b0 += 4 * kThreads) {
+      double t[4][7];
 #pragma unroll
-      for (int k = 0; k < 7; ++k) v[2 + k] += a.p_nl[7 * b + k];
+      for (int u = 0; u < 4; ++u) {
+        const int b = b0 + u * kThreads;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) t[u][k] = (k < nk && b < nb) ? p[(size_t)stride * b + k] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+#pragma unroll
+        for (int k = 0; k < 7; ++k)
+          if (k < nk) v[k0 + k] += t[u][k];
+      }
     }
+  };
+  if (mode != FIN_EKZ) {
+    acc(a.p_x, a.nb_x, 2, 0, 2);
+    acc(a.p_nl, a.nb_nl, 7, 2, 7);
   }
-  if (mode != FIN_OBSERVE || a.geom == 0) {
-    for (int b = tid; b < a.nb_col; b += kThreads) {
-      v[9] += a.p_col[2 * b];
-      v[10] += a.p_col[2 * b + 1];
-    }
-  }
+  if (mode != FIN_OBSERVE || a.geom == 0) acc(a.p_col, a.nb_col, 2, 9, 2);
   block_sum<11>(v, red);
   if (tid != 0) return;
   const double s = *a.scale;

@@ -57,20 +57,12 @@ struct StepScalars {
 // MODE_ADJ: the adjoint sweep of a real-time step (A -> conj(A) = -i Ar).
 enum : int { MODE_IMAG = 0, MODE_REAL = 1, MODE_OBSERVE = 2, MODE_PHI = 3, MODE_ADJ = 4 };
 
-// Coefficients of one CN sweep: A and B = 1 - 2A.
+// CN coupling of one sweep: A = a (imaginary time) or A = i a (real time: a = Ar;
+// adjoint of a real-time sweep: a = -Ar).
+template <int MODE>
+constexpr bool cn_imag_a() { return MODE != MODE_IMAG; }
 template <typename T, int MODE>
-__device__ __forceinline__ void cn_coeffs(double Ar, cpx<T>& A, cpx<T>& B) {
-  if constexpr (MODE == MODE_IMAG) {
-    A = cpx<T>{(T)Ar, 0};
-    B = cpx<T>{(T)(1.0 - 2.0 * Ar), 0};
-  } else if constexpr (MODE == MODE_REAL) {
-    A = cpx<T>{0, (T)Ar};
-    B = cpx<T>{(T)1, (T)(-2.0 * Ar)};
-  } else {
-    A = cpx<T>{0, (T)(-Ar)};
-    B = cpx<T>{(T)1, (T)(2.0 * Ar)};
-  }
-}
+__device__ __forceinline__ T cn_a(double Ar) { return (T)(MODE == MODE_ADJ ? -Ar : Ar); }
 
 // Global-memory phases are statically unrolled over ITERS = ceil(elements/kThreads)
 // so that every load of a thread is issued before the first one is consumed.
@@ -547,7 +539,9 @@ __device__ __forceinline__ void c2r_nl_cnx_body(
         if constexpr (MODE == MODE_IMAG) {
           f = cpx<T>{exp(-th), (T)0};
         } else {
-          f = cpx<T>{cos(th), -sin(th)};
+          T sn, cs;
+          sincos_phase(th, sn, cs);
+          f = cpx<T>{cs, -sn};
         }
         PS[jl * LSP + cpad<SX>(i)] = p * f;
       }
@@ -559,9 +553,7 @@ __device__ __forceinline__ void c2r_nl_cnx_body(
     }
     if constexpr (STEP) {
       __syncthreads();
-      cpx<T> A, B;
-      cn_coeffs<T, MODE>(sc.Ar, A, B);
-      cn_solve_lines<T, N0, TJ, LSP, 1, PX>(PS, MT, A, B);
+      cn_solve_lines<T, N0, TJ, LSP, 1, PX, cn_imag_a<MODE>()>(PS, MT, cn_a<T, MODE>(sc.Ar));
 #pragma unroll
       for (int it = 0; it < IT::N; ++it) {
         const int u = tid + it * kThreads;
@@ -613,9 +605,7 @@ __device__ __forceinline__ void cn_col_body(cpx<T>* __restrict__ psi,
   }
   __syncthreads();
   if constexpr (SOLVE) {
-    cpx<T> A, Bc;
-    cn_coeffs<T, MODE>(Ar, A, Bc);
-    cn_solve_lines<T, N, TC, 1, RS, PC>(B, MT, A, Bc);
+    cn_solve_lines<T, N, TC, 1, RS, PC, cn_imag_a<MODE>()>(B, MT, cn_a<T, MODE>(Ar));
   }
   double sums[2] = {0.0, 0.0};
 #pragma unroll
@@ -691,9 +681,7 @@ __device__ __forceinline__ void adj_x_body(
     if (IT::valid(u)) PS[(u / N0) * LSP + cpad<SX>(u % N0)] = lv[it];
   }
   c2r_tile<T, N0, NP>(Z, W, sa, sb);  // ends with a barrier
-  cpx<T> A, Bc;
-  cn_coeffs<T, MODE_ADJ>(sc.Ar, A, Bc);
-  cn_solve_lines<T, N0, TJ, LSP, 1, PX>(PS, MT, A, Bc);
+  cn_solve_lines<T, N0, TJ, LSP, 1, PX, true>(PS, MT, cn_a<T, MODE_ADJ>(sc.Ar));
   double sums[2] = {0.0, 0.0};
   const T dt = (T)sc.dt;
 #pragma unroll
@@ -707,7 +695,9 @@ __device__ __forceinline__ void adj_x_body(
     const T n = p.re * p.re + p.im * p.im;
     const T th = dt * (vv[it] + (T)sc.gc * n + (T)sc.gdd * phi);
     const cpx<T> la = PS[jl * LSP + cpad<SX>(i)];
-    const cpx<T> mu = la * cpx<T>{cos(th), sin(th)};
+    T sn, cs;
+    sincos_phase(th, sn, cs);
+    const cpx<T> mu = la * cpx<T>{cs, sn};
     const T s = (T)2 * dt * (mu.re * p.im - mu.im * p.re);
     lam[pbase + u] = mu;
     sfield[pbase + u] = s;

@@ -1,0 +1,138 @@
+"""Batched ensemble (one persistent launch per pass and size class) against the FP64
+oracle per instance and against each instance run alone through the single-grid path."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1601_04640_amd import inputs as I
+from tests.gpu_util import (FP32_E_TOL, FP32_PART_TOL, FP32_PSI_TOL, FP64_E_TOL, FP64_PSI_TOL, banner, obs_close,
+                            oparams, rel_l2)
+
+pytestmark = pytest.mark.gpu
+
+
+def small_ensemble(count=12, seed=77):
+    """Mixed XY/XZ instances, sizes from {32, 48, 64, 96} (both classes: 384 added once)."""
+    return I.batched_ensemble(count=count, seed=seed, sizes=(32, 48, 64, 96))
+
+
+def start(w, i):
+    return I.psi0_instance(w, seed=[1606, i])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_matches_oracle_per_instance(prec, gpu_lib):
+    from paper_1601_04640_amd.binding import Batch
+    ens = small_ensemble()
+    ens[3] = dict(ens[3], nx=384)            # one large-class x axis
+    banner("batch vs oracle", prec, len(ens))
+    b = Batch(ens, prec=prec)
+    psis = [start(w, i) for i, w in enumerate(ens)]
+    for i, p in enumerate(psis):
+        b.set_psi(i, p)
+    b.step_imag(12)
+    b.step_real(9)
+    tol = FP64_PSI_TOL if prec == "fp64" else FP32_PSI_TOL
+    energies = b.energy()
+    for i, w in enumerate(ens):
+        p = oparams(w)
+        ref = O.run(O.run(psis[i], p, True, 12), p, False, 9)
+        err = rel_l2(b.get_psi(i), ref)
+        assert err <= tol, (i, w["geom"], w["nx"], err)
+        if prec == "fp64":
+            bad = obs_close(energies[i], O.observables(ref, p), FP64_E_TOL)
+        else:
+            bad = obs_close(energies[i], O.observables(ref, p), FP32_E_TOL, part_tol=FP32_PART_TOL)
+        assert not bad, (i, bad)
+    b.close()
+
+
+SAME_PATH_TOL = 1e-6  # same tile bodies and partial-sum order; allows for contraction choices
+
+
+def test_batch_equals_single_grid_path(gpu_lib):
+    """Same tile bodies, same partial-sum order as running each instance alone."""
+    from paper_1601_04640_amd.binding import Batch, Solver
+    ens = small_ensemble(count=6, seed=78)
+    banner("batch vs single path")
+    b = Batch(ens, prec="fp32")
+    for i, w in enumerate(ens):
+        b.set_psi(i, start(w, i))
+    b.step_imag(10)
+    for i, w in enumerate(ens):
+        s = Solver(w, prec="fp32")
+        s.set_psi(start(w, i))
+        s.step_imag(10)
+        a, c = s.get_psi(), b.get_psi(i)
+        print("instance", i, "bitwise" if np.array_equal(a, c) else f"rel {rel_l2(c, a):.2e}")
+        assert rel_l2(c, a) <= SAME_PATH_TOL, i
+        for ha, hb in zip(s.history(10), b.history(i, 10)):
+            assert abs(ha["energy"] - hb["energy"]) <= SAME_PATH_TOL * abs(ha["energy"])
+        s.close()
+    b.close()
+
+
+def test_full_ensemble_sampled(gpu_lib):
+    """The 192-instance ensemble (sizes 96..512): a few steps; sampled instances against
+    the single-grid path (bitwise) and the oracle (FP32 tolerance)."""
+    from paper_1601_04640_amd.binding import Batch, Solver
+    ens = I.batched_ensemble()
+    banner("full ensemble", len(ens))
+    b = Batch(ens, prec="fp32")
+    for i, w in enumerate(ens):
+        b.set_psi(i, start(w, i))
+    b.step_imag(8)
+    rng = np.random.default_rng(5)
+    for i in rng.choice(len(ens), size=4, replace=False):
+        i = int(i)
+        w = ens[i]
+        s = Solver(w, prec="fp32")
+        s.set_psi(start(w, i))
+        s.step_imag(8)
+        assert rel_l2(b.get_psi(i), s.get_psi()) <= SAME_PATH_TOL, i
+        s.close()
+        ref = O.run(start(w, i), oparams(w), True, 8)
+        assert rel_l2(b.get_psi(i), ref) <= FP32_PSI_TOL
+    b.close()
+
+
+def test_autotuner_keeps_results(tmp_path, gpu_lib):
+    from paper_1601_04640_amd import autotune
+    from paper_1601_04640_amd.binding import Batch
+    ens = small_ensemble(count=8, seed=79)
+    banner("autotune")
+    b = Batch(ens, prec="fp32")
+    for i, w in enumerate(ens):
+        b.set_psi(i, start(w, i))
+    b.step_imag(8)
+    ref = [b.get_psi(i) for i in range(len(ens))]
+    plan = autotune.tune(b, steps=8, cache_path=str(tmp_path / "tune.json"))
+    assert plan and all(v >= 1 for v in plan.values())
+    assert (tmp_path / "tune.json").exists()
+    b.close()
+    # a different launch plan gives bitwise the same results
+    b2 = Batch(ens, prec="fp32")
+    autotune.tune(b2, steps=8, cache_path=str(tmp_path / "tune.json"))  # cached plan
+    for i, w in enumerate(ens):
+        b2.set_psi(i, start(w, i))
+    b2.step_imag(8)
+    for i in range(len(ens)):
+        assert np.array_equal(b2.get_psi(i), ref[i])
+    b2.close()
+
+
+def test_batch_rejects_bad_params(gpu_lib):
+    from paper_1601_04640_amd import binding as B
+    banner("batch errors")
+    ens = small_ensemble(count=3)
+    with pytest.raises(B.GPError) as e:
+        B.Batch([dict(ens[0], nx=80)] + ens[1:])
+    assert e.value.status == B.GP_E_SIZE
+    with pytest.raises(B.GPError) as e:
+        B.Batch([dict(geom="3d", nx=32, ny=32, nz=32)])
+    assert e.value.status == B.GP_E_ARG
+    b = B.Batch(ens)
+    with pytest.raises(B.GPError) as e:
+        b.step_imag(1)
+    assert e.value.status == B.GP_E_STATE
+    b.close()
