@@ -13,7 +13,6 @@ Prints ONE JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -27,19 +26,6 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "grid-point-steps/s (3D dipolar CN step), %HBM peak, FP32 vs FP64 at stated err"
 WORKLOAD = "real3d_128x96x80"
 DOMINANT = "c2r_nl_cnx"
-
-# Kernel sources whose hash identifies the code the PMC counters were taken on.
-KERNEL_SOURCES = ["paper_1601_04640_amd/csrc/gp_device.hpp",
-                  "paper_1601_04640_amd/csrc/gp_kernels.hpp"]
-
-
-def kernel_hash():
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
 
 def pass_bytes(name, npts, nspec, esz):
     """Algorithmic HBM bytes of one launch of a pass: each input read once, each output
@@ -67,6 +53,7 @@ def read_traffic(kernel, workload, prec):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
+    from paper_1601_04640_amd.profile_run import kernel_hash
     if kv.get("kernel_source_hash") != kernel_hash():
         return None
     try:
@@ -148,6 +135,67 @@ def roofline(r, esz):
             "algorithmic_bytes_per_launch": alg}
 
 
+def step_bytes_2d(n0, n1, esz):
+    """Algorithmic HBM bytes of one quasi-2D step (r2c, y convolution, c2r + phase + CN x,
+    CN y), each pass reading its inputs once and writing its outputs once."""
+    npts = n0 * n1
+    nspec = (n0 // 2 + 1) * n1
+    c = 2 * esz
+    return ((npts * c + nspec * c) + (2 * nspec * c + nspec * esz)
+            + (nspec * c + npts * c + npts * esz + npts * c) + 2 * npts * c)
+
+
+def time_batch(steps, tune_steps=16):
+    """The 192-instance quasi-2D ensemble (sizes from {96..512}^2, mixed XY/XZ), FP32 with
+    FP64 reductions, imaginary time: default launch plan, then the autotuned plan; each
+    timed region runs `steps` steps from the same seeded start (graph replay)."""
+    import torch
+    from paper_1601_04640_amd import autotune
+    from paper_1601_04640_amd import inputs as I
+    from paper_1601_04640_amd.binding import Batch
+    ens = I.batched_ensemble()
+    b = Batch(ens, prec="fp32")
+    starts = [I.psi0_instance(w, seed=[1606, i]) for i, w in enumerate(ens)]
+
+    def reset():
+        for i, p in enumerate(starts):
+            b.set_psi(i, p)
+
+    def timed():
+        reset()
+        b.step_imag(8)                       # graph capture outside the timed region
+        reset()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record(b.stream)
+        b.step_imag(steps)
+        ev1.record(b.stream)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, ev0.elapsed_time(ev1)
+
+    wall0, _ = timed()
+    reset()
+    plan = autotune.tune(b, steps=tune_steps)
+    wall1, gpu1 = timed()
+    npts = b.points()
+    byts = sum(step_bytes_2d(w["nx"], w["ny"] if w["geom"] == "2dxy" else w["nz"], 4)
+               for w in ens)
+    energies = [e["energy"] for e in b.energy()]
+    out = {"workload": "imag2d ensemble: 192 XY/XZ instances, sizes {96..512}^2, dt 0.001",
+           "instances": len(ens), "points": npts, "steps": steps,
+           "value": npts * steps / wall1, "unit": "grid-point-steps/s",
+           "ms_per_step": wall1 * 1e3 / steps, "gpu_event_ms_per_step": gpu1 / steps,
+           "ms_per_step_default_plan": wall0 * 1e3 / steps,
+           "step_algorithmic_bytes": byts,
+           "step_achieved_GBs": round(byts / (wall1 / steps) / 1e9, 1),
+           "tuned_plan": plan,
+           "energy_range": [min(energies), max(energies)]}
+    b.close()
+    return out
+
+
 def cpu_baseline(budget_s=15.0):
     """The FP64 oracle (as is) on the same workload: real-time steps of the 128x96x80
     quench from the same seeded start, single thread, until ~budget_s seconds."""
@@ -187,6 +235,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-large", action="store_true", help="skip the 256^3 workload")
     ap.add_argument("--large-steps", type=int, default=100)
+    ap.add_argument("--no-batch", action="store_true", help="skip the 2D ensemble")
+    ap.add_argument("--batch-steps", type=int, default=1000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the "
@@ -232,7 +282,8 @@ def main():
                    "grid": [128, 96, 80], "points": npts},
         "roofline": roof,
         "fp64": {"value": npts * args.steps / r64["graph"]["wall"], "ms_per_step": ms64,
-                 "roofline": roofline(r64, 8)},
+                 "roofline": dict(roofline(r64, 8),
+                                  traffic=read_traffic(DOMINANT, WORKLOAD, "fp64"))},
         "fp32_vs_fp64": {"psi_rel_l2_after_steps": err,
                          "energy_rel": abs(e32 - e64) / abs(e64),
                          "note": "same FP64 ground state, same quench; FP64 path matches "
@@ -251,10 +302,16 @@ def main():
             r = time_gpu("real3d_256", prec, psi5, args.large_steps, 5)
             big[prec] = {"value": r["npts"] * args.large_steps / r["graph"]["wall"],
                          "ms_per_step": r["graph"]["wall"] * 1e3 / args.large_steps,
-                         "roofline": roofline(r, esz)}
+                         "roofline": dict(roofline(r, esz),
+                                          traffic=read_traffic(DOMINANT, "real3d_256", prec))}
             print(f"[bench] real3d_256 {prec}: {big[prec]['ms_per_step']:.4f} ms/step",
                   file=sys.stderr, flush=True)
         line["real3d_256"] = big
+    if not args.no_batch:
+        line["batched_2d"] = time_batch(args.batch_steps)
+        print(f"[bench] batched 2d: {line['batched_2d']['ms_per_step']:.4f} ms/step "
+              f"(default plan {line['batched_2d']['ms_per_step_default_plan']:.4f})",
+              file=sys.stderr, flush=True)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline()

@@ -220,7 +220,7 @@ def dipolar_potential(n, p: Params, kernel=None):
     if kernel is None:
         kernel = dipolar_kernel(p)
     spec = np.fft.rfftn(n)
-    return np.fft.irfftn(spec * kernel, s=n.shape)
+    return np.fft.irfftn(spec * kernel, s=n.shape, axes=tuple(range(n.ndim)))
 
 
 # ------------------------------------------------------------- Crank-Nicolson sweep

@@ -96,6 +96,11 @@ WORKLOADS = {
     "real3d_256": dict(geom="3d", nx=256, ny=256, nz=256, dx=0.1, dy=0.1, dz=0.1,
                        dt=0.0005, gamma=1.0, nu=1.0, lam=3.0, g=50.0, gdd=25.0,
                        R=12.8, imag=False, steps=500),
+    # the large workload's adjoint companion: 128^3 at twice the spacing (same box),
+    # 200 real-time steps, recompute every 20
+    "adjoint3d_128": dict(geom="3d", nx=128, ny=128, nz=128, dx=0.2, dy=0.2, dz=0.2,
+                          dt=0.0005, gamma=1.0, nu=1.0, lam=3.0, g=50.0, gdd=25.0,
+                          R=12.8, imag=False, steps=200, K=20),
 }
 
 
@@ -125,6 +130,29 @@ def psi0_real2dxy_256():
     w = WORKLOADS["real2dxy_256"]
     return gaussian("2dxy", w["nx"], w["ny"], 1, w["dx"], w["dy"], w["dz"],
                     widths=(1.0 / math.sqrt(1.5), 1.0))
+
+
+def trap_perturbation_real2dxy_256(seed=1608):
+    """Smooth random perturbation of the 256^2 trap: amplitude 0.1 (RMS), correlation
+    length 1.0 (added to the harmonic trap by the caller)."""
+    w = WORKLOADS["real2dxy_256"]
+    return 0.1 * smooth_random_field((w["ny"], w["nx"]), (w["dy"], w["dx"]), 1.0, seed)
+
+
+def displaced_target(w, seed, widths):
+    """Normalised Gaussian target whose centre is drawn from U[-0.5, 0.5) per axis."""
+    rng = np.random.default_rng(seed)
+    ndim = 3 if w["geom"] == "3d" else 2
+    center = list(rng.uniform(-0.5, 0.5, size=ndim))
+    return gaussian(w["geom"], w["nx"], w["ny"], w["nz"], w["dx"], w["dy"], w["dz"],
+                    widths=widths, center=center)
+
+
+def psi0_adjoint3d_128(seed=1609):
+    """exp(-(x^2 + y^2 + 3 z^2)/2) with 0.5 % phase noise on the 128^3 grid."""
+    w = WORKLOADS["adjoint3d_128"]
+    return gaussian("3d", w["nx"], w["ny"], w["nz"], w["dx"], w["dy"], w["dz"],
+                    widths=(1.0 / math.sqrt(3.0), 1.0, 1.0), phase_noise=0.005, seed=seed)
 
 
 def batched_ensemble(count=192, seed=1606, sizes=(96, 128, 192, 256, 384, 512)):
