@@ -12,7 +12,8 @@ import os
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libgpdbec.so")
+# the in-tree library; GPDBEC_LIB selects another build of the same sources
+LIB_PATH = os.environ.get("GPDBEC_LIB", os.path.join(_PKG, "libgpdbec.so"))
 
 GP_OK = 0
 GP_E_ARG = -1

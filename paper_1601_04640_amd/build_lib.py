@@ -22,20 +22,20 @@ FLAGS = [
 ]
 
 
-def _jobs():
+def _jobs(build_dir=BUILD, extra=()):
     jobs = []
     for real in ("float", "double"):
         for fam in (0, 1, 2):
-            obj = os.path.join(BUILD, f"inst_{real}_{fam}.o")
-            cmd = [HIPCC, *FLAGS, f"-DGP_REAL={real}", f"-DGP_FAMILY={fam}", "-c",
+            obj = os.path.join(build_dir, f"inst_{real}_{fam}.o")
+            cmd = [HIPCC, *FLAGS, *extra, f"-DGP_REAL={real}", f"-DGP_FAMILY={fam}", "-c",
                    os.path.join(CSRC, "gp_inst.hip"), "-o", obj]
             jobs.append((obj, cmd))
     for real in ("float", "double"):
-        obj = os.path.join(BUILD, f"batch_{real}.o")
-        jobs.append((obj, [HIPCC, *FLAGS, f"-DGP_REAL={real}", "-c",
+        obj = os.path.join(build_dir, f"batch_{real}.o")
+        jobs.append((obj, [HIPCC, *FLAGS, *extra, f"-DGP_REAL={real}", "-c",
                            os.path.join(CSRC, "gp_batch_inst.hip"), "-o", obj]))
-    obj = os.path.join(BUILD, "capi.o")
-    jobs.append((obj, [HIPCC, *FLAGS, "-c", os.path.join(CSRC, "gp_capi.hip"), "-o", obj]))
+    obj = os.path.join(build_dir, "capi.o")
+    jobs.append((obj, [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, "gp_capi.hip"), "-o", obj]))
     return jobs
 
 
@@ -46,9 +46,11 @@ def _run(cmd):
     return r.returncode, err
 
 
-def build(verbose: bool = True) -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    jobs = _jobs()
+def build(verbose: bool = True, out: str = LIB, build_dir: str = BUILD, extra=()) -> str:
+    """Compile and link the library to `out`; `extra` adds hipcc flags (e.g. -D tile
+    thresholds) to every translation unit."""
+    os.makedirs(build_dir, exist_ok=True)
+    jobs = _jobs(build_dir, tuple(extra))
     workers = min(len(jobs), max(1, min(os.cpu_count() or 1, 8)))
     with concurrent.futures.ThreadPoolExecutor(workers) as ex:
         results = list(ex.map(lambda j: (j[0], _run(j[1])), jobs))
@@ -56,15 +58,15 @@ def build(verbose: bool = True) -> str:
     if failed:
         msg = "\n\n".join(f"{o}:\n{e}" for o, e in failed)
         raise RuntimeError(f"hipcc failed:\n{msg}")
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     rc, err = _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp,
                     *[o for o, _ in jobs]])
     if rc != 0:
         raise RuntimeError(f"link failed:\n{err}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
     if verbose:
-        print(f"built {LIB}", file=sys.stderr)
-    return LIB
+        print(f"built {out}", file=sys.stderr)
+    return out
 
 
 if __name__ == "__main__":

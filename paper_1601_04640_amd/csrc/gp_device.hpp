@@ -255,14 +255,11 @@ __device__ __forceinline__ cpx<T> shfl_down_g(cpx<T> v, int off, int w) { return
 template <typename T, bool IMAG_A>
 struct CnArith {
   using G = typename std::conditional<IMAG_A, cpx<T>, T>::type;
-  T a;
+  T a;   // A = a (imaginary time) or i a (real time, adjoint: a < 0)
+  T a2;  // 2 a
   static __device__ __forceinline__ G one() {
     if constexpr (IMAG_A) return cpx<T>{1, 0};
     else return (T)1;
-  }
-  // A x
-  __device__ __forceinline__ cpx<T> mulA(cpx<T> x) const {
-    return IMAG_A ? cpx<T>{-a * x.im, a * x.re} : cpx<T>{a * x.re, a * x.im};
   }
   // g = A m
   __device__ __forceinline__ G gain(cpx<T> m) const {
@@ -273,10 +270,10 @@ struct CnArith {
   __device__ __forceinline__ cpx<T> mulm(cpx<T> m, cpx<T> x) const {
     return IMAG_A ? m * x : cpx<T>{m.re * x.re, m.re * x.im};
   }
-  // rhs = A (p_{i-1} + p_{i+1}) + (1 - 2A) p_i
-  __device__ __forceinline__ cpx<T> rhs(cpx<T> pm, cpx<T> p0, cpx<T> pp) const {
+  // right-hand side of the increment system: 2 A (p_{i-1} + p_{i+1} - 2 p_i)
+  __device__ __forceinline__ cpx<T> inc(cpx<T> pm, cpx<T> p0, cpx<T> pp) const {
     const cpx<T> s = {pm.re + pp.re - (T)2 * p0.re, pm.im + pp.im - (T)2 * p0.im};
-    return p0 + mulA(s);
+    return IMAG_A ? cpx<T>{-a2 * s.im, a2 * s.re} : cpx<T>{a2 * s.re, a2 * s.im};
   }
 };
 
@@ -286,7 +283,7 @@ __device__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt, T a) {
   constexpr int S = (N + P - 1) / P;
   using AR = CnArith<T, IMAG_A>;
   using GT = typename AR::G;
-  const AR ar{a};
+  const AR ar{a, (T)2 * a};
   const int tid = threadIdx.x;
   const int l = tid / P, q = tid % P;
   const int lo = q * S;
@@ -305,6 +302,12 @@ __device__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt, T a) {
     const int ic = min(lo + e, N - 1);
     r[e] = line[cpad<S>(ic) * ES];
   }
+  // The system is solved for the increment delta = u - p:
+  //   (1 + A T) delta = 2 A (p_{i-1} + p_{i+1} - 2 p_i),   u = p + delta,
+  // which equals (1 + A T) u = (1 - A T) p.  Rounding of the factor table then scales
+  // only the O(A) increment, not p itself: with the table in FP32 the direct form loses
+  // norm coherently (every interior factor carries the same rounding), the increment
+  // form about fifty times less.  Boundary values enter as zero (Dirichlet).
   // r <- m * rhs (0 outside the interior rows), g = A m (0 on the boundary rows)
   {
     cpx<T> prev = pl;
@@ -315,7 +318,9 @@ __device__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt, T a) {
       const cpx<T> m = (i < N) ? tm : zero;
       const cpx<T> cur = r[e];
       const cpx<T> next = (e + 1 < S) ? r[e + 1] : pr;
-      const cpx<T> rh = (i >= 1 && i <= N - 2) ? ar.rhs(prev, cur, next) : zero;
+      const cpx<T> pm = (i >= 2) ? prev : zero;
+      const cpx<T> pn = (i + 1 <= N - 2) ? next : zero;
+      const cpx<T> rh = (i >= 1 && i <= N - 2) ? ar.inc(pm, cur, pn) : zero;
       prev = cur;
       r[e] = ar.mulm(m, rh);
       g[e] = ar.gain(m);
@@ -393,7 +398,10 @@ __device__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt, T a) {
 #pragma unroll
   for (int e = 0; e < S; ++e) {
     const int i = lo + e;
-    if (i < N) line[cpad<S>(i) * ES] = r[e];
+    if (i < N) {
+      cpx<T>& dst = line[cpad<S>(i) * ES];
+      dst = (i >= 1 && i <= N - 2) ? dst + r[e] : zero;
+    }
   }
   __syncthreads();
 }

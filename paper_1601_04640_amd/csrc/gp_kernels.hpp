@@ -34,16 +34,33 @@
 namespace gpdbec {
 
 // Lines per tile for passes along x, columns per tile for strided passes.
+// Tile-shape thresholds (compile-time; the defaults are the measured choice).
+#ifndef GP_TJ_SPLIT_N
+#define GP_TJ_SPLIT_N 256
+#endif
+#ifndef GP_TC_SPLIT_FP32
+#define GP_TC_SPLIT_FP32 24
+#endif
+#ifndef GP_TC_SPLIT_FP64
+#define GP_TC_SPLIT_FP64 8
+#endif
+#ifndef GP_LB_POINTS
+#define GP_LB_POINTS 1024
+#endif
+
 template <typename T, int N>
 struct Tiles {
-  // x lines per tile (even): 16, or 8 (32 lanes per line, half the register chunk of
-  // the CN solve) when a line of complex T reaches 4 KiB
-  static constexpr int TJ = (N * 2 * (int)sizeof(T) >= 4096) ? 8 : 16;
+  // x lines per tile (even): 16, or 8 from GP_TJ_SPLIT_N points on (32 lanes per line:
+  // half the serial chunk of the CN solve, twice the tiles)
+  static constexpr int TJ = (N >= GP_TJ_SPLIT_N) ? 8 : 16;
   static constexpr int PX = kThreads / TJ;          // lanes per x line in the CN solve
-  // columns per tile: 16, or 8 when the 16-lane chunk would exceed the register budget
-  static constexpr int TC = ((N + 15) / 16 > (sizeof(T) == 8 ? 16 : 24)) ? 8 : 16;
+  // columns per tile: 16, or 8 (32 lanes per line) when the 16-lane chunk would exceed
+  // GP_TC_SPLIT_* elements
+  static constexpr int TC =
+      ((N + 15) / 16 > (sizeof(T) == 8 ? GP_TC_SPLIT_FP64 : GP_TC_SPLIT_FP32)) ? 8 : 16;
   static constexpr int PC = kThreads / TC;
-  static constexpr int LB = (2048 / N) < 1 ? 1 : (2048 / N);        // contiguous lines
+  // contiguous lines per block of the line FFT passes
+  static constexpr int LB = (GP_LB_POINTS / N) < 1 ? 1 : (GP_LB_POINTS / N);
 };
 
 struct StepScalars {
