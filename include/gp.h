@@ -177,6 +177,14 @@ typedef enum {
 } gp_pass;
 gp_status gp_timing_enable(gp_ctx* ctx, unsigned pass_mask);
 gp_status gp_timing_read(gp_ctx* ctx, double* total_ms, int* launches);
+/* Duration of one pass alone: `reps` (1..4096) back-to-back launches of the pass, on the
+ * current state exactly as inside a real-time step, are captured into a HIP graph and
+ * replayed twice; the second replay is bracketed by one pair of events on the context's
+ * stream and *ms_per_launch = its duration / reps.  Passes: GP_PASS_R2C_X,
+ * GP_PASS_C2R_NL_CNX, GP_PASS_CN_Y, GP_PASS_CN_Z (3D).  Synchronous.  The stored state is
+ * advanced by the repeated partial steps: set psi again before using the context for a
+ * run.  GP_E_ARG for another pass or reps out of range, GP_E_STATE before gp_set_psi. */
+gp_status gp_timing_burst(gp_ctx* ctx, int pass, int reps, double* ms_per_launch);
 
 /* ------------------------------------------------------------ batched ensemble
  * Many independent quasi-2D instances (GP_2D_XY / GP_2D_XZ, any mix) of uneven sizes

@@ -77,6 +77,8 @@ _SIGS = {
     "gp_sync": (ctypes.c_int, [_P]),
     "gp_last_error": (ctypes.c_char_p, []),
     "gp_use_graphs": (ctypes.c_int, [_P, ctypes.c_int]),
+    "gp_timing_burst": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_double)]),
     "gp_batch_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(gp_params), ctypes.c_int,
                                                 ctypes.POINTER(ctypes.c_size_t)]),
     "gp_batch_init": (ctypes.c_int, [ctypes.POINTER(gp_params), ctypes.c_int, _P, ctypes.c_size_t,
@@ -236,6 +238,13 @@ def gp_timing_read(ctx: int) -> dict:
     return {PASS_NAMES[i]: (ms[i], cnt[i]) for i in range(n)}
 
 
+def gp_timing_burst(ctx: int, pass_name: str, reps: int) -> float:
+    ms = ctypes.c_double(0.0)
+    _check(load().gp_timing_burst(_P(ctx), PASS_NAMES.index(pass_name), reps, ctypes.byref(ms)),
+           "gp_timing_burst")
+    return ms.value
+
+
 # ------------------------------------------------------------ convenience class
 class Solver:
     """One context on one device: owns a torch workspace tensor and uses a torch stream.
@@ -338,6 +347,10 @@ class Solver:
 
     def timing_read(self) -> dict:
         return gp_timing_read(self.ctx)
+
+    def timing_burst(self, pass_name: str, reps: int = 64) -> float:
+        """ms per launch of one pass replayed back to back (advances the state)."""
+        return gp_timing_burst(self.ctx, pass_name, reps)
 
 
 def _shape(params):

@@ -385,6 +385,37 @@ struct Passes {
     return finalize(c, fin);
   }
 
+  // One launch of a pass exactly as inside a real-time step (burst timing).
+  static gp_status launch_pass(gp_ctx* c, int pass) {
+    const Layout& L = c->L;
+    const int tcy = tc_of(c->fp64, L.n1);
+    switch (pass) {
+      case GP_PASS_R2C_X:
+        return dev(Launch<T>::r2c_x(L.n0, L.nb_x, c->st, psi(c), &c->sc()->scale, spec(c),
+                                    tw(c, 0), c->at<double>(L.o_px), L.n1, L.n2));
+      case GP_PASS_C2R_NL_CNX:
+        return dev(Launch<T>::c2r_nl_cnx(L.n0, MODE_REAL, L.nb_x, c->st, psi(c),
+                                         c->at<T>(L.o_V), &c->sc()->scale, spec(c), tw(c, 0),
+                                         cn(c, 0, 2), scalars_for(c, 0), c->at<double>(L.o_pnl),
+                                         nullptr, L.n1, L.n2));
+      case GP_PASS_CN_Y:
+        if (c->p.geom == GP_3D)
+          return dev(Launch<T>::cn_col(L.n1, MODE_REAL, false, ((L.n0 + tcy - 1) / tcy) * L.n2,
+                                       c->st, psi(c), cn(c, 1, 2), scalars_for(c, 1).Ar, nullptr,
+                                       L.n0, (size_t)L.n0, (size_t)L.n0 * L.n1));
+        return dev(Launch<T>::cn_col(L.n1, MODE_REAL, true, L.nb_col, c->st, psi(c), cn(c, 1, 2),
+                                     scalars_for(c, 1).Ar, c->at<double>(L.o_pcol), L.n0,
+                                     (size_t)L.n0, (size_t)L.n0 * L.n1));
+      case GP_PASS_CN_Z:
+        if (c->p.geom != GP_3D) return GP_E_ARG;
+        return dev(Launch<T>::cn_col(L.n2, MODE_REAL, true, L.nb_col, c->st, psi(c), cn(c, 2, 2),
+                                     scalars_for(c, 2).Ar, c->at<double>(L.o_pcol), L.n0,
+                                     (size_t)L.n0 * L.n1, (size_t)L.n0));
+      default:
+        return GP_E_ARG;
+    }
+  }
+
   static gp_status observe(gp_ctx* c) {
     const Layout& L = c->L;
     GP_TRY(convolution(c));
@@ -1010,6 +1041,54 @@ gp_status gp_timing_read(gp_ctx* c, double* total_ms, int* launches) {
     total_ms[k] = acc;
     launches[k] = (int)c->tev[k].size();
   }
+  return GP_OK;
+}
+
+gp_status gp_timing_burst(gp_ctx* c, int pass, int reps, double* ms_per_launch) {
+  clear_stale_error();
+  if (!c || !ms_per_launch || reps < 1 || reps > 4096) return GP_E_ARG;
+  if (!c->psi_set) return GP_E_STATE;
+  if (pass != GP_PASS_R2C_X && pass != GP_PASS_C2R_NL_CNX && pass != GP_PASS_CN_Y &&
+      pass != GP_PASS_CN_Z)
+    return GP_E_ARG;
+  if (pass == GP_PASS_CN_Z && c->p.geom != GP_3D) return GP_E_ARG;
+  if (!c->cap_st) GP_HIP(hipStreamCreateWithFlags(&c->cap_st, hipStreamNonBlocking));
+  GP_HIP(hipStreamSynchronize(c->st));
+  const hipStream_t user = c->st;
+  c->st = c->cap_st;
+  hipGraph_t g = nullptr;
+  gp_status s = dev(hipStreamBeginCapture(c->cap_st, hipStreamCaptureModeThreadLocal));
+  if (s == GP_OK) {
+    for (int i = 0; i < reps && s == GP_OK; ++i)
+      s = c->fp64 ? Passes<double>::launch_pass(c, pass) : Passes<float>::launch_pass(c, pass);
+    const gp_status e = dev(hipStreamEndCapture(c->cap_st, &g));
+    if (s == GP_OK) s = e;
+  }
+  c->st = user;
+  if (s != GP_OK) {
+    if (g) hipGraphDestroy(g);
+    return s;
+  }
+  hipGraphExec_t ex = nullptr;
+  s = dev(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+  hipGraphDestroy(g);
+  if (s != GP_OK) return s;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  float ms = 0.f;
+  s = dev(hipEventCreate(&e0));
+  if (s == GP_OK) s = dev(hipEventCreate(&e1));
+  if (s == GP_OK) s = dev(hipGraphLaunch(ex, c->st));  // warm-up
+  if (s == GP_OK) s = dev(hipEventRecord(e0, c->st));
+  if (s == GP_OK) s = dev(hipGraphLaunch(ex, c->st));
+  if (s == GP_OK) s = dev(hipEventRecord(e1, c->st));
+  if (s == GP_OK) s = dev(hipEventSynchronize(e1));
+  if (s == GP_OK) s = dev(hipEventElapsedTime(&ms, e0, e1));
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  hipGraphExecDestroy(ex);
+  if (s != GP_OK) return s;
+  *ms_per_launch = (double)ms / reps;
+  c->ekz_valid = false;  // the stored state was advanced by partial steps
   return GP_OK;
 }
 

@@ -211,3 +211,24 @@ def test_timing_counts_launches(gpu_lib):
     assert t["c2r_nl_cnx"][1] == 10 and t["cn_z"][1] == 10 and t["r2c_x"][1] == 0
     assert t["c2r_nl_cnx"][0] > 0
     s.close()
+
+
+def test_timing_burst(gpu_lib):
+    """gp_timing_burst: positive per-launch time for the supported passes, argument and
+    state errors otherwise; the state stays finite (real-time partial steps)."""
+    from paper_1601_04640_amd import binding as B
+    w = CASES["3d_24x20x16"]
+    banner("timing burst")
+    s = make_solver(w, "fp32")
+    with pytest.raises(B.GPError) as e:
+        s.timing_burst("c2r_nl_cnx", 4)
+    assert e.value.status == B.GP_E_STATE
+    s.set_psi(start_state(w, 109))
+    for name in ("r2c_x", "c2r_nl_cnx", "cn_y", "cn_z"):
+        assert s.timing_burst(name, 16) > 0
+    for name, reps in (("fft_y_fwd", 4), ("c2r_nl_cnx", 0), ("c2r_nl_cnx", 5000)):
+        with pytest.raises(B.GPError) as e:
+            s.timing_burst(name, reps)
+        assert e.value.status == B.GP_E_ARG
+    assert np.all(np.isfinite(s.get_psi()))
+    s.close()
