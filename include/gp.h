@@ -158,10 +158,14 @@ gp_status gp_sync(gp_ctx* ctx);
 gp_status gp_use_graphs(gp_ctx* ctx, int enable);
 
 /* Optional per-pass timing (profiling and benchmarks).  With a non-zero mask, every
- * launch of a selected pass (bit 1 << gp_pass) is bracketed by HIP events recorded on
- * the context's stream; gp_timing_read synchronises, returns the summed durations (ms)
- * and launch counts of every pass since the last enable, and keeps timing on.  Mask 0
- * turns timing off.  Events are host-side objects; no device memory is allocated. */
+ * launch of a selected pass (bit 1 << gp_pass) inside a step is timed with a pair of HIP
+ * events on the context's stream: GP_PASS_C2R_NL_CNX is launched with
+ * hipExtLaunchKernelGGL, whose events take the kernel dispatch's own start and end
+ * timestamps; the other passes are bracketed by event records.  gp_timing_read
+ * synchronises, returns the summed durations (ms) and launch counts of every pass since
+ * the last enable, and keeps timing on.  Mask 0 turns timing off.  Steps run without
+ * graph replay while timing is on.  Events are host-side objects; no device memory is
+ * allocated. */
 typedef enum {
   GP_PASS_R2C_X = 0,      /* |psi|^2, x real-to-complex FFT, x/y kinetic sums      */
   GP_PASS_FFT_Y_FWD = 1,  /* 3D: forward y FFT of the half spectrum                */
@@ -177,6 +181,13 @@ typedef enum {
 } gp_pass;
 gp_status gp_timing_enable(gp_ctx* ctx, unsigned pass_mask);
 gp_status gp_timing_read(gp_ctx* ctx, double* total_ms, int* launches);
+/* In-kernel span of a timed pass: while timing is enabled for GP_PASS_C2R_NL_CNX, every
+ * launch of that pass inside a step also stamps each block's start and end with the
+ * device wall clock, and a one-block kernel adds (last end - first start) to a device
+ * accumulator.  Returns the summed spans (ms) and launch count since gp_timing_enable;
+ * unlike the event pairs it excludes the events' own latency.  Synchronous.  GP_E_ARG for
+ * any other pass. */
+gp_status gp_timing_span(gp_ctx* ctx, int pass, double* total_ms, int* launches);
 /* Duration of one pass alone: `reps` (1..4096) back-to-back launches of the pass, on the
  * current state exactly as inside a real-time step, are captured into a HIP graph and
  * replayed twice; the second replay is bracketed by one pair of events on the context's

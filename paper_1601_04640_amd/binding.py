@@ -77,6 +77,8 @@ _SIGS = {
     "gp_sync": (ctypes.c_int, [_P]),
     "gp_last_error": (ctypes.c_char_p, []),
     "gp_use_graphs": (ctypes.c_int, [_P, ctypes.c_int]),
+    "gp_timing_span": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_int)]),
     "gp_timing_burst": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int,
                                        ctypes.POINTER(ctypes.c_double)]),
     "gp_batch_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(gp_params), ctypes.c_int,
@@ -238,6 +240,14 @@ def gp_timing_read(ctx: int) -> dict:
     return {PASS_NAMES[i]: (ms[i], cnt[i]) for i in range(n)}
 
 
+def gp_timing_span(ctx: int, pass_name: str) -> tuple:
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int(0)
+    _check(load().gp_timing_span(_P(ctx), PASS_NAMES.index(pass_name), ctypes.byref(ms),
+                                 ctypes.byref(n)), "gp_timing_span")
+    return ms.value, n.value
+
+
 def gp_timing_burst(ctx: int, pass_name: str, reps: int) -> float:
     ms = ctypes.c_double(0.0)
     _check(load().gp_timing_burst(_P(ctx), PASS_NAMES.index(pass_name), reps, ctypes.byref(ms)),
@@ -347,6 +357,10 @@ class Solver:
 
     def timing_read(self) -> dict:
         return gp_timing_read(self.ctx)
+
+    def timing_span(self, pass_name: str = "c2r_nl_cnx") -> tuple:
+        """(summed in-kernel spans in ms, launches) since timing_enable."""
+        return gp_timing_span(self.ctx, pass_name)
 
     def timing_burst(self, pass_name: str, reps: int = 64) -> float:
         """ms per launch of one pass replayed back to back (advances the state)."""

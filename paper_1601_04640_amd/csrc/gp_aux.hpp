@@ -212,4 +212,34 @@ __global__ void k_set_scale_one(double* scale) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *scale = 1.0;
 }
 
+// Span of one stamped launch (last block end - first block start, wall-clock ticks),
+// added to acc[0]; acc[1] counts launches.  One block.
+__global__ __launch_bounds__(kThreads) void k_span_reduce(const unsigned long long* stamps,
+                                                          int nb, unsigned long long* acc) {
+  __shared__ unsigned long long lo[kThreads], hi[kThreads];
+  unsigned long long mn = ~0ull, mx = 0ull;
+  for (int b = threadIdx.x; b < nb; b += kThreads) {
+    mn = min(mn, stamps[2 * b]);
+    mx = max(mx, stamps[2 * b + 1]);
+  }
+  lo[threadIdx.x] = mn;
+  hi[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      lo[threadIdx.x] = min(lo[threadIdx.x], lo[threadIdx.x + w]);
+      hi[threadIdx.x] = max(hi[threadIdx.x], hi[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    acc[0] += (hi[0] > lo[0]) ? hi[0] - lo[0] : 0ull;
+    acc[1] += 1ull;
+  }
+}
+
+__global__ void k_clear_u64(unsigned long long* p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0ull;
+}
+
 }  // namespace gpdbec

@@ -45,7 +45,7 @@ struct Layout {
   int nb_x, nb_col, nb_colobs;
   // byte offsets inside the workspace
   size_t o_psi, o_V, o_spec, o_ktab, o_tw[3], o_cn[3][6], o_px, o_pnl, o_pcol, o_padj, o_sfield,
-      o_scalars, o_ring, o_obs, o_io, total;
+      o_scalars, o_ring, o_obs, o_io, o_stamps, total;
 };
 
 struct Scalars {  // device-side scalars (one 256-byte block)
@@ -55,6 +55,7 @@ struct Scalars {  // device-side scalars (one 256-byte block)
   double obs_pad;
   int flags;
   int ring_pos;
+  unsigned long long span[2];  // c2r kernel-span timing: ticks, launches
 };
 
 gp_status validate(const gp_params* p) {
@@ -132,6 +133,7 @@ Layout make_layout(const gp_params* p) {
   L.o_ring = take(sizeof(double) * kRecord * kRingCap);
   L.o_obs = take(sizeof(double) * kRecord);
   L.o_io = take(16 * L.npts);
+  L.o_stamps = take(16 * (size_t)L.nb_x);
   L.total = o;
   return L;
 }
@@ -155,6 +157,7 @@ struct gp_ctx {
   bool psi_set;
   bool ekz_valid;
   double gc;
+  int clock_khz = 0;  // device wall clock (kernel-span timing)
   template <typename X>
   X* at(size_t off) const { return reinterpret_cast<X*>(ws + off); }
   Scalars* sc() const { return at<Scalars>(L.o_scalars); }
@@ -360,10 +363,29 @@ struct Passes {
     const int k = imag ? 0 : 2;  // factor table: imaginary or real time
     GP_TRY(convolution(c));
     const StepScalars sx = scalars_for(c, 0);
-    GP_PASS(c, GP_PASS_C2R_NL_CNX,
-            Launch<T>::c2r_nl_cnx(L.n0, mode, L.nb_x, c->st, psi(c), c->at<T>(L.o_V),
-                                  &c->sc()->scale, spec(c), tw(c, 0), cn(c, 0, k), sx,
-                                  c->at<double>(L.o_pnl), nullptr, L.n1, L.n2));
+    // timed: the launch's own dispatch timestamps fill the event pair (no separate event
+    // packets around it), and every block stamps its start and end
+    const bool span = (c->tmask >> GP_PASS_C2R_NL_CNX) & 1u;
+    unsigned long long* stamps = span ? c->at<unsigned long long>(L.o_stamps) : nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (span) {
+      e0 = take_event(c);
+      e1 = take_event(c);
+      if (!e0 || !e1) {
+        if (e0) c->tpool.push_back(e0);
+        if (e1) c->tpool.push_back(e1);
+        return GP_E_DEVICE;
+      }
+      c->tev[GP_PASS_C2R_NL_CNX].emplace_back(e0, e1);
+    }
+    GP_HIP(Launch<T>::c2r_nl_cnx(L.n0, mode, L.nb_x, c->st, psi(c), c->at<T>(L.o_V),
+                                 &c->sc()->scale, spec(c), tw(c, 0), cn(c, 0, k), sx,
+                                 c->at<double>(L.o_pnl), nullptr, L.n1, L.n2, stamps, e0, e1));
+    if (span) {
+      hipLaunchKernelGGL(k_span_reduce, dim3(1), dim3(kThreads), 0, c->st, stamps, L.nb_x,
+                         c->sc()->span);
+      GP_HIP(hipGetLastError());
+    }
     const int tcy = tc_of(c->fp64, L.n1);
     const double Ay = scalars_for(c, 1).Ar;
     if (c->p.geom == GP_3D) {
@@ -477,6 +499,7 @@ struct Passes {
     Scalars* s = c->sc();
     hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, c->st, &s->scale, &s->one, &s->ekz,
                        &s->flags, &s->ring_pos);
+    hipLaunchKernelGGL(k_clear_u64, dim3(1), dim3(64), 0, c->st, s->span, 2);
     return dev(hipGetLastError());
   }
 
@@ -885,6 +908,11 @@ gp_status gp_init(const gp_params* params, void* dev_workspace, size_t ws_bytes,
   c->psi_set = false;
   c->ekz_valid = false;
   c->gc = contact(c->p);
+  int devid = 0;
+  if (hipGetDevice(&devid) != hipSuccess ||
+      hipDeviceGetAttribute(&c->clock_khz, hipDeviceAttributeWallClockRate, devid) != hipSuccess)
+    c->clock_khz = 0;
+  clear_stale_error();
   const gp_status s = c->fp64 ? Passes<double>::init_tables(c) : Passes<float>::init_tables(c);
   if (s != GP_OK) {
     delete c;
@@ -1024,6 +1052,19 @@ gp_status gp_timing_enable(gp_ctx* c, unsigned mask) {
     c->tev[k].clear();
   }
   c->tmask = mask & ((1u << GP_PASS_COUNT) - 1);
+  hipLaunchKernelGGL(k_clear_u64, dim3(1), dim3(64), 0, c->st, c->sc()->span, 2);
+  return dev(hipGetLastError());
+}
+
+gp_status gp_timing_span(gp_ctx* c, int pass, double* total_ms, int* launches) {
+  if (!c || !total_ms || !launches) return GP_E_ARG;
+  if (pass != GP_PASS_C2R_NL_CNX) return GP_E_ARG;
+  clear_stale_error();
+  unsigned long long acc[2] = {0ull, 0ull};
+  GP_HIP(hipMemcpyAsync(acc, c->sc()->span, sizeof(acc), hipMemcpyDeviceToHost, c->st));
+  GP_HIP(hipStreamSynchronize(c->st));
+  *total_ms = c->clock_khz > 0 ? (double)acc[0] / (double)c->clock_khz : 0.0;
+  *launches = (int)acc[1];
   return GP_OK;
 }
 

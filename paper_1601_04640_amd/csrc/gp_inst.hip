@@ -3,6 +3,8 @@
 //   GP_FAMILY 0: x passes (r2c_x, c2r_nl_cnx)
 //   GP_FAMILY 1: spectrum passes (fft_line, conv_line, conv_col)
 //   GP_FAMILY 2: strided CN sweeps (cn_col) and tile queries
+#include <hip/hip_ext.h>
+
 #include "gp_kernels.hpp"
 #include "gp_launch.hpp"
 
@@ -41,11 +43,19 @@ template <>
 hipError_t Launch<T>::c2r_nl_cnx(int n0, int mode, int blocks, hipStream_t st, cpx<T>* psi,
                                  const T* V, const double* scale, const cpx<T>* spec,
                                  const cpx<T>* tw0, const cpx<T>* cnm, const StepScalars& sc,
-                                 double* part, T* phi_out, int n1, int n2) {
+                                 double* part, T* phi_out, int n1, int n2,
+                                 unsigned long long* stamps, hipEvent_t ev0, hipEvent_t ev1) {
+  // with events: the launch records them from its own dispatch start/end timestamps
 #define CASE_MODE(N, M)                                                                      \
   case M:                                                                                    \
-    GP_LAUNCH((k_c2r_nl_cnx<T, N, M>), blocks, st, psi, V, scale, spec, tw0, cnm, sc, part, \
-              phi_out, n1, n2);                                                              \
+    if (ev0 != nullptr) {                                                                    \
+      hipExtLaunchKernelGGL((k_c2r_nl_cnx<T, N, M>), dim3(blocks), dim3(kThreads), 0, st,    \
+                            ev0, ev1, 0, psi, V, scale, spec, tw0, cnm, sc, part, phi_out,   \
+                            n1, n2, stamps);                                                 \
+    } else {                                                                                 \
+      GP_LAUNCH((k_c2r_nl_cnx<T, N, M>), blocks, st, psi, V, scale, spec, tw0, cnm, sc,     \
+                part, phi_out, n1, n2, stamps);                                              \
+    }                                                                                        \
     break;
   switch (n0) {
 #define X(N)                               \

@@ -826,10 +826,16 @@ __global__ __launch_bounds__(kThreads) void k_c2r_nl_cnx(
     cpx<T>* __restrict__ psi, const T* __restrict__ V, const double* __restrict__ scale,
     const cpx<T>* __restrict__ spec, const cpx<T>* __restrict__ tw0,
     const cpx<T>* __restrict__ cnm, StepScalars sc, double* __restrict__ partials,
-    T* __restrict__ phi_out, int n1, int n2) {
+    T* __restrict__ phi_out, int n1, int n2, unsigned long long* __restrict__ stamps) {
   GP_LDS(T, N0, ((MODE == MODE_IMAG || MODE == MODE_REAL) ? P_C2R_STEP : P_C2R_OBS));
+  // optional wall-clock stamps of the block's start and end (kernel-span timing)
+  if (stamps != nullptr && threadIdx.x == 0) stamps[2 * blockIdx.x] = wall_clock64();
   c2r_nl_cnx_body<T, N0, MODE>(psi, V, scale, spec, tw0, cnm, sc, partials, phi_out, n1, n2,
                                blockIdx.x, lds);
+  if (stamps != nullptr) {
+    __syncthreads();
+    if (threadIdx.x == 0) stamps[2 * blockIdx.x + 1] = wall_clock64();
+  }
 }
 
 template <typename T, int N, int MODE, bool SUMS>

@@ -37,7 +37,9 @@ struct Launch {
   static hipError_t c2r_nl_cnx(int n0, int mode, int blocks, hipStream_t st, cpx<T>* psi,
                                const T* V, const double* scale, const cpx<T>* spec,
                                const cpx<T>* tw0, const cpx<T>* cnm, const StepScalars& sc,
-                               double* part, T* phi_out, int n1, int n2);
+                               double* part, T* phi_out, int n1, int n2,
+                               unsigned long long* stamps = nullptr, hipEvent_t ev0 = nullptr,
+                               hipEvent_t ev1 = nullptr);
   // adjoint x passes
   static hipError_t r2c_real(int n0, int blocks, hipStream_t st, const T* f, cpx<T>* spec,
                              const cpx<T>* tw0, int n1, int n2);
@@ -69,7 +71,8 @@ struct Launch {
   template <> hipError_t Launch<T>::c2r_nl_cnx(int, int, int, hipStream_t, cpx<T>*, const T*, \
                                                const double*, const cpx<T>*, const cpx<T>*,    \
                                                const cpx<T>*, const StepScalars&, double*, T*, \
-                                               int, int);                                      \
+                                               int, int, unsigned long long*, hipEvent_t,      \
+                                               hipEvent_t);                                    \
   template <> hipError_t Launch<T>::r2c_real(int, int, hipStream_t, const T*, cpx<T>*,        \
                                              const cpx<T>*, int, int);                          \
   template <> hipError_t Launch<T>::adj_x(int, int, hipStream_t, cpx<T>*, const cpx<T>*,       \

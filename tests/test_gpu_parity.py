@@ -232,3 +232,27 @@ def test_timing_burst(gpu_lib):
         assert e.value.status == B.GP_E_ARG
     assert np.all(np.isfinite(s.get_psi()))
     s.close()
+
+
+def test_timing_span(gpu_lib):
+    """gp_timing_span: one span per timed c2r launch inside steps, shorter than the event
+    pair around the same launch; nothing recorded when the pass is not timed."""
+    from paper_1601_04640_amd import binding as B
+    w = CASES["3d_40x30x48"]
+    banner("timing span")
+    s = make_solver(w, "fp32")
+    s.set_psi(start_state(w, 110))
+    s.timing_enable(["c2r_nl_cnx"])
+    s.step_real(10)
+    ms, n = s.timing_span("c2r_nl_cnx")
+    ev_ms, ev_n = s.timing_read()["c2r_nl_cnx"]
+    assert n == 10 and ev_n == 10
+    assert 0 < ms <= ev_ms
+    s.timing_enable(["cn_z"])
+    s.step_real(3)
+    assert s.timing_span("c2r_nl_cnx") == (0.0, 0)
+    with pytest.raises(B.GPError) as e:
+        s.timing_span("cn_z")
+    assert e.value.status == B.GP_E_ARG
+    s.timing_enable([])
+    s.close()
