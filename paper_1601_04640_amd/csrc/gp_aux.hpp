@@ -179,6 +179,11 @@ __global__ __launch_bounds__(kThreads) void k_finalize(FinArgs a, int mode) {
   finalize_block(a, mode);
 }
 
+// First stage of the two-stage finalisation (one block per slice).
+__global__ __launch_bounds__(kThreads) void k_prereduce(FinArgs a, int mode) {
+  prereduce_block(a, mode, blockIdx.x);
+}
+
 // dL/dg += cfac * sum(s n), dL/dg_dd += sum(s Phi) over the k_adj_x partials (one block,
 // fixed summation order).
 __global__ __launch_bounds__(kThreads) void k_adj_reduce(const double* __restrict__ partials,

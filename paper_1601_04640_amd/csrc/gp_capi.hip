@@ -22,6 +22,8 @@ using namespace gpdbec;
 namespace {
 
 constexpr int kRingCap = 4096;
+constexpr long long kStageThreshold = 16384;  // partial values above which the finalize
+constexpr long long kStageSlice = 2048;       // runs in two stages, ~kStageSlice per slice
 constexpr int kGraphSteps = 8;  // steps per captured graph
 
 bool size_ok(int n) {
@@ -45,7 +47,7 @@ struct Layout {
   int nb_x, nb_col, nb_colobs;
   // byte offsets inside the workspace
   size_t o_psi, o_V, o_spec, o_ktab, o_tw[3], o_cn[3][6], o_px, o_pnl, o_pcol, o_padj, o_sfield,
-      o_scalars, o_ring, o_obs, o_io, o_stamps, total;
+      o_scalars, o_ring, o_obs, o_io, o_stamps, o_stage, total;
 };
 
 struct Scalars {  // device-side scalars (one 256-byte block)
@@ -134,6 +136,7 @@ Layout make_layout(const gp_params* p) {
   L.o_obs = take(sizeof(double) * kRecord);
   L.o_io = take(16 * L.npts);
   L.o_stamps = take(16 * (size_t)L.nb_x);
+  L.o_stage = take(sizeof(double) * kStageVals * kStageMax);
   L.total = o;
   return L;
 }
@@ -262,6 +265,12 @@ FinArgs fin_args(const gp_ctx* c) {
   a.ring_pos = &s->ring_pos;
   a.ring_cap = kRingCap;
   a.obs = c->at<double>(c->L.o_obs);
+  // many partials: a first stage of up to kStageMax blocks sums slices of ~2K values
+  const long long nvals = 9LL * c->L.nb_x + 2LL * c->L.nb_col;
+  a.stage = c->at<double>(c->L.o_stage);
+  a.nstage = nvals > kStageThreshold
+                 ? (int)std::min<long long>(kStageMax, (nvals + kStageSlice - 1) / kStageSlice)
+                 : 0;
   return a;
 }
 
@@ -341,7 +350,10 @@ struct Passes {
   // FIN_OBSERVE for gp_energy, FIN_EKZ for the pending z-kinetic part)
   static gp_status finalize(gp_ctx* c, int fin_mode) {
     GP_TRY(pass_begin(c, GP_PASS_FINALIZE));
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, c->st, fin_args(c), fin_mode);
+    const FinArgs a = fin_args(c);
+    if (a.nstage > 0)
+      hipLaunchKernelGGL(k_prereduce, dim3(a.nstage), dim3(kThreads), 0, c->st, a, fin_mode);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, c->st, a, fin_mode);
     GP_HIP(hipGetLastError());
     return pass_end(c, GP_PASS_FINALIZE);
   }
@@ -751,6 +763,7 @@ gp_status batch_write_desc(gp_batch* b) {
     d.n0 = L.n0;
     d.n1 = L.n1;
     d.fa = fin_args(c);
+    d.fa.nstage = 0;  // the per-instance finalize blocks read their partials directly
     b->cpl[2 * i] = c->p.g;
     b->cpl[2 * i + 1] = c->p.gdd;
   }

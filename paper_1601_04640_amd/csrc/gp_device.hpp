@@ -200,7 +200,7 @@ struct LdsFFT {
   }
 
   template <bool INV>
-  __device__ static void run(cpx<T>* buf, const cpx<T>* tw) {
+  __device__ __forceinline__ static void run(cpx<T>* buf, const cpx<T>* tw) {
     stage<0, INV>(buf, tw);
   }
 };
@@ -278,7 +278,7 @@ struct CnArith {
 };
 
 template <typename T, int N, int NL, int LS, int ES, int P, bool IMAG_A>
-__device__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt, T a) {
+__device__ __forceinline__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt, T a) {
   static_assert(64 % P == 0 && NL * P == kThreads, "lanes per line");
   constexpr int S = (N + P - 1) / P;
   using AR = CnArith<T, IMAG_A>;
@@ -408,14 +408,27 @@ __device__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt, T a) {
 
 // exp(-i x) as (cos x, sin x): Taylor series in Horner form for |x| <= pi/4 (truncation
 // below 1e-9 relative in float, 1e-19 in double), the library sincos beyond.
+__device__ __forceinline__ void sincos_taylor(float x, float& s, float& c) {
+  const float x2 = x * x;
+  s = x * (1.f + x2 * (-1.f / 6.f + x2 * (1.f / 120.f + x2 * (-1.f / 5040.f + x2 * (1.f / 362880.f)))));
+  c = 1.f + x2 * (-0.5f + x2 * (1.f / 24.f + x2 * (-1.f / 720.f + x2 * (1.f / 40320.f +
+      x2 * (-1.f / 3628800.f)))));
+}
+// Beyond pi/4 the argument is reduced modulo pi/2 in double precision, x = k pi/2 + r,
+// |r| <= pi/4 (the error of pi/2 rounded to double, 6e-17, times k stays far below
+// float resolution for any |x| < 1e7), and the quadrant k mod 4 rotates (sin r, cos r).
 __device__ __forceinline__ void sincos_phase(float x, float& s, float& c) {
   if (fabsf(x) <= 0.78539816339744831f) {
-    const float x2 = x * x;
-    s = x * (1.f + x2 * (-1.f / 6.f + x2 * (1.f / 120.f + x2 * (-1.f / 5040.f + x2 * (1.f / 362880.f)))));
-    c = 1.f + x2 * (-0.5f + x2 * (1.f / 24.f + x2 * (-1.f / 720.f + x2 * (1.f / 40320.f +
-        x2 * (-1.f / 3628800.f)))));
+    sincos_taylor(x, s, c);
   } else {
-    sincosf(x, &s, &c);
+    const double xd = (double)x;
+    const double k = rint(xd * 0.63661977236758134);          // 2/pi
+    const float r = (float)fma(-k, 1.5707963267948966, xd);    // pi/2
+    float sr, cr;
+    sincos_taylor(r, sr, cr);
+    const int q = (int)(long long)k & 3;
+    s = (q == 0) ? sr : (q == 1) ? cr : (q == 2) ? -sr : -cr;
+    c = (q == 0) ? cr : (q == 1) ? -sr : (q == 2) ? -cr : sr;
   }
 }
 __device__ __forceinline__ void sincos_phase(double x, double& s, double& c) {

@@ -26,24 +26,28 @@ struct FinArgs {
   int* ring_pos;
   int ring_cap;
   double* obs;         // FIN_OBSERVE output record
+  double* stage;       // two-stage reduction: kStageVals doubles per pre-reduced slice
+  int nstage;          // slices (0: the finalize block reads the partials directly)
 };
 
-// All threads of one block must call this.
-__device__ inline void finalize_block(const FinArgs& a, int mode) {
-  __shared__ double red[11 * kWaves];
+constexpr int kStageVals = 11;   // totals carried per slice (the v[] of finalize_block)
+constexpr int kStageMax = 64;    // slices of the two-stage reduction
+
+// Sums the partial arrays a block reads, blocks [lo, hi) of each, into v[11] (per
+// thread; fixed order).  4 slots per iteration keep 4 loads in flight.
+__device__ inline void fin_gather(const FinArgs& a, int mode, int slice, int nslice,
+                                  double (&v)[11]) {
   const int tid = threadIdx.x;
-  double v[11];
-#pragma unroll
-  for (int k = 0; k < 11; ++k) v[k] = 0.0;
-  // blocks are summed in a fixed order; 4 slots per iteration keep 4 loads in flight
   auto acc = [&](const double* p, int nb, int stride, int k0, int nk) {
-    for (int b0 = tid; b0 < nb; b0 += 4 * kThreads) {
+    const int lo = (int)((long long)nb * slice / nslice);
+    const int hi = (int)((long long)nb * (slice + 1) / nslice);
+    for (int b0 = lo + tid; b0 < hi; b0 += 4 * kThreads) {
       double t[4][7];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int b = b0 + u * kThreads;
 #pragma unroll
-        for (int k = 0; k < 7; ++k) t[u][k] = (k < nk && b < nb) ? p[(size_t)stride * b + k] : 0.0;
+        for (int k = 0; k < 7; ++k) t[u][k] = (k < nk && b < hi) ? p[(size_t)stride * b + k] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -58,6 +62,39 @@ __device__ inline void finalize_block(const FinArgs& a, int mode) {
     acc(a.p_nl, a.nb_nl, 7, 2, 7);
   }
   if (mode != FIN_OBSERVE || a.geom == 0) acc(a.p_col, a.nb_col, 2, 9, 2);
+}
+
+// First stage of the two-stage reduction: block g writes the totals of slice g.
+__device__ inline void prereduce_block(const FinArgs& a, int mode, int g) {
+  __shared__ double red[11 * kWaves];
+  double v[11];
+#pragma unroll
+  for (int k = 0; k < 11; ++k) v[k] = 0.0;
+  fin_gather(a, mode, g, a.nstage, v);
+  block_sum<11>(v, red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < kStageVals; ++k) a.stage[g * kStageVals + k] = v[k];
+  }
+}
+
+// All threads of one block must call this.
+__device__ inline void finalize_block(const FinArgs& a, int mode) {
+  __shared__ double red[11 * kWaves];
+  const int tid = threadIdx.x;
+  double v[11];
+#pragma unroll
+  for (int k = 0; k < 11; ++k) v[k] = 0.0;
+  if (a.nstage > 0) {
+    // one pre-reduced slice per thread (nstage <= kStageMax < kThreads), then the
+    // fixed-order block sum
+    if (tid < a.nstage) {
+#pragma unroll
+      for (int k = 0; k < kStageVals; ++k) v[k] = a.stage[tid * kStageVals + k];
+    }
+  } else {
+    fin_gather(a, mode, 0, 1, v);
+  }
   block_sum<11>(v, red);
   if (tid != 0) return;
   const double s = *a.scale;

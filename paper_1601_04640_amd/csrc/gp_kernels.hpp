@@ -63,6 +63,16 @@ struct Tiles {
   static constexpr int LB = (GP_LB_POINTS / N) < 1 ? 1 : (GP_LB_POINTS / N);
 };
 
+// Workgroups are dispatched to the 8 XCDs round-robin (block b runs on XCD b % 8), and
+// each XCD has its own L2.  The x passes renumber their tiles so that every XCD works
+// through one contiguous range: neighbouring x tiles, which read the two halves of the
+// same 128-byte spectrum lines when a tile holds 8 lines of FP32, then share an L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int x = b % kXcds, i = b / kXcds, per = nb / kXcds, rem = nb % kXcds;
+  return x * per + (x < rem ? x : rem) + i;
+}
+
 struct StepScalars {
   double dt;        // time step
   double gc;        // contact coupling (2D: includes 1/(sqrt(2 pi) d))
@@ -786,7 +796,8 @@ __global__ __launch_bounds__(kThreads) void k_r2c_x(const cpx<T>* __restrict__ p
                                                     const cpx<T>* __restrict__ tw0,
                                                     double* __restrict__ partials, int n1, int n2) {
   GP_LDS(T, N0, P_R2C);
-  r2c_x_body<T, N0>(psi, scale, spec, tw0, partials, n1, n2, blockIdx.x, lds);
+  r2c_x_body<T, N0>(psi, scale, spec, tw0, partials, n1, n2, xcd_tile(blockIdx.x, gridDim.x),
+                    lds);
 }
 
 template <typename T, int N0>
@@ -795,7 +806,7 @@ __global__ __launch_bounds__(kThreads) void k_r2c_real(const T* __restrict__ f,
                                                        const cpx<T>* __restrict__ tw0, int n1,
                                                        int n2) {
   GP_LDS(T, N0, P_R2C_REAL);
-  r2c_real_body<T, N0>(f, spec, tw0, n1, n2, blockIdx.x, lds);
+  r2c_real_body<T, N0>(f, spec, tw0, n1, n2, xcd_tile(blockIdx.x, gridDim.x), lds);
 }
 
 template <typename T, int N, bool INV>
@@ -831,7 +842,7 @@ __global__ __launch_bounds__(kThreads) void k_c2r_nl_cnx(
   // optional wall-clock stamps of the block's start and end (kernel-span timing)
   if (stamps != nullptr && threadIdx.x == 0) stamps[2 * blockIdx.x] = wall_clock64();
   c2r_nl_cnx_body<T, N0, MODE>(psi, V, scale, spec, tw0, cnm, sc, partials, phi_out, n1, n2,
-                               blockIdx.x, lds);
+                               xcd_tile(blockIdx.x, gridDim.x), lds);
   if (stamps != nullptr) {
     __syncthreads();
     if (threadIdx.x == 0) stamps[2 * blockIdx.x + 1] = wall_clock64();
@@ -855,7 +866,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_x(
     double* __restrict__ gradV, double* __restrict__ partials, int n1, int n2) {
   GP_LDS(T, N0, P_ADJ_X);
   adj_x_body<T, N0>(lam, psin, V, spec, tw0, cnm, sc, sfield, gradV, partials, n1, n2,
-                    blockIdx.x, lds);
+                    xcd_tile(blockIdx.x, gridDim.x), lds);
 }
 
 template <typename T, int N0>
@@ -866,7 +877,8 @@ __global__ __launch_bounds__(kThreads) void k_adj_fin(cpx<T>* __restrict__ lam,
                                                       const cpx<T>* __restrict__ tw0,
                                                       StepScalars sc, int n1, int n2) {
   GP_LDS(T, N0, P_ADJ_FIN);
-  adj_fin_body<T, N0>(lam, psin, sfield, spec, tw0, sc, n1, n2, blockIdx.x, lds);
+  adj_fin_body<T, N0>(lam, psin, sfield, spec, tw0, sc, n1, n2, xcd_tile(blockIdx.x, gridDim.x),
+                      lds);
 }
 
 #undef GP_LDS
