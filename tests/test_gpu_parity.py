@@ -203,6 +203,30 @@ def test_graph_replay_equals_direct_launches(prec, gpu_lib):
     assert runs[0][1] == runs[1][1]
 
 
+@pytest.mark.parametrize("name", ["3d_24x20x16", "2dxy_48x40"])
+def test_imag_then_real_graphs_match_oracle(name, gpu_lib):
+    """Imaginary-time graphs leave a pending renormalisation factor (lazy scale); the
+    real-time steps and graph replays that follow must apply it.  FP64 against the
+    oracle, per-step records included."""
+    w = CASES[name]
+    banner("imag then real graphs", name)
+    p = oparams(w)
+    psi0 = start_state(w, 111)
+    s = make_solver(w, "fp64")
+    s.set_psi(psi0)
+    s.step_imag(8)
+    s.step_real(25)                           # 1 direct + 3 graph replays
+    got = s.get_psi()
+    recs = s.history(33)
+    mid, hist_i = O.run(psi0, p, True, 8, record=True)
+    ref, hist_r = O.run(mid, p, False, 25, record=True)
+    assert rel_l2(got, ref) <= FP64_PSI_TOL
+    for k, (g_, r_) in enumerate(zip(recs, hist_i + hist_r)):
+        bad = obs_close(g_, r_, FP64_E_TOL * 10)
+        assert not bad, (k, bad)
+    s.close()
+
+
 def test_timing_counts_launches(gpu_lib):
     w = CASES["3d_24x20x16"]
     banner("timing")
