@@ -277,67 +277,94 @@ struct CnArith {
   }
 };
 
+// Component-wise select of two complex values (a select of whole structs can be lowered
+// through scratch memory).
+template <typename T>
+__device__ __forceinline__ cpx<T> csel(bool c, cpx<T> a, cpx<T> b) {
+  return cpx<T>{c ? a.re : b.re, c ? a.im : b.im};
+}
+
 template <typename T, int N, int NL, int LS, int ES, int P, bool IMAG_A>
 __device__ __forceinline__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt, T a) {
   static_assert(64 % P == 0 && NL * P == kThreads, "lanes per line");
   constexpr int S = (N + P - 1) / P;
+  constexpr bool FULL = (N % P == 0);  // every lane's chunk lies inside the line
   using AR = CnArith<T, IMAG_A>;
   using GT = typename AR::G;
   const AR ar{a, (T)2 * a};
   const int tid = threadIdx.x;
   const int l = tid / P, q = tid % P;
-  const int lo = q * S;
+  const int lo = q * S;          // first element of the lane's chunk
+  const int base = lo + q;       // its chunk-padded position: cpad<S>(lo + e) = base + e
   cpx<T>* line = buf + l * LS;
   cpx<T> r[S];
   GT g[S];
   const cpx<T> zero = {0, 0};
-  // chunk, its left/right neighbours and the chunk's factors, read once (indices are
-  // clamped into the line so every read is unconditional; out-of-line values -> 0)
-  const cpx<T> tl = line[cpad<S>(min(max(lo - 1, 0), N - 1)) * ES];
-  const cpx<T> tr = line[cpad<S>(min(lo + S, N - 1)) * ES];
-  const cpx<T> pl = (lo >= 1 && lo - 1 < N) ? tl : zero;
-  const cpx<T> pr = (lo + S < N) ? tr : zero;
-#pragma unroll
-  for (int e = 0; e < S; ++e) {
-    const int ic = min(lo + e, N - 1);
-    r[e] = line[cpad<S>(ic) * ES];
-  }
   // The system is solved for the increment delta = u - p:
   //   (1 + A T) delta = 2 A (p_{i-1} + p_{i+1} - 2 p_i),   u = p + delta,
   // which equals (1 + A T) u = (1 - A T) p.  Rounding of the factor table then scales
   // only the O(A) increment, not p itself: with the table in FP32 the direct form loses
   // norm coherently (every interior factor carries the same rounding), the increment
-  // form about fifty times less.  Boundary values enter as zero (Dirichlet).
-  // r <- m * rhs (0 outside the interior rows), g = A m (0 on the boundary rows)
+  // form about fifty times less.  Boundary values enter as zero (Dirichlet); the table
+  // holds m = 0 on the two boundary rows, so those rows get delta = 0 and g = 0, and
+  // elements past the line end (chunks that overhang it) are zero as well, which makes
+  // the recurrences below need no per-element guards.
+  // Neighbours of the chunk (interior elements only) and the chunk, read once with
+  // indices clamped into the line.
+  // (lanes past the end of a line that the chunks overhang have lo >= N: neither
+  // neighbour is an interior element, and every index below is clamped into the line)
+  constexpr int last = (N - 1) + (N - 1) / S;  // padded position of element N - 1
+  const bool has_l = lo - 1 >= 1 && lo - 1 <= N - 2;
+  const bool has_r = lo + S <= N - 2;
+  const cpx<T> tl = line[(has_l ? base - 2 : 0) * ES];
+  const cpx<T> tr = line[(has_r ? base + S + 1 : 0) * ES];
+  const cpx<T> pl = csel(has_l, tl, zero);
+  const cpx<T> pr = csel(has_r, tr, zero);
+#pragma unroll
+  for (int e = 0; e < S; ++e) {
+    if constexpr (FULL) {
+      r[e] = line[(base + e) * ES];
+    } else {
+      const int i = lo + e;
+      const cpx<T> v = line[(i < N ? base + e : last) * ES];
+      r[e] = csel(i < N - 1, v, zero);
+    }
+  }
+  r[0] = csel(q == 0, zero, r[0]);                // element 0
+  if constexpr (FULL) {
+    r[S - 1] = csel(q == P - 1, zero, r[S - 1]);  // element N - 1
+  }
+  // r <- m * rhs, g = A m (m = 0 on the boundary rows and past the line end)
   {
     cpx<T> prev = pl;
 #pragma unroll
     for (int e = 0; e < S; ++e) {
-      const int i = lo + e;
-      const cpx<T> tm = mt[cpad<S>(min(i, N - 1))];
-      const cpx<T> m = (i < N) ? tm : zero;
+      cpx<T> m;
+      if constexpr (FULL) {
+        m = mt[base + e];
+      } else {
+        const cpx<T> f = mt[lo + e < N ? base + e : last];
+        m = csel(lo + e < N, f, zero);
+      }
       const cpx<T> cur = r[e];
       const cpx<T> next = (e + 1 < S) ? r[e + 1] : pr;
-      const cpx<T> pm = (i >= 2) ? prev : zero;
-      const cpx<T> pn = (i + 1 <= N - 2) ? next : zero;
-      const cpx<T> rh = (i >= 1 && i <= N - 2) ? ar.inc(pm, cur, pn) : zero;
-      prev = cur;
-      r[e] = ar.mulm(m, rh);
+      r[e] = ar.mulm(m, ar.inc(prev, cur, next));
       g[e] = ar.gain(m);
+      prev = cur;
     }
   }
-  // forward recurrence d_i = (m r)_i + g_i d_{i-1}: local affine map (G, D)
-  GT Gn = AR::one();
+  // forward recurrence d_i = r_i + g_i d_{i-1}: the chunk's affine map (Gc, D), an
+  // inclusive scan of the maps across the P lanes, then the chunk from its true input
+  GT Gc = AR::one();
   cpx<T> D = {0, 0};
 #pragma unroll
   for (int e = 0; e < S; ++e) {
-    if (lo + e < N) {
-      D = r[e] + mulg(g[e], D);
-      Gn = g[e] * Gn;
-    }
+    D = r[e] + mulg(g[e], D);
+    Gc = g[e] * Gc;
   }
   cpx<T> din = {0, 0};
   if constexpr (P > 1) {
+    GT Gn = Gc;
 #pragma unroll
     for (int off = 1; off < P; off <<= 1) {
       const GT Gp = shfl_up_g(Gn, off, P);
@@ -348,30 +375,24 @@ __device__ __forceinline__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt, T 
       }
     }
     din = shfl_up_c(D, 1, P);
-    if (q == 0) din = cpx<T>{0, 0};
+    din = csel(q == 0, zero, din);
   }
   {
     cpx<T> d = din;
 #pragma unroll
     for (int e = 0; e < S; ++e) {
-      if (lo + e < N) {
-        d = r[e] + mulg(g[e], d);
-        r[e] = d;
-      }
+      d = r[e] + mulg(g[e], d);
+      r[e] = d;
     }
   }
-  // backward recurrence: local map u_lo = G u_in + X, u_in = u at the next chunk start
-  Gn = AR::one();
+  // backward recurrence u_i = d_i + g_i u_{i+1}: the chunk's map is (Gc, X) with the same
+  // product of factors
   cpx<T> X = {0, 0};
 #pragma unroll
-  for (int e = S - 1; e >= 0; --e) {
-    if (lo + e < N) {
-      X = r[e] + mulg(g[e], X);
-      Gn = g[e] * Gn;
-    }
-  }
+  for (int e = S - 1; e >= 0; --e) X = r[e] + mulg(g[e], X);
   cpx<T> xin = {0, 0};
   if constexpr (P > 1) {
+    GT Gn = Gc;
 #pragma unroll
     for (int off = 1; off < P; off <<= 1) {
       const GT Gq = shfl_down_g(Gn, off, P);
@@ -382,25 +403,30 @@ __device__ __forceinline__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt, T 
       }
     }
     xin = shfl_down_c(X, 1, P);
-    if (q == P - 1) xin = cpx<T>{0, 0};
+    xin = csel(q == P - 1, zero, xin);
   }
   {
     cpx<T> x = xin;
 #pragma unroll
     for (int e = S - 1; e >= 0; --e) {
-      if (lo + e < N) {
-        x = r[e] + mulg(g[e], x);
-        r[e] = x;
-      }
+      x = r[e] + mulg(g[e], x);
+      r[e] = x;
     }
   }
   __syncthreads();  // every lane has read its neighbours
+  // u = p + delta on the interior, 0 on the boundary rows
 #pragma unroll
   for (int e = 0; e < S; ++e) {
     const int i = lo + e;
-    if (i < N) {
-      cpx<T>& dst = line[cpad<S>(i) * ES];
-      dst = (i >= 1 && i <= N - 2) ? dst + r[e] : zero;
+    if constexpr (FULL) {
+      cpx<T>& dst = line[(base + e) * ES];
+      cpx<T> u = dst + r[e];
+      if (e == 0) u = csel(q == 0, zero, u);
+      if (e == S - 1) u = csel(q == P - 1, zero, u);
+      dst = u;
+    } else if (i < N) {
+      cpx<T>& dst = line[(base + e) * ES];
+      dst = csel(i >= 1 && i <= N - 2, dst + r[e], zero);
     }
   }
   __syncthreads();

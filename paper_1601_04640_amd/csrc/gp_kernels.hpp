@@ -111,6 +111,20 @@ struct Carve {
   }
 };
 
+// Element `idx` of an array whose byte offset from `base` fits in 32 bits (every
+// workspace array does: at most 512^3 complex doubles).  The 64-bit tile base is
+// uniform, the 32-bit offset per lane, which maps onto scalar-base + vector-offset
+// addressing instead of a 64-bit address computation per access.
+template <typename X>
+__device__ __forceinline__ X& at32(X* base, unsigned idx) {
+  return *reinterpret_cast<X*>(reinterpret_cast<char*>(base) + idx * (unsigned)sizeof(X));
+}
+template <typename X>
+__device__ __forceinline__ const X& at32(const X* base, unsigned idx) {
+  return *reinterpret_cast<const X*>(reinterpret_cast<const char*>(base) +
+                                     idx * (unsigned)sizeof(X));
+}
+
 // Geometry of an x-line tile (TJ lines of N0 points; NP packed complex pairs).
 template <typename T, int N0>
 struct XT {
@@ -186,10 +200,9 @@ __device__ __forceinline__ void r2c_x_body(const cpx<T>* __restrict__ psi,
     // clamped indices keep every load in bounds; at the last point of an axis the
     // neighbour is the point itself (zero difference), outside the grid all are zero
     const int jc = min(j, n1 - 1);
-    const cpx<T>* line = plane + (size_t)jc * N0;
-    const cpx<T> l0 = line[i];
-    const cpx<T> l1 = line[min(i + 1, N0 - 1)];
-    const cpx<T> l2 = plane[(size_t)min(jc + 1, n1 - 1) * N0 + i];
+    const cpx<T> l0 = at32(plane, (unsigned)(jc * N0 + i));
+    const cpx<T> l1 = at32(plane, (unsigned)(jc * N0 + min(i + 1, N0 - 1)));
+    const cpx<T> l2 = at32(plane, (unsigned)(min(jc + 1, n1 - 1) * N0 + i));
     a[it] = in ? l0 : z;
     bx[it] = in ? l1 : z;
     by[it] = in ? l2 : z;
@@ -224,7 +237,9 @@ __device__ __forceinline__ void r2c_x_body(const cpx<T>* __restrict__ psi,
     const cpx<T> zk = Z[p * LSZ + kx];
     const cpx<T> zm = Z[p * LSZ + ((N0 - kx) % N0)];
     const T hf = (T)0.5;
-    cpx<T>* o = spec + ((size_t)kx * n2 + k2) * n1 + j;
+    cpx<T>* sp = spec + (size_t)k2 * n1 + j0;  // uniform; + kx n2 n1 + 2p per lane
+    const unsigned off = (unsigned)(kx * n2 * n1 + 2 * p);
+    cpx<T>* o = &at32(sp, off);
     o[0] = cpx<T>{hf * (zk.re + zm.re), hf * (zk.im - zm.im)};
     o[1] = cpx<T>{hf * (zk.im + zm.im), hf * (zm.re - zk.re)};  // n1 even: line j+1 exists
   }
@@ -256,7 +271,7 @@ __device__ __forceinline__ void r2c_real_body(const T* __restrict__ f, cpx<T>* _
 #pragma unroll
   for (int it = 0; it < IT::N; ++it) {
     const int u = tid + it * kThreads;
-    fv[it] = (IT::valid(u) && j0 + u / N0 < n1) ? f[pbase + u] : (T)0;
+    fv[it] = (IT::valid(u) && j0 + u / N0 < n1) ? at32(f + pbase, (unsigned)u) : (T)0;
   }
   for (int i = tid; i < N0; i += kThreads) W[i] = tw0[i];
 #pragma unroll
@@ -280,7 +295,9 @@ __device__ __forceinline__ void r2c_real_body(const T* __restrict__ f, cpx<T>* _
     const cpx<T> zk = Z[p * LSZ + kx];
     const cpx<T> zm = Z[p * LSZ + ((N0 - kx) % N0)];
     const T hf = (T)0.5;
-    cpx<T>* o = spec + ((size_t)kx * n2 + k2) * n1 + j;
+    cpx<T>* sp = spec + (size_t)k2 * n1 + j0;  // uniform; + kx n2 n1 + 2p per lane
+    const unsigned off = (unsigned)(kx * n2 * n1 + 2 * p);
+    cpx<T>* o = &at32(sp, off);
     o[0] = cpx<T>{hf * (zk.re + zm.re), hf * (zk.im - zm.im)};
     o[1] = cpx<T>{hf * (zk.im + zm.im), hf * (zm.re - zk.re)};
   }
@@ -296,7 +313,7 @@ __device__ __forceinline__ void load_lines(cpx<T>* B, const cpx<T>* __restrict__
   for (int it = 0; it < IT::N; ++it) {
     const int u = threadIdx.x + it * kThreads;
     const int l = u / N, i = u % N;
-    v[it] = (IT::valid(u) && l0 + l < nlines) ? data[(size_t)(l0 + l) * N + i] : cpx<T>{0, 0};
+    v[it] = (IT::valid(u) && l0 + l < nlines) ? at32(data + (size_t)l0 * N, (unsigned)(l * N + i)) : cpx<T>{0, 0};
   }
 #pragma unroll
   for (int it = 0; it < IT::N; ++it) {
@@ -313,7 +330,7 @@ __device__ __forceinline__ void store_lines(const cpx<T>* B, cpx<T>* __restrict_
   for (int it = 0; it < IT::N; ++it) {
     const int u = threadIdx.x + it * kThreads;
     const int l = u / N, i = u % N;
-    if (IT::valid(u) && l0 + l < nlines) data[(size_t)(l0 + l) * N + i] = B[l * (N + 1) + i];
+    if (IT::valid(u) && l0 + l < nlines) at32(data + (size_t)l0 * N, (unsigned)(l * N + i)) = B[l * (N + 1) + i];
   }
 }
 
@@ -354,7 +371,7 @@ __device__ __forceinline__ void conv_line_body(cpx<T>* __restrict__ data,
   for (int it = 0; it < IT::N; ++it) {
     const int u = tid + it * kThreads;
     const int l = u / N, i = u % N;
-    kv[it] = (IT::valid(u) && l0 + l < nlines) ? ktab[(size_t)(l0 + l) * N + i] : (T)0;
+    kv[it] = (IT::valid(u) && l0 + l < nlines) ? at32(ktab + (size_t)l0 * N, (unsigned)(l * N + i)) : (T)0;
   }
   for (int i = tid; i < N; i += kThreads) W[i] = tw[i];
   __syncthreads();
@@ -397,9 +414,9 @@ __device__ __forceinline__ void conv_col_body(cpx<T>* __restrict__ spec,
     const int u = tid + it * kThreads;
     const int c = u % TC, r = u / TC;
     const bool in = IT::valid(u) && c0 + c < n1;
-    const size_t g = plane + (size_t)r * n1 + c0 + c;
-    v[it] = in ? spec[g] : cpx<T>{0, 0};
-    kv[it] = in ? ktab[g] : (T)0;
+    const unsigned g = (unsigned)(r * n1 + c);
+    v[it] = in ? at32(spec + plane + c0, g) : cpx<T>{0, 0};
+    kv[it] = in ? at32(ktab + plane + c0, g) : (T)0;
   }
   for (int i = tid; i < N2; i += kThreads) W[i] = tw2[i];
 #pragma unroll
@@ -423,7 +440,7 @@ __device__ __forceinline__ void conv_col_body(cpx<T>* __restrict__ spec,
   for (int it = 0; it < IT::N; ++it) {
     const int u = tid + it * kThreads;
     const int c = u % TC, r = u / TC;
-    if (IT::valid(u) && c0 + c < n1) spec[plane + (size_t)r * n1 + c0 + c] = B[r * RS + c];
+    if (IT::valid(u) && c0 + c < n1) at32(spec + plane + c0, (unsigned)(r * n1 + c)) = B[r * RS + c];
   }
 }
 
@@ -440,7 +457,7 @@ __device__ __forceinline__ void load_spec_pairs(const cpx<T>* __restrict__ spec,
     const int p = u % NP, kx = u / NP;
     const int j = j0 + 2 * p;
     const bool in = IH::valid(u) && j < n1;
-    const cpx<T>* o = spec + ((size_t)kx * n2 + k2) * n1 + j;
+    const cpx<T>* o = &at32(spec + (size_t)k2 * n1 + j0, (unsigned)(kx * n2 * n1 + 2 * p));
     sa[it] = in ? o[0] : cpx<T>{0, 0};
     sb[it] = in ? o[1] : cpx<T>{0, 0};
   }
@@ -517,8 +534,8 @@ __device__ __forceinline__ void c2r_nl_cnx_body(
     for (int it = 0; it < IT::N; ++it) {
       const int u = tid + it * kThreads;
       const bool in = IT::valid(u) && j0 + u / N0 < n1;
-      pv[it] = in ? psi[pbase + u] : cpx<T>{0, 0};
-      vv[it] = in ? V[pbase + u] : (T)0;
+      pv[it] = in ? at32(psi + pbase, (unsigned)u) : cpx<T>{0, 0};
+      vv[it] = in ? at32(V + pbase, (unsigned)u) : (T)0;
     }
   }
   for (int i = tid; i < N0; i += kThreads) W[i] = tw0[i];
@@ -530,7 +547,7 @@ __device__ __forceinline__ void c2r_nl_cnx_body(
     for (int it = 0; it < IT::N; ++it) {
       const int u = tid + it * kThreads;
       const int jl = u / N0, i = u % N0;
-      if (IT::valid(u) && j0 + jl < n1) phi_out[pbase + u] = tile_real(Z, LSZ, jl, i);
+      if (IT::valid(u) && j0 + jl < n1) at32(phi_out + pbase, (unsigned)u) = tile_real(Z, LSZ, jl, i);
     }
   } else {
     double sums[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -585,7 +602,7 @@ __device__ __forceinline__ void c2r_nl_cnx_body(
       for (int it = 0; it < IT::N; ++it) {
         const int u = tid + it * kThreads;
         const int jl = u / N0, i = u % N0;
-        if (IT::valid(u) && j0 + jl < n1) psi[pbase + u] = PS[jl * LSP + cpad<SX>(i)];
+        if (IT::valid(u) && j0 + jl < n1) at32(psi + pbase, (unsigned)u) = PS[jl * LSP + cpad<SX>(i)];
       }
     }
   }
@@ -622,7 +639,8 @@ __device__ __forceinline__ void cn_col_body(cpx<T>* __restrict__ psi,
   for (int it = 0; it < IT::N; ++it) {
     const int u = tid + it * kThreads;
     const int c = u % TC, r = u / TC;
-    v[it] = (IT::valid(u) && x0 + c < n0) ? base[(size_t)r * estride + c] : cpx<T>{0, 0};
+    const unsigned es = (unsigned)estride;
+    v[it] = (IT::valid(u) && x0 + c < n0) ? at32(base, r * es + c) : cpx<T>{0, 0};
   }
   if constexpr (SOLVE) load_cn_table<T, N, PC>(MT, cnm);
 #pragma unroll
@@ -641,7 +659,7 @@ __device__ __forceinline__ void cn_col_body(cpx<T>* __restrict__ psi,
     const int c = u % TC, r = u / TC;
     if (!IT::valid(u) || x0 + c >= n0) continue;
     const cpx<T> val = B[cpad<SC>(r) * RS + c];
-    if constexpr (SOLVE) base[(size_t)r * estride + c] = val;
+    if constexpr (SOLVE) at32(base, r * (unsigned)estride + c) = val;
     if constexpr (SUMS) {
       sums[0] += abs2_d(val);
       if (r + 1 < N) sums[1] += absdiff2_d(B[cpad<SC>(r + 1) * RS + c], val);
@@ -696,9 +714,9 @@ __device__ __forceinline__ void adj_x_body(
   for (int it = 0; it < IT::N; ++it) {
     const int u = tid + it * kThreads;
     const bool in = IT::valid(u) && j0 + u / N0 < n1;
-    lv[it] = in ? lam[pbase + u] : cpx<T>{0, 0};
-    pv[it] = in ? psin[pbase + u] : cpx<T>{0, 0};
-    vv[it] = in ? V[pbase + u] : (T)0;
+    lv[it] = in ? at32(lam + pbase, (unsigned)u) : cpx<T>{0, 0};
+    pv[it] = in ? at32(psin + pbase, (unsigned)u) : cpx<T>{0, 0};
+    vv[it] = in ? at32(V + pbase, (unsigned)u) : (T)0;
   }
   for (int i = tid; i < N0; i += kThreads) W[i] = tw0[i];
   load_cn_table<T, N0, PX>(MT, cnm);
@@ -726,9 +744,9 @@ __device__ __forceinline__ void adj_x_body(
     sincos_phase(th, sn, cs);
     const cpx<T> mu = la * cpx<T>{cs, sn};
     const T s = (T)2 * dt * (mu.re * p.im - mu.im * p.re);
-    lam[pbase + u] = mu;
-    sfield[pbase + u] = s;
-    gradV[pbase + u] += (double)s;
+    at32(lam + pbase, (unsigned)u) = mu;
+    at32(sfield + pbase, (unsigned)u) = s;
+    at32(gradV + pbase, (unsigned)u) += (double)s;
     sums[0] += (double)s * (double)n;
     sums[1] += (double)s * (double)phi;
   }
@@ -768,9 +786,9 @@ __device__ __forceinline__ void adj_fin_body(cpx<T>* __restrict__ lam,
   for (int it = 0; it < IT::N; ++it) {
     const int u = tid + it * kThreads;
     const bool in = IT::valid(u) && j0 + u / N0 < n1;
-    mv[it] = in ? lam[pbase + u] : cpx<T>{0, 0};
-    pv[it] = in ? psin[pbase + u] : cpx<T>{0, 0};
-    sv[it] = in ? sfield[pbase + u] : (T)0;
+    mv[it] = in ? at32(lam + pbase, (unsigned)u) : cpx<T>{0, 0};
+    pv[it] = in ? at32(psin + pbase, (unsigned)u) : cpx<T>{0, 0};
+    sv[it] = in ? at32(sfield + pbase, (unsigned)u) : (T)0;
   }
   for (int i = tid; i < N0; i += kThreads) W[i] = tw0[i];
   c2r_tile<T, N0, NP>(Z, W, sa, sb);
@@ -781,7 +799,7 @@ __device__ __forceinline__ void adj_fin_body(cpx<T>* __restrict__ lam,
     const int jl = u / N0, i = u % N0;
     if (j0 + jl >= n1) continue;
     const T w = (T)sc.gc * sv[it] + (T)sc.gdd * tile_real(Z, LSZ, jl, i);
-    lam[pbase + u] = mv[it] + scl(pv[it], w);
+    at32(lam + pbase, (unsigned)u) = mv[it] + scl(pv[it], w);
   }
 }
 
