@@ -210,14 +210,16 @@ __device__ __forceinline__ void r2c_x_body(const cpx<T>* __restrict__ psi,
   for (int i = tid; i < N0; i += kThreads) W[i] = tw0[i];
   const double s = *scale;
   const T s2 = (T)(s * s);
-  double sums[2] = {0.0, 0.0};
+  // per-thread partials in T (at most 16 points), FP64 above
+  T ps[2] = {0, 0};
 #pragma unroll
   for (int it = 0; it < IT::N; ++it) {
     const int u = tid + it * kThreads;
     if (!IT::valid(u)) continue;
     const int jl = u / N0, i = u % N0;
-    sums[0] += absdiff2_d(bx[it], a[it]);
-    sums[1] += absdiff2_d(by[it], a[it]);
+    const cpx<T> dx = bx[it] - a[it], dy = by[it] - a[it];
+    ps[0] += dx.re * dx.re + dx.im * dx.im;
+    ps[1] += dy.re * dy.re + dy.im * dy.im;
     const T nv = s2 * (a[it].re * a[it].re + a[it].im * a[it].im);
     cpx<T>& zc = Z[(jl >> 1) * LSZ + i];
     if (jl & 1) zc.im = nv;
@@ -243,6 +245,7 @@ __device__ __forceinline__ void r2c_x_body(const cpx<T>* __restrict__ psi,
     o[0] = cpx<T>{hf * (zk.re + zm.re), hf * (zk.im - zm.im)};
     o[1] = cpx<T>{hf * (zk.im + zm.im), hf * (zm.re - zk.re)};  // n1 even: line j+1 exists
   }
+  double sums[2] = {(double)ps[0], (double)ps[1]};
   block_sum<2>(sums, red);
   if (tid == 0) {
     partials[bid * 2 + 0] = sums[0];
@@ -550,10 +553,13 @@ __device__ __forceinline__ void c2r_nl_cnx_body(
       if (IT::valid(u) && j0 + jl < n1) at32(phi_out + pbase, (unsigned)u) = tile_real(Z, LSZ, jl, i);
     }
   } else {
-    double sums[7] = {0, 0, 0, 0, 0, 0, 0};
+    // Each thread's partials over its IT::N points (at most 16) are formed in T, then
+    // widened: the block and grid sums are FP64.  In FP32 an 8- or 16-term partial
+    // carries an unbiased rounding of ~1e-7 of itself, far below the observables' bar.
+    T ps[6] = {0, 0, 0, 0, 0, 0};
     const T ts = (T)(*scale);
-    const double h0 = sc.h0, h1 = sc.h1, h2 = sc.h2;
-    const double zc = (k2 - n2 / 2) * h2;
+    const T h0 = (T)sc.h0, h1 = (T)sc.h1;
+    const double zc = (k2 - n2 / 2) * sc.h2;
 #pragma unroll
     for (int it = 0; it < IT::N; ++it) {
       const int u = tid + it * kThreads;
@@ -567,17 +573,15 @@ __device__ __forceinline__ void c2r_nl_cnx_body(
       const T phi = tile_real(Z, LSZ, jl, i);
       const cpx<T> p = scl(pv[it], ts);
       const T v = vv[it];
-      const double nd = abs2_d(p);
-      const double xc = (i - N0 / 2) * h0, yc = (j - n1 / 2) * h1;
-      sums[0] += nd;
-      sums[1] += (double)v * nd;
-      sums[2] += nd * nd;
-      sums[3] += (double)phi * nd;
-      sums[4] += xc * xc * nd;
-      sums[5] += yc * yc * nd;
-      sums[6] += zc * zc * nd;
+      const T n = p.re * p.re + p.im * p.im;
+      const T xc = (T)(i - N0 / 2) * h0, yc = (T)(j - n1 / 2) * h1;
+      ps[0] += n;
+      ps[1] += v * n;
+      ps[2] += n * n;
+      ps[3] += phi * n;
+      ps[4] += xc * xc * n;
+      ps[5] += yc * yc * n;
       if constexpr (STEP) {
-        const T n = p.re * p.re + p.im * p.im;
         const T th = (T)sc.dt * (v + (T)sc.gc * n + (T)sc.gdd * phi);
         cpx<T> f;
         if constexpr (MODE == MODE_IMAG) {
@@ -590,6 +594,10 @@ __device__ __forceinline__ void c2r_nl_cnx_body(
         PS[jl * LSP + cpad<SX>(i)] = p * f;
       }
     }
+    double sums[7];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) sums[k] = (double)ps[k];
+    sums[6] = zc * zc * sums[0];
     block_sum<7>(sums, red);
     if (tid == 0) {
 #pragma unroll
