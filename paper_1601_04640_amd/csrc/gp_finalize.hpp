@@ -120,7 +120,8 @@ __device__ inline void finalize_block(const FinArgs& a, int mode) {
   rec[4] = epot;
   rec[5] = eint;
   rec[6] = edd;
-  const double r0 = sqrt(v[6] * dV / norm), r1 = sqrt(v[7] * dV / norm), r2 = sqrt(v[8] * dV / norm);
+  const double inv = norm > 0.0 ? 1.0 / norm : 0.0;  // rms of a zero state: 0
+  const double r0 = sqrt(v[6] * dV * inv), r1 = sqrt(v[7] * dV * inv), r2 = sqrt(v[8] * dV * inv);
   rec[7] = r0;
   rec[8] = (a.geom == 2) ? 0.0 : r1;
   rec[9] = (a.geom == 0) ? r2 : (a.geom == 2 ? r1 : 0.0);
@@ -138,7 +139,9 @@ __device__ inline void finalize_block(const FinArgs& a, int mode) {
   if (mode == FIN_OBSERVE) return;
   // new state: imaginary time renormalises, real time keeps the physical values
   const double nout = v[9] * dV;
-  if (!isfinite(nout) || !(nout > 0.0)) {
+  // imaginary time must renormalise (a zero state cannot be); real time only needs the
+  // state to stay finite (zero is a solution)
+  if (!isfinite(nout) || (mode == FIN_IMAG && !(nout > 0.0))) {
     *a.flags |= 1;
     *a.scale = 1.0;
     return;

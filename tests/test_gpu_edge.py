@@ -1,0 +1,110 @@
+"""Degenerate cases and limits of the method on the GPU: the non-interacting limit against
+its closed form, a zero wave function, the largest supported grid, and the extreme axis
+lengths of the quasi-2D path."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1601_04640_amd import inputs as I
+from tests.gpu_util import FP32_PSI_TOL, FP64_PSI_TOL, banner, oparams, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def harmonic_2d(n, h, prec):
+    from paper_1601_04640_amd.binding import Solver
+    w = dict(geom="2dxy", nx=n, ny=n, nz=1, dx=h, dy=h, dz=1.0, dt=0.0005, gamma=1.0,
+             nu=1.5, lam=4.0, g=0.0, gdd=0.0, R=0.0)
+    s = Solver(w, prec=prec)
+    s.set_psi(I.gaussian("2dxy", n, n, 1, h, h, 1.0, widths=(1 / math.sqrt(1.5), 1.0)))
+    s.step_imag(8000)                      # t = 4: the discrete ground state
+    e = s.energy()["energy"]
+    s.close()
+    return e
+
+
+def test_noninteracting_ground_state_energy(gpu_lib):
+    """g = g_dd = 0: the imaginary-time ground-state energy approaches (gamma + nu)/2 =
+    1.25 as O(h^2) (the error falls fourfold when h halves), in FP64 and FP32."""
+    banner("non-interacting ground state")
+    e_coarse = harmonic_2d(64, 0.25, "fp64")
+    e_fine = harmonic_2d(128, 0.125, "fp64")
+    exact = 1.25
+    assert abs(e_fine - exact) < 2e-3, e_fine
+    ratio = (e_coarse - exact) / (e_fine - exact)
+    assert 3.7 < ratio < 4.3, (e_coarse, e_fine, ratio)
+    e32 = harmonic_2d(128, 0.125, "fp32")
+    assert abs(e32 - e_fine) <= 1e-6 * exact, (e32, e_fine)
+
+
+def test_zero_wave_function(gpu_lib):
+    """psi = 0: real time keeps it zero; imaginary time cannot renormalise it and flags
+    the state as non-finite."""
+    from paper_1601_04640_amd import binding as B
+    from paper_1601_04640_amd.binding import Solver
+    w = dict(geom="3d", nx=24, ny=20, nz=16, dx=0.35, dy=0.4, dz=0.45, dt=0.002,
+             gamma=1.0, nu=1.3, lam=2.0, g=25.0, gdd=8.0, R=2.8)
+    banner("zero psi")
+    s = Solver(w, prec="fp32")
+    s.set_psi(np.zeros((16, 20, 24), dtype=np.complex128))
+    s.step_real(3)
+    assert not np.any(s.get_psi())
+    s.step_imag(1)
+    with pytest.raises(B.GPError) as e:
+        s.sync()
+    assert e.value.status == B.GP_E_NONFINITE
+    s.close()
+
+
+@pytest.mark.parametrize("geom,nx,n1", [("2dxz", 512, 8), ("2dxy", 8, 512), ("2dxy", 10, 12)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_extreme_axis_lengths_2d(geom, nx, n1, prec, gpu_lib):
+    """The shortest (8, 10, 12) and longest (512) supported axes against the oracle."""
+    from paper_1601_04640_amd.binding import Solver
+    h = 0.08 if max(nx, n1) == 512 else 0.6
+    w = dict(geom=geom, nx=nx, ny=n1 if geom == "2dxy" else 1, nz=n1 if geom == "2dxz" else 1,
+             dx=h, dy=h, dz=h, dt=0.001, gamma=1.0, nu=2.0, lam=2.0, g=20.0, gdd=8.0, R=0.0)
+    banner("extreme axes", geom, nx, n1, prec)
+    p = oparams(w)
+    psi0 = I.gaussian(geom, w["nx"], w["ny"], w["nz"], h, h, h, widths=(1.0, 1.2),
+                      amp_noise=0.02, phase_noise=0.01, seed=1612)
+    s = Solver(w, prec=prec)
+    s.set_psi(psi0)
+    s.step_imag(6)
+    s.step_real(6)
+    ref = O.run(O.run(psi0, p, True, 6), p, False, 6)
+    assert rel_l2(s.get_psi(), ref) <= (FP64_PSI_TOL if prec == "fp64" else FP32_PSI_TOL)
+    s.close()
+
+
+def test_largest_grid_512_cubed(gpu_lib):
+    """512^3 FP32 (every axis at the maximum): real-time steps keep the norm and the
+    Dirichlet faces, and the energy stays finite; the start is built on the device."""
+    import torch
+    from paper_1601_04640_amd.binding import Solver
+    n, h = 512, 0.05
+    w = dict(geom="3d", nx=n, ny=n, nz=n, dx=h, dy=h, dz=h, dt=0.0002, gamma=1.0, nu=1.0,
+             lam=2.0, g=50.0, gdd=20.0, R=6.0)
+    banner("512^3 fp32")
+    s = Solver(w, prec="fp32")
+    ax = (torch.arange(n, device="cuda:0", dtype=torch.float32) - n // 2) * h
+    g1 = torch.exp(-0.5 * ax * ax)
+    gz = torch.exp(-ax * ax)                       # lambda = 2: width 1/sqrt(2)
+    psi = (gz[:, None, None] * g1[None, :, None] * g1[None, None, :]).to(torch.complex64)
+    psi[0], psi[-1], psi[:, 0], psi[:, -1], psi[:, :, 0], psi[:, :, -1] = 0, 0, 0, 0, 0, 0
+    psi /= torch.sqrt(torch.sum(psi.abs() ** 2) * h ** 3)
+    s.set_psi(psi)
+    del psi
+    e0 = s.energy()
+    s.step_real(4)
+    e1 = s.energy()
+    assert abs(e1["norm"] - 1.0) <= 1e-5 and abs(e0["norm"] - 1.0) <= 1e-5
+    assert np.isfinite(e1["energy"]) and abs(e1["energy"] - e0["energy"]) <= 1e-3 * abs(e0["energy"])
+    out = s.get_psi_device()
+    faces = [out[0], out[-1], out[:, 0], out[:, -1], out[:, :, 0], out[:, :, -1]]
+    assert all(float(f.abs().max()) == 0.0 for f in faces)
+    del out
+    s.close()
+    torch.cuda.empty_cache()
