@@ -23,7 +23,7 @@ namespace {
 
 constexpr int kRingCap = 4096;
 constexpr long long kStageThreshold = 16384;  // partial values above which the finalize
-constexpr long long kStageSlice = 2048;       // runs in two stages, ~kStageSlice per slice
+constexpr long long kStageSlice = 512;        // runs in two stages, ~kStageSlice per slice
 constexpr int kGraphSteps = 8;  // steps per captured graph
 
 bool size_ok(int n) {
@@ -265,7 +265,7 @@ FinArgs fin_args(const gp_ctx* c) {
   a.ring_pos = &s->ring_pos;
   a.ring_cap = kRingCap;
   a.obs = c->at<double>(c->L.o_obs);
-  // many partials: a first stage of up to kStageMax blocks sums slices of ~2K values
+  // many partials: a first stage of up to kStageMax blocks sums slices of ~512 values
   const long long nvals = 9LL * c->L.nb_x + 2LL * c->L.nb_col;
   a.stage = c->at<double>(c->L.o_stage);
   a.nstage = nvals > kStageThreshold

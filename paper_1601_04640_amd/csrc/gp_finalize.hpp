@@ -31,7 +31,7 @@ struct FinArgs {
 };
 
 constexpr int kStageVals = 11;   // totals carried per slice (the v[] of finalize_block)
-constexpr int kStageMax = 64;    // slices of the two-stage reduction
+constexpr int kStageMax = 256;   // slices of the two-stage reduction (<= kThreads)
 
 // Sums the partial arrays a block reads, blocks [lo, hi) of each, into v[11] (per
 // thread; fixed order).  4 slots per iteration keep 4 loads in flight.

@@ -64,9 +64,10 @@ struct Tiles {
 };
 
 // Workgroups are dispatched to the 8 XCDs round-robin (block b runs on XCD b % 8), and
-// each XCD has its own L2.  The x passes renumber their tiles so that every XCD works
-// through one contiguous range: neighbouring x tiles, which read the two halves of the
-// same 128-byte spectrum lines when a tile holds 8 lines of FP32, then share an L2.
+// each XCD has its own L2.  The x passes and the z convolution renumber their tiles so
+// that every XCD works through one contiguous range: neighbouring tiles, which read the
+// two halves of the same 128-byte lines (spectrum lines of 8-line FP32 x tiles, kernel
+// table rows of 16-column z tiles), then share an L2.
 constexpr int kXcds = 8;
 __device__ __forceinline__ int xcd_tile(int b, int nb) {
   const int x = b % kXcds, i = b / kXcds, per = nb / kXcds, rem = nb % kXcds;
@@ -855,7 +856,7 @@ __global__ __launch_bounds__(kThreads) void k_conv_col(cpx<T>* __restrict__ spec
                                                        const T* __restrict__ ktab,
                                                        const cpx<T>* __restrict__ tw2, int n1) {
   GP_LDS(T, N2, P_CONV_COL);
-  conv_col_body<T, N2>(spec, ktab, tw2, n1, blockIdx.x, lds);
+  conv_col_body<T, N2>(spec, ktab, tw2, n1, xcd_tile(blockIdx.x, gridDim.x), lds);
 }
 
 template <typename T, int N0, int MODE>
