@@ -59,6 +59,8 @@ def tune(batch, steps=16, imag=True, cache_path=None, verbose=False):
         for g in trials:
             batch.set_blocks(p, c, g)
             t = _time_steps(batch, steps, imag)
+            if verbose:
+                print(f"[autotune]   {p} class {c}: {g} blocks {t:.4f} ms/step", flush=True)
             if best_t is None or t < best_t:
                 best_g, best_t = g, t
         batch.set_blocks(p, c, best_g)

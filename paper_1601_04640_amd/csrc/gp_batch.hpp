@@ -13,25 +13,26 @@
 
 namespace gpdbec {
 
+// Per-instance descriptor.  Arrays are byte offsets from the batch workspace base, which
+// the kernels receive as an argument: pointers formed from a kernel argument keep the
+// global address space (pointers loaded from memory would fall back to flat accesses with
+// 64-bit per-lane addresses).
 template <typename T>
 struct BDesc {
-  cpx<T>* psi;
-  const T* V;
-  cpx<T>* spec;
-  const T* ktab;
-  const cpx<T>* tw0;
-  const cpx<T>* tw1;
-  const cpx<T>* cn0[2];  // x-axis factor tables: [imaginary, real time]
-  const cpx<T>* cn1[2];  // second-axis factor tables
-  double* p_x;
-  double* p_nl;
-  double* p_col;
-  const double* scale;
-  StepScalars sc;        // x-axis scalars (Ar for x)
-  double Ar1;            // dt/(4 h1^2)
+  size_t psi, V, spec, ktab, tw0, tw1;
+  size_t cn0[2];  // x-axis factor tables: [imaginary, real time]
+  size_t cn1[2];  // second-axis factor tables
+  size_t p_x, p_nl, p_col, scale;
+  StepScalars sc;  // x-axis scalars (Ar for x)
+  double Ar1;      // dt/(4 h1^2)
   int n0, n1;
-  FinArgs fa;            // FP64 finalisation of this instance
+  FinArgs fa;      // FP64 finalisation of this instance
 };
+
+template <typename X>
+__device__ __forceinline__ X* bptr(char* base, size_t off) {
+  return reinterpret_cast<X*>(base + off);
+}
 
 struct WorkItem {
   int inst;
@@ -52,7 +53,8 @@ __host__ __device__ constexpr int batch_class(int n) { return n > 256 ? 1 : 0; }
 // Every block walks items blockIdx.x + k gridDim.x of the work list.
 #define GP_BATCH_KERNEL(NAME, AXIS, BODY)                                              \
   template <typename T, int MODE, int CLS>                                             \
-  __global__ __launch_bounds__(kThreads) void NAME(const BDesc<T>* __restrict__ D,     \
+  __global__ __launch_bounds__(kThreads) void NAME(char* __restrict__ base,             \
+                                                   const BDesc<T>* __restrict__ D,     \
                                                    const WorkItem* __restrict__ work,  \
                                                    int nwork) {                        \
     extern __shared__ __attribute__((aligned(16))) char lds[];                         \
@@ -72,21 +74,28 @@ __host__ __device__ constexpr int batch_class(int n) { return n > 256 ? 1 : 0; }
 
 #define GP_BODY_R2C(N)                                                                  \
   case N:                                                                               \
-    r2c_x_body<T, N>(d.psi, d.scale, d.spec, d.tw0, d.p_x, d.n1, 1, item.tile, lds);    \
+    r2c_x_body<T, N>(bptr<cpx<T>>(base, d.psi), bptr<double>(base, d.scale),              \
+                     bptr<cpx<T>>(base, d.spec), bptr<cpx<T>>(base, d.tw0),              \
+                     bptr<double>(base, d.p_x), d.n1, 1, item.tile, lds);                 \
     break;
 #define GP_BODY_CONV(N)                                                                 \
   case N:                                                                               \
-    conv_line_body<T, N>(d.spec, d.ktab, d.tw1, d.n0 / 2 + 1, item.tile, lds);          \
+    conv_line_body<T, N>(bptr<cpx<T>>(base, d.spec), bptr<T>(base, d.ktab),              \
+                         bptr<cpx<T>>(base, d.tw1), d.n0 / 2 + 1, item.tile, lds);       \
     break;
 #define GP_BODY_C2R(N)                                                                  \
   case N:                                                                               \
-    c2r_nl_cnx_body<T, N, MODE>(d.psi, d.V, d.scale, d.spec, d.tw0, d.cn0[K], d.sc,     \
-                                d.p_nl, nullptr, d.n1, 1, item.tile, lds);              \
+    c2r_nl_cnx_body<T, N, MODE>(bptr<cpx<T>>(base, d.psi), bptr<T>(base, d.V),           \
+                                bptr<double>(base, d.scale), bptr<cpx<T>>(base, d.spec), \
+                                bptr<cpx<T>>(base, d.tw0), bptr<cpx<T>>(base, d.cn0[K]), \
+                                d.sc, bptr<double>(base, d.p_nl), nullptr, d.n1, 1,      \
+                                item.tile, lds);                                         \
     break;
 #define GP_BODY_CN(N)                                                                   \
   case N:                                                                               \
-    cn_col_body<T, N, MODE, true>(d.psi, d.cn1[K], d.Ar1, d.p_col, d.n0, (size_t)d.n0,  \
-                                  (size_t)d.n0 * d.n1, item.tile, lds);                 \
+    cn_col_body<T, N, MODE, true>(bptr<cpx<T>>(base, d.psi), bptr<cpx<T>>(base, d.cn1[K]), \
+                                  d.Ar1, bptr<double>(base, d.p_col), d.n0, (size_t)d.n0, \
+                                  (size_t)d.n0 * d.n1, item.tile, lds);                   \
     break;
 GP_BATCH_KERNEL(kb_r2c_x, n0, GP_BODY_R2C)
 GP_BATCH_KERNEL(kb_conv_y, n1, GP_BODY_CONV)

@@ -1,4 +1,6 @@
 // Persistent multi-instance kernels for one precision (GP_REAL) and their launcher.
+// (Item-loop kernels: see thread_idx.)
+#define GP_ITEM_LOOP_KERNELS
 #include "gp_batch.hpp"
 #include "gp_batch_launch.hpp"
 
@@ -71,9 +73,9 @@ void batch_tiles<T>(int n0, int n1, int* nb_x, int* nb_conv, int* nb_col) {
 }
 
 template <typename K>
-static hipError_t launch_dyn(K kern, int grid, size_t lds, hipStream_t st, const BDesc<T>* D,
-                             const WorkItem* work, int nwork) {
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, st, D, work, nwork);
+static hipError_t launch_dyn(K kern, int grid, size_t lds, hipStream_t st, char* base,
+                             const BDesc<T>* D, const WorkItem* work, int nwork) {
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, st, base, D, work, nwork);
   return hipGetLastError();
 }
 
@@ -114,22 +116,22 @@ hipError_t batch_reserve_lds<T>(int pass, int mode, int cls, size_t lds) {
 
 template <int CLS>
 static hipError_t launch_class(int pass, int mode, int grid, size_t lds, hipStream_t st,
-                               const BDesc<T>* D, const WorkItem* work, int nwork) {
+                               char* base, const BDesc<T>* D, const WorkItem* work, int nwork) {
   switch (pass) {
     case BP_R2C:
-      return launch_dyn(kb_r2c_x<T, 0, CLS>, grid, lds, st, D, work, nwork);
+      return launch_dyn(kb_r2c_x<T, 0, CLS>, grid, lds, st, base, D, work, nwork);
     case BP_CONV:
-      return launch_dyn(kb_conv_y<T, 0, CLS>, grid, lds, st, D, work, nwork);
+      return launch_dyn(kb_conv_y<T, 0, CLS>, grid, lds, st, base, D, work, nwork);
     case BP_C2R:
       if (mode == MODE_IMAG)
-        return launch_dyn(kb_c2r_nl_cnx<T, MODE_IMAG, CLS>, grid, lds, st, D, work, nwork);
+        return launch_dyn(kb_c2r_nl_cnx<T, MODE_IMAG, CLS>, grid, lds, st, base, D, work, nwork);
       if (mode == MODE_REAL)
-        return launch_dyn(kb_c2r_nl_cnx<T, MODE_REAL, CLS>, grid, lds, st, D, work, nwork);
-      return launch_dyn(kb_c2r_nl_cnx<T, MODE_OBSERVE, CLS>, grid, lds, st, D, work, nwork);
+        return launch_dyn(kb_c2r_nl_cnx<T, MODE_REAL, CLS>, grid, lds, st, base, D, work, nwork);
+      return launch_dyn(kb_c2r_nl_cnx<T, MODE_OBSERVE, CLS>, grid, lds, st, base, D, work, nwork);
     case BP_CN:
       if (mode == MODE_IMAG)
-        return launch_dyn(kb_cn_y<T, MODE_IMAG, CLS>, grid, lds, st, D, work, nwork);
-      return launch_dyn(kb_cn_y<T, MODE_REAL, CLS>, grid, lds, st, D, work, nwork);
+        return launch_dyn(kb_cn_y<T, MODE_IMAG, CLS>, grid, lds, st, base, D, work, nwork);
+      return launch_dyn(kb_cn_y<T, MODE_REAL, CLS>, grid, lds, st, base, D, work, nwork);
     default:
       return hipErrorInvalidValue;
   }
@@ -137,10 +139,10 @@ static hipError_t launch_class(int pass, int mode, int grid, size_t lds, hipStre
 
 template <>
 hipError_t batch_launch<T>(int pass, int mode, int cls, int grid, size_t lds, hipStream_t st,
-                           const BDesc<T>* D, const WorkItem* work, int nwork) {
+                           char* base, const BDesc<T>* D, const WorkItem* work, int nwork) {
   if (grid <= 0 || nwork <= 0) return hipSuccess;
-  return cls == 0 ? launch_class<0>(pass, mode, grid, lds, st, D, work, nwork)
-                  : launch_class<1>(pass, mode, grid, lds, st, D, work, nwork);
+  return cls == 0 ? launch_class<0>(pass, mode, grid, lds, st, base, D, work, nwork)
+                  : launch_class<1>(pass, mode, grid, lds, st, base, D, work, nwork);
 }
 
 template <>

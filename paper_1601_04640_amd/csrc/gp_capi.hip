@@ -744,20 +744,22 @@ gp_status batch_write_desc(gp_batch* b) {
     gp_ctx* c = b->inst[i];
     const Layout& L = c->L;
     BDesc<T>& d = D[i];
-    d.psi = c->at<cpx<T>>(L.o_psi);
-    d.V = c->at<T>(L.o_V);
-    d.spec = c->at<cpx<T>>(L.o_spec);
-    d.ktab = c->at<T>(L.o_ktab);
-    d.tw0 = c->at<cpx<T>>(L.o_tw[0]);
-    d.tw1 = c->at<cpx<T>>(L.o_tw[1]);
-    d.cn0[0] = c->at<cpx<T>>(L.o_cn[0][0]);
-    d.cn0[1] = c->at<cpx<T>>(L.o_cn[0][2]);
-    d.cn1[0] = c->at<cpx<T>>(L.o_cn[1][0]);
-    d.cn1[1] = c->at<cpx<T>>(L.o_cn[1][2]);
-    d.p_x = c->at<double>(L.o_px);
-    d.p_nl = c->at<double>(L.o_pnl);
-    d.p_col = c->at<double>(L.o_pcol);
-    d.scale = &c->sc()->scale;
+    // byte offsets from the batch workspace base
+    const size_t o = (size_t)(c->ws - b->ws);
+    d.psi = o + L.o_psi;
+    d.V = o + L.o_V;
+    d.spec = o + L.o_spec;
+    d.ktab = o + L.o_ktab;
+    d.tw0 = o + L.o_tw[0];
+    d.tw1 = o + L.o_tw[1];
+    d.cn0[0] = o + L.o_cn[0][0];
+    d.cn0[1] = o + L.o_cn[0][2];
+    d.cn1[0] = o + L.o_cn[1][0];
+    d.cn1[1] = o + L.o_cn[1][2];
+    d.p_x = o + L.o_px;
+    d.p_nl = o + L.o_pnl;
+    d.p_col = o + L.o_pcol;
+    d.scale = o + L.o_scalars + offsetof(Scalars, scale);
     d.sc = scalars_for(c, 0);
     d.Ar1 = scalars_for(c, 1).Ar;
     d.n0 = L.n0;
@@ -835,8 +837,8 @@ gp_status batch_step(gp_batch* b, hipStream_t st, bool imag) {
   const int passes[4] = {BP_R2C, BP_CONV, BP_C2R, BP_CN};
   for (int p : passes) {
     for (int k = 0; k < kBatchClasses; ++k) {
-      GP_HIP(batch_launch<T>(p, mode, k, b->grid[p][k], b->lds[p][k][mi], st, D, b->work[p][k],
-                             b->nwork[p][k]));
+      GP_HIP(batch_launch<T>(p, mode, k, b->grid[p][k], b->lds[p][k][mi], st, b->ws, D,
+                             b->work[p][k], b->nwork[p][k]));
     }
   }
   return dev(batch_finalize<T>(b->count, imag ? (int)FIN_IMAG : (int)FIN_REAL, st, D));

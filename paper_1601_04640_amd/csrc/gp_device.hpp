@@ -16,6 +16,20 @@ namespace gpdbec {
 
 constexpr int kThreads = 256;
 
+// Thread index in the block.  The translation unit of the persistent batched kernels
+// (which loop over work items) defines GP_ITEM_LOOP_KERNELS: there every use goes through
+// an empty volatile asm and yields a fresh value, so each item recomputes its index
+// arithmetic instead of the compiler hoisting all of it out of the item loop, where it
+// would stay live across items and exhaust the registers.  Elsewhere it is plain, and
+// the index arithmetic is shared across a kernel.
+__device__ __forceinline__ int thread_idx() {
+  int t = (int)threadIdx.x;
+#ifdef GP_ITEM_LOOP_KERNELS
+  asm volatile("" : "+v"(t));
+#endif
+  return t;
+}
+
 template <typename T>
 struct alignas(2 * sizeof(T)) cpx {
   T re, im;
@@ -158,7 +172,7 @@ struct LdsFFT {
       constexpr int IT = (TOT + kThreads - 1) / kThreads;
       constexpr int TWS = N / (L * R);
       cpx<T> v[IT][R];
-      const int tid = threadIdx.x;
+      const int tid = thread_idx();
 #pragma unroll
       for (int it = 0; it < IT; ++it) {
         const int u = tid + it * kThreads;
@@ -292,7 +306,7 @@ __device__ __forceinline__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt, T 
   using AR = CnArith<T, IMAG_A>;
   using GT = typename AR::G;
   const AR ar{a, (T)2 * a};
-  const int tid = threadIdx.x;
+  const int tid = thread_idx();
   const int l = tid / P, q = tid % P;
   const int lo = q * S;          // first element of the lane's chunk
   const int base = lo + q;       // its chunk-padded position: cpad<S>(lo + e) = base + e
@@ -490,7 +504,7 @@ __device__ __forceinline__ void sincos_phase(double x, double& s, double& c) {
 template <typename T, int N, int P>
 __device__ __forceinline__ void load_cn_table(cpx<T>* mt, const cpx<T>* __restrict__ m) {
   constexpr int S = (N + P - 1) / P;
-  for (int i = threadIdx.x; i < N; i += kThreads) mt[cpad<S>(i)] = m[i];
+  for (int i = thread_idx(); i < N; i += kThreads) mt[cpad<S>(i)] = m[i];
 }
 template <int N, int P>
 constexpr int cn_table_len() {
@@ -504,7 +518,7 @@ constexpr int cn_table_len() {
 constexpr int kWaves = kThreads / 64;
 template <int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double* red /* LDS NV*kWaves */) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = thread_idx() & 63, wave = thread_idx() >> 6;
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
 #pragma unroll
@@ -515,7 +529,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red /* LDS NV
     for (int k = 0; k < NV; ++k) red[k * kWaves + wave] = v[k];
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (thread_idx() == 0) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
       double acc = red[k * kWaves];

@@ -185,7 +185,7 @@ __device__ __forceinline__ void r2c_x_body(const cpx<T>* __restrict__ psi,
   cpx<T>* Z = cv.take<cpx<T>>(NP * LSZ);
   cpx<T>* W = cv.take<cpx<T>>(N0);
   double* red = cv.take<double>(8 * kWaves);
-  const int tid = threadIdx.x;
+  const int tid = thread_idx();
   const int nt1 = (n1 + TJ - 1) / TJ;
   const int k2 = bid / nt1;
   const int j0 = (bid % nt1) * TJ;
@@ -266,7 +266,7 @@ __device__ __forceinline__ void r2c_real_body(const T* __restrict__ f, cpx<T>* _
   Carve cv{lds};
   cpx<T>* Z = cv.take<cpx<T>>(NP * LSZ);
   cpx<T>* W = cv.take<cpx<T>>(N0);
-  const int tid = threadIdx.x;
+  const int tid = thread_idx();
   const int nt1 = (n1 + TJ - 1) / TJ;
   const int k2 = bid / nt1;
   const int j0 = (bid % nt1) * TJ;
@@ -315,13 +315,13 @@ __device__ __forceinline__ void load_lines(cpx<T>* B, const cpx<T>* __restrict__
   cpx<T> v[IT::N];
 #pragma unroll
   for (int it = 0; it < IT::N; ++it) {
-    const int u = threadIdx.x + it * kThreads;
+    const int u = thread_idx() + it * kThreads;
     const int l = u / N, i = u % N;
     v[it] = (IT::valid(u) && l0 + l < nlines) ? at32(data + (size_t)l0 * N, (unsigned)(l * N + i)) : cpx<T>{0, 0};
   }
 #pragma unroll
   for (int it = 0; it < IT::N; ++it) {
-    const int u = threadIdx.x + it * kThreads;
+    const int u = thread_idx() + it * kThreads;
     if (IT::valid(u)) B[(u / N) * (N + 1) + u % N] = v[it];
   }
 }
@@ -332,7 +332,7 @@ __device__ __forceinline__ void store_lines(const cpx<T>* B, cpx<T>* __restrict_
   using IT = Iters<LB * N>;
 #pragma unroll
   for (int it = 0; it < IT::N; ++it) {
-    const int u = threadIdx.x + it * kThreads;
+    const int u = thread_idx() + it * kThreads;
     const int l = u / N, i = u % N;
     if (IT::valid(u) && l0 + l < nlines) at32(data + (size_t)l0 * N, (unsigned)(l * N + i)) = B[l * (N + 1) + i];
   }
@@ -350,7 +350,7 @@ __device__ __forceinline__ void fft_line_body(cpx<T>* __restrict__ data,
   cpx<T>* W = cv.take<cpx<T>>(N);
   const int l0 = bid * LB;
   load_lines<T, N, LB>(B, data, l0, nlines);
-  for (int i = threadIdx.x; i < N; i += kThreads) W[i] = tw[i];
+  for (int i = thread_idx(); i < N; i += kThreads) W[i] = tw[i];
   __syncthreads();
   LdsFFT<T, N, LB, LSZ, 1, false>::template run<INV>(B, W);
   store_lines<T, N, LB>(B, data, l0, nlines);
@@ -367,7 +367,7 @@ __device__ __forceinline__ void conv_line_body(cpx<T>* __restrict__ data,
   Carve cv{lds};
   cpx<T>* B = cv.take<cpx<T>>(LB * LSZ);
   cpx<T>* W = cv.take<cpx<T>>(N);
-  const int tid = threadIdx.x;
+  const int tid = thread_idx();
   const int l0 = bid * LB;
   load_lines<T, N, LB>(B, data, l0, nlines);
   T kv[IT::N];  // kernel values: loaded now, used after the forward FFT
@@ -406,7 +406,7 @@ __device__ __forceinline__ void conv_col_body(cpx<T>* __restrict__ spec,
   Carve cv{lds};
   cpx<T>* B = cv.take<cpx<T>>(N2 * RS);
   cpx<T>* W = cv.take<cpx<T>>(N2);
-  const int tid = threadIdx.x;
+  const int tid = thread_idx();
   const int nt = (n1 + TC - 1) / TC;
   const int kx = bid / nt;
   const int c0 = (bid % nt) * TC;
@@ -457,7 +457,7 @@ __device__ __forceinline__ void load_spec_pairs(const cpx<T>* __restrict__ spec,
   using IH = Iters<(N0 / 2 + 1) * NP>;
 #pragma unroll
   for (int it = 0; it < IH::N; ++it) {
-    const int u = threadIdx.x + it * kThreads;
+    const int u = thread_idx() + it * kThreads;
     const int p = u % NP, kx = u / NP;
     const int j = j0 + 2 * p;
     const bool in = IH::valid(u) && j < n1;
@@ -478,7 +478,7 @@ __device__ __forceinline__ void c2r_tile(cpx<T>* Z, const cpx<T>* W,
   using IH = Iters<H * NP>;
 #pragma unroll
   for (int it = 0; it < IH::N; ++it) {
-    const int u = threadIdx.x + it * kThreads;
+    const int u = thread_idx() + it * kThreads;
     if (!IH::valid(u)) continue;
     const int p = u % NP, kx = u / NP;
     const cpx<T> a = sa[it], b = sb[it];
@@ -523,7 +523,7 @@ __device__ __forceinline__ void c2r_nl_cnx_body(
   cpx<T>* W = cv.take<cpx<T>>(N0);
   cpx<T>* MT = STEP ? cv.take<cpx<T>>(cn_table_len<N0, PX>()) : nullptr;
   double* red = cv.take<double>(8 * kWaves);
-  const int tid = threadIdx.x;
+  const int tid = thread_idx();
   const int nt1 = (n1 + TJ - 1) / TJ;
   const int k2 = bid / nt1;
   const int j0 = (bid % nt1) * TJ;
@@ -638,7 +638,7 @@ __device__ __forceinline__ void cn_col_body(cpx<T>* __restrict__ psi,
   cpx<T>* B = cv.take<cpx<T>>(G::NR * RS);
   cpx<T>* MT = cv.take<cpx<T>>(cn_table_len<N, PC>());
   double* red = cv.take<double>(8 * kWaves);
-  const int tid = threadIdx.x;
+  const int tid = thread_idx();
   const int nt = (n0 + TC - 1) / TC;
   const int outer = bid / nt;
   const int x0 = (bid % nt) * TC;
@@ -710,7 +710,7 @@ __device__ __forceinline__ void adj_x_body(
   cpx<T>* W = cv.take<cpx<T>>(N0);
   cpx<T>* MT = cv.take<cpx<T>>(cn_table_len<N0, PX>());
   double* red = cv.take<double>(8 * kWaves);
-  const int tid = threadIdx.x;
+  const int tid = thread_idx();
   const int nt1 = (n1 + TJ - 1) / TJ;
   const int k2 = bid / nt1;
   const int j0 = (bid % nt1) * TJ;
@@ -782,7 +782,7 @@ __device__ __forceinline__ void adj_fin_body(cpx<T>* __restrict__ lam,
   Carve cv{lds};
   cpx<T>* Z = cv.take<cpx<T>>(NP * LSZ);
   cpx<T>* W = cv.take<cpx<T>>(N0);
-  const int tid = threadIdx.x;
+  const int tid = thread_idx();
   const int nt1 = (n1 + TJ - 1) / TJ;
   const int k2 = bid / nt1;
   const int j0 = (bid % nt1) * TJ;
