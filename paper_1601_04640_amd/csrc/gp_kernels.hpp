@@ -126,6 +126,13 @@ __device__ __forceinline__ const X& at32(const X* base, unsigned idx) {
                                      idx * (unsigned)sizeof(X));
 }
 
+// Two neighbouring complex values (the lines j, j + 1 of a packed pair), moved as one
+// aligned access: j is even, so a pair starts on a 2 * sizeof(cpx<T>) boundary.
+template <typename T>
+struct alignas(2 * sizeof(cpx<T>)) cpx2 {
+  cpx<T> a, b;
+};
+
 // Geometry of an x-line tile (TJ lines of N0 points; NP packed complex pairs).
 template <typename T, int N0>
 struct XT {
@@ -242,9 +249,9 @@ __device__ __forceinline__ void r2c_x_body(const cpx<T>* __restrict__ psi,
     const T hf = (T)0.5;
     cpx<T>* sp = spec + (size_t)k2 * n1 + j0;  // uniform; + kx n2 n1 + 2p per lane
     const unsigned off = (unsigned)(kx * n2 * n1 + 2 * p);
-    cpx<T>* o = &at32(sp, off);
-    o[0] = cpx<T>{hf * (zk.re + zm.re), hf * (zk.im - zm.im)};
-    o[1] = cpx<T>{hf * (zk.im + zm.im), hf * (zm.re - zk.re)};  // n1 even: line j+1 exists
+    *reinterpret_cast<cpx2<T>*>(&at32(sp, off)) =
+        cpx2<T>{{hf * (zk.re + zm.re), hf * (zk.im - zm.im)},
+                {hf * (zk.im + zm.im), hf * (zm.re - zk.re)}};  // n1 even: line j+1 exists
   }
   double sums[2] = {(double)ps[0], (double)ps[1]};
   block_sum<2>(sums, red);
@@ -301,9 +308,9 @@ __device__ __forceinline__ void r2c_real_body(const T* __restrict__ f, cpx<T>* _
     const T hf = (T)0.5;
     cpx<T>* sp = spec + (size_t)k2 * n1 + j0;  // uniform; + kx n2 n1 + 2p per lane
     const unsigned off = (unsigned)(kx * n2 * n1 + 2 * p);
-    cpx<T>* o = &at32(sp, off);
-    o[0] = cpx<T>{hf * (zk.re + zm.re), hf * (zk.im - zm.im)};
-    o[1] = cpx<T>{hf * (zk.im + zm.im), hf * (zm.re - zk.re)};
+    *reinterpret_cast<cpx2<T>*>(&at32(sp, off)) =
+        cpx2<T>{{hf * (zk.re + zm.re), hf * (zk.im - zm.im)},
+                {hf * (zk.im + zm.im), hf * (zm.re - zk.re)}};  // n1 even: line j+1 exists
   }
 }
 
@@ -461,9 +468,11 @@ __device__ __forceinline__ void load_spec_pairs(const cpx<T>* __restrict__ spec,
     const int p = u % NP, kx = u / NP;
     const int j = j0 + 2 * p;
     const bool in = IH::valid(u) && j < n1;
-    const cpx<T>* o = &at32(spec + (size_t)k2 * n1 + j0, (unsigned)(kx * n2 * n1 + 2 * p));
-    sa[it] = in ? o[0] : cpx<T>{0, 0};
-    sb[it] = in ? o[1] : cpx<T>{0, 0};
+    const cpx2<T> v = in ? *reinterpret_cast<const cpx2<T>*>(
+                               &at32(spec + (size_t)k2 * n1 + j0, (unsigned)(kx * n2 * n1 + 2 * p)))
+                         : cpx2<T>{{0, 0}, {0, 0}};
+    sa[it] = v.a;
+    sb[it] = v.b;
   }
 }
 
