@@ -540,4 +540,31 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red /* LDS NV
   }
 }
 
+// Block totals of NV per-thread doubles written to out[0..NV) (global): the wave totals
+// are combined by NV threads in parallel, each in wave order (the same summation order as
+// block_sum), so no thread waits on a serial tail.
+template <int NV>
+__device__ __forceinline__ void block_sum_store(double (&v)[NV], double* red /* LDS NV*kWaves */,
+                                                double* __restrict__ out) {
+  static_assert(NV <= kThreads, "one thread per total");
+  const int t = thread_idx();
+  const int lane = t & 63, wave = t >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[k * kWaves + wave] = v[k];
+  }
+  __syncthreads();
+  if (t < NV) {
+    double acc = red[t * kWaves];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) acc += red[t * kWaves + w];
+    out[t] = acc;
+  }
+}
+
 }  // namespace gpdbec

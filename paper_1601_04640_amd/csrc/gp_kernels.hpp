@@ -167,7 +167,8 @@ constexpr size_t lds_bytes() {
   if (PASS == P_R2C_REAL) return X::Z + X::W;
   if (PASS == P_FFT_LINE || PASS == P_CONV_LINE) return a16(LB * (N + 1) * C) + a16(N * C);
   if (PASS == P_CONV_COL) return a16(N * (TC + 1) * C) + a16(N * C);
-  if (PASS == P_C2R_STEP || PASS == P_ADJ_X) return X::Z + X::PS + X::W + X::MT + X::RED;
+  if (PASS == P_C2R_STEP) return (X::Z > X::PS ? X::Z : X::PS) + X::W + X::MT + X::RED;
+  if (PASS == P_ADJ_X) return X::Z + X::PS + X::W + X::MT + X::RED;
   if (PASS == P_C2R_OBS) return X::Z + X::W + X::RED;
   if (PASS == P_CN_COL) return CT<T, N>::B + CT<T, N>::MT + CT<T, N>::RED;
   if (PASS == P_ADJ_FIN) return X::Z + X::W;
@@ -254,11 +255,7 @@ __device__ __forceinline__ void r2c_x_body(const cpx<T>* __restrict__ psi,
                 {hf * (zk.im + zm.im), hf * (zm.re - zk.re)}};  // n1 even: line j+1 exists
   }
   double sums[2] = {(double)ps[0], (double)ps[1]};
-  block_sum<2>(sums, red);
-  if (tid == 0) {
-    partials[bid * 2 + 0] = sums[0];
-    partials[bid * 2 + 1] = sums[1];
-  }
+  block_sum_store<2>(sums, red, partials + bid * 2);
 }
 
 // Real-to-complex x pass of a real field f (the adjoint's second convolution input).
@@ -527,8 +524,11 @@ __device__ __forceinline__ void c2r_nl_cnx_body(
   using IT = Iters<TJ * N0>;
   using IH = Iters<(N0 / 2 + 1) * NP>;
   Carve cv{lds};
-  cpx<T>* Z = cv.take<cpx<T>>(NP * LSZ);
-  cpx<T>* PS = STEP ? cv.take<cpx<T>>(TJ * LSP) : nullptr;
+  // The step modes keep the CN lines in the FFT tile's memory (Phi is read into registers
+  // before the first CN write): the smaller footprint lets more blocks share a CU.
+  constexpr int ZL = NP * LSZ, PL = STEP ? TJ * LSP : 0;
+  cpx<T>* Z = cv.take<cpx<T>>(ZL > PL ? ZL : PL);
+  cpx<T>* PS = STEP ? Z : nullptr;
   cpx<T>* W = cv.take<cpx<T>>(N0);
   cpx<T>* MT = STEP ? cv.take<cpx<T>>(cn_table_len<N0, PX>()) : nullptr;
   double* red = cv.take<double>(8 * kWaves);
@@ -570,6 +570,13 @@ __device__ __forceinline__ void c2r_nl_cnx_body(
     const T ts = (T)(*scale);
     const T h0 = (T)sc.h0, h1 = (T)sc.h1;
     const double zc = (k2 - n2 / 2) * sc.h2;
+    T phv[IT::N];
+#pragma unroll
+    for (int it = 0; it < IT::N; ++it) {
+      const int u = tid + it * kThreads;
+      phv[it] = IT::valid(u) ? tile_real(Z, LSZ, u / N0, u % N0) : (T)0;
+    }
+    if constexpr (STEP) __syncthreads();  // every Phi read before PS (= Z) is written
 #pragma unroll
     for (int it = 0; it < IT::N; ++it) {
       const int u = tid + it * kThreads;
@@ -580,7 +587,7 @@ __device__ __forceinline__ void c2r_nl_cnx_body(
         if constexpr (STEP) PS[jl * LSP + cpad<SX>(i)] = cpx<T>{0, 0};
         continue;
       }
-      const T phi = tile_real(Z, LSZ, jl, i);
+      const T phi = phv[it];
       const cpx<T> p = scl(pv[it], ts);
       const T v = vv[it];
       const T n = p.re * p.re + p.im * p.im;
@@ -604,15 +611,6 @@ __device__ __forceinline__ void c2r_nl_cnx_body(
         PS[jl * LSP + cpad<SX>(i)] = p * f;
       }
     }
-    double sums[7];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) sums[k] = (double)ps[k];
-    sums[6] = zc * zc * sums[0];
-    block_sum<7>(sums, red);
-    if (tid == 0) {
-#pragma unroll
-      for (int k = 0; k < 7; ++k) partials[bid * 7 + k] = sums[k];
-    }
     if constexpr (STEP) {
       __syncthreads();
       cn_solve_lines<T, N0, TJ, LSP, 1, PX, cn_imag_a<MODE>()>(PS, MT, cn_a<T, MODE>(sc.Ar));
@@ -623,6 +621,12 @@ __device__ __forceinline__ void c2r_nl_cnx_body(
         if (IT::valid(u) && j0 + jl < n1) at32(psi + pbase, (unsigned)u) = PS[jl * LSP + cpad<SX>(i)];
       }
     }
+    // the block reduction of the observables sums comes last, off the solve's path
+    double sums[7];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) sums[k] = (double)ps[k];
+    sums[6] = zc * zc * sums[0];
+    block_sum_store<7>(sums, red, partials + bid * 7);
   }
 }
 
@@ -683,13 +687,7 @@ __device__ __forceinline__ void cn_col_body(cpx<T>* __restrict__ psi,
       if (r + 1 < N) sums[1] += absdiff2_d(B[cpad<SC>(r + 1) * RS + c], val);
     }
   }
-  if constexpr (SUMS) {
-    block_sum<2>(sums, red);
-    if (tid == 0) {
-      partials[bid * 2 + 0] = sums[0];
-      partials[bid * 2 + 1] = sums[1];
-    }
-  }
+  if constexpr (SUMS) block_sum_store<2>(sums, red, partials + bid * 2);
 }
 
 // ============================================================ adjoint bodies
@@ -768,11 +766,7 @@ __device__ __forceinline__ void adj_x_body(
     sums[0] += (double)s * (double)n;
     sums[1] += (double)s * (double)phi;
   }
-  block_sum<2>(sums, red);
-  if (tid == 0) {
-    partials[bid * 2 + 0] = sums[0];
-    partials[bid * 2 + 1] = sums[1];
-  }
+  block_sum_store<2>(sums, red, partials + bid * 2);
 }
 
 // Adjoint closing x pass: K s from the spectrum; lambda = mu + (g_c s + g_dd K s) psi_n.
