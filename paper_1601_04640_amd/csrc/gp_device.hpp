@@ -512,19 +512,42 @@ constexpr int cn_table_len() {
 }
 
 // ------------------------------------------------------------- reductions
+// Moves a double between lanes with one DPP control (both 32-bit halves), so a lane
+// reads another lane's register directly instead of through the LDS crossbar.  Lanes
+// whose source lies outside the wave receive an unspecified value.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                          (unsigned)lo));
+}
+
+// Sum over the 64 lanes of a wave, valid in lane 63 only, in a fixed order: pairs, quads,
+// half rows and rows of 16 (every lane of a row then holds the row total), then row 2
+// into row 3 (and row 0 into row 1), then rows 0-1 (lane 31) into row 3.  Lanes of
+// rows 0-2 end with partial or unspecified values.
+__device__ __forceinline__ double wave_sum_to_last(double v) {
+  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);  // row_half_mirror
+  v += dpp_f64<0x140>(v);  // row_mirror
+  v += dpp_f64<0x142>(v);  // row_bcast:15 (lane 15 of each row to the next row)
+  v += dpp_f64<0x143>(v);  // row_bcast:31 (lane 31 to rows 2 and 3)
+  return v;
+}
+
 // Deterministic FP64 block sum of NV values per thread; result valid in thread 0.
-// Butterfly reduction inside each wave64 (shuffles), then the kThreads/64 wave totals
-// are added in wave order: one barrier, fixed summation order.
+// Each wave sums in registers (wave_sum_to_last), then the kThreads/64 wave totals are
+// added in wave order: one barrier, fixed summation order.
 constexpr int kWaves = kThreads / 64;
 template <int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double* red /* LDS NV*kWaves */) {
   const int lane = thread_idx() & 63, wave = thread_idx() >> 6;
 #pragma unroll
-  for (int k = 0; k < NV; ++k) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
-  }
-  if (lane == 0) {
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum_to_last(v[k]);
+  if (lane == 63) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) red[k * kWaves + wave] = v[k];
   }
@@ -550,11 +573,8 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NV], double* red /* 
   const int t = thread_idx();
   const int lane = t & 63, wave = t >> 6;
 #pragma unroll
-  for (int k = 0; k < NV; ++k) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
-  }
-  if (lane == 0) {
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum_to_last(v[k]);
+  if (lane == 63) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) red[k * kWaves + wave] = v[k];
   }
