@@ -3,7 +3,7 @@
 //   * LdsFFT            batched mixed-radix (2, 3, 4, 5) Stockham FFT of lines held in LDS
 //   * cn_solve_lines    constant-coefficient tridiagonal Crank-Nicolson solves of lines in
 //                       LDS, several lanes per line, exact chunked scan of the two Thomas
-//                       recurrences across the lanes (wave shuffles)
+//                       recurrences across the lanes (DPP lane moves)
 //   * block_sum         deterministic FP64 block reductions
 // All kernels run with 256 threads per block (4 wave64s).
 #pragma once
@@ -219,20 +219,63 @@ struct LdsFFT {
   }
 };
 
+// ------------------------------------------------------------------ lane moves
+// DPP moves: a lane reads another lane's register directly, without the LDS crossbar.
+// A wave64 is four rows of 16 lanes.  Lanes whose source lies outside their row
+// (row_shl / row_shr), or outside the wave, receive an unspecified value, which callers
+// select away.  Every lane of the wave must be active.
+enum : int {
+  DPP_QUAD_1032 = 0xB1,        // quad_perm [1,0,3,2]
+  DPP_QUAD_2301 = 0x4E,        // quad_perm [2,3,0,1]
+  DPP_ROW_SHL = 0x100,         // + k: lane reads lane + k of its row
+  DPP_ROW_SHR = 0x110,         // + k: lane reads lane - k of its row
+  DPP_WAVE_SHL1 = 0x130,       // lane reads lane + 1
+  DPP_WAVE_SHR1 = 0x138,       // lane reads lane - 1
+  DPP_ROW_MIRROR = 0x140,      // lane reads lane 15 - l of its row
+  DPP_ROW_HALF_MIRROR = 0x141, // the same within each half row of 8
+  DPP_ROW_BCAST15 = 0x142,     // row r reads lane 15 of row r - 1
+  DPP_ROW_BCAST31 = 0x143,     // rows 2 and 3 read lane 31
+};
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                          (unsigned)lo));
+}
+template <int CTRL, typename T>
+__device__ __forceinline__ cpx<T> dpp(cpx<T> v) {
+  return cpx<T>{dpp<CTRL>(v.re), dpp<CTRL>(v.im)};
+}
+// The value of lane LANE, in every lane.
+template <int LANE>
+__device__ __forceinline__ float lane_val(float v) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), LANE));
+}
+template <int LANE>
+__device__ __forceinline__ double lane_val(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)b, LANE);
+  const int hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), LANE);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                          (unsigned)lo));
+}
+template <int LANE, typename T>
+__device__ __forceinline__ cpx<T> lane_val(cpx<T> v) {
+  return cpx<T>{lane_val<LANE>(v.re), lane_val<LANE>(v.im)};
+}
+
 // ---------------------------------------------------- Crank-Nicolson line solves
 // Chunk-padded position of element i for a line split into chunks of S elements: one
 // spare slot after every chunk keeps the P lanes of a line on distinct LDS banks.
 template <int S>
 __device__ __forceinline__ int cpad(int i) { return i + i / S; }
 
-template <typename T>
-__device__ __forceinline__ cpx<T> shfl_up_c(cpx<T> v, int off, int width) {
-  return {__shfl_up(v.re, off, width), __shfl_up(v.im, off, width)};
-}
-template <typename T>
-__device__ __forceinline__ cpx<T> shfl_down_c(cpx<T> v, int off, int width) {
-  return {__shfl_down(v.re, off, width), __shfl_down(v.im, off, width)};
-}
 
 // Solve, for NL lines of N points (two Dirichlet end points included) held in LDS at
 // buf[l*LS + cpad<S>(i)*ES] with S = ceil(N/P):
@@ -246,7 +289,7 @@ __device__ __forceinline__ cpx<T> shfl_down_c(cpx<T> v, int off, int width) {
 //     backward  u_i = d_i + g_i u_{i+1}
 // (m = 0 on the two boundary rows makes them u = 0).  Each recurrence is an affine map
 // per chunk, composed across the P lanes of a line by a Hillis-Steele scan of (gain,
-// offset) pairs through wave shuffles, then re-run with the exact carry-in.  P divides
+// offset) pairs through DPP lane moves, then re-run with the exact carry-in.  P divides
 // 64, so one line never spans two waves.  mt holds m_i in LDS at cpad<S>(i) (the same
 // chunk padding as the data, so the P lanes of a line read distinct banks); each lane
 // reads its chunk, its two neighbours and its m_i once into registers.  Every thread
@@ -257,14 +300,6 @@ template <typename T>
 __device__ __forceinline__ cpx<T> mulg(cpx<T> g, cpx<T> x) { return g * x; }
 template <typename T>
 __device__ __forceinline__ cpx<T> mulg(T g, cpx<T> x) { return {g * x.re, g * x.im}; }
-template <typename T>
-__device__ __forceinline__ T shfl_up_g(T v, int off, int w) { return __shfl_up(v, off, w); }
-template <typename T>
-__device__ __forceinline__ cpx<T> shfl_up_g(cpx<T> v, int off, int w) { return shfl_up_c(v, off, w); }
-template <typename T>
-__device__ __forceinline__ T shfl_down_g(T v, int off, int w) { return __shfl_down(v, off, w); }
-template <typename T>
-__device__ __forceinline__ cpx<T> shfl_down_g(cpx<T> v, int off, int w) { return shfl_down_c(v, off, w); }
 
 template <typename T, bool IMAG_A>
 struct CnArith {
@@ -297,10 +332,28 @@ template <typename T>
 __device__ __forceinline__ cpx<T> csel(bool c, cpx<T> a, cpx<T> b) {
   return cpx<T>{c ? a.re : b.re, c ? a.im : b.im};
 }
+template <typename T>
+__device__ __forceinline__ T csel(bool c, T a, T b) {
+  return c ? a : b;
+}
+
+// One step of the scan of chunk maps x -> V + G x: where `take`, compose the lane's map
+// with the map (Gs, Vs) of the chunk it depends on, V + G (Vs + Gs x).
+template <typename T, typename GT>
+__device__ __forceinline__ void cn_compose(GT& G, cpx<T>& V, GT Gs, cpx<T> Vs, bool take) {
+  const cpx<T> Vn = mulg(G, Vs) + V;
+  const GT Gn = G * Gs;
+  V = csel(take, Vn, V);
+  G = csel(take, Gn, G);
+}
+template <int CTRL, typename T, typename GT>
+__device__ __forceinline__ void cn_scan_step(GT& G, cpx<T>& V, bool take) {
+  cn_compose(G, V, dpp<CTRL>(G), dpp<CTRL>(V), take);
+}
 
 template <typename T, int N, int NL, int LS, int ES, int P, bool IMAG_A>
 __device__ __forceinline__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt, T a) {
-  static_assert(64 % P == 0 && NL * P == kThreads, "lanes per line");
+  static_assert(64 % P == 0 && P <= 32 && NL * P == kThreads, "lanes per line");
   constexpr int S = (N + P - 1) / P;
   constexpr bool FULL = (N % P == 0);  // every lane's chunk lies inside the line
   using AR = CnArith<T, IMAG_A>;
@@ -376,20 +429,21 @@ __device__ __forceinline__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt, T 
     D = r[e] + mulg(g[e], D);
     Gc = g[e] * Gc;
   }
+  // Lines of P <= 16 lanes lie inside one row of 16 lanes; a line of 32 lanes spans two
+  // rows.  The scans move values with DPP: row shifts inside a row, then one step across
+  // the row pair.
+  constexpr int PR = P < 16 ? P : 16;
+  const int rq = tid & (PR - 1);  // lane within the line's part of its row
   cpx<T> din = {0, 0};
   if constexpr (P > 1) {
     GT Gn = Gc;
-#pragma unroll
-    for (int off = 1; off < P; off <<= 1) {
-      const GT Gp = shfl_up_g(Gn, off, P);
-      const cpx<T> Dp = shfl_up_c(D, off, P);
-      if (q >= off) {
-        D = mulg(Gn, Dp) + D;
-        Gn = Gn * Gp;
-      }
-    }
-    din = shfl_up_c(D, 1, P);
-    din = csel(q == 0, zero, din);
+    if constexpr (PR > 1) cn_scan_step<DPP_ROW_SHR + 1>(Gn, D, rq >= 1);
+    if constexpr (PR > 2) cn_scan_step<DPP_ROW_SHR + 2>(Gn, D, rq >= 2);
+    if constexpr (PR > 4) cn_scan_step<DPP_ROW_SHR + 4>(Gn, D, rq >= 4);
+    if constexpr (PR > 8) cn_scan_step<DPP_ROW_SHR + 8>(Gn, D, rq >= 8);
+    // the upper row of a 32-lane line takes the total of the lower row (its lane 15)
+    if constexpr (P == 32) cn_scan_step<DPP_ROW_BCAST15>(Gn, D, (tid & 16) != 0);
+    din = csel(q == 0, zero, dpp<DPP_WAVE_SHR1>(D));
   }
   {
     cpx<T> d = din;
@@ -407,17 +461,19 @@ __device__ __forceinline__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt, T 
   cpx<T> xin = {0, 0};
   if constexpr (P > 1) {
     GT Gn = Gc;
-#pragma unroll
-    for (int off = 1; off < P; off <<= 1) {
-      const GT Gq = shfl_down_g(Gn, off, P);
-      const cpx<T> Xn = shfl_down_c(X, off, P);
-      if (q + off < P) {
-        X = mulg(Gn, Xn) + X;
-        Gn = Gn * Gq;
-      }
+    if constexpr (PR > 1) cn_scan_step<DPP_ROW_SHL + 1>(Gn, X, rq + 1 < PR);
+    if constexpr (PR > 2) cn_scan_step<DPP_ROW_SHL + 2>(Gn, X, rq + 2 < PR);
+    if constexpr (PR > 4) cn_scan_step<DPP_ROW_SHL + 4>(Gn, X, rq + 4 < PR);
+    if constexpr (PR > 8) cn_scan_step<DPP_ROW_SHL + 8>(Gn, X, rq + 8 < PR);
+    if constexpr (P == 32) {
+      // the lower row of a 32-lane line takes the total of the upper row, held by the
+      // upper row's first lane (16 or 48)
+      const bool second = (tid & 32) != 0;
+      const GT Gs = csel(second, lane_val<48>(Gn), lane_val<16>(Gn));
+      const cpx<T> Xs = csel(second, lane_val<48>(X), lane_val<16>(X));
+      cn_compose(Gn, X, Gs, Xs, (tid & 16) == 0);
     }
-    xin = shfl_down_c(X, 1, P);
-    xin = csel(q == P - 1, zero, xin);
+    xin = csel(q == P - 1, zero, dpp<DPP_WAVE_SHL1>(X));
   }
   {
     cpx<T> x = xin;
@@ -512,29 +568,17 @@ constexpr int cn_table_len() {
 }
 
 // ------------------------------------------------------------- reductions
-// Moves a double between lanes with one DPP control (both 32-bit halves), so a lane
-// reads another lane's register directly instead of through the LDS crossbar.  Lanes
-// whose source lies outside the wave receive an unspecified value.
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
-  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
-                                          (unsigned)lo));
-}
-
 // Sum over the 64 lanes of a wave, valid in lane 63 only, in a fixed order: pairs, quads,
 // half rows and rows of 16 (every lane of a row then holds the row total), then row 2
 // into row 3 (and row 0 into row 1), then rows 0-1 (lane 31) into row 3.  Lanes of
 // rows 0-2 end with partial or unspecified values.
 __device__ __forceinline__ double wave_sum_to_last(double v) {
-  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
-  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
-  v += dpp_f64<0x141>(v);  // row_half_mirror
-  v += dpp_f64<0x140>(v);  // row_mirror
-  v += dpp_f64<0x142>(v);  // row_bcast:15 (lane 15 of each row to the next row)
-  v += dpp_f64<0x143>(v);  // row_bcast:31 (lane 31 to rows 2 and 3)
+  v += dpp<DPP_QUAD_1032>(v);
+  v += dpp<DPP_QUAD_2301>(v);
+  v += dpp<DPP_ROW_HALF_MIRROR>(v);
+  v += dpp<DPP_ROW_MIRROR>(v);
+  v += dpp<DPP_ROW_BCAST15>(v);
+  v += dpp<DPP_ROW_BCAST31>(v);
   return v;
 }
 
