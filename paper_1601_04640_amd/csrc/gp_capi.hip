@@ -85,6 +85,7 @@ gp_status validate(const gp_params* p) {
 
 int tj_of(bool fp64, int n) { return fp64 ? Launch<double>::tj(n) : Launch<float>::tj(n); }
 int tc_of(bool fp64, int n) { return fp64 ? Launch<double>::tc(n) : Launch<float>::tc(n); }
+int tv_of(bool fp64, int n) { return fp64 ? Launch<double>::tv(n) : Launch<float>::tv(n); }
 
 Layout make_layout(const gp_params* p) {
   Layout L{};
@@ -289,7 +290,7 @@ struct Passes {
     if (c->p.geom == GP_3D) {
       const int nl = H * L.n2;
       const int lb = c->fp64 ? Launch<double>::lb(L.n1) : Launch<float>::lb(L.n1);
-      const int tc = tc_of(c->fp64, L.n2);
+      const int tc = tv_of(c->fp64, L.n2);
       GP_PASS(c, GP_PASS_FFT_Y_FWD,
               Launch<T>::fft_line(L.n1, false, (nl + lb - 1) / lb, c->st, spec(c), tw(c, 1), nl));
       GP_PASS(c, GP_PASS_CONV_Z,

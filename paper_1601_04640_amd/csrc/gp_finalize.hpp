@@ -34,34 +34,37 @@ constexpr int kStageVals = 11;   // totals carried per slice (the v[] of finaliz
 constexpr int kStageMax = 256;   // slices of the two-stage reduction (<= kThreads)
 
 // Sums the partial arrays a block reads, blocks [lo, hi) of each, into v[11] (per
-// thread; fixed order).  4 slots per iteration keep 4 loads in flight.
+// thread; fixed order).  Each iteration first issues the loads of 4 blocks of every
+// array, then adds them, so a small step's partials arrive in one memory round trip.
 __device__ inline void fin_gather(const FinArgs& a, int mode, int slice, int nslice,
                                   double (&v)[11]) {
   const int tid = threadIdx.x;
-  auto acc = [&](const double* p, int nb, int stride, int k0, int nk) {
-    const int lo = (int)((long long)nb * slice / nslice);
-    const int hi = (int)((long long)nb * (slice + 1) / nslice);
-    for (int b0 = lo + tid; b0 < hi; b0 += 4 * kThreads) {
-      double t[4][7];
+  const bool xnl = mode != FIN_EKZ;
+  const bool col = mode != FIN_OBSERVE || a.geom == 0;
+  auto lo_of = [&](int nb) { return (int)((long long)nb * slice / nslice); };
+  auto hi_of = [&](int nb) { return (int)((long long)nb * (slice + 1) / nslice); };
+  const int lx = lo_of(a.nb_x), nx = xnl ? hi_of(a.nb_x) - lx : 0;
+  const int ln = lo_of(a.nb_nl), nn = xnl ? hi_of(a.nb_nl) - ln : 0;
+  const int lc = lo_of(a.nb_col), nc = col ? hi_of(a.nb_col) - lc : 0;
+  const int span = nx > nn ? (nx > nc ? nx : nc) : (nn > nc ? nn : nc);
+  for (int b0 = tid; b0 < span; b0 += 4 * kThreads) {
+    double t[4][11];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int b = b0 + u * kThreads;
+    for (int u = 0; u < 4; ++u) {
+      const int b = b0 + u * kThreads;
 #pragma unroll
-        for (int k = 0; k < 7; ++k) t[u][k] = (k < nk && b < hi) ? p[(size_t)stride * b + k] : 0.0;
-      }
+      for (int k = 0; k < 2; ++k) t[u][k] = b < nx ? a.p_x[2 * (size_t)(lx + b) + k] : 0.0;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int k = 0; k < 7; ++k) t[u][2 + k] = b < nn ? a.p_nl[7 * (size_t)(ln + b) + k] : 0.0;
 #pragma unroll
-        for (int k = 0; k < 7; ++k)
-          if (k < nk) v[k0 + k] += t[u][k];
-      }
+      for (int k = 0; k < 2; ++k) t[u][9 + k] = b < nc ? a.p_col[2 * (size_t)(lc + b) + k] : 0.0;
     }
-  };
-  if (mode != FIN_EKZ) {
-    acc(a.p_x, a.nb_x, 2, 0, 2);
-    acc(a.p_nl, a.nb_nl, 7, 2, 7);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+#pragma unroll
+      for (int k = 0; k < 11; ++k) v[k] += t[u][k];
+    }
   }
-  if (mode != FIN_OBSERVE || a.geom == 0) acc(a.p_col, a.nb_col, 2, 9, 2);
 }
 
 // First stage of the two-stage reduction: block g writes the totals of slice g.
@@ -85,6 +88,14 @@ __device__ inline void finalize_block(const FinArgs& a, int mode) {
   double v[11];
 #pragma unroll
   for (int k = 0; k < 11; ++k) v[k] = 0.0;
+  // the scalars thread 0 needs at the end are fetched before the gather
+  double s = 1.0, ekz_in = 0.0;
+  int pos = 0;
+  if (tid == 0) {
+    s = *a.scale;
+    if (mode != FIN_EKZ && mode != FIN_OBSERVE && a.geom == 0) ekz_in = *a.ekz;
+    if (mode != FIN_EKZ && mode != FIN_OBSERVE) pos = *a.ring_pos;
+  }
   if (a.nstage > 0) {
     // one pre-reduced slice per thread (nstage <= kStageMax < kThreads), then the
     // fixed-order block sum
@@ -97,7 +108,6 @@ __device__ inline void finalize_block(const FinArgs& a, int mode) {
   }
   block_sum<11>(v, red);
   if (tid != 0) return;
-  const double s = *a.scale;
   const double s2 = s * s;
   if (mode == FIN_EKZ) {
     *a.ekz = 0.5 * s2 * v[10] / (a.h2 * a.h2) * a.dV;
@@ -108,7 +118,7 @@ __device__ inline void finalize_block(const FinArgs& a, int mode) {
   const double norm = v[2] * dV;
   double ekin = 0.5 * s2 * (v[0] / (a.h0 * a.h0) + v[1] / (a.h1 * a.h1)) * dV;
   if (a.geom == 0) {
-    ekin += (mode == FIN_OBSERVE) ? 0.5 * s2 * v[10] / (a.h2 * a.h2) * dV : *a.ekz;
+    ekin += (mode == FIN_OBSERVE) ? 0.5 * s2 * v[10] / (a.h2 * a.h2) * dV : ekz_in;
   }
   const double epot = v[3] * dV;
   const double eint = 0.5 * a.gc * v[4] * dV;
@@ -129,7 +139,6 @@ __device__ inline void finalize_block(const FinArgs& a, int mode) {
   if (mode == FIN_OBSERVE) {
     dst = a.obs;
   } else {
-    const int pos = *a.ring_pos;
     dst = a.ring + (size_t)(pos % a.ring_cap) * kRecord;
     *a.ring_pos = pos + 1;
   }

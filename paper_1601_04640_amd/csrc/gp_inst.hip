@@ -240,6 +240,17 @@ int Launch<T>::tc(int n) {
   return 0;
 }
 template <>
+int Launch<T>::tv(int n) {
+  switch (n) {
+#define X(N) \
+  case N:    \
+    return Tiles<T, N>::TV;
+    GP_FOR_SIZES(X)
+#undef X
+  }
+  return 0;
+}
+template <>
 int Launch<T>::lb(int n) {
   switch (n) {
 #define X(N) \

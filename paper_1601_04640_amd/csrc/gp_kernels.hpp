@@ -47,6 +47,9 @@ namespace gpdbec {
 #ifndef GP_LB_POINTS
 #define GP_LB_POINTS 1024
 #endif
+#ifndef GP_TV_SPLIT_BYTES
+#define GP_TV_SPLIT_BYTES 65536
+#endif
 
 template <typename T, int N>
 struct Tiles {
@@ -59,6 +62,9 @@ struct Tiles {
   static constexpr int TC =
       ((N + 15) / 16 > (sizeof(T) == 8 ? GP_TC_SPLIT_FP64 : GP_TC_SPLIT_FP32)) ? 8 : 16;
   static constexpr int PC = kThreads / TC;
+  // columns per tile of the z convolution: 16, or 8 when a 16-column tile would take more
+  // than GP_TV_SPLIT_BYTES of LDS (more resident blocks per CU)
+  static constexpr int TV = ((size_t)N * 17 * 2 * sizeof(T) > (size_t)GP_TV_SPLIT_BYTES) ? 8 : 16;
   // contiguous lines per block of the line FFT passes
   static constexpr int LB = (GP_LB_POINTS / N) < 1 ? 1 : (GP_LB_POINTS / N);
 };
@@ -166,7 +172,7 @@ constexpr size_t lds_bytes() {
   if (PASS == P_R2C) return X::Z + X::W + X::RED;
   if (PASS == P_R2C_REAL) return X::Z + X::W;
   if (PASS == P_FFT_LINE || PASS == P_CONV_LINE) return a16(LB * (N + 1) * C) + a16(N * C);
-  if (PASS == P_CONV_COL) return a16(N * (TC + 1) * C) + a16(N * C);
+  if (PASS == P_CONV_COL) return a16(N * (Tiles<T, N>::TV + 1) * C) + a16(N * C);
   if (PASS == P_C2R_STEP) return (X::Z > X::PS ? X::Z : X::PS) + X::W + X::MT + X::RED;
   if (PASS == P_ADJ_X) return X::Z + X::PS + X::W + X::MT + X::RED;
   if (PASS == P_C2R_OBS) return X::Z + X::W + X::RED;
@@ -405,7 +411,7 @@ __device__ __forceinline__ void conv_col_body(cpx<T>* __restrict__ spec,
                                               const T* __restrict__ ktab,
                                               const cpx<T>* __restrict__ tw2, int n1, int bid,
                                               char* lds) {
-  constexpr int TC = Tiles<T, N2>::TC, RS = TC + 1;
+  constexpr int TC = Tiles<T, N2>::TV, RS = TC + 1;
   using IT = Iters<N2 * TC>;
   Carve cv{lds};
   cpx<T>* B = cv.take<cpx<T>>(N2 * RS);

@@ -23,6 +23,7 @@ struct Launch {
   // tile geometry of the pass kernels for line length n
   static int tj(int n);  // x lines per block
   static int tc(int n);  // columns per block (strided passes)
+  static int tv(int n);  // columns per block (z convolution)
   static int lb(int n);  // contiguous lines per block
 
   static hipError_t r2c_x(int n0, int blocks, hipStream_t st, const cpx<T>* psi,
@@ -59,6 +60,7 @@ struct Launch {
 #define GP_DECLARE_LAUNCH(T)                                                                  \
   template <> int Launch<T>::tj(int);                                                         \
   template <> int Launch<T>::tc(int);                                                         \
+  template <> int Launch<T>::tv(int);                                                         \
   template <> int Launch<T>::lb(int);                                                         \
   template <> hipError_t Launch<T>::r2c_x(int, int, hipStream_t, const cpx<T>*, const double*, \
                                           cpx<T>*, const cpx<T>*, double*, int, int);          \
