@@ -72,9 +72,15 @@ struct RadixPlan {
   int n;
   int r[16];
 };
-constexpr RadixPlan make_plan(int N) {
+// Radices of a Stockham plan for length N: powers of two up to RMAX (16, 8 or 4) first,
+// then 2, 3, 5.
+constexpr RadixPlan make_plan(int N, int RMAX = 4) {
   RadixPlan p{0, {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
   int m = N;
+  if (RMAX >= 16)
+    while (m % 16 == 0) { p.r[p.n++] = 16; m /= 16; }
+  if (RMAX >= 8)
+    while (m % 8 == 0) { p.r[p.n++] = 8; m /= 8; }
   while (m % 4 == 0) { p.r[p.n++] = 4; m /= 4; }
   while (m % 2 == 0) { p.r[p.n++] = 2; m /= 2; }
   while (m % 3 == 0) { p.r[p.n++] = 3; m /= 3; }
@@ -88,8 +94,8 @@ constexpr bool plan_ok(int N) {
   while (m % 5 == 0) m /= 5;
   return m == 1;
 }
-constexpr int plan_span(int N, int s) {  // product of the radices before stage s
-  RadixPlan p = make_plan(N);
+constexpr int plan_span(int N, int s, int RMAX = 4) {  // product of the radices before stage s
+  RadixPlan p = make_plan(N, RMAX);
   int L = 1;
   for (int i = 0; i < s; ++i) L *= p.r[i];
   return L;
@@ -142,12 +148,54 @@ __device__ __forceinline__ void dft5(cpx<T>* x) {
   x[2] = a2 + b2;
   x[3] = a2 - b2;
 }
+// exp(-2 pi i e/16) for 0 <= e < 16 (forward sign; INV conjugates).
+template <typename T, bool INV>
+__device__ __forceinline__ cpx<T> w16(int e) {
+  constexpr double c1 = 0.92387953251128675613, s1 = 0.38268343236508977173;  // pi/8
+  constexpr double h = 0.70710678118654752440;                                // pi/4
+  constexpr double cs[16] = {1, c1, h, s1, 0, -s1, -h, -c1, -1, -c1, -h, -s1, 0, s1, h, c1};
+  const double c = cs[e & 15], sn = cs[(e + 12) & 15];  // sin(a) = cos(a - pi/2)
+  return cpx<T>{(T)c, INV ? (T)sn : (T)-sn};
+}
+
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dft(cpx<T>* x);
+
+// DFT of length R = R1 R2 from DFTs of lengths R1 and R2 (R divides 16): with
+// n = R2 n1 + n2 and k = k1 + R1 k2,
+//   X[k1 + R1 k2] = sum_n2 W_R2^(n2 k2) W_R^(n2 k1) sum_n1 W_R1^(n1 k1) x[R2 n1 + n2].
+template <typename T, int R1, int R2, bool INV>
+__device__ __forceinline__ void dft_split(cpx<T>* x) {
+  constexpr int R = R1 * R2;
+  cpx<T> y[R2][R1];
+#pragma unroll
+  for (int n2 = 0; n2 < R2; ++n2) {
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) y[n2][n1] = x[R2 * n1 + n2];
+    dft<T, R1, INV>(y[n2]);
+#pragma unroll
+    for (int k1 = 1; k1 < R1; ++k1)
+      if (n2 > 0) y[n2][k1] = y[n2][k1] * w16<T, INV>((16 / R) * n2 * k1);
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < R1; ++k1) {
+    cpx<T> b[R2];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) b[n2] = y[n2][k1];
+    dft<T, R2, INV>(b);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) x[k1 + R1 * k2] = b[k2];
+  }
+}
+
 template <typename T, int R, bool INV>
 __device__ __forceinline__ void dft(cpx<T>* x) {
   if constexpr (R == 2) dft2<T, INV>(x);
   else if constexpr (R == 3) dft3<T, INV>(x);
   else if constexpr (R == 4) dft4<T, INV>(x);
-  else dft5<T, INV>(x);
+  else if constexpr (R == 5) dft5<T, INV>(x);
+  else if constexpr (R == 8) dft_split<T, 4, 2, INV>(x);
+  else dft_split<T, 4, 4, INV>(x);
 }
 
 // --------------------------------------------------------------- LDS FFT
@@ -159,14 +207,17 @@ __device__ __forceinline__ void dft(cpx<T>* x) {
 // returns after a final barrier.  Forward: unnormalised exp(-i...); INV: exp(+i...).
 template <typename T, int N, int NL, int LS, int ES, bool LINE_FAST>
 struct LdsFFT {
-  static constexpr RadixPlan P = make_plan(N);
+  // Radices up to 16 while every thread still has a butterfly of each stage (a block of
+  // NL lines of N points); never below 4.
+  static constexpr int RMAX = (NL * N >= 16 * kThreads) ? 16 : (NL * N >= 8 * kThreads) ? 8 : 4;
+  static constexpr RadixPlan P = make_plan(N, RMAX);
   static_assert(plan_ok(N), "FFT length must factor into 2, 3, 5");
 
   template <int S, bool INV>
   __device__ static __forceinline__ void stage(cpx<T>* buf, const cpx<T>* tw) {
     if constexpr (S < P.n) {
       constexpr int R = P.r[S];
-      constexpr int L = plan_span(N, S);
+      constexpr int L = plan_span(N, S, RMAX);
       constexpr int NB = N / R;                 // butterflies per line
       constexpr int TOT = NL * NB;
       constexpr int IT = (TOT + kThreads - 1) / kThreads;
