@@ -433,13 +433,51 @@ __device__ __forceinline__ void conv_col_body(cpx<T>* __restrict__ spec,
     kv[it] = in ? at32(ktab + plane + c0, g) : (T)0;
   }
   for (int i = tid; i < N2; i += kThreads) W[i] = tw2[i];
+  using FFT = LdsFFT<T, N2, TC, 1, RS, true>;
+  constexpr int R = IT::N;
+  if constexpr (FFT::P.n == 2 && FFT::P.r[0] == R && FFT::P.r[1] == R && kThreads / TC == R &&
+                IT::N * kThreads == N2 * TC) {
+    // N2 = R * R with R points per thread at stride R (rows g + R m of column c): the
+    // first forward stage works on the loaded registers, the second leaves spectrum
+    // index g + R m in register m, where the kernel multiply and the first inverse stage
+    // follow; the last inverse stage leaves row g + R m in register m for the store.
+    // Two LDS exchanges per tile.
+    const int c = tid % TC, g = tid / TC;
+    dft<T, R, false>(v);
+#pragma unroll
+    for (int m = 0; m < R; ++m) B[(g * R + m) * RS + c] = v[m];
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const cpx<T> e = B[(g + R * m) * RS + c];
+      v[m] = (m == 0) ? e : e * W[g * m];
+    }
+    dft<T, R, false>(v);
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[m] = scl(v[m], kv[m]);
+    dft<T, R, true>(v);
+    __syncthreads();  // every forward read of the buffer is done
+#pragma unroll
+    for (int m = 0; m < R; ++m) B[(g * R + m) * RS + c] = v[m];
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const cpx<T> e = B[(g + R * m) * RS + c];
+      v[m] = (m == 0) ? e : e * conjg(W[g * m]);
+    }
+    dft<T, R, true>(v);
+#pragma unroll
+    for (int m = 0; m < R; ++m)
+      if (c0 + c < n1) at32(spec + plane + c0, (unsigned)((g + R * m) * n1 + c)) = v[m];
+    return;
+  }
 #pragma unroll
   for (int it = 0; it < IT::N; ++it) {
     const int u = tid + it * kThreads;
     if (IT::valid(u)) B[(u / TC) * RS + u % TC] = v[it];
   }
   __syncthreads();
-  LdsFFT<T, N2, TC, 1, RS, true>::template run<false>(B, W);
+  FFT::template run<false>(B, W);
 #pragma unroll
   for (int it = 0; it < IT::N; ++it) {
     const int u = tid + it * kThreads;
@@ -449,7 +487,7 @@ __device__ __forceinline__ void conv_col_body(cpx<T>* __restrict__ spec,
     }
   }
   __syncthreads();
-  LdsFFT<T, N2, TC, 1, RS, true>::template run<true>(B, W);
+  FFT::template run<true>(B, W);
 #pragma unroll
   for (int it = 0; it < IT::N; ++it) {
     const int u = tid + it * kThreads;

@@ -29,6 +29,10 @@ CASES = {
                        gamma=1.0, nu=4.0, lam=2.5, g=20.0, gdd=15.0, R=0.0),
     "2dxy_120x96": dict(geom="2dxy", nx=120, ny=96, nz=1, dx=0.15, dy=0.15, dz=1.0, dt=0.001,
                         gamma=1.0, nu=1.2, lam=4.0, g=40.0, gdd=20.0, R=0.0),
+    # 256-point z lines: the FP32 z convolution runs as two 16-point stages held in
+    # registers; ny = 20 leaves a ragged 4-column tile
+    "3d_12x20x256": dict(geom="3d", nx=12, ny=20, nz=256, dx=0.5, dy=0.45, dz=0.04,
+                         dt=0.0005, gamma=1.0, nu=1.0, lam=1.0, g=15.0, gdd=6.0, R=2.0),
     # 2048 x-line tiles: the FP64 finalisation runs in two stages (pre-reduced slices)
     "3d_16x64x512": dict(geom="3d", nx=16, ny=64, nz=512, dx=0.45, dy=0.12, dz=0.02,
                          dt=0.0005, gamma=1.0, nu=1.0, lam=1.0, g=10.0, gdd=4.0, R=1.5),
