@@ -30,28 +30,68 @@ __device__ inline zd zinv(zd a) {
   const double d = a.re * a.re + a.im * a.im;
   return {a.re / d, -a.im / d};
 }
+
+// Each table holds m_0..m_{N-1}, then the scan weights of the line solve that sweeps
+// this axis with P lanes per line (chunks of S = ceil(N/P) points; cn_solve_lines):
+// per lane q, the gain its (gain, offset) map carries into each step of the forward
+// scan (entries s P + q) and of the backward scan (entries (NS + s) P + q), NS = log2 P.
+// They depend on the factors only: the products g of every chunk, composed across the
+// lanes in the solve's own step order.
+constexpr int kScanWeights = 2 * 5 * 32;  // 2 NS P for P <= 32
+__device__ inline void cn_scan_weights(const zd* gc, int P, cpx<double>* w) {
+  const int PR = P < 16 ? P : 16;  // lanes of a line inside one row of 16
+  int NS = 0;
+  while ((1 << NS) < P) ++NS;
+  zd G[32], H[32];
+  for (int dir = 0; dir < 2; ++dir) {
+    for (int q = 0; q < P; ++q) G[q] = gc[q];
+    int s = 0;
+    for (int off = 1; off < PR; off <<= 1, ++s) {
+      for (int q = 0; q < P; ++q) {
+        w[(dir * NS + s) * P + q] = cpx<double>{G[q].re, G[q].im};
+        const int rq = q % PR;
+        const bool take = dir == 0 ? rq >= off : rq + off < PR;
+        H[q] = take ? zmul(G[q], G[dir == 0 ? q - off : q + off]) : G[q];
+      }
+      for (int q = 0; q < P; ++q) G[q] = H[q];
+    }
+    if (P == 32)  // the step across the two rows of a 32-lane line
+      for (int q = 0; q < P; ++q) w[(dir * NS + s) * P + q] = cpx<double>{G[q].re, G[q].im};
+  }
+}
+
 // Third set: A = -i Ar, the adjoint sweep of a real-time step (conjugate factors).
 template <typename T>
-__global__ void k_cn_tables(cpx<T>* m_im, cpx<T>* g_im, cpx<T>* m_re, cpx<T>* g_re,
-                            cpx<T>* m_adj, cpx<T>* g_adj, int N, double Ar) {
+__global__ void k_cn_tables(cpx<T>* m_im, cpx<T>* m_re, cpx<T>* m_adj, int N, double Ar, int P) {
   if (blockIdx.x != 0 || threadIdx.x > 2) return;
   const int set = threadIdx.x;
   cpx<T>* mt = set == 0 ? m_im : (set == 1 ? m_re : m_adj);
-  cpx<T>* gt = set == 0 ? g_im : (set == 1 ? g_re : g_adj);
   const zd A = set == 0 ? zd{Ar, 0.0} : (set == 1 ? zd{0.0, Ar} : zd{0.0, -Ar});
   const zd a = {-A.re, -A.im};
   const zd b = {1.0 + 2.0 * A.re, 2.0 * A.im};
+  const int S = (N + P - 1) / P;
+  // chunk products of g; a chunk holding a boundary row or reaching past the line end
+  // has a zero factor
+  zd gc[32];
+  for (int q = 0; q < P; ++q) {
+    const bool zero = q == 0 || (q + 1) * S > N - 1;
+    gc[q] = zero ? zd{0.0, 0.0} : zd{1.0, 0.0};
+  }
   zd c = {0.0, 0.0};
   mt[0] = cpx<T>{0, 0};
-  gt[0] = cpx<T>{0, 0};
   for (int i = 1; i <= N - 2; ++i) {
     const zd m = zinv(zsub(b, zmul(a, c)));
     c = zmul(a, m);
     mt[i] = cpx<T>{(T)m.re, (T)m.im};
-    gt[i] = cpx<T>{(T)(-c.re), (T)(-c.im)};
+    const int q = i / S;
+    gc[q] = zmul(gc[q], zd{-c.re, -c.im});
   }
   mt[N - 1] = cpx<T>{0, 0};
-  gt[N - 1] = cpx<T>{0, 0};
+  cpx<double> w[kScanWeights];
+  cn_scan_weights(gc, P, w);
+  int NS = 0;
+  while ((1 << NS) < P) ++NS;
+  for (int k = 0; k < 2 * NS * P; ++k) mt[N + k] = cpx<T>{(T)w[k].re, (T)w[k].im};
 }
 
 // Spherical-cutoff factor b(s) = 1 + 3 cos s/s^2 - 3 sin s/s^3 (s = kR); for s < 1 the

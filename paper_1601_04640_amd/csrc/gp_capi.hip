@@ -46,7 +46,7 @@ struct Layout {
   size_t esz;           // bytes of one real value
   int nb_x, nb_col, nb_colobs;
   // byte offsets inside the workspace
-  size_t o_psi, o_V, o_spec, o_ktab, o_tw[3], o_cn[3][6], o_px, o_pnl, o_pcol, o_padj, o_sfield,
+  size_t o_psi, o_V, o_spec, o_ktab, o_tw[3], o_cn[3][3], o_px, o_pnl, o_pcol, o_padj, o_sfield,
       o_scalars, o_ring, o_obs, o_io, o_stamps, o_stage, total;
 };
 
@@ -125,7 +125,8 @@ Layout make_layout(const gp_params* p) {
   const int ns[3] = {L.n0, L.n1, L.n2};
   for (int a = 0; a < 3; ++a) {
     L.o_tw[a] = take(2 * L.esz * ns[a]);
-    for (int t = 0; t < 6; ++t) L.o_cn[a][t] = take(2 * L.esz * ns[a]);
+    // factor table and scan weights per set (imaginary time, real time, adjoint)
+    for (int t = 0; t < 3; ++t) L.o_cn[a][t] = take(2 * L.esz * (ns[a] + kScanWeights));
   }
   L.o_px = take(sizeof(double) * 2 * L.nb_x);
   L.o_pnl = take(sizeof(double) * 7 * L.nb_x);
@@ -281,6 +282,7 @@ struct Passes {
   static cpx<T>* psi(gp_ctx* c) { return c->at<cpx<T>>(c->L.o_psi); }
   static cpx<T>* spec(gp_ctx* c) { return c->at<cpx<T>>(c->L.o_spec); }
   static const cpx<T>* tw(gp_ctx* c, int a) { return c->at<cpx<T>>(c->L.o_tw[a]); }
+  // factor table of axis a, set k (0: imaginary time, 1: real time, 2: adjoint sweep)
   static const cpx<T>* cn(gp_ctx* c, int a, int k) { return c->at<cpx<T>>(c->L.o_cn[a][k]); }
 
   // y/z transforms of the x-half spectrum, U(k)/N product, inverse y/z transforms
@@ -324,11 +326,11 @@ struct Passes {
     const int tcy = tc_of(c->fp64, L.n1);
     const int nb_y = ((L.n0 + tcy - 1) / tcy) * L.n2;
     if (c->p.geom == GP_3D) {
-      GP_HIP(Launch<T>::cn_col(L.n2, MODE_ADJ, false, L.nb_col, c->st, lam, cn(c, 2, 4),
+      GP_HIP(Launch<T>::cn_col(L.n2, MODE_ADJ, false, L.nb_col, c->st, lam, cn(c, 2, 2),
                                scalars_for(c, 2).Ar, nullptr, L.n0, (size_t)L.n0 * L.n1,
                                (size_t)L.n0));
     }
-    GP_HIP(Launch<T>::cn_col(L.n1, MODE_ADJ, false, nb_y, c->st, lam, cn(c, 1, 4),
+    GP_HIP(Launch<T>::cn_col(L.n1, MODE_ADJ, false, nb_y, c->st, lam, cn(c, 1, 2),
                              scalars_for(c, 1).Ar, nullptr, L.n0, (size_t)L.n0,
                              (size_t)L.n0 * L.n1));
     GP_TRY(convolution(c, psin, &c->sc()->one));
@@ -336,7 +338,7 @@ struct Passes {
     T* sf = c->at<T>(L.o_sfield);
     double* pa = c->at<double>(L.o_padj);
     GP_HIP(Launch<T>::adj_x(L.n0, L.nb_x, c->st, lam, psin, c->at<T>(L.o_V), spec(c), tw(c, 0),
-                            cn(c, 0, 4), sx, sf, gradV, pa, L.n1, L.n2));
+                            cn(c, 0, 2), sx, sf, gradV, pa, L.n1, L.n2));
     GP_HIP(Launch<T>::r2c_real(L.n0, L.nb_x, c->st, sf, spec(c), tw(c, 0), L.n1, L.n2));
     GP_TRY(spectrum_passes(c));
     GP_HIP(Launch<T>::adj_fin(L.n0, L.nb_x, c->st, lam, psin, sf, spec(c), tw(c, 0), sx, L.n1,
@@ -373,7 +375,7 @@ struct Passes {
     const Layout& L = c->L;
     const int mode = imag ? MODE_IMAG : MODE_REAL;
     const int fin = imag ? (int)FIN_IMAG : (int)FIN_REAL;
-    const int k = imag ? 0 : 2;  // factor table: imaginary or real time
+    const int k = imag ? 0 : 1;  // factor table: imaginary or real time
     GP_TRY(convolution(c));
     const StepScalars sx = scalars_for(c, 0);
     // timed: the launch's own dispatch timestamps fill the event pair (no separate event
@@ -431,19 +433,19 @@ struct Passes {
       case GP_PASS_C2R_NL_CNX:
         return dev(Launch<T>::c2r_nl_cnx(L.n0, MODE_REAL, L.nb_x, c->st, psi(c),
                                          c->at<T>(L.o_V), &c->sc()->scale, spec(c), tw(c, 0),
-                                         cn(c, 0, 2), scalars_for(c, 0), c->at<double>(L.o_pnl),
+                                         cn(c, 0, 1), scalars_for(c, 0), c->at<double>(L.o_pnl),
                                          nullptr, L.n1, L.n2));
       case GP_PASS_CN_Y:
         if (c->p.geom == GP_3D)
           return dev(Launch<T>::cn_col(L.n1, MODE_REAL, false, ((L.n0 + tcy - 1) / tcy) * L.n2,
-                                       c->st, psi(c), cn(c, 1, 2), scalars_for(c, 1).Ar, nullptr,
+                                       c->st, psi(c), cn(c, 1, 1), scalars_for(c, 1).Ar, nullptr,
                                        L.n0, (size_t)L.n0, (size_t)L.n0 * L.n1));
-        return dev(Launch<T>::cn_col(L.n1, MODE_REAL, true, L.nb_col, c->st, psi(c), cn(c, 1, 2),
+        return dev(Launch<T>::cn_col(L.n1, MODE_REAL, true, L.nb_col, c->st, psi(c), cn(c, 1, 1),
                                      scalars_for(c, 1).Ar, c->at<double>(L.o_pcol), L.n0,
                                      (size_t)L.n0, (size_t)L.n0 * L.n1));
       case GP_PASS_CN_Z:
         if (c->p.geom != GP_3D) return GP_E_ARG;
-        return dev(Launch<T>::cn_col(L.n2, MODE_REAL, true, L.nb_col, c->st, psi(c), cn(c, 2, 2),
+        return dev(Launch<T>::cn_col(L.n2, MODE_REAL, true, L.nb_col, c->st, psi(c), cn(c, 2, 1),
                                      scalars_for(c, 2).Ar, c->at<double>(L.o_pcol), L.n0,
                                      (size_t)L.n0 * L.n1, (size_t)L.n0));
       default:
@@ -481,10 +483,12 @@ struct Passes {
       hipLaunchKernelGGL(k_twiddles<T>, dim3(blocks_for(ns[a])), dim3(kThreads), 0, c->st,
                          c->at<cpx<T>>(L.o_tw[a]), ns[a]);
       const double Ar = c->p.dt / (4.0 * hs[a] * hs[a]);
+      // lanes per line of the solve that sweeps this axis: x lines in the x pass, columns
+      // in the strided sweeps
+      const int P = kThreads / (a == 0 ? Launch<T>::tj(ns[a]) : Launch<T>::tc(ns[a]));
       hipLaunchKernelGGL(k_cn_tables<T>, dim3(1), dim3(64), 0, c->st,
                          c->at<cpx<T>>(L.o_cn[a][0]), c->at<cpx<T>>(L.o_cn[a][1]),
-                         c->at<cpx<T>>(L.o_cn[a][2]), c->at<cpx<T>>(L.o_cn[a][3]),
-                         c->at<cpx<T>>(L.o_cn[a][4]), c->at<cpx<T>>(L.o_cn[a][5]), ns[a], Ar);
+                         c->at<cpx<T>>(L.o_cn[a][2]), ns[a], Ar, P);
     }
     KernelGeom kg{};
     kg.geom = c->p.geom;
@@ -754,9 +758,9 @@ gp_status batch_write_desc(gp_batch* b) {
     d.tw0 = o + L.o_tw[0];
     d.tw1 = o + L.o_tw[1];
     d.cn0[0] = o + L.o_cn[0][0];
-    d.cn0[1] = o + L.o_cn[0][2];
+    d.cn0[1] = o + L.o_cn[0][1];
     d.cn1[0] = o + L.o_cn[1][0];
-    d.cn1[1] = o + L.o_cn[1][2];
+    d.cn1[1] = o + L.o_cn[1][1];
     d.p_x = o + L.o_px;
     d.p_nl = o + L.o_pnl;
     d.p_col = o + L.o_pcol;

@@ -388,22 +388,36 @@ __device__ __forceinline__ T csel(bool c, T a, T b) {
   return c ? a : b;
 }
 
-// One step of the scan of chunk maps x -> V + G x: where `take`, compose the lane's map
-// with the map (Gs, Vs) of the chunk it depends on, V + G (Vs + Gs x).
-template <typename T, typename GT>
-__device__ __forceinline__ void cn_compose(GT& G, cpx<T>& V, GT Gs, cpx<T> Vs, bool take) {
+// One step of the scan of chunk maps x -> V + G x with the gains composed on the fly:
+// where `take`, compose the lane's map with the map (Gs, Vs) of the lane CTRL reads,
+// V + G (Vs + Gs x).
+template <int CTRL, typename T, typename GT>
+__device__ __forceinline__ void cn_scan_step(GT& G, cpx<T>& V, bool take) {
+  const GT Gs = dpp<CTRL>(G);
+  const cpx<T> Vs = dpp<CTRL>(V);
   const cpx<T> Vn = mulg(G, Vs) + V;
   const GT Gn = G * Gs;
   V = csel(take, Vn, V);
   G = csel(take, Gn, G);
 }
+// One step of the scan with the lane's gain w for this step precomputed: where `take`,
+// V + w Vs with Vs the offset of the lane CTRL reads.
 template <int CTRL, typename T, typename GT>
-__device__ __forceinline__ void cn_scan_step(GT& G, cpx<T>& V, bool take) {
-  cn_compose(G, V, dpp<CTRL>(G), dpp<CTRL>(V), take);
+__device__ __forceinline__ void cn_scan_w(GT w, cpx<T>& V, bool take) {
+  const cpx<T> Vs = dpp<CTRL>(V);
+  V = csel(take, mulg(w, Vs) + V, V);
 }
+// A scan weight as the gain type (real gains keep the real part).
+template <typename GT, typename T>
+__device__ __forceinline__ GT scan_weight(const cpx<T>* __restrict__ w) {
+  if constexpr (std::is_same<GT, T>::value) return w->re;
+  else return *w;
+}
+constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 
 template <typename T, int N, int NL, int LS, int ES, int P, bool IMAG_A>
-__device__ __forceinline__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt, T a) {
+__device__ __forceinline__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt,
+                                               const cpx<T>* __restrict__ wt, T a) {
   static_assert(64 % P == 0 && P <= 32 && NL * P == kThreads, "lanes per line");
   constexpr int S = (N + P - 1) / P;
   constexpr bool FULL = (N % P == 0);  // every lane's chunk lies inside the line
@@ -472,13 +486,20 @@ __device__ __forceinline__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt, T 
     }
   }
   // forward recurrence d_i = r_i + g_i d_{i-1}: the chunk's affine map (Gc, D), an
-  // inclusive scan of the maps across the P lanes, then the chunk from its true input
+  // inclusive scan of the maps across the P lanes, then the chunk from its true input.
+  // The gains of the scan (Gc and its compositions) depend on the factors only.  Lines of
+  // up to 16 lanes read the gain lane q carries into step s from the table (wt[s P + q],
+  // backward wt[(NS + s) P + q]) and move only the offsets between lanes; 32-lane lines
+  // compose the gains as they go (ten table gains in flight would cost a wave of
+  // occupancy, or expose their load latency at three waves per SIMD).
+  constexpr int NS = ilog2(P);
+  constexpr bool WTAB = P <= 16;
   GT Gc = AR::one();
   cpx<T> D = {0, 0};
 #pragma unroll
   for (int e = 0; e < S; ++e) {
     D = r[e] + mulg(g[e], D);
-    Gc = g[e] * Gc;
+    if constexpr (!WTAB) Gc = g[e] * Gc;
   }
   // Lines of P <= 16 lanes lie inside one row of 16 lanes; a line of 32 lanes spans two
   // rows.  The scans move values with DPP: row shifts inside a row, then one step across
@@ -486,14 +507,23 @@ __device__ __forceinline__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt, T 
   constexpr int PR = P < 16 ? P : 16;
   const int rq = tid & (PR - 1);  // lane within the line's part of its row
   cpx<T> din = {0, 0};
-  if constexpr (P > 1) {
+  if constexpr (P > 1 && WTAB) {
+    GT w[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) w[k] = scan_weight<GT>(wt + k * P + q);
+    if constexpr (PR > 1) cn_scan_w<DPP_ROW_SHR + 1>(w[0], D, rq >= 1);
+    if constexpr (PR > 2) cn_scan_w<DPP_ROW_SHR + 2>(w[1], D, rq >= 2);
+    if constexpr (PR > 4) cn_scan_w<DPP_ROW_SHR + 4>(w[2], D, rq >= 4);
+    if constexpr (PR > 8) cn_scan_w<DPP_ROW_SHR + 8>(w[3], D, rq >= 8);
+    din = csel(q == 0, zero, dpp<DPP_WAVE_SHR1>(D));
+  } else if constexpr (P > 1) {
     GT Gn = Gc;
-    if constexpr (PR > 1) cn_scan_step<DPP_ROW_SHR + 1>(Gn, D, rq >= 1);
-    if constexpr (PR > 2) cn_scan_step<DPP_ROW_SHR + 2>(Gn, D, rq >= 2);
-    if constexpr (PR > 4) cn_scan_step<DPP_ROW_SHR + 4>(Gn, D, rq >= 4);
-    if constexpr (PR > 8) cn_scan_step<DPP_ROW_SHR + 8>(Gn, D, rq >= 8);
+    cn_scan_step<DPP_ROW_SHR + 1>(Gn, D, rq >= 1);
+    cn_scan_step<DPP_ROW_SHR + 2>(Gn, D, rq >= 2);
+    cn_scan_step<DPP_ROW_SHR + 4>(Gn, D, rq >= 4);
+    cn_scan_step<DPP_ROW_SHR + 8>(Gn, D, rq >= 8);
     // the upper row of a 32-lane line takes the total of the lower row (its lane 15)
-    if constexpr (P == 32) cn_scan_step<DPP_ROW_BCAST15>(Gn, D, (tid & 16) != 0);
+    cn_scan_step<DPP_ROW_BCAST15>(Gn, D, (tid & 16) != 0);
     din = csel(q == 0, zero, dpp<DPP_WAVE_SHR1>(D));
   }
   {
@@ -510,20 +540,26 @@ __device__ __forceinline__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt, T 
 #pragma unroll
   for (int e = S - 1; e >= 0; --e) X = r[e] + mulg(g[e], X);
   cpx<T> xin = {0, 0};
-  if constexpr (P > 1) {
+  if constexpr (P > 1 && WTAB) {
+    GT w[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) w[k] = scan_weight<GT>(wt + (NS + k) * P + q);
+    if constexpr (PR > 1) cn_scan_w<DPP_ROW_SHL + 1>(w[0], X, rq + 1 < PR);
+    if constexpr (PR > 2) cn_scan_w<DPP_ROW_SHL + 2>(w[1], X, rq + 2 < PR);
+    if constexpr (PR > 4) cn_scan_w<DPP_ROW_SHL + 4>(w[2], X, rq + 4 < PR);
+    if constexpr (PR > 8) cn_scan_w<DPP_ROW_SHL + 8>(w[3], X, rq + 8 < PR);
+    xin = csel(q == P - 1, zero, dpp<DPP_WAVE_SHL1>(X));
+  } else if constexpr (P > 1) {
     GT Gn = Gc;
-    if constexpr (PR > 1) cn_scan_step<DPP_ROW_SHL + 1>(Gn, X, rq + 1 < PR);
-    if constexpr (PR > 2) cn_scan_step<DPP_ROW_SHL + 2>(Gn, X, rq + 2 < PR);
-    if constexpr (PR > 4) cn_scan_step<DPP_ROW_SHL + 4>(Gn, X, rq + 4 < PR);
-    if constexpr (PR > 8) cn_scan_step<DPP_ROW_SHL + 8>(Gn, X, rq + 8 < PR);
-    if constexpr (P == 32) {
-      // the lower row of a 32-lane line takes the total of the upper row, held by the
-      // upper row's first lane (16 or 48)
-      const bool second = (tid & 32) != 0;
-      const GT Gs = csel(second, lane_val<48>(Gn), lane_val<16>(Gn));
-      const cpx<T> Xs = csel(second, lane_val<48>(X), lane_val<16>(X));
-      cn_compose(Gn, X, Gs, Xs, (tid & 16) == 0);
-    }
+    cn_scan_step<DPP_ROW_SHL + 1>(Gn, X, rq + 1 < PR);
+    cn_scan_step<DPP_ROW_SHL + 2>(Gn, X, rq + 2 < PR);
+    cn_scan_step<DPP_ROW_SHL + 4>(Gn, X, rq + 4 < PR);
+    cn_scan_step<DPP_ROW_SHL + 8>(Gn, X, rq + 8 < PR);
+    // the lower row of a 32-lane line takes the total of the upper row, held by the
+    // upper row's first lane (16 or 48)
+    const bool second = (tid & 32) != 0;
+    const cpx<T> Xs = csel(second, lane_val<48>(X), lane_val<16>(X));
+    X = csel((tid & 16) == 0, mulg(Gn, Xs) + X, X);
     xin = csel(q == P - 1, zero, dpp<DPP_WAVE_SHL1>(X));
   }
   {

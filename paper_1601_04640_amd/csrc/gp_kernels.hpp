@@ -657,7 +657,8 @@ __device__ __forceinline__ void c2r_nl_cnx_body(
     }
     if constexpr (STEP) {
       __syncthreads();
-      cn_solve_lines<T, N0, TJ, LSP, 1, PX, cn_imag_a<MODE>()>(PS, MT, cn_a<T, MODE>(sc.Ar));
+      cn_solve_lines<T, N0, TJ, LSP, 1, PX, cn_imag_a<MODE>()>(PS, MT, cnm + N0,
+                                                                cn_a<T, MODE>(sc.Ar));
 #pragma unroll
       for (int it = 0; it < IT::N; ++it) {
         const int u = tid + it * kThreads;
@@ -716,7 +717,7 @@ __device__ __forceinline__ void cn_col_body(cpx<T>* __restrict__ psi,
   }
   __syncthreads();
   if constexpr (SOLVE) {
-    cn_solve_lines<T, N, TC, 1, RS, PC, cn_imag_a<MODE>()>(B, MT, cn_a<T, MODE>(Ar));
+    cn_solve_lines<T, N, TC, 1, RS, PC, cn_imag_a<MODE>()>(B, MT, cnm + N, cn_a<T, MODE>(Ar));
   }
   double sums[2] = {0.0, 0.0};
 #pragma unroll
@@ -786,7 +787,7 @@ __device__ __forceinline__ void adj_x_body(
     if (IT::valid(u)) PS[(u / N0) * LSP + cpad<SX>(u % N0)] = lv[it];
   }
   c2r_tile<T, N0, NP>(Z, W, sa, sb);  // ends with a barrier
-  cn_solve_lines<T, N0, TJ, LSP, 1, PX, true>(PS, MT, cn_a<T, MODE_ADJ>(sc.Ar));
+  cn_solve_lines<T, N0, TJ, LSP, 1, PX, true>(PS, MT, cnm + N0, cn_a<T, MODE_ADJ>(sc.Ar));
   double sums[2] = {0.0, 0.0};
   const T dt = (T)sc.dt;
 #pragma unroll
