@@ -718,4 +718,58 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NV], double* red /* 
   }
 }
 
+// Block totals of NV <= 8 per-thread doubles written to out[0..NV) (global), for the
+// larger sets: partner lanes first split the values between them (lane pairs 1 apart
+// keep values 0-3 and 4-7, then pairs 2 apart keep half of those), so that each lane
+// goes on summing two values only; row shifts by 4 and 8 leave each row of 16 lanes
+// with its totals in lanes 12-15, and the 16 row totals of every value (4 waves x 4
+// rows) are added in a fixed order by NV threads.  red: LDS of 128 doubles, free for
+// this call (the caller has synchronised the block if it aliases other data).  Returns
+// total t to thread t < NV (0 elsewhere).
+template <int NV>
+__device__ __forceinline__ double block_sum_store8(double (&v)[NV], double* red,
+                                                   double* __restrict__ out) {
+  static_assert(NV > 2 && NV <= 8, "two to eight values");
+  const int t = thread_idx();
+  const int lane = t & 63, wave = t >> 6;
+  double x[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) x[k] = k < NV ? v[k] : 0.0;
+  const bool odd = lane & 1, hi2 = lane & 2;
+  double a[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double send = odd ? x[k] : x[k + 4];
+    const double keep = odd ? x[k + 4] : x[k];
+    a[k] = keep + dpp<DPP_QUAD_1032>(send);
+  }
+  double b[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const double send = hi2 ? a[k] : a[k + 2];
+    const double keep = hi2 ? a[k + 2] : a[k];
+    b[k] = keep + dpp<DPP_QUAD_2301>(send);
+  }
+  // lane holds values 4 (lane & 1) + 2 ((lane >> 1) & 1) + k, k < 2
+#pragma unroll
+  for (int k = 0; k < 2; ++k) b[k] += dpp<DPP_ROW_SHR + 4>(b[k]);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) b[k] += dpp<DPP_ROW_SHR + 8>(b[k]);
+  if ((lane & 15) >= 12) {
+    const int base = 4 * (lane & 1) + 2 * ((lane >> 1) & 1);
+    const int row = (wave << 2) | (lane >> 4);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) red[row * 8 + base + k] = b[k];
+  }
+  __syncthreads();
+  double acc = 0.0;
+  if (t < NV) {
+    acc = red[t];
+#pragma unroll
+    for (int r = 1; r < 4 * kWaves; ++r) acc += red[r * 8 + t];
+    out[t] = acc;
+  }
+  return acc;
+}
+
 }  // namespace gpdbec

@@ -148,7 +148,9 @@ struct XT {
   static constexpr size_t C = sizeof(cpx<T>);
   static constexpr size_t Z = a16(NP * LSZ * C), W = a16(N0 * C), PS = a16(TJ * LSP * C),
                           MT = a16(cn_table_len<N0, PX>() * C),
-                          RED = a16(8 * kWaves * sizeof(double));
+                          RED = a16(8 * kWaves * sizeof(double)),
+                          RED8 = a16(32 * kWaves * sizeof(double));  // block_sum_store8
+  static constexpr size_t mx(size_t a, size_t b) { return a > b ? a : b; }
 };
 
 // Geometry of a strided-column CN tile (TC columns of N points).
@@ -173,9 +175,9 @@ constexpr size_t lds_bytes() {
   if (PASS == P_R2C_REAL) return X::Z + X::W;
   if (PASS == P_FFT_LINE || PASS == P_CONV_LINE) return a16(LB * (N + 1) * C) + a16(N * C);
   if (PASS == P_CONV_COL) return a16(N * (Tiles<T, N>::TV + 1) * C) + a16(N * C);
-  if (PASS == P_C2R_STEP) return (X::Z > X::PS ? X::Z : X::PS) + X::W + X::MT + X::RED;
+  if (PASS == P_C2R_STEP) return X::mx(X::mx(X::Z, X::PS), X::RED8) + X::W + X::MT;
   if (PASS == P_ADJ_X) return X::Z + X::PS + X::W + X::MT + X::RED;
-  if (PASS == P_C2R_OBS) return X::Z + X::W + X::RED;
+  if (PASS == P_C2R_OBS) return X::mx(X::Z, X::RED8) + X::W;
   if (PASS == P_CN_COL) return CT<T, N>::B + CT<T, N>::MT + CT<T, N>::RED;
   if (PASS == P_ADJ_FIN) return X::Z + X::W;
   return 0;
@@ -571,11 +573,14 @@ __device__ __forceinline__ void c2r_nl_cnx_body(
   // The step modes keep the CN lines in the FFT tile's memory (Phi is read into registers
   // before the first CN write): the smaller footprint lets more blocks share a CU.
   constexpr int ZL = NP * LSZ, PL = STEP ? TJ * LSP : 0;
-  cpx<T>* Z = cv.take<cpx<T>>(ZL > PL ? ZL : PL);
+  constexpr int RL = (int)(X::RED8 / sizeof(cpx<T>));  // the reduction's 32 per wave
+  constexpr int TL = ZL > PL ? ZL : PL;
+  cpx<T>* Z = cv.take<cpx<T>>(TL > RL ? TL : RL);
   cpx<T>* PS = STEP ? Z : nullptr;
   cpx<T>* W = cv.take<cpx<T>>(N0);
   cpx<T>* MT = STEP ? cv.take<cpx<T>>(cn_table_len<N0, PX>()) : nullptr;
-  double* red = cv.take<double>(8 * kWaves);
+  // the observables reduction at the end reuses the tile's memory
+  double* red = reinterpret_cast<double*>(Z);
   const int tid = thread_idx();
   const int nt1 = (n1 + TJ - 1) / TJ;
   const int k2 = bid / nt1;
@@ -666,12 +671,15 @@ __device__ __forceinline__ void c2r_nl_cnx_body(
         if (IT::valid(u) && j0 + jl < n1) at32(psi + pbase, (unsigned)u) = PS[jl * LSP + cpad<SX>(i)];
       }
     }
-    // the block reduction of the observables sums comes last, off the solve's path
-    double sums[7];
+    // the block reduction of the observables sums comes last, off the solve's path; the
+    // tile (the reduction's LDS) is free once every thread has passed the barrier, and
+    // sum z^2 n is zc^2 times the block's sum n (zc is one value per tile)
+    double sums[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) sums[k] = (double)ps[k];
-    sums[6] = zc * zc * sums[0];
-    block_sum_store<7>(sums, red, partials + bid * 7);
+    __syncthreads();
+    const double total = block_sum_store8<6>(sums, red, partials + bid * 7);
+    if (tid == 0) partials[bid * 7 + 6] = zc * zc * total;  // thread 0 holds sum n
   }
 }
 
