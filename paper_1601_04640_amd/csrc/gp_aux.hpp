@@ -38,7 +38,8 @@ __device__ inline zd zinv(zd a) {
 // They depend on the factors only: the products g of every chunk, composed across the
 // lanes in the solve's own step order.
 constexpr int kScanWeights = 2 * 5 * 32;  // 2 NS P for P <= 32
-__device__ inline void cn_scan_weights(const zd* gc, int P, cpx<double>* w) {
+template <typename T>
+__device__ inline void cn_scan_weights(const zd* gc, int P, cpx<T>* w) {
   const int PR = P < 16 ? P : 16;  // lanes of a line inside one row of 16
   int NS = 0;
   while ((1 << NS) < P) ++NS;
@@ -48,7 +49,7 @@ __device__ inline void cn_scan_weights(const zd* gc, int P, cpx<double>* w) {
     int s = 0;
     for (int off = 1; off < PR; off <<= 1, ++s) {
       for (int q = 0; q < P; ++q) {
-        w[(dir * NS + s) * P + q] = cpx<double>{G[q].re, G[q].im};
+        w[(dir * NS + s) * P + q] = cpx<T>{(T)G[q].re, (T)G[q].im};
         const int rq = q % PR;
         const bool take = dir == 0 ? rq >= off : rq + off < PR;
         H[q] = take ? zmul(G[q], G[dir == 0 ? q - off : q + off]) : G[q];
@@ -56,7 +57,7 @@ __device__ inline void cn_scan_weights(const zd* gc, int P, cpx<double>* w) {
       for (int q = 0; q < P; ++q) G[q] = H[q];
     }
     if (P == 32)  // the step across the two rows of a 32-lane line
-      for (int q = 0; q < P; ++q) w[(dir * NS + s) * P + q] = cpx<double>{G[q].re, G[q].im};
+      for (int q = 0; q < P; ++q) w[(dir * NS + s) * P + q] = cpx<T>{(T)G[q].re, (T)G[q].im};
   }
 }
 
@@ -87,11 +88,7 @@ __global__ void k_cn_tables(cpx<T>* m_im, cpx<T>* m_re, cpx<T>* m_adj, int N, do
     gc[q] = zmul(gc[q], zd{-c.re, -c.im});
   }
   mt[N - 1] = cpx<T>{0, 0};
-  cpx<double> w[kScanWeights];
-  cn_scan_weights(gc, P, w);
-  int NS = 0;
-  while ((1 << NS) < P) ++NS;
-  for (int k = 0; k < 2 * NS * P; ++k) mt[N + k] = cpx<T>{(T)w[k].re, (T)w[k].im};
+  cn_scan_weights(gc, P, mt + N);
 }
 
 // Spherical-cutoff factor b(s) = 1 + 3 cos s/s^2 - 3 sin s/s^3 (s = kR); for s < 1 the
