@@ -291,7 +291,7 @@ struct Passes {
     const int H = L.n0 / 2 + 1;
     if (c->p.geom == GP_3D) {
       const int nl = H * L.n2;
-      const int lb = c->fp64 ? Launch<double>::lb(L.n1) : Launch<float>::lb(L.n1);
+      const int lb = c->fp64 ? Launch<double>::lbf(L.n1) : Launch<float>::lbf(L.n1);
       const int tc = tv_of(c->fp64, L.n2);
       GP_PASS(c, GP_PASS_FFT_Y_FWD,
               Launch<T>::fft_line(L.n1, false, (nl + lb - 1) / lb, c->st, spec(c), tw(c, 1), nl));

@@ -251,6 +251,17 @@ int Launch<T>::tv(int n) {
   return 0;
 }
 template <>
+int Launch<T>::lbf(int n) {
+  switch (n) {
+#define X(N) \
+  case N:    \
+    return Tiles<T, N>::LBF;
+    GP_FOR_SIZES(X)
+#undef X
+  }
+  return 0;
+}
+template <>
 int Launch<T>::lb(int n) {
   switch (n) {
 #define X(N) \

@@ -67,6 +67,10 @@ struct Tiles {
   static constexpr int TV = ((size_t)N * 17 * 2 * sizeof(T) > (size_t)GP_TV_SPLIT_BYTES) ? 8 : 16;
   // contiguous lines per block of the line FFT passes
   static constexpr int LB = (GP_LB_POINTS / N) < 1 ? 1 : (GP_LB_POINTS / N);
+  // lines per block of the y FFT pass: 16 for FP32 lines of 16 x 16 points (one 16-point
+  // stage in registers on each side of a single LDS exchange), else LB
+  static constexpr bool FFT16 = (N == 256 && sizeof(T) == 4);
+  static constexpr int LBF = FFT16 ? 16 : LB;
 };
 
 // Workgroups are dispatched to the 8 XCDs round-robin (block b runs on XCD b % 8), and
@@ -173,7 +177,10 @@ constexpr size_t lds_bytes() {
   constexpr int LB = Tiles<T, N>::LB, TC = Tiles<T, N>::TC;
   if (PASS == P_R2C) return X::Z + X::W + X::RED;
   if (PASS == P_R2C_REAL) return X::Z + X::W;
-  if (PASS == P_FFT_LINE || PASS == P_CONV_LINE) return a16(LB * (N + 1) * C) + a16(N * C);
+  if (PASS == P_FFT_LINE)
+    return Tiles<T, N>::FFT16 ? a16(16 * (N + N / 16) * C) + a16(N * C)
+                              : a16(LB * (N + 1) * C) + a16(N * C);
+  if (PASS == P_CONV_LINE) return a16(LB * (N + 1) * C) + a16(N * C);
   if (PASS == P_CONV_COL) return a16(N * (Tiles<T, N>::TV + 1) * C) + a16(N * C);
   if (PASS == P_C2R_STEP) return X::mx(X::mx(X::Z, X::PS), X::RED8) + X::W + X::MT;
   if (PASS == P_ADJ_X) return X::Z + X::PS + X::W + X::MT + X::RED;
@@ -356,6 +363,42 @@ template <typename T, int N, bool INV>
 __device__ __forceinline__ void fft_line_body(cpx<T>* __restrict__ data,
                                               const cpx<T>* __restrict__ tw, int nlines, int bid,
                                               char* lds) {
+  if constexpr (Tiles<T, N>::FFT16) {
+    // 16 lines of 16 x 16 points; thread (line l, g) holds points g + 16 m of its line.
+    // First 16-point stage on the loaded values, one LDS exchange (line pitch 272: one
+    // spare slot per 16 points keeps the stride-16 writes on distinct banks), second
+    // stage with twiddles W^(g m), stored from registers: point g + 16 m again.
+    constexpr int R = 16, LP = N + N / R;
+    Carve cv{lds};
+    cpx<T>* B = cv.take<cpx<T>>(R * LP);
+    cpx<T>* W = cv.take<cpx<T>>(N);
+    const int tid = thread_idx();
+    const int l = tid / R, g = tid % R;
+    const int line = bid * R + l;
+    const bool in = line < nlines;
+    cpx<T>* src = data + (size_t)bid * R * N;
+    cpx<T> v[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m)
+      v[m] = in ? at32(src, (unsigned)(l * N + g + R * m)) : cpx<T>{0, 0};
+    for (int i = tid; i < N; i += kThreads) W[i] = tw[i];
+    dft<T, R, INV>(v);
+    cpx<T>* b = B + l * LP;
+#pragma unroll
+    for (int m = 0; m < R; ++m) b[g * (R + 1) + m] = v[m];  // point R g + m, padded
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const cpx<T> e = b[g + (R + 1) * m];  // point g + R m, padded
+      const cpx<T> w = INV ? conjg(W[g * m]) : W[g * m];
+      v[m] = (m == 0) ? e : e * w;
+    }
+    dft<T, R, INV>(v);
+#pragma unroll
+    for (int m = 0; m < R; ++m)
+      if (in) at32(src, (unsigned)(l * N + g + R * m)) = v[m];
+    return;
+  }
   constexpr int LB = Tiles<T, N>::LB, LSZ = N + 1;
   Carve cv{lds};
   cpx<T>* B = cv.take<cpx<T>>(LB * LSZ);

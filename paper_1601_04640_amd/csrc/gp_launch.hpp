@@ -25,6 +25,7 @@ struct Launch {
   static int tc(int n);  // columns per block (strided passes)
   static int tv(int n);  // columns per block (z convolution)
   static int lb(int n);  // contiguous lines per block
+  static int lbf(int n); // contiguous lines per block of the y FFT pass
 
   static hipError_t r2c_x(int n0, int blocks, hipStream_t st, const cpx<T>* psi,
                           const double* scale, cpx<T>* spec, const cpx<T>* tw0, double* part,
@@ -62,6 +63,7 @@ struct Launch {
   template <> int Launch<T>::tc(int);                                                         \
   template <> int Launch<T>::tv(int);                                                         \
   template <> int Launch<T>::lb(int);                                                         \
+  template <> int Launch<T>::lbf(int);                                                        \
   template <> hipError_t Launch<T>::r2c_x(int, int, hipStream_t, const cpx<T>*, const double*, \
                                           cpx<T>*, const cpx<T>*, double*, int, int);          \
   template <> hipError_t Launch<T>::fft_line(int, bool, int, hipStream_t, cpx<T>*,             \

@@ -33,6 +33,10 @@ CASES = {
     # registers; ny = 20 leaves a ragged 4-column tile
     "3d_12x20x256": dict(geom="3d", nx=12, ny=20, nz=256, dx=0.5, dy=0.45, dz=0.04,
                          dt=0.0005, gamma=1.0, nu=1.0, lam=1.0, g=15.0, gdd=6.0, R=2.0),
+    # 256-point y lines: the FP32 y FFT runs 16 x 16 with one LDS exchange; 7 x 20 = 140
+    # lines leave a ragged last block of 16
+    "3d_12x256x20": dict(geom="3d", nx=12, ny=256, nz=20, dx=0.5, dy=0.04, dz=0.45,
+                         dt=0.0005, gamma=1.0, nu=1.0, lam=1.0, g=15.0, gdd=6.0, R=2.0),
     # 2048 x-line tiles: the FP64 finalisation runs in two stages (pre-reduced slices)
     "3d_16x64x512": dict(geom="3d", nx=16, ny=64, nz=512, dx=0.45, dy=0.12, dz=0.02,
                          dt=0.0005, gamma=1.0, nu=1.0, lam=1.0, g=10.0, gdd=4.0, R=1.5),
