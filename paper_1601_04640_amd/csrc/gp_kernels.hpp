@@ -659,6 +659,8 @@ __device__ __forceinline__ void c2r_nl_cnx_body(
     // widened: the block and grid sums are FP64.  In FP32 an 8- or 16-term partial
     // carries an unbiased rounding of ~1e-7 of itself, far below the observables' bar.
     T ps[6] = {0, 0, 0, 0, 0, 0};
+    // when N0 divides the block size every point of a thread has the same x index
+    constexpr bool XFIX = kThreads % N0 == 0;
     const T ts = (T)(*scale);
     const T h0 = (T)sc.h0, h1 = (T)sc.h1;
     const double zc = (k2 - n2 / 2) * sc.h2;
@@ -688,7 +690,7 @@ __device__ __forceinline__ void c2r_nl_cnx_body(
       ps[1] += v * n;
       ps[2] += n * n;
       ps[3] += phi * n;
-      ps[4] += xc * xc * n;
+      if constexpr (!XFIX) ps[4] += xc * xc * n;
       ps[5] += yc * yc * n;
       if constexpr (STEP) {
         const T th = (T)sc.dt * (v + (T)sc.gc * n + (T)sc.gdd * phi);
@@ -713,6 +715,10 @@ __device__ __forceinline__ void c2r_nl_cnx_body(
         const int jl = u / N0, i = u % N0;
         if (IT::valid(u) && j0 + jl < n1) at32(psi + pbase, (unsigned)u) = PS[jl * LSP + cpad<SX>(i)];
       }
+    }
+    if constexpr (XFIX) {  // one x per thread: sum x^2 n = x^2 sum n
+      const T xc = (T)(tid % N0 - N0 / 2) * h0;
+      ps[4] = xc * xc * ps[0];
     }
     // the block reduction of the observables sums comes last, off the solve's path; the
     // tile (the reduction's LDS) is free once every thread has passed the barrier, and
