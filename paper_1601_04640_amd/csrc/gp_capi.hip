@@ -46,7 +46,7 @@ struct Layout {
   size_t esz;           // bytes of one real value
   int nb_x, nb_col, nb_colobs;
   // byte offsets inside the workspace
-  size_t o_psi, o_V, o_spec, o_ktab, o_tw[3], o_cn[3][3], o_px, o_pnl, o_pcol, o_padj, o_sfield,
+  size_t o_psi, o_V, o_spec, o_ktab, o_tw[3], o_cn[3][3], o_px[2], o_pnl, o_pcol, o_padj, o_sfield,
       o_scalars, o_ring, o_obs, o_io, o_stamps, o_stage, total;
 };
 
@@ -128,7 +128,9 @@ Layout make_layout(const gp_params* p) {
     // factor table and scan weights per set (imaginary time, real time, adjoint)
     for (int t = 0; t < 3; ++t) L.o_cn[a][t] = take(2 * L.esz * (ns[a] + kScanWeights));
   }
-  L.o_px = take(sizeof(double) * 2 * L.nb_x);
+  // two x-partial buffers: a real-time step's x pass writes one while the previous
+  // step's folded finalisation reads the other
+  for (int k = 0; k < 2; ++k) L.o_px[k] = take(sizeof(double) * 2 * L.nb_x);
   L.o_pnl = take(sizeof(double) * 7 * L.nb_x);
   L.o_pcol = take(sizeof(double) * 2 * L.nb_col);
   L.o_padj = take(sizeof(double) * 2 * L.nb_x);
@@ -149,7 +151,15 @@ struct gp_ctx {
   // step loop replay: kGraphSteps steps captured once per time direction
   bool use_graphs = true;
   hipStream_t cap_st = nullptr;
-  hipGraphExec_t gexec[2] = {nullptr, nullptr};  // [imaginary, real]
+  // [imaginary, real entered with the pending finalisation reading x-partials 0, ... 1]
+  hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
+  // Real-time steps with the scale at 1 defer their finalisation into the next step's
+  // first pass: fin_pending marks one outstanding (its x partials in buffer pend_sel);
+  // px_sel is the buffer the x pass writes next; scale_one: the device scale is 1.
+  bool fin_pending = false;
+  int pend_sel = 0;
+  int px_sel = 0;
+  bool scale_one = true;
   // optional per-pass timing: event pairs recorded around selected pass launches
   unsigned tmask = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[GP_PASS_COUNT];
@@ -244,9 +254,10 @@ StepScalars scalars_for(const gp_ctx* c, int axis) {
   return s;
 }
 
-FinArgs fin_args(const gp_ctx* c) {
+// Partials of the pass sequence whose x pass wrote buffer `sel`.
+FinArgs fin_args(const gp_ctx* c, int sel) {
   FinArgs a{};
-  a.p_x = c->at<double>(c->L.o_px);
+  a.p_x = c->at<double>(c->L.o_px[sel]);
   a.nb_x = c->L.nb_x;
   a.p_nl = c->at<double>(c->L.o_pnl);
   a.nb_nl = c->L.nb_x;
@@ -276,6 +287,19 @@ FinArgs fin_args(const gp_ctx* c) {
   return a;
 }
 
+// The outstanding real-time finalisation, if any, as its own launch(es).  Every entry
+// point other than the real-time step calls this first.
+gp_status settle(gp_ctx* c) {
+  if (!c->fin_pending) return GP_OK;
+  c->fin_pending = false;
+  FinArgs a = fin_args(c, c->pend_sel);
+  a.keep_scale = 1;
+  if (a.nstage > 0)
+    hipLaunchKernelGGL(k_prereduce, dim3(a.nstage), dim3(kThreads), 0, c->st, a, (int)FIN_REAL);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, c->st, a, (int)FIN_REAL);
+  return dev(hipGetLastError());
+}
+
 // ------------------------------------------------------------- pass schedule
 template <typename T>
 struct Passes {
@@ -286,15 +310,22 @@ struct Passes {
   static const cpx<T>* cn(gp_ctx* c, int a, int k) { return c->at<cpx<T>>(c->L.o_cn[a][k]); }
 
   // y/z transforms of the x-half spectrum, U(k)/N product, inverse y/z transforms
-  static gp_status spectrum_passes(gp_ctx* c) {
+  // fin2: a two-stage folded finalisation whose second stage rides in the forward y FFT
+  static gp_status spectrum_passes(gp_ctx* c, const FinArgs* fin2 = nullptr) {
     const Layout& L = c->L;
     const int H = L.n0 / 2 + 1;
     if (c->p.geom == GP_3D) {
       const int nl = H * L.n2;
       const int lb = c->fp64 ? Launch<double>::lbf(L.n1) : Launch<float>::lbf(L.n1);
       const int tc = tv_of(c->fp64, L.n2);
-      GP_PASS(c, GP_PASS_FFT_Y_FWD,
-              Launch<T>::fft_line(L.n1, false, (nl + lb - 1) / lb, c->st, spec(c), tw(c, 1), nl));
+      if (fin2) {
+        GP_HIP(Launch<T>::fft_line_fin(L.n1, (nl + lb - 1) / lb, c->st, spec(c), tw(c, 1), nl,
+                                       *fin2));
+      } else {
+        GP_PASS(c, GP_PASS_FFT_Y_FWD,
+                Launch<T>::fft_line(L.n1, false, (nl + lb - 1) / lb, c->st, spec(c), tw(c, 1),
+                                    nl));
+      }
       GP_PASS(c, GP_PASS_CONV_Z,
               Launch<T>::conv_col(L.n2, ((L.n1 + tc - 1) / tc) * H, c->st, spec(c),
                                   c->at<T>(L.o_ktab), tw(c, 2), L.n1));
@@ -309,13 +340,22 @@ struct Passes {
     return GP_OK;
   }
 
-  // density of `src` (times scale^2) -> spectrum -> U(k) product -> x-half spectrum
-  static gp_status convolution(gp_ctx* c, const cpx<T>* src, const double* scale) {
+  // density of `src` (times scale^2) -> spectrum -> U(k) product -> x-half spectrum;
+  // `fold`: the previous real-time step's finalisation rides in the x pass (one block,
+  // or the first-stage slices there and the finalize block in the forward y FFT)
+  static gp_status convolution(gp_ctx* c, const cpx<T>* src, const double* scale,
+                               const FinArgs* fold = nullptr) {
     const Layout& L = c->L;
-    GP_PASS(c, GP_PASS_R2C_X,
-            Launch<T>::r2c_x(L.n0, L.nb_x, c->st, src, scale, spec(c), tw(c, 0),
-                             c->at<double>(L.o_px), L.n1, L.n2));
-    return spectrum_passes(c);
+    double* px = c->at<double>(L.o_px[c->px_sel]);
+    if (fold) {
+      GP_HIP(Launch<T>::r2c_x_fin(L.n0, L.nb_x, c->st, src, scale, spec(c), tw(c, 0), px,
+                                  L.n1, L.n2, *fold, fold->nstage > 0 ? fold->nstage : 1));
+    } else {
+      GP_PASS(c, GP_PASS_R2C_X,
+              Launch<T>::r2c_x(L.n0, L.nb_x, c->st, src, scale, spec(c), tw(c, 0), px, L.n1,
+                               L.n2));
+    }
+    return spectrum_passes(c, fold && fold->nstage > 0 ? fold : nullptr);
   }
   static gp_status convolution(gp_ctx* c) { return convolution(c, psi(c), &c->sc()->scale); }
 
@@ -353,7 +393,7 @@ struct Passes {
   // FIN_OBSERVE for gp_energy, FIN_EKZ for the pending z-kinetic part)
   static gp_status finalize(gp_ctx* c, int fin_mode) {
     GP_TRY(pass_begin(c, GP_PASS_FINALIZE));
-    const FinArgs a = fin_args(c);
+    const FinArgs a = fin_args(c, c->px_sel);
     if (a.nstage > 0)
       hipLaunchKernelGGL(k_prereduce, dim3(a.nstage), dim3(kThreads), 0, c->st, a, fin_mode);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, c->st, a, fin_mode);
@@ -376,7 +416,24 @@ struct Passes {
     const int mode = imag ? MODE_IMAG : MODE_REAL;
     const int fin = imag ? (int)FIN_IMAG : (int)FIN_REAL;
     const int k = imag ? 0 : 1;  // factor table: imaginary or real time
-    GP_TRY(convolution(c));
+    // A real-time step with the scale at 1 and no per-pass timing defers its
+    // finalisation: the next step's x pass (or forward y FFT) carries it while writing
+    // the other x-partial buffer.  Its record and non-finite flag therefore land one
+    // launch later; every other entry point settles an outstanding one first.
+    const bool defer = !imag && c->scale_one && c->tmask == 0;
+    FinArgs prev{};
+    bool fold = false;
+    if (defer && c->fin_pending) {
+      prev = fin_args(c, c->pend_sel);
+      prev.keep_scale = 1;
+      fold = c->p.geom == GP_3D || prev.nstage == 0;
+      if (fold) {
+        c->fin_pending = false;
+        c->px_sel = 1 - c->pend_sel;
+      }
+    }
+    GP_TRY(settle(c));
+    GP_TRY(convolution(c, psi(c), &c->sc()->scale, fold ? &prev : nullptr));
     const StepScalars sx = scalars_for(c, 0);
     // timed: the launch's own dispatch timestamps fill the event pair (no separate event
     // packets around it), and every block stamps its start and end
@@ -419,7 +476,14 @@ struct Passes {
                                 c->at<double>(L.o_pcol), L.n0, (size_t)L.n0,
                                 (size_t)L.n0 * L.n1));
     }
-    return finalize(c, fin);
+    if (defer) {
+      c->fin_pending = true;
+      c->pend_sel = c->px_sel;
+      return GP_OK;
+    }
+    GP_TRY(finalize(c, fin));
+    c->scale_one = !imag;  // a real-time finalisation sets the scale to 1
+    return GP_OK;
   }
 
   // One launch of a pass exactly as inside a real-time step (burst timing).
@@ -429,7 +493,7 @@ struct Passes {
     switch (pass) {
       case GP_PASS_R2C_X:
         return dev(Launch<T>::r2c_x(L.n0, L.nb_x, c->st, psi(c), &c->sc()->scale, spec(c),
-                                    tw(c, 0), c->at<double>(L.o_px), L.n1, L.n2));
+                                    tw(c, 0), c->at<double>(L.o_px[c->px_sel]), L.n1, L.n2));
       case GP_PASS_C2R_NL_CNX:
         return dev(Launch<T>::c2r_nl_cnx(L.n0, MODE_REAL, L.nb_x, c->st, psi(c),
                                          c->at<T>(L.o_V), &c->sc()->scale, spec(c), tw(c, 0),
@@ -537,6 +601,7 @@ struct Passes {
       GP_HIP(hipStreamSynchronize(c->st));
     }
     hipLaunchKernelGGL(k_set_scale_one, dim3(1), dim3(64), 0, c->st, &c->sc()->scale);
+    c->scale_one = true;
     return dev(hipGetLastError());
   }
 
@@ -607,7 +672,7 @@ gp_status one_step(gp_ctx* c, bool imag) {
 
 // Capture kGraphSteps steps on a private stream (the caller's stream may be the null
 // stream, which cannot be captured); the graph is launched on the caller's stream.
-gp_status build_graph(gp_ctx* c, bool imag) {
+gp_status build_graph(gp_ctx* c, bool imag, int gi) {
   if (!c->cap_st) GP_HIP(hipStreamCreateWithFlags(&c->cap_st, hipStreamNonBlocking));
   const hipStream_t user = c->st;
   c->st = c->cap_st;
@@ -627,7 +692,7 @@ gp_status build_graph(gp_ctx* c, bool imag) {
   s = dev(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
   hipGraphDestroy(g);
   if (s != GP_OK) return s;
-  c->gexec[imag ? 0 : 1] = ex;
+  c->gexec[gi] = ex;
   return GP_OK;
 }
 
@@ -636,6 +701,7 @@ gp_status run_steps(gp_ctx* c, int nsteps, bool imag) {
   clear_stale_error();
   if (nsteps < 0) return GP_E_ARG;
   if (!c->psi_set) return GP_E_STATE;
+  if (imag || !c->ekz_valid) GP_TRY(settle(c));
   if (c->p.geom == GP_3D && !c->ekz_valid) {
     if (c->fp64) {
       GP_TRY(Passes<double>::z_observe(c, FIN_EKZ));
@@ -646,8 +712,16 @@ gp_status run_steps(gp_ctx* c, int nsteps, bool imag) {
   }
   int done = 0;
   if (c->use_graphs && c->tmask == 0 && nsteps >= kGraphSteps) {
-    const int gi = imag ? 0 : 1;
-    if (!c->gexec[gi]) GP_TRY(build_graph(c, imag));
+    // A real-time graph is captured and replayed from one state: the scale at 1 and a
+    // finalisation outstanding in x-partial buffer 0 or 1 (its graph index); the eight
+    // steps of a replay return to that state.
+    if (!imag)
+      while (done < nsteps && !(c->scale_one && c->fin_pending)) {
+        GP_TRY(one_step(c, false));
+        ++done;
+      }
+    const int gi = imag ? 0 : 1 + c->pend_sel;
+    if (nsteps - done >= kGraphSteps && !c->gexec[gi]) GP_TRY(build_graph(c, imag, gi));
     for (; nsteps - done >= kGraphSteps; done += kGraphSteps)
       GP_HIP(hipGraphLaunch(c->gexec[gi], c->st));
   }
@@ -761,7 +835,7 @@ gp_status batch_write_desc(gp_batch* b) {
     d.cn0[1] = o + L.o_cn[0][1];
     d.cn1[0] = o + L.o_cn[1][0];
     d.cn1[1] = o + L.o_cn[1][1];
-    d.p_x = o + L.o_px;
+    d.p_x = o + L.o_px[0];
     d.p_nl = o + L.o_pnl;
     d.p_col = o + L.o_pcol;
     d.scale = o + L.o_scalars + offsetof(Scalars, scale);
@@ -769,7 +843,7 @@ gp_status batch_write_desc(gp_batch* b) {
     d.Ar1 = scalars_for(c, 1).Ar;
     d.n0 = L.n0;
     d.n1 = L.n1;
-    d.fa = fin_args(c);
+    d.fa = fin_args(c, 0);
     d.fa.nstage = 0;  // the per-instance finalize blocks read their partials directly
     b->cpl[2 * i] = c->p.g;
     b->cpl[2 * i + 1] = c->p.gdd;
@@ -974,6 +1048,7 @@ const char* gp_status_string(gp_status s) {
 gp_status gp_set_psi(gp_ctx* c, const void* psi, int on_device) {
   clear_stale_error();
   if (!c || !psi) return GP_E_ARG;
+  GP_TRY(settle(c));
   GP_TRY(c->fp64 ? Passes<double>::set_psi(c, psi, on_device)
                  : Passes<float>::set_psi(c, psi, on_device));
   c->psi_set = true;
@@ -985,6 +1060,7 @@ gp_status gp_get_psi(gp_ctx* c, void* psi, int on_device) {
   clear_stale_error();
   if (!c || !psi) return GP_E_ARG;
   if (!c->psi_set) return GP_E_STATE;
+  GP_TRY(settle(c));
   GP_TRY(c->fp64 ? Passes<double>::get_psi(c, psi, on_device)
                  : Passes<float>::get_psi(c, psi, on_device));
   return on_device ? GP_OK : check_flags(c);
@@ -993,12 +1069,14 @@ gp_status gp_get_psi(gp_ctx* c, void* psi, int on_device) {
 gp_status gp_set_potential(gp_ctx* c, const void* V, int on_device) {
   clear_stale_error();
   if (!c || !V) return GP_E_ARG;
+  GP_TRY(settle(c));
   return c->fp64 ? Passes<double>::set_potential(c, V, on_device)
                  : Passes<float>::set_potential(c, V, on_device);
 }
 
 gp_status gp_set_couplings(gp_ctx* c, double g, double gdd) {
   if (!c || !isfinite(g) || !isfinite(gdd)) return GP_E_ARG;
+  GP_TRY(settle(c));
   c->p.g = g;
   c->p.gdd = gdd;
   c->gc = contact(c->p);
@@ -1012,6 +1090,7 @@ gp_status gp_step_real_adjoint(gp_ctx* c, const void* psi_n, void* lam, double* 
                                double* grad_g, double* grad_gdd) {
   if (!c || !psi_n || !lam || !gradV || !grad_g || !grad_gdd) return GP_E_ARG;
   clear_stale_error();
+  GP_TRY(settle(c));
   if (c->fp64) {
     return Passes<double>::adjoint(c, reinterpret_cast<const cpx<double>*>(psi_n),
                                    reinterpret_cast<cpx<double>*>(lam), gradV, grad_g, grad_gdd);
@@ -1025,6 +1104,7 @@ gp_status gp_energy(gp_ctx* c, gp_observables* out) {
   clear_stale_error();
   if (!c || !out) return GP_E_ARG;
   if (!c->psi_set) return GP_E_STATE;
+  GP_TRY(settle(c));
   GP_TRY(c->fp64 ? Passes<double>::observe(c) : Passes<float>::observe(c));
   double rec[kRecord];
   GP_HIP(hipMemcpyAsync(rec, c->at<double>(c->L.o_obs), sizeof(rec), hipMemcpyDeviceToHost, c->st));
@@ -1046,6 +1126,7 @@ gp_status gp_dipolar_potential(gp_ctx* c, void* phi, int on_device) {
   clear_stale_error();
   if (!c || !phi) return GP_E_ARG;
   if (!c->psi_set) return GP_E_STATE;
+  GP_TRY(settle(c));
   return c->fp64 ? Passes<double>::dipolar(c, phi, on_device)
                  : Passes<float>::dipolar(c, phi, on_device);
 }
@@ -1063,6 +1144,7 @@ gp_status gp_use_graphs(gp_ctx* c, int enable) {
 gp_status gp_timing_enable(gp_ctx* c, unsigned mask) {
   if (!c) return GP_E_ARG;
   clear_stale_error();
+  GP_TRY(settle(c));
   GP_HIP(hipStreamSynchronize(c->st));
   for (int k = 0; k < GP_PASS_COUNT; ++k) {
     for (auto& e : c->tev[k]) {
@@ -1080,6 +1162,7 @@ gp_status gp_timing_span(gp_ctx* c, int pass, double* total_ms, int* launches) {
   if (!c || !total_ms || !launches) return GP_E_ARG;
   if (pass != GP_PASS_C2R_NL_CNX) return GP_E_ARG;
   clear_stale_error();
+  GP_TRY(settle(c));
   unsigned long long acc[2] = {0ull, 0ull};
   GP_HIP(hipMemcpyAsync(acc, c->sc()->span, sizeof(acc), hipMemcpyDeviceToHost, c->st));
   GP_HIP(hipStreamSynchronize(c->st));
@@ -1091,6 +1174,7 @@ gp_status gp_timing_span(gp_ctx* c, int pass, double* total_ms, int* launches) {
 gp_status gp_timing_read(gp_ctx* c, double* total_ms, int* launches) {
   if (!c || !total_ms || !launches) return GP_E_ARG;
   clear_stale_error();
+  GP_TRY(settle(c));
   GP_HIP(hipStreamSynchronize(c->st));
   for (int k = 0; k < GP_PASS_COUNT; ++k) {
     double acc = 0.0;
@@ -1109,6 +1193,7 @@ gp_status gp_timing_burst(gp_ctx* c, int pass, int reps, double* ms_per_launch) 
   clear_stale_error();
   if (!c || !ms_per_launch || reps < 1 || reps > 4096) return GP_E_ARG;
   if (!c->psi_set) return GP_E_STATE;
+  GP_TRY(settle(c));
   if (pass != GP_PASS_R2C_X && pass != GP_PASS_C2R_NL_CNX && pass != GP_PASS_CN_Y &&
       pass != GP_PASS_CN_Z)
     return GP_E_ARG;
@@ -1156,6 +1241,7 @@ gp_status gp_timing_burst(gp_ctx* c, int pass, int reps, double* ms_per_launch) 
 gp_status gp_history(gp_ctx* c, gp_observables* out, int max_records, int* count) {
   clear_stale_error();
   if (!c || !count || max_records < 0 || (max_records > 0 && !out)) return GP_E_ARG;
+  GP_TRY(settle(c));
   int pos = 0;
   GP_HIP(hipMemcpyAsync(&pos, &c->sc()->ring_pos, sizeof(int), hipMemcpyDeviceToHost, c->st));
   GP_HIP(hipStreamSynchronize(c->st));
@@ -1282,6 +1368,7 @@ gp_status gp_batch_use_graphs(gp_batch* b, int enable) {
 gp_status gp_sync(gp_ctx* c) {
   clear_stale_error();
   if (!c) return GP_E_ARG;
+  GP_TRY(settle(c));
   return check_flags(c);
 }
 

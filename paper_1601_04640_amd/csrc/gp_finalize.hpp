@@ -28,14 +28,17 @@ struct FinArgs {
   double* obs;         // FIN_OBSERVE output record
   double* stage;       // two-stage reduction: kStageVals doubles per pre-reduced slice
   int nstage;          // slices (0: the finalize block reads the partials directly)
+  int keep_scale;      // real time with the scale already 1: leave it untouched
 };
 
 constexpr int kStageVals = 11;   // totals carried per slice (the v[] of finalize_block)
 constexpr int kStageMax = 256;   // slices of the two-stage reduction (<= kThreads)
 
 // Sums the partial arrays a block reads, blocks [lo, hi) of each, into v[11] (per
-// thread; fixed order).  Each iteration first issues the loads of 4 blocks of every
-// array, then adds them, so a small step's partials arrive in one memory round trip.
+// thread; fixed order).  Each iteration first issues the loads of U blocks of every
+// array, then adds them, so a small step's partials arrive in one memory round trip
+// (U = 4; U = 1 inside a pass kernel, to stay within the pass's register budget).
+template <int U = 4>
 __device__ inline void fin_gather(const FinArgs& a, int mode, int slice, int nslice,
                                   double (&v)[11]) {
   const int tid = threadIdx.x;
@@ -47,10 +50,10 @@ __device__ inline void fin_gather(const FinArgs& a, int mode, int slice, int nsl
   const int ln = lo_of(a.nb_nl), nn = xnl ? hi_of(a.nb_nl) - ln : 0;
   const int lc = lo_of(a.nb_col), nc = col ? hi_of(a.nb_col) - lc : 0;
   const int span = nx > nn ? (nx > nc ? nx : nc) : (nn > nc ? nn : nc);
-  for (int b0 = tid; b0 < span; b0 += 4 * kThreads) {
-    double t[4][11];
+  for (int b0 = tid; b0 < span; b0 += U * kThreads) {
+    double t[U][11];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int b = b0 + u * kThreads;
 #pragma unroll
       for (int k = 0; k < 2; ++k) t[u][k] = b < nx ? a.p_x[2 * (size_t)(lx + b) + k] : 0.0;
@@ -60,7 +63,7 @@ __device__ inline void fin_gather(const FinArgs& a, int mode, int slice, int nsl
       for (int k = 0; k < 2; ++k) t[u][9 + k] = b < nc ? a.p_col[2 * (size_t)(lc + b) + k] : 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
 #pragma unroll
       for (int k = 0; k < 11; ++k) v[k] += t[u][k];
     }
@@ -68,12 +71,13 @@ __device__ inline void fin_gather(const FinArgs& a, int mode, int slice, int nsl
 }
 
 // First stage of the two-stage reduction: block g writes the totals of slice g.
+template <int U = 4>
 __device__ inline void prereduce_block(const FinArgs& a, int mode, int g) {
   __shared__ double red[11 * kWaves];
   double v[11];
 #pragma unroll
   for (int k = 0; k < 11; ++k) v[k] = 0.0;
-  fin_gather(a, mode, g, a.nstage, v);
+  fin_gather<U>(a, mode, g, a.nstage, v);
   block_sum<11>(v, red);
   if (threadIdx.x == 0) {
 #pragma unroll
@@ -82,7 +86,11 @@ __device__ inline void prereduce_block(const FinArgs& a, int mode, int g) {
 }
 
 // All threads of one block must call this.
+template <int U = 4>
 __device__ inline void finalize_block(const FinArgs& a, int mode) {
+  // no multiply-add contraction: the record rounds the same wherever this is inlined (its
+  // own kernel, or folded into a pass kernel)
+#pragma clang fp contract(off)
   __shared__ double red[11 * kWaves];
   const int tid = threadIdx.x;
   double v[11];
@@ -104,7 +112,7 @@ __device__ inline void finalize_block(const FinArgs& a, int mode) {
       for (int k = 0; k < kStageVals; ++k) v[k] = a.stage[tid * kStageVals + k];
     }
   } else {
-    fin_gather(a, mode, 0, 1, v);
+    fin_gather<U>(a, mode, 0, 1, v);
   }
   block_sum<11>(v, red);
   if (tid != 0) return;
@@ -152,11 +160,11 @@ __device__ inline void finalize_block(const FinArgs& a, int mode) {
   // state to stay finite (zero is a solution)
   if (!isfinite(nout) || (mode == FIN_IMAG && !(nout > 0.0))) {
     *a.flags |= 1;
-    *a.scale = 1.0;
+    if (!a.keep_scale) *a.scale = 1.0;
     return;
   }
   const double sn = (mode == FIN_IMAG) ? 1.0 / sqrt(nout) : 1.0;
-  *a.scale = sn;
+  if (!a.keep_scale) *a.scale = sn;
   if (a.geom == 0) *a.ekz = 0.5 * sn * sn * v[10] / (a.h2 * a.h2) * dV;
 }
 

@@ -23,6 +23,26 @@ using T = GP_REAL;
 
 #if GP_FAMILY == 0
 template <>
+hipError_t Launch<T>::r2c_x_fin(int n0, int blocks, hipStream_t st, const cpx<T>* psi,
+                                const double* scale, cpx<T>* spec, const cpx<T>* tw0,
+                                double* part, int n1, int n2, const FinArgs& fa, int nfin) {
+  if (nfin < 1 || nfin > kStageMax) return hipErrorInvalidValue;
+  const int nlead = (nfin + kFinLead - 1) / kFinLead * kFinLead;
+  switch (n0) {
+#define X(N)                                                                              \
+  case N:                                                                                 \
+    GP_LAUNCH((k_r2c_x_fin<T, N>), blocks + nlead, st, psi, scale, spec, tw0, part, n1, n2, \
+              fa, nfin, nlead);                                                           \
+    break;
+    GP_FOR_SIZES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <>
 hipError_t Launch<T>::r2c_x(int n0, int blocks, hipStream_t st, const cpx<T>* psi,
                             const double* scale, cpx<T>* spec, const cpx<T>* tw0, double* part,
                             int n1, int n2) {
@@ -132,6 +152,22 @@ hipError_t Launch<T>::adj_fin(int n0, int blocks, hipStream_t st, cpx<T>* lam,
 #endif
 
 #if GP_FAMILY == 1
+template <>
+hipError_t Launch<T>::fft_line_fin(int n, int blocks, hipStream_t st, cpx<T>* data,
+                                   const cpx<T>* tw, int nlines, const FinArgs& fa) {
+  switch (n) {
+#define X(N)                                                                               \
+  case N:                                                                                  \
+    GP_LAUNCH((k_fft_line_fin<T, N>), blocks + kFinLead, st, data, tw, nlines, fa);        \
+    break;
+    GP_FOR_SIZES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <>
 hipError_t Launch<T>::fft_line(int n, bool inv, int blocks, hipStream_t st, cpx<T>* data,
                                const cpx<T>* tw, int nlines) {

@@ -79,6 +79,7 @@ struct Tiles {
 // two halves of the same 128-byte lines (spectrum lines of 8-line FP32 x tiles, kernel
 // table rows of 16-column z tiles), then share an L2.
 constexpr int kXcds = 8;
+constexpr int kFinLead = kXcds;  // leading blocks that carry a folded finalisation
 __device__ __forceinline__ int xcd_tile(int b, int nb) {
   const int x = b % kXcds, i = b / kXcds, per = nb / kXcds, rem = nb % kXcds;
   return x * per + (x < rem ? x : rem) + i;
@@ -932,6 +933,31 @@ __global__ __launch_bounds__(kThreads) void k_r2c_x(const cpx<T>* __restrict__ p
                     lds);
 }
 
+// The x R2C of a real-time step with the previous step's finalisation folded in (the
+// scale is 1 and stays so; that finalisation reads the previous step's partials, which
+// this pass does not write).  The first nlead blocks (a multiple of 8, so that the tiles
+// keep their XCD placement) carry it: nfin of them run the finalize block or the
+// first-stage slices, the others return; the remaining blocks are the tiles.
+template <typename T, int N0>
+__global__ __launch_bounds__(kThreads) void k_r2c_x_fin(const cpx<T>* __restrict__ psi,
+                                                        const double* __restrict__ scale,
+                                                        cpx<T>* __restrict__ spec,
+                                                        const cpx<T>* __restrict__ tw0,
+                                                        double* __restrict__ partials, int n1,
+                                                        int n2, FinArgs fa, int nfin, int nlead) {
+  GP_LDS(T, N0, P_R2C);
+  const int b = blockIdx.x;
+  if (b < nlead) {
+    if (b < nfin) {
+      if (fa.nstage > 0) prereduce_block<1>(fa, FIN_REAL, b);
+      else finalize_block<1>(fa, FIN_REAL);
+    }
+    return;
+  }
+  r2c_x_body<T, N0>(psi, scale, spec, tw0, partials, n1, n2,
+                    xcd_tile(b - nlead, gridDim.x - nlead), lds);
+}
+
 template <typename T, int N0>
 __global__ __launch_bounds__(kThreads) void k_r2c_real(const T* __restrict__ f,
                                                        cpx<T>* __restrict__ spec,
@@ -946,6 +972,21 @@ __global__ __launch_bounds__(kThreads) void k_fft_line(cpx<T>* __restrict__ data
                                                        const cpx<T>* __restrict__ tw, int nlines) {
   GP_LDS(T, N, P_FFT_LINE);
   fft_line_body<T, N, INV>(data, tw, nlines, blockIdx.x, lds);
+}
+
+// Forward y FFT with the second stage of a two-stage folded finalisation (see
+// k_r2c_x_fin) in its first block; blocks 1-7 return, the rest are the lines.
+template <typename T, int N>
+__global__ __launch_bounds__(kThreads) void k_fft_line_fin(cpx<T>* __restrict__ data,
+                                                           const cpx<T>* __restrict__ tw,
+                                                           int nlines, FinArgs fa) {
+  GP_LDS(T, N, P_FFT_LINE);
+  const int b = blockIdx.x;
+  if (b < kFinLead) {
+    if (b == 0) finalize_block<1>(fa, FIN_REAL);
+    return;
+  }
+  fft_line_body<T, N, false>(data, tw, nlines, b - kFinLead, lds);
 }
 
 template <typename T, int N>

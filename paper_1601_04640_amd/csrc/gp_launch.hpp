@@ -32,6 +32,13 @@ struct Launch {
                           int n1, int n2);
   static hipError_t fft_line(int n, bool inv, int blocks, hipStream_t st, cpx<T>* data,
                              const cpx<T>* tw, int nlines);
+  // the real-time step's x R2C / forward y FFT carrying the previous step's
+  // finalisation (nfin blocks: 1 finalize block, or the first-stage slices)
+  static hipError_t r2c_x_fin(int n0, int blocks, hipStream_t st, const cpx<T>* psi,
+                              const double* scale, cpx<T>* spec, const cpx<T>* tw0,
+                              double* part, int n1, int n2, const FinArgs& fa, int nfin);
+  static hipError_t fft_line_fin(int n, int blocks, hipStream_t st, cpx<T>* data,
+                                 const cpx<T>* tw, int nlines, const FinArgs& fa);
   static hipError_t conv_line(int n, int blocks, hipStream_t st, cpx<T>* data, const T* ktab,
                               const cpx<T>* tw, int nlines);
   static hipError_t conv_col(int n2, int blocks, hipStream_t st, cpx<T>* spec, const T* ktab,
@@ -68,6 +75,11 @@ struct Launch {
                                           cpx<T>*, const cpx<T>*, double*, int, int);          \
   template <> hipError_t Launch<T>::fft_line(int, bool, int, hipStream_t, cpx<T>*,             \
                                              const cpx<T>*, int);                              \
+  template <> hipError_t Launch<T>::r2c_x_fin(int, int, hipStream_t, const cpx<T>*,           \
+                                              const double*, cpx<T>*, const cpx<T>*, double*, \
+                                              int, int, const FinArgs&, int);                 \
+  template <> hipError_t Launch<T>::fft_line_fin(int, int, hipStream_t, cpx<T>*,              \
+                                                 const cpx<T>*, int, const FinArgs&);          \
   template <> hipError_t Launch<T>::conv_line(int, int, hipStream_t, cpx<T>*, const T*,       \
                                               const cpx<T>*, int);                             \
   template <> hipError_t Launch<T>::conv_col(int, int, hipStream_t, cpx<T>*, const T*,        \

@@ -291,3 +291,42 @@ def test_timing_span(gpu_lib):
     assert e.value.status == B.GP_E_ARG
     s.timing_enable([])
     s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["3d_24x20x16", "2dxy_48x40", "3d_16x64x512"])
+def test_deferred_finalisation_bit_exact(name, prec, gpu_lib):
+    """Real-time steps fold each step's finalisation into the next step's first pass
+    (two-stage on 3d_16x64x512: first stage in the x pass, second in the forward y FFT),
+    through graphs and direct launches.  With per-pass timing on, every step finalises
+    in its own launch instead: psi, every history record and the energy are the same
+    bit for bit.  The run enters real time from imaginary time (scale not 1) and leaves
+    it for imaginary time and back."""
+    from paper_1601_04640_amd.binding import PASS_NAMES
+    w = CASES[name]
+    banner("deferred finalisation", name, prec)
+    psi0 = start_state(w, 301)
+
+    def run(timed):
+        s = make_solver(w, prec)
+        s.set_psi(psi0)
+        if timed:
+            s.timing_enable(list(PASS_NAMES))
+        s.step_imag(3)
+        s.step_real(19)
+        h = s.history(19)
+        s.step_imag(1)
+        s.step_real(10)
+        h += s.history(10)
+        e = s.energy()
+        psi = s.get_psi()
+        s.close()
+        return psi, h, e
+
+    psi_a, h_a, e_a = run(False)
+    psi_b, h_b, e_b = run(True)
+    assert np.array_equal(psi_a, psi_b)
+    assert len(h_a) == len(h_b) == 29
+    for ra, rb in zip(h_a, h_b):
+        assert ra == rb, (ra, rb)
+    assert e_a == e_b
