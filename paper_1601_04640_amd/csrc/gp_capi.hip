@@ -748,6 +748,11 @@ struct gp_batch {
   hipStream_t cap_st = nullptr;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   std::vector<double> cpl;                    // (g, g_dd) per instance in the descriptors
+  // The two size-class kernels of one pass touch disjoint work items: the larger class
+  // runs on a second stream (default priority), forked from and joined back to the
+  // step's stream around each pass.
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace {
@@ -915,9 +920,21 @@ gp_status batch_step(gp_batch* b, hipStream_t st, bool imag) {
   const BDesc<T>* D = reinterpret_cast<const BDesc<T>*>(b->desc);
   const int passes[4] = {BP_R2C, BP_CONV, BP_C2R, BP_CN};
   for (int p : passes) {
+    // an instance's class can differ between passes (x length vs y length), so the two
+    // classes of one pass run side by side and the pass ends with both joined
+    const bool two = b->side != nullptr && b->nwork[p][0] > 0 && b->nwork[p][1] > 0;
+    if (two) {
+      GP_HIP(hipEventRecord(b->ev_fork, st));
+      GP_HIP(hipStreamWaitEvent(b->side, b->ev_fork, 0));
+    }
     for (int k = 0; k < kBatchClasses; ++k) {
-      GP_HIP(batch_launch<T>(p, mode, k, b->grid[p][k], b->lds[p][k][mi], st, b->ws, D,
+      const hipStream_t sk = (two && k == 1) ? b->side : st;
+      GP_HIP(batch_launch<T>(p, mode, k, b->grid[p][k], b->lds[p][k][mi], sk, b->ws, D,
                              b->work[p][k], b->nwork[p][k]));
+    }
+    if (two) {
+      GP_HIP(hipEventRecord(b->ev_join, b->side));
+      GP_HIP(hipStreamWaitEvent(st, b->ev_join, 0));
     }
   }
   return dev(batch_finalize<T>(b->count, imag ? (int)FIN_IMAG : (int)FIN_REAL, st, D));
@@ -1308,6 +1325,9 @@ gp_status gp_batch_init(const gp_params* params, int count, void* dev_workspace,
     if (s == GP_OK) b->inst.push_back(c);
   }
   if (s == GP_OK) s = b->fp64 ? batch_build<double>(b, BL) : batch_build<float>(b, BL);
+  if (s == GP_OK) s = dev(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
+  if (s == GP_OK) s = dev(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+  if (s == GP_OK) s = dev(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
   if (s != GP_OK) {
     gp_batch_destroy(b);
     return s;
@@ -1319,8 +1339,12 @@ gp_status gp_batch_init(const gp_params* params, int count, void* dev_workspace,
 gp_status gp_batch_destroy(gp_batch* b) {
   if (!b) return GP_E_ARG;
   const hipError_t e = hipStreamSynchronize(b->st);
+  if (b->side) hipStreamSynchronize(b->side);
   batch_drop_graphs(b);
   if (b->cap_st) hipStreamDestroy(b->cap_st);
+  if (b->side) hipStreamDestroy(b->side);
+  if (b->ev_fork) hipEventDestroy(b->ev_fork);
+  if (b->ev_join) hipEventDestroy(b->ev_join);
   for (gp_ctx* c : b->inst) gp_destroy(c);
   delete b;
   return dev(e);
