@@ -74,14 +74,15 @@ __host__ __device__ constexpr int batch_class(int n) { return n > 256 ? 1 : 0; }
 
 #define GP_BODY_R2C(N)                                                                  \
   case N:                                                                               \
-    r2c_x_body<T, N>(bptr<cpx<T>>(base, d.psi), bptr<double>(base, d.scale),              \
-                     bptr<cpx<T>>(base, d.spec), bptr<cpx<T>>(base, d.tw0),              \
-                     bptr<double>(base, d.p_x), d.n1, 1, item.tile, lds);                 \
+    r2c_x_body<T, N>(bptr<cpx<T>>(base, d.psi), bptr<cpx<T>>(base, d.spec),              \
+                     bptr<cpx<T>>(base, d.tw0), bptr<double>(base, d.p_x), d.n1, 1,      \
+                     item.tile, lds);                                                     \
     break;
 #define GP_BODY_CONV(N)                                                                 \
   case N:                                                                               \
     conv_line_body<T, N>(bptr<cpx<T>>(base, d.spec), bptr<T>(base, d.ktab),              \
-                         bptr<cpx<T>>(base, d.tw1), d.n0 / 2 + 1, item.tile, lds);       \
+                         bptr<double>(base, d.scale), bptr<cpx<T>>(base, d.tw1),         \
+                         d.n0 / 2 + 1, item.tile, lds);                                  \
     break;
 #define GP_BODY_C2R(N)                                                                  \
   case N:                                                                               \

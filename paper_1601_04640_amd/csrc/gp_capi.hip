@@ -151,15 +151,16 @@ struct gp_ctx {
   // step loop replay: kGraphSteps steps captured once per time direction
   bool use_graphs = true;
   hipStream_t cap_st = nullptr;
-  // [imaginary, real entered with the pending finalisation reading x-partials 0, ... 1]
-  hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
-  // Real-time steps with the scale at 1 defer their finalisation into the next step's
-  // first pass: fin_pending marks one outstanding (its x partials in buffer pend_sel);
-  // px_sel is the buffer the x pass writes next; scale_one: the device scale is 1.
+  // [time direction imaginary/real][x-partial buffer of the finalisation outstanding
+  // when the graph starts]
+  hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  // Steps defer their finalisation into the next step's first pass: fin_pending marks
+  // one outstanding (mode pend_mode, its x partials in buffer pend_sel); px_sel is the
+  // buffer the x pass writes next.
   bool fin_pending = false;
   int pend_sel = 0;
+  int pend_mode = FIN_REAL;
   int px_sel = 0;
-  bool scale_one = true;
   // optional per-pass timing: event pairs recorded around selected pass launches
   unsigned tmask = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[GP_PASS_COUNT];
@@ -292,11 +293,10 @@ FinArgs fin_args(const gp_ctx* c, int sel) {
 gp_status settle(gp_ctx* c) {
   if (!c->fin_pending) return GP_OK;
   c->fin_pending = false;
-  FinArgs a = fin_args(c, c->pend_sel);
-  a.keep_scale = 1;
+  const FinArgs a = fin_args(c, c->pend_sel);
   if (a.nstage > 0)
-    hipLaunchKernelGGL(k_prereduce, dim3(a.nstage), dim3(kThreads), 0, c->st, a, (int)FIN_REAL);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, c->st, a, (int)FIN_REAL);
+    hipLaunchKernelGGL(k_prereduce, dim3(a.nstage), dim3(kThreads), 0, c->st, a, c->pend_mode);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, c->st, a, c->pend_mode);
   return dev(hipGetLastError());
 }
 
@@ -310,8 +310,11 @@ struct Passes {
   static const cpx<T>* cn(gp_ctx* c, int a, int k) { return c->at<cpx<T>>(c->L.o_cn[a][k]); }
 
   // y/z transforms of the x-half spectrum, U(k)/N product, inverse y/z transforms
-  // fin2: a two-stage folded finalisation whose second stage rides in the forward y FFT
-  static gp_status spectrum_passes(gp_ctx* c, const FinArgs* fin2 = nullptr) {
+  // y/z transforms of the x-half spectrum of the stored density, U(k) scale^2/N product,
+  // inverse transforms; fin2: a two-stage folded finalisation (mode fin_mode) whose
+  // second stage rides in the forward y FFT
+  static gp_status spectrum_passes(gp_ctx* c, const double* scale,
+                                   const FinArgs* fin2 = nullptr, int fin_mode = FIN_REAL) {
     const Layout& L = c->L;
     const int H = L.n0 / 2 + 1;
     if (c->p.geom == GP_3D) {
@@ -320,7 +323,7 @@ struct Passes {
       const int tc = tv_of(c->fp64, L.n2);
       if (fin2) {
         GP_HIP(Launch<T>::fft_line_fin(L.n1, (nl + lb - 1) / lb, c->st, spec(c), tw(c, 1), nl,
-                                       *fin2));
+                                       *fin2, fin_mode));
       } else {
         GP_PASS(c, GP_PASS_FFT_Y_FWD,
                 Launch<T>::fft_line(L.n1, false, (nl + lb - 1) / lb, c->st, spec(c), tw(c, 1),
@@ -328,34 +331,33 @@ struct Passes {
       }
       GP_PASS(c, GP_PASS_CONV_Z,
               Launch<T>::conv_col(L.n2, ((L.n1 + tc - 1) / tc) * H, c->st, spec(c),
-                                  c->at<T>(L.o_ktab), tw(c, 2), L.n1));
+                                  c->at<T>(L.o_ktab), scale, tw(c, 2), L.n1));
       GP_PASS(c, GP_PASS_FFT_Y_INV,
               Launch<T>::fft_line(L.n1, true, (nl + lb - 1) / lb, c->st, spec(c), tw(c, 1), nl));
     } else {
       const int lb = c->fp64 ? Launch<double>::lb(L.n1) : Launch<float>::lb(L.n1);
       GP_PASS(c, GP_PASS_CONV_Y,
               Launch<T>::conv_line(L.n1, (H + lb - 1) / lb, c->st, spec(c), c->at<T>(L.o_ktab),
-                                   tw(c, 1), H));
+                                   scale, tw(c, 1), H));
     }
     return GP_OK;
   }
 
   // density of `src` (times scale^2) -> spectrum -> U(k) product -> x-half spectrum;
-  // `fold`: the previous real-time step's finalisation rides in the x pass (one block,
-  // or the first-stage slices there and the finalize block in the forward y FFT)
+  // `fold`: the previous step's finalisation (mode fin_mode) rides in the x pass (one
+  // block, or the first-stage slices there and the finalize block in the forward y FFT)
   static gp_status convolution(gp_ctx* c, const cpx<T>* src, const double* scale,
-                               const FinArgs* fold = nullptr) {
+                               const FinArgs* fold = nullptr, int fin_mode = FIN_REAL) {
     const Layout& L = c->L;
     double* px = c->at<double>(L.o_px[c->px_sel]);
     if (fold) {
-      GP_HIP(Launch<T>::r2c_x_fin(L.n0, L.nb_x, c->st, src, scale, spec(c), tw(c, 0), px,
-                                  L.n1, L.n2, *fold, fold->nstage > 0 ? fold->nstage : 1));
+      GP_HIP(Launch<T>::r2c_x_fin(L.n0, L.nb_x, c->st, src, spec(c), tw(c, 0), px, L.n1, L.n2,
+                                  *fold, fin_mode, fold->nstage > 0 ? fold->nstage : 1));
     } else {
       GP_PASS(c, GP_PASS_R2C_X,
-              Launch<T>::r2c_x(L.n0, L.nb_x, c->st, src, scale, spec(c), tw(c, 0), px, L.n1,
-                               L.n2));
+              Launch<T>::r2c_x(L.n0, L.nb_x, c->st, src, spec(c), tw(c, 0), px, L.n1, L.n2));
     }
-    return spectrum_passes(c, fold && fold->nstage > 0 ? fold : nullptr);
+    return spectrum_passes(c, scale, fold && fold->nstage > 0 ? fold : nullptr, fin_mode);
   }
   static gp_status convolution(gp_ctx* c) { return convolution(c, psi(c), &c->sc()->scale); }
 
@@ -380,7 +382,7 @@ struct Passes {
     GP_HIP(Launch<T>::adj_x(L.n0, L.nb_x, c->st, lam, psin, c->at<T>(L.o_V), spec(c), tw(c, 0),
                             cn(c, 0, 2), sx, sf, gradV, pa, L.n1, L.n2));
     GP_HIP(Launch<T>::r2c_real(L.n0, L.nb_x, c->st, sf, spec(c), tw(c, 0), L.n1, L.n2));
-    GP_TRY(spectrum_passes(c));
+    GP_TRY(spectrum_passes(c, &c->sc()->one));
     GP_HIP(Launch<T>::adj_fin(L.n0, L.nb_x, c->st, lam, psin, sf, spec(c), tw(c, 0), sx, L.n1,
                               L.n2));
     const double cfac = (c->p.geom == GP_3D) ? 1.0 : 1.0 / (sqrt(2.0 * M_PI) * d_perp(c->p));
@@ -416,16 +418,17 @@ struct Passes {
     const int mode = imag ? MODE_IMAG : MODE_REAL;
     const int fin = imag ? (int)FIN_IMAG : (int)FIN_REAL;
     const int k = imag ? 0 : 1;  // factor table: imaginary or real time
-    // A real-time step with the scale at 1 and no per-pass timing defers its
-    // finalisation: the next step's x pass (or forward y FFT) carries it while writing
-    // the other x-partial buffer.  Its record and non-finite flag therefore land one
+    // Without per-pass timing a step defers its finalisation: the next step's x pass (or
+    // its forward y FFT) carries it while writing the other x-partial buffer.  The x pass
+    // does not read the scale the finalisation writes (the convolution and the x CN pass
+    // apply it, after it).  The record and non-finite flag of a step therefore land one
     // launch later; every other entry point settles an outstanding one first.
-    const bool defer = !imag && c->scale_one && c->tmask == 0;
+    const bool defer = c->tmask == 0;
     FinArgs prev{};
     bool fold = false;
+    const int prev_mode = c->pend_mode;
     if (defer && c->fin_pending) {
       prev = fin_args(c, c->pend_sel);
-      prev.keep_scale = 1;
       fold = c->p.geom == GP_3D || prev.nstage == 0;
       if (fold) {
         c->fin_pending = false;
@@ -433,7 +436,7 @@ struct Passes {
       }
     }
     GP_TRY(settle(c));
-    GP_TRY(convolution(c, psi(c), &c->sc()->scale, fold ? &prev : nullptr));
+    GP_TRY(convolution(c, psi(c), &c->sc()->scale, fold ? &prev : nullptr, prev_mode));
     const StepScalars sx = scalars_for(c, 0);
     // timed: the launch's own dispatch timestamps fill the event pair (no separate event
     // packets around it), and every block stamps its start and end
@@ -479,11 +482,10 @@ struct Passes {
     if (defer) {
       c->fin_pending = true;
       c->pend_sel = c->px_sel;
+      c->pend_mode = fin;
       return GP_OK;
     }
-    GP_TRY(finalize(c, fin));
-    c->scale_one = !imag;  // a real-time finalisation sets the scale to 1
-    return GP_OK;
+    return finalize(c, fin);
   }
 
   // One launch of a pass exactly as inside a real-time step (burst timing).
@@ -492,7 +494,7 @@ struct Passes {
     const int tcy = tc_of(c->fp64, L.n1);
     switch (pass) {
       case GP_PASS_R2C_X:
-        return dev(Launch<T>::r2c_x(L.n0, L.nb_x, c->st, psi(c), &c->sc()->scale, spec(c),
+        return dev(Launch<T>::r2c_x(L.n0, L.nb_x, c->st, psi(c), spec(c),
                                     tw(c, 0), c->at<double>(L.o_px[c->px_sel]), L.n1, L.n2));
       case GP_PASS_C2R_NL_CNX:
         return dev(Launch<T>::c2r_nl_cnx(L.n0, MODE_REAL, L.nb_x, c->st, psi(c),
@@ -601,7 +603,6 @@ struct Passes {
       GP_HIP(hipStreamSynchronize(c->st));
     }
     hipLaunchKernelGGL(k_set_scale_one, dim3(1), dim3(64), 0, c->st, &c->sc()->scale);
-    c->scale_one = true;
     return dev(hipGetLastError());
   }
 
@@ -660,10 +661,11 @@ gp_status check_flags(gp_ctx* c) {
 }
 
 void drop_graphs(gp_ctx* c) {
-  for (auto& g : c->gexec) {
-    if (g) hipGraphExecDestroy(g);
-    g = nullptr;
-  }
+  for (auto& row : c->gexec)
+    for (auto& g : row) {
+      if (g) hipGraphExecDestroy(g);
+      g = nullptr;
+    }
 }
 
 gp_status one_step(gp_ctx* c, bool imag) {
@@ -672,7 +674,7 @@ gp_status one_step(gp_ctx* c, bool imag) {
 
 // Capture kGraphSteps steps on a private stream (the caller's stream may be the null
 // stream, which cannot be captured); the graph is launched on the caller's stream.
-gp_status build_graph(gp_ctx* c, bool imag, int gi) {
+gp_status build_graph(gp_ctx* c, bool imag, int sel) {
   if (!c->cap_st) GP_HIP(hipStreamCreateWithFlags(&c->cap_st, hipStreamNonBlocking));
   const hipStream_t user = c->st;
   c->st = c->cap_st;
@@ -692,7 +694,7 @@ gp_status build_graph(gp_ctx* c, bool imag, int gi) {
   s = dev(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
   hipGraphDestroy(g);
   if (s != GP_OK) return s;
-  c->gexec[gi] = ex;
+  c->gexec[imag ? 0 : 1][sel] = ex;
   return GP_OK;
 }
 
@@ -701,7 +703,7 @@ gp_status run_steps(gp_ctx* c, int nsteps, bool imag) {
   clear_stale_error();
   if (nsteps < 0) return GP_E_ARG;
   if (!c->psi_set) return GP_E_STATE;
-  if (imag || !c->ekz_valid) GP_TRY(settle(c));
+  if (!c->ekz_valid) GP_TRY(settle(c));
   if (c->p.geom == GP_3D && !c->ekz_valid) {
     if (c->fp64) {
       GP_TRY(Passes<double>::z_observe(c, FIN_EKZ));
@@ -712,18 +714,18 @@ gp_status run_steps(gp_ctx* c, int nsteps, bool imag) {
   }
   int done = 0;
   if (c->use_graphs && c->tmask == 0 && nsteps >= kGraphSteps) {
-    // A real-time graph is captured and replayed from one state: the scale at 1 and a
-    // finalisation outstanding in x-partial buffer 0 or 1 (its graph index); the eight
+    // A graph is captured and replayed from one state: a finalisation of the same time
+    // direction outstanding in x-partial buffer 0 or 1 (its graph index); the eight
     // steps of a replay return to that state.
-    if (!imag)
-      while (done < nsteps && !(c->scale_one && c->fin_pending)) {
-        GP_TRY(one_step(c, false));
-        ++done;
-      }
-    const int gi = imag ? 0 : 1 + c->pend_sel;
-    if (nsteps - done >= kGraphSteps && !c->gexec[gi]) GP_TRY(build_graph(c, imag, gi));
+    const int fmode = imag ? (int)FIN_IMAG : (int)FIN_REAL;
+    if (!(c->fin_pending && c->pend_mode == fmode)) {
+      GP_TRY(one_step(c, imag));
+      ++done;
+    }
+    hipGraphExec_t& g = c->gexec[imag ? 0 : 1][c->pend_sel];
+    if (nsteps - done >= kGraphSteps && !g) GP_TRY(build_graph(c, imag, c->pend_sel));
     for (; nsteps - done >= kGraphSteps; done += kGraphSteps)
-      GP_HIP(hipGraphLaunch(c->gexec[gi], c->st));
+      GP_HIP(hipGraphLaunch(g, c->st));
   }
   for (; done < nsteps; ++done) GP_TRY(one_step(c, imag));
   return GP_OK;

@@ -28,7 +28,6 @@ struct FinArgs {
   double* obs;         // FIN_OBSERVE output record
   double* stage;       // two-stage reduction: kStageVals doubles per pre-reduced slice
   int nstage;          // slices (0: the finalize block reads the partials directly)
-  int keep_scale;      // real time with the scale already 1: leave it untouched
 };
 
 constexpr int kStageVals = 11;   // totals carried per slice (the v[] of finalize_block)
@@ -160,11 +159,11 @@ __device__ inline void finalize_block(const FinArgs& a, int mode) {
   // state to stay finite (zero is a solution)
   if (!isfinite(nout) || (mode == FIN_IMAG && !(nout > 0.0))) {
     *a.flags |= 1;
-    if (!a.keep_scale) *a.scale = 1.0;
+    *a.scale = 1.0;
     return;
   }
   const double sn = (mode == FIN_IMAG) ? 1.0 / sqrt(nout) : 1.0;
-  if (!a.keep_scale) *a.scale = sn;
+  *a.scale = sn;
   if (a.geom == 0) *a.ekz = 0.5 * sn * sn * v[10] / (a.h2 * a.h2) * dV;
 }
 

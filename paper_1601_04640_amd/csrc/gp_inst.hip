@@ -24,15 +24,15 @@ using T = GP_REAL;
 #if GP_FAMILY == 0
 template <>
 hipError_t Launch<T>::r2c_x_fin(int n0, int blocks, hipStream_t st, const cpx<T>* psi,
-                                const double* scale, cpx<T>* spec, const cpx<T>* tw0,
-                                double* part, int n1, int n2, const FinArgs& fa, int nfin) {
+                                cpx<T>* spec, const cpx<T>* tw0, double* part, int n1, int n2,
+                                const FinArgs& fa, int fin_mode, int nfin) {
   if (nfin < 1 || nfin > kStageMax) return hipErrorInvalidValue;
   const int nlead = (nfin + kFinLead - 1) / kFinLead * kFinLead;
   switch (n0) {
 #define X(N)                                                                              \
   case N:                                                                                 \
-    GP_LAUNCH((k_r2c_x_fin<T, N>), blocks + nlead, st, psi, scale, spec, tw0, part, n1, n2, \
-              fa, nfin, nlead);                                                           \
+    GP_LAUNCH((k_r2c_x_fin<T, N>), blocks + nlead, st, psi, spec, tw0, part, n1, n2, fa,  \
+              fin_mode, nfin, nlead);                                                     \
     break;
     GP_FOR_SIZES(X)
 #undef X
@@ -44,12 +44,11 @@ hipError_t Launch<T>::r2c_x_fin(int n0, int blocks, hipStream_t st, const cpx<T>
 
 template <>
 hipError_t Launch<T>::r2c_x(int n0, int blocks, hipStream_t st, const cpx<T>* psi,
-                            const double* scale, cpx<T>* spec, const cpx<T>* tw0, double* part,
-                            int n1, int n2) {
+                            cpx<T>* spec, const cpx<T>* tw0, double* part, int n1, int n2) {
   switch (n0) {
 #define X(N)                                                                        \
   case N:                                                                           \
-    GP_LAUNCH((k_r2c_x<T, N>), blocks, st, psi, scale, spec, tw0, part, n1, n2);    \
+    GP_LAUNCH((k_r2c_x<T, N>), blocks, st, psi, spec, tw0, part, n1, n2);           \
     break;
     GP_FOR_SIZES(X)
 #undef X
@@ -154,11 +153,12 @@ hipError_t Launch<T>::adj_fin(int n0, int blocks, hipStream_t st, cpx<T>* lam,
 #if GP_FAMILY == 1
 template <>
 hipError_t Launch<T>::fft_line_fin(int n, int blocks, hipStream_t st, cpx<T>* data,
-                                   const cpx<T>* tw, int nlines, const FinArgs& fa) {
+                                   const cpx<T>* tw, int nlines, const FinArgs& fa,
+                                   int fin_mode) {
   switch (n) {
 #define X(N)                                                                               \
   case N:                                                                                  \
-    GP_LAUNCH((k_fft_line_fin<T, N>), blocks + kFinLead, st, data, tw, nlines, fa);        \
+    GP_LAUNCH((k_fft_line_fin<T, N>), blocks + kFinLead, st, data, tw, nlines, fa, fin_mode); \
     break;
     GP_FOR_SIZES(X)
 #undef X
@@ -189,11 +189,11 @@ hipError_t Launch<T>::fft_line(int n, bool inv, int blocks, hipStream_t st, cpx<
 
 template <>
 hipError_t Launch<T>::conv_line(int n, int blocks, hipStream_t st, cpx<T>* data, const T* ktab,
-                                const cpx<T>* tw, int nlines) {
+                                const double* scale, const cpx<T>* tw, int nlines) {
   switch (n) {
 #define X(N)                                                                    \
   case N:                                                                       \
-    GP_LAUNCH((k_conv_line<T, N>), blocks, st, data, ktab, tw, nlines);         \
+    GP_LAUNCH((k_conv_line<T, N>), blocks, st, data, ktab, scale, tw, nlines);  \
     break;
     GP_FOR_SIZES(X)
 #undef X
@@ -205,11 +205,11 @@ hipError_t Launch<T>::conv_line(int n, int blocks, hipStream_t st, cpx<T>* data,
 
 template <>
 hipError_t Launch<T>::conv_col(int n2, int blocks, hipStream_t st, cpx<T>* spec, const T* ktab,
-                               const cpx<T>* tw2, int n1) {
+                               const double* scale, const cpx<T>* tw2, int n1) {
   switch (n2) {
 #define X(N)                                                                    \
   case N:                                                                       \
-    GP_LAUNCH((k_conv_col<T, N>), blocks, st, spec, ktab, tw2, n1);             \
+    GP_LAUNCH((k_conv_col<T, N>), blocks, st, spec, ktab, scale, tw2, n1);      \
     break;
     GP_FOR_SIZES(X)
 #undef X

@@ -193,11 +193,11 @@ constexpr size_t lds_bytes() {
 
 // ================================================================ pass bodies
 // ---------------------------------------------------------------- r2c_x
-// tiles: ceil(n1/TJ) * n2.  partials[bid*2 + {0,1}] = sum |dx psi|^2, sum |dy psi|^2 of
-// the stored psi (unscaled), the y difference reaching one line past the tile.
+// tiles: ceil(n1/TJ) * n2.  Spectrum of the stored |psi|^2 (unscaled: the convolution
+// applies scale^2).  partials[bid*2 + {0,1}] = sum |dx psi|^2, sum |dy psi|^2 of the
+// stored psi (unscaled), the y difference reaching one line past the tile.
 template <typename T, int N0>
 __device__ __forceinline__ void r2c_x_body(const cpx<T>* __restrict__ psi,
-                                           const double* __restrict__ scale,
                                            cpx<T>* __restrict__ spec,
                                            const cpx<T>* __restrict__ tw0,
                                            double* __restrict__ partials, int n1, int n2, int bid,
@@ -233,8 +233,6 @@ __device__ __forceinline__ void r2c_x_body(const cpx<T>* __restrict__ psi,
     by[it] = in ? l2 : z;
   }
   for (int i = tid; i < N0; i += kThreads) W[i] = tw0[i];
-  const double s = *scale;
-  const T s2 = (T)(s * s);
   // per-thread partials in T (at most 16 points), FP64 above
   T ps[2] = {0, 0};
 #pragma unroll
@@ -245,7 +243,7 @@ __device__ __forceinline__ void r2c_x_body(const cpx<T>* __restrict__ psi,
     const cpx<T> dx = bx[it] - a[it], dy = by[it] - a[it];
     ps[0] += dx.re * dx.re + dx.im * dx.im;
     ps[1] += dy.re * dy.re + dy.im * dy.im;
-    const T nv = s2 * (a[it].re * a[it].re + a[it].im * a[it].im);
+    const T nv = a[it].re * a[it].re + a[it].im * a[it].im;
     cpx<T>& zc = Z[(jl >> 1) * LSZ + i];
     if (jl & 1) zc.im = nv;
     else zc.re = nv;
@@ -416,6 +414,7 @@ __device__ __forceinline__ void fft_line_body(cpx<T>* __restrict__ data,
 template <typename T, int N>
 __device__ __forceinline__ void conv_line_body(cpx<T>* __restrict__ data,
                                                const T* __restrict__ ktab,
+                                               const double* __restrict__ scale,
                                                const cpx<T>* __restrict__ tw, int nlines, int bid,
                                                char* lds) {
   constexpr int LB = Tiles<T, N>::LB, LSZ = N + 1;
@@ -433,6 +432,8 @@ __device__ __forceinline__ void conv_line_body(cpx<T>* __restrict__ data,
     const int l = u / N, i = u % N;
     kv[it] = (IT::valid(u) && l0 + l < nlines) ? at32(ktab + (size_t)l0 * N, (unsigned)(l * N + i)) : (T)0;
   }
+  const double sc = *scale;
+  const T s2 = (T)(sc * sc);  // the density was transformed unscaled
   for (int i = tid; i < N; i += kThreads) W[i] = tw[i];
   __syncthreads();
   LdsFFT<T, N, LB, LSZ, 1, false>::template run<false>(B, W);
@@ -441,7 +442,7 @@ __device__ __forceinline__ void conv_line_body(cpx<T>* __restrict__ data,
     const int u = tid + it * kThreads;
     if (IT::valid(u)) {
       cpx<T>& e = B[(u / N) * LSZ + u % N];
-      e = scl(e, kv[it]);
+      e = scl(e, kv[it] * s2);
     }
   }
   __syncthreads();
@@ -455,6 +456,7 @@ __device__ __forceinline__ void conv_line_body(cpx<T>* __restrict__ data,
 template <typename T, int N2>
 __device__ __forceinline__ void conv_col_body(cpx<T>* __restrict__ spec,
                                               const T* __restrict__ ktab,
+                                              const double* __restrict__ scale,
                                               const cpx<T>* __restrict__ tw2, int n1, int bid,
                                               char* lds) {
   constexpr int TC = Tiles<T, N2>::TV, RS = TC + 1;
@@ -479,6 +481,12 @@ __device__ __forceinline__ void conv_col_body(cpx<T>* __restrict__ spec,
     kv[it] = in ? at32(ktab + plane + c0, g) : (T)0;
   }
   for (int i = tid; i < N2; i += kThreads) W[i] = tw2[i];
+  {
+    const double sc = *scale;
+    const T s2 = (T)(sc * sc);  // the density was transformed unscaled
+#pragma unroll
+    for (int it = 0; it < IT::N; ++it) kv[it] *= s2;
+  }
   using FFT = LdsFFT<T, N2, TC, 1, RS, true>;
   constexpr int R = IT::N;
   if constexpr (FFT::P.n == 2 && FFT::P.r[0] == R && FFT::P.r[1] == R && kThreads / TC == R &&
@@ -924,38 +932,37 @@ __device__ __forceinline__ void adj_fin_body(cpx<T>* __restrict__ lam,
 
 template <typename T, int N0>
 __global__ __launch_bounds__(kThreads) void k_r2c_x(const cpx<T>* __restrict__ psi,
-                                                    const double* __restrict__ scale,
                                                     cpx<T>* __restrict__ spec,
                                                     const cpx<T>* __restrict__ tw0,
                                                     double* __restrict__ partials, int n1, int n2) {
   GP_LDS(T, N0, P_R2C);
-  r2c_x_body<T, N0>(psi, scale, spec, tw0, partials, n1, n2, xcd_tile(blockIdx.x, gridDim.x),
-                    lds);
+  r2c_x_body<T, N0>(psi, spec, tw0, partials, n1, n2, xcd_tile(blockIdx.x, gridDim.x), lds);
 }
 
-// The x R2C of a real-time step with the previous step's finalisation folded in (the
-// scale is 1 and stays so; that finalisation reads the previous step's partials, which
-// this pass does not write).  The first nlead blocks (a multiple of 8, so that the tiles
-// keep their XCD placement) carry it: nfin of them run the finalize block or the
-// first-stage slices, the others return; the remaining blocks are the tiles.
+// The x R2C of a step with the previous step's finalisation folded in: that finalisation
+// reads the previous step's partials, which this pass does not write, and writes the
+// scale, which this pass does not read (the convolution applies it).  The first nlead
+// blocks (a multiple of 8, so that the tiles keep their XCD placement) carry it: nfin of
+// them run the finalize block or the first-stage slices, the others return; the
+// remaining blocks are the tiles.
 template <typename T, int N0>
 __global__ __launch_bounds__(kThreads) void k_r2c_x_fin(const cpx<T>* __restrict__ psi,
-                                                        const double* __restrict__ scale,
                                                         cpx<T>* __restrict__ spec,
                                                         const cpx<T>* __restrict__ tw0,
                                                         double* __restrict__ partials, int n1,
-                                                        int n2, FinArgs fa, int nfin, int nlead) {
+                                                        int n2, FinArgs fa, int fin_mode,
+                                                        int nfin, int nlead) {
   GP_LDS(T, N0, P_R2C);
   const int b = blockIdx.x;
   if (b < nlead) {
     if (b < nfin) {
-      if (fa.nstage > 0) prereduce_block<1>(fa, FIN_REAL, b);
-      else finalize_block<1>(fa, FIN_REAL);
+      if (fa.nstage > 0) prereduce_block<1>(fa, fin_mode, b);
+      else finalize_block<1>(fa, fin_mode);
     }
     return;
   }
-  r2c_x_body<T, N0>(psi, scale, spec, tw0, partials, n1, n2,
-                    xcd_tile(b - nlead, gridDim.x - nlead), lds);
+  r2c_x_body<T, N0>(psi, spec, tw0, partials, n1, n2, xcd_tile(b - nlead, gridDim.x - nlead),
+                    lds);
 }
 
 template <typename T, int N0>
@@ -979,11 +986,12 @@ __global__ __launch_bounds__(kThreads) void k_fft_line(cpx<T>* __restrict__ data
 template <typename T, int N>
 __global__ __launch_bounds__(kThreads) void k_fft_line_fin(cpx<T>* __restrict__ data,
                                                            const cpx<T>* __restrict__ tw,
-                                                           int nlines, FinArgs fa) {
+                                                           int nlines, FinArgs fa,
+                                                           int fin_mode) {
   GP_LDS(T, N, P_FFT_LINE);
   const int b = blockIdx.x;
   if (b < kFinLead) {
-    if (b == 0) finalize_block<1>(fa, FIN_REAL);
+    if (b == 0) finalize_block<1>(fa, fin_mode);
     return;
   }
   fft_line_body<T, N, false>(data, tw, nlines, b - kFinLead, lds);
@@ -992,17 +1000,19 @@ __global__ __launch_bounds__(kThreads) void k_fft_line_fin(cpx<T>* __restrict__ 
 template <typename T, int N>
 __global__ __launch_bounds__(kThreads) void k_conv_line(cpx<T>* __restrict__ data,
                                                         const T* __restrict__ ktab,
+                                                        const double* __restrict__ scale,
                                                         const cpx<T>* __restrict__ tw, int nlines) {
   GP_LDS(T, N, P_CONV_LINE);
-  conv_line_body<T, N>(data, ktab, tw, nlines, blockIdx.x, lds);
+  conv_line_body<T, N>(data, ktab, scale, tw, nlines, blockIdx.x, lds);
 }
 
 template <typename T, int N2>
 __global__ __launch_bounds__(kThreads) void k_conv_col(cpx<T>* __restrict__ spec,
                                                        const T* __restrict__ ktab,
+                                                       const double* __restrict__ scale,
                                                        const cpx<T>* __restrict__ tw2, int n1) {
   GP_LDS(T, N2, P_CONV_COL);
-  conv_col_body<T, N2>(spec, ktab, tw2, n1, xcd_tile(blockIdx.x, gridDim.x), lds);
+  conv_col_body<T, N2>(spec, ktab, scale, tw2, n1, xcd_tile(blockIdx.x, gridDim.x), lds);
 }
 
 template <typename T, int N0, int MODE>

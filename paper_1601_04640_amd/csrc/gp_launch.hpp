@@ -27,22 +27,21 @@ struct Launch {
   static int lb(int n);  // contiguous lines per block
   static int lbf(int n); // contiguous lines per block of the y FFT pass
 
-  static hipError_t r2c_x(int n0, int blocks, hipStream_t st, const cpx<T>* psi,
-                          const double* scale, cpx<T>* spec, const cpx<T>* tw0, double* part,
-                          int n1, int n2);
+  static hipError_t r2c_x(int n0, int blocks, hipStream_t st, const cpx<T>* psi, cpx<T>* spec,
+                          const cpx<T>* tw0, double* part, int n1, int n2);
   static hipError_t fft_line(int n, bool inv, int blocks, hipStream_t st, cpx<T>* data,
                              const cpx<T>* tw, int nlines);
-  // the real-time step's x R2C / forward y FFT carrying the previous step's
-  // finalisation (nfin blocks: 1 finalize block, or the first-stage slices)
+  // a step's x R2C / forward y FFT carrying the previous step's finalisation (mode
+  // fin_mode; nfin blocks: 1 finalize block, or the first-stage slices)
   static hipError_t r2c_x_fin(int n0, int blocks, hipStream_t st, const cpx<T>* psi,
-                              const double* scale, cpx<T>* spec, const cpx<T>* tw0,
-                              double* part, int n1, int n2, const FinArgs& fa, int nfin);
+                              cpx<T>* spec, const cpx<T>* tw0, double* part, int n1, int n2,
+                              const FinArgs& fa, int fin_mode, int nfin);
   static hipError_t fft_line_fin(int n, int blocks, hipStream_t st, cpx<T>* data,
-                                 const cpx<T>* tw, int nlines, const FinArgs& fa);
+                                 const cpx<T>* tw, int nlines, const FinArgs& fa, int fin_mode);
   static hipError_t conv_line(int n, int blocks, hipStream_t st, cpx<T>* data, const T* ktab,
-                              const cpx<T>* tw, int nlines);
+                              const double* scale, const cpx<T>* tw, int nlines);
   static hipError_t conv_col(int n2, int blocks, hipStream_t st, cpx<T>* spec, const T* ktab,
-                             const cpx<T>* tw2, int n1);
+                             const double* scale, const cpx<T>* tw2, int n1);
   static hipError_t c2r_nl_cnx(int n0, int mode, int blocks, hipStream_t st, cpx<T>* psi,
                                const T* V, const double* scale, const cpx<T>* spec,
                                const cpx<T>* tw0, const cpx<T>* cnm, const StepScalars& sc,
@@ -71,19 +70,19 @@ struct Launch {
   template <> int Launch<T>::tv(int);                                                         \
   template <> int Launch<T>::lb(int);                                                         \
   template <> int Launch<T>::lbf(int);                                                        \
-  template <> hipError_t Launch<T>::r2c_x(int, int, hipStream_t, const cpx<T>*, const double*, \
-                                          cpx<T>*, const cpx<T>*, double*, int, int);          \
+  template <> hipError_t Launch<T>::r2c_x(int, int, hipStream_t, const cpx<T>*, cpx<T>*,      \
+                                          const cpx<T>*, double*, int, int);                   \
   template <> hipError_t Launch<T>::fft_line(int, bool, int, hipStream_t, cpx<T>*,             \
                                              const cpx<T>*, int);                              \
-  template <> hipError_t Launch<T>::r2c_x_fin(int, int, hipStream_t, const cpx<T>*,           \
-                                              const double*, cpx<T>*, const cpx<T>*, double*, \
-                                              int, int, const FinArgs&, int);                 \
+  template <> hipError_t Launch<T>::r2c_x_fin(int, int, hipStream_t, const cpx<T>*, cpx<T>*,  \
+                                              const cpx<T>*, double*, int, int, const FinArgs&, \
+                                              int, int);                                      \
   template <> hipError_t Launch<T>::fft_line_fin(int, int, hipStream_t, cpx<T>*,              \
-                                                 const cpx<T>*, int, const FinArgs&);          \
+                                                 const cpx<T>*, int, const FinArgs&, int);     \
   template <> hipError_t Launch<T>::conv_line(int, int, hipStream_t, cpx<T>*, const T*,       \
-                                              const cpx<T>*, int);                             \
+                                              const double*, const cpx<T>*, int);              \
   template <> hipError_t Launch<T>::conv_col(int, int, hipStream_t, cpx<T>*, const T*,        \
-                                             const cpx<T>*, int);                              \
+                                             const double*, const cpx<T>*, int);               \
   template <> hipError_t Launch<T>::c2r_nl_cnx(int, int, int, hipStream_t, cpx<T>*, const T*, \
                                                const double*, const cpx<T>*, const cpx<T>*,    \
                                                const cpx<T>*, const StepScalars&, double*, T*, \

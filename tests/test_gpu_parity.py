@@ -296,12 +296,12 @@ def test_timing_span(gpu_lib):
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("name", ["3d_24x20x16", "2dxy_48x40", "3d_16x64x512"])
 def test_deferred_finalisation_bit_exact(name, prec, gpu_lib):
-    """Real-time steps fold each step's finalisation into the next step's first pass
-    (two-stage on 3d_16x64x512: first stage in the x pass, second in the forward y FFT),
-    through graphs and direct launches.  With per-pass timing on, every step finalises
-    in its own launch instead: psi, every history record and the energy are the same
-    bit for bit.  The run enters real time from imaginary time (scale not 1) and leaves
-    it for imaginary time and back."""
+    """Steps fold each step's finalisation into the next step's first pass (two-stage on
+    3d_16x64x512: first stage in the x pass, second in the forward y FFT), through
+    graphs and direct launches, in imaginary time (which renormalises) and real time.
+    With per-pass timing on, every step finalises in its own launch instead: psi, every
+    history record and the energy are the same bit for bit, across the switches between
+    the two time directions."""
     from paper_1601_04640_amd.binding import PASS_NAMES
     w = CASES[name]
     banner("deferred finalisation", name, prec)
@@ -312,12 +312,13 @@ def test_deferred_finalisation_bit_exact(name, prec, gpu_lib):
         s.set_psi(psi0)
         if timed:
             s.timing_enable(list(PASS_NAMES))
-        s.step_imag(3)
+        s.step_imag(11)
+        h = s.history(11)
         s.step_real(19)
-        h = s.history(19)
+        h += s.history(19)
         s.step_imag(1)
         s.step_real(10)
-        h += s.history(10)
+        h += s.history(11)
         e = s.energy()
         psi = s.get_psi()
         s.close()
@@ -326,7 +327,7 @@ def test_deferred_finalisation_bit_exact(name, prec, gpu_lib):
     psi_a, h_a, e_a = run(False)
     psi_b, h_b, e_b = run(True)
     assert np.array_equal(psi_a, psi_b)
-    assert len(h_a) == len(h_b) == 29
+    assert len(h_a) == len(h_b) == 41
     for ra, rb in zip(h_a, h_b):
         assert ra == rb, (ra, rb)
     assert e_a == e_b
