@@ -115,12 +115,11 @@ gp_status gp_set_couplings(gp_ctx* ctx, double g, double gdd);
 
 /* nsteps >= 0 steps in imaginary time (with renormalisation) / real time.
  * Asynchronous.  Each step also reduces the FP64 observables of the state it starts
- * from (kept in a history ring, see gp_history).  A real-time step taken with the
- * stored state at unit scale (any real-time step after the first one following
- * gp_set_psi or imaginary-time steps) leaves its final FP64 reduction to the next
- * real-time step's first launch; every other call on the context (gp_history, gp_sync,
- * gp_energy, gp_get_psi, ...) completes an outstanding one before it does anything
- * else, so what those calls see is unchanged. */
+ * from (kept in a history ring, see gp_history).  Each step leaves its final FP64
+ * reduction (the record, the non-finite check and, in imaginary time, the new
+ * renormalisation factor) to the next step's first launch; every other call on the
+ * context (gp_history, gp_sync, gp_energy, gp_get_psi, ...) completes an outstanding
+ * one before it does anything else, so what those calls see is unchanged. */
 gp_status gp_step_imag(gp_ctx* ctx, int nsteps);
 gp_status gp_step_real(gp_ctx* ctx, int nsteps);
 
