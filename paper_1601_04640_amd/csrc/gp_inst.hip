@@ -27,12 +27,17 @@ hipError_t Launch<T>::r2c_x_fin(int n0, int blocks, hipStream_t st, const cpx<T>
                                 cpx<T>* spec, const cpx<T>* tw0, double* part, int n1, int n2,
                                 const FinArgs& fa, int fin_mode, int nfin) {
   if (nfin < 1 || nfin > kStageMax) return hipErrorInvalidValue;
+  if (fin_mode != FIN_IMAG && fin_mode != FIN_REAL) return hipErrorInvalidValue;
   const int nlead = (nfin + kFinLead - 1) / kFinLead * kFinLead;
   switch (n0) {
 #define X(N)                                                                              \
   case N:                                                                                 \
-    GP_LAUNCH((k_r2c_x_fin<T, N>), blocks + nlead, st, psi, spec, tw0, part, n1, n2, fa,  \
-              fin_mode, nfin, nlead);                                                     \
+    if (fin_mode == FIN_IMAG)                                                             \
+      GP_LAUNCH((k_r2c_x_fin<T, N, FIN_IMAG>), blocks + nlead, st, psi, spec, tw0, part,  \
+                n1, n2, fa, nfin, nlead);                                                 \
+    else                                                                                  \
+      GP_LAUNCH((k_r2c_x_fin<T, N, FIN_REAL>), blocks + nlead, st, psi, spec, tw0, part,  \
+                n1, n2, fa, nfin, nlead);                                                 \
     break;
     GP_FOR_SIZES(X)
 #undef X
@@ -158,7 +163,10 @@ hipError_t Launch<T>::fft_line_fin(int n, int blocks, hipStream_t st, cpx<T>* da
   switch (n) {
 #define X(N)                                                                               \
   case N:                                                                                  \
-    GP_LAUNCH((k_fft_line_fin<T, N>), blocks + kFinLead, st, data, tw, nlines, fa, fin_mode); \
+    if (fin_mode == FIN_IMAG)                                                              \
+      GP_LAUNCH((k_fft_line_fin<T, N, FIN_IMAG>), blocks + kFinLead, st, data, tw, nlines, fa); \
+    else                                                                                   \
+      GP_LAUNCH((k_fft_line_fin<T, N, FIN_REAL>), blocks + kFinLead, st, data, tw, nlines, fa); \
     break;
     GP_FOR_SIZES(X)
 #undef X

@@ -216,6 +216,35 @@ __device__ __forceinline__ void r2c_x_body(const cpx<T>* __restrict__ psi,
   const cpx<T>* plane = psi + (size_t)k2 * n1 * N0;
   // all loads first: the point, its x neighbour and its y neighbour (mostly cache hits)
   cpx<T> a[IT::N], bx[IT::N], by[IT::N];
+  if constexpr (N0 == kThreads && sizeof(T) == 8) {
+    // lane = x index, register it = line j0 + it: the y neighbour is the next register
+    // (one halo line loaded past the tile), the x neighbour the next lane (a wave shift;
+    // the last lane of each wave loads its own).  In FP64 this frees the registers that
+    // held the neighbours (3 -> 4 waves per SIMD); FP32 is faster with the plain loads.
+    const cpx<T> z = {0, 0};
+    const int i = tid;
+    const bool last_lane = (tid & 63) == 63;
+#pragma unroll
+    for (int it = 0; it < IT::N; ++it) {
+      const int j = j0 + it;
+      const int jc = min(j, n1 - 1);
+      const cpx<T> l0 = at32(plane, (unsigned)(jc * N0 + i));
+      a[it] = j < n1 ? l0 : z;
+    }
+    const cpx<T> halo = at32(plane, (unsigned)(min(j0 + IT::N, n1 - 1) * N0 + i));
+#pragma unroll
+    for (int it = 0; it < IT::N; ++it) {
+      const int j = j0 + it;
+      const bool in = j < n1;
+      // min(j + 1, n1 - 1): the next line if there is one, else the point itself
+      const cpx<T> nxt = (it + 1 < IT::N) ? a[it + 1 < IT::N ? it + 1 : it] : halo;
+      by[it] = in ? csel(j + 1 <= n1 - 1, nxt, a[it]) : z;
+      const cpx<T> sh = dpp<DPP_WAVE_SHL1>(a[it]);
+      cpx<T> nb = sh;
+      if (last_lane && i < N0 - 1) nb = at32(plane, (unsigned)(min(j, n1 - 1) * N0 + i + 1));
+      bx[it] = in ? csel(i < N0 - 1, nb, a[it]) : z;
+    }
+  } else {
 #pragma unroll
   for (int it = 0; it < IT::N; ++it) {
     const int u = tid + it * kThreads;
@@ -231,6 +260,7 @@ __device__ __forceinline__ void r2c_x_body(const cpx<T>* __restrict__ psi,
     a[it] = in ? l0 : z;
     bx[it] = in ? l1 : z;
     by[it] = in ? l2 : z;
+  }
   }
   for (int i = tid; i < N0; i += kThreads) W[i] = tw0[i];
   // per-thread partials in T (at most 16 points), FP64 above
@@ -945,19 +975,19 @@ __global__ __launch_bounds__(kThreads) void k_r2c_x(const cpx<T>* __restrict__ p
 // blocks (a multiple of 8, so that the tiles keep their XCD placement) carry it: nfin of
 // them run the finalize block or the first-stage slices, the others return; the
 // remaining blocks are the tiles.
-template <typename T, int N0>
+template <typename T, int N0, int FIN_MODE>
 __global__ __launch_bounds__(kThreads) void k_r2c_x_fin(const cpx<T>* __restrict__ psi,
                                                         cpx<T>* __restrict__ spec,
                                                         const cpx<T>* __restrict__ tw0,
                                                         double* __restrict__ partials, int n1,
-                                                        int n2, FinArgs fa, int fin_mode,
-                                                        int nfin, int nlead) {
+                                                        int n2, FinArgs fa, int nfin,
+                                                        int nlead) {
   GP_LDS(T, N0, P_R2C);
   const int b = blockIdx.x;
   if (b < nlead) {
     if (b < nfin) {
-      if (fa.nstage > 0) prereduce_block<1>(fa, fin_mode, b);
-      else finalize_block<1>(fa, fin_mode);
+      if (fa.nstage > 0) prereduce_block<1>(fa, FIN_MODE, b);
+      else finalize_block<1>(fa, FIN_MODE);
     }
     return;
   }
@@ -983,15 +1013,14 @@ __global__ __launch_bounds__(kThreads) void k_fft_line(cpx<T>* __restrict__ data
 
 // Forward y FFT with the second stage of a two-stage folded finalisation (see
 // k_r2c_x_fin) in its first block; blocks 1-7 return, the rest are the lines.
-template <typename T, int N>
+template <typename T, int N, int FIN_MODE>
 __global__ __launch_bounds__(kThreads) void k_fft_line_fin(cpx<T>* __restrict__ data,
                                                            const cpx<T>* __restrict__ tw,
-                                                           int nlines, FinArgs fa,
-                                                           int fin_mode) {
+                                                           int nlines, FinArgs fa) {
   GP_LDS(T, N, P_FFT_LINE);
   const int b = blockIdx.x;
   if (b < kFinLead) {
-    if (b == 0) finalize_block<1>(fa, fin_mode);
+    if (b == 0) finalize_block<1>(fa, FIN_MODE);
     return;
   }
   fft_line_body<T, N, false>(data, tw, nlines, b - kFinLead, lds);
