@@ -123,13 +123,18 @@ struct KernelGeom {
 //  XZ:  U = [-1 + 3 sqrt(pi) (kz^2/q^2) xi erfcx(xi)]/(sqrt(2 pi) d)   (axis 1 = z)
 template <typename T>
 __global__ void k_kernel_table(T* ktab, KernelGeom kg) {
+  // 3D: U depends on k1 and k2 through their squares only, so the table holds the
+  // quadrant k1 <= n1/2, k2 <= n2/2 (ktab[(kx (n2/2+1) + k2) (n1/2+1) + k1]); the z
+  // convolution reads index min(k, n - k).  2D: the full [kx][k1] table.
   const int H = kg.n0 / 2 + 1;
-  const size_t total = (size_t)H * kg.n1 * kg.n2;
+  const bool q3 = kg.geom == 0;
+  const int m1n = q3 ? kg.n1 / 2 + 1 : kg.n1, m2n = q3 ? kg.n2 / 2 + 1 : kg.n2;
+  const size_t total = (size_t)H * m1n * m2n;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= total) return;
-  const int k1 = (int)(idx % kg.n1);
-  const int k2 = (int)((idx / kg.n1) % kg.n2);
-  const int kx = (int)(idx / ((size_t)kg.n1 * kg.n2));
+  const int k1 = (int)(idx % m1n);
+  const int k2 = (int)((idx / m1n) % m2n);
+  const int kx = (int)(idx / ((size_t)m1n * m2n));
   const double pi = 3.14159265358979323846;
   const double qx = 2.0 * pi * kx / (kg.n0 * kg.h0);
   const int m1 = (k1 < kg.n1 / 2) ? k1 : k1 - kg.n1;

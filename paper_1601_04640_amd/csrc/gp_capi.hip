@@ -42,7 +42,7 @@ size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 struct Layout {
   int n0, n1, n2;       // grid axes, x fastest
   double h0, h1, h2;
-  size_t npts, nspec;   // grid points, half-spectrum values
+  size_t npts, nspec, nktab;  // grid points, half-spectrum values, kernel-table values
   size_t esz;           // bytes of one real value
   int nb_x, nb_col, nb_colobs;
   // byte offsets inside the workspace
@@ -121,7 +121,9 @@ Layout make_layout(const gp_params* p) {
   L.o_psi = take(2 * L.esz * L.npts);
   L.o_V = take(L.esz * L.npts);
   L.o_spec = take(2 * L.esz * L.nspec);
-  L.o_ktab = take(L.esz * L.nspec);
+  // kernel table: 3D holds the quadrant k1 <= n1/2, k2 <= n2/2 of the half spectrum
+  L.nktab = (p->geom == GP_3D) ? (size_t)H * (L.n1 / 2 + 1) * (L.n2 / 2 + 1) : L.nspec;
+  L.o_ktab = take(L.esz * L.nktab);
   const int ns[3] = {L.n0, L.n1, L.n2};
   for (int a = 0; a < 3; ++a) {
     L.o_tw[a] = take(2 * L.esz * ns[a]);
@@ -566,7 +568,7 @@ struct Passes {
     kg.h2 = L.h2;
     kg.R = c->p.cutoff_R;
     kg.d = (c->p.geom == GP_3D) ? 0.0 : d_perp(c->p);
-    hipLaunchKernelGGL(k_kernel_table<T>, dim3(blocks_for(L.nspec)), dim3(kThreads), 0, c->st,
+    hipLaunchKernelGGL(k_kernel_table<T>, dim3(blocks_for(L.nktab)), dim3(kThreads), 0, c->st,
                        c->at<T>(L.o_ktab), kg);
     double w0 = c->p.gamma, w1, w2 = 0.0;
     if (c->p.geom == GP_3D) {

@@ -499,6 +499,9 @@ __device__ __forceinline__ void conv_col_body(cpx<T>* __restrict__ spec,
   const int kx = bid / nt;
   const int c0 = (bid % nt) * TC;
   const size_t plane = (size_t)kx * N2 * n1;
+  // the kernel table holds the quadrant k1 <= n1/2, k2 <= N2/2 (U is even in both)
+  const int H1 = n1 / 2 + 1;
+  const T* kq = ktab + (size_t)kx * (N2 / 2 + 1) * H1;
   cpx<T> v[IT::N];
   T kv[IT::N];
 #pragma unroll
@@ -507,8 +510,10 @@ __device__ __forceinline__ void conv_col_body(cpx<T>* __restrict__ spec,
     const int c = u % TC, r = u / TC;
     const bool in = IT::valid(u) && c0 + c < n1;
     const unsigned g = (unsigned)(r * n1 + c);
+    const int k1 = c0 + c;
+    const int k1r = min(k1, n1 - k1), k2r = min(r, N2 - r);
     v[it] = in ? at32(spec + plane + c0, g) : cpx<T>{0, 0};
-    kv[it] = in ? at32(ktab + plane + c0, g) : (T)0;
+    kv[it] = in ? at32(kq, (unsigned)(k2r * H1 + k1r)) : (T)0;
   }
   for (int i = tid; i < N2; i += kThreads) W[i] = tw2[i];
   {
