@@ -31,7 +31,8 @@ __device__ inline zd zinv(zd a) {
   return {a.re / d, -a.im / d};
 }
 
-// Each table holds m_0..m_{N-1}, then the scan weights of the line solve that sweeps
+// Each table holds f_i = 2 A m_i for i = 0..N-1 (the factor the solve multiplies the
+// right-hand side p_{i-1} + p_{i+1} - 2 p_i by; g_i = f_i / 2), then the scan weights of the line solve that sweeps
 // this axis with P lanes per line (chunks of S = ceil(N/P) points; cn_solve_lines):
 // per lane q, the gain its (gain, offset) map carries into each step of the forward
 // scan (entries s P + q) and of the backward scan (entries (NS + s) P + q), NS = log2 P.
@@ -83,7 +84,8 @@ __global__ void k_cn_tables(cpx<T>* m_im, cpx<T>* m_re, cpx<T>* m_adj, int N, do
   for (int i = 1; i <= N - 2; ++i) {
     const zd m = zinv(zsub(b, zmul(a, c)));
     c = zmul(a, m);
-    mt[i] = cpx<T>{(T)m.re, (T)m.im};
+    const zd f = zmul(zd{2.0 * A.re, 2.0 * A.im}, m);  // the solve's factor 2 A m
+    mt[i] = cpx<T>{(T)f.re, (T)f.im};
     const int q = i / S;
     gc[q] = zmul(gc[q], zd{-c.re, -c.im});
   }

@@ -24,7 +24,6 @@ struct BDesc {
   size_t cn1[2];  // second-axis factor tables
   size_t p_x, p_nl, p_col, scale;
   StepScalars sc;  // x-axis scalars (Ar for x)
-  double Ar1;      // dt/(4 h1^2)
   int n0, n1;
   FinArgs fa;      // FP64 finalisation of this instance
 };
@@ -95,7 +94,7 @@ __host__ __device__ constexpr int batch_class(int n) { return n > 256 ? 1 : 0; }
 #define GP_BODY_CN(N)                                                                   \
   case N:                                                                               \
     cn_col_body<T, N, MODE, true>(bptr<cpx<T>>(base, d.psi), bptr<cpx<T>>(base, d.cn1[K]), \
-                                  d.Ar1, bptr<double>(base, d.p_col), d.n0, (size_t)d.n0, \
+                                  bptr<double>(base, d.p_col), d.n0, (size_t)d.n0,        \
                                   (size_t)d.n0 * d.n1, item.tile, lds);                   \
     break;
 GP_BATCH_KERNEL(kb_r2c_x, n0, GP_BODY_R2C)

@@ -370,12 +370,10 @@ struct Passes {
     const int tcy = tc_of(c->fp64, L.n1);
     const int nb_y = ((L.n0 + tcy - 1) / tcy) * L.n2;
     if (c->p.geom == GP_3D) {
-      GP_HIP(Launch<T>::cn_col(L.n2, MODE_ADJ, false, L.nb_col, c->st, lam, cn(c, 2, 2),
-                               scalars_for(c, 2).Ar, nullptr, L.n0, (size_t)L.n0 * L.n1,
+      GP_HIP(Launch<T>::cn_col(L.n2, MODE_ADJ, false, L.nb_col, c->st, lam, cn(c, 2, 2), nullptr, L.n0, (size_t)L.n0 * L.n1,
                                (size_t)L.n0));
     }
-    GP_HIP(Launch<T>::cn_col(L.n1, MODE_ADJ, false, nb_y, c->st, lam, cn(c, 1, 2),
-                             scalars_for(c, 1).Ar, nullptr, L.n0, (size_t)L.n0,
+    GP_HIP(Launch<T>::cn_col(L.n1, MODE_ADJ, false, nb_y, c->st, lam, cn(c, 1, 2), nullptr, L.n0, (size_t)L.n0,
                              (size_t)L.n0 * L.n1));
     GP_TRY(convolution(c, psin, &c->sc()->one));
     const StepScalars sx = scalars_for(c, 0);
@@ -409,7 +407,7 @@ struct Passes {
   // with fin_mode (FIN_EKZ: pending z-kinetic part; FIN_OBSERVE: full record)
   static gp_status z_observe(gp_ctx* c, int fin_mode) {
     const Layout& L = c->L;
-    GP_HIP(Launch<T>::cn_col(L.n2, MODE_OBSERVE, true, L.nb_col, c->st, psi(c), nullptr, 0.0,
+    GP_HIP(Launch<T>::cn_col(L.n2, MODE_OBSERVE, true, L.nb_col, c->st, psi(c), nullptr,
                              c->at<double>(L.o_pcol), L.n0, (size_t)L.n0 * L.n1,
                              (size_t)L.n0));
     return finalize(c, fin_mode);
@@ -464,20 +462,18 @@ struct Passes {
       GP_HIP(hipGetLastError());
     }
     const int tcy = tc_of(c->fp64, L.n1);
-    const double Ay = scalars_for(c, 1).Ar;
     if (c->p.geom == GP_3D) {
       GP_PASS(c, GP_PASS_CN_Y,
               Launch<T>::cn_col(L.n1, mode, false, ((L.n0 + tcy - 1) / tcy) * L.n2, c->st,
-                                psi(c), cn(c, 1, k), Ay, nullptr, L.n0, (size_t)L.n0,
+                                psi(c), cn(c, 1, k), nullptr, L.n0, (size_t)L.n0,
                                 (size_t)L.n0 * L.n1));
-      const double Az = scalars_for(c, 2).Ar;
       GP_PASS(c, GP_PASS_CN_Z,
-              Launch<T>::cn_col(L.n2, mode, true, L.nb_col, c->st, psi(c), cn(c, 2, k), Az,
+              Launch<T>::cn_col(L.n2, mode, true, L.nb_col, c->st, psi(c), cn(c, 2, k),
                                 c->at<double>(L.o_pcol), L.n0, (size_t)L.n0 * L.n1,
                                 (size_t)L.n0));
     } else {
       GP_PASS(c, GP_PASS_CN_Y,
-              Launch<T>::cn_col(L.n1, mode, true, L.nb_col, c->st, psi(c), cn(c, 1, k), Ay,
+              Launch<T>::cn_col(L.n1, mode, true, L.nb_col, c->st, psi(c), cn(c, 1, k),
                                 c->at<double>(L.o_pcol), L.n0, (size_t)L.n0,
                                 (size_t)L.n0 * L.n1));
     }
@@ -506,15 +502,15 @@ struct Passes {
       case GP_PASS_CN_Y:
         if (c->p.geom == GP_3D)
           return dev(Launch<T>::cn_col(L.n1, MODE_REAL, false, ((L.n0 + tcy - 1) / tcy) * L.n2,
-                                       c->st, psi(c), cn(c, 1, 1), scalars_for(c, 1).Ar, nullptr,
+                                       c->st, psi(c), cn(c, 1, 1), nullptr,
                                        L.n0, (size_t)L.n0, (size_t)L.n0 * L.n1));
         return dev(Launch<T>::cn_col(L.n1, MODE_REAL, true, L.nb_col, c->st, psi(c), cn(c, 1, 1),
-                                     scalars_for(c, 1).Ar, c->at<double>(L.o_pcol), L.n0,
+                                     c->at<double>(L.o_pcol), L.n0,
                                      (size_t)L.n0, (size_t)L.n0 * L.n1));
       case GP_PASS_CN_Z:
         if (c->p.geom != GP_3D) return GP_E_ARG;
         return dev(Launch<T>::cn_col(L.n2, MODE_REAL, true, L.nb_col, c->st, psi(c), cn(c, 2, 1),
-                                     scalars_for(c, 2).Ar, c->at<double>(L.o_pcol), L.n0,
+                                     c->at<double>(L.o_pcol), L.n0,
                                      (size_t)L.n0 * L.n1, (size_t)L.n0));
       default:
         return GP_E_ARG;
@@ -849,7 +845,6 @@ gp_status batch_write_desc(gp_batch* b) {
     d.p_col = o + L.o_pcol;
     d.scale = o + L.o_scalars + offsetof(Scalars, scale);
     d.sc = scalars_for(c, 0);
-    d.Ar1 = scalars_for(c, 1).Ar;
     d.n0 = L.n0;
     d.n1 = L.n1;
     d.fa = fin_args(c, 0);

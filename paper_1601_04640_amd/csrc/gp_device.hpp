@@ -341,9 +341,11 @@ __device__ __forceinline__ int cpad(int i) { return i + i / S; }
 // (m = 0 on the two boundary rows makes them u = 0).  Each recurrence is an affine map
 // per chunk, composed across the P lanes of a line by a Hillis-Steele scan of (gain,
 // offset) pairs through DPP lane moves, then re-run with the exact carry-in.  P divides
-// 64, so one line never spans two waves.  mt holds m_i in LDS at cpad<S>(i) (the same
-// chunk padding as the data, so the P lanes of a line read distinct banks); each lane
-// reads its chunk, its two neighbours and its m_i once into registers.  Every thread
+// 64, so one line never spans two waves.  mt holds f_i = 2 A m_i in LDS at cpad<S>(i)
+// (the same chunk padding as the data, so the P lanes of a line read distinct banks):
+// the right-hand side 2 A (p_{i-1} + p_{i+1} - 2 p_i) enters as m_i r_i = f_i (p_{i-1} +
+// p_{i+1} - 2 p_i), and g_i = f_i / 2.  Each lane reads its chunk, its two neighbours and
+// its f_i once into registers.  Every thread
 // must call this; it ends with a block barrier.
 // Gains g = A m of the recurrences: complex when A = i a, real when A = a (then m is
 // real too).  mulg(g, x) = g x for a complex x; gg(g, h) = g h.
@@ -355,25 +357,24 @@ __device__ __forceinline__ cpx<T> mulg(T g, cpx<T> x) { return {g * x.re, g * x.
 template <typename T, bool IMAG_A>
 struct CnArith {
   using G = typename std::conditional<IMAG_A, cpx<T>, T>::type;
-  T a;   // A = a (imaginary time) or i a (real time, adjoint: a < 0)
-  T a2;  // 2 a
   static __device__ __forceinline__ G one() {
     if constexpr (IMAG_A) return cpx<T>{1, 0};
     else return (T)1;
   }
-  // g = A m
-  __device__ __forceinline__ G gain(cpx<T> m) const {
-    if constexpr (IMAG_A) return cpx<T>{-a * m.im, a * m.re};
-    else return a * m.re;
+  // The table holds f = 2 A m (complex when A = i a, real when A = a).
+  // g = A m = f / 2
+  __device__ __forceinline__ G gain(cpx<T> f) const {
+    if constexpr (IMAG_A) return cpx<T>{(T)0.5 * f.re, (T)0.5 * f.im};
+    else return (T)0.5 * f.re;
   }
-  // m x
-  __device__ __forceinline__ cpx<T> mulm(cpx<T> m, cpx<T> x) const {
-    return IMAG_A ? m * x : cpx<T>{m.re * x.re, m.re * x.im};
+  // f x = m * (2 A x)
+  __device__ __forceinline__ cpx<T> mulm(cpx<T> f, cpx<T> x) const {
+    return IMAG_A ? f * x : cpx<T>{f.re * x.re, f.re * x.im};
   }
-  // right-hand side of the increment system: 2 A (p_{i-1} + p_{i+1} - 2 p_i)
+  // the right-hand side of the increment system without its factor 2 A (which the
+  // table carries): p_{i-1} + p_{i+1} - 2 p_i
   __device__ __forceinline__ cpx<T> inc(cpx<T> pm, cpx<T> p0, cpx<T> pp) const {
-    const cpx<T> s = {pm.re + pp.re - (T)2 * p0.re, pm.im + pp.im - (T)2 * p0.im};
-    return IMAG_A ? cpx<T>{-a2 * s.im, a2 * s.re} : cpx<T>{a2 * s.re, a2 * s.im};
+    return cpx<T>{pm.re + pp.re - (T)2 * p0.re, pm.im + pp.im - (T)2 * p0.im};
   }
 };
 
@@ -417,13 +418,13 @@ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 
 template <typename T, int N, int NL, int LS, int ES, int P, bool IMAG_A>
 __device__ __forceinline__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt,
-                                               const cpx<T>* __restrict__ wt, T a) {
+                                               const cpx<T>* __restrict__ wt) {
   static_assert(64 % P == 0 && P <= 32 && NL * P == kThreads, "lanes per line");
   constexpr int S = (N + P - 1) / P;
   constexpr bool FULL = (N % P == 0);  // every lane's chunk lies inside the line
   using AR = CnArith<T, IMAG_A>;
   using GT = typename AR::G;
-  const AR ar{a, (T)2 * a};
+  const AR ar{};
   const int tid = thread_idx();
   const int l = tid / P, q = tid % P;
   const int lo = q * S;          // first element of the lane's chunk
@@ -466,7 +467,8 @@ __device__ __forceinline__ void cn_solve_lines(cpx<T>* buf, const cpx<T>* mt,
   if constexpr (FULL) {
     r[S - 1] = csel(q == P - 1, zero, r[S - 1]);  // element N - 1
   }
-  // r <- m * rhs, g = A m (m = 0 on the boundary rows and past the line end)
+  // r <- m * rhs = f * (p_{i-1} + p_{i+1} - 2 p_i), g = A m = f / 2 (f = 2 A m from the
+  // table; 0 on the boundary rows and past the line end)
   {
     cpx<T> prev = pl;
 #pragma unroll

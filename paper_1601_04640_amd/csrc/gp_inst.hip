@@ -231,10 +231,10 @@ hipError_t Launch<T>::conv_col(int n2, int blocks, hipStream_t st, cpx<T>* spec,
 #if GP_FAMILY == 2
 template <>
 hipError_t Launch<T>::cn_col(int n, int mode, bool sums, int blocks, hipStream_t st,
-                             cpx<T>* psi, const cpx<T>* cnm, double Ar, double* part, int n0,
+                             cpx<T>* psi, const cpx<T>* cnm, double* part, int n0,
                              size_t estride, size_t ostride) {
 #define CN(N, M, S) \
-  GP_LAUNCH((k_cn_col<T, N, M, S>), blocks, st, psi, cnm, Ar, part, n0, estride, ostride)
+  GP_LAUNCH((k_cn_col<T, N, M, S>), blocks, st, psi, cnm, part, n0, estride, ostride)
   switch (n) {
 #define X(N)                                        \
   case N:                                           \

@@ -96,12 +96,11 @@ struct StepScalars {
 // MODE_ADJ: the adjoint sweep of a real-time step (A -> conj(A) = -i Ar).
 enum : int { MODE_IMAG = 0, MODE_REAL = 1, MODE_OBSERVE = 2, MODE_PHI = 3, MODE_ADJ = 4 };
 
-// CN coupling of one sweep: A = a (imaginary time) or A = i a (real time: a = Ar;
-// adjoint of a real-time sweep: a = -Ar).
+// CN coupling of one sweep: A = Ar (imaginary time) or A = i Ar (real time; its adjoint
+// sweep: A = -i Ar).  The factor tables carry A; the sweep only needs to know whether it
+// is complex.
 template <int MODE>
 constexpr bool cn_imag_a() { return MODE != MODE_IMAG; }
-template <typename T, int MODE>
-__device__ __forceinline__ T cn_a(double Ar) { return (T)(MODE == MODE_ADJ ? -Ar : Ar); }
 
 // Global-memory phases are statically unrolled over ITERS = ceil(elements/kThreads)
 // so that every load of a thread is issued before the first one is consumed.
@@ -751,8 +750,7 @@ __device__ __forceinline__ void c2r_nl_cnx_body(
     }
     if constexpr (STEP) {
       __syncthreads();
-      cn_solve_lines<T, N0, TJ, LSP, 1, PX, cn_imag_a<MODE>()>(PS, MT, cnm + N0,
-                                                                cn_a<T, MODE>(sc.Ar));
+      cn_solve_lines<T, N0, TJ, LSP, 1, PX, cn_imag_a<MODE>()>(PS, MT, cnm + N0);
 #pragma unroll
       for (int it = 0; it < IT::N; ++it) {
         const int u = tid + it * kThreads;
@@ -786,7 +784,7 @@ __device__ __forceinline__ void c2r_nl_cnx_body(
 // tiles: ceil(n0/TC) * n_outer.
 template <typename T, int N, int MODE, bool SUMS>
 __device__ __forceinline__ void cn_col_body(cpx<T>* __restrict__ psi,
-                                            const cpx<T>* __restrict__ cnm, double Ar,
+                                            const cpx<T>* __restrict__ cnm,
                                             double* __restrict__ partials, int n0,
                                             size_t estride, size_t ostride, int bid, char* lds) {
   using G = CT<T, N>;
@@ -818,7 +816,7 @@ __device__ __forceinline__ void cn_col_body(cpx<T>* __restrict__ psi,
   }
   __syncthreads();
   if constexpr (SOLVE) {
-    cn_solve_lines<T, N, TC, 1, RS, PC, cn_imag_a<MODE>()>(B, MT, cnm + N, cn_a<T, MODE>(Ar));
+    cn_solve_lines<T, N, TC, 1, RS, PC, cn_imag_a<MODE>()>(B, MT, cnm + N);
   }
   double sums[2] = {0.0, 0.0};
 #pragma unroll
@@ -888,7 +886,7 @@ __device__ __forceinline__ void adj_x_body(
     if (IT::valid(u)) PS[(u / N0) * LSP + cpad<SX>(u % N0)] = lv[it];
   }
   c2r_tile<T, N0, NP>(Z, W, sa, sb);  // ends with a barrier
-  cn_solve_lines<T, N0, TJ, LSP, 1, PX, true>(PS, MT, cnm + N0, cn_a<T, MODE_ADJ>(sc.Ar));
+  cn_solve_lines<T, N0, TJ, LSP, 1, PX, true>(PS, MT, cnm + N0);
   double sums[2] = {0.0, 0.0};
   const T dt = (T)sc.dt;
 #pragma unroll
@@ -1069,10 +1067,10 @@ __global__ __launch_bounds__(kThreads) void k_c2r_nl_cnx(
 template <typename T, int N, int MODE, bool SUMS>
 __global__ __launch_bounds__(kThreads) void k_cn_col(cpx<T>* __restrict__ psi,
                                                      const cpx<T>* __restrict__ cnm,
-                                                     double Ar, double* __restrict__ partials,
+                                                     double* __restrict__ partials,
                                                      int n0, size_t estride, size_t ostride) {
   GP_LDS(T, N, P_CN_COL);
-  cn_col_body<T, N, MODE, SUMS>(psi, cnm, Ar, partials, n0, estride, ostride, blockIdx.x, lds);
+  cn_col_body<T, N, MODE, SUMS>(psi, cnm, partials, n0, estride, ostride, blockIdx.x, lds);
 }
 
 template <typename T, int N0>

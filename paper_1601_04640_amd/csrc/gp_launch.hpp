@@ -59,7 +59,7 @@ struct Launch {
                             const cpx<T>* psin, const T* sfield, const cpx<T>* spec,
                             const cpx<T>* tw0, const StepScalars& sc, int n1, int n2);
   static hipError_t cn_col(int n, int mode, bool sums, int blocks, hipStream_t st, cpx<T>* psi,
-                           const cpx<T>* cnm, double Ar, double* part, int n0, size_t estride,
+                           const cpx<T>* cnm, double* part, int n0, size_t estride,
                            size_t ostride);
 };
 
@@ -98,7 +98,7 @@ struct Launch {
                                             const T*, const cpx<T>*, const cpx<T>*,             \
                                             const StepScalars&, int, int);                      \
   template <> hipError_t Launch<T>::cn_col(int, int, bool, int, hipStream_t, cpx<T>*,         \
-                                           const cpx<T>*, double, double*, int, size_t, size_t);
+                                           const cpx<T>*, double*, int, size_t, size_t);
 GP_DECLARE_LAUNCH(float)
 GP_DECLARE_LAUNCH(double)
 #undef GP_DECLARE_LAUNCH
