@@ -23,7 +23,7 @@ struct BDesc {
   size_t cn0[2];  // x-axis factor tables: [imaginary, real time]
   size_t cn1[2];  // second-axis factor tables
   size_t p_x, p_nl, p_col, scale;
-  StepScalars sc;  // x-axis scalars (Ar for x)
+  StepScalars sc;  // step scalars (dt, couplings, spacings)
   int n0, n1;
   FinArgs fa;      // FP64 finalisation of this instance
 };

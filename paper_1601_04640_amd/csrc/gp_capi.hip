@@ -244,13 +244,11 @@ double contact(const gp_params& p) {
   return p.g / (sqrt(2.0 * M_PI) * d_perp(p));
 }
 
-StepScalars scalars_for(const gp_ctx* c, int axis) {
+StepScalars step_scalars(const gp_ctx* c) {
   StepScalars s{};
-  const double h[3] = {c->L.h0, c->L.h1, c->L.h2};
   s.dt = c->p.dt;
   s.gc = c->gc;
   s.gdd = c->p.gdd;
-  s.Ar = c->p.dt / (4.0 * h[axis] * h[axis]);
   s.h0 = c->L.h0;
   s.h1 = c->L.h1;
   s.h2 = c->L.h2;
@@ -376,7 +374,7 @@ struct Passes {
     GP_HIP(Launch<T>::cn_col(L.n1, MODE_ADJ, false, nb_y, c->st, lam, cn(c, 1, 2), nullptr, L.n0, (size_t)L.n0,
                              (size_t)L.n0 * L.n1));
     GP_TRY(convolution(c, psin, &c->sc()->one));
-    const StepScalars sx = scalars_for(c, 0);
+    const StepScalars sx = step_scalars(c);
     T* sf = c->at<T>(L.o_sfield);
     double* pa = c->at<double>(L.o_padj);
     GP_HIP(Launch<T>::adj_x(L.n0, L.nb_x, c->st, lam, psin, c->at<T>(L.o_V), spec(c), tw(c, 0),
@@ -437,7 +435,7 @@ struct Passes {
     }
     GP_TRY(settle(c));
     GP_TRY(convolution(c, psi(c), &c->sc()->scale, fold ? &prev : nullptr, prev_mode));
-    const StepScalars sx = scalars_for(c, 0);
+    const StepScalars sx = step_scalars(c);
     // timed: the launch's own dispatch timestamps fill the event pair (no separate event
     // packets around it), and every block stamps its start and end
     const bool span = (c->tmask >> GP_PASS_C2R_NL_CNX) & 1u;
@@ -497,7 +495,7 @@ struct Passes {
       case GP_PASS_C2R_NL_CNX:
         return dev(Launch<T>::c2r_nl_cnx(L.n0, MODE_REAL, L.nb_x, c->st, psi(c),
                                          c->at<T>(L.o_V), &c->sc()->scale, spec(c), tw(c, 0),
-                                         cn(c, 0, 1), scalars_for(c, 0), c->at<double>(L.o_pnl),
+                                         cn(c, 0, 1), step_scalars(c), c->at<double>(L.o_pnl),
                                          nullptr, L.n1, L.n2));
       case GP_PASS_CN_Y:
         if (c->p.geom == GP_3D)
@@ -520,7 +518,7 @@ struct Passes {
   static gp_status observe(gp_ctx* c) {
     const Layout& L = c->L;
     GP_TRY(convolution(c));
-    const StepScalars sx = scalars_for(c, 0);
+    const StepScalars sx = step_scalars(c);
     GP_HIP(Launch<T>::c2r_nl_cnx(L.n0, MODE_OBSERVE, L.nb_x, c->st, psi(c), c->at<T>(L.o_V),
                                  &c->sc()->scale, spec(c), tw(c, 0), nullptr, sx,
                                  c->at<double>(L.o_pnl), nullptr, L.n1, L.n2));
@@ -531,7 +529,7 @@ struct Passes {
   static gp_status phi(gp_ctx* c, T* out) {
     const Layout& L = c->L;
     GP_TRY(convolution(c));
-    const StepScalars sx = scalars_for(c, 0);
+    const StepScalars sx = step_scalars(c);
     GP_HIP(Launch<T>::c2r_nl_cnx(L.n0, MODE_PHI, L.nb_x, c->st, psi(c), c->at<T>(L.o_V),
                                  &c->sc()->scale, spec(c), tw(c, 0), nullptr, sx,
                                  c->at<double>(L.o_pnl), out, L.n1, L.n2));
@@ -844,7 +842,7 @@ gp_status batch_write_desc(gp_batch* b) {
     d.p_nl = o + L.o_pnl;
     d.p_col = o + L.o_pcol;
     d.scale = o + L.o_scalars + offsetof(Scalars, scale);
-    d.sc = scalars_for(c, 0);
+    d.sc = step_scalars(c);
     d.n0 = L.n0;
     d.n1 = L.n1;
     d.fa = fin_args(c, 0);

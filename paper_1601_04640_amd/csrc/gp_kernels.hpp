@@ -89,7 +89,6 @@ struct StepScalars {
   double dt;        // time step
   double gc;        // contact coupling (2D: includes 1/(sqrt(2 pi) d))
   double gdd;       // dipolar coupling
-  double Ar;        // dt/(4 dx^2): A = Ar (imaginary) or i Ar (real time)
   double h0, h1, h2;  // spacings along axes 0, 1, 2
 };
 
