@@ -72,6 +72,27 @@ def test_batch_equals_single_grid_path(gpu_lib):
     b.close()
 
 
+@pytest.mark.parametrize("shape", [("2dxy", 48, 64), ("2dxz", 384, 32)])
+def test_single_instance_batch(shape, gpu_lib):
+    """An ensemble of one instance (each pass then has a single size class, and the
+    384-point x axis puts the x passes in the large class alone) against the oracle."""
+    from paper_1601_04640_amd.binding import Batch
+    geom, nx, n1 = shape
+    w = small_ensemble(count=2, seed=80)[0 if geom == "2dxy" else 1]
+    w = dict(w, nx=nx, **({"ny": n1} if geom == "2dxy" else {"nz": n1}))
+    banner("single-instance batch", geom, nx, n1)
+    b = Batch([w], prec="fp64")
+    psi0 = start(w, 0)
+    b.set_psi(0, psi0)
+    b.step_imag(6)
+    b.step_real(5)
+    p = oparams(w)
+    ref = O.run(O.run(psi0, p, True, 6), p, False, 5)
+    assert rel_l2(b.get_psi(0), ref) <= FP64_PSI_TOL
+    assert not obs_close(b.energy()[0], O.observables(ref, p), FP64_E_TOL)
+    b.close()
+
+
 def test_full_ensemble_sampled(gpu_lib):
     """The 192-instance ensemble (sizes 96..512): a few steps; sampled instances against
     the single-grid path (bitwise) and the oracle (FP32 tolerance)."""
