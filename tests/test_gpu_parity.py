@@ -185,6 +185,31 @@ def test_zero_steps_and_boundary_zeroing(gpu_lib):
     s.close()
 
 
+def test_history_ring_wraps(gpu_lib):
+    """Past the ring's capacity the history holds the latest records, oldest first: the
+    records read before the wrap reappear bit for bit, followed by the new ones."""
+    from paper_1601_04640_amd import binding as B
+    cap = B.load().gp_history_capacity()
+    w = dict(CASES["2dxy_48x40"], nx=32, ny=32)
+    banner("history ring wrap", cap)
+    s = make_solver(w, "fp64")
+    s.set_psi(start_state(w, seed=12))
+    first = cap - 6
+    s.step_imag(first)
+    h1 = s.history(first)
+    assert len(h1) == first
+    s.step_imag(20)
+    h2 = s.history(cap + 100)
+    assert len(h2) == cap
+    key = lambda h: [h[k] for k in sorted(h)]
+    assert [key(h) for h in h2[:cap - 20]] == [key(h) for h in h1[20 - 6:]]
+    tail = s.history(20)
+    assert [key(h) for h in h2[cap - 20:]] == [key(h) for h in tail]
+    # every record left in the wrapped ring is of a state the previous step renormalised
+    assert all(abs(h["norm"] - 1.0) < 1e-12 for h in h2)
+    s.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_graph_replay_equals_direct_launches(prec, gpu_lib):
     """Steps replayed from captured HIP graphs are bitwise equal to direct launches, for
