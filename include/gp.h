@@ -87,34 +87,50 @@ typedef struct gp_observables {
 typedef struct gp_ctx gp_ctx;
 
 /* Bytes of device workspace a context with these parameters needs.  Validates params
- * exactly as gp_init does. */
+ * exactly as gp_init does.  (The paper's programs allocate the wave function, one complex
+ * temporary and up to two real grids on the device once, before any computation:
+ * "Summary of revisions" and Fig. 1; here the caller allocates that memory as one
+ * block.) */
 gp_status gp_workspace_bytes(const gp_params* params, size_t* bytes);
 
-/* Create a context.  dev_workspace: device pointer, >= gp_workspace_bytes, 256-byte
- * aligned, owned by the caller and kept alive until gp_destroy.  hip_stream: a
- * hipStream_t (NULL = the null stream).  Builds the FFT twiddles, the kernel table
- * U(k)/N, the CN factor tables and the harmonic V on the device; psi is unset. */
+/* Create a context ("Summary of revisions": the host initialises the variables, which
+ * are copied to the device once and stay there).  dev_workspace: device pointer,
+ * >= gp_workspace_bytes, 256-byte aligned, owned by the caller and kept alive until
+ * gp_destroy.  hip_stream: a hipStream_t (NULL = the null stream).  Builds the FFT
+ * twiddles, the kernel table U(k)/N (the momentum-space dipolar term of "Solution
+ * method"), the CN factor tables and the harmonic V ("Nature of problem") on the device;
+ * psi is unset.  Errors: GP_E_ARG (null pointer, misaligned or small workspace, bad
+ * parameter), GP_E_SIZE (see above), GP_E_NOMEM, GP_E_DEVICE. */
 gp_status gp_init(const gp_params* params, void* dev_workspace, size_t ws_bytes,
                   void* hip_stream, gp_ctx** out);
 gp_status gp_destroy(gp_ctx* ctx);
 const char* gp_status_string(gp_status status);
 
-/* Wave function I/O.  on_device = 0: host buffer of interleaved complex double.
- * on_device = 1: device buffer of interleaved complex in the context precision
- * (double for GP_FP64, float for GP_FP32_MIXED).  set: boundary points are zeroed;
- * the input is otherwise used as is (not renormalised).  get to host synchronises. */
+/* Wave function I/O ("Summary of revisions": only the wave function returns to the
+ * host, when output is written).  on_device = 0: host buffer of interleaved complex
+ * double.  on_device = 1: device buffer of interleaved complex in the context precision
+ * (double for GP_FP64, float for GP_FP32_MIXED).  The caller owns the buffer; it must
+ * hold nx*ny*nz (3D) or the plane's point count values.  set: boundary points are
+ * zeroed; the input is otherwise used as is (not renormalised).  get to host
+ * synchronises and reports GP_E_NONFINITE if the sticky flag is set. */
 gp_status gp_set_psi(gp_ctx* ctx, const void* psi, int on_device);
 gp_status gp_get_psi(gp_ctx* ctx, void* psi, int on_device);
 
-/* Replace the trap by an arbitrary real grid V (host: double; device: context
- * precision), same layout as psi. */
+/* Replace the trap ("Nature of problem": the harmonic anisotropic trap; the paper's pot
+ * array, Fig. 1) by an arbitrary real grid V (host: double; device: context precision),
+ * same layout as psi.  The caller keeps ownership; the values are copied. */
 gp_status gp_set_potential(gp_ctx* ctx, const void* V, int on_device);
 
-/* Change the couplings (e.g. a quench g -> g').  Takes effect for later steps. */
+/* Change the contact and dipolar couplings ("Nature of problem": contact and dipolar
+ * interactions), e.g. a quench g -> g'.  Takes effect for later steps.  GP_E_ARG for a
+ * non-finite value. */
 gp_status gp_set_couplings(gp_ctx* ctx, double g, double gdd);
 
-/* nsteps >= 0 steps in imaginary time (with renormalisation) / real time.
- * Asynchronous.  Each step also reduces the FP64 observables of the state it starts
+/* nsteps >= 0 steps in imaginary time (with renormalisation) / real time ("Solution
+ * method": propagation in imaginary or real time over small time steps; one step runs
+ * calcpsidd2, calcnu, calclux, calcluy, calcluz and, in imaginary time, calcnorm, in the
+ * order "Summary of revisions" lists them).  Asynchronous.  GP_E_STATE before
+ * gp_set_psi, GP_E_ARG for nsteps < 0.  Each step also reduces the FP64 observables of the state it starts
  * from (kept in a history ring, see gp_history).  Each step leaves its final FP64
  * reduction (the record, the non-finite check and, in imaginary time, the new
  * renormalisation factor) to the next step's first launch; every other call on the
@@ -140,11 +156,18 @@ gp_status gp_step_real(gp_ctx* ctx, int nsteps);
 gp_status gp_step_real_adjoint(gp_ctx* ctx, const void* psi_n, void* lam, double* gradV,
                                double* grad_g, double* grad_gdd);
 
-/* Observables of the current psi (computes Phi of this psi).  Synchronous. */
+/* Observables of the current psi: norm (calcnorm), energy, chemical potential and their
+ * parts (calcmuen, with the forward-difference kinetic term that calcmuen's partial
+ * derivatives stand for) and rms sizes (calcrms), all accumulated in FP64 ("Summary of
+ * revisions").  Computes Phi of this psi.  Synchronous; GP_E_NONFINITE if the sticky flag
+ * is set, GP_E_STATE before gp_set_psi. */
 gp_status gp_energy(gp_ctx* ctx, gp_observables* out);
 
-/* Phi = F^-1[U F[|psi|^2]] of the current psi, WITHOUT the g_dd factor.
- * on_device = 0: host buffer of double; 1: device buffer in context precision. */
+/* Phi = F^-1[U F[|psi|^2]] of the current psi, WITHOUT the g_dd factor: the dipolar
+ * potential that calcpsidd2 evaluates by the convolution theorem ("Solution method";
+ * real-to-complex and complex-to-real transforms of the real density, "Summary of
+ * revisions").  on_device = 0: host buffer of double (synchronous); 1: device buffer in
+ * context precision (asynchronous).  The caller owns the buffer. */
 gp_status gp_dipolar_potential(gp_ctx* ctx, void* phi, int on_device);
 
 /* Observables of the states the most recent steps started from, oldest first.
@@ -218,7 +241,12 @@ gp_status gp_batch_destroy(gp_batch* batch);
 /* The single-grid context of instance idx (owned by the batch; NULL if out of range):
  * use it for gp_set_psi / gp_get_psi / gp_energy / gp_history of that instance. */
 gp_ctx* gp_batch_context(gp_batch* batch, int idx);
-/* nsteps imaginary- / real-time steps of every instance (all psi must be set). */
+/* gp_set_psi / gp_get_psi of instance idx (GP_E_ARG if idx is out of range). */
+gp_status gp_batch_set_psi(gp_batch* batch, int idx, const void* psi, int on_device);
+gp_status gp_batch_get_psi(gp_batch* batch, int idx, void* psi, int on_device);
+/* nsteps imaginary- / real-time steps of every instance (all psi must be set;
+ * GP_E_STATE otherwise).  An instance context stepped on its own since the last batch
+ * step is brought up to date first. */
 gp_status gp_batch_step_imag(gp_batch* batch, int nsteps);
 gp_status gp_batch_step_real(gp_batch* batch, int nsteps);
 /* Observables of every instance's current psi (count records).  Synchronous. */
@@ -230,9 +258,33 @@ gp_status gp_batch_energy(gp_batch* batch, gp_observables* out);
 gp_status gp_batch_plan(gp_batch* batch, int* items, int* blocks);
 gp_status gp_batch_set_blocks(gp_batch* batch, int pass, int size_class, int blocks);
 gp_status gp_batch_use_graphs(gp_batch* batch, int enable);
+/* enable = 1: the larger size class of every pass runs on a second stream, forked from
+ * and joined back to the batch stream around the pass (so the two classes overlap; a
+ * captured step graph then has two branches per pass).  Default 0: one stream, one
+ * linear chain of launches. */
+gp_status gp_batch_use_streams(gp_batch* batch, int enable);
 
-/* Text of the HIP error behind the calling thread's most recent GP_E_DEVICE ("" if none).
- * The pointer stays valid until the thread's next failing call. */
+/* ------------------------------------------------------------ allocation-free call
+ * For callers that cannot allocate device memory, and cannot hand the library a
+ * workspace either: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Computes the same Phi = F^-1[U F[|psi|^2]] as gp_dipolar_potential
+ * (without the g_dd factor), for a device psi, with no context: psi and phi are device
+ * buffers in the precision of params->prec (interleaved complex / real, the layout of
+ * gp_set_psi), owned by the caller; work is enqueued on hip_stream (a hipStream_t, NULL =
+ * the null stream) and the call returns without waiting.  The half spectrum, the kernel
+ * table, the twiddles and the partial sums live in a library-owned static device array of
+ * 64 MiB per device (held until the process ends; enough for 128^3 in FP64, about 200^3
+ * in FP32); the call allocates no host or device memory.  Every call on one device
+ * shares that array and overwrites it, so calls that overlap on one device (two streams,
+ * two threads) race: serialise them.  Errors: GP_E_ARG (null pointer, bad parameter),
+ * GP_E_SIZE (unsupported axis, or a grid whose arrays exceed the 64 MiB; gp_last_error
+ * then gives the bytes needed), GP_E_DEVICE. */
+gp_status gp_dipolar_potential_noalloc(const gp_params* params, const void* psi, void* phi,
+                                       void* hip_stream);
+
+/* Text of the HIP error behind the calling thread's most recent GP_E_DEVICE, or of the
+ * size limit behind a GP_E_SIZE of gp_dipolar_potential_noalloc ("" if none).  The
+ * pointer stays valid until the thread's next failing call. */
 const char* gp_last_error(void);
 
 #ifdef __cplusplus

@@ -116,3 +116,35 @@ def energy_costate(psi, p: G.Params, V=None, kernel=None):
         pad_hi[ax] = (0, 1)
         tpsi += 0.5 * (np.pad(d, pad_lo) - np.pad(d, pad_hi)) / (h * h)
     return (tpsi + V * psi + G.contact_coupling(p) * n * psi + p.gdd * phi * psi) * p.dV()
+
+
+def energy_gradients(psi0, p: G.Params, nsteps, V=None):
+    """L = E(psi(T)) (the observables' energy of the state after nsteps real-time steps)
+    and its gradients with respect to V (grid), g and g_dd, plus the costate of the
+    initial state.  E depends on V, g and g_dd directly as well as through psi(T): the
+    direct terms are dE/dV = n dV, dE/dg_c = 1/2 sum n^2 dV, dE/dg_dd = 1/2 sum Phi n dV,
+    with n and Phi of psi(T); the rest comes back through the adjoint steps from the
+    terminal costate (energy_costate)."""
+    if V is None:
+        V = G.harmonic_potential(p)
+    kernel = G.dipolar_kernel(p)
+    states = forward_states(psi0, p, nsteps, V, kernel)
+    psiT = states[-1]
+    L = G.observables(psiT, p, V=V, kernel=kernel)["energy"]
+    n = np.abs(psiT) ** 2
+    phi = G.dipolar_potential(n, p, kernel)
+    dV = p.dV()
+    gV = n * dV
+    gg = 0.5 * float(np.sum(n * n)) * dV
+    ggdd = 0.5 * float(np.sum(phi * n)) * dV
+    # psi(T) is zero on the boundary rows whatever the inputs (Dirichlet), so its
+    # perturbations are too, and the costate's boundary rows carry nothing; the adjoint
+    # steps take them as zero (the adjoint of a sweep whose boundary outputs are fixed)
+    lam = G.zero_boundary(energy_costate(psiT, p, V=V, kernel=kernel))
+    for k in range(nsteps - 1, -1, -1):
+        lam, s, sn, sphi = adjoint_step(states[k], lam, p, V, kernel)
+        gV = gV + s
+        gg += sn
+        ggdd += sphi
+    return {"loss": L, "dV": gV, "dg": gg * contact_factor(p), "dgdd": ggdd, "lambda0": lam,
+            "final": psiT}

@@ -94,6 +94,10 @@ _SIGS = {
     "gp_batch_set_blocks": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "gp_batch_use_graphs": (ctypes.c_int, [_P, ctypes.c_int]),
     "gp_step_real_adjoint": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "gp_batch_set_psi": (ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.c_int]),
+    "gp_batch_get_psi": (ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.c_int]),
+    "gp_batch_use_streams": (ctypes.c_int, [_P, ctypes.c_int]),
+    "gp_dipolar_potential_noalloc": (ctypes.c_int, [ctypes.POINTER(gp_params), _P, _P, _P]),
     "gp_timing_enable": (ctypes.c_int, [_P, ctypes.c_uint]),
     "gp_timing_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_int)]),
@@ -131,8 +135,9 @@ class GPError(RuntimeError):
         self.status = status
         lib = load()
         msg = lib.gp_status_string(status).decode()
-        if status == GP_E_DEVICE:
-            msg += ": " + lib.gp_last_error().decode()
+        detail = lib.gp_last_error().decode() if status in (GP_E_DEVICE, GP_E_SIZE) else ""
+        if detail:
+            msg += ": " + detail
         super().__init__(f"{where}: {msg} ({status})")
 
 
@@ -213,6 +218,12 @@ def gp_dipolar_potential(ctx: int, ptr: int, on_device: int):
     _check(load().gp_dipolar_potential(_P(ctx), _P(ptr), on_device), "gp_dipolar_potential")
 
 
+def gp_dipolar_potential_noalloc(params: gp_params, psi_ptr: int, phi_ptr: int,
+                                 stream_ptr: int):
+    _check(load().gp_dipolar_potential_noalloc(ctypes.byref(params), _P(psi_ptr), _P(phi_ptr),
+                                               _P(stream_ptr)), "gp_dipolar_potential_noalloc")
+
+
 def gp_history(ctx: int, max_records: int) -> list:
     arr = (gp_observables * max(1, max_records))()
     cnt = ctypes.c_int(0)
@@ -253,6 +264,17 @@ def gp_timing_burst(ctx: int, pass_name: str, reps: int) -> float:
     _check(load().gp_timing_burst(_P(ctx), PASS_NAMES.index(pass_name), reps, ctypes.byref(ms)),
            "gp_timing_burst")
     return ms.value
+
+
+def supported_sizes(limit: int = 16384) -> list:
+    """Axis lengths gp_init accepts (probed through gp_workspace_bytes on a 2D grid)."""
+    out = []
+    for n in range(2, limit + 1, 2):
+        p = make_params("2dxy", nx=n, ny=8, lam=1.0)
+        nb = ctypes.c_size_t(0)
+        if load().gp_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == GP_OK:
+            out.append(n)
+    return out
 
 
 # ------------------------------------------------------------ convenience class
@@ -340,6 +362,13 @@ class Solver:
         gp_dipolar_potential(self.ctx, out.ctypes.data, 0)
         return out
 
+    def dipolar_potential_device(self):
+        """Phi of the current psi (without g_dd) as a device tensor of the context
+        precision (asynchronous on the solver's stream)."""
+        t = self.torch.empty(self.shape, dtype=self.rdtype, device=self.device)
+        gp_dipolar_potential(self.ctx, t.data_ptr(), 1)
+        return t
+
     def history(self, n: int) -> list:
         return gp_history(self.ctx, n)
 
@@ -424,12 +453,18 @@ class Batch:
     def set_psi(self, idx, psi):
         a = np.ascontiguousarray(psi, dtype=np.complex128)
         assert a.shape == self.shapes[idx]
-        gp_set_psi(self.ctxs[idx], a.ctypes.data, 0)
+        _check(load().gp_batch_set_psi(_P(self.handle), idx, _P(a.ctypes.data), 0),
+               "gp_batch_set_psi")
 
     def get_psi(self, idx):
         out = np.empty(self.shapes[idx], dtype=np.complex128)
-        gp_get_psi(self.ctxs[idx], out.ctypes.data, 0)
+        _check(load().gp_batch_get_psi(_P(self.handle), idx, _P(out.ctypes.data), 0),
+               "gp_batch_get_psi")
         return out
+
+    def use_streams(self, enable):
+        _check(load().gp_batch_use_streams(_P(self.handle), int(bool(enable))),
+               "gp_batch_use_streams")
 
     def step_imag(self, n):
         _check(load().gp_batch_step_imag(_P(self.handle), n), "gp_batch_step_imag")

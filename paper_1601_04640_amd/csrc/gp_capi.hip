@@ -6,9 +6,10 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+#include <mutex>
 #include <new>
 #include <utility>
-#include <algorithm>
 #include <vector>
 
 #include "../../include/gp.h"
@@ -727,6 +728,112 @@ gp_status run_steps(gp_ctx* c, int nsteps, bool imag) {
   return GP_OK;
 }
 
+// ------------------------------------------------ allocation-free dipolar potential
+// Library-owned scratch for gp_dipolar_potential_noalloc: the half spectrum, the kernel
+// table, the twiddles, the x-pass partial sums and the device scalars of one call.  Each
+// device holds its own copy for the life of the process.  In host code `scratch` only
+// names the symbol; the device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+gp_status scratch_for_current_device(char** out) {
+  int devid = 0;
+  GP_HIP(hipGetDevice(&devid));
+  if (devid < 0 || devid >= kMaxDevices) return GP_E_ARG;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[devid]) {
+    void* ptr = nullptr;
+    GP_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return GP_E_DEVICE;
+    g_scratch_ptr[devid] = reinterpret_cast<char*>(ptr);
+  }
+  *out = g_scratch_ptr[devid];
+  return GP_OK;
+}
+
+// The arrays one dipolar-potential evaluation touches, carved from offset 0: the pass
+// kernels address them through the context exactly as in a workspace.
+Layout scratch_layout(const gp_params* p) {
+  Layout L = make_layout(p);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t r = o;
+    o += align_up(bytes);
+    return r;
+  };
+  L.o_spec = take(2 * L.esz * L.nspec);
+  L.o_ktab = take(L.esz * L.nktab);
+  const int ns[3] = {L.n0, L.n1, L.n2};
+  for (int a = 0; a < 3; ++a) L.o_tw[a] = take(2 * L.esz * ns[a]);
+  L.o_px[0] = L.o_px[1] = take(sizeof(double) * 2 * L.nb_x);
+  L.o_scalars = take(sizeof(Scalars));
+  L.total = o;
+  return L;
+}
+
+template <typename T>
+gp_status dipolar_noalloc_t(gp_ctx* c, const cpx<T>* psi, T* phi) {
+  const Layout& L = c->L;
+  // tables of this call's grid (the scratch keeps whatever the last call left)
+  const int ns[3] = {L.n0, L.n1, L.n2};
+  const int naxes = (c->p.geom == GP_3D) ? 3 : 2;
+  for (int a = 0; a < naxes; ++a)
+    hipLaunchKernelGGL(k_twiddles<T>, dim3(blocks_for(ns[a])), dim3(kThreads), 0, c->st,
+                       c->at<cpx<T>>(L.o_tw[a]), ns[a]);
+  KernelGeom kg{};
+  kg.geom = c->p.geom;
+  kg.n0 = L.n0;
+  kg.n1 = L.n1;
+  kg.n2 = L.n2;
+  kg.h0 = L.h0;
+  kg.h1 = L.h1;
+  kg.h2 = L.h2;
+  kg.R = c->p.cutoff_R;
+  kg.d = (c->p.geom == GP_3D) ? 0.0 : d_perp(c->p);
+  hipLaunchKernelGGL(k_kernel_table<T>, dim3(blocks_for(L.nktab)), dim3(kThreads), 0, c->st,
+                     c->at<T>(L.o_ktab), kg);
+  Scalars* sc = c->sc();
+  hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, c->st, &sc->scale, &sc->one,
+                     &sc->ekz, &sc->flags, &sc->ring_pos);
+  GP_HIP(hipGetLastError());
+  // |psi|^2 of the caller's (physical) psi -> spectrum -> U(k)/N product -> inverse
+  GP_TRY(Passes<T>::convolution(c, psi, &sc->one));
+  GP_HIP(Launch<T>::c2r_nl_cnx(L.n0, MODE_PHI, L.nb_x, c->st, nullptr, nullptr, &sc->one,
+                               Passes<T>::spec(c), Passes<T>::tw(c, 0), nullptr,
+                               step_scalars(c), nullptr, phi, L.n1, L.n2));
+  return GP_OK;
+}
+
+gp_status dipolar_noalloc(const gp_params* p, const void* psi, void* phi, hipStream_t st) {
+  const Layout L = scratch_layout(p);
+  if (L.total > kScratchBytes) {
+    snprintf(g_last_error, sizeof(g_last_error),
+             "grid needs %zu bytes of scratch; the allocation-free call holds %zu",
+             L.total, kScratchBytes);
+    return GP_E_SIZE;
+  }
+  char* base = nullptr;
+  GP_TRY(scratch_for_current_device(&base));
+  // a context on the stack over the scratch: no host or device allocation
+  gp_ctx c;
+  c.p = *p;
+  c.L = L;
+  c.st = st;
+  c.ws = base;
+  c.fp64 = p->prec == GP_FP64;
+  c.psi_set = true;
+  c.ekz_valid = true;
+  c.gc = contact(c.p);
+  return c.fp64 ? dipolar_noalloc_t<double>(&c, reinterpret_cast<const cpx<double>*>(psi),
+                                            reinterpret_cast<double*>(phi))
+                : dipolar_noalloc_t<float>(&c, reinterpret_cast<const cpx<float>*>(psi),
+                                           reinterpret_cast<float*>(phi));
+}
+
 }  // namespace
 
 // =============================================================== batched ensemble
@@ -746,9 +853,11 @@ struct gp_batch {
   hipStream_t cap_st = nullptr;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   std::vector<double> cpl;                    // (g, g_dd) per instance in the descriptors
-  // The two size-class kernels of one pass touch disjoint work items: the larger class
-  // runs on a second stream (default priority), forked from and joined back to the
-  // step's stream around each pass.
+  // The two size-class kernels of one pass touch disjoint work items.  With
+  // two_streams set, the larger class runs on a second stream (default priority),
+  // forked from and joined back to the step's stream around each pass; by default both
+  // run in order on the step's stream, so a captured step graph is one linear chain.
+  bool two_streams = false;
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
@@ -919,7 +1028,8 @@ gp_status batch_step(gp_batch* b, hipStream_t st, bool imag) {
   for (int p : passes) {
     // an instance's class can differ between passes (x length vs y length), so the two
     // classes of one pass run side by side and the pass ends with both joined
-    const bool two = b->side != nullptr && b->nwork[p][0] > 0 && b->nwork[p][1] > 0;
+    const bool two =
+        b->two_streams && b->side != nullptr && b->nwork[p][0] > 0 && b->nwork[p][1] > 0;
     if (two) {
       GP_HIP(hipEventRecord(b->ev_fork, st));
       GP_HIP(hipStreamWaitEvent(b->side, b->ev_fork, 0));
@@ -974,6 +1084,16 @@ gp_status batch_run(gp_batch* b, int nsteps, bool imag) {
   if (stale) {  // gp_set_couplings on an instance context since the descriptors were written
     batch_drop_graphs(b);
     GP_TRY(b->fp64 ? batch_write_desc<double>(b) : batch_write_desc<float>(b));
+  }
+  // An instance context stepped on its own (gp_step_imag/real on it) may hold a deferred
+  // finalisation: complete it, so its scale and record are current before the batch
+  // kernels read them, and return its x-partial selection to buffer 0, which the batch
+  // descriptors name.
+  for (int i = 0; i < b->count; ++i) {
+    gp_ctx* c = b->inst[i];
+    GP_TRY(settle(c));
+    c->px_sel = 0;
+    c->pend_sel = 0;
   }
   int done = 0;
   if (b->use_graphs && nsteps >= kGraphSteps) {
@@ -1067,6 +1187,11 @@ gp_status gp_set_psi(gp_ctx* c, const void* psi, int on_device) {
                  : Passes<float>::set_psi(c, psi, on_device));
   c->psi_set = true;
   c->ekz_valid = false;
+  // nothing is outstanding after settle(): restart the x-partial double buffer, so that
+  // a step loop after a new state always starts from the same buffer (and replays the
+  // same captured graph)
+  c->px_sel = 0;
+  c->pend_sel = 0;
   return GP_OK;
 }
 
@@ -1386,11 +1511,37 @@ gp_status gp_batch_use_graphs(gp_batch* b, int enable) {
   return GP_OK;
 }
 
+gp_status gp_batch_use_streams(gp_batch* b, int enable) {
+  if (!b) return GP_E_ARG;
+  if (b->two_streams != (enable != 0)) batch_drop_graphs(b);  // a different graph shape
+  b->two_streams = enable != 0;
+  return GP_OK;
+}
+
+gp_status gp_batch_set_psi(gp_batch* b, int idx, const void* psi, int on_device) {
+  if (!b || idx < 0 || idx >= b->count) return GP_E_ARG;
+  return gp_set_psi(b->inst[idx], psi, on_device);
+}
+
+gp_status gp_batch_get_psi(gp_batch* b, int idx, void* psi, int on_device) {
+  if (!b || idx < 0 || idx >= b->count) return GP_E_ARG;
+  return gp_get_psi(b->inst[idx], psi, on_device);
+}
+
 gp_status gp_sync(gp_ctx* c) {
   clear_stale_error();
   if (!c) return GP_E_ARG;
   GP_TRY(settle(c));
   return check_flags(c);
+}
+
+gp_status gp_dipolar_potential_noalloc(const gp_params* params, const void* psi, void* phi,
+                                       void* hip_stream) {
+  clear_stale_error();
+  g_last_error[0] = '\0';
+  if (!params || !psi || !phi) return GP_E_ARG;
+  GP_TRY(validate(params));
+  return dipolar_noalloc(params, psi, phi, reinterpret_cast<hipStream_t>(hip_stream));
 }
 
 }  // extern "C"

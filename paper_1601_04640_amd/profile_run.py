@@ -30,16 +30,19 @@ import os
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL_SOURCES = ["paper_1601_04640_amd/csrc/gp_device.hpp",
-                  "paper_1601_04640_amd/csrc/gp_kernels.hpp"]
+CSRC = "paper_1601_04640_amd/csrc"
 
 
 def kernel_hash():
-    """Hash of the device sources the counters depend on."""
+    """Hash of every device and launch source the counters depend on (all of csrc/:
+    the kernels, the finalisation folded into them, the launch shapes and the host
+    schedule that orders the passes)."""
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+    for f in sorted(os.listdir(os.path.join(ROOT, CSRC))):
+        if f.endswith((".hpp", ".hip", ".h")):
+            with open(os.path.join(ROOT, CSRC, f), "rb") as fh:
+                h.update(f.encode())
+                h.update(fh.read())
     return h.hexdigest()[:16]
 
 

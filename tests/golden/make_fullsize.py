@@ -11,8 +11,29 @@ Every value here comes from the FP64 oracle (`oracle/`) on the seeded inputs of
                           192-instance quasi-2D ensemble (the four smallest grids and the
                           two smallest with a 384/512 axis): final observables and psi at
                           256 seeded sample points each.
+  ensemble_all_1000.json  the same 1000 steps for all 192 instances: final observables
+                          and psi at 64 seeded sample points per instance.
+  quench_128x96x80.json   128x96x80, dx 0.2, trap (1,1,2), g_dd 6, R 8: 1500 imaginary-
+                          time steps (dt 0.002) at g 20 from the seeded Gaussian (the
+                          ground state), then the quench to g 15 and 2000 real-time steps
+                          (dt 0.001).  Stores the ground state's observables and psi at
+                          1024 sample points, the observables every 10 real-time steps
+                          (state at the start of steps 0, 10, ..., 1990) and after the
+                          last one, and psi at the same 1024 points after 2000 steps.
+  real3d_256_500.json     256^3, dx 0.1, trap (1,1,3), g 50, g_dd 25, R 12.8: 500 real-
+                          time steps (dt 0.0005) from the seeded phase-noise Gaussian;
+                          observables every 10 steps and after the last one, psi at 4096
+                          sample points after 500 steps.
+  adjoint_real2dxy_256_4000.json, adjoint3d_128_200.json
+                          the adjoint oracle's overlap-loss gradients of the 256^2 x 4000
+                          step and 128^3 x 200 step real-time runs: loss, dL/dg, dL/dg_dd,
+                          the norm of dL/dV and dL/dV at sampled grid points.
 
-Usage: python tests/golden/make_fullsize.py   (about two minutes, one process)
+Usage: python tests/golden/make_fullsize.py [name ...]
+  (names: imag3d_64 ensemble ensemble_all quench real3d_256 adjoint_256 adjoint_128;
+  default all.  The two
+  large 3D runs take about 15 and 40 minutes on one core; ensemble_all uses a process
+  pool of up to 6 workers.)
 """
 from __future__ import annotations
 
@@ -106,12 +127,141 @@ def ensemble():
             "instances": recs}
 
 
-def main():
-    with open(os.path.join(HERE, "imag3d_64_500.json"), "w") as f:
-        json.dump(imag3d_64(), f)
-    with open(os.path.join(HERE, "ensemble_imag_1000.json"), "w") as f:
-        json.dump(ensemble(), f)
+def _instance_final(i):
+    ens = I.batched_ensemble()
+    w = ens[i]
+    p = params(w)
+    psi = O.run(I.psi0_instance(w, seed=[1606, i]), p, True, 1000)
+    idx = sample_indices(psi.shape, 64, 9000 + i)
+    return {"index": i, "final": obs_json(O.observables(psi, p)),
+            "sample_index": idx.tolist(),
+            "psi_re": psi.ravel()[idx].real.tolist(),
+            "psi_im": psi.ravel()[idx].imag.tolist()}
+
+
+def ensemble_all():
+    import multiprocessing as mp
+    ens = I.batched_ensemble()
+    t0 = time.time()
+    # largest instances first, so the pool's tail is short
+    order = sorted(range(len(ens)), key=lambda i: -ens[i]["nx"] * (
+        ens[i]["ny"] if ens[i]["geom"] == "2dxy" else ens[i]["nz"]))
+    with mp.Pool(min(6, os.cpu_count() or 1)) as pool:
+        recs = pool.map(_instance_final, order, chunksize=1)
+    recs.sort(key=lambda r: r["index"])
+    print(f"ensemble_all: {time.time() - t0:.1f} s", flush=True)
+    return {"ensemble": "inputs.batched_ensemble(count=192, seed=1606)",
+            "psi0": "inputs.psi0_instance(w, seed=[1606, i])", "steps": 1000,
+            "instances": recs}
+
+
+def _real_run_recorded(psi, p, nsteps, every):
+    """nsteps real-time steps; observables of the state at the start of every
+    `every`-th step and of the final state."""
+    V = O.harmonic_potential(p)
+    kernel = O.dipolar_kernel(p)
+    recs = []
+    for k in range(nsteps):
+        if k % every == 0:
+            recs.append(obs_json(O.observables(psi, p, V=V, kernel=kernel)))
+        psi = O.step(psi, p, False, V=V, kernel=kernel)
+    return psi, recs, obs_json(O.observables(psi, p, V=V, kernel=kernel))
+
+
+def quench():
+    w = I.WORKLOADS["real3d_128x96x80"]
+    t0 = time.time()
+    pg = params(dict(w, g=w["g_ground"], dt=0.002))
+    ground = O.run(I.psi0_real3d_128x96x80(), pg, True, 1500)
+    idx = sample_indices(ground.shape, 1024, 7003)
+    p = params(w)
+    psi, recs, final = _real_run_recorded(ground, p, 2000, 10)
+    print(f"quench: {time.time() - t0:.1f} s, E = {final['energy']:.12f}", flush=True)
+    return {"workload": "real3d_128x96x80", "ground_steps": 1500, "ground_dt": 0.002,
+            "ground_g": w["g_ground"], "steps": 2000, "every": 10,
+            "params": {k: w[k] for k in KEYS},
+            "psi0": "inputs.psi0_real3d_128x96x80(seed=1602)",
+            "ground": obs_json(O.observables(ground, pg)),
+            "sample_index": idx.tolist(),
+            "ground_re": ground.ravel()[idx].real.tolist(),
+            "ground_im": ground.ravel()[idx].imag.tolist(),
+            "records": recs, "final": final,
+            "psi_re": psi.ravel()[idx].real.tolist(),
+            "psi_im": psi.ravel()[idx].imag.tolist()}
+
+
+def real3d_256():
+    w = I.WORKLOADS["real3d_256"]
+    t0 = time.time()
+    p = params(w)
+    psi, recs, final = _real_run_recorded(I.psi0_real3d_256(), p, w["steps"], 10)
+    idx = sample_indices(psi.shape, 4096, 7004)
+    print(f"real3d_256: {time.time() - t0:.1f} s, E = {final['energy']:.12f}", flush=True)
+    return {"workload": "real3d_256", "steps": w["steps"], "every": 10,
+            "params": {k: w[k] for k in KEYS}, "psi0": "inputs.psi0_real3d_256(seed=1607)",
+            "records": recs, "final": final, "sample_index": idx.tolist(),
+            "psi_re": psi.ravel()[idx].real.tolist(),
+            "psi_im": psi.ravel()[idx].imag.tolist()}
+
+
+def _adjoint_record(ref, npoints, seed):
+    dV = ref["dV"]
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(dV.size, size=npoints, replace=False))
+    return {"loss": float(ref["loss"]), "dg": float(ref["dg"]), "dgdd": float(ref["dgdd"]),
+            "dV_norm": float(np.linalg.norm(dV)), "dV_index": idx.tolist(),
+            "dV_sample": dV.ravel()[idx].tolist()}
+
+
+def adjoint_256():
+    """The 256^2 real-time XY run with the perturbed trap, 4000 steps, overlap loss with
+    the displaced target: oracle gradients (the oracle keeps every state; K does not
+    enter the exact gradient)."""
+    from oracle import gp_adjoint as A
+    w = I.WORKLOADS["real2dxy_256"]
+    p = params(w)
+    t0 = time.time()
+    V = O.harmonic_potential(p) + I.trap_perturbation_real2dxy_256()
+    target = I.displaced_target(w, 1610, widths=(1.0 / np.sqrt(1.5), 1.0))
+    ref = A.overlap_gradients(I.psi0_real2dxy_256(), target, p, w["steps"], V=V)
+    print(f"adjoint_256: {time.time() - t0:.1f} s, L = {ref['loss']:.12f}", flush=True)
+    return dict(_adjoint_record(ref, 2048, 7005), workload="real2dxy_256", steps=w["steps"],
+                V="harmonic + inputs.trap_perturbation_real2dxy_256(seed=1608)",
+                target="inputs.displaced_target(w, 1610, widths=(1/sqrt(1.5), 1))")
+
+
+def adjoint_128():
+    """The 128^3 companion of the large 3D workload: 200 real-time steps, overlap loss with
+    the displaced target, harmonic trap: oracle gradients."""
+    from oracle import gp_adjoint as A
+    w = I.WORKLOADS["adjoint3d_128"]
+    p = params(w)
+    t0 = time.time()
+    target = I.displaced_target(w, 1611, widths=(1.0 / np.sqrt(3.0), 1.0, 1.0))
+    ref = A.overlap_gradients(I.psi0_adjoint3d_128(), target, p, w["steps"])
+    print(f"adjoint_128: {time.time() - t0:.1f} s, L = {ref['loss']:.12f}", flush=True)
+    return dict(_adjoint_record(ref, 4096, 7006), workload="adjoint3d_128", steps=w["steps"],
+                V="harmonic", target="inputs.displaced_target(w, 1611, widths=(1/sqrt(3), 1, 1))")
+
+
+JOBS = {
+    "imag3d_64": ("imag3d_64_500.json", imag3d_64),
+    "ensemble": ("ensemble_imag_1000.json", ensemble),
+    "ensemble_all": ("ensemble_all_1000.json", ensemble_all),
+    "quench": ("quench_128x96x80.json", quench),
+    "real3d_256": ("real3d_256_500.json", real3d_256),
+    "adjoint_256": ("adjoint_real2dxy_256_4000.json", adjoint_256),
+    "adjoint_128": ("adjoint3d_128_200.json", adjoint_128),
+}
+
+
+def main(names):
+    for name in names or list(JOBS):
+        fname, fn = JOBS[name]
+        out = fn()
+        with open(os.path.join(HERE, fname), "w") as f:
+            json.dump(out, f)
 
 
 if __name__ == "__main__":
-    main()
+    main(sys.argv[1:])

@@ -96,3 +96,71 @@ def test_adjoint_step_abi_accumulates(gpu_lib):
     assert abs(outs[1][1] - 2 * outs[0][1]) <= 1e-12 * abs(outs[0][1])
     assert abs(outs[1][2] - 2 * outs[0][2]) <= 1e-12 * abs(outs[0][2])
     s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_energy_loss_gradients_match_oracle(name, prec, gpu_lib):
+    """L = E(psi(T)): the terminal costate and direct terms of the energy loss, chained
+    through the adjoint steps, against the FP64 oracle (itself pinned by central
+    differences)."""
+    import torch
+    from paper_1601_04640_amd.adjoint import energy_loss, evolve_real
+    from paper_1601_04640_amd.binding import Solver
+    w, nsteps, K = CASES[name]
+    banner("adjoint energy loss", name, prec, nsteps, K)
+    p, psi0, _, V = inputs_for(w)
+    ref = A.energy_gradients(psi0, p, nsteps, V=V)
+    s = Solver(w, prec=prec)
+    dev = "cuda:0"
+    psi0_t = torch.from_numpy(psi0).to(dev, s.cdtype).requires_grad_(True)
+    V_t = torch.from_numpy(V).to(dev).requires_grad_(True)
+    g_t = torch.tensor(w["g"], dtype=torch.float64, device=dev, requires_grad=True)
+    gdd_t = torch.tensor(w["gdd"], dtype=torch.float64, device=dev, requires_grad=True)
+    L = energy_loss(evolve_real(s, psi0_t, V_t, g_t, gdd_t, nsteps, K), V_t, g_t, gdd_t, s)
+    L.backward()
+    tol = 1e-9 if prec == "fp64" else 1e-4
+    assert abs(float(L) - ref["loss"]) <= (1e-12 if prec == "fp64" else 1e-6) * abs(ref["loss"])
+    gV = V_t.grad.cpu().numpy()
+    err_v = np.linalg.norm(gV - ref["dV"]) / np.linalg.norm(ref["dV"])
+    assert err_v <= tol, err_v
+    assert abs(float(g_t.grad) - ref["dg"]) <= tol * abs(ref["dg"]), (float(g_t.grad), ref["dg"])
+    assert abs(float(gdd_t.grad) - ref["dgdd"]) <= tol * abs(ref["dgdd"]), \
+        (float(gdd_t.grad), ref["dgdd"])
+    lam0 = 0.5 * psi0_t.grad.cpu().numpy().astype(np.complex128)
+    err_l = np.linalg.norm(lam0 - ref["lambda0"]) / np.linalg.norm(ref["lambda0"])
+    assert err_l <= tol, err_l
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_solver_reused_between_forward_and_backward(prec, gpu_lib):
+    """Two forwards on one solver with different V and couplings, then backward through
+    the first: its gradients are those of its own V, g and g_dd (the oracle adjoint)."""
+    import torch
+    from paper_1601_04640_amd.adjoint import evolve_real, overlap_loss
+    from paper_1601_04640_amd.binding import Solver
+    w, nsteps, K = CASES["2dxy_48x40"]
+    banner("adjoint solver reuse", prec)
+    p, psi0, psi_t, V = inputs_for(w)
+    ref = A.overlap_gradients(psi0, psi_t, p, nsteps, V=V)
+    s = Solver(w, prec=prec)
+    dev = "cuda:0"
+
+    def forward(Vx, g, gdd):
+        p0 = torch.from_numpy(psi0).to(dev, s.cdtype).requires_grad_(True)
+        Vt = torch.from_numpy(Vx).to(dev).requires_grad_(True)
+        gt = torch.tensor(g, dtype=torch.float64, device=dev, requires_grad=True)
+        gdt = torch.tensor(gdd, dtype=torch.float64, device=dev, requires_grad=True)
+        L = overlap_loss(evolve_real(s, p0, Vt, gt, gdt, nsteps, K),
+                         torch.from_numpy(psi_t).to(dev, s.cdtype), p.dV())
+        return L, Vt, gt, gdt
+    L1, V1, g1, gdd1 = forward(V, w["g"], w["gdd"])
+    L2, _, _, _ = forward(1.3 * V, 0.5 * w["g"], 2.0 * w["gdd"])   # reuses the solver
+    L1.backward()
+    tol = 1e-9 if prec == "fp64" else 1e-4
+    err_v = np.linalg.norm(V1.grad.cpu().numpy() - ref["dV"]) / np.linalg.norm(ref["dV"])
+    assert err_v <= tol, err_v
+    assert abs(float(g1.grad) - ref["dg"]) <= tol * abs(ref["dg"])
+    assert abs(float(gdd1.grad) - ref["dgdd"]) <= tol * abs(ref["dgdd"])
+    s.close()

@@ -8,7 +8,7 @@ import pytest
 
 import oracle as O
 from paper_1601_04640_amd import inputs as I
-from tests.gpu_util import FP32_PSI_TOL, FP64_PSI_TOL, banner, oparams, rel_l2
+from tests.gpu_util import FP32_PSI_TOL, FP64_PSI_TOL, assert_psi_close, banner, oparams
 
 pytestmark = pytest.mark.gpu
 
@@ -75,7 +75,7 @@ def test_extreme_axis_lengths_2d(geom, nx, n1, prec, gpu_lib):
     s.step_imag(6)
     s.step_real(6)
     ref = O.run(O.run(psi0, p, True, 6), p, False, 6)
-    assert rel_l2(s.get_psi(), ref) <= (FP64_PSI_TOL if prec == "fp64" else FP32_PSI_TOL)
+    assert_psi_close(s.get_psi(), ref, FP64_PSI_TOL if prec == "fp64" else FP32_PSI_TOL)
     s.close()
 
 

@@ -14,7 +14,7 @@ import oracle as O
 from oracle import gp_adjoint as A
 from paper_1601_04640_amd import inputs as I
 from tests.gpu_util import (FP32_E_TOL, FP32_PART_TOL, FP32_PSI_TOL, FP64_E_TOL, FP64_PSI_TOL,
-                            banner, obs_close, oparams, rel_l2)
+                            assert_psi_close, banner, obs_close, oparams, rel_l2)
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -49,7 +49,7 @@ def test_imag3d_64_500_steps(prec, gpu_lib):
     psi = s.get_psi()
     got, ref = sampled(psi, g)
     ptol, etol = bars(prec)
-    assert rel_l2(got, ref) <= ptol, rel_l2(got, ref)
+    assert_psi_close(got, ref, ptol)
     bad = obs_close(s.energy(), g["final"], **etol)
     assert not bad, bad
     hist = s.history(g["steps"])
@@ -82,44 +82,66 @@ def test_real3d_128x96x80_steps_match_oracle(prec, gpu_lib):
     s.step_real(10)
     ref = oracle_quench_10()
     ptol, etol = bars(prec)
-    err = rel_l2(s.get_psi(), ref)
-    assert err <= ptol, err
+    assert_psi_close(s.get_psi(), ref, ptol)
     bad = obs_close(s.energy(), O.observables(ref, oparams(w)), **etol)
     assert not bad, bad
     s.close()
 
 
-def test_real3d_128x96x80_quench_properties(gpu_lib):
-    """FP64 relaxation at g = 20 (dt 0.002), quench to g = 15, 2000 real-time steps:
-    the norm is conserved to roundoff, the weaker repulsion contracts the cloud, and the
-    FP32 run from the same state stays within the FP32 bar of the FP64 run."""
+@functools.lru_cache(maxsize=None)
+def gpu_ground_state_128x96x80():
+    """The FP64 imaginary-time ground state at g = 20 (dt 0.002, 1500 steps) on the GPU,
+    the start of both quench runs, with its observables."""
     from paper_1601_04640_amd.binding import Solver
     w = dict(I.WORKLOADS["real3d_128x96x80"])
-    banner("real3d_128x96x80 quench 2000 steps")
     gs = Solver(dict(w, g=w["g_ground"], dt=0.002), prec="fp64")
     gs.set_psi(I.psi0_real3d_128x96x80())
     gs.step_imag(1500)
-    psi_g = gs.get_psi()
+    psi, ob = gs.get_psi(), gs.energy()
     gs.close()
-    runs = {}
-    for prec in ("fp64", "fp32"):
-        s = Solver(w, prec=prec)
-        s.set_psi(psi_g)
-        s.step_real(2000)
-        runs[prec] = (s.history(2000), s.get_psi(), s.energy())
-        s.close()
-    hist, psi64, end64 = runs["fp64"]
-    norms = np.array([h["norm"] for h in hist] + [end64["norm"]])
-    assert np.max(np.abs(norms - 1.0)) <= 1e-11
-    rx = np.array([h["rms"][0] for h in hist])
-    assert rx.min() < rx[0] - 1e-3                          # contraction after the quench
-    hist32, psi32, end32 = runs["fp32"]
-    n32 = np.array([h["norm"] for h in hist32])
-    assert np.max(np.abs(n32 - 1.0)) <= 1e-5
-    print("fp32 vs fp64 after 2000 steps: psi rel", rel_l2(psi32, psi64),
-          "energy rel", abs(end32["energy"] - end64["energy"]) / abs(end64["energy"]))
-    assert rel_l2(psi32, psi64) <= 1e-3
-    assert abs(end32["energy"] - end64["energy"]) <= 1e-5 * abs(end64["energy"])
+    return psi, ob
+
+
+def check_records(recs, ref_recs, every, etol, what):
+    """Per-step records of the GPU run against the oracle's, every `every` steps."""
+    for k, r in enumerate(ref_recs):
+        bad = obs_close(recs[k * every], r, **etol)
+        assert not bad, (what, k * every, bad)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_real3d_128x96x80_quench_vs_oracle(prec, gpu_lib):
+    """The whole quench workload against the oracle: the FP64 ground state at g = 20
+    (1500 imaginary-time steps), then g = 15 and 2000 real-time steps in `prec`.  The
+    ground state, the observables every 10 steps, the final observables and psi at 1024
+    sampled points are held at the parity bars; the norm stays 1."""
+    from paper_1601_04640_amd.binding import Solver
+    g = golden("quench_128x96x80.json")
+    w = I.WORKLOADS["real3d_128x96x80"]
+    banner("real3d_128x96x80 quench 1500 + 2000 steps", prec)
+    psi_g, ob_g = gpu_ground_state_128x96x80()
+    idx = np.asarray(g["sample_index"])
+    ref_g = np.asarray(g["ground_re"]) + 1j * np.asarray(g["ground_im"])
+    l2, mx = assert_psi_close(psi_g.ravel()[idx], ref_g, FP64_PSI_TOL, "ground state")
+    print(f"ground state vs oracle: rel-L2 {l2:.2e}, max {mx:.2e}")
+    assert not obs_close(ob_g, g["ground"], FP64_E_TOL)
+    s = Solver(w, prec=prec)
+    s.set_psi(psi_g)
+    s.step_real(g["steps"])
+    ptol, etol = bars(prec)
+    recs = s.history(g["steps"])
+    assert len(recs) == g["steps"]
+    check_records(recs, g["records"], g["every"], etol, "quench")
+    end = s.energy()
+    assert not obs_close(end, g["final"], **etol)
+    got = s.get_psi().ravel()[idx]
+    ref = np.asarray(g["psi_re"]) + 1j * np.asarray(g["psi_im"])
+    l2, mx = assert_psi_close(got, ref, ptol, "after 2000 steps")
+    print(f"{prec} after 2000 real-time steps vs oracle: rel-L2 {l2:.2e}, max {mx:.2e}, "
+          f"energy rel {abs(end['energy'] - g['final']['energy']) / abs(g['final']['energy']):.2e}")
+    norms = np.array([h["norm"] for h in recs] + [end["norm"]])
+    assert np.max(np.abs(norms - 1.0)) <= (1e-11 if prec == "fp64" else 1e-5)
+    s.close()
 
 
 # ----------------------------------------------------------------- real3d 256^3
@@ -130,19 +152,29 @@ def oracle_256_one_step():
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_real3d_256_step_matches_oracle(prec, gpu_lib):
+def test_real3d_256_500_steps_vs_oracle(prec, gpu_lib):
+    """The large workload: the first step against the oracle on the whole grid, then the
+    500 steps against the oracle's fixture (observables every 10 steps and at the end,
+    psi at 4096 sampled points)."""
     from paper_1601_04640_amd.binding import Solver
+    g = golden("real3d_256_500.json")
     w = I.WORKLOADS["real3d_256"]
-    banner("real3d_256 one step", prec)
+    banner("real3d_256 500 steps", prec)
     s = Solver(w, prec=prec)
     s.set_psi(I.psi0_real3d_256())
     s.step_real(1)
-    err = rel_l2(s.get_psi(), oracle_256_one_step())
-    ptol, _ = bars(prec)
-    assert err <= ptol, err
-    # then the workload's 500 steps: the norm stays 1
-    s.step_real(499)
-    nrm = np.array([h["norm"] for h in s.history(499)])
+    ptol, etol = bars(prec)
+    assert_psi_close(s.get_psi(), oracle_256_one_step(), ptol, "one step")
+    s.step_real(g["steps"] - 1)
+    recs = s.history(g["steps"])
+    assert len(recs) == g["steps"]
+    check_records(recs, g["records"], g["every"], etol, "real3d_256")
+    end = s.energy()
+    assert not obs_close(end, g["final"], **etol)
+    got, ref = sampled(s.get_psi(), g)
+    l2, mx = assert_psi_close(got, ref, ptol, "after 500 steps")
+    print(f"{prec} 256^3 after 500 steps vs oracle: rel-L2 {l2:.2e}, max {mx:.2e}")
+    nrm = np.array([h["norm"] for h in recs] + [end["norm"]])
     assert np.max(np.abs(nrm - 1.0)) <= (1e-11 if prec == "fp64" else 1e-5)
     s.close()
 
@@ -222,13 +254,29 @@ def check_fd(w, prec, psi0, V, target, nsteps, grads, params=("g", "gdd"), npoin
         assert abs(dV[idx] - fd) <= tol * gmax, (idx, dV[idx], fd)
 
 
+def check_adjoint_fixture(grads, g, prec):
+    """Loss and gradients against the adjoint oracle's fixture: FP64 1e-9 relative
+    (loss 1e-12), FP32 1e-4 (loss 1e-6); dL/dV by its norm and at the sampled points."""
+    tol = 1e-9 if prec == "fp64" else 1e-4
+    ltol = 1e-12 if prec == "fp64" else 1e-6
+    assert abs(grads["loss"] - g["loss"]) <= ltol * abs(g["loss"]), (grads["loss"], g["loss"])
+    assert abs(grads["dg"] - g["dg"]) <= tol * abs(g["dg"]), (grads["dg"], g["dg"])
+    assert abs(grads["dgdd"] - g["dgdd"]) <= tol * abs(g["dgdd"]), (grads["dgdd"], g["dgdd"])
+    dV = grads["dV"]
+    assert abs(np.linalg.norm(dV) - g["dV_norm"]) <= tol * g["dV_norm"]
+    got = dV.ravel()[np.asarray(g["dV_index"])]
+    ref = np.asarray(g["dV_sample"])
+    assert np.max(np.abs(got - ref)) <= tol * np.max(np.abs(ref))
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_adjoint_real2dxy_256_4000_steps_fd(prec, gpu_lib):
+    """The 4000-step adjoint workload (checkpoints every 50): against the adjoint oracle's
+    fixture of the same run, and against central differences of the FP64 GPU forward."""
     w, psi0, V, target = adjoint_2d_inputs()
     banner("adjoint real2dxy_256 4000 steps K=50", prec)
     grads = gpu_gradients(w, prec, psi0, V, target, 4000, 50)
-    L64 = forward_loss(w, "fp64", psi0, V, target, 4000)
-    assert abs(grads["loss"] - L64) <= (1e-12 if prec == "fp64" else 1e-5)
+    check_adjoint_fixture(grads, golden("adjoint_real2dxy_256_4000.json"), prec)
     check_fd(w, prec, psi0, V, target, 4000, grads, tol=1e-6 if prec == "fp64" else 1e-4)
 
 
@@ -255,6 +303,7 @@ def test_adjoint3d_128_fd(prec, gpu_lib):
     V = O.harmonic_potential(p)
     target = I.displaced_target(w, 1611, widths=(1.0 / np.sqrt(3.0), 1.0, 1.0))
     grads = gpu_gradients(w, prec, psi0, V, target, w["steps"], w["K"])
+    check_adjoint_fixture(grads, golden("adjoint3d_128_200.json"), prec)
     check_fd(w, prec, psi0, V, target, w["steps"], grads, params=("gdd",), npoints=2,
              tol=1e-6 if prec == "fp64" else 1e-4)
 
@@ -273,9 +322,21 @@ def test_ensemble_1000_steps(gpu_lib):
     for rec in g["instances"]:
         i = rec["index"]
         got, ref = sampled(b.get_psi(i), rec)
-        assert rel_l2(got, ref) <= FP32_PSI_TOL, (i, rel_l2(got, ref))
+        assert_psi_close(got, ref, FP32_PSI_TOL, i)
         bad = obs_close(energies[i], rec["final"], FP32_E_TOL, part_tol=FP32_PART_TOL)
         assert not bad, (i, bad)
+    # every instance: final observables and psi at 64 sampled points against the oracle
+    ga = golden("ensemble_all_1000.json")
+    assert len(ga["instances"]) == len(ens)
+    worst = 0.0
+    for rec in ga["instances"]:
+        i = rec["index"]
+        got, ref = sampled(b.get_psi(i), rec)
+        l2, mx = assert_psi_close(got, ref, FP32_PSI_TOL, i)
+        worst = max(worst, l2, mx)
+        bad = obs_close(energies[i], rec["final"], FP32_E_TOL, part_tol=FP32_PART_TOL)
+        assert not bad, (i, bad)
+    print(f"ensemble: all {len(ens)} instances within the FP32 bars (worst psi error {worst:.2e})")
     for i in range(len(ens)):
         assert abs(energies[i]["norm"] - 1.0) <= 1e-6, i
         e = np.array([h["energy"] for h in b.history(i, g["steps"])])

@@ -114,3 +114,35 @@ def test_energy_costate_matches_finite_differences():
     fd = central(E, 1e-6)
     an = 2.0 * float(np.real(np.sum(np.conj(lamE) * d)))
     assert abs(an - fd) <= 1e-6 * abs(fd), (an, fd)
+
+
+@pytest.mark.parametrize("name", ["2dxz", "3d"])
+def test_energy_loss_gradients_match_finite_differences(name):
+    """L = E(psi(T)) through NSTEPS real-time steps: couplings, grid values of V and the
+    initial costate against central differences of the forward oracle's energy."""
+    p, psi0, _, V = setup(name)
+
+    def L(pp=p, psi=psi0, W=V):
+        return O.observables(O.run(psi, pp, False, NSTEPS, V=W), pp, V=W)["energy"]
+    g = A.energy_gradients(psi0, p, NSTEPS, V=V)
+    assert abs(g["loss"] - L()) <= 1e-13 * abs(g["loss"])
+    for key, attr in (("dg", "g"), ("dgdd", "gdd")):
+        base = getattr(p, attr)
+        h = 1e-5 * base
+        fd = central(lambda e: L(pp=O.Params(**{**p.__dict__, attr: base + e})), h)
+        assert abs(g[key] - fd) <= 1e-6 * abs(fd), (name, key, g[key], fd)
+    big = np.flatnonzero(np.abs(g["dV"].ravel()) > 1e-2 * np.abs(g["dV"]).max())
+    rng = np.random.default_rng(19)
+    for k in rng.choice(big, size=3, replace=False):
+        k = int(k)
+
+        def f(e):
+            W = V.ravel().copy()
+            W[k] += e
+            return L(W=W.reshape(V.shape))
+        fd = central(f, 1e-4)
+        assert abs(g["dV"].ravel()[k] - fd) <= 1e-6 * abs(fd), (name, k)
+    d = O.zero_boundary(rng.standard_normal(psi0.shape) + 1j * rng.standard_normal(psi0.shape))
+    fd = central(lambda e: L(psi=psi0 + e * d), 1e-6)
+    an = 2.0 * float(np.real(np.sum(np.conj(g["lambda0"]) * d)))
+    assert abs(an - fd) <= 1e-6 * abs(fd), (name, an, fd)

@@ -274,6 +274,61 @@ def test_noninteracting_2d_ground_energy_is_tridiagonal_eigenvalue_sum(dt):
     assert abs(ob["norm"] - 1.0) < 1e-13
 
 
+def test_noninteracting_2dxz_ground_state():
+    """The x-z plane (program summaries (ii) and (v)): the trap acts with gamma along x
+    and lambda along z, nu being the frozen transverse frequency.  With g = g_dd = 0 the
+    relaxed energy is the sum of the two tridiagonal ground eigenvalues, x with gamma = 1
+    and z with lambda = 2.5, within the O(dt^2) splitting offset; a swapped pair
+    (gamma on z) gives a different sum on this non-square grid and fails.  The rms sizes
+    are those of the harmonic ground state, 1/sqrt(2 omega) per axis, to O(h^2)."""
+    dt = 0.002
+    gam, lam = 1.0, 2.5
+    p = O.Params(geom="2dxz", nx=44, nz=36, dx=0.3, dz=0.2, dt=dt, gamma=gam, nu=4.0, lam=lam)
+    psi = I.gaussian("2dxz", 44, 1, 36, 0.3, 0.3, 0.2, widths=(0.8, 1.1), amp_noise=0.01,
+                     seed=4)
+    psi, ob = relax(p, psi, int(12.0 / dt))
+
+    def eig(n, h, w):
+        x = O.coords(n, h)[1:-1]
+        return scipy.linalg.eigh_tridiagonal(1.0 / h**2 + 0.5 * w * w * x * x,
+                                             -0.5 / h**2 * np.ones(n - 3), select="i",
+                                             select_range=(0, 0), eigvals_only=True)[0]
+    e0 = eig(44, 0.3, gam) + eig(36, 0.2, lam)
+    swapped = eig(44, 0.3, lam) + eig(36, 0.2, gam)
+    err = ob["energy"] - e0
+    assert 0 <= err <= 3.0 * dt * dt, err
+    assert abs(swapped - e0) > 100 * 3.0 * dt * dt
+    # continuum (gamma + lambda)/2 to O(h^2)
+    assert abs(ob["energy"] - 0.5 * (gam + lam)) < 0.02
+    assert ob["rms"][1] == 0.0
+    assert abs(ob["rms"][0] - 1.0 / math.sqrt(2.0 * gam)) < 0.01
+    assert abs(ob["rms"][2] - 1.0 / math.sqrt(2.0 * lam)) < 0.01
+
+
+def test_kohn_dipole_mode_along_z_in_2dxz():
+    """The x-z plane with in-plane dipoles: a ground state displaced along z oscillates
+    at lambda, the z trap frequency, whatever g and g_dd: <z>(pi/lambda) = -z0, while
+    <x> stays at 0."""
+    p = O.Params(geom="2dxz", nx=48, nz=64, dx=0.25, dz=0.15, dt=0.002, gamma=1.0, nu=4.0,
+                 lam=2.0, g=15.0, gdd=10.0)
+    psi = I.gaussian("2dxz", 48, 1, 64, 0.25, 0.25, 0.15, widths=(0.7, 1.0))
+    psi, _ = relax(p, psi, 3000)
+    m = 4
+    z0 = m * p.dz
+    f = np.roll(psi, m, axis=0)
+    pr = O.Params(**{**p.__dict__, "dt": 0.0005})
+    V = O.harmonic_potential(p)
+    K = O.dipolar_kernel(p)
+    Z, X = O.mesh(p)
+    for _ in range(int(round(math.pi / p.lam / pr.dt))):
+        f = O.step(f, pr, False, V=V, kernel=K)
+    nrm = float(np.sum(np.abs(f) ** 2))
+    zm = float(np.sum(Z * np.abs(f) ** 2) / nrm)
+    xm = float(np.sum(X * np.abs(f) ** 2) / nrm)
+    assert abs(zm + z0) < 2e-3 * z0, (zm, z0)
+    assert abs(xm) < 1e-10
+
+
 def test_noninteracting_3d_ground_energy():
     p = O.Params(geom="3d", nx=20, ny=18, nz=16, dx=0.45, dy=0.5, dz=0.4, dt=0.002,
                  gamma=1.0, nu=1.2, lam=2.0)
