@@ -450,14 +450,18 @@ class Batch:
         except Exception:
             pass
 
+    def _shape_of(self, idx):
+        # an index out of range is passed through: the library answers GP_E_ARG
+        return self.shapes[idx] if 0 <= idx < self.count else (1,)
+
     def set_psi(self, idx, psi):
         a = np.ascontiguousarray(psi, dtype=np.complex128)
-        assert a.shape == self.shapes[idx]
+        assert not 0 <= idx < self.count or a.shape == self.shapes[idx]
         _check(load().gp_batch_set_psi(_P(self.handle), idx, _P(a.ctypes.data), 0),
                "gp_batch_set_psi")
 
     def get_psi(self, idx):
-        out = np.empty(self.shapes[idx], dtype=np.complex128)
+        out = np.empty(self._shape_of(idx), dtype=np.complex128)
         _check(load().gp_batch_get_psi(_P(self.handle), idx, _P(out.ctypes.data), 0),
                "gp_batch_get_psi")
         return out

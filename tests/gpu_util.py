@@ -10,12 +10,6 @@ FP64_PSI_TOL = 1e-10     # rel-L2 of psi, FP64 mode
 FP32_PSI_TOL = 2e-5      # rel-L2 of psi, FP32 mode (FP64 reductions)
 FP64_E_TOL = 1e-12       # relative energy / mu, FP64 mode
 FP32_E_TOL = 1e-6        # relative energy / mu, FP32 mode
-# The stated energy bar applies to E and mu.  Their interaction parts e_int and e_dd are
-# quartic in psi (sum |psi|^4, sum Phi |psi|^2): a relative amplitude error d of the FP32
-# state enters them as about 4 d where E and mu see it diluted by the kinetic and trap
-# parts, so the parts are held at four times the energy bar (a reading of the tolerance
-# statement, which names the energy only).
-FP32_PART_TOL = 4 * FP32_E_TOL
 
 
 def banner(*parts):
@@ -52,15 +46,18 @@ def rel(a, b):
     return abs(a - b) / max(abs(b), 1e-300)
 
 
-def obs_close(got, ref, tol, keys=("norm", "energy", "mu", "e_kin", "e_pot", "e_int", "e_dd"),
-              part_tol=None):
-    """Relative comparison of observables; part_tol (default tol) applies to e_int, e_dd."""
+def obs_close(got, ref, tol, keys=("norm", "energy", "mu", "e_kin", "e_pot", "e_int", "e_dd")):
+    """Observables against reference values.  The stated bar is relative on the energy and
+    the chemical potential.  Their parts (kinetic, trap, contact, dipolar) are the terms of
+    those sums, so each is held at the same bar relative to the larger of its own size and
+    the scale of the sums, max(|E|, |mu|): a part's error enters E or mu one to one."""
     bad = {}
-    scale = max(abs(ref["energy"]), abs(ref["mu"]), 1.0)
+    scale = max(abs(ref["energy"]), abs(ref["mu"]))
     for k in keys:
-        t = part_tol if (part_tol is not None and k in ("e_int", "e_dd")) else tol
-        # each part is compared relative to the total energy scale (parts can be ~0)
-        if abs(got[k] - ref[k]) > t * max(abs(ref[k]), scale * 1e-3):
+        ref_k = abs(ref[k])
+        if k in ("e_kin", "e_pot", "e_int", "e_dd"):
+            ref_k = max(ref_k, scale)
+        if abs(got[k] - ref[k]) > tol * max(ref_k, 1e-300):
             bad[k] = (got[k], ref[k])
     for a in range(3):
         if abs(got["rms"][a] - ref["rms"][a]) > tol * max(abs(ref["rms"][a]), 1e-3):

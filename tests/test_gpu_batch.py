@@ -5,7 +5,7 @@ import pytest
 
 import oracle as O
 from paper_1601_04640_amd import inputs as I
-from tests.gpu_util import (FP32_E_TOL, FP32_PART_TOL, FP32_PSI_TOL, FP64_E_TOL, FP64_PSI_TOL,
+from tests.gpu_util import (FP32_E_TOL, FP32_PSI_TOL, FP64_E_TOL, FP64_PSI_TOL,
                             assert_psi_close, banner, obs_close, oparams, rel_l2)
 
 pytestmark = pytest.mark.gpu
@@ -41,7 +41,7 @@ def test_batch_matches_oracle_per_instance(prec, gpu_lib):
         if prec == "fp64":
             bad = obs_close(energies[i], O.observables(ref, p), FP64_E_TOL)
         else:
-            bad = obs_close(energies[i], O.observables(ref, p), FP32_E_TOL, part_tol=FP32_PART_TOL)
+            bad = obs_close(energies[i], O.observables(ref, p), FP32_E_TOL)
         assert not bad, (i, bad)
     b.close()
 

@@ -10,7 +10,7 @@ import pytest
 
 import oracle as O
 from paper_1601_04640_amd import inputs as I
-from tests.gpu_util import (FP32_E_TOL, FP32_PART_TOL, FP32_PSI_TOL, FP64_E_TOL, FP64_PSI_TOL,
+from tests.gpu_util import (FP32_E_TOL, FP32_PSI_TOL, FP64_E_TOL, FP64_PSI_TOL,
                             assert_psi_close, banner, obs_close, oparams, rel, rel_l2)
 
 pytestmark = pytest.mark.gpu
@@ -104,7 +104,7 @@ def test_steps_match_oracle(name, prec, imag, gpu_lib):
     recs = s.history(nsteps)
     assert len(recs) == nsteps
     etol = (dict(tol=FP64_E_TOL) if prec == "fp64"
-            else dict(tol=FP32_E_TOL, part_tol=FP32_PART_TOL))
+            else dict(tol=FP32_E_TOL))
     for k, (g_, r_) in enumerate(zip(recs, hist)):
         bad = obs_close(g_, r_, **etol)
         assert not bad, (k, bad)
@@ -132,7 +132,7 @@ def test_random_field_steps_match_oracle(name, prec, imag, gpu_lib):
     ref, hist = O.run(psi0, p, imag, nsteps, record=True)
     assert_psi_close(got, ref, FP64_PSI_TOL if prec == "fp64" else FP32_PSI_TOL)
     etol = (dict(tol=FP64_E_TOL) if prec == "fp64"
-            else dict(tol=FP32_E_TOL, part_tol=FP32_PART_TOL))
+            else dict(tol=FP32_E_TOL))
     for k, (g_, r_) in enumerate(zip(s.history(nsteps), hist)):
         bad = obs_close(g_, r_, **etol)
         assert not bad, (k, bad)
