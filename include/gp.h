@@ -56,6 +56,7 @@ typedef int gp_status;
 #define GP_E_NONFINITE  -4  /* the wave function became NaN/Inf (or its norm underflowed to 0) */
 #define GP_E_STATE      -5  /* call out of order (e.g. stepping before gp_set_psi) */
 #define GP_E_NOMEM      -6  /* host-side allocation failed */
+#define GP_E_IO         -7  /* a state file could not be written or read, or is not one */
 
 typedef enum { GP_3D = 0, GP_2D_XY = 1, GP_2D_XZ = 2 } gp_geom;
 typedef enum { GP_FP64 = 0, GP_FP32_MIXED = 1 } gp_prec;
@@ -263,6 +264,73 @@ gp_status gp_batch_use_graphs(gp_batch* batch, int enable);
  * captured step graph then has two branches per pass).  Default 0: one stream, one
  * linear chain of launches. */
 gp_status gp_batch_use_streams(gp_batch* batch, int enable);
+
+/* ------------------------------------------------------ saved states and output
+ * The imaginary-time run hands its stationary state to the real-time run through a file
+ * (program summaries of the real-time programs: a run with no imaginary-time steps of its
+ * own reads the imaginary-time program's output), and runs report the chemical
+ * potential, energy, rms sizes (calcmuen, calcrms) and the density at chosen steps; only
+ * the wave function returns to the host, for output ("Summary of revisions").
+ *
+ * State file (the library's own layout; little-endian):
+ *   bytes   0..7    magic "GPDBECS1"
+ *           8       uint32 version (1)
+ *          12       uint32 kind: 1 = wave function, 2 = density |psi|^2
+ *          16..31   int32 geom, nx, ny, nz
+ *          32..111  double dx, dy, dz, dt, gamma, nu, lambda, g, gdd, cutoff_R
+ *         112       int32 prec of the context that wrote it
+ *         120       int64 step (the caller's label)     128  double time (the caller's label)
+ *         136       uint64 npoints (the grid's point count: nx*ny*nz, or the plane's)
+ *         144       uint64 FNV-1a 64 of the payload bytes; the rest of the 256 bytes is zero
+ *   payload from byte 256: npoints complex doubles (re, im) for kind 1, npoints doubles
+ *   for kind 2, in the psi layout (x fastest).  Values are FP64 whatever the context
+ *   precision (an FP32 context's values widened exactly). */
+#define GP_STATE_PSI     1
+#define GP_STATE_DENSITY 2
+typedef struct gp_state_info {
+  int kind;                 /* GP_STATE_PSI or GP_STATE_DENSITY */
+  gp_params params;         /* the writing context's parameters */
+  long long step;
+  double time;
+  unsigned long long npoints;
+  unsigned long long checksum;
+} gp_state_info;
+
+/* The parameters the context runs with (those of gp_init, with the couplings of the last
+ * gp_set_couplings).  Host only. */
+gp_status gp_get_params(gp_ctx* ctx, gp_params* out);
+
+/* Write the current wave function (kind 1) or its density (kind 2) to `path`, labelled
+ * with step and time.  Synchronous (the values come to the host through gp_get_psi, so
+ * GP_E_NONFINITE is reported as there).  A failed write removes the file: GP_E_IO. */
+gp_status gp_save_state(gp_ctx* ctx, const char* path, long long step, double time);
+gp_status gp_save_density(gp_ctx* ctx, const char* path, long long step, double time);
+
+/* Read a wave-function file into the context (as gp_set_psi from a host buffer: the
+ * boundary points are zeroed, the values are otherwise used as they are).  The file's grid
+ * (geometry, point counts, spacings to 1e-12 relative) must be the context's: else
+ * GP_E_ARG; the trap, couplings, dt and precision may differ (a quench, a real-time run
+ * from an imaginary-time state).  GP_E_IO for a missing, short, over-long or corrupt file
+ * (checksum).  info (may be NULL) receives the header. */
+gp_status gp_load_state(gp_ctx* ctx, const char* path, gp_state_info* info);
+
+/* Header of a state file (no GPU work).  GP_E_IO if it is not a state file. */
+gp_status gp_state_read_info(const char* path, gp_state_info* info);
+/* Header and payload: data receives npoints * (2 for kind 1, 1 for kind 2) doubles;
+ * GP_E_ARG if that exceeds max_doubles, GP_E_IO for a short, over-long or corrupt file. */
+gp_status gp_state_read(const char* path, gp_state_info* info, double* data,
+                        size_t max_doubles);
+
+/* Step loop with output cadence: nsteps imaginary-time (imag != 0) or real-time steps,
+ * in runs of `every` steps (every = 0: one run).  When fn is not NULL it is called on the
+ * host with the observables of the state after 0, every, 2 every, ... and nsteps steps
+ * (gp_energy of that state, FP64); inside the call the context may be used (gp_get_psi,
+ * gp_save_state, gp_save_density, ...).  A non-zero return stops the loop after that
+ * output.  *steps_done (may be NULL) receives the steps taken.  Errors as gp_step_* and
+ * gp_energy. */
+typedef int (*gp_output_fn)(void* user, gp_ctx* ctx, int step, const gp_observables* obs);
+gp_status gp_evolve(gp_ctx* ctx, int imag, int nsteps, int every, gp_output_fn fn, void* user,
+                    int* steps_done);
 
 /* ------------------------------------------------------------ allocation-free call
  * For callers that cannot allocate device memory, and cannot hand the library a

@@ -22,6 +22,8 @@ GP_E_DEVICE = -3
 GP_E_NONFINITE = -4
 GP_E_STATE = -5
 GP_E_NOMEM = -6
+GP_E_IO = -7
+GP_STATE_PSI, GP_STATE_DENSITY = 1, 2
 
 GP_3D, GP_2D_XY, GP_2D_XZ = 0, 1, 2
 GP_FP64, GP_FP32_MIXED = 0, 1
@@ -55,8 +57,19 @@ class gp_observables(ctypes.Structure):
                 "e_dd": self.e_dd, "rms": tuple(self.rms)}
 
 
+class gp_state_info(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int), ("params", gp_params), ("step", ctypes.c_longlong),
+        ("time", ctypes.c_double), ("npoints", ctypes.c_ulonglong),
+        ("checksum", ctypes.c_ulonglong),
+    ]
+
+
 # name -> (restype, argtypes), mirroring include/gp.h
 _P = ctypes.c_void_p
+# int (*gp_output_fn)(void* user, gp_ctx* ctx, int step, const gp_observables* obs)
+GP_OUTPUT_FN = ctypes.CFUNCTYPE(ctypes.c_int, _P, _P, ctypes.c_int,
+                                ctypes.POINTER(gp_observables))
 _SIGS = {
     "gp_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(gp_params), ctypes.POINTER(ctypes.c_size_t)]),
     "gp_init": (ctypes.c_int, [ctypes.POINTER(gp_params), _P, ctypes.c_size_t, _P,
@@ -99,6 +112,15 @@ _SIGS = {
     "gp_batch_use_streams": (ctypes.c_int, [_P, ctypes.c_int]),
     "gp_dipolar_potential_noalloc": (ctypes.c_int, [ctypes.POINTER(gp_params), _P, _P, _P]),
     "gp_timing_enable": (ctypes.c_int, [_P, ctypes.c_uint]),
+    "gp_get_params": (ctypes.c_int, [_P, ctypes.POINTER(gp_params)]),
+    "gp_save_state": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_longlong, ctypes.c_double]),
+    "gp_save_density": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_longlong, ctypes.c_double]),
+    "gp_load_state": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.POINTER(gp_state_info)]),
+    "gp_state_read_info": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(gp_state_info)]),
+    "gp_state_read": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(gp_state_info), _P,
+                                     ctypes.c_size_t]),
+    "gp_evolve": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, GP_OUTPUT_FN, _P,
+                                 ctypes.POINTER(ctypes.c_int)]),
     "gp_timing_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_int)]),
 }
@@ -266,6 +288,76 @@ def gp_timing_burst(ctx: int, pass_name: str, reps: int) -> float:
     return ms.value
 
 
+def _info_dict(info: gp_state_info) -> dict:
+    p = info.params
+    geom = {v: k for k, v in GEOM.items()}[p.geom]
+    return {"kind": info.kind, "step": info.step, "time": info.time, "npoints": info.npoints,
+            "params": {"geom": geom, "nx": p.nx, "ny": p.ny, "nz": p.nz, "dx": p.dx,
+                       "dy": p.dy, "dz": p.dz, "dt": p.dt, "gamma": p.gamma, "nu": p.nu,
+                       "lam": p.lambda_, "g": p.g, "gdd": p.gdd, "R": p.cutoff_R,
+                       "prec": "fp64" if p.prec == GP_FP64 else "fp32"}}
+
+
+def gp_get_params(ctx: int) -> gp_params:
+    p = gp_params()
+    _check(load().gp_get_params(_P(ctx), ctypes.byref(p)), "gp_get_params")
+    return p
+
+
+def gp_save_state(ctx: int, path: str, step: int = 0, time: float = 0.0):
+    _check(load().gp_save_state(_P(ctx), os.fsencode(path), step, time), "gp_save_state")
+
+
+def gp_save_density(ctx: int, path: str, step: int = 0, time: float = 0.0):
+    _check(load().gp_save_density(_P(ctx), os.fsencode(path), step, time), "gp_save_density")
+
+
+def gp_load_state(ctx: int, path: str) -> dict:
+    info = gp_state_info()
+    _check(load().gp_load_state(_P(ctx), os.fsencode(path), ctypes.byref(info)), "gp_load_state")
+    return _info_dict(info)
+
+
+def gp_state_read_info(path: str) -> dict:
+    info = gp_state_info()
+    _check(load().gp_state_read_info(os.fsencode(path), ctypes.byref(info)), "gp_state_read_info")
+    return _info_dict(info)
+
+
+def gp_state_read(path: str):
+    """(header dict, values): complex128 for a wave-function file, float64 for a density
+    file, in the grid's shape."""
+    head = gp_state_read_info(path)
+    k = 2 if head["kind"] == GP_STATE_PSI else 1
+    buf = np.empty(head["npoints"] * k, dtype=np.float64)
+    info = gp_state_info()
+    _check(load().gp_state_read(os.fsencode(path), ctypes.byref(info), _P(buf.ctypes.data),
+                                buf.size), "gp_state_read")
+    vals = buf.view(np.complex128) if k == 2 else buf
+    return head, vals.reshape(_shape(head["params"]))
+
+
+def gp_evolve(ctx: int, imag: bool, nsteps: int, every: int, fn=None) -> int:
+    """nsteps steps in runs of `every`; fn(step, observables dict) is called after 0, every,
+    ... and nsteps steps (return True to stop).  Returns the steps taken."""
+    done = ctypes.c_int(0)
+    errors = []
+
+    def tramp(_user, _ctx, step, obs):
+        try:
+            return 1 if fn(step, obs.contents.as_dict()) else 0
+        except Exception as e:  # noqa: BLE001 - re-raised below, after the C loop returns
+            errors.append(e)
+            return 1
+
+    cb = GP_OUTPUT_FN(tramp) if fn is not None else GP_OUTPUT_FN()
+    st = load().gp_evolve(_P(ctx), int(bool(imag)), nsteps, every, cb, None, ctypes.byref(done))
+    if errors:
+        raise errors[0]
+    _check(st, "gp_evolve")
+    return done.value
+
+
 def supported_sizes(limit: int = 16384) -> list:
     """Axis lengths gp_init accepts (probed through gp_workspace_bytes on a 2D grid)."""
     out = []
@@ -390,6 +482,19 @@ class Solver:
     def timing_span(self, pass_name: str = "c2r_nl_cnx") -> tuple:
         """(summed in-kernel spans in ms, launches) since timing_enable."""
         return gp_timing_span(self.ctx, pass_name)
+
+    # --- saved states and output cadence
+    def save_state(self, path: str, step: int = 0, time: float = 0.0):
+        gp_save_state(self.ctx, path, step, time)
+
+    def save_density(self, path: str, step: int = 0, time: float = 0.0):
+        gp_save_density(self.ctx, path, step, time)
+
+    def load_state(self, path: str) -> dict:
+        return gp_load_state(self.ctx, path)
+
+    def evolve(self, imag: bool, nsteps: int, every: int = 0, fn=None) -> int:
+        return gp_evolve(self.ctx, imag, nsteps, every, fn)
 
     def timing_burst(self, pass_name: str, reps: int = 64) -> float:
         """ms per launch of one pass replayed back to back (advances the state)."""

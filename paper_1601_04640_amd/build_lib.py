@@ -14,6 +14,8 @@ LIB = os.path.join(PKG, "libgpdbec.so")
 ARCH = os.environ.get("GPDBEC_ARCH", "gfx950")
 
 HIPCC = "/opt/rocm/bin/hipcc"
+GXX = "g++"
+HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wextra"]
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions are kept out of the generated code
@@ -31,11 +33,18 @@ def _jobs(build_dir=BUILD, extra=()):
                    os.path.join(CSRC, "gp_inst.hip"), "-o", obj]
             jobs.append((obj, cmd))
     for real in ("float", "double"):
+        obj = os.path.join(build_dir, f"generic_{real}.o")
+        jobs.append((obj, [HIPCC, *FLAGS, *extra, f"-DGP_REAL={real}", "-c",
+                           os.path.join(CSRC, "gp_generic_inst.hip"), "-o", obj]))
+    for real in ("float", "double"):
         obj = os.path.join(build_dir, f"batch_{real}.o")
         jobs.append((obj, [HIPCC, *FLAGS, *extra, f"-DGP_REAL={real}", "-c",
                            os.path.join(CSRC, "gp_batch_inst.hip"), "-o", obj]))
     obj = os.path.join(build_dir, "capi.o")
     jobs.append((obj, [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, "gp_capi.hip"), "-o", obj]))
+    # host-only code over the public C ABI (saved states, output cadence)
+    obj = os.path.join(build_dir, "state.o")
+    jobs.append((obj, [GXX, *HOST_FLAGS, "-c", os.path.join(CSRC, "gp_state.cpp"), "-o", obj]))
     return jobs
 
 

@@ -15,6 +15,7 @@
 #include "../../include/gp.h"
 #include "gp_aux.hpp"
 #include "gp_batch_launch.hpp"
+#include "gp_generic_launch.hpp"
 #include "gp_kernels.hpp"
 #include "gp_launch.hpp"
 
@@ -27,7 +28,8 @@ constexpr long long kStageThreshold = 16384;  // partial values above which the 
 constexpr long long kStageSlice = 512;        // runs in two stages, ~kStageSlice per slice
 constexpr int kGraphSteps = 8;  // steps per captured graph
 
-bool size_ok(int n) {
+// Axis lengths with compile-time specialised passes.
+bool fast_size(int n) {
   switch (n) {
 #define X(N) case N:
     GP_FOR_SIZES(X)
@@ -38,6 +40,25 @@ bool size_ok(int n) {
   }
 }
 
+// Every axis length a context accepts: a specialised one, or one the run-time-length
+// passes take (even, >= 4, prime factors <= 31, one line within 64 KiB of LDS).
+bool size_ok(int n, bool fp64) {
+  return fast_size(n) || (fp64 ? gen_size_ok<double>(n) : gen_size_ok<float>(n));
+}
+
+// The axes a geometry uses: (n0, n1, n2) with n2 = 1 in 2D.
+void plane_axes(const gp_params* p, int* n0, int* n1, int* n2) {
+  *n0 = p->nx;
+  *n1 = p->geom == GP_2D_XZ ? p->nz : p->ny;
+  *n2 = p->geom == GP_3D ? p->nz : 1;
+}
+
+bool is_generic(const gp_params* p) {
+  int n0, n1, n2;
+  plane_axes(p, &n0, &n1, &n2);
+  return !fast_size(n0) || !fast_size(n1) || (p->geom == GP_3D && !fast_size(n2));
+}
+
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
@@ -45,10 +66,13 @@ struct Layout {
   double h0, h1, h2;
   size_t npts, nspec, nktab;  // grid points, half-spectrum values, kernel-table values
   size_t esz;           // bytes of one real value
-  int nb_x, nb_col, nb_colobs;
-  // byte offsets inside the workspace
+  int nb_x, nb_nl, nb_col, nb_colobs;
+  // axes without a compile-time specialisation run the run-time-length passes
+  bool generic;
+  // byte offsets inside the workspace (o_gA, o_gB: the run-time-length passes' transposed
+  // state and sweep scratch, zero-sized otherwise)
   size_t o_psi, o_V, o_spec, o_ktab, o_tw[3], o_cn[3][3], o_px[2], o_pnl, o_pcol, o_padj, o_sfield,
-      o_scalars, o_ring, o_obs, o_io, o_stamps, o_stage, total;
+      o_scalars, o_ring, o_obs, o_io, o_stamps, o_stage, o_gA, o_gB, total;
 };
 
 struct Scalars {  // device-side scalars (one 256-byte block)
@@ -70,17 +94,22 @@ gp_status validate(const gp_params* p) {
   if (!isfinite(p->g) || !isfinite(p->gdd) || !isfinite(p->gamma) || !isfinite(p->nu) ||
       !isfinite(p->lambda) || !isfinite(p->cutoff_R))
     return GP_E_ARG;
-  if (!size_ok(p->nx)) return GP_E_SIZE;
+  const bool fp64 = p->prec == GP_FP64;
+  if (!size_ok(p->nx, fp64)) return GP_E_SIZE;
   if (p->geom == GP_3D) {
     if (!(p->dy > 0) || !(p->dz > 0)) return GP_E_ARG;
-    if (!size_ok(p->ny) || !size_ok(p->nz)) return GP_E_SIZE;
+    if (!size_ok(p->ny, fp64) || !size_ok(p->nz, fp64)) return GP_E_SIZE;
   } else if (p->geom == GP_2D_XY) {
     if (!(p->dy > 0) || !(p->lambda > 0)) return GP_E_ARG;
-    if (!size_ok(p->ny)) return GP_E_SIZE;
+    if (!size_ok(p->ny, fp64)) return GP_E_SIZE;
   } else {
     if (!(p->dz > 0) || !(p->nu > 0)) return GP_E_ARG;
-    if (!size_ok(p->nz)) return GP_E_SIZE;
+    if (!size_ok(p->nz, fp64)) return GP_E_SIZE;
   }
+  // the run-time-length passes address the grid with 32-bit line offsets
+  int n0, n1, n2;
+  plane_axes(p, &n0, &n1, &n2);
+  if (is_generic(p) && (double)n0 * n1 * n2 > 2147483647.0) return GP_E_SIZE;
   return GP_OK;
 }
 
@@ -104,14 +133,25 @@ Layout make_layout(const gp_params* p) {
   L.npts = (size_t)L.n0 * L.n1 * L.n2;
   const int H = L.n0 / 2 + 1;
   L.nspec = (size_t)H * L.n1 * L.n2;
-  const int tj = tj_of(fp64, L.n0);
-  L.nb_x = ((L.n1 + tj - 1) / tj) * L.n2;
-  if (p->geom == GP_3D) {
-    const int tcz = tc_of(fp64, L.n2);
-    L.nb_col = ((L.n0 + tcz - 1) / tcz) * L.n1;   // z sweep / z observe
+  L.generic = is_generic(p);
+  if (L.generic) {
+    L.nb_x = fp64 ? GLaunch<double>::x_blocks(L.n0, L.n1, L.n2)
+                  : GLaunch<float>::x_blocks(L.n0, L.n1, L.n2);
+    L.nb_nl = fp64 ? GLaunch<double>::nl_blocks(L.n0, L.n1, L.n2)
+                   : GLaunch<float>::nl_blocks(L.n0, L.n1, L.n2);
+    // one thread per column of the last sweep (z in 3D, y in 2D) and of the z observe
+    L.nb_col = GLaunch<float>::col_blocks(p->geom == GP_3D ? L.n0 * L.n1 : L.n0);
   } else {
-    const int tcy = tc_of(fp64, L.n1);
-    L.nb_col = ((L.n0 + tcy - 1) / tcy) * L.n2;   // y sweep (last pass in 2D)
+    const int tj = tj_of(fp64, L.n0);
+    L.nb_x = ((L.n1 + tj - 1) / tj) * L.n2;
+    L.nb_nl = L.nb_x;   // the x pass writes both
+    if (p->geom == GP_3D) {
+      const int tcz = tc_of(fp64, L.n2);
+      L.nb_col = ((L.n0 + tcz - 1) / tcz) * L.n1;   // z sweep / z observe
+    } else {
+      const int tcy = tc_of(fp64, L.n1);
+      L.nb_col = ((L.n0 + tcy - 1) / tcy) * L.n2;   // y sweep (last pass in 2D)
+    }
   }
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -134,7 +174,7 @@ Layout make_layout(const gp_params* p) {
   // two x-partial buffers: a real-time step's x pass writes one while the previous
   // step's folded finalisation reads the other
   for (int k = 0; k < 2; ++k) L.o_px[k] = take(sizeof(double) * 2 * L.nb_x);
-  L.o_pnl = take(sizeof(double) * 7 * L.nb_x);
+  L.o_pnl = take(sizeof(double) * 7 * L.nb_nl);
   L.o_pcol = take(sizeof(double) * 2 * L.nb_col);
   L.o_padj = take(sizeof(double) * 2 * L.nb_x);
   L.o_sfield = take(L.esz * L.npts);
@@ -144,6 +184,8 @@ Layout make_layout(const gp_params* p) {
   L.o_io = take(16 * L.npts);
   L.o_stamps = take(16 * (size_t)L.nb_x);
   L.o_stage = take(sizeof(double) * kStageVals * kStageMax);
+  L.o_gA = take(L.generic ? 2 * L.esz * L.npts : 0);
+  L.o_gB = take(L.generic ? 2 * L.esz * L.npts : 0);
   L.total = o;
   return L;
 }
@@ -177,6 +219,7 @@ struct gp_ctx {
   bool ekz_valid;
   double gc;
   int clock_khz = 0;  // device wall clock (kernel-span timing)
+  GPlan gplan[3] = {};  // radix plans of the run-time-length passes (axes 0, 1, 2)
   template <typename X>
   X* at(size_t off) const { return reinterpret_cast<X*>(ws + off); }
   Scalars* sc() const { return at<Scalars>(L.o_scalars); }
@@ -262,7 +305,7 @@ FinArgs fin_args(const gp_ctx* c, int sel) {
   a.p_x = c->at<double>(c->L.o_px[sel]);
   a.nb_x = c->L.nb_x;
   a.p_nl = c->at<double>(c->L.o_pnl);
-  a.nb_nl = c->L.nb_x;
+  a.nb_nl = c->L.nb_nl;
   a.p_col = c->at<double>(c->L.o_pcol);
   a.nb_col = c->L.nb_col;
   a.dV = c->L.h0 * c->L.h1 * (c->p.geom == GP_3D ? c->L.h2 : 1.0);
@@ -281,7 +324,7 @@ FinArgs fin_args(const gp_ctx* c, int sel) {
   a.ring_cap = kRingCap;
   a.obs = c->at<double>(c->L.o_obs);
   // many partials: a first stage of up to kStageMax blocks sums slices of ~512 values
-  const long long nvals = 9LL * c->L.nb_x + 2LL * c->L.nb_col;
+  const long long nvals = 2LL * c->L.nb_x + 7LL * c->L.nb_nl + 2LL * c->L.nb_col;
   a.stage = c->at<double>(c->L.o_stage);
   a.nstage = nvals > kStageThreshold
                  ? (int)std::min<long long>(kStageMax, (nvals + kStageSlice - 1) / kStageSlice)
@@ -309,6 +352,110 @@ struct Passes {
   static const cpx<T>* tw(gp_ctx* c, int a) { return c->at<cpx<T>>(c->L.o_tw[a]); }
   // factor table of axis a, set k (0: imaginary time, 1: real time, 2: adjoint sweep)
   static const cpx<T>* cn(gp_ctx* c, int a, int k) { return c->at<cpx<T>>(c->L.o_cn[a][k]); }
+
+  // ------------------------------------------- run-time-length passes (gp_generic.hpp)
+  // The same step as the specialised passes, in simpler launches: the x R2C, the y FFT,
+  // the z convolution and the inverse y FFT (2D: the y convolution), the x C2R into a
+  // real Phi grid, the phase written x-major, the x sweep on the transposed state, the
+  // transpose back, then the y and z sweeps; the finalisation runs after every step.
+  static gp_status g_convolution(gp_ctx* c, const cpx<T>* src, const double* scale) {
+    const Layout& L = c->L;
+    const int H = L.n0 / 2 + 1;
+    GP_PASS(c, GP_PASS_R2C_X,
+            GLaunch<T>::r2c_x(c->st, src, spec(c), c->gplan[0], tw(c, 0),
+                              c->at<double>(L.o_px[0]), L.n0, L.n1, L.n2));
+    const GKtab none{0, L.n1, L.n2};
+    if (c->p.geom == GP_3D) {
+      // y lines l = kx n2 + k2 (contiguous); z lines l = kx n1 + k1 (stride n1)
+      GP_PASS(c, GP_PASS_FFT_Y_FWD,
+              GLaunch<T>::lines(GL_FWD, c->st, spec(c), L.n1, H * L.n2, 1, L.n1, 0, 1,
+                                c->gplan[1], tw(c, 1), nullptr, none, scale));
+      GP_PASS(c, GP_PASS_CONV_Z,
+              GLaunch<T>::lines(GL_CONV, c->st, spec(c), L.n2, H * L.n1, L.n1,
+                                (long long)L.n1 * L.n2, 1, L.n1, c->gplan[2], tw(c, 2),
+                                c->at<T>(L.o_ktab), GKtab{1, L.n1, L.n2}, scale));
+      GP_PASS(c, GP_PASS_FFT_Y_INV,
+              GLaunch<T>::lines(GL_INV, c->st, spec(c), L.n1, H * L.n2, 1, L.n1, 0, 1,
+                                c->gplan[1], tw(c, 1), nullptr, none, scale));
+    } else {
+      GP_PASS(c, GP_PASS_CONV_Y,
+              GLaunch<T>::lines(GL_CONV, c->st, spec(c), L.n1, H, 1, L.n1, 0, 1, c->gplan[1],
+                                tw(c, 1), c->at<T>(L.o_ktab), GKtab{0, L.n1, 1}, scale));
+    }
+    return GP_OK;
+  }
+
+  static GStep g_scalars(gp_ctx* c) {
+    return GStep{c->p.dt, c->gc, c->p.gdd, c->L.h0, c->L.h1, c->L.h2};
+  }
+
+  // Phi of src into phi (the convolution, then the x C2R)
+  static gp_status g_phi(gp_ctx* c, const cpx<T>* src, const double* scale, T* phi) {
+    const Layout& L = c->L;
+    GP_TRY(g_convolution(c, src, scale));
+    GP_HIP(GLaunch<T>::c2r_x(c->st, spec(c), phi, c->gplan[0], tw(c, 0), L.n0, L.n1, L.n2));
+    return GP_OK;
+  }
+
+  // column sweep of axis 1 (y) or 2 (z) of the stored state; sums: 0, 1 (new state), 2
+  static gp_status g_sweep(gp_ctx* c, int axis, int k, int sums) {
+    const Layout& L = c->L;
+    cpx<T>* gB = c->at<cpx<T>>(L.o_gB);
+    double* pc = c->at<double>(L.o_pcol);
+    const cpx<T>* f = sums == 2 ? nullptr : cn(c, axis, k);
+    if (axis == 1) {  // lines (i, k2) along y: base k2 n0 n1 + i, stride n0
+      return dev(GLaunch<T>::cn_cols(sums, c->st, psi(c), gB, f, L.n1, L.n0,
+                                     (long long)L.n0 * L.n1, L.n0, L.n0 * L.n2, pc));
+    }
+    // lines (i, j) along z: base j n0 + i, stride n0 n1
+    return dev(GLaunch<T>::cn_cols(sums, c->st, psi(c), gB, f, L.n2, L.n0 * L.n1, 0,
+                                   (long long)L.n0 * L.n1, L.n0 * L.n1, pc));
+  }
+
+  static gp_status g_step(gp_ctx* c, bool imag) {
+    const Layout& L = c->L;
+    const int mode = imag ? MODE_IMAG : MODE_REAL;
+    const int k = imag ? 0 : 1;
+    T* phi = c->at<T>(L.o_sfield);
+    cpx<T>* gA = c->at<cpx<T>>(L.o_gA);
+    cpx<T>* gB = c->at<cpx<T>>(L.o_gB);
+    GP_TRY(settle(c));
+    GP_TRY(g_convolution(c, psi(c), &c->sc()->scale));
+    GP_TRY(pass_begin(c, GP_PASS_C2R_NL_CNX));
+    GP_HIP(GLaunch<T>::c2r_x(c->st, spec(c), phi, c->gplan[0], tw(c, 0), L.n0, L.n1, L.n2));
+    GP_HIP(GLaunch<T>::nl_transpose(mode, c->st, psi(c), c->at<T>(L.o_V), phi, &c->sc()->scale,
+                                    gA, g_scalars(c), L.n0, L.n1, L.n2,
+                                    c->at<double>(L.o_pnl)));
+    // x lines of the transposed state (k2, j): base k2 n0 n1 + j, stride n1
+    GP_HIP(GLaunch<T>::cn_cols(0, c->st, gA, gB, cn(c, 0, k), L.n0, L.n1,
+                               (long long)L.n0 * L.n1, L.n1, L.n1 * L.n2, nullptr));
+    GP_HIP(GLaunch<T>::transpose(c->st, gA, psi(c), L.n1, L.n0, L.n2));
+    GP_TRY(pass_end(c, GP_PASS_C2R_NL_CNX));
+    if (c->p.geom == GP_3D) {
+      GP_TRY(pass_begin(c, GP_PASS_CN_Y));
+      GP_TRY(g_sweep(c, 1, k, 0));
+      GP_TRY(pass_end(c, GP_PASS_CN_Y));
+      GP_TRY(pass_begin(c, GP_PASS_CN_Z));
+      GP_TRY(g_sweep(c, 2, k, 1));
+      GP_TRY(pass_end(c, GP_PASS_CN_Z));
+    } else {
+      GP_TRY(pass_begin(c, GP_PASS_CN_Y));
+      GP_TRY(g_sweep(c, 1, k, 1));
+      GP_TRY(pass_end(c, GP_PASS_CN_Y));
+    }
+    return finalize(c, imag ? (int)FIN_IMAG : (int)FIN_REAL);
+  }
+
+  static gp_status g_observe(gp_ctx* c) {
+    const Layout& L = c->L;
+    T* phi = c->at<T>(L.o_sfield);
+    GP_TRY(g_phi(c, psi(c), &c->sc()->scale, phi));
+    GP_HIP(GLaunch<T>::nl_transpose(MODE_OBSERVE, c->st, psi(c), c->at<T>(L.o_V), phi,
+                                    &c->sc()->scale, nullptr, g_scalars(c), L.n0, L.n1, L.n2,
+                                    c->at<double>(L.o_pnl)));
+    if (c->p.geom == GP_3D) return z_observe(c, FIN_OBSERVE);
+    return finalize(c, FIN_OBSERVE);
+  }
 
   // y/z transforms of the x-half spectrum, U(k)/N product, inverse y/z transforms
   // y/z transforms of the x-half spectrum of the stored density, U(k) scale^2/N product,
@@ -360,12 +507,20 @@ struct Passes {
     }
     return spectrum_passes(c, scale, fold && fold->nstage > 0 ? fold : nullptr, fin_mode);
   }
-  static gp_status convolution(gp_ctx* c) { return convolution(c, psi(c), &c->sc()->scale); }
+  static gp_status convolution(gp_ctx* c) {
+    if (c->L.generic) return g_convolution(c, psi(c), &c->sc()->scale);
+    return convolution(c, psi(c), &c->sc()->scale);
+  }
 
   // Backpropagation through one real-time step (see gp_step_real_adjoint).
   static gp_status adjoint(gp_ctx* c, const cpx<T>* psin, cpx<T>* lam, double* gradV,
                            double* grad_g, double* grad_gdd) {
     const Layout& L = c->L;
+    if (L.generic) {
+      snprintf(g_last_error, sizeof(g_last_error),
+               "the adjoint step needs axis lengths with specialised passes");
+      return GP_E_SIZE;
+    }
     const int tcy = tc_of(c->fp64, L.n1);
     const int nb_y = ((L.n0 + tcy - 1) / tcy) * L.n2;
     if (c->p.geom == GP_3D) {
@@ -406,6 +561,10 @@ struct Passes {
   // with fin_mode (FIN_EKZ: pending z-kinetic part; FIN_OBSERVE: full record)
   static gp_status z_observe(gp_ctx* c, int fin_mode) {
     const Layout& L = c->L;
+    if (L.generic) {
+      GP_TRY(g_sweep(c, 2, 0, 2));
+      return finalize(c, fin_mode);
+    }
     GP_HIP(Launch<T>::cn_col(L.n2, MODE_OBSERVE, true, L.nb_col, c->st, psi(c), nullptr,
                              c->at<double>(L.o_pcol), L.n0, (size_t)L.n0 * L.n1,
                              (size_t)L.n0));
@@ -413,6 +572,7 @@ struct Passes {
   }
 
   static gp_status step(gp_ctx* c, bool imag) {
+    if (c->L.generic) return g_step(c, imag);
     const Layout& L = c->L;
     const int mode = imag ? MODE_IMAG : MODE_REAL;
     const int fin = imag ? (int)FIN_IMAG : (int)FIN_REAL;
@@ -488,6 +648,7 @@ struct Passes {
   // One launch of a pass exactly as inside a real-time step (burst timing).
   static gp_status launch_pass(gp_ctx* c, int pass) {
     const Layout& L = c->L;
+    if (L.generic) return GP_E_ARG;
     const int tcy = tc_of(c->fp64, L.n1);
     switch (pass) {
       case GP_PASS_R2C_X:
@@ -517,6 +678,7 @@ struct Passes {
   }
 
   static gp_status observe(gp_ctx* c) {
+    if (c->L.generic) return g_observe(c);
     const Layout& L = c->L;
     GP_TRY(convolution(c));
     const StepScalars sx = step_scalars(c);
@@ -528,6 +690,7 @@ struct Passes {
   }
 
   static gp_status phi(gp_ctx* c, T* out) {
+    if (c->L.generic) return g_phi(c, psi(c), &c->sc()->scale, out);
     const Layout& L = c->L;
     GP_TRY(convolution(c));
     const StepScalars sx = step_scalars(c);
@@ -539,6 +702,12 @@ struct Passes {
 
   static gp_status init_tables(gp_ctx* c) {
     const Layout& L = c->L;
+    if (L.generic) {
+      const int ns3[3] = {L.n0, L.n1, L.n2};
+      for (int a = 0; a < (c->p.geom == GP_3D ? 3 : 2); ++a)
+        if (!gen_plan(ns3[a], &c->gplan[a])) return GP_E_SIZE;
+      GP_HIP(GLaunch<T>::prepare());
+    }
     const int ns[3] = {L.n0, L.n1, L.n2};
     const double hs[3] = {L.h0, L.h1, L.h2};
     const int naxes = (c->p.geom == GP_3D) ? 3 : 2;
@@ -548,7 +717,8 @@ struct Passes {
       const double Ar = c->p.dt / (4.0 * hs[a] * hs[a]);
       // lanes per line of the solve that sweeps this axis: x lines in the x pass, columns
       // in the strided sweeps
-      const int P = kThreads / (a == 0 ? Launch<T>::tj(ns[a]) : Launch<T>::tc(ns[a]));
+      const int P = L.generic ? 1
+                              : kThreads / (a == 0 ? Launch<T>::tj(ns[a]) : Launch<T>::tc(ns[a]));
       hipLaunchKernelGGL(k_cn_tables<T>, dim3(1), dim3(64), 0, c->st,
                          c->at<cpx<T>>(L.o_cn[a][0]), c->at<cpx<T>>(L.o_cn[a][1]),
                          c->at<cpx<T>>(L.o_cn[a][2]), ns[a], Ar, P);
@@ -809,6 +979,11 @@ gp_status dipolar_noalloc_t(gp_ctx* c, const cpx<T>* psi, T* phi) {
 }
 
 gp_status dipolar_noalloc(const gp_params* p, const void* psi, void* phi, hipStream_t st) {
+  if (is_generic(p)) {
+    snprintf(g_last_error, sizeof(g_last_error),
+             "the allocation-free call needs axis lengths with specialised passes");
+    return GP_E_SIZE;
+  }
   const Layout L = scratch_layout(p);
   if (L.total > kScratchBytes) {
     snprintf(g_last_error, sizeof(g_last_error),
@@ -1170,11 +1345,12 @@ const char* gp_status_string(gp_status s) {
   switch (s) {
     case GP_OK: return "ok";
     case GP_E_ARG: return "invalid argument";
-    case GP_E_SIZE: return "unsupported grid size (even 8..512, factors 2, 3, 5 with 3 and 5 at most once)";
+    case GP_E_SIZE: return "unsupported grid size (an axis odd, < 4, with a prime factor above 31, or a line longer than 8192 FP32 / 4096 FP64 points)";
     case GP_E_DEVICE: return "HIP runtime error";
     case GP_E_NONFINITE: return "wave function became non-finite";
     case GP_E_STATE: return "call out of order (set psi first)";
     case GP_E_NOMEM: return "host allocation failed";
+    case GP_E_IO: return "state file could not be written or read, or is not a state file";
     default: return "unknown status";
   }
 }
@@ -1526,6 +1702,12 @@ gp_status gp_batch_set_psi(gp_batch* b, int idx, const void* psi, int on_device)
 gp_status gp_batch_get_psi(gp_batch* b, int idx, void* psi, int on_device) {
   if (!b || idx < 0 || idx >= b->count) return GP_E_ARG;
   return gp_get_psi(b->inst[idx], psi, on_device);
+}
+
+gp_status gp_get_params(gp_ctx* c, gp_params* out) {
+  if (!c || !out) return GP_E_ARG;
+  *out = c->p;
+  return GP_OK;
 }
 
 gp_status gp_sync(gp_ctx* c) {

@@ -37,7 +37,7 @@ def test_struct_layouts_match_header():
 
 def test_status_strings():
     lib = B.load()
-    for s in (0, -1, -2, -3, -4, -5, -6):
+    for s in (0, -1, -2, -3, -4, -5, -6, -7):
         assert len(lib.gp_status_string(s)) > 0
 
 
@@ -47,20 +47,56 @@ def ws(**kw):
     return B.gp_workspace_bytes(B.make_params(**base))
 
 
-@pytest.mark.parametrize("n", [7, 9, 14, 6, 4, 514, 1024, 22, 26, 36, 90, 0, -8])
+# odd, below 4, a prime factor above 31 (37, 41, 43, 47, 53), or a line past 64 KiB of
+# LDS (FP64: 4096 points)
+@pytest.mark.parametrize("n", [7, 9, 15, 2, 0, -8, 74, 82, 86, 94, 106, 2 * 37 * 3, 4098, 8192])
 def test_unsupported_sizes_rejected(n):
     with pytest.raises(B.GPError) as e:
-        ws(nx=n)
+        ws(nx=n, prec="fp64")
     assert e.value.status == B.GP_E_SIZE
     with pytest.raises(B.GPError) as e:
-        ws(nz=n)
+        ws(nz=n, prec="fp64")
     assert e.value.status == B.GP_E_SIZE
 
 
+def test_line_length_limit_depends_on_precision():
+    assert ws(geom="2dxy", nx=8192, ny=8, prec="fp32") > 0
+    with pytest.raises(B.GPError) as e:
+        ws(geom="2dxy", nx=8192, ny=8, prec="fp64")
+    assert e.value.status == B.GP_E_SIZE
+    with pytest.raises(B.GPError) as e:
+        ws(geom="2dxy", nx=8194, ny=8, prec="fp32")
+    assert e.value.status == B.GP_E_SIZE
+
+
+# the specialised lengths, and lengths the run-time-length passes take (the paper's
+# grids 50, 540, 600, 1000 among them; radices 7, 11, 13, 31)
 @pytest.mark.parametrize("n", [8, 10, 12, 16, 20, 24, 30, 32, 40, 48, 60, 64, 80, 96, 120,
-                               128, 160, 192, 240, 256, 320, 384, 480, 512])
+                               128, 160, 192, 240, 256, 320, 384, 480, 512,
+                               4, 6, 14, 22, 26, 36, 50, 54, 62, 90, 100, 540, 600, 1000,
+                               1024, 2048, 4096])
 def test_supported_sizes_accepted(n):
-    assert ws(nx=n, ny=8, nz=8) > 0
+    assert ws(nx=n, ny=8, nz=8, prec="fp64") > 0
+
+
+def test_supported_size_set_follows_the_factor_rule():
+    """Every even length 4..600 is accepted exactly when all its prime factors are at
+    most 31 (FP32 and FP64 agree below the FP64 line limit)."""
+    def ok(n):
+        m = n
+        for p in (2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31):
+            while m % p == 0:
+                m //= p
+        return m == 1
+    for n in range(4, 601, 2):
+        for prec in ("fp32", "fp64"):
+            try:
+                ws(geom="2dxy", nx=n, ny=8, prec=prec)
+                got = True
+            except B.GPError as e:
+                assert e.status == B.GP_E_SIZE
+                got = False
+            assert got == ok(n), (n, prec)
 
 
 @pytest.mark.parametrize("kw", [dict(dt=0.0), dict(dt=-1e-3), dict(dx=0.0), dict(dy=-0.1),

@@ -1,0 +1,169 @@
+"""Axis lengths without compile-time specialised passes (the run-time-length kernels):
+every even length >= 4 whose prime factors are at most 31, up to 8192 (FP32) / 4096
+(FP64) points per line.  The paper's programs take any grid and enlarge it silently for
+the FFT ("Unusual features"); here each length runs as given.  Parity with the FP64
+oracle through the C ABI at the same bars as the specialised sizes: psi rel-L2 and
+element-wise <= 1e-10 / 2e-5, energy and mu <= 1e-12 / 1e-6."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1601_04640_amd import binding as B
+from paper_1601_04640_amd import inputs as I
+from tests.gpu_util import (FP32_E_TOL, FP32_PSI_TOL, FP64_E_TOL, FP64_PSI_TOL,
+                            assert_psi_close, banner, obs_close, oparams, rel_l2)
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    # the paper's small grid (50 = 2 5^2) with 3^3 and 2^2 3^2 axes
+    "3d_50x54x36": dict(geom="3d", nx=50, ny=54, nz=36, dx=0.3, dy=0.28, dz=0.4, dt=0.002,
+                        gamma=1.0, nu=1.2, lam=2.0, g=25.0, gdd=8.0, R=4.0),
+    # radices 7, 11, 13 (the larger-prime kernels)
+    "3d_14x22x26": dict(geom="3d", nx=14, ny=22, nz=26, dx=0.7, dy=0.5, dz=0.4, dt=0.002,
+                        gamma=1.0, nu=1.0, lam=1.5, g=10.0, gdd=4.0, R=3.0),
+    # specialised x (48) with run-time-length y and z
+    "3d_48x34x38": dict(geom="3d", nx=48, ny=34, nz=38, dx=0.3, dy=0.4, dz=0.35, dt=0.001,
+                        gamma=1.0, nu=1.1, lam=1.8, g=30.0, gdd=12.0, R=5.0),
+    "2dxy_100x90": dict(geom="2dxy", nx=100, ny=90, nz=1, dx=0.15, dy=0.18, dz=1.0, dt=0.002,
+                        gamma=1.0, nu=1.5, lam=4.0, g=30.0, gdd=10.0, R=0.0),
+    # 62 = 2 31, 98 = 2 7^2
+    "2dxz_62x98": dict(geom="2dxz", nx=62, ny=1, nz=98, dx=0.25, dy=1.0, dz=0.12, dt=0.001,
+                       gamma=1.0, nu=4.0, lam=2.5, g=20.0, gdd=15.0, R=0.0),
+    # the paper's 2D sizes 540 and 600 (2^2 3^3 5 and 2^3 3 5^2)
+    "2dxy_540x600": dict(geom="2dxy", nx=540, ny=600, nz=1, dx=0.04, dy=0.04, dz=1.0,
+                         dt=0.0005, gamma=1.0, nu=1.2, lam=4.0, g=40.0, gdd=20.0, R=0.0),
+    # degenerate lengths: 4 and 6 points (two and four interior points)
+    "3d_4x6x10": dict(geom="3d", nx=4, ny=6, nz=10, dx=1.0, dy=0.8, dz=0.6, dt=0.002,
+                      gamma=1.0, nu=1.0, lam=1.0, g=5.0, gdd=2.0, R=2.0),
+}
+
+
+def start_state(w, seed):
+    widths = {"3d": (0.8, 1.0, 1.1), "2dxy": (0.9, 1.1), "2dxz": (0.8, 1.0)}[w["geom"]]
+    return I.gaussian(w["geom"], w["nx"], w["ny"], w["nz"], w["dx"], w["dy"], w["dz"],
+                      widths=widths, amp_noise=0.05, phase_noise=0.02, seed=seed)
+
+
+def bars(prec):
+    return (FP64_PSI_TOL, FP64_E_TOL) if prec == "fp64" else (FP32_PSI_TOL, FP32_E_TOL)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_dipolar_potential_and_energy(name, prec, gpu_lib):
+    from paper_1601_04640_amd.binding import Solver
+    w = CASES[name]
+    banner("run-time-length sizes: Phi and energy", name, prec)
+    p = oparams(w)
+    psi = start_state(w, 501)
+    s = Solver(w, prec=prec)
+    s.set_psi(psi)
+    got = s.dipolar_potential()
+    ref = O.dipolar_potential(np.abs(psi) ** 2, p)
+    assert rel_l2(got, ref) <= (1e-12 if prec == "fp64" else 2e-6), rel_l2(got, ref)
+    bad = obs_close(s.energy(), O.observables(psi, p), bars(prec)[1])
+    assert not bad, bad
+    s.close()
+
+
+@pytest.mark.parametrize("imag", [True, False])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_steps_match_oracle(name, prec, imag, gpu_lib):
+    from paper_1601_04640_amd.binding import Solver
+    w = CASES[name]
+    nsteps = 4 if name == "2dxy_540x600" else 12
+    banner("run-time-length sizes: steps", name, prec, "imag" if imag else "real", nsteps)
+    p = oparams(w)
+    psi0 = start_state(w, 502)
+    s = Solver(w, prec=prec)
+    s.set_psi(psi0)
+    s.step_imag(nsteps) if imag else s.step_real(nsteps)
+    ref, hist = O.run(psi0, p, imag, nsteps, record=True)
+    ptol, etol = bars(prec)
+    assert_psi_close(s.get_psi(), ref, ptol)
+    recs = s.history(nsteps)
+    assert len(recs) == nsteps
+    for k, (g_, r_) in enumerate(zip(recs, hist)):
+        bad = obs_close(g_, r_, etol)
+        assert not bad, (k, bad)
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_random_field_start(prec, gpu_lib):
+    """A white-noise start puts weight on every tile, the ragged ones included."""
+    from paper_1601_04640_amd.binding import Solver
+    w = CASES["3d_50x54x36"]
+    banner("run-time-length sizes: random field", prec)
+    p = oparams(w)
+    psi0 = I.random_complex(p.shape(), 503, p.dV())
+    for imag in (True, False):
+        s = Solver(w, prec=prec)
+        s.set_psi(psi0)
+        s.step_imag(10) if imag else s.step_real(10)
+        ref = O.run(psi0, p, imag, 10)
+        assert_psi_close(s.get_psi(), ref, bars(prec)[0], imag)
+        s.close()
+
+
+@pytest.mark.parametrize("prec,n", [("fp32", 8192), ("fp64", 4096), ("fp64", 2 * 3 * 7 * 29)])
+def test_longest_lines(prec, n, gpu_lib):
+    """The longest x and y lines one block holds (and a 29-point radix) in 2D."""
+    from paper_1601_04640_amd.binding import Solver
+    for nx, ny in ((n, 12), (12, n)):
+        h = 25.6 / n
+        w = dict(geom="2dxy", nx=nx, ny=ny, nz=1, dx=h if nx == n else 0.5,
+                 dy=h if ny == n else 0.5, dz=1.0, dt=0.0005, gamma=1.0, nu=1.0, lam=4.0,
+                 g=10.0, gdd=5.0, R=0.0)
+        banner("run-time-length sizes: longest line", prec, nx, ny)
+        p = oparams(w)
+        psi0 = I.random_complex(p.shape(), 504, p.dV())
+        s = Solver(w, prec=prec)
+        s.set_psi(psi0)
+        s.step_real(3)
+        assert_psi_close(s.get_psi(), O.run(psi0, p, False, 3), bars(prec)[0], (nx, ny))
+        s.close()
+
+
+def test_graph_replay_equals_direct_launches(gpu_lib):
+    from paper_1601_04640_amd.binding import Solver
+    w = CASES["3d_50x54x36"]
+    banner("run-time-length sizes: graph replay")
+    psi0 = start_state(w, 505)
+    out = []
+    for graphs in (True, False):
+        s = Solver(w, prec="fp32")
+        s.use_graphs(graphs)
+        s.set_psi(psi0)
+        s.step_imag(17)
+        s.step_real(16)
+        out.append((s.get_psi(), s.history(33)))
+        s.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert out[0][1] == out[1][1]
+
+
+def test_calls_needing_specialised_lengths_refuse(gpu_lib):
+    import torch
+    from paper_1601_04640_amd.binding import Solver
+    w = CASES["3d_14x22x26"]
+    banner("run-time-length sizes: refusals")
+    s = Solver(w, prec="fp64")
+    s.set_psi(start_state(w, 506))
+    z = torch.zeros(s.shape, dtype=torch.complex128, device="cuda:0")
+    gv = torch.zeros(s.shape, dtype=torch.float64, device="cuda:0")
+    g = torch.zeros(2, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(B.GPError) as e:
+        B.gp_step_real_adjoint(s.ctx, z.data_ptr(), z.data_ptr(), gv.data_ptr(), g.data_ptr(),
+                               g.data_ptr() + 8)
+    assert e.value.status == B.GP_E_SIZE
+    with pytest.raises(B.GPError) as e:
+        B.gp_dipolar_potential_noalloc(B.make_params(**{**w, "prec": "fp64"}), z.data_ptr(),
+                                       gv.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    assert e.value.status == B.GP_E_SIZE
+    with pytest.raises(B.GPError) as e:
+        B.Batch([dict(w, geom="2dxy", nz=1)], prec="fp64")
+    assert e.value.status == B.GP_E_SIZE
+    s.close()
