@@ -27,6 +27,7 @@ constexpr int kRingCap = 4096;
 constexpr long long kStageThreshold = 16384;  // partial values above which the finalize
 constexpr long long kStageSlice = 512;        // runs in two stages, ~kStageSlice per slice
 constexpr int kGraphSteps = 8;  // steps per captured graph
+constexpr size_t kIoChunk = (size_t)1 << 22;  // points per host-transfer chunk (64 MiB FP64)
 
 // Axis lengths with compile-time specialised passes.
 bool fast_size(int n) {
@@ -181,7 +182,7 @@ Layout make_layout(const gp_params* p) {
   L.o_scalars = take(sizeof(Scalars));
   L.o_ring = take(sizeof(double) * kRecord * kRingCap);
   L.o_obs = take(sizeof(double) * kRecord);
-  L.o_io = take(16 * L.npts);
+  L.o_io = take(16 * std::min(L.npts, kIoChunk));
   L.o_stamps = take(16 * (size_t)L.nb_x);
   L.o_stage = take(sizeof(double) * kStageVals * kStageMax);
   L.o_gA = take(L.generic ? 2 * L.esz * L.npts : 0);
@@ -753,7 +754,8 @@ struct Passes {
     return dev(hipGetLastError());
   }
 
-  // host FP64 or device T input, chunked through the io staging area
+  // Host transfers go through the io staging area in chunks of at most kIoChunk points
+  // (FP64 values), so the workspace holds 16 B x min(points, kIoChunk) for them.
   static gp_status set_psi(gp_ctx* c, const void* src, int on_device) {
     const Layout& L = c->L;
     if (on_device) {
@@ -763,10 +765,14 @@ struct Passes {
       GP_HIP(hipGetLastError());
     } else {
       cpx<double>* io = c->at<cpx<double>>(L.o_io);
-      GP_HIP(hipMemcpyAsync(io, src, 16 * L.npts, hipMemcpyHostToDevice, c->st));
-      hipLaunchKernelGGL((k_psi_in<T, double>), dim3(blocks_for(L.npts)), dim3(kThreads), 0,
-                         c->st, psi(c), io, (size_t)0, L.npts, L.n0, L.n1, L.n2);
-      GP_HIP(hipGetLastError());
+      const cpx<double>* h = reinterpret_cast<const cpx<double>*>(src);
+      for (size_t off = 0; off < L.npts; off += kIoChunk) {
+        const size_t cnt = std::min(kIoChunk, L.npts - off);
+        GP_HIP(hipMemcpyAsync(io, h + off, 16 * cnt, hipMemcpyHostToDevice, c->st));
+        hipLaunchKernelGGL((k_psi_in<T, double>), dim3(blocks_for(cnt)), dim3(kThreads), 0,
+                           c->st, psi(c), io, off, cnt, L.n0, L.n1, L.n2);
+        GP_HIP(hipGetLastError());
+      }
       GP_HIP(hipStreamSynchronize(c->st));
     }
     hipLaunchKernelGGL(k_set_scale_one, dim3(1), dim3(64), 0, c->st, &c->sc()->scale);
@@ -782,10 +788,14 @@ struct Passes {
       return dev(hipGetLastError());
     }
     cpx<double>* io = c->at<cpx<double>>(L.o_io);
-    hipLaunchKernelGGL((k_psi_out<T, double>), dim3(blocks_for(L.npts)), dim3(kThreads), 0,
-                       c->st, io, psi(c), &c->sc()->scale, (size_t)0, L.npts);
-    GP_HIP(hipGetLastError());
-    GP_HIP(hipMemcpyAsync(dst, io, 16 * L.npts, hipMemcpyDeviceToHost, c->st));
+    cpx<double>* h = reinterpret_cast<cpx<double>*>(dst);
+    for (size_t off = 0; off < L.npts; off += kIoChunk) {
+      const size_t cnt = std::min(kIoChunk, L.npts - off);
+      hipLaunchKernelGGL((k_psi_out<T, double>), dim3(blocks_for(cnt)), dim3(kThreads), 0,
+                         c->st, io, psi(c), &c->sc()->scale, off, cnt);
+      GP_HIP(hipGetLastError());
+      GP_HIP(hipMemcpyAsync(h + off, io, 16 * cnt, hipMemcpyDeviceToHost, c->st));
+    }
     GP_HIP(hipStreamSynchronize(c->st));
     return GP_OK;
   }
@@ -797,10 +807,14 @@ struct Passes {
       return GP_OK;
     }
     double* io = c->at<double>(L.o_io);
-    GP_HIP(hipMemcpyAsync(io, src, 8 * L.npts, hipMemcpyHostToDevice, c->st));
-    hipLaunchKernelGGL((k_real_convert<T, double>), dim3(blocks_for(L.npts)), dim3(kThreads), 0,
-                       c->st, c->at<T>(L.o_V), io, L.npts);
-    GP_HIP(hipGetLastError());
+    const double* h = reinterpret_cast<const double*>(src);
+    for (size_t off = 0; off < L.npts; off += kIoChunk) {
+      const size_t cnt = std::min(kIoChunk, L.npts - off);
+      GP_HIP(hipMemcpyAsync(io, h + off, 8 * cnt, hipMemcpyHostToDevice, c->st));
+      hipLaunchKernelGGL((k_real_convert<T, double>), dim3(blocks_for(cnt)), dim3(kThreads), 0,
+                         c->st, c->at<T>(L.o_V) + off, io, cnt);
+      GP_HIP(hipGetLastError());
+    }
     GP_HIP(hipStreamSynchronize(c->st));
     return GP_OK;
   }
@@ -808,13 +822,17 @@ struct Passes {
   static gp_status dipolar(gp_ctx* c, void* dst, int on_device) {
     const Layout& L = c->L;
     if (on_device) return phi(c, reinterpret_cast<T*>(dst));
-    T* tmp = c->at<T>(L.o_io);
+    T* tmp = c->at<T>(L.o_sfield);  // free outside the adjoint step
     GP_TRY(phi(c, tmp));
-    double* outd = c->at<double>(L.o_io + 8 * L.npts);
-    hipLaunchKernelGGL((k_real_convert<double, T>), dim3(blocks_for(L.npts)), dim3(kThreads), 0,
-                       c->st, outd, tmp, L.npts);
-    GP_HIP(hipGetLastError());
-    GP_HIP(hipMemcpyAsync(dst, outd, 8 * L.npts, hipMemcpyDeviceToHost, c->st));
+    double* io = c->at<double>(L.o_io);
+    double* h = reinterpret_cast<double*>(dst);
+    for (size_t off = 0; off < L.npts; off += kIoChunk) {
+      const size_t cnt = std::min(kIoChunk, L.npts - off);
+      hipLaunchKernelGGL((k_real_convert<double, T>), dim3(blocks_for(cnt)), dim3(kThreads), 0,
+                         c->st, io, tmp + off, cnt);
+      GP_HIP(hipGetLastError());
+      GP_HIP(hipMemcpyAsync(h + off, io, 8 * cnt, hipMemcpyDeviceToHost, c->st));
+    }
     GP_HIP(hipStreamSynchronize(c->st));
     return GP_OK;
   }

@@ -30,10 +30,14 @@ def sampled(psi, g):
     return psi.ravel()[idx], np.asarray(g["psi_re"]) + 1j * np.asarray(g["psi_im"])
 
 
-def bars(prec):
+def bars(prec, real_time=False):
+    """psi bar and observable bars.  Long FP32 real-time runs compare the observables per
+    particle (divided by the state's norm), since FP32 rounding moves the norm that the
+    exact evolution conserves (by about 1e-6 over 2000 steps); the norm drift is then
+    checked on its own."""
     if prec == "fp64":
         return FP64_PSI_TOL, dict(tol=FP64_E_TOL)
-    return FP32_PSI_TOL, dict(tol=FP32_E_TOL)
+    return FP32_PSI_TOL, dict(tol=FP32_E_TOL, per_particle=real_time)
 
 
 # ------------------------------------------------------------- imag3d 64^3, 500 steps
@@ -128,7 +132,7 @@ def test_real3d_128x96x80_quench_vs_oracle(prec, gpu_lib):
     s = Solver(w, prec=prec)
     s.set_psi(psi_g)
     s.step_real(g["steps"])
-    ptol, etol = bars(prec)
+    ptol, etol = bars(prec, real_time=True)
     recs = s.history(g["steps"])
     assert len(recs) == g["steps"]
     check_records(recs, g["records"], g["every"], etol, "quench")
@@ -163,7 +167,7 @@ def test_real3d_256_500_steps_vs_oracle(prec, gpu_lib):
     s = Solver(w, prec=prec)
     s.set_psi(I.psi0_real3d_256())
     s.step_real(1)
-    ptol, etol = bars(prec)
+    ptol, etol = bars(prec, real_time=True)
     assert_psi_close(s.get_psi(), oracle_256_one_step(), ptol, "one step")
     s.step_real(g["steps"] - 1)
     recs = s.history(g["steps"])
