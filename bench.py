@@ -326,7 +326,7 @@ def imag3d_64(steps):
             "steps": steps}
 
 
-def time_batch(steps, tune_steps=16):
+def time_batch(steps, tune_steps=16, two_streams=False):
     """The 192-instance quasi-2D ensemble (sizes from {96..512}^2, mixed XY/XZ), FP32 with
     FP64 reductions, imaginary time: the default launch plan, the autotuned plan, and the
     autotuned plan with the two size classes on two streams; each timed region runs
@@ -361,9 +361,11 @@ def time_batch(steps, tune_steps=16):
     reset()
     plan = autotune.tune(b, steps=tune_steps)
     wall1, gpu1 = timed()
-    b.use_streams(True)
-    wall2, _ = timed()
-    b.use_streams(False)
+    wall2 = None
+    if two_streams:
+        b.use_streams(True)
+        wall2, _ = timed()
+        b.use_streams(False)
     npts = b.points()
     byts = sum(step_bytes_2d(w["nx"], w["ny"] if w["geom"] == "2dxy" else w["nz"], 4)
                for w in ens)
@@ -373,7 +375,7 @@ def time_batch(steps, tune_steps=16):
            "value": npts * steps / wall1, "unit": "grid-point-steps/s",
            "ms_per_step": wall1 * 1e3 / steps, "gpu_event_ms_per_step": gpu1 / steps,
            "ms_per_step_default_plan": wall0 * 1e3 / steps,
-           "ms_per_step_two_streams": wall2 * 1e3 / steps,
+           "ms_per_step_two_streams": None if wall2 is None else wall2 * 1e3 / steps,
            "step_algorithmic_bytes": byts,
            "step_achieved_GBs": round(byts / (wall1 / steps) / 1e9, 1),
            "tuned_plan": plan,
@@ -423,52 +425,60 @@ def adjoint_128(nsteps=200, K=20):
 
 
 # ---------------------------------------------------------------------- sweep
+SWEEP3 = (48, 50, 64, 80, 96, 100, 120, 128, 150, 160, 192, 200, 240, 250, 256, 300, 320, 360,
+          384, 400, 450, 480, 500, 512, 540, 600)
+SWEEP2 = (256, 384, 512, 1000, 1024, 1500, 2000, 2048, 3000, 4000, 4096, 5000, 6000, 8000, 8192)
+
+
 def sweep(args):
-    """Throughput against grid size (one JSON line per grid): real-time steps of 3D
-    cubes and 2D squares (trap (1,1,2), g 20, g_dd 6, R half the box), graph replay."""
+    """Throughput against grid size (one JSON line per grid and precision), the axis of the
+    paper's Fig. 2 (3D cubes 50^3 -> 600^3, 2D squares from 1000^2): real-time steps of
+    cubes and squares (trap (1,1,2), g 20, g_dd 6, R half the box in 3D; box 12.8),
+    graph-replayed.  Lengths with specialised passes report the dominant pass's HBM
+    fraction; the run-time-length kernels (other lengths) report null there."""
     import numpy as np
     import torch
     from paper_1601_04640_amd import binding as B
-    from paper_1601_04640_amd.binding import Solver
-    dims3 = [n for n in B.supported_sizes() if 48 <= n <= args.sweep_max3]
-    dims2 = [n for n in B.supported_sizes() if 256 <= n <= args.sweep_max2]
     cases = []
     if 3 in args.sweep_dims:
-        cases += [("3d", n) for n in dims3]
+        cases += [("3d", n) for n in SWEEP3 if n <= args.sweep_max3]
     if 2 in args.sweep_dims:
-        cases += [("2dxy", n) for n in dims2]
-    free = torch.cuda.mem_get_info()[0]
+        cases += [("2dxy", n) for n in SWEEP2 if n <= args.sweep_max2]
     for geom, n in cases:
         for prec in args.sweep_prec:
             esz = 8 if prec == "fp64" else 4
+            kind = B.gp_axis_kind(n, prec)
+            if kind == 0:
+                continue
             h = 12.8 / n
             w = dict(geom=geom, nx=n, ny=n, nz=n if geom == "3d" else 1, dx=h, dy=h, dz=h,
                      dt=0.0005, gamma=1.0, nu=1.0, lam=2.0 if geom == "3d" else 4.0, g=20.0,
                      gdd=6.0, R=6.4 if geom == "3d" else 0.0)
             need = B.gp_workspace_bytes(B.make_params(**{**w, "prec": prec}))
-            if need > 0.8 * free:
+            if need > 0.8 * torch.cuda.mem_get_info()[0]:
                 continue
-            x = (np.arange(n) - n // 2) * h
+            x = ((np.arange(n) - n // 2) * h).astype(np.float64)
+            g1 = np.exp(-0.5 * x * x)
+            g1[0] = g1[-1] = 0.0
             if geom == "3d":
-                psi = np.exp(-0.5 * (x[:, None, None] ** 2 * 2.0 + x[None, :, None] ** 2 +
-                                     x[None, None, :] ** 2)).astype(np.complex128)
-                psi[0] = psi[-1] = psi[:, 0] = psi[:, -1] = psi[:, :, 0] = psi[:, :, -1] = 0
+                gz = np.exp(-0.5 * 2.0 * x * x)
+                gz[0] = gz[-1] = 0.0
+                psi = (gz[:, None, None] * g1[None, :, None] * g1[None, None, :]).astype(np.complex128)
             else:
-                psi = np.exp(-0.5 * (x[:, None] ** 2 + x[None, :] ** 2)).astype(np.complex128)
-                psi[0] = psi[-1] = psi[:, 0] = psi[:, -1] = 0
+                psi = (g1[:, None] * g1[None, :]).astype(np.complex128)
             psi /= np.sqrt(np.sum(np.abs(psi) ** 2) * h ** (3 if geom == "3d" else 2))
             npts = psi.size
             steps = max(GRAPH_STEPS, min(400, int(2e9 / npts) // GRAPH_STEPS * GRAPH_STEPS))
             r = time_gpu(None, prec, psi, steps, GRAPH_STEPS + 1, solver_params=w)
             wall = r["graph"]["wall"]
             byts = (step_bytes_3d(n, n, n, esz) if geom == "3d" else step_bytes_2d(n, n, esz))
-            line = {"sweep": "grid size", "geom": geom, "n": n, "points": npts, "dtype":
-                    "f64" if prec == "fp64" else "f32", "steps": steps,
-                    "value": npts * steps / wall, "unit": "grid-point-steps/s",
-                    "ms_per_step": wall * 1e3 / steps,
-                    "step_algorithmic_bytes": byts,
+            line = {"sweep": "grid size", "geom": geom, "n": n, "points": npts,
+                    "dtype": "f64" if prec == "fp64" else "f32",
+                    "passes": "specialised" if kind == 1 else "run-time length",
+                    "steps": steps, "value": npts * steps / wall, "unit": "grid-point-steps/s",
+                    "ms_per_step": wall * 1e3 / steps, "step_algorithmic_bytes": byts,
                     "step_hbm_frac": round(byts / (wall / steps) / 1e9 / HBM_PEAK_GBS, 4),
-                    "dominant_kernel_frac": roofline(r, esz)["frac"]}
+                    "dominant_kernel_frac": roofline(r, esz)["frac"] if kind == 1 else None}
             print(json.dumps(line), flush=True)
             del psi
             torch.cuda.empty_cache()
@@ -485,10 +495,12 @@ def main():
                     help="only the headline workload (FP64 and FP32)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 2D ensemble")
     ap.add_argument("--batch-steps", type=int, default=400)
+    ap.add_argument("--two-streams", action="store_true",
+                    help="also time the ensemble with its two size classes on two streams")
     ap.add_argument("--sweep", action="store_true", help="throughput against grid size")
     ap.add_argument("--sweep-dims", type=int, nargs="*", default=[3, 2])
     ap.add_argument("--sweep-prec", nargs="*", default=["fp32", "fp64"])
-    ap.add_argument("--sweep-max3", type=int, default=512)
+    ap.add_argument("--sweep-max3", type=int, default=600)
     ap.add_argument("--sweep-max2", type=int, default=16384)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -548,10 +560,9 @@ def main():
         log("128^3 adjoint")
         line["adjoint3d_128"] = adjoint_128()
         if not args.no_batch:
-            line["batched_2d"] = time_batch(args.batch_steps)
+            line["batched_2d"] = time_batch(args.batch_steps, two_streams=args.two_streams)
             log(f"batched 2d: {line['batched_2d']['ms_per_step']:.4f} ms/step "
-                f"(default plan {line['batched_2d']['ms_per_step_default_plan']:.4f}, two "
-                f"streams {line['batched_2d']['ms_per_step_two_streams']:.4f})")
+                f"(default plan {line['batched_2d']['ms_per_step_default_plan']:.4f})")
     line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
 

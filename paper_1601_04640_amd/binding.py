@@ -113,6 +113,7 @@ _SIGS = {
     "gp_dipolar_potential_noalloc": (ctypes.c_int, [ctypes.POINTER(gp_params), _P, _P, _P]),
     "gp_timing_enable": (ctypes.c_int, [_P, ctypes.c_uint]),
     "gp_get_params": (ctypes.c_int, [_P, ctypes.POINTER(gp_params)]),
+    "gp_axis_kind": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
     "gp_save_state": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_longlong, ctypes.c_double]),
     "gp_save_density": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_longlong, ctypes.c_double]),
     "gp_load_state": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.POINTER(gp_state_info)]),
@@ -358,13 +359,17 @@ def gp_evolve(ctx: int, imag: bool, nsteps: int, every: int, fn=None) -> int:
     return done.value
 
 
-def supported_sizes(limit: int = 16384) -> list:
-    """Axis lengths gp_init accepts (probed through gp_workspace_bytes on a 2D grid)."""
+def gp_axis_kind(n: int, prec: str = "fp64") -> int:
+    """1: specialised passes, 2: run-time-length passes, 0: unsupported."""
+    return load().gp_axis_kind(n, PREC[prec])
+
+
+def supported_sizes(limit: int = 16384, prec: str = "fp64", kind=None) -> list:
+    """Axis lengths gp_init accepts (kind 1 or 2, or only the given kind)."""
     out = []
     for n in range(2, limit + 1, 2):
-        p = make_params("2dxy", nx=n, ny=8, lam=1.0)
-        nb = ctypes.c_size_t(0)
-        if load().gp_workspace_bytes(ctypes.byref(p), ctypes.byref(nb)) == GP_OK:
+        k = gp_axis_kind(n, prec)
+        if k and (kind is None or k == kind):
             out.append(n)
     return out
 

@@ -1722,6 +1722,12 @@ gp_status gp_batch_get_psi(gp_batch* b, int idx, void* psi, int on_device) {
   return gp_get_psi(b->inst[idx], psi, on_device);
 }
 
+int gp_axis_kind(int n, int prec) {
+  if (prec != GP_FP64 && prec != GP_FP32_MIXED) return 0;
+  if (fast_size(n)) return 1;
+  return size_ok(n, prec == GP_FP64) ? 2 : 0;
+}
+
 gp_status gp_get_params(gp_ctx* c, gp_params* out) {
   if (!c || !out) return GP_E_ARG;
   *out = c->p;
