@@ -68,12 +68,12 @@ struct Layout {
   size_t npts, nspec, nktab;  // grid points, half-spectrum values, kernel-table values
   size_t esz;           // bytes of one real value
   int nb_x, nb_nl, nb_col, nb_colobs;
-  // axes without a compile-time specialisation run the run-time-length passes
-  bool generic;
-  // byte offsets inside the workspace (o_gA, o_gB: the run-time-length passes' transposed
-  // state and sweep scratch, zero-sized otherwise)
+  // axes without a compile-time specialisation run the run-time-length passes; gscr: their
+  // one-thread-per-line sweeps need a grid of scratch values (o_gscr)
+  bool generic, gscr;
+  // byte offsets inside the workspace
   size_t o_psi, o_V, o_spec, o_ktab, o_tw[3], o_cn[3][3], o_px[2], o_pnl, o_pcol, o_padj, o_sfield,
-      o_scalars, o_ring, o_obs, o_io, o_stamps, o_stage, o_gA, o_gB, total;
+      o_scalars, o_ring, o_obs, o_io, o_stamps, o_stage, o_gscr, total;
 };
 
 struct Scalars {  // device-side scalars (one 256-byte block)
@@ -140,8 +140,15 @@ Layout make_layout(const gp_params* p) {
                   : GLaunch<float>::x_blocks(L.n0, L.n1, L.n2);
     L.nb_nl = fp64 ? GLaunch<double>::nl_blocks(L.n0, L.n1, L.n2)
                    : GLaunch<float>::nl_blocks(L.n0, L.n1, L.n2);
-    // one thread per column of the last sweep (z in 3D, y in 2D) and of the z observe
-    L.nb_col = GLaunch<float>::col_blocks(p->geom == GP_3D ? L.n0 * L.n1 : L.n0);
+    // blocks of the last sweep (z in 3D, y in 2D), which the z observe shares
+    L.nb_col = p->geom == GP_3D
+                   ? (fp64 ? GLaunch<double>::cn_blocks(L.n2, L.n0 * L.n1, true)
+                           : GLaunch<float>::cn_blocks(L.n2, L.n0 * L.n1, true))
+                   : (fp64 ? GLaunch<double>::cn_blocks(L.n1, L.n0, true)
+                           : GLaunch<float>::cn_blocks(L.n1, L.n0, true));
+    // scratch of the one-thread-per-line sweeps (3D grids whose y or z sweep has many lines)
+    L.gscr = p->geom == GP_3D && (L.n0 * L.n2 >= GLaunch<float>::kColLines ||
+                                  L.n0 * L.n1 >= GLaunch<float>::kColLines);
   } else {
     const int tj = tj_of(fp64, L.n0);
     L.nb_x = ((L.n1 + tj - 1) / tj) * L.n2;
@@ -185,8 +192,7 @@ Layout make_layout(const gp_params* p) {
   L.o_io = take(16 * std::min(L.npts, kIoChunk));
   L.o_stamps = take(16 * (size_t)L.nb_x);
   L.o_stage = take(sizeof(double) * kStageVals * kStageMax);
-  L.o_gA = take(L.generic ? 2 * L.esz * L.npts : 0);
-  L.o_gB = take(L.generic ? 2 * L.esz * L.npts : 0);
+  L.o_gscr = take(L.generic && L.gscr ? 2 * L.esz * L.npts : 0);
   L.total = o;
   return L;
 }
@@ -398,19 +404,23 @@ struct Passes {
     return GP_OK;
   }
 
-  // column sweep of axis 1 (y) or 2 (z) of the stored state; sums: 0, 1 (new state), 2
-  static gp_status g_sweep(gp_ctx* c, int axis, int k, int sums) {
+  // CN sweep of axis a (0: x, 1: y, 2: z) of the stored state; mode 0: solve, 1: solve
+  // with the new-state sums, 2: the sums of the stored state only
+  static gp_status g_sweep(gp_ctx* c, int axis, int k, int mode) {
     const Layout& L = c->L;
-    cpx<T>* gB = c->at<cpx<T>>(L.o_gB);
-    double* pc = c->at<double>(L.o_pcol);
-    const cpx<T>* f = sums == 2 ? nullptr : cn(c, axis, k);
-    if (axis == 1) {  // lines (i, k2) along y: base k2 n0 n1 + i, stride n0
-      return dev(GLaunch<T>::cn_cols(sums, c->st, psi(c), gB, f, L.n1, L.n0,
-                                     (long long)L.n0 * L.n1, L.n0, L.n0 * L.n2, pc));
-    }
+    double* pc = mode == 0 ? nullptr : c->at<double>(L.o_pcol);
+    const cpx<T>* f = mode == 2 ? nullptr : cn(c, axis, k);
+    const long long plane = (long long)L.n0 * L.n1;
+    cpx<T>* dscr = c->at<cpx<T>>(L.o_gscr);
+    if (axis == 0)  // lines (j, k2), contiguous
+      return dev(GLaunch<T>::cn_lines(mode, c->st, psi(c), L.n0, L.n1 * L.n2, 1, L.n0, 0, 1,
+                                      f, pc, dscr));
+    if (axis == 1)  // lines (i, k2) along y: base k2 n0 n1 + i, stride n0
+      return dev(GLaunch<T>::cn_lines(mode, c->st, psi(c), L.n1, L.n0 * L.n2, L.n0, plane, 1,
+                                      L.n0, f, pc, dscr));
     // lines (i, j) along z: base j n0 + i, stride n0 n1
-    return dev(GLaunch<T>::cn_cols(sums, c->st, psi(c), gB, f, L.n2, L.n0 * L.n1, 0,
-                                   (long long)L.n0 * L.n1, L.n0 * L.n1, pc));
+    return dev(GLaunch<T>::cn_lines(mode, c->st, psi(c), L.n2, L.n0 * L.n1, L.n0 * L.n1, 0, 1,
+                                    plane, f, pc, dscr));
   }
 
   static gp_status g_step(gp_ctx* c, bool imag) {
@@ -418,19 +428,13 @@ struct Passes {
     const int mode = imag ? MODE_IMAG : MODE_REAL;
     const int k = imag ? 0 : 1;
     T* phi = c->at<T>(L.o_sfield);
-    cpx<T>* gA = c->at<cpx<T>>(L.o_gA);
-    cpx<T>* gB = c->at<cpx<T>>(L.o_gB);
     GP_TRY(settle(c));
     GP_TRY(g_convolution(c, psi(c), &c->sc()->scale));
     GP_TRY(pass_begin(c, GP_PASS_C2R_NL_CNX));
     GP_HIP(GLaunch<T>::c2r_x(c->st, spec(c), phi, c->gplan[0], tw(c, 0), L.n0, L.n1, L.n2));
-    GP_HIP(GLaunch<T>::nl_transpose(mode, c->st, psi(c), c->at<T>(L.o_V), phi, &c->sc()->scale,
-                                    gA, g_scalars(c), L.n0, L.n1, L.n2,
-                                    c->at<double>(L.o_pnl)));
-    // x lines of the transposed state (k2, j): base k2 n0 n1 + j, stride n1
-    GP_HIP(GLaunch<T>::cn_cols(0, c->st, gA, gB, cn(c, 0, k), L.n0, L.n1,
-                               (long long)L.n0 * L.n1, L.n1, L.n1 * L.n2, nullptr));
-    GP_HIP(GLaunch<T>::transpose(c->st, gA, psi(c), L.n1, L.n0, L.n2));
+    GP_HIP(GLaunch<T>::nonlinear(mode, c->st, psi(c), c->at<T>(L.o_V), phi, &c->sc()->scale,
+                                 g_scalars(c), L.n0, L.n1, L.n2, c->at<double>(L.o_pnl)));
+    GP_TRY(g_sweep(c, 0, k, 0));
     GP_TRY(pass_end(c, GP_PASS_C2R_NL_CNX));
     if (c->p.geom == GP_3D) {
       GP_TRY(pass_begin(c, GP_PASS_CN_Y));
@@ -451,9 +455,9 @@ struct Passes {
     const Layout& L = c->L;
     T* phi = c->at<T>(L.o_sfield);
     GP_TRY(g_phi(c, psi(c), &c->sc()->scale, phi));
-    GP_HIP(GLaunch<T>::nl_transpose(MODE_OBSERVE, c->st, psi(c), c->at<T>(L.o_V), phi,
-                                    &c->sc()->scale, nullptr, g_scalars(c), L.n0, L.n1, L.n2,
-                                    c->at<double>(L.o_pnl)));
+    GP_HIP(GLaunch<T>::nonlinear(MODE_OBSERVE, c->st, psi(c), c->at<T>(L.o_V), phi,
+                                 &c->sc()->scale, g_scalars(c), L.n0, L.n1, L.n2,
+                                 c->at<double>(L.o_pnl)));
     if (c->p.geom == GP_3D) return z_observe(c, FIN_OBSERVE);
     return finalize(c, FIN_OBSERVE);
   }

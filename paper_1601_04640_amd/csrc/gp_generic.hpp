@@ -11,13 +11,15 @@
 //   kg_lines        line FFTs of the half spectrum (forward, inverse, or forward + U(k)
 //                   product + inverse, the convolution along the last axis)
 //   kg_c2r_x        x complex-to-real FFT -> Phi (a real grid)
-//   kg_nl_transpose psi <- scale psi exp(-eps dt (V + g_c n + g_dd Phi)) with the
-//                   norm / potential / contact / dipolar / rms sums, written x-major
-//                   (transposed), so that the x lines become columns
-//   kg_cn_cols      Crank-Nicolson sweep of columns (one thread per line, Thomas
-//                   recurrences through a scratch array), optionally with the norm and
-//                   difference sums of the new state
-//   kg_transpose    back to the psi layout
+//   kg_nonlinear    psi <- scale psi exp(-eps dt (V + g_c n + g_dd Phi)) in place, with the
+//                   norm / potential / contact / dipolar / rms sums
+//   kg_cn_lines     Crank-Nicolson sweep of lines held in LDS, one wave per line (a
+//                   chunked scan of the Thomas recurrences): x lines, and strided lines
+//                   when there are few of them; optionally with the norm and difference
+//                   sums of the new state
+//   kg_cn_cols      the same sweep, one thread per strided line with the recurrence
+//                   values in a scratch grid: strided axes with many lines, where
+//                   consecutive threads read consecutive addresses
 // The partial sums have the meaning the FP64 finalisation reads (gp_finalize.hpp).
 #pragma once
 #include "gp_device.hpp"
@@ -357,103 +359,192 @@ struct GStep {
   double dt, gc, gdd, h0, h1, h2;
 };
 
-// Nonlinear sub-step of 32 x 32 (x, axis 1) tiles of one plane, written transposed
-// (dst[(k n0 + i) n1 + j]) unless MODE is MODE_OBSERVE.  part[7 b ...]: sum n, V n,
-// n^2, Phi n, x^2 n, a1^2 n, a2^2 n of the physical incoming state (scale psi).
+// Blocks of the nonlinear pass: a fixed count (each walks its share of the grid), so the
+// number of partial-sum slots is known when the workspace is laid out.
+__host__ __device__ inline int gen_nl_blocks(long long npts) {
+  long long b = (npts + 4095) / 4096;
+  return (int)(b < 1 ? 1 : (b > 2048 ? 2048 : b));
+}
+
+// Nonlinear sub-step in place: psi <- scale psi exp(-eps dt (V + g_c n + g_dd Phi)),
+// eps = 1 (MODE_IMAG) or i (MODE_REAL); MODE_OBSERVE only sums.  part[7 b ...]: sum n,
+// V n, n^2, Phi n, x^2 n, a1^2 n, a2^2 n of the physical incoming state (scale psi).
 template <typename T, int MODE>
-__global__ void __launch_bounds__(kThreads) kg_nl_transpose(const cpx<T>* __restrict__ psi,
-                                                            const T* __restrict__ V,
-                                                            const T* __restrict__ phi,
-                                                            const double* __restrict__ scale,
-                                                            cpx<T>* __restrict__ dst, GStep sc,
-                                                            int n0, int n1, int n2,
-                                                            double* __restrict__ part) {
-  __shared__ cpx<T> tile[32][33];
+__global__ void __launch_bounds__(kThreads) kg_nonlinear(cpx<T>* __restrict__ psi,
+                                                         const T* __restrict__ V,
+                                                         const T* __restrict__ phi,
+                                                         const double* __restrict__ scale,
+                                                         GStep sc, int n0, int n1, int n2,
+                                                         double* __restrict__ part) {
   __shared__ double red[7 * kWaves];
-  const int tx = (n0 + 31) / 32, ty = (n1 + 31) / 32;
-  const int b = blockIdx.x;
-  const int k = b / (tx * ty);
-  const int rem = b - k * tx * ty;
-  const int i0 = (rem % tx) * 32, jt0 = (rem / tx) * 32;
+  const long long npts = (long long)n0 * n1 * n2;
+  const long long per = (npts + gridDim.x - 1) / gridDim.x;
+  const long long lo = per * blockIdx.x;
+  const long long hi = lo + per < npts ? lo + per : npts;
   const T ts = (T)(*scale);
   double ps[7] = {0, 0, 0, 0, 0, 0, 0};
-  const double a2 = (k - n2 / 2) * sc.h2;
-  const int li = threadIdx.x & 31;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int lj = (threadIdx.x >> 5) + 8 * r;
-    const int i = i0 + li, j = jt0 + lj;
-    if (i < n0 && j < n1) {
-      const long long a = ((long long)k * n1 + j) * n0 + i;
-      const cpx<T> pv = scl(psi[a], ts);
-      const T v = V[a], ph = phi[a];
-      const T n = pv.re * pv.re + pv.im * pv.im;
-      const double nd = (double)n;
-      const double x = (i - n0 / 2) * sc.h0, y = (j - n1 / 2) * sc.h1;
-      ps[0] += nd;
-      ps[1] += (double)v * nd;
-      ps[2] += nd * nd;
-      ps[3] += (double)ph * nd;
-      ps[4] += x * x * nd;
-      ps[5] += y * y * nd;
-      ps[6] += a2 * a2 * nd;
-      if constexpr (MODE == MODE_IMAG || MODE == MODE_REAL) {
-        const T th = (T)sc.dt * (v + (T)sc.gc * n + (T)sc.gdd * ph);
-        cpx<T> f;
-        if constexpr (MODE == MODE_IMAG) {
-          f = cpx<T>{exp(-th), (T)0};
-        } else {
-          T sn, cs;
-          sincos_phase(th, sn, cs);
-          f = cpx<T>{cs, -sn};
-        }
-        tile[lj][li] = pv * f;
+  for (long long a = lo + threadIdx.x; a < hi; a += kThreads) {
+    const int i = (int)(a % n0);
+    const long long r = a / n0;
+    const int j = (int)(r % n1), k = (int)(r / n1);
+    const cpx<T> pv = scl(psi[a], ts);
+    const T v = V[a], ph = phi[a];
+    const T n = pv.re * pv.re + pv.im * pv.im;
+    const double nd = (double)n;
+    const double x = (i - n0 / 2) * sc.h0, y = (j - n1 / 2) * sc.h1, z = (k - n2 / 2) * sc.h2;
+    ps[0] += nd;
+    ps[1] += (double)v * nd;
+    ps[2] += nd * nd;
+    ps[3] += (double)ph * nd;
+    ps[4] += x * x * nd;
+    ps[5] += y * y * nd;
+    ps[6] += z * z * nd;
+    if constexpr (MODE == MODE_IMAG || MODE == MODE_REAL) {
+      const T th = (T)sc.dt * (v + (T)sc.gc * n + (T)sc.gdd * ph);
+      cpx<T> f;
+      if constexpr (MODE == MODE_IMAG) {
+        f = cpx<T>{exp(-th), (T)0};
+      } else {
+        T sn, cs;
+        sincos_phase(th, sn, cs);
+        f = cpx<T>{cs, -sn};
       }
+      psi[a] = pv * f;
     }
   }
   block_sum<7>(ps, red);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int q = 0; q < 7; ++q) part[7 * (long long)b + q] = ps[q];
+    for (int q = 0; q < 7; ++q) part[7 * (long long)blockIdx.x + q] = ps[q];
   }
-  if constexpr (MODE == MODE_IMAG || MODE == MODE_REAL) {
+}
+
+template <typename T>
+__device__ __forceinline__ cpx<T> shfl_up_c(cpx<T> v, int off) {
+  return cpx<T>{__shfl_up(v.re, off, 64), __shfl_up(v.im, off, 64)};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> shfl_down_c(cpx<T> v, int off) {
+  return cpx<T>{__shfl_down(v.re, off, 64), __shfl_down(v.im, off, 64)};
+}
+
+// Crank-Nicolson sweep of lines held in LDS, one 64-lane wave per line.  In increment
+// form, with Delta_i = psi_(i-1) + psi_(i+1) - 2 psi_i and the factor table
+// f_i = 2 A m_i (Thomas factors m of (1 + 2A) u_i - A (u_(i-1) + u_(i+1)); f = 0 on the
+// two boundary rows), g_i = f_i / 2:
+//   forward  d_i = f_i Delta_i + g_i d_(i-1)      backward  e_i = d_i + g_i e_(i+1)
+//   u_i = psi_i + e_i.
+// Both are first-order linear recurrences.  Lane q takes the chunk of S = ceil(N/64)
+// consecutive rows, runs the recurrence from a zero carry, and the lanes' chunks are
+// joined by a scan of the affine maps c -> (prod g) c + (local result) across the wave;
+// each lane then adds its carry times the running product of g.  The result equals the
+// sequential recurrence up to rounding order.
+// MODE 0: solve; 1: solve, then part[2b] = sum |u|^2, part[2b+1] = sum |u_(i+1) - u_i|^2
+// of the new state; 2: those sums of the stored state, no solve.
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kThreads) kg_cn_lines(cpx<T>* __restrict__ data, GLines g,
+                                                        const cpx<T>* __restrict__ f,
+                                                        double* __restrict__ part) {
+  extern __shared__ __align__(16) char lds_raw[];
+  const int N = g.n;
+  const int l0 = blockIdx.x * g.nl;
+  const int nl = min(g.nl, g.nlines - l0);
+  const int tot = nl * N;
+  cpx<T>* ps = reinterpret_cast<cpx<T>*>(lds_raw);        // nl lines of psi (then u)
+  cpx<T>* dv = ps + (size_t)g.nl * N;                      // nl lines of d
+  const bool contig = g.se == 1;
+  for (int t = threadIdx.x; t < tot; t += kThreads) {
+    const int line = contig ? t / N : t % nl;
+    const int e = contig ? t - line * N : t / nl;
+    ps[line * N + e] = data[g.addr(l0 + line, e)];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int S = (N + 63) / 64;
+  const int i0 = lane * S;
+  const int i1 = min(i0 + S, N);
+  double s0 = 0.0, s1 = 0.0;
+  if constexpr (MODE != 2) {
+    for (int line = wave; line < nl; line += kWaves) {
+      cpx<T>* p = ps + line * N;
+      cpx<T>* d = dv + line * N;
+      // forward, zero carry: local d and the chunk's product of g
+      cpx<T> acc = {0, 0}, prod = {1, 0};
+      for (int i = i0; i < i1; ++i) {
+        const cpx<T> fi = f[i];
+        const cpx<T> gi = scl(fi, (T)0.5);
+        const cpx<T> pm = i > 0 ? p[i - 1] : cpx<T>{0, 0};
+        const cpx<T> pn = i + 1 < N ? p[i + 1] : cpx<T>{0, 0};
+        const cpx<T> pc = p[i];
+        acc = fi * ((pm + pn) - (pc + pc)) + gi * acc;
+        prod = gi * prod;
+        d[i] = acc;
+      }
+      // inclusive scan of the maps c -> prod c + acc over the lanes
+      cpx<T> P = prod, B = acc;
+      for (int off = 1; off < 64; off <<= 1) {
+        const cpx<T> Pp = shfl_up_c(P, off), Bp = shfl_up_c(B, off);
+        if (lane >= off) {
+          B = P * Bp + B;
+          P = P * Pp;
+        }
+      }
+      cpx<T> carry = shfl_up_c(B, 1);   // d at the end of the previous chunk
+      if (lane == 0) carry = cpx<T>{0, 0};
+      for (int i = i0; i < i1; ++i) {
+        carry = scl(f[i], (T)0.5) * carry;
+        d[i] = d[i] + carry;
+      }
+      // backward, zero carry from the right: local e (kept in d)
+      acc = cpx<T>{0, 0};
+      for (int i = i1 - 1; i >= i0; --i) {
+        acc = d[i] + scl(f[i], (T)0.5) * acc;
+        d[i] = acc;
+      }
+      P = prod;
+      B = acc;
+      for (int off = 1; off < 64; off <<= 1) {
+        const cpx<T> Pn = shfl_down_c(P, off), Bn = shfl_down_c(B, off);
+        if (lane + off < 64) {
+          B = P * Bn + B;
+          P = P * Pn;
+        }
+      }
+      carry = shfl_down_c(B, 1);         // e at the start of the next chunk
+      if (lane == 63) carry = cpx<T>{0, 0};
+      for (int i = i1 - 1; i >= i0; --i) {
+        carry = scl(f[i], (T)0.5) * carry;
+        p[i] = p[i] + (d[i] + carry);
+      }
+    }
     __syncthreads();
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int li2 = (threadIdx.x >> 5) + 8 * r;   // x within the tile
-      const int lj2 = threadIdx.x & 31;             // axis 1 within the tile
-      const int i = i0 + li2, j = jt0 + lj2;
-      if (i < n0 && j < n1) dst[((long long)k * n0 + i) * n1 + j] = tile[lj2][li2];
+  }
+  if constexpr (MODE != 0) {
+    for (int line = wave; line < nl; line += kWaves) {
+      const cpx<T>* p = ps + line * N;
+      for (int i = i0; i < i1; ++i) {
+        s0 += abs2_d(p[i]);
+        if (i + 1 < N) s1 += absdiff2_d(p[i + 1], p[i]);
+      }
+    }
+    double s[2] = {s0, s1};
+    block_sum<2>(s, reinterpret_cast<double*>(dv));   // d is no longer needed
+    if (threadIdx.x == 0) {
+      part[2 * blockIdx.x] = s[0];
+      part[2 * blockIdx.x + 1] = s[1];
+    }
+  }
+  if constexpr (MODE != 2) {
+    for (int t = threadIdx.x; t < tot; t += kThreads) {
+      const int line = contig ? t / N : t % nl;
+      const int e = contig ? t - line * N : t / nl;
+      data[g.addr(l0 + line, e)] = ps[line * N + e];
     }
   }
 }
 
-// dst[(k a + x) b + y] = src[(k b + y) a + x]: the two fastest axes of nz planes swapped.
-template <typename T>
-__global__ void __launch_bounds__(kThreads) kg_transpose(const cpx<T>* __restrict__ src,
-                                                         cpx<T>* __restrict__ dst, int a, int b,
-                                                         int nz) {
-  __shared__ cpx<T> tile[32][33];
-  const int tx = (a + 31) / 32, ty = (b + 31) / 32;
-  const int blk = blockIdx.x;
-  const int k = blk / (tx * ty);
-  const int rem = blk - k * tx * ty;
-  const int x0 = (rem % tx) * 32, y0 = (rem / tx) * 32;
-  const int l = threadIdx.x & 31;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int yy = (threadIdx.x >> 5) + 8 * r;
-    if (x0 + l < a && y0 + yy < b) tile[yy][l] = src[((long long)k * b + y0 + yy) * a + x0 + l];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int xx = (threadIdx.x >> 5) + 8 * r;
-    if (x0 + xx < a && y0 + l < b) dst[((long long)k * a + x0 + xx) * b + y0 + l] = tile[l][xx];
-  }
-}
-
-// Crank-Nicolson sweep of columns, one thread per line (line l: element e at
+// Crank-Nicolson sweep of strided lines with many lines per sweep (3D y and z), one thread
+// per line (line l: element e at
 // (l / G) so + (l mod G) + e se, consecutive lines adjacent in memory).  In increment
 // form: with Delta_i = psi_(i-1) + psi_(i+1) - 2 psi_i and the factor table f_i = 2 A m_i
 // (Thomas factors m of (1 + 2A) u_i - A (u_(i-1) + u_(i+1)), zero on the boundary rows),
@@ -525,5 +616,6 @@ __global__ void __launch_bounds__(kThreads) kg_cn_cols(cpx<T>* __restrict__ u,
     }
   }
 }
+
 
 }  // namespace gpdbec

@@ -58,6 +58,15 @@ hipError_t GLaunch<T>::prepare() {
     const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
   }
+  // the CN sweeps hold two buffers of up to 64 KiB
+  const void* kc[] = {reinterpret_cast<const void*>(&kg_cn_lines<T, 0>),
+                      reinterpret_cast<const void*>(&kg_cn_lines<T, 1>),
+                      reinterpret_cast<const void*>(&kg_cn_lines<T, 2>)};
+  for (const void* k : kc) {
+    const hipError_t e =
+        hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 2 * lds);
+    if (e != hipSuccess) return e;
+  }
   done = true;
   return hipSuccess;
 }
@@ -87,8 +96,15 @@ int GLaunch<T>::x_blocks(int n0, int n1, int n2) {
 }
 
 template <>
-int GLaunch<T>::nl_blocks(int n0, int n1, int n2) {
-  return ((n0 + 31) / 32) * ((n1 + 31) / 32) * n2;
+int GLaunch<T>::cn_lines_per_block(int n, int nlines) {
+  // two LDS buffers (psi and the recurrence values) of nl lines within 128 KiB; about
+  // 4096 values per block, halved while the sweep would have fewer than 512 blocks
+  const int cap = 2 * gen_max_line<T>() / (2 * n);
+  int nl = 4096 / n;
+  if (nl < 1) nl = 1;
+  if (nl > cap) nl = cap;
+  while (nl > 1 && (nlines + nl - 1) / nl < 512) nl /= 2;
+  return nl;
 }
 
 template <>
@@ -153,22 +169,22 @@ hipError_t GLaunch<T>::lines(int kind, hipStream_t st, cpx<T>* data, int n, int 
 }
 
 template <>
-hipError_t GLaunch<T>::nl_transpose(int mode, hipStream_t st, const cpx<T>* psi, const T* V,
-                                    const T* phi, const double* scale, cpx<T>* dst,
-                                    const GStep& sc, int n0, int n1, int n2, double* part) {
+hipError_t GLaunch<T>::nonlinear(int mode, hipStream_t st, cpx<T>* psi, const T* V,
+                                 const T* phi, const double* scale, const GStep& sc, int n0,
+                                 int n1, int n2, double* part) {
   const int blocks = nl_blocks(n0, n1, n2);
   switch (mode) {
     case MODE_IMAG:
-      hipLaunchKernelGGL((kg_nl_transpose<T, MODE_IMAG>), dim3(blocks), dim3(kThreads), 0, st,
-                         psi, V, phi, scale, dst, sc, n0, n1, n2, part);
+      hipLaunchKernelGGL((kg_nonlinear<T, MODE_IMAG>), dim3(blocks), dim3(kThreads), 0, st,
+                         psi, V, phi, scale, sc, n0, n1, n2, part);
       break;
     case MODE_REAL:
-      hipLaunchKernelGGL((kg_nl_transpose<T, MODE_REAL>), dim3(blocks), dim3(kThreads), 0, st,
-                         psi, V, phi, scale, dst, sc, n0, n1, n2, part);
+      hipLaunchKernelGGL((kg_nonlinear<T, MODE_REAL>), dim3(blocks), dim3(kThreads), 0, st,
+                         psi, V, phi, scale, sc, n0, n1, n2, part);
       break;
     case MODE_OBSERVE:
-      hipLaunchKernelGGL((kg_nl_transpose<T, MODE_OBSERVE>), dim3(blocks), dim3(kThreads), 0,
-                         st, psi, V, phi, scale, dst, sc, n0, n1, n2, part);
+      hipLaunchKernelGGL((kg_nonlinear<T, MODE_OBSERVE>), dim3(blocks), dim3(kThreads), 0, st,
+                         psi, V, phi, scale, sc, n0, n1, n2, part);
       break;
     default:
       return hipErrorInvalidValue;
@@ -177,30 +193,56 @@ hipError_t GLaunch<T>::nl_transpose(int mode, hipStream_t st, const cpx<T>* psi,
 }
 
 template <>
-hipError_t GLaunch<T>::transpose(hipStream_t st, const cpx<T>* src, cpx<T>* dst, int a, int b,
-                                 int nz) {
-  const int blocks = ((a + 31) / 32) * ((b + 31) / 32) * nz;
-  hipLaunchKernelGGL((kg_transpose<T>), dim3(blocks), dim3(kThreads), 0, st, src, dst, a, b, nz);
-  return hipGetLastError();
-}
-
-template <>
-hipError_t GLaunch<T>::cn_cols(int sums, hipStream_t st, cpx<T>* u, cpx<T>* dscr,
-                               const cpx<T>* f, int n, int G, long long so, long long se,
-                               int nlines, double* part) {
-  const int blocks = col_blocks(nlines);
-  switch (sums) {
+hipError_t GLaunch<T>::cn_lines(int mode, hipStream_t st, cpx<T>* data, int n, int nlines,
+                                int G, long long so, long long si, long long se,
+                                const cpx<T>* f, double* part, cpx<T>* dscr) {
+  if (n > gen_max_line<T>() || nlines < 1) return hipErrorInvalidValue;
+  if (cn_by_columns(se != 1, nlines)) {
+    // consecutive lines adjacent (si = 1): one thread per line
+    if (si != 1) return hipErrorInvalidValue;
+    const int blocks = (nlines + kThreads - 1) / kThreads;
+    switch (mode) {
+      case 0:
+        hipLaunchKernelGGL((kg_cn_cols<T, false, false>), dim3(blocks), dim3(kThreads), 0, st,
+                           data, dscr, f, n, G, so, se, nlines, part);
+        break;
+      case 1:
+        hipLaunchKernelGGL((kg_cn_cols<T, true, false>), dim3(blocks), dim3(kThreads), 0, st,
+                           data, dscr, f, n, G, so, se, nlines, part);
+        break;
+      case 2:
+        hipLaunchKernelGGL((kg_cn_cols<T, false, true>), dim3(blocks), dim3(kThreads), 0, st,
+                           data, dscr, f, n, G, so, se, nlines, part);
+        break;
+      default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
+  GLines g{};
+  g.n = n;
+  g.nlines = nlines;
+  g.nl = cn_lines_per_block(n, nlines);
+  g.G = G;
+  g.so = so;
+  g.si = si;
+  g.se = se;
+  const int blocks = (nlines + g.nl - 1) / g.nl;
+  // psi lines, then the recurrence values (at least the block reduction's 64 bytes)
+  const size_t one = lds_of(g.nl * n);
+  const size_t lds = one + (one < 64 ? 64 : one);
+  switch (mode) {
     case 0:
-      hipLaunchKernelGGL((kg_cn_cols<T, false, false>), dim3(blocks), dim3(kThreads), 0, st, u,
-                         dscr, f, n, G, so, se, nlines, part);
+      hipLaunchKernelGGL((kg_cn_lines<T, 0>), dim3(blocks), dim3(kThreads), lds, st, data, g,
+                         f, part);
       break;
     case 1:
-      hipLaunchKernelGGL((kg_cn_cols<T, true, false>), dim3(blocks), dim3(kThreads), 0, st, u,
-                         dscr, f, n, G, so, se, nlines, part);
+      hipLaunchKernelGGL((kg_cn_lines<T, 1>), dim3(blocks), dim3(kThreads), lds, st, data, g,
+                         f, part);
       break;
     case 2:
-      hipLaunchKernelGGL((kg_cn_cols<T, false, true>), dim3(blocks), dim3(kThreads), 0, st, u,
-                         dscr, f, n, G, so, se, nlines, part);
+      hipLaunchKernelGGL((kg_cn_lines<T, 2>), dim3(blocks), dim3(kThreads), lds, st, data, g,
+                         f, part);
       break;
     default:
       return hipErrorInvalidValue;

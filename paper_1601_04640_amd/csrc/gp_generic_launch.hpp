@@ -31,9 +31,19 @@ struct GLaunch {
   // x passes: tile of the grid (line pairs per block) and its block count
   static GXTile xtile(int n0, int n1, int n2);
   static int x_blocks(int n0, int n1, int n2);
-  // nonlinear / transpose tiles (32 x 32 of the two fastest axes)
-  static int nl_blocks(int n0, int n1, int n2);
-  static int col_blocks(int nlines) { return (nlines + kThreads - 1) / kThreads; }
+  // blocks of the nonlinear pass (partial-sum slots) and of a CN sweep over nlines lines
+  static int nl_blocks(int n0, int n1, int n2) {
+    return gen_nl_blocks((long long)n0 * n1 * n2);
+  }
+  static int cn_lines_per_block(int n, int nlines);
+  // strided sweeps with at least this many lines run one thread per line
+  static constexpr int kColLines = 32768;
+  static bool cn_by_columns(bool strided, int nlines) { return strided && nlines >= kColLines; }
+  static int cn_blocks(int n, int nlines, bool strided) {
+    if (cn_by_columns(strided, nlines)) return (nlines + kThreads - 1) / kThreads;
+    const int nl = cn_lines_per_block(n, nlines);
+    return (nlines + nl - 1) / nl;
+  }
 
   static hipError_t r2c_x(hipStream_t st, const cpx<T>* psi, cpx<T>* spec, const GPlan& p,
                           const cpx<T>* tw, double* part, int n0, int n1, int n2);
@@ -43,22 +53,23 @@ struct GLaunch {
   static hipError_t lines(int kind, hipStream_t st, cpx<T>* data, int n, int nlines, int G,
                           long long so, long long si, long long se, const GPlan& p,
                           const cpx<T>* tw, const T* ktab, GKtab km, const double* scale);
-  // mode: MODE_IMAG, MODE_REAL (write dst), MODE_OBSERVE (sums only)
-  static hipError_t nl_transpose(int mode, hipStream_t st, const cpx<T>* psi, const T* V,
-                                 const T* phi, const double* scale, cpx<T>* dst,
-                                 const GStep& sc, int n0, int n1, int n2, double* part);
-  static hipError_t transpose(hipStream_t st, const cpx<T>* src, cpx<T>* dst, int a, int b,
-                              int nz);
-  // sums: 0 none, 1 new-state sums, 2 observe only (no solve)
-  static hipError_t cn_cols(int sums, hipStream_t st, cpx<T>* u, cpx<T>* dscr, const cpx<T>* f,
-                            int n, int G, long long so, long long se, int nlines, double* part);
+  // mode: MODE_IMAG, MODE_REAL (update psi), MODE_OBSERVE (sums only)
+  static hipError_t nonlinear(int mode, hipStream_t st, cpx<T>* psi, const T* V, const T* phi,
+                              const double* scale, const GStep& sc, int n0, int n1, int n2,
+                              double* part);
+  // CN sweep of nlines lines (addressing as `lines`); mode 0 solve, 1 solve + new-state
+  // sums, 2 sums of the stored state only
+  // (strided sweeps of many lines run kg_cn_cols, with dscr: a grid of scratch values)
+  static hipError_t cn_lines(int mode, hipStream_t st, cpx<T>* data, int n, int nlines, int G,
+                             long long so, long long si, long long se, const cpx<T>* f,
+                             double* part, cpx<T>* dscr);
 };
 
 #define GP_DECLARE_GLAUNCH(T)                                                                  \
   template <> hipError_t GLaunch<T>::prepare();                                                \
   template <> GXTile GLaunch<T>::xtile(int, int, int);                                         \
   template <> int GLaunch<T>::x_blocks(int, int, int);                                         \
-  template <> int GLaunch<T>::nl_blocks(int, int, int);                                        \
+  template <> int GLaunch<T>::cn_lines_per_block(int, int);                                    \
   template <> hipError_t GLaunch<T>::r2c_x(hipStream_t, const cpx<T>*, cpx<T>*, const GPlan&, \
                                            const cpx<T>*, double*, int, int, int);             \
   template <> hipError_t GLaunch<T>::c2r_x(hipStream_t, const cpx<T>*, T*, const GPlan&,      \
@@ -66,14 +77,12 @@ struct GLaunch {
   template <> hipError_t GLaunch<T>::lines(int, hipStream_t, cpx<T>*, int, int, int,          \
                                            long long, long long, long long, const GPlan&,     \
                                            const cpx<T>*, const T*, GKtab, const double*);    \
-  template <> hipError_t GLaunch<T>::nl_transpose(int, hipStream_t, const cpx<T>*, const T*,  \
-                                                  const T*, const double*, cpx<T>*,           \
-                                                  const GStep&, int, int, int, double*);      \
-  template <> hipError_t GLaunch<T>::transpose(hipStream_t, const cpx<T>*, cpx<T>*, int, int, \
-                                               int);                                           \
-  template <> hipError_t GLaunch<T>::cn_cols(int, hipStream_t, cpx<T>*, cpx<T>*,              \
-                                             const cpx<T>*, int, int, long long, long long,   \
-                                             int, double*);
+  template <> hipError_t GLaunch<T>::nonlinear(int, hipStream_t, cpx<T>*, const T*, const T*, \
+                                               const double*, const GStep&, int, int, int,    \
+                                               double*);                                       \
+  template <> hipError_t GLaunch<T>::cn_lines(int, hipStream_t, cpx<T>*, int, int, int,       \
+                                              long long, long long, long long, const cpx<T>*, \
+                                              double*, cpx<T>*);
 GP_DECLARE_GLAUNCH(float)
 GP_DECLARE_GLAUNCH(double)
 #undef GP_DECLARE_GLAUNCH

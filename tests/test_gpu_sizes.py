@@ -1,6 +1,7 @@
-"""Axis lengths without compile-time specialised passes (the run-time-length kernels):
-every even length >= 4 whose prime factors are at most 31, up to 8192 (FP32) / 4096
-(FP64) points per line.  The paper's programs take any grid and enlarge it silently for
+"""Axis lengths.  Those without compile-time specialised passes run the run-time-length
+kernels: every even length >= 4 whose prime factors are at most 31, up to 8192 (FP32) /
+4096 (FP64) points per line; and every specialised length is run in each role (x, y and
+z line).  The paper's programs take any grid and enlarge it silently for
 the FFT ("Unusual features"); here each length runs as given.  Parity with the FP64
 oracle through the C ABI at the same bars as the specialised sizes: psi rel-L2 and
 element-wise <= 1e-10 / 2e-5, energy and mu <= 1e-12 / 1e-6."""
@@ -167,3 +168,34 @@ def test_calls_needing_specialised_lengths_refuse(gpu_lib):
         B.Batch([dict(w, geom="2dxy", nz=1)], prec="fp64")
     assert e.value.status == B.GP_E_SIZE
     s.close()
+
+
+SPECIALISED = (8, 10, 12, 16, 20, 24, 30, 32, 40, 48, 60, 64, 80, 96, 120, 128, 160, 192,
+               240, 256, 320, 384, 480, 512)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", SPECIALISED)
+def test_every_specialised_length_in_every_role(n, prec, gpu_lib):
+    """Each compile-time specialised length as the x line (2D XY, n x 12), the y line
+    (2D XY, 12 x n) and the z line (3D 12 x 10 x n), from a white-noise start: three
+    real-time steps against the oracle."""
+    from paper_1601_04640_amd.binding import Solver
+    assert B.gp_axis_kind(n, prec) == 1
+    h = 12.0 / n
+    roles = {
+        "x": dict(geom="2dxy", nx=n, ny=12, nz=1, dx=h, dy=0.9, dz=1.0),
+        "y": dict(geom="2dxy", nx=12, ny=n, nz=1, dx=0.9, dy=h, dz=1.0),
+        "z": dict(geom="3d", nx=12, ny=10, nz=n, dx=0.9, dy=1.0, dz=h),
+    }
+    for role, g in roles.items():
+        w = dict(g, dt=0.001, gamma=1.0, nu=1.2, lam=2.0 if g["geom"] == "3d" else 4.0,
+                 g=15.0, gdd=5.0, R=2.5 if g["geom"] == "3d" else 0.0)
+        banner("specialised length", n, "as", role, prec)
+        p = oparams(w)
+        psi0 = I.random_complex(p.shape(), 600 + n, p.dV())
+        s = Solver(w, prec=prec)
+        s.set_psi(psi0)
+        s.step_real(3)
+        assert_psi_close(s.get_psi(), O.run(psi0, p, False, 3), bars(prec)[0], (n, role))
+        s.close()
