@@ -173,7 +173,7 @@ def cpu_baseline(budget_s=15.0):
 
 
 # ------------------------------------------------------------------------ GPU
-def time_gpu(workload, prec, psi_start, steps, warmup, solver_params=None):
+def time_gpu(workload, prec, psi_start, steps, warmup, solver_params=None, host=()):
     """Two live timed regions of `steps` full steps from the same start, on the solver's
     stream: (1) steps replayed from captured HIP graphs, no instrumentation -> value;
     (2) the same steps launched directly with the dominant pass's launches timed by their
@@ -184,15 +184,19 @@ def time_gpu(workload, prec, psi_start, steps, warmup, solver_params=None):
     from paper_1601_04640_amd import inputs as I
     from paper_1601_04640_amd.binding import Solver
     w = solver_params or I.WORKLOADS[workload]
-    s = Solver(w, prec=prec)
-    s.set_psi(psi_start)
+    s = Solver(w, prec=prec, host=host)
+    # the start state is kept on the device: resetting it between runs is a device copy,
+    # so the GPU does not sit idle (and clock down) behind a host transfer just before a
+    # timed region
+    psi_dev = torch.from_numpy(psi_start).to(s.device, s.cdtype)
+    s.set_psi(psi_dev)
     s.step_real(max(warmup, GRAPH_STEPS + 1))
-    s.set_psi(psi_start)
+    s.set_psi(psi_dev)
     s.step_real(steps)
     s.sync()
     res = {}
     for region in ("graph", "events"):
-        s.set_psi(psi_start)                 # every timed run starts afresh
+        s.set_psi(psi_dev)                   # every timed run starts afresh
         if region == "events":
             s.timing_enable([DOMINANT])
         else:
@@ -304,6 +308,25 @@ def quench_128x96x80(steps, warmup):
     return out
 
 
+def host_resident_256(steps, warmup):
+    """The headline workload with the trap potential and the dipolar kernel table in
+    pinned host memory (read over the host link every step), FP32 and FP64: step time and
+    the device memory it saves."""
+    from paper_1601_04640_amd import binding as B
+    from paper_1601_04640_amd import inputs as I
+    psi5 = I.psi0_real3d_256()
+    out = {}
+    for prec in ("fp32", "fp64"):
+        r = time_gpu(WORKLOAD, prec, psi5, steps, warmup, host=("V", "ktab"))
+        prm = B.make_params(**{**I.WORKLOADS[WORKLOAD], "prec": prec})
+        out[prec] = {"ms_per_step": r["graph"]["wall"] * 1e3 / steps,
+                     "value": r["npts"] * steps / r["graph"]["wall"],
+                     "workspace_bytes": B.gp_workspace_bytes_ex(prm, B.GP_HOST_V | B.GP_HOST_KTAB),
+                     "workspace_bytes_resident": B.gp_workspace_bytes(prm)}
+    out["note"] = "V and the kernel table in pinned host memory (gp_init_ex), 256^3 real time"
+    return out
+
+
 def imag3d_64(steps):
     """The 64^3 imaginary-time workload (FP64): graph-replayed steps from its start."""
     import torch
@@ -311,7 +334,7 @@ def imag3d_64(steps):
     from paper_1601_04640_amd.binding import Solver
     w = I.WORKLOADS["imag3d_64"]
     s = Solver(w, prec="fp64")
-    psi0 = I.psi0_imag3d_64()
+    psi0 = torch.from_numpy(I.psi0_imag3d_64()).to(s.device)   # reset by a device copy
     s.set_psi(psi0)
     s.step_imag(steps)
     s.set_psi(psi0)
@@ -337,7 +360,9 @@ def time_batch(steps, tune_steps=16, two_streams=False):
     from paper_1601_04640_amd.binding import Batch
     ens = I.batched_ensemble()
     b = Batch(ens, prec="fp32")
-    starts = [I.psi0_instance(w, seed=[1606, i]) for i, w in enumerate(ens)]
+    # start states kept on the device: resets are device copies, not host transfers
+    starts = [torch.from_numpy(I.psi0_instance(w, seed=[1606, i])).to(b.device, torch.complex64)
+              for i, w in enumerate(ens)]
 
     def reset():
         for i, p in enumerate(starts):
@@ -555,6 +580,8 @@ def main():
     if not args.no_extra:
         log("128x96x80 quench")
         line["real3d_128x96x80"] = quench_128x96x80(args.steps, args.warmup)
+        log("256^3 with V and the kernel table in host memory")
+        line["host_resident_256"] = host_resident_256(args.steps, args.warmup)
         log("64^3 imaginary time")
         line["imag3d_64"] = imag3d_64(args.steps)
         log("128^3 adjoint")

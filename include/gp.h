@@ -118,6 +118,27 @@ gp_status gp_init(const gp_params* params, void* dev_workspace, size_t ws_bytes,
 gp_status gp_destroy(gp_ctx* ctx);
 const char* gp_status_string(gp_status status);
 
+/* Host-resident arrays (the paper's POTMEM choice, Fig. 1 and "Summary of revisions":
+ * the potentials may stay in host memory mapped into the GPU's address space, so that
+ * larger grids fit on the device).  GP_HOST_V keeps the trap potential V, GP_HOST_KTAB
+ * the dipolar kernel table U(k)/N, in caller-owned pinned host memory (hipHostMalloc;
+ * torch's pin_memory) instead of the device workspace; the kernels read them through the
+ * host mapping at every step, over the host link.  gp_workspace_bytes_ex gives the
+ * smaller workspace; gp_host_bytes the sizes of the two host arrays (V: one real value
+ * per grid point, in the context precision; the table: its own layout).  gp_init_ex is
+ * gp_init with these flags: host_v / host_ktab must be pinned host memory (16-byte
+ * aligned) of at least those sizes when their flag is set (else GP_E_ARG), are written
+ * at init (the harmonic V, the table) and by gp_set_potential, and must stay alive and
+ * untouched by the caller until gp_destroy.  Results are bit for bit those of a context
+ * with the arrays resident. */
+#define GP_HOST_V    1u
+#define GP_HOST_KTAB 2u
+gp_status gp_workspace_bytes_ex(const gp_params* params, unsigned host, size_t* bytes);
+gp_status gp_host_bytes(const gp_params* params, size_t* v_bytes, size_t* ktab_bytes);
+gp_status gp_init_ex(const gp_params* params, unsigned host, void* dev_workspace,
+                     size_t ws_bytes, void* host_v, void* host_ktab, void* hip_stream,
+                     gp_ctx** out);
+
 /* Wave function I/O ("Summary of revisions": only the wave function returns to the
  * host, when output is written).  on_device = 0: host buffer of interleaved complex
  * double.  on_device = 1: device buffer of interleaved complex in the context precision

@@ -24,6 +24,7 @@ GP_E_STATE = -5
 GP_E_NOMEM = -6
 GP_E_IO = -7
 GP_STATE_PSI, GP_STATE_DENSITY = 1, 2
+GP_HOST_V, GP_HOST_KTAB = 1, 2
 
 GP_3D, GP_2D_XY, GP_2D_XZ = 0, 1, 2
 GP_FP64, GP_FP32_MIXED = 0, 1
@@ -114,6 +115,12 @@ _SIGS = {
     "gp_timing_enable": (ctypes.c_int, [_P, ctypes.c_uint]),
     "gp_get_params": (ctypes.c_int, [_P, ctypes.POINTER(gp_params)]),
     "gp_axis_kind": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
+    "gp_workspace_bytes_ex": (ctypes.c_int, [ctypes.POINTER(gp_params), ctypes.c_uint,
+                                             ctypes.POINTER(ctypes.c_size_t)]),
+    "gp_host_bytes": (ctypes.c_int, [ctypes.POINTER(gp_params), ctypes.POINTER(ctypes.c_size_t),
+                                     ctypes.POINTER(ctypes.c_size_t)]),
+    "gp_init_ex": (ctypes.c_int, [ctypes.POINTER(gp_params), ctypes.c_uint, _P, ctypes.c_size_t,
+                                  _P, _P, _P, ctypes.POINTER(_P)]),
     "gp_save_state": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_longlong, ctypes.c_double]),
     "gp_save_density": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_longlong, ctypes.c_double]),
     "gp_load_state": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.POINTER(gp_state_info)]),
@@ -194,6 +201,30 @@ def gp_init(params: gp_params, workspace_ptr: int, ws_bytes: int, stream_ptr: in
     ctx = _P()
     _check(load().gp_init(ctypes.byref(params), _P(workspace_ptr), ws_bytes, _P(stream_ptr),
                           ctypes.byref(ctx)), "gp_init")
+    return ctx.value
+
+
+def gp_workspace_bytes_ex(params: gp_params, host: int) -> int:
+    n = ctypes.c_size_t(0)
+    _check(load().gp_workspace_bytes_ex(ctypes.byref(params), host, ctypes.byref(n)),
+           "gp_workspace_bytes_ex")
+    return n.value
+
+
+def gp_host_bytes(params: gp_params) -> tuple:
+    v = ctypes.c_size_t(0)
+    k = ctypes.c_size_t(0)
+    _check(load().gp_host_bytes(ctypes.byref(params), ctypes.byref(v), ctypes.byref(k)),
+           "gp_host_bytes")
+    return v.value, k.value
+
+
+def gp_init_ex(params: gp_params, host: int, workspace_ptr: int, ws_bytes: int, host_v: int,
+               host_ktab: int, stream_ptr: int) -> int:
+    ctx = _P()
+    _check(load().gp_init_ex(ctypes.byref(params), host, _P(workspace_ptr), ws_bytes,
+                             _P(host_v), _P(host_ktab), _P(stream_ptr), ctypes.byref(ctx)),
+           "gp_init_ex")
     return ctx.value
 
 
@@ -381,7 +412,8 @@ class Solver:
     params: dict with the keys of `make_params` (geom, nx, ny, nz, dx, dy, dz, dt, gamma,
     nu, lam, g, gdd, R); prec: "fp64" or "fp32" (FP32 bulk, FP64 reductions)."""
 
-    def __init__(self, params: dict, prec: str = "fp64", device: str = "cuda:0", stream=None):
+    def __init__(self, params: dict, prec: str = "fp64", device: str = "cuda:0", stream=None,
+                 host=()):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -390,11 +422,24 @@ class Solver:
         self.p = make_params(**{**params, "prec": prec})
         self.shape = _shape(params)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self.ws_bytes = gp_workspace_bytes(self.p)
+        # host: "V" and/or "ktab" kept in pinned host memory (gp_init_ex)
+        flags = (GP_HOST_V if "V" in host else 0) | (GP_HOST_KTAB if "ktab" in host else 0)
+        self.host_flags = flags
+        self.ws_bytes = gp_workspace_bytes_ex(self.p, flags)
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
         base = self.ws.data_ptr()
         self._ws_ptr = (base + 255) & ~255
-        self.ctx = gp_init(self.p, self._ws_ptr, self.ws_bytes, self.stream.cuda_stream)
+        self.host_v = self.host_ktab = None
+        if flags:
+            vb, kb = gp_host_bytes(self.p)
+            if flags & GP_HOST_V:
+                self.host_v = torch.empty(vb, dtype=torch.uint8, pin_memory=True)
+            if flags & GP_HOST_KTAB:
+                self.host_ktab = torch.empty(kb, dtype=torch.uint8, pin_memory=True)
+        self.ctx = gp_init_ex(self.p, flags, self._ws_ptr, self.ws_bytes,
+                              self.host_v.data_ptr() if self.host_v is not None else 0,
+                              self.host_ktab.data_ptr() if self.host_ktab is not None else 0,
+                              self.stream.cuda_stream)
         self.cdtype = torch.complex128 if prec == "fp64" else torch.complex64
         self.rdtype = torch.float64 if prec == "fp64" else torch.float32
 
@@ -565,10 +610,20 @@ class Batch:
         return self.shapes[idx] if 0 <= idx < self.count else (1,)
 
     def set_psi(self, idx, psi):
-        a = np.ascontiguousarray(psi, dtype=np.complex128)
-        assert not 0 <= idx < self.count or a.shape == self.shapes[idx]
-        _check(load().gp_batch_set_psi(_P(self.handle), idx, _P(a.ctypes.data), 0),
+        """psi: a host array (converted from FP64), or a device tensor of the batch
+        precision (copied on the device)."""
+        if isinstance(psi, np.ndarray):
+            a = np.ascontiguousarray(psi, dtype=np.complex128)
+            assert not 0 <= idx < self.count or a.shape == self.shapes[idx]
+            _check(load().gp_batch_set_psi(_P(self.handle), idx, _P(a.ctypes.data), 0),
+                   "gp_batch_set_psi")
+            return
+        cd = self.torch.complex128 if self.prec == "fp64" else self.torch.complex64
+        t = psi.to(device=self.device, dtype=cd).contiguous()
+        assert not 0 <= idx < self.count or tuple(t.shape) == self.shapes[idx]
+        _check(load().gp_batch_set_psi(_P(self.handle), idx, _P(t.data_ptr()), 1),
                "gp_batch_set_psi")
+        self.stream.synchronize()
 
     def get_psi(self, idx):
         out = np.empty(self._shape_of(idx), dtype=np.complex128)

@@ -118,7 +118,7 @@ int tj_of(bool fp64, int n) { return fp64 ? Launch<double>::tj(n) : Launch<float
 int tc_of(bool fp64, int n) { return fp64 ? Launch<double>::tc(n) : Launch<float>::tc(n); }
 int tv_of(bool fp64, int n) { return fp64 ? Launch<double>::tv(n) : Launch<float>::tv(n); }
 
-Layout make_layout(const gp_params* p) {
+Layout make_layout(const gp_params* p, unsigned host = 0) {
   Layout L{};
   const bool fp64 = p->prec == GP_FP64;
   L.n0 = p->nx;
@@ -168,11 +168,11 @@ Layout make_layout(const gp_params* p) {
     return r;
   };
   L.o_psi = take(2 * L.esz * L.npts);
-  L.o_V = take(L.esz * L.npts);
+  L.o_V = take((host & GP_HOST_V) ? 0 : L.esz * L.npts);
   L.o_spec = take(2 * L.esz * L.nspec);
   // kernel table: 3D holds the quadrant k1 <= n1/2, k2 <= n2/2 of the half spectrum
   L.nktab = (p->geom == GP_3D) ? (size_t)H * (L.n1 / 2 + 1) * (L.n2 / 2 + 1) : L.nspec;
-  L.o_ktab = take(L.esz * L.nktab);
+  L.o_ktab = take((host & GP_HOST_KTAB) ? 0 : L.esz * L.nktab);
   const int ns[3] = {L.n0, L.n1, L.n2};
   for (int a = 0; a < 3; ++a) {
     L.o_tw[a] = take(2 * L.esz * ns[a]);
@@ -200,12 +200,19 @@ Layout make_layout(const gp_params* p) {
 }  // namespace
 
 struct gp_ctx {
-  // step loop replay: kGraphSteps steps captured once per time direction
+  // Step loops replay captured HIP graphs of 8, 4, 2 and 1 steps (a run of n steps is
+  // the binary decomposition of n, eights first), captured once per
+  // [time direction imaginary/real][start state: nothing outstanding, or a finalisation of
+  // that direction outstanding in x-partial buffer 0 / 1][length]; each records the state
+  // its steps leave behind.
   bool use_graphs = true;
   hipStream_t cap_st = nullptr;
-  // [time direction imaginary/real][x-partial buffer of the finalisation outstanding
-  // when the graph starts]
-  hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  struct GraphRec {
+    hipGraphExec_t ex = nullptr;
+    bool end_pending = false;
+    int end_sel = 0;
+  };
+  GraphRec gexec[2][3][4];
   // Steps defer their finalisation into the next step's first pass: fin_pending marks
   // one outstanding (mode pend_mode, its x partials in buffer pend_sel); px_sel is the
   // buffer the x pass writes next.
@@ -227,6 +234,10 @@ struct gp_ctx {
   double gc;
   int clock_khz = 0;  // device wall clock (kernel-span timing)
   GPlan gplan[3] = {};  // radix plans of the run-time-length passes (axes 0, 1, 2)
+  // device addresses of caller-owned pinned host memory holding V / the kernel table
+  // (gp_init_ex with GP_HOST_V / GP_HOST_KTAB), else null
+  char* hostV = nullptr;
+  char* hostK = nullptr;
   template <typename X>
   X* at(size_t off) const { return reinterpret_cast<X*>(ws + off); }
   Scalars* sc() const { return at<Scalars>(L.o_scalars); }
@@ -356,6 +367,12 @@ template <typename T>
 struct Passes {
   static cpx<T>* psi(gp_ctx* c) { return c->at<cpx<T>>(c->L.o_psi); }
   static cpx<T>* spec(gp_ctx* c) { return c->at<cpx<T>>(c->L.o_spec); }
+  // the trap potential and the kernel table: in the workspace, or in caller-owned pinned
+  // host memory read through its device mapping (gp_init_ex)
+  static T* Vp(gp_ctx* c) { return c->hostV ? reinterpret_cast<T*>(c->hostV) : c->at<T>(c->L.o_V); }
+  static T* Kp(gp_ctx* c) {
+    return c->hostK ? reinterpret_cast<T*>(c->hostK) : c->at<T>(c->L.o_ktab);
+  }
   static const cpx<T>* tw(gp_ctx* c, int a) { return c->at<cpx<T>>(c->L.o_tw[a]); }
   // factor table of axis a, set k (0: imaginary time, 1: real time, 2: adjoint sweep)
   static const cpx<T>* cn(gp_ctx* c, int a, int k) { return c->at<cpx<T>>(c->L.o_cn[a][k]); }
@@ -380,14 +397,14 @@ struct Passes {
       GP_PASS(c, GP_PASS_CONV_Z,
               GLaunch<T>::lines(GL_CONV, c->st, spec(c), L.n2, H * L.n1, L.n1,
                                 (long long)L.n1 * L.n2, 1, L.n1, c->gplan[2], tw(c, 2),
-                                c->at<T>(L.o_ktab), GKtab{1, L.n1, L.n2}, scale));
+                                Kp(c), GKtab{1, L.n1, L.n2}, scale));
       GP_PASS(c, GP_PASS_FFT_Y_INV,
               GLaunch<T>::lines(GL_INV, c->st, spec(c), L.n1, H * L.n2, 1, L.n1, 0, 1,
                                 c->gplan[1], tw(c, 1), nullptr, none, scale));
     } else {
       GP_PASS(c, GP_PASS_CONV_Y,
               GLaunch<T>::lines(GL_CONV, c->st, spec(c), L.n1, H, 1, L.n1, 0, 1, c->gplan[1],
-                                tw(c, 1), c->at<T>(L.o_ktab), GKtab{0, L.n1, 1}, scale));
+                                tw(c, 1), Kp(c), GKtab{0, L.n1, 1}, scale));
     }
     return GP_OK;
   }
@@ -432,7 +449,7 @@ struct Passes {
     GP_TRY(g_convolution(c, psi(c), &c->sc()->scale));
     GP_TRY(pass_begin(c, GP_PASS_C2R_NL_CNX));
     GP_HIP(GLaunch<T>::c2r_x(c->st, spec(c), phi, c->gplan[0], tw(c, 0), L.n0, L.n1, L.n2));
-    GP_HIP(GLaunch<T>::nonlinear(mode, c->st, psi(c), c->at<T>(L.o_V), phi, &c->sc()->scale,
+    GP_HIP(GLaunch<T>::nonlinear(mode, c->st, psi(c), Vp(c), phi, &c->sc()->scale,
                                  g_scalars(c), L.n0, L.n1, L.n2, c->at<double>(L.o_pnl)));
     GP_TRY(g_sweep(c, 0, k, 0));
     GP_TRY(pass_end(c, GP_PASS_C2R_NL_CNX));
@@ -455,7 +472,7 @@ struct Passes {
     const Layout& L = c->L;
     T* phi = c->at<T>(L.o_sfield);
     GP_TRY(g_phi(c, psi(c), &c->sc()->scale, phi));
-    GP_HIP(GLaunch<T>::nonlinear(MODE_OBSERVE, c->st, psi(c), c->at<T>(L.o_V), phi,
+    GP_HIP(GLaunch<T>::nonlinear(MODE_OBSERVE, c->st, psi(c), Vp(c), phi,
                                  &c->sc()->scale, g_scalars(c), L.n0, L.n1, L.n2,
                                  c->at<double>(L.o_pnl)));
     if (c->p.geom == GP_3D) return z_observe(c, FIN_OBSERVE);
@@ -484,13 +501,13 @@ struct Passes {
       }
       GP_PASS(c, GP_PASS_CONV_Z,
               Launch<T>::conv_col(L.n2, ((L.n1 + tc - 1) / tc) * H, c->st, spec(c),
-                                  c->at<T>(L.o_ktab), scale, tw(c, 2), L.n1));
+                                  Kp(c), scale, tw(c, 2), L.n1));
       GP_PASS(c, GP_PASS_FFT_Y_INV,
               Launch<T>::fft_line(L.n1, true, (nl + lb - 1) / lb, c->st, spec(c), tw(c, 1), nl));
     } else {
       const int lb = c->fp64 ? Launch<double>::lb(L.n1) : Launch<float>::lb(L.n1);
       GP_PASS(c, GP_PASS_CONV_Y,
-              Launch<T>::conv_line(L.n1, (H + lb - 1) / lb, c->st, spec(c), c->at<T>(L.o_ktab),
+              Launch<T>::conv_line(L.n1, (H + lb - 1) / lb, c->st, spec(c), Kp(c),
                                    scale, tw(c, 1), H));
     }
     return GP_OK;
@@ -538,7 +555,7 @@ struct Passes {
     const StepScalars sx = step_scalars(c);
     T* sf = c->at<T>(L.o_sfield);
     double* pa = c->at<double>(L.o_padj);
-    GP_HIP(Launch<T>::adj_x(L.n0, L.nb_x, c->st, lam, psin, c->at<T>(L.o_V), spec(c), tw(c, 0),
+    GP_HIP(Launch<T>::adj_x(L.n0, L.nb_x, c->st, lam, psin, Vp(c), spec(c), tw(c, 0),
                             cn(c, 0, 2), sx, sf, gradV, pa, L.n1, L.n2));
     GP_HIP(Launch<T>::r2c_real(L.n0, L.nb_x, c->st, sf, spec(c), tw(c, 0), L.n1, L.n2));
     GP_TRY(spectrum_passes(c, &c->sc()->one));
@@ -617,7 +634,7 @@ struct Passes {
       }
       c->tev[GP_PASS_C2R_NL_CNX].emplace_back(e0, e1);
     }
-    GP_HIP(Launch<T>::c2r_nl_cnx(L.n0, mode, L.nb_x, c->st, psi(c), c->at<T>(L.o_V),
+    GP_HIP(Launch<T>::c2r_nl_cnx(L.n0, mode, L.nb_x, c->st, psi(c), Vp(c),
                                  &c->sc()->scale, spec(c), tw(c, 0), cn(c, 0, k), sx,
                                  c->at<double>(L.o_pnl), nullptr, L.n1, L.n2, stamps, e0, e1));
     if (span) {
@@ -661,7 +678,7 @@ struct Passes {
                                     tw(c, 0), c->at<double>(L.o_px[c->px_sel]), L.n1, L.n2));
       case GP_PASS_C2R_NL_CNX:
         return dev(Launch<T>::c2r_nl_cnx(L.n0, MODE_REAL, L.nb_x, c->st, psi(c),
-                                         c->at<T>(L.o_V), &c->sc()->scale, spec(c), tw(c, 0),
+                                         Vp(c), &c->sc()->scale, spec(c), tw(c, 0),
                                          cn(c, 0, 1), step_scalars(c), c->at<double>(L.o_pnl),
                                          nullptr, L.n1, L.n2));
       case GP_PASS_CN_Y:
@@ -687,7 +704,7 @@ struct Passes {
     const Layout& L = c->L;
     GP_TRY(convolution(c));
     const StepScalars sx = step_scalars(c);
-    GP_HIP(Launch<T>::c2r_nl_cnx(L.n0, MODE_OBSERVE, L.nb_x, c->st, psi(c), c->at<T>(L.o_V),
+    GP_HIP(Launch<T>::c2r_nl_cnx(L.n0, MODE_OBSERVE, L.nb_x, c->st, psi(c), Vp(c),
                                  &c->sc()->scale, spec(c), tw(c, 0), nullptr, sx,
                                  c->at<double>(L.o_pnl), nullptr, L.n1, L.n2));
     if (c->p.geom == GP_3D) return z_observe(c, FIN_OBSERVE);
@@ -699,7 +716,7 @@ struct Passes {
     const Layout& L = c->L;
     GP_TRY(convolution(c));
     const StepScalars sx = step_scalars(c);
-    GP_HIP(Launch<T>::c2r_nl_cnx(L.n0, MODE_PHI, L.nb_x, c->st, psi(c), c->at<T>(L.o_V),
+    GP_HIP(Launch<T>::c2r_nl_cnx(L.n0, MODE_PHI, L.nb_x, c->st, psi(c), Vp(c),
                                  &c->sc()->scale, spec(c), tw(c, 0), nullptr, sx,
                                  c->at<double>(L.o_pnl), out, L.n1, L.n2));
     return GP_OK;
@@ -739,7 +756,7 @@ struct Passes {
     kg.R = c->p.cutoff_R;
     kg.d = (c->p.geom == GP_3D) ? 0.0 : d_perp(c->p);
     hipLaunchKernelGGL(k_kernel_table<T>, dim3(blocks_for(L.nktab)), dim3(kThreads), 0, c->st,
-                       c->at<T>(L.o_ktab), kg);
+                       Kp(c), kg);
     double w0 = c->p.gamma, w1, w2 = 0.0;
     if (c->p.geom == GP_3D) {
       w1 = c->p.nu;
@@ -750,7 +767,7 @@ struct Passes {
       w1 = c->p.lambda;
     }
     hipLaunchKernelGGL(k_harmonic<T>, dim3(blocks_for(L.npts)), dim3(kThreads), 0, c->st,
-                       c->at<T>(L.o_V), L.n0, L.n1, L.n2, L.h0, L.h1, L.h2, w0, w1, w2);
+                       Vp(c), L.n0, L.n1, L.n2, L.h0, L.h1, L.h2, w0, w1, w2);
     Scalars* s = c->sc();
     hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, c->st, &s->scale, &s->one, &s->ekz,
                        &s->flags, &s->ring_pos);
@@ -807,7 +824,7 @@ struct Passes {
   static gp_status set_potential(gp_ctx* c, const void* src, int on_device) {
     const Layout& L = c->L;
     if (on_device) {
-      GP_HIP(hipMemcpyAsync(c->at<T>(L.o_V), src, L.esz * L.npts, hipMemcpyDeviceToDevice, c->st));
+      GP_HIP(hipMemcpyAsync(Vp(c), src, L.esz * L.npts, hipMemcpyDefault, c->st));
       return GP_OK;
     }
     double* io = c->at<double>(L.o_io);
@@ -816,7 +833,7 @@ struct Passes {
       const size_t cnt = std::min(kIoChunk, L.npts - off);
       GP_HIP(hipMemcpyAsync(io, h + off, 8 * cnt, hipMemcpyHostToDevice, c->st));
       hipLaunchKernelGGL((k_real_convert<T, double>), dim3(blocks_for(cnt)), dim3(kThreads), 0,
-                         c->st, c->at<T>(L.o_V) + off, io, cnt);
+                         c->st, Vp(c) + off, io, cnt);
       GP_HIP(hipGetLastError());
     }
     GP_HIP(hipStreamSynchronize(c->st));
@@ -850,27 +867,30 @@ gp_status check_flags(gp_ctx* c) {
 }
 
 void drop_graphs(gp_ctx* c) {
-  for (auto& row : c->gexec)
-    for (auto& g : row) {
-      if (g) hipGraphExecDestroy(g);
-      g = nullptr;
-    }
+  for (auto& dir : c->gexec)
+    for (auto& st : dir)
+      for (auto& g : st) {
+        if (g.ex) hipGraphExecDestroy(g.ex);
+        g = gp_ctx::GraphRec{};
+      }
 }
 
 gp_status one_step(gp_ctx* c, bool imag) {
   return c->fp64 ? Passes<double>::step(c, imag) : Passes<float>::step(c, imag);
 }
 
-// Capture kGraphSteps steps on a private stream (the caller's stream may be the null
-// stream, which cannot be captured); the graph is launched on the caller's stream.
-gp_status build_graph(gp_ctx* c, bool imag, int sel) {
+// Capture `len` steps on a private stream (the caller's stream may be the null stream,
+// which cannot be captured); the graph is launched on the caller's stream.  Capturing
+// runs the host side of the steps, so the context's finalisation state afterwards is the
+// one the graph leaves behind; it is recorded with the graph for later replays.
+gp_status build_graph(gp_ctx* c, bool imag, int len, gp_ctx::GraphRec* rec) {
   if (!c->cap_st) GP_HIP(hipStreamCreateWithFlags(&c->cap_st, hipStreamNonBlocking));
   const hipStream_t user = c->st;
   c->st = c->cap_st;
   hipGraph_t g = nullptr;
   gp_status s = dev(hipStreamBeginCapture(c->cap_st, hipStreamCaptureModeThreadLocal));
   if (s == GP_OK) {
-    for (int i = 0; i < kGraphSteps && s == GP_OK; ++i) s = one_step(c, imag);
+    for (int i = 0; i < len && s == GP_OK; ++i) s = one_step(c, imag);
     const gp_status e = dev(hipStreamEndCapture(c->cap_st, &g));
     if (s == GP_OK) s = e;
   }
@@ -883,7 +903,9 @@ gp_status build_graph(gp_ctx* c, bool imag, int sel) {
   s = dev(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
   hipGraphDestroy(g);
   if (s != GP_OK) return s;
-  c->gexec[imag ? 0 : 1][sel] = ex;
+  rec->ex = ex;
+  rec->end_pending = c->fin_pending;
+  rec->end_sel = c->pend_sel;
   return GP_OK;
 }
 
@@ -901,22 +923,30 @@ gp_status run_steps(gp_ctx* c, int nsteps, bool imag) {
     }
     c->ekz_valid = true;
   }
-  int done = 0;
-  if (c->use_graphs && c->tmask == 0 && nsteps >= kGraphSteps) {
-    // A graph is captured and replayed from one state: a finalisation of the same time
-    // direction outstanding in x-partial buffer 0 or 1 (its graph index); the eight
-    // steps of a replay return to that state.
-    const int fmode = imag ? (int)FIN_IMAG : (int)FIN_REAL;
-    if (!(c->fin_pending && c->pend_mode == fmode)) {
-      GP_TRY(one_step(c, imag));
-      ++done;
-    }
-    hipGraphExec_t& g = c->gexec[imag ? 0 : 1][c->pend_sel];
-    if (nsteps - done >= kGraphSteps && !g) GP_TRY(build_graph(c, imag, c->pend_sel));
-    for (; nsteps - done >= kGraphSteps; done += kGraphSteps)
-      GP_HIP(hipGraphLaunch(g, c->st));
+  if (!c->use_graphs || c->tmask != 0) {
+    for (int done = 0; done < nsteps; ++done) GP_TRY(one_step(c, imag));
+    return GP_OK;
   }
-  for (; done < nsteps; ++done) GP_TRY(one_step(c, imag));
+  // a finalisation of the other time direction is completed first, so that every graph
+  // starts from nothing outstanding or from one of its own direction
+  const int fmode = imag ? (int)FIN_IMAG : (int)FIN_REAL;
+  if (c->fin_pending && c->pend_mode != fmode) GP_TRY(settle(c));
+  for (int done = 0; done < nsteps;) {
+    int li = 3;
+    while ((1 << li) > nsteps - done) --li;
+    const int start = c->fin_pending ? 1 + c->pend_sel : 0;
+    gp_ctx::GraphRec& g = c->gexec[imag ? 0 : 1][start][li];
+    if (!g.ex) {
+      GP_TRY(build_graph(c, imag, 1 << li, &g));   // leaves the host state at g's end
+    } else {
+      c->fin_pending = g.end_pending;
+      c->pend_sel = g.end_sel;
+      c->px_sel = g.end_sel;
+      c->pend_mode = fmode;
+    }
+    GP_HIP(hipGraphLaunch(g.ex, c->st));
+    done += 1 << li;
+  }
   return GP_OK;
 }
 
@@ -1314,15 +1344,48 @@ gp_status gp_workspace_bytes(const gp_params* params, size_t* bytes) {
   return GP_OK;
 }
 
-gp_status gp_init(const gp_params* params, void* dev_workspace, size_t ws_bytes, void* hip_stream,
-                  gp_ctx** out) {
-  clear_stale_error();
-  if (!out || !dev_workspace) return GP_E_ARG;
-  *out = nullptr;
+gp_status gp_workspace_bytes_ex(const gp_params* params, unsigned host, size_t* bytes) {
+  if (!bytes || (host & ~(GP_HOST_V | GP_HOST_KTAB))) return GP_E_ARG;
+  GP_TRY(validate(params));
+  *bytes = make_layout(params, host).total;
+  return GP_OK;
+}
+
+gp_status gp_host_bytes(const gp_params* params, size_t* v_bytes, size_t* ktab_bytes) {
+  if (!v_bytes || !ktab_bytes) return GP_E_ARG;
   GP_TRY(validate(params));
   const Layout L = make_layout(params);
+  *v_bytes = L.esz * L.npts;
+  *ktab_bytes = L.esz * L.nktab;
+  return GP_OK;
+}
+
+gp_status gp_init_ex(const gp_params* params, unsigned host, void* dev_workspace,
+                     size_t ws_bytes, void* host_v, void* host_ktab, void* hip_stream,
+                     gp_ctx** out) {
+  clear_stale_error();
+  if (!out || !dev_workspace || (host & ~(GP_HOST_V | GP_HOST_KTAB))) return GP_E_ARG;
+  *out = nullptr;
+  GP_TRY(validate(params));
+  const Layout L = make_layout(params, host);
   if (ws_bytes < L.total) return GP_E_ARG;
   if ((reinterpret_cast<uintptr_t>(dev_workspace) & 255) != 0) return GP_E_ARG;
+  // host-resident arrays: pinned host memory, mapped into the device's address space
+  void* maps[2] = {nullptr, nullptr};
+  void* const hp[2] = {host_v, host_ktab};
+  const unsigned fl[2] = {GP_HOST_V, GP_HOST_KTAB};
+  for (int k = 0; k < 2; ++k) {
+    if (!(host & fl[k])) continue;
+    if (!hp[k] || (reinterpret_cast<uintptr_t>(hp[k]) & 15) != 0) return GP_E_ARG;
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, hp[k]) != hipSuccess || at.type != hipMemoryTypeHost) {
+      clear_stale_error();
+      snprintf(g_last_error, sizeof(g_last_error),
+               "host array %d is not pinned host memory (hipHostMalloc)", k);
+      return GP_E_ARG;
+    }
+    GP_HIP(hipHostGetDevicePointer(&maps[k], hp[k], 0));
+  }
   gp_ctx* c = new (std::nothrow) gp_ctx();
   if (!c) return GP_E_NOMEM;
   c->p = *params;
@@ -1333,18 +1396,27 @@ gp_status gp_init(const gp_params* params, void* dev_workspace, size_t ws_bytes,
   c->psi_set = false;
   c->ekz_valid = false;
   c->gc = contact(c->p);
+  c->hostV = reinterpret_cast<char*>(maps[0]);
+  c->hostK = reinterpret_cast<char*>(maps[1]);
   int devid = 0;
   if (hipGetDevice(&devid) != hipSuccess ||
       hipDeviceGetAttribute(&c->clock_khz, hipDeviceAttributeWallClockRate, devid) != hipSuccess)
     c->clock_khz = 0;
   clear_stale_error();
-  const gp_status s = c->fp64 ? Passes<double>::init_tables(c) : Passes<float>::init_tables(c);
+  gp_status s = c->fp64 ? Passes<double>::init_tables(c) : Passes<float>::init_tables(c);
+  // the tables written through a host mapping are complete before the call returns
+  if (s == GP_OK && host) s = dev(hipStreamSynchronize(c->st));
   if (s != GP_OK) {
     delete c;
     return s;
   }
   *out = c;
   return GP_OK;
+}
+
+gp_status gp_init(const gp_params* params, void* dev_workspace, size_t ws_bytes, void* hip_stream,
+                  gp_ctx** out) {
+  return gp_init_ex(params, 0u, dev_workspace, ws_bytes, nullptr, nullptr, hip_stream, out);
 }
 
 gp_status gp_destroy(gp_ctx* ctx) {

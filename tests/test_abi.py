@@ -132,3 +132,20 @@ def test_null_arguments_rejected():
     assert lib.gp_destroy(None) == B.GP_E_ARG
     assert lib.gp_sync(None) == B.GP_E_ARG
     assert lib.gp_history_capacity() >= 1000
+
+
+def test_host_resident_arrays_shrink_the_workspace():
+    def align(n):
+        return (n + 255) // 256 * 256
+    for geom, kw in (("3d", {}), ("2dxz", dict(nx=40, ny=1, nz=48))):
+        p = B.make_params(**{**dict(geom=geom, nx=24, ny=20, nz=16, dx=0.2, dy=0.2, dz=0.2,
+                                    dt=1e-3, nu=4.0), **kw, "prec": "fp32"})
+        full = B.gp_workspace_bytes(p)
+        vb, kb = B.gp_host_bytes(p)
+        assert B.gp_workspace_bytes_ex(p, 0) == full
+        assert full - B.gp_workspace_bytes_ex(p, B.GP_HOST_V) == align(vb)
+        assert full - B.gp_workspace_bytes_ex(p, B.GP_HOST_KTAB) == align(kb)
+        assert full - B.gp_workspace_bytes_ex(p, B.GP_HOST_V | B.GP_HOST_KTAB) == align(vb) + align(kb)
+    with pytest.raises(B.GPError) as e:
+        B.gp_workspace_bytes_ex(p, 4)
+    assert e.value.status == B.GP_E_ARG
