@@ -290,6 +290,13 @@ gp_status gp_batch_energy(gp_batch* batch, gp_observables* out);
  * the default (min(items, 1024)). */
 gp_status gp_batch_plan(gp_batch* batch, int* items, int* blocks);
 gp_status gp_batch_set_blocks(gp_batch* batch, int pass, int size_class, int blocks);
+/* Tile shape of one (pass, class), for the autotuner: 0 = the default tiles; 1 = x tiles
+ * and CN column tiles of 8 lines (32 lanes per line) where the default is 16, and
+ * line-FFT blocks of twice the default points.  The work lists, the launches' LDS and the
+ * captured graphs are rebuilt (outstanding finalisations are completed first); results
+ * change only by rounding order.  gp_batch_shapes copies the 4 x 2 shapes in use. */
+gp_status gp_batch_set_shape(gp_batch* batch, int pass, int size_class, int shape);
+gp_status gp_batch_shapes(gp_batch* batch, int* shapes);
 gp_status gp_batch_use_graphs(gp_batch* batch, int enable);
 /* enable = 1: the larger size class of every pass runs on a second stream, forked from
  * and joined back to the batch stream around the pass (so the two classes overlap; a

@@ -1,9 +1,11 @@
 """Autotuner for the batched ensemble's launch plan.
 
-For every (pass, size class) of a `binding.Batch`, it times a few graph-replayed steps
-for each candidate number of persistent blocks and keeps the fastest, one coordinate at
-a time.  Results are cached in a JSON file keyed by the ensemble's size multiset,
-precision and device name, so a later run with the same ensemble reuses the plan.
+For every (pass, size class) of a `binding.Batch` it chooses the tile shape (the default
+tiles, or x and CN column tiles of 8 lines and line-FFT blocks of twice the points:
+`gp_batch_set_shape`) and the number of persistent blocks, timing a few graph-replayed
+steps for each candidate and keeping the fastest, one coordinate at a time.  Results are
+cached in a JSON file keyed by the ensemble's size multiset, precision and device name, so
+a later run with the same ensemble reuses the plan.
 """
 from __future__ import annotations
 
@@ -12,6 +14,7 @@ import json
 import os
 
 CANDIDATES = (128, 256, 384, 512, 768, 1024, 1536, 2048, 4096)
+SHAPES = (0, 1)
 
 
 def ensemble_key(batch, device_name: str) -> str:
@@ -33,9 +36,18 @@ def _time_steps(batch, steps, imag):
     return ev0.elapsed_time(ev1) / steps
 
 
+def apply(batch, plan):
+    """Set a plan {"pass:class": {"shape": s, "blocks": g}} on a batch."""
+    for name, v in plan.items():
+        p, c = name.split(":")
+        batch.set_shape(p, int(c), v["shape"])
+        batch.set_blocks(p, int(c), v["blocks"])
+
+
 def tune(batch, steps=16, imag=True, cache_path=None, verbose=False):
-    """Choose persistent block counts per (pass, size class); returns {key: blocks}.
-    The instances' wave functions must be set (tuning steps evolve them)."""
+    """Choose a tile shape and a persistent block count per (pass, size class); returns
+    {"pass:class": {"shape": s, "blocks": g}}.  The instances' wave functions must be set
+    (tuning steps evolve them)."""
     torch = batch.torch
     dev_name = torch.cuda.get_device_name(batch.device)
     key = ensemble_key(batch, dev_name)
@@ -44,30 +56,32 @@ def tune(batch, steps=16, imag=True, cache_path=None, verbose=False):
         with open(cache_path) as f:
             cache = json.load(f)
     if key in cache:
-        plan = cache[key]
-        for name, blocks in plan.items():
-            p, c = name.split(":")
-            batch.set_blocks(p, int(c), blocks)
-        return plan
+        apply(batch, cache[key])
+        return cache[key]
     best_plan = {}
     base = _time_steps(batch, steps, imag)
     for (p, c), (items, _) in batch.plan().items():
         if items == 0:
             continue
-        trials = sorted({g for g in CANDIDATES if g < items} | {items})
-        best_g, best_t = None, None
-        for g in trials:
-            batch.set_blocks(p, c, g)
-            t = _time_steps(batch, steps, imag)
-            if verbose:
-                print(f"[autotune]   {p} class {c}: {g} blocks {t:.4f} ms/step", flush=True)
-            if best_t is None or t < best_t:
-                best_g, best_t = g, t
-        batch.set_blocks(p, c, best_g)
-        best_plan[f"{p}:{c}"] = best_g
+        best = None
+        for shape in SHAPES:
+            batch.set_shape(p, c, shape)
+            n = batch.plan()[(p, c)][0]
+            for g in sorted({g for g in CANDIDATES if g < n} | {n}):
+                batch.set_blocks(p, c, g)
+                t = _time_steps(batch, steps, imag)
+                if verbose:
+                    print(f"[autotune]   {p} class {c}: shape {shape}, {g} blocks "
+                          f"{t:.4f} ms/step", flush=True)
+                if best is None or t < best[0]:
+                    best = (t, shape, g)
+        _, shape, g = best
+        batch.set_shape(p, c, shape)
+        batch.set_blocks(p, c, g)
+        best_plan[f"{p}:{c}"] = {"shape": shape, "blocks": g}
         if verbose:
-            print(f"[autotune] {p} class {c}: {items} items -> {best_g} blocks "
-                  f"({best_t:.4f} ms/step)", flush=True)
+            print(f"[autotune] {p} class {c}: shape {shape}, {g} blocks "
+                  f"({best[0]:.4f} ms/step)", flush=True)
     if verbose:
         print(f"[autotune] default {base:.4f} ms/step -> tuned "
               f"{_time_steps(batch, steps, imag):.4f} ms/step", flush=True)

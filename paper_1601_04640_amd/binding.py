@@ -107,6 +107,8 @@ _SIGS = {
     "gp_batch_plan": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "gp_batch_set_blocks": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "gp_batch_use_graphs": (ctypes.c_int, [_P, ctypes.c_int]),
+    "gp_batch_set_shape": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "gp_batch_shapes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int)]),
     "gp_step_real_adjoint": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "gp_batch_set_psi": (ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.c_int]),
     "gp_batch_get_psi": (ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.c_int]),
@@ -660,6 +662,16 @@ class Batch:
     def set_blocks(self, pass_name, size_class, blocks):
         _check(load().gp_batch_set_blocks(_P(self.handle), BATCH_PASSES.index(pass_name),
                                           size_class, blocks), "gp_batch_set_blocks")
+
+    def set_shape(self, pass_name, size_class, shape):
+        _check(load().gp_batch_set_shape(_P(self.handle), BATCH_PASSES.index(pass_name),
+                                         size_class, shape), "gp_batch_set_shape")
+
+    def tile_shapes(self):
+        k = len(BATCH_PASSES) * BATCH_CLASSES
+        out = (ctypes.c_int * k)()
+        _check(load().gp_batch_shapes(_P(self.handle), out), "gp_batch_shapes")
+        return {(BATCH_PASSES[i // BATCH_CLASSES], i % BATCH_CLASSES): out[i] for i in range(k)}
 
     def use_graphs(self, enable):
         _check(load().gp_batch_use_graphs(_P(self.handle), int(bool(enable))), "gp_batch_use_graphs")

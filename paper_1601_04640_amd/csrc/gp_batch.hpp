@@ -13,6 +13,9 @@
 
 namespace gpdbec {
 
+// Tile-shape variants per pass and size class (Tiles<T, N, S>), chosen by the autotuner.
+constexpr int kBatchShapes = 2;
+
 // Per-instance descriptor.  Arrays are byte offsets from the batch workspace base, which
 // the kernels receive as an argument: pointers formed from a kernel argument keep the
 // global address space (pointers loaded from memory would fall back to flat accesses with
@@ -51,7 +54,7 @@ __host__ __device__ constexpr int batch_class(int n) { return n > 256 ? 1 : 0; }
 // Dynamic LDS: the largest body of the pass and class present is requested at launch.
 // Every block walks items blockIdx.x + k gridDim.x of the work list.
 #define GP_BATCH_KERNEL(NAME, AXIS, BODY)                                              \
-  template <typename T, int MODE, int CLS>                                             \
+  template <typename T, int MODE, int CLS, int S>                                      \
   __global__ __launch_bounds__(kThreads) void NAME(char* __restrict__ base,             \
                                                    const BDesc<T>* __restrict__ D,     \
                                                    const WorkItem* __restrict__ work,  \
@@ -73,19 +76,19 @@ __host__ __device__ constexpr int batch_class(int n) { return n > 256 ? 1 : 0; }
 
 #define GP_BODY_R2C(N)                                                                  \
   case N:                                                                               \
-    r2c_x_body<T, N>(bptr<cpx<T>>(base, d.psi), bptr<cpx<T>>(base, d.spec),              \
+    r2c_x_body<T, N, S>(bptr<cpx<T>>(base, d.psi), bptr<cpx<T>>(base, d.spec),           \
                      bptr<cpx<T>>(base, d.tw0), bptr<double>(base, d.p_x), d.n1, 1,      \
                      item.tile, lds);                                                     \
     break;
 #define GP_BODY_CONV(N)                                                                 \
   case N:                                                                               \
-    conv_line_body<T, N>(bptr<cpx<T>>(base, d.spec), bptr<T>(base, d.ktab),              \
+    conv_line_body<T, N, S>(bptr<cpx<T>>(base, d.spec), bptr<T>(base, d.ktab),           \
                          bptr<double>(base, d.scale), bptr<cpx<T>>(base, d.tw1),         \
                          d.n0 / 2 + 1, item.tile, lds);                                  \
     break;
 #define GP_BODY_C2R(N)                                                                  \
   case N:                                                                               \
-    c2r_nl_cnx_body<T, N, MODE>(bptr<cpx<T>>(base, d.psi), bptr<T>(base, d.V),           \
+    c2r_nl_cnx_body<T, N, MODE, S>(bptr<cpx<T>>(base, d.psi), bptr<T>(base, d.V),        \
                                 bptr<double>(base, d.scale), bptr<cpx<T>>(base, d.spec), \
                                 bptr<cpx<T>>(base, d.tw0), bptr<cpx<T>>(base, d.cn0[K]), \
                                 d.sc, bptr<double>(base, d.p_nl), nullptr, d.n1, 1,      \
@@ -93,7 +96,7 @@ __host__ __device__ constexpr int batch_class(int n) { return n > 256 ? 1 : 0; }
     break;
 #define GP_BODY_CN(N)                                                                   \
   case N:                                                                               \
-    cn_col_body<T, N, MODE, true>(bptr<cpx<T>>(base, d.psi), bptr<cpx<T>>(base, d.cn1[K]), \
+    cn_col_body<T, N, MODE, true, S>(bptr<cpx<T>>(base, d.psi), bptr<cpx<T>>(base, d.cn1[K]), \
                                   bptr<double>(base, d.p_col), d.n0, (size_t)d.n0,        \
                                   (size_t)d.n0 * d.n1, item.tile, lds);                   \
     break;

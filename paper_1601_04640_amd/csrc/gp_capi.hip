@@ -179,11 +179,19 @@ Layout make_layout(const gp_params* p, unsigned host = 0) {
     // factor table and scan weights per set (imaginary time, real time, adjoint)
     for (int t = 0; t < 3; ++t) L.o_cn[a][t] = take(2 * L.esz * (ns[a] + kScanWeights));
   }
+  // Partial-sum slots: one per tile, for the largest tile count any shape variant of the
+  // batched passes can use (x and column tiles of 8 lines).
+  int cap_x = L.nb_x, cap_nl = L.nb_nl, cap_col = L.nb_col;
+  if (!L.generic) {
+    cap_x = std::max(cap_x, ((L.n1 + 7) / 8) * L.n2);
+    cap_nl = std::max(cap_nl, cap_x);
+    cap_col = std::max(cap_col, ((L.n0 + 7) / 8) * (p->geom == GP_3D ? L.n1 : L.n2));
+  }
   // two x-partial buffers: a real-time step's x pass writes one while the previous
   // step's folded finalisation reads the other
-  for (int k = 0; k < 2; ++k) L.o_px[k] = take(sizeof(double) * 2 * L.nb_x);
-  L.o_pnl = take(sizeof(double) * 7 * L.nb_nl);
-  L.o_pcol = take(sizeof(double) * 2 * L.nb_col);
+  for (int k = 0; k < 2; ++k) L.o_px[k] = take(sizeof(double) * 2 * cap_x);
+  L.o_pnl = take(sizeof(double) * 7 * cap_nl);
+  L.o_pcol = take(sizeof(double) * 2 * cap_col);
   L.o_padj = take(sizeof(double) * 2 * L.nb_x);
   L.o_sfield = take(L.esz * L.npts);
   L.o_scalars = take(sizeof(Scalars));
@@ -1074,6 +1082,11 @@ struct gp_batch {
   void* desc = nullptr;                       // device BDesc<T>[count]
   WorkItem* work[BP_COUNT][kBatchClasses] = {};
   int nwork[BP_COUNT][kBatchClasses] = {};
+  // tile-shape variant per (pass, class) (Tiles<T, N, S>) and the persistent block count
+  // asked for (0: the default, min(items, 1024))
+  int shape[BP_COUNT][kBatchClasses] = {};
+  int grid_req[BP_COUNT][kBatchClasses] = {};
+  WorkItem* work_base = nullptr;  // device work-list region (per-(pass, class) capacities)
   size_t lds[BP_COUNT][kBatchClasses][3] = {};  // [pass][class][mode imag/real/observe]
   int grid[BP_COUNT][kBatchClasses] = {};
   bool use_graphs = true;
@@ -1115,23 +1128,41 @@ struct BatchLayout {
   int total_items;
 };
 
+// The class (size class of the pass's line length) and work items of instance (n0, n1)
+// in pass p with shape variant sh.
+int batch_pass_class(int p, int n0, int n1) {
+  return batch_class((p == BP_R2C || p == BP_C2R) ? n0 : n1);
+}
 template <typename T>
-int batch_items(const gp_params* arr, int count) {
-  int tot = 0;
+int batch_item_cap(int p, int n0, int n1) {
+  int m = 0;
+  for (int sh = 0; sh < kBatchShapes; ++sh) m = std::max(m, batch_tiles<T>(p, n0, n1, sh));
+  return m;
+}
+
+// Work-list capacity per (pass, class): every instance's largest tile count over the
+// shape variants, so a variant change rebuilds a list in place.
+template <typename T>
+void batch_caps(const gp_params* arr, int count, int cap[BP_COUNT][kBatchClasses]) {
+  for (int p = 0; p < BP_COUNT; ++p)
+    for (int k = 0; k < kBatchClasses; ++k) cap[p][k] = 0;
   for (int i = 0; i < count; ++i) {
-    const int n1 = arr[i].geom == GP_2D_XY ? arr[i].ny : arr[i].nz;
-    int nbx, nbc, nbcol;
-    batch_tiles<T>(arr[i].nx, n1, &nbx, &nbc, &nbcol);
-    tot += 2 * nbx + nbc + nbcol;
+    const int n0 = arr[i].nx, n1 = arr[i].geom == GP_2D_XY ? arr[i].ny : arr[i].nz;
+    for (int p = 0; p < BP_COUNT; ++p)
+      cap[p][batch_pass_class(p, n0, n1)] += batch_item_cap<T>(p, n0, n1);
   }
-  return tot;
 }
 
 BatchLayout batch_layout(const gp_params* arr, int count) {
   BatchLayout B{};
   const bool fp64 = arr[0].prec == GP_FP64;
   const size_t dsz = fp64 ? sizeof(BDesc<double>) : sizeof(BDesc<float>);
-  B.total_items = fp64 ? batch_items<double>(arr, count) : batch_items<float>(arr, count);
+  int cap[BP_COUNT][kBatchClasses];
+  if (fp64) batch_caps<double>(arr, count, cap);
+  else batch_caps<float>(arr, count, cap);
+  B.total_items = 0;
+  for (int p = 0; p < BP_COUNT; ++p)
+    for (int k = 0; k < kBatchClasses; ++k) B.total_items += cap[p][k];
   size_t o = 0;
   B.o_desc = o;
   o += align_up(dsz * count);
@@ -1183,6 +1214,12 @@ gp_status batch_write_desc(gp_batch* b) {
     d.n1 = L.n1;
     d.fa = fin_args(c, 0);
     d.fa.nstage = 0;  // the per-instance finalize blocks read their partials directly
+    // partial sums written by the batch passes: one slot per tile of the shape in use
+    // (the instance workspace holds slots for the largest tile count of any shape)
+    const int cx = batch_class(L.n0), cy = batch_class(L.n1);
+    d.fa.nb_x = batch_tiles<T>(BP_R2C, L.n0, L.n1, b->shape[BP_R2C][cx]);
+    d.fa.nb_nl = batch_tiles<T>(BP_C2R, L.n0, L.n1, b->shape[BP_C2R][cx]);
+    d.fa.nb_col = batch_tiles<T>(BP_CN, L.n0, L.n1, b->shape[BP_CN][cy]);
     b->cpl[2 * i] = c->p.g;
     b->cpl[2 * i + 1] = c->p.gdd;
   }
@@ -1191,55 +1228,56 @@ gp_status batch_write_desc(gp_batch* b) {
   return dev(hipStreamSynchronize(b->st));
 }
 
+// Work lists per (pass, class) for the current shape variants (instances by decreasing
+// size, then their tiles), the dynamic LDS of each launch, and the descriptors.  Called
+// at set-up and after a shape change, never inside a capture.
 template <typename T>
-gp_status batch_build(gp_batch* b, const BatchLayout& BL) {
+gp_status batch_build(gp_batch* b) {
   GP_TRY(batch_write_desc<T>(b));
   std::vector<int> n0(b->count), n1(b->count);
   for (int i = 0; i < b->count; ++i) {
     n0[i] = b->inst[i]->L.n0;
     n1[i] = b->inst[i]->L.n1;
   }
-  // work lists per (pass, class): instances by decreasing size, then their tiles
   std::vector<int> order(b->count);
   for (int i = 0; i < b->count; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
     return (size_t)n0[x] * n1[x] > (size_t)n0[y] * n1[y];
   });
   std::vector<WorkItem> lists[BP_COUNT][kBatchClasses];
+  for (int p = 0; p < BP_COUNT; ++p)
+    for (int k = 0; k < kBatchClasses; ++k)
+      for (int m = 0; m < 3; ++m) b->lds[p][k][m] = 0;
+  const int modes[3] = {MODE_IMAG, MODE_REAL, MODE_OBSERVE};
   for (int i : order) {
-    int nbx, nbc, nbcol;
-    batch_tiles<T>(n0[i], n1[i], &nbx, &nbc, &nbcol);
-    const int c0 = batch_class(n0[i]), c1 = batch_class(n1[i]);
-    for (int t = 0; t < nbx; ++t) lists[BP_R2C][c0].push_back({i, t});
-    for (int t = 0; t < nbc; ++t) lists[BP_CONV][c1].push_back({i, t});
-    for (int t = 0; t < nbx; ++t) lists[BP_C2R][c0].push_back({i, t});
-    for (int t = 0; t < nbcol; ++t) lists[BP_CN][c1].push_back({i, t});
-    const int modes[3] = {MODE_IMAG, MODE_REAL, MODE_OBSERVE};
-    for (int m = 0; m < 3; ++m) {
-      size_t* L0 = b->lds[BP_R2C][c0];
-      L0[m] = std::max(L0[m], batch_lds<T>(BP_R2C, n0[i], modes[m]));
-      size_t* L1 = b->lds[BP_CONV][c1];
-      L1[m] = std::max(L1[m], batch_lds<T>(BP_CONV, n1[i], modes[m]));
-      size_t* L2 = b->lds[BP_C2R][c0];
-      L2[m] = std::max(L2[m], batch_lds<T>(BP_C2R, n0[i], modes[m]));
-      size_t* L3 = b->lds[BP_CN][c1];
-      L3[m] = std::max(L3[m], batch_lds<T>(BP_CN, n1[i], modes[m]));
+    for (int p = 0; p < BP_COUNT; ++p) {
+      const int k = batch_pass_class(p, n0[i], n1[i]);
+      const int sh = b->shape[p][k];
+      const int nt = batch_tiles<T>(p, n0[i], n1[i], sh);
+      for (int t = 0; t < nt; ++t) lists[p][k].push_back({i, t});
+      const int n = (p == BP_R2C || p == BP_C2R) ? n0[i] : n1[i];
+      for (int m = 0; m < 3; ++m)
+        b->lds[p][k][m] = std::max(b->lds[p][k][m], batch_lds<T>(p, n, modes[m], sh));
     }
   }
-  WorkItem* dev_work = reinterpret_cast<WorkItem*>(b->ws + BL.o_work);
+  int cap[BP_COUNT][kBatchClasses];
+  batch_caps<T>(b->params.data(), b->count, cap);
   size_t off = 0;
   for (int p = 0; p < BP_COUNT; ++p) {
     for (int k = 0; k < kBatchClasses; ++k) {
-      b->work[p][k] = dev_work + off;
+      if ((int)lists[p][k].size() > cap[p][k]) return GP_E_ARG;  // cannot happen
+      b->work[p][k] = b->work_base + off;
       b->nwork[p][k] = (int)lists[p][k].size();
-      b->grid[p][k] = std::min(b->nwork[p][k], kBatchDefaultGrid);
+      const int req = b->grid_req[p][k];
+      b->grid[p][k] = std::min(b->nwork[p][k], req > 0 ? req : kBatchDefaultGrid);
       if (!lists[p][k].empty())
-        GP_HIP(hipMemcpyAsync(dev_work + off, lists[p][k].data(),
+        GP_HIP(hipMemcpyAsync(b->work[p][k], lists[p][k].data(),
                               sizeof(WorkItem) * lists[p][k].size(), hipMemcpyHostToDevice,
                               b->st));
-      off += lists[p][k].size();
+      off += cap[p][k];
       for (int m = 0; m < 3; ++m)
-        if (b->lds[p][k][m] > 0) GP_HIP(batch_reserve_lds<T>(p, m, k, b->lds[p][k][m]));
+        if (b->lds[p][k][m] > 0)
+          GP_HIP(batch_reserve_lds<T>(p, m, k, b->shape[p][k], b->lds[p][k][m]));
     }
   }
   GP_HIP(hipStreamSynchronize(b->st));
@@ -1263,8 +1301,8 @@ gp_status batch_step(gp_batch* b, hipStream_t st, bool imag) {
     }
     for (int k = 0; k < kBatchClasses; ++k) {
       const hipStream_t sk = (two && k == 1) ? b->side : st;
-      GP_HIP(batch_launch<T>(p, mode, k, b->grid[p][k], b->lds[p][k][mi], sk, b->ws, D,
-                             b->work[p][k], b->nwork[p][k]));
+      GP_HIP(batch_launch<T>(p, mode, k, b->shape[p][k], b->grid[p][k], b->lds[p][k][mi], sk,
+                             b->ws, D, b->work[p][k], b->nwork[p][k]));
     }
     if (two) {
       GP_HIP(hipEventRecord(b->ev_join, b->side));
@@ -1716,7 +1754,8 @@ gp_status gp_batch_init(const gp_params* params, int count, void* dev_workspace,
     s = gp_init(&params[i], b->ws + BL.o_inst[i], make_layout(&params[i]).total, hip_stream, &c);
     if (s == GP_OK) b->inst.push_back(c);
   }
-  if (s == GP_OK) s = b->fp64 ? batch_build<double>(b, BL) : batch_build<float>(b, BL);
+  b->work_base = reinterpret_cast<WorkItem*>(b->ws + BL.o_work);
+  if (s == GP_OK) s = b->fp64 ? batch_build<double>(b) : batch_build<float>(b);
   if (s == GP_OK) s = dev(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
   if (s == GP_OK) s = dev(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
   if (s == GP_OK) s = dev(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
@@ -1770,8 +1809,30 @@ gp_status gp_batch_set_blocks(gp_batch* b, int pass, int size_class, int blocks)
   if (!b || pass < 0 || pass >= BP_COUNT || size_class < 0 || size_class >= kBatchClasses)
     return GP_E_ARG;
   const int n = b->nwork[pass][size_class];
+  b->grid_req[pass][size_class] = blocks <= 0 ? 0 : blocks;
   b->grid[pass][size_class] = blocks <= 0 ? std::min(n, kBatchDefaultGrid) : std::min(blocks, n);
   batch_drop_graphs(b);  // the grid sizes are captured launch parameters
+  return GP_OK;
+}
+
+gp_status gp_batch_set_shape(gp_batch* b, int pass, int size_class, int shape) {
+  if (!b || pass < 0 || pass >= BP_COUNT || size_class < 0 || size_class >= kBatchClasses ||
+      shape < 0 || shape >= kBatchShapes)
+    return GP_E_ARG;
+  clear_stale_error();
+  if (b->shape[pass][size_class] == shape) return GP_OK;
+  // the batch's partial sums of the previous shape must be consumed first
+  for (gp_ctx* c : b->inst) GP_TRY(settle(c));
+  GP_HIP(hipStreamSynchronize(b->st));
+  b->shape[pass][size_class] = shape;
+  batch_drop_graphs(b);
+  return b->fp64 ? batch_build<double>(b) : batch_build<float>(b);
+}
+
+gp_status gp_batch_shapes(gp_batch* b, int* shapes) {
+  if (!b || !shapes) return GP_E_ARG;
+  for (int p = 0; p < BP_COUNT; ++p)
+    for (int k = 0; k < kBatchClasses; ++k) shapes[p * kBatchClasses + k] = b->shape[p][k];
   return GP_OK;
 }
 

@@ -51,22 +51,33 @@ namespace gpdbec {
 #define GP_TV_SPLIT_BYTES 65536
 #endif
 
-template <typename T, int N>
+// S selects a tile-shape variant (the batched ensemble's autotuner chooses per pass and
+// size class; the single-grid passes use S = 0):
+//   S = 1: x tiles and CN column tiles of 8 lines (32 lanes per line) where the default
+//          is 16, and line-FFT blocks of twice the default points.
+// A variant only ever goes from 16 to 32 lanes per line: 32-lane solves compose the scan
+// gains on the fly, so the factor table (whose gains are stored for the default lane
+// count) serves both.
+template <typename T, int N, int S = 0>
 struct Tiles {
   // x lines per tile (even): 16, or 8 from GP_TJ_SPLIT_N points on (32 lanes per line:
   // half the serial chunk of the CN solve, twice the tiles)
-  static constexpr int TJ = (N >= GP_TJ_SPLIT_N) ? 8 : 16;
+  static constexpr int TJ0 = (N >= GP_TJ_SPLIT_N) ? 8 : 16;
+  static constexpr int TJ = S == 1 ? 8 : TJ0;
   static constexpr int PX = kThreads / TJ;          // lanes per x line in the CN solve
   // columns per tile: 16, or 8 (32 lanes per line) when the 16-lane chunk would exceed
   // GP_TC_SPLIT_* elements
-  static constexpr int TC =
+  static constexpr int TC0 =
       ((N + 15) / 16 > (sizeof(T) == 8 ? GP_TC_SPLIT_FP64 : GP_TC_SPLIT_FP32)) ? 8 : 16;
+  static constexpr int TC = S == 1 ? 8 : TC0;
   static constexpr int PC = kThreads / TC;
   // columns per tile of the z convolution: 16, or 8 when a 16-column tile would take more
   // than GP_TV_SPLIT_BYTES of LDS (more resident blocks per CU)
   static constexpr int TV = ((size_t)N * 17 * 2 * sizeof(T) > (size_t)GP_TV_SPLIT_BYTES) ? 8 : 16;
   // contiguous lines per block of the line FFT passes
-  static constexpr int LB = (GP_LB_POINTS / N) < 1 ? 1 : (GP_LB_POINTS / N);
+  static constexpr int LB0 = (GP_LB_POINTS / N) < 1 ? 1 : (GP_LB_POINTS / N);
+  static constexpr int LB = S == 1 ? ((2 * GP_LB_POINTS / N) < 1 ? 1 : (2 * GP_LB_POINTS / N))
+                                   : LB0;
   // lines per block of the y FFT pass: 16 for FP32 lines of 16 x 16 points (one 16-point
   // stage in registers on each side of a single LDS exchange), else LB
   static constexpr bool FFT16 = (N == 256 && sizeof(T) == 4);
@@ -143,10 +154,10 @@ struct alignas(2 * sizeof(cpx<T>)) cpx2 {
 };
 
 // Geometry of an x-line tile (TJ lines of N0 points; NP packed complex pairs).
-template <typename T, int N0>
+template <typename T, int N0, int S = 0>
 struct XT {
-  static constexpr int TJ = Tiles<T, N0>::TJ, NP = TJ / 2, H = N0 / 2 + 1, LSZ = N0 + 1;
-  static constexpr int PX = Tiles<T, N0>::PX, SX = (N0 + PX - 1) / PX;
+  static constexpr int TJ = Tiles<T, N0, S>::TJ, NP = TJ / 2, H = N0 / 2 + 1, LSZ = N0 + 1;
+  static constexpr int PX = Tiles<T, N0, S>::PX, SX = (N0 + PX - 1) / PX;
   static constexpr int LSP = N0 + (N0 + SX - 1) / SX;  // chunk-padded line for CN
   static constexpr size_t C = sizeof(cpx<T>);
   static constexpr size_t Z = a16(NP * LSZ * C), W = a16(N0 * C), PS = a16(TJ * LSP * C),
@@ -157,9 +168,9 @@ struct XT {
 };
 
 // Geometry of a strided-column CN tile (TC columns of N points).
-template <typename T, int N>
+template <typename T, int N, int S = 0>
 struct CT {
-  static constexpr int TC = Tiles<T, N>::TC, PC = Tiles<T, N>::PC, SC = (N + PC - 1) / PC;
+  static constexpr int TC = Tiles<T, N, S>::TC, PC = Tiles<T, N, S>::PC, SC = (N + PC - 1) / PC;
   static constexpr int RS = TC + 1, NR = N + (N + SC - 1) / SC;  // padded rows
   static constexpr size_t C = sizeof(cpx<T>);
   static constexpr size_t B = a16(NR * RS * C), MT = a16(cn_table_len<N, PC>() * C),
@@ -169,11 +180,12 @@ struct CT {
 // -------------------------------------------------------------------- LDS sizes
 enum : int { P_R2C = 0, P_R2C_REAL, P_FFT_LINE, P_CONV_LINE, P_CONV_COL, P_C2R_STEP, P_C2R_OBS,
              P_CN_COL, P_ADJ_X, P_ADJ_FIN };
-template <typename T, int N, int PASS>
+template <typename T, int N, int PASS, int S = 0>
 constexpr size_t lds_bytes() {
-  using X = XT<T, N>;
+  using X = XT<T, N, S>;
+  using G = CT<T, N, S>;
   constexpr size_t C = sizeof(cpx<T>);
-  constexpr int LB = Tiles<T, N>::LB, TC = Tiles<T, N>::TC;
+  constexpr int LB = Tiles<T, N, S>::LB, TC = Tiles<T, N, S>::TC;
   if (PASS == P_R2C) return X::Z + X::W + X::RED;
   if (PASS == P_R2C_REAL) return X::Z + X::W;
   if (PASS == P_FFT_LINE)
@@ -184,7 +196,7 @@ constexpr size_t lds_bytes() {
   if (PASS == P_C2R_STEP) return X::mx(X::mx(X::Z, X::PS), X::RED8) + X::W + X::MT;
   if (PASS == P_ADJ_X) return X::Z + X::PS + X::W + X::MT + X::RED;
   if (PASS == P_C2R_OBS) return X::mx(X::Z, X::RED8) + X::W;
-  if (PASS == P_CN_COL) return CT<T, N>::B + CT<T, N>::MT + CT<T, N>::RED;
+  if (PASS == P_CN_COL) return G::B + G::MT + G::RED;
   if (PASS == P_ADJ_FIN) return X::Z + X::W;
   return 0;
 }
@@ -194,13 +206,13 @@ constexpr size_t lds_bytes() {
 // tiles: ceil(n1/TJ) * n2.  Spectrum of the stored |psi|^2 (unscaled: the convolution
 // applies scale^2).  partials[bid*2 + {0,1}] = sum |dx psi|^2, sum |dy psi|^2 of the
 // stored psi (unscaled), the y difference reaching one line past the tile.
-template <typename T, int N0>
+template <typename T, int N0, int S = 0>
 __device__ __forceinline__ void r2c_x_body(const cpx<T>* __restrict__ psi,
                                            cpx<T>* __restrict__ spec,
                                            const cpx<T>* __restrict__ tw0,
                                            double* __restrict__ partials, int n1, int n2, int bid,
                                            char* lds) {
-  using X = XT<T, N0>;
+  using X = XT<T, N0, S>;
   constexpr int TJ = X::TJ, NP = X::NP, H = X::H, LSZ = X::LSZ;
   using IT = Iters<TJ * N0>;
   Carve cv{lds};
@@ -439,13 +451,13 @@ __device__ __forceinline__ void fft_line_body(cpx<T>* __restrict__ data,
 }
 
 // FFT -> multiply by the kernel table -> inverse FFT of contiguous lines (2D: y lines).
-template <typename T, int N>
+template <typename T, int N, int S = 0>
 __device__ __forceinline__ void conv_line_body(cpx<T>* __restrict__ data,
                                                const T* __restrict__ ktab,
                                                const double* __restrict__ scale,
                                                const cpx<T>* __restrict__ tw, int nlines, int bid,
                                                char* lds) {
-  constexpr int LB = Tiles<T, N>::LB, LSZ = N + 1;
+  constexpr int LB = Tiles<T, N, S>::LB, LSZ = N + 1;
   using IT = Iters<LB * N>;
   Carve cv{lds};
   cpx<T>* B = cv.take<cpx<T>>(LB * LSZ);
@@ -642,13 +654,13 @@ __device__ __forceinline__ T tile_real(const cpx<T>* Z, int LSZ, int jl, int i) 
 // MODE_OBSERVE: sums only.  MODE_PHI: writes Phi (without g_dd) to phi_out.
 // partials[bid*7 + ...] = sum n, sum V n, sum n^2, sum Phi n, sum x^2 n, sum y^2 n,
 // sum z^2 n of the incoming (scaled) state; axis coordinates (idx - n/2) h.
-template <typename T, int N0, int MODE>
+template <typename T, int N0, int MODE, int S = 0>
 __device__ __forceinline__ void c2r_nl_cnx_body(
     cpx<T>* __restrict__ psi, const T* __restrict__ V, const double* __restrict__ scale,
     const cpx<T>* __restrict__ spec, const cpx<T>* __restrict__ tw0,
     const cpx<T>* __restrict__ cnm, const StepScalars& sc, double* __restrict__ partials,
     T* __restrict__ phi_out, int n1, int n2, int bid, char* lds) {
-  using X = XT<T, N0>;
+  using X = XT<T, N0, S>;
   constexpr int TJ = X::TJ, NP = X::NP, LSZ = X::LSZ, PX = X::PX, SX = X::SX, LSP = X::LSP;
   constexpr bool STEP = (MODE == MODE_IMAG || MODE == MODE_REAL);
   constexpr bool NEEDPSI = (MODE != MODE_PHI);
@@ -781,12 +793,12 @@ __device__ __forceinline__ void c2r_nl_cnx_body(
 // SUMS: also partials[bid*2+{0,1}] = sum |u|^2, sum |u_{i+1}-u_i|^2 along the line of
 // the result (MODE_OBSERVE: of the stored input, nothing written; sums unscaled).
 // tiles: ceil(n0/TC) * n_outer.
-template <typename T, int N, int MODE, bool SUMS>
+template <typename T, int N, int MODE, bool SUMS, int S = 0>
 __device__ __forceinline__ void cn_col_body(cpx<T>* __restrict__ psi,
                                             const cpx<T>* __restrict__ cnm,
                                             double* __restrict__ partials, int n0,
                                             size_t estride, size_t ostride, int bid, char* lds) {
-  using G = CT<T, N>;
+  using G = CT<T, N, S>;
   constexpr int TC = G::TC, PC = G::PC, SC = G::SC, RS = G::RS;
   constexpr bool SOLVE = (MODE == MODE_IMAG || MODE == MODE_REAL || MODE == MODE_ADJ);
   using IT = Iters<N * TC>;

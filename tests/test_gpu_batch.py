@@ -127,18 +127,62 @@ def test_autotuner_keeps_results(tmp_path, gpu_lib):
     b.step_imag(8)
     ref = [b.get_psi(i) for i in range(len(ens))]
     plan = autotune.tune(b, steps=8, cache_path=str(tmp_path / "tune.json"))
-    assert plan and all(v >= 1 for v in plan.values())
+    assert plan and all(v["blocks"] >= 1 and v["shape"] in (0, 1) for v in plan.values())
     assert (tmp_path / "tune.json").exists()
     b.close()
-    # a different launch plan gives bitwise the same results
+    # the cached plan is applied as it was chosen; block counts change only which block
+    # runs a tile, so with the default shapes the results are bitwise those of the default
+    # plan, and with the tuned shapes they stay at the FP32 bars against the oracle
     b2 = Batch(ens, prec="fp32")
     autotune.tune(b2, steps=8, cache_path=str(tmp_path / "tune.json"))  # cached plan
+    assert {f"{p}:{c}": v for (p, c), v in b2.tile_shapes().items()
+            if f"{p}:{c}" in plan} == {k: v["shape"] for k, v in plan.items()}
+    for i, w in enumerate(ens):
+        b2.set_psi(i, start(w, i))
+    b2.step_imag(8)
+    for i, w in enumerate(ens):
+        assert_psi_close(b2.get_psi(i), O.run(start(w, i), oparams(w), True, 8),
+                         FP32_PSI_TOL, i)
+    for (p, c) in b2.tile_shapes():
+        b2.set_shape(p, c, 0)
     for i, w in enumerate(ens):
         b2.set_psi(i, start(w, i))
     b2.step_imag(8)
     for i in range(len(ens)):
         assert np.array_equal(b2.get_psi(i), ref[i])
     b2.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_tile_shapes_match_oracle(prec, gpu_lib):
+    """Every pass and class with the alternative tile shape (8-line x and column tiles,
+    twice the line-FFT block), imaginary and real time, against the oracle; the energies
+    and per-instance records through the batch finalisation."""
+    from paper_1601_04640_amd.binding import Batch
+    ens = small_ensemble(count=6, seed=83)
+    ens[1] = dict(ens[1], nx=384)            # a class-1 x axis
+    banner("batch tile shapes", prec)
+    b = Batch(ens, prec=prec)
+    for (p, c) in b.tile_shapes():
+        b.set_shape(p, c, 1)
+    assert set(b.tile_shapes().values()) == {1}
+    for i, w in enumerate(ens):
+        b.set_psi(i, start(w, i))
+    b.step_imag(9)
+    b.step_real(7)
+    tol = FP64_PSI_TOL if prec == "fp64" else FP32_PSI_TOL
+    etol = FP64_E_TOL if prec == "fp64" else FP32_E_TOL
+    energies = b.energy()
+    for i, w in enumerate(ens):
+        p = oparams(w)
+        ref = O.run(O.run(start(w, i), p, True, 9), p, False, 7)
+        assert_psi_close(b.get_psi(i), ref, tol, i)
+        assert not obs_close(energies[i], O.observables(ref, p), etol), i
+        # the record of the state the last step started from, reduced by the batch
+        rec = b.history(i, 16)[-1]
+        prev = O.run(O.run(start(w, i), p, True, 9), p, False, 6)
+        assert not obs_close(rec, O.observables(prev, p), etol), i
+    b.close()
 
 
 def test_batch_rejects_bad_params(gpu_lib):
