@@ -5,6 +5,9 @@ Run modes (each is one small program to put after `rocprofv3 ... --`):
   python3 paper_1601_04640_amd/profile_run.py steps W PREC N
       N direct-launch (no graph) real-time steps of workload W (a key of inputs.WORKLOADS)
       in precision PREC (fp32 / fp64) from its seeded Gaussian start.
+  python3 paper_1601_04640_amd/profile_run.py grid GEOM N PREC STEPS
+      STEPS direct-launch real-time steps of the grid-size sweep's N^3 cube (GEOM 3d) or
+      N^2 square (2dxy), any supported length.
   python3 paper_1601_04640_amd/profile_run.py batch N
       N imaginary-time steps of the 192-instance quasi-2D ensemble (FP32), direct launches.
   python3 paper_1601_04640_amd/profile_run.py copy MIB
@@ -63,6 +66,30 @@ def run_steps(workload, prec, n):
     s.set_psi(psi0)
     print(f"[profile] {workload} {prec}: {n} steps", flush=True)
     s.step_real(n)
+    s.sync()
+    s.close()
+
+
+def run_grid(geom, n, prec, steps):
+    """Real-time steps of the grid-size sweep's n^3 cube or n^2 square (trap (1,1,2),
+    g 20, g_dd 6, box 12.8), launched pass by pass."""
+    sys.path.insert(0, ROOT)
+    import numpy as np
+    from paper_1601_04640_amd.binding import Solver
+    h = 12.8 / n
+    w = dict(geom=geom, nx=n, ny=n, nz=n if geom == "3d" else 1, dx=h, dy=h, dz=h,
+             dt=0.0005, gamma=1.0, nu=1.0, lam=2.0 if geom == "3d" else 4.0, g=20.0,
+             gdd=6.0, R=6.4 if geom == "3d" else 0.0)
+    s = Solver(w, prec=prec)
+    s.use_graphs(False)
+    x = (np.arange(n) - n // 2) * h
+    g1 = np.exp(-0.5 * x * x)
+    g1[0] = g1[-1] = 0.0
+    psi = (g1[:, None, None] * g1[None, :, None] * g1[None, None, :] if geom == "3d"
+           else g1[:, None] * g1[None, :]).astype(np.complex128)
+    s.set_psi(psi / np.sqrt(np.sum(np.abs(psi) ** 2) * h ** psi.ndim))
+    print(f"[profile] {geom} {n} {prec}: {steps} steps", flush=True)
+    s.step_real(steps)
     s.sync()
     s.close()
 
@@ -166,6 +193,8 @@ def main(argv):
     mode = argv[0]
     if mode == "steps":
         run_steps(argv[1], argv[2], int(argv[3]))
+    elif mode == "grid":
+        run_grid(argv[1], int(argv[2]), argv[3], int(argv[4]))
     elif mode == "batch":
         run_batch(int(argv[1]))
     elif mode == "copy":
