@@ -146,9 +146,10 @@ Layout make_layout(const gp_params* p, unsigned host = 0) {
                            : GLaunch<float>::cn_blocks(L.n2, L.n0 * L.n1, true))
                    : (fp64 ? GLaunch<double>::cn_blocks(L.n1, L.n0, true)
                            : GLaunch<float>::cn_blocks(L.n1, L.n0, true));
-    // scratch of the one-thread-per-line sweeps (3D grids whose y or z sweep has many lines)
-    L.gscr = p->geom == GP_3D && (L.n0 * L.n2 >= GLaunch<float>::kColLines ||
-                                  L.n0 * L.n1 >= GLaunch<float>::kColLines);
+    // scratch of the one-thread-per-line sweeps (3D grids whose y or z sweep has many
+    // lines longer than a tile)
+    L.gscr = p->geom == GP_3D && (GLaunch<float>::cn_by_columns(L.n1, true, L.n0 * L.n2) ||
+                                  GLaunch<float>::cn_by_columns(L.n2, true, L.n0 * L.n1));
   } else {
     const int tj = tj_of(fp64, L.n0);
     L.nb_x = ((L.n1 + tj - 1) / tj) * L.n2;
@@ -388,15 +389,15 @@ struct Passes {
   // ------------------------------------------- run-time-length passes (gp_generic.hpp)
   // The same step as the specialised passes, in simpler launches: the x R2C, the y FFT,
   // the z convolution and the inverse y FFT (2D: the y convolution), the x C2R into a
-  // real Phi grid, the phase written x-major, the x sweep on the transposed state, the
-  // transpose back, then the y and z sweeps; the finalisation runs after every step.
+  // real Phi grid, the phase in place, then the x, y and z sweeps; the finalisation runs
+  // after every step.
   static gp_status g_convolution(gp_ctx* c, const cpx<T>* src, const double* scale) {
     const Layout& L = c->L;
     const int H = L.n0 / 2 + 1;
     GP_PASS(c, GP_PASS_R2C_X,
             GLaunch<T>::r2c_x(c->st, src, spec(c), c->gplan[0], tw(c, 0),
                               c->at<double>(L.o_px[0]), L.n0, L.n1, L.n2));
-    const GKtab none{0, L.n1, L.n2};
+    const GKtab none{0, L.n1, L.n2, fdiv_make((uint32_t)L.n1)};
     if (c->p.geom == GP_3D) {
       // y lines l = kx n2 + k2 (contiguous); z lines l = kx n1 + k1 (stride n1)
       GP_PASS(c, GP_PASS_FFT_Y_FWD,
@@ -405,20 +406,22 @@ struct Passes {
       GP_PASS(c, GP_PASS_CONV_Z,
               GLaunch<T>::lines(GL_CONV, c->st, spec(c), L.n2, H * L.n1, L.n1,
                                 (long long)L.n1 * L.n2, 1, L.n1, c->gplan[2], tw(c, 2),
-                                Kp(c), GKtab{1, L.n1, L.n2}, scale));
+                                Kp(c), GKtab{1, L.n1, L.n2, fdiv_make((uint32_t)L.n1)}, scale));
       GP_PASS(c, GP_PASS_FFT_Y_INV,
               GLaunch<T>::lines(GL_INV, c->st, spec(c), L.n1, H * L.n2, 1, L.n1, 0, 1,
                                 c->gplan[1], tw(c, 1), nullptr, none, scale));
     } else {
       GP_PASS(c, GP_PASS_CONV_Y,
               GLaunch<T>::lines(GL_CONV, c->st, spec(c), L.n1, H, 1, L.n1, 0, 1, c->gplan[1],
-                                tw(c, 1), Kp(c), GKtab{0, L.n1, 1}, scale));
+                                tw(c, 1), Kp(c), GKtab{0, L.n1, 1, fdiv_make((uint32_t)L.n1)},
+                                scale));
     }
     return GP_OK;
   }
 
   static GStep g_scalars(gp_ctx* c) {
-    return GStep{c->p.dt, c->gc, c->p.gdd, c->L.h0, c->L.h1, c->L.h2};
+    return GStep{c->p.dt, c->gc, c->p.gdd, c->L.h0, c->L.h1, c->L.h2,
+                 fdiv_make((uint32_t)c->L.n0), fdiv_make((uint32_t)c->L.n1)};
   }
 
   // Phi of src into phi (the convolution, then the x C2R)
@@ -457,9 +460,17 @@ struct Passes {
     GP_TRY(g_convolution(c, psi(c), &c->sc()->scale));
     GP_TRY(pass_begin(c, GP_PASS_C2R_NL_CNX));
     GP_HIP(GLaunch<T>::c2r_x(c->st, spec(c), phi, c->gplan[0], tw(c, 0), L.n0, L.n1, L.n2));
-    GP_HIP(GLaunch<T>::nonlinear(mode, c->st, psi(c), Vp(c), phi, &c->sc()->scale,
-                                 g_scalars(c), L.n0, L.n1, L.n2, c->at<double>(L.o_pnl)));
-    GP_TRY(g_sweep(c, 0, k, 0));
+    if (GLaunch<T>::x_fused(L.n0)) {
+      // the nonlinear sub-step rides in the x sweep's loads
+      const GNl nlz{Vp(c), phi, &c->sc()->scale, g_scalars(c), L.n0, L.n1, L.n2,
+                    c->at<double>(L.o_pnl)};
+      GP_HIP(GLaunch<T>::cn_x_nonlinear(mode, c->st, psi(c), L.n0, L.n1 * L.n2, cn(c, 0, k),
+                                        nlz));
+    } else {
+      GP_HIP(GLaunch<T>::nonlinear(mode, c->st, psi(c), Vp(c), phi, &c->sc()->scale,
+                                   g_scalars(c), L.n0, L.n1, L.n2, c->at<double>(L.o_pnl)));
+      GP_TRY(g_sweep(c, 0, k, 0));
+    }
     GP_TRY(pass_end(c, GP_PASS_C2R_NL_CNX));
     if (c->p.geom == GP_3D) {
       GP_TRY(pass_begin(c, GP_PASS_CN_Y));

@@ -23,6 +23,7 @@
 // The partial sums have the meaning the FP64 finalisation reads (gp_finalize.hpp).
 #pragma once
 #include "gp_device.hpp"
+#include "gp_fdiv.hpp"
 #include "gp_kernels.hpp"  // pass modes
 
 namespace gpdbec {
@@ -54,12 +55,19 @@ __device__ __forceinline__ void gblock_sum(double (&v)[NV], double* red) {
   }
 }
 constexpr int kGenMaxPrime = 31;
+// Copy loops between global memory and LDS move kGenU values per thread per round, all
+// loads issued before the first is used, so a block waits on one memory latency per
+// round rather than one per value.
+constexpr int kGenU = 8;
 
-// Radices of an N-point FFT: factors 8, 4, 2, then the odd primes up to 31.
+// Radices of an N-point FFT: factors 8, 4, 2, then the odd primes up to 31; per stage
+// the divisors of its butterfly indexing (N / R butterflies per line, L = the product of
+// the earlier radices).
 struct GPlan {
   int n;
   int nst;
   int rad[kGenMaxStages];
+  FDiv nb[kGenMaxStages], l[kGenMaxStages];
 };
 
 __host__ __device__ inline bool gen_plan(int n, GPlan* p) {
@@ -67,10 +75,14 @@ __host__ __device__ inline bool gen_plan(int n, GPlan* p) {
   p->nst = 0;
   int m = n;
   const int order[] = {8, 4, 2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31};
+  int L = 1;
   for (int r : order) {
     while (m % r == 0) {
       if (p->nst >= kGenMaxStages) return false;
+      p->nb[p->nst] = fdiv_make((uint32_t)(n / r));
+      p->l[p->nst] = fdiv_make((uint32_t)L);
       p->rad[p->nst++] = r;
+      L *= r;
       m /= r;
     }
   }
@@ -106,7 +118,7 @@ __device__ __forceinline__ cpx<T> twid(const cpx<T>* __restrict__ tw, long long 
 // output is written (all threads, across a barrier), so the stage runs in place.
 // Each thread holds at most QM butterflies: NL*N/R <= QM*blockDim.
 template <typename T, int R, bool INV, int QM>
-__device__ __forceinline__ void gstage(cpx<T>* buf, int NL, int N, int L,
+__device__ __forceinline__ void gstage(cpx<T>* buf, int NL, int N, int L, FDiv fnb, FDiv fl,
                                        const cpx<T>* __restrict__ tw) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int NB = N / R;
@@ -118,12 +130,15 @@ __device__ __forceinline__ void gstage(cpx<T>* buf, int NL, int N, int L,
     for (int k = 0; k < R; ++k) w[k] = twid<T, INV>(tw, (long long)k * (N / R));
   }
   cpx<T> v[QM][R];
+  int dst[QM];
 #pragma unroll
   for (int q = 0; q < QM; ++q) {
     const int b = tid + q * nt;
+    dst[q] = -1;
     if (b < tot) {
-      const int line = b / NB, i = b - line * NB;
-      const int k = i % L;
+      const int line = (int)fdiv((uint32_t)b, fnb), i = b - line * NB;
+      const int hi = (int)fdiv((uint32_t)i, fl), k = i - hi * L;
+      dst[q] = line * N + hi * L * R + k;
       cpx<T>* x = buf + (size_t)line * N;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q][r] = x[i + r * NB];
@@ -141,11 +156,8 @@ __device__ __forceinline__ void gstage(cpx<T>* buf, int NL, int N, int L,
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < QM; ++q) {
-    const int b = tid + q * nt;
-    if (b < tot) {
-      const int line = b / NB, i = b - line * NB;
-      const int k = i % L;
-      cpx<T>* y = buf + (size_t)line * N + (i / L) * L * R + k;
+    if (dst[q] >= 0) {
+      cpx<T>* y = buf + dst[q];
 #pragma unroll
       for (int r = 0; r < R; ++r) y[r * L] = v[q][r];
     }
@@ -165,13 +177,14 @@ __device__ inline void gfft(cpx<T>* buf, int NL, const GPlan& p, const cpx<T>* _
     switch (R) {
 #define GSTAGE(RR)                                                   \
   case RR:                                                           \
-    gstage<T, RR, INV, (EMAX + RR - 1) / RR>(buf, NL, p.n, L, tw);   \
+    gstage<T, RR, INV, (EMAX + RR - 1) / RR>(buf, NL, p.n, L, p.nb[s], p.l[s], tw); \
     break;
       GSTAGE(2) GSTAGE(3) GSTAGE(4) GSTAGE(5) GSTAGE(7) GSTAGE(8)
 #undef GSTAGE
 #define GSTAGE(RR)                                                               \
   case RR:                                                                       \
-    if constexpr (!SMALL) gstage<T, RR, INV, (EMAX + RR - 1) / RR>(buf, NL, p.n, L, tw); \
+    if constexpr (!SMALL)                                                        \
+      gstage<T, RR, INV, (EMAX + RR - 1) / RR>(buf, NL, p.n, L, p.nb[s], p.l[s], tw); \
     break;
       GSTAGE(11) GSTAGE(13) GSTAGE(17) GSTAGE(19) GSTAGE(23) GSTAGE(29) GSTAGE(31)
 #undef GSTAGE
@@ -189,13 +202,25 @@ __host__ __device__ inline bool gen_plan_small(const GPlan& p) {
   return true;
 }
 
-// Line l, element e of a strided batch: (l / G) so + (l mod G) si + e se.
+// Line l, element e of a strided batch: (l / G) so + (l mod G) si + e se.  fn, fnl, fg:
+// divisors by n, nl and G.
 struct GLines {
   int n, nlines, nl;   // line length, lines, lines per block
   int G;
   long long so, si, se;
+  FDiv fn, fnl, fg;
   __device__ __forceinline__ long long addr(int l, int e) const {
-    return (long long)(l / G) * so + (long long)(l % G) * si + (long long)e * se;
+    const int hi = (int)fdiv((uint32_t)l, fg);
+    return (long long)hi * so + (long long)(l - hi * G) * si + (long long)e * se;
+  }
+  // element t of a block's tile of nl lines as (line, element): line-major when the lines
+  // are contiguous, element-major when strided, so that consecutive threads touch
+  // consecutive addresses (value selects: no pointer into registers)
+  __device__ __forceinline__ int2 tile_index(int t) const {
+    const bool c = se == 1;
+    const int q = (int)fdiv((uint32_t)t, c ? fn : fnl);
+    const int r = t - q * (c ? n : nl);
+    return c ? make_int2(q, r) : make_int2(r, q);
   }
 };
 
@@ -205,9 +230,10 @@ struct GLines {
 //   2D:      lines along axis 1, l = kx, e = k1; ktab[kx n1 + k1]
 struct GKtab {
   int q3, n1, n2;
+  FDiv fn1;
   __device__ __forceinline__ long long index(int l, int e) const {
     if (q3) {
-      const int kx = l / n1, k1 = l - kx * n1;
+      const int kx = (int)fdiv((uint32_t)l, fn1), k1 = l - kx * n1;
       const int m1 = k1 <= n1 - k1 ? k1 : n1 - k1;
       const int m2 = e <= n2 - e ? e : n2 - e;
       return ((long long)kx * (n2 / 2 + 1) + m2) * (n1 / 2 + 1) + m1;
@@ -230,41 +256,69 @@ __global__ void __launch_bounds__(kGenThreads) kg_lines(cpx<T>* __restrict__ dat
   const int l0 = blockIdx.x * g.nl;
   const int nl = min(g.nl, g.nlines - l0);
   const int N = g.n;
-  const int tot = nl * N;
-  const bool contig = g.se == 1;
-  for (int t = threadIdx.x; t < tot; t += blockDim.x) {
-    const int line = contig ? t / N : t % nl;
-    const int e = contig ? t - line * N : t / nl;
-    buf[line * N + e] = data[g.addr(l0 + line, e)];
+  const int nt = blockDim.x;
+  const int tot = g.nl * N;  // the full tile's indexing; lines past nl are skipped
+  for (int t0 = threadIdx.x; t0 < tot; t0 += kGenU * nt) {
+    T vr[kGenU], vi[kGenU];  // separate parts: arrays of the aligned pair type stay in memory
+    int at[kGenU];
+#pragma unroll
+    for (int u = 0; u < kGenU; ++u) {
+      const int t = t0 + u * nt;
+      const int2 le = g.tile_index(t);
+      const int line = le.x, e = le.y;
+      at[u] = (t < tot && line < nl) ? line * N + e : -1;
+      if (at[u] >= 0) {
+        const cpx<T> v = data[g.addr(l0 + line, e)];
+        vr[u] = v.re;
+        vi[u] = v.im;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kGenU; ++u)
+      if (at[u] >= 0) buf[at[u]] = cpx<T>{vr[u], vi[u]};
   }
   __syncthreads();
   if constexpr (KIND == GL_CONV) {
     gfft<T, false, EMAX, SMALL>(buf, nl, p, tw);
     const double s = *scale;
     const T s2 = (T)(s * s);
-    for (int t = threadIdx.x; t < tot; t += blockDim.x) {
-      const int line = t / N, e = t - line * N;
-      buf[t] = scl(buf[t], ktab[km.index(l0 + line, e)] * s2);
+    const int totl = nl * N;
+    for (int t0 = threadIdx.x; t0 < totl; t0 += kGenU * nt) {
+      T kv[kGenU];
+#pragma unroll
+      for (int u = 0; u < kGenU; ++u) {
+        const int t = t0 + u * nt;
+        if (t < totl) {
+          const int line = (int)fdiv((uint32_t)t, g.fn), e = t - line * N;
+          kv[u] = ktab[km.index(l0 + line, e)];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kGenU; ++u) {
+        const int t = t0 + u * nt;
+        if (t < totl) buf[t] = scl(buf[t], kv[u] * s2);
+      }
     }
     __syncthreads();
     gfft<T, true, EMAX, SMALL>(buf, nl, p, tw);
   } else {
     gfft<T, KIND == GL_INV, EMAX, SMALL>(buf, nl, p, tw);
   }
-  for (int t = threadIdx.x; t < tot; t += blockDim.x) {
-    const int line = contig ? t / N : t % nl;
-    const int e = contig ? t - line * N : t / nl;
-    data[g.addr(l0 + line, e)] = buf[line * N + e];
+  for (int t = threadIdx.x; t < tot; t += nt) {
+    const int2 le = g.tile_index(t);
+    if (le.x < nl) data[g.addr(l0 + le.x, le.y)] = buf[le.x * N + le.y];
   }
 }
 
 // Grid of the x passes: block b covers the line pairs (j, j+1), j = j0, j0 + 2, ...,
 // j0 + 2 np - 2 (j0 = 2 np (b mod nbj)) of the plane k = b / nbj.  Spectrum layout
-// spec[(kx n2 + k) n1 + j], kx = 0..n0/2.
+// spec[(kx n2 + k) n1 + j], kx = 0..n0/2.  fn0, fnp, f2np, fnbj: divisors by n0, np, 2 np
+// and nbj.
 struct GXTile {
   int n0, n1, n2, np, nbj;
+  FDiv fn0, fnp, f2np, fnbj;
   __device__ __forceinline__ void locate(int b, int* k, int* j0, int* npairs) const {
-    *k = b / nbj;
+    *k = (int)fdiv((uint32_t)b, fnbj);
     *j0 = 2 * np * (b - *k * nbj);
     const int left = (n1 - *j0) / 2;
     *npairs = left < np ? left : np;
@@ -280,30 +334,62 @@ __global__ void __launch_bounds__(kGenThreads) kg_r2c_x(const cpx<T>* __restrict
                                                      cpx<T>* __restrict__ spec, GXTile xt,
                                                      GPlan p, const cpx<T>* __restrict__ tw,
                                                      double* __restrict__ part) {
+  // five loads per value: fewer values per round than the plain copy loops
+  constexpr int U = sizeof(T) == 4 ? 4 : 2;
   extern __shared__ __align__(16) char lds_raw[];
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lds_raw);
   int k, j0, npairs;
   xt.locate(blockIdx.x, &k, &j0, &npairs);
   const int N = xt.n0, n1 = xt.n1;
+  const int nt = blockDim.x;
   const int tot = npairs * N;
   double dx = 0.0, dy = 0.0;  // reduced at the end, through the same LDS
-  for (int t = threadIdx.x; t < tot; t += blockDim.x) {
-    const int q = t / N, i = t - q * N;
-    const int j = j0 + 2 * q;
-    const long long a = ((long long)k * n1 + j) * N + i;
-    const cpx<T> u = psi[a], v = psi[a + N];
-    buf[q * N + i] = cpx<T>{u.re * u.re + u.im * u.im, v.re * v.re + v.im * v.im};
-    if (i + 1 < N) dx += absdiff2_d(psi[a + 1], u) + absdiff2_d(psi[a + N + 1], v);
-    dy += absdiff2_d(v, u);
-    if (j + 2 < n1) dy += absdiff2_d(psi[a + 2 * N], v);
+  for (int t0 = threadIdx.x; t0 < tot; t0 += U * nt) {
+    // |psi|^2 needs the two values; the differences their x and axis-1 neighbours
+    T n0v[U], n1v[U];
+    double ddx[U], ddy[U];
+    int jj[U];
+    cpx<T> a0[U], a1[U], b0[U], b1[U], c1[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * nt;
+      const int q = (int)fdiv((uint32_t)t, xt.fn0);
+      const int i = t - q * N;
+      jj[u] = t < tot ? j0 + 2 * q : -1;
+      // loads from in-range addresses only, selected afterwards (a select between a
+      // load and a constant would be turned into a load through a stack slot)
+      const bool ok = jj[u] >= 0;
+      const long long a = ok ? ((long long)k * n1 + j0 + 2 * q) * N + i : 0;
+      a0[u] = psi[a];
+      a1[u] = psi[a + N];
+      b0[u] = psi[ok && i + 1 < N ? a + 1 : a];
+      b1[u] = psi[ok && i + 1 < N ? a + N + 1 : a + N];
+      c1[u] = psi[ok && jj[u] + 2 < n1 ? a + 2 * N : a + N];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      n0v[u] = a0[u].re * a0[u].re + a0[u].im * a0[u].im;
+      n1v[u] = a1[u].re * a1[u].re + a1[u].im * a1[u].im;
+      ddx[u] = absdiff2_d(b0[u], a0[u]) + absdiff2_d(b1[u], a1[u]);
+      ddy[u] = absdiff2_d(a1[u], a0[u]) + absdiff2_d(c1[u], a1[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (jj[u] >= 0) {
+        buf[t0 + u * nt] = cpx<T>{n0v[u], n1v[u]};
+        dx += ddx[u];
+        dy += ddy[u];
+      }
+    }
   }
   __syncthreads();
   gfft<T, false, EMAX, SMALL>(buf, npairs, p, tw);
   const int H = N / 2 + 1;
-  const int tot2 = H * 2 * npairs;
-  for (int t = threadIdx.x; t < tot2; t += blockDim.x) {
-    const int kx = t / (2 * npairs), r = t - kx * 2 * npairs;
+  const int tot2 = H * 2 * xt.np;  // the full tile's indexing; pairs past npairs skipped
+  for (int t = threadIdx.x; t < tot2; t += nt) {
+    const int kx = (int)fdiv((uint32_t)t, xt.f2np), r = t - kx * 2 * xt.np;
     const int q = r >> 1, which = r & 1;
+    if (q >= npairs) continue;
     const cpx<T> zk = buf[q * N + kx];
     const cpx<T> zm = buf[q * N + (kx == 0 ? 0 : N - kx)];
     cpx<T> o;
@@ -329,25 +415,45 @@ template <typename T, int EMAX, bool SMALL>
 __global__ void __launch_bounds__(kGenThreads) kg_c2r_x(const cpx<T>* __restrict__ spec,
                                                      T* __restrict__ phi, GXTile xt, GPlan p,
                                                      const cpx<T>* __restrict__ tw) {
+  constexpr int U = kGenU / 2;  // two loads per value
   extern __shared__ __align__(16) char lds_raw[];
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lds_raw);
   int k, j0, npairs;
   xt.locate(blockIdx.x, &k, &j0, &npairs);
   const int N = xt.n0, n1 = xt.n1;
   const int H = N / 2 + 1;
-  const int tot = H * npairs;
-  for (int t = threadIdx.x; t < tot; t += blockDim.x) {
-    const int kx = t / npairs, q = t - kx * npairs;
-    const long long a = ((long long)kx * xt.n2 + k) * n1 + j0 + 2 * q;
-    const cpx<T> A = spec[a], B = spec[a + 1];
-    buf[q * N + kx] = cpx<T>{A.re - B.im, A.im + B.re};
-    if (kx > 0 && kx < N - kx) buf[q * N + N - kx] = cpx<T>{A.re + B.im, B.re - A.im};
+  const int nt = blockDim.x;
+  const int tot = H * xt.np;  // the full tile's indexing; pairs past npairs skipped
+  for (int t0 = threadIdx.x; t0 < tot; t0 += U * nt) {
+    cpx<T> A[U], B[U];
+    int kk[U], qq[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * nt;
+      kk[u] = (int)fdiv((uint32_t)t, xt.fnp);
+      qq[u] = t - kk[u] * xt.np;
+      if (t >= tot || qq[u] >= npairs) qq[u] = -1;
+      // in-range addresses only (see kg_r2c_x)
+      const long long a =
+          qq[u] >= 0 ? ((long long)kk[u] * xt.n2 + k) * n1 + j0 + 2 * qq[u] : 0;
+      A[u] = spec[a];
+      B[u] = spec[a + 1];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (qq[u] >= 0) {
+        const int kx = kk[u], q = qq[u];
+        buf[q * N + kx] = cpx<T>{A[u].re - B[u].im, A[u].im + B[u].re};
+        if (kx > 0 && kx < N - kx)
+          buf[q * N + N - kx] = cpx<T>{A[u].re + B[u].im, B[u].re - A[u].im};
+      }
+    }
   }
   __syncthreads();
   gfft<T, true, EMAX, SMALL>(buf, npairs, p, tw);
   const int tot2 = npairs * N;
-  for (int t = threadIdx.x; t < tot2; t += blockDim.x) {
-    const int q = t / N, i = t - q * N;
+  for (int t = threadIdx.x; t < tot2; t += nt) {
+    const int q = (int)fdiv((uint32_t)t, xt.fn0), i = t - q * N;
     const long long a = ((long long)k * n1 + j0 + 2 * q) * N + i;
     const cpx<T> z = buf[t];
     phi[a] = z.re;
@@ -355,8 +461,10 @@ __global__ void __launch_bounds__(kGenThreads) kg_c2r_x(const cpx<T>* __restrict
   }
 }
 
+// Step scalars of the nonlinear pass; f0, f1: divisors by n0 and n1.
 struct GStep {
   double dt, gc, gdd, h0, h1, h2;
+  FDiv f0, f1;
 };
 
 // Blocks of the nonlinear pass: a fixed count (each walks its share of the grid), so the
@@ -369,6 +477,8 @@ __host__ __device__ inline int gen_nl_blocks(long long npts) {
 // Nonlinear sub-step in place: psi <- scale psi exp(-eps dt (V + g_c n + g_dd Phi)),
 // eps = 1 (MODE_IMAG) or i (MODE_REAL); MODE_OBSERVE only sums.  part[7 b ...]: sum n,
 // V n, n^2, Phi n, x^2 n, a1^2 n, a2^2 n of the physical incoming state (scale psi).
+// Each thread walks its points kThreads apart, U at a time with their loads in flight;
+// the point's row r = a / n0 and column i advance by the divisor of n0.
 template <typename T, int MODE>
 __global__ void __launch_bounds__(kThreads) kg_nonlinear(cpx<T>* __restrict__ psi,
                                                          const T* __restrict__ V,
@@ -376,6 +486,7 @@ __global__ void __launch_bounds__(kThreads) kg_nonlinear(cpx<T>* __restrict__ ps
                                                          const double* __restrict__ scale,
                                                          GStep sc, int n0, int n1, int n2,
                                                          double* __restrict__ part) {
+  constexpr int U = 4;
   __shared__ double red[7 * kWaves];
   const long long npts = (long long)n0 * n1 * n2;
   const long long per = (npts + gridDim.x - 1) / gridDim.x;
@@ -383,33 +494,64 @@ __global__ void __launch_bounds__(kThreads) kg_nonlinear(cpx<T>* __restrict__ ps
   const long long hi = lo + per < npts ? lo + per : npts;
   const T ts = (T)(*scale);
   double ps[7] = {0, 0, 0, 0, 0, 0, 0};
-  for (long long a = lo + threadIdx.x; a < hi; a += kThreads) {
-    const int i = (int)(a % n0);
-    const long long r = a / n0;
-    const int j = (int)(r % n1), k = (int)(r / n1);
-    const cpx<T> pv = scl(psi[a], ts);
-    const T v = V[a], ph = phi[a];
-    const T n = pv.re * pv.re + pv.im * pv.im;
-    const double nd = (double)n;
-    const double x = (i - n0 / 2) * sc.h0, y = (j - n1 / 2) * sc.h1, z = (k - n2 / 2) * sc.h2;
-    ps[0] += nd;
-    ps[1] += (double)v * nd;
-    ps[2] += nd * nd;
-    ps[3] += (double)ph * nd;
-    ps[4] += x * x * nd;
-    ps[5] += y * y * nd;
-    ps[6] += z * z * nd;
-    if constexpr (MODE == MODE_IMAG || MODE == MODE_REAL) {
-      const T th = (T)sc.dt * (v + (T)sc.gc * n + (T)sc.gdd * ph);
-      cpx<T> f;
-      if constexpr (MODE == MODE_IMAG) {
-        f = cpx<T>{exp(-th), (T)0};
-      } else {
-        T sn, cs;
-        sincos_phase(th, sn, cs);
-        f = cpx<T>{cs, -sn};
+  long long a = lo + threadIdx.x;
+  // row and column of a (a < 2^31 n0: one 64-bit division per thread)
+  uint32_t r = 0;
+  int i = 0;
+  if (a < hi) {
+    r = (uint32_t)(a / n0);
+    i = (int)(a - (long long)r * n0);
+  }
+  for (; a < hi; a += U * kThreads) {
+    cpx<T> pv[U];
+    T vv[U], ph[U];
+    int ii[U];
+    uint32_t rr[U];
+    bool ok[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long au = a + (long long)u * kThreads;
+      ok[u] = au < hi;
+      ii[u] = i;
+      rr[u] = r;
+      const long long as = ok[u] ? au : lo;  // in-range addresses only (see kg_r2c_x)
+      pv[u] = psi[as];
+      vv[u] = V[as];
+      ph[u] = phi[as];
+      i += kThreads;
+      const uint32_t dq = fdiv((uint32_t)i, sc.f0);
+      r += dq;
+      i -= (int)dq * n0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (!ok[u]) continue;
+      const int k = (int)fdiv(rr[u], sc.f1), j = (int)rr[u] - k * n1;
+      const cpx<T> p = scl(pv[u], ts);
+      const T v = vv[u];
+      const T n = p.re * p.re + p.im * p.im;
+      const double nd = (double)n;
+      const double x = (ii[u] - n0 / 2) * sc.h0, y = (j - n1 / 2) * sc.h1,
+                   z = (k - n2 / 2) * sc.h2;
+      ps[0] += nd;
+      ps[1] += (double)v * nd;
+      ps[2] += nd * nd;
+      ps[3] += (double)ph[u] * nd;
+      ps[4] += x * x * nd;
+      ps[5] += y * y * nd;
+      ps[6] += z * z * nd;
+      if constexpr (MODE == MODE_IMAG || MODE == MODE_REAL) {
+        const T th = (T)sc.dt * (v + (T)sc.gc * n + (T)sc.gdd * ph[u]);
+        cpx<T> f;
+        if constexpr (MODE == MODE_IMAG) {
+          f = cpx<T>{exp(-th), (T)0};
+        } else {
+          T sn, cs;
+          sincos_phase(th, sn, cs);
+          f = cpx<T>{cs, -sn};
+        }
+        psi[a + (long long)u * kThreads] = p * f;
       }
-      psi[a] = pv * f;
     }
   }
   block_sum<7>(ps, red);
@@ -439,46 +581,81 @@ __device__ __forceinline__ cpx<T> shfl_down_c(cpx<T> v, int off) {
 // joined by a scan of the affine maps c -> (prod g) c + (local result) across the wave;
 // each lane then adds its carry times the running product of g.  The result equals the
 // sequential recurrence up to rounding order.
+// LDS layout of a line: lane q's rows sit at [q Sp, q Sp + S) with Sp = S | 1 (odd), so
+// the 64 lanes reading the j-th rows of their chunks touch distinct bank pairs; a line
+// takes ceil(N/S) Sp values (cn_line_slots; lanes past the last chunk own none), psi and
+// d one buffer each.
 // MODE 0: solve; 1: solve, then part[2b] = sum |u|^2, part[2b+1] = sum |u_(i+1) - u_i|^2
 // of the new state; 2: those sums of the stored state, no solve.
+__host__ __device__ inline int cn_line_slots(int n) {
+  const int S = (n + 63) / 64;
+  return ((n + S - 1) / S) * (S | 1);
+}
+
 template <typename T, int MODE>
 __global__ void __launch_bounds__(kThreads) kg_cn_lines(cpx<T>* __restrict__ data, GLines g,
+                                                        FDiv fs,
                                                         const cpx<T>* __restrict__ f,
                                                         double* __restrict__ part) {
   extern __shared__ __align__(16) char lds_raw[];
   const int N = g.n;
+  const int S = (N + 63) / 64, Sp = S | 1, LS = cn_line_slots(N);
   const int l0 = blockIdx.x * g.nl;
   const int nl = min(g.nl, g.nlines - l0);
-  const int tot = nl * N;
-  cpx<T>* ps = reinterpret_cast<cpx<T>*>(lds_raw);        // nl lines of psi (then u)
-  cpx<T>* dv = ps + (size_t)g.nl * N;                      // nl lines of d
-  const bool contig = g.se == 1;
-  for (int t = threadIdx.x; t < tot; t += kThreads) {
-    const int line = contig ? t / N : t % nl;
-    const int e = contig ? t - line * N : t / nl;
-    ps[line * N + e] = data[g.addr(l0 + line, e)];
+  const int tot = g.nl * N;  // the full tile's indexing; lines past nl are skipped
+  cpx<T>* ps = reinterpret_cast<cpx<T>*>(lds_raw);   // nl lines of psi (then u)
+  cpx<T>* dv = ps + (size_t)g.nl * LS;                // nl lines of d
+  for (int t0 = threadIdx.x; t0 < tot; t0 += kGenU * kThreads) {
+    T vr[kGenU], vi[kGenU];
+    int at[kGenU];
+#pragma unroll
+    for (int u = 0; u < kGenU; ++u) {
+      const int t = t0 + u * kThreads;
+      const int2 le = g.tile_index(t);
+      const int line = le.x, e = le.y;
+      const int c = (int)fdiv((uint32_t)e, fs);
+      at[u] = (t < tot && line < nl) ? line * LS + c * Sp + (e - c * S) : -1;
+      if (at[u] >= 0) {
+        const cpx<T> v = data[g.addr(l0 + line, e)];
+        vr[u] = v.re;
+        vi[u] = v.im;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kGenU; ++u)
+      if (at[u] >= 0) ps[at[u]] = cpx<T>{vr[u], vi[u]};
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int S = (N + 63) / 64;
   const int i0 = lane * S;
-  const int i1 = min(i0 + S, N);
+  const int cnt = min(S, N - i0);  // rows of this lane's chunk (<= 0: none)
+  const int slot = cnt > 0 ? lane * Sp : 0;  // lanes with no chunk point at the line start
+  const cpx<T> zero{0, 0};
   double s0 = 0.0, s1 = 0.0;
   if constexpr (MODE != 2) {
     for (int line = wave; line < nl; line += kWaves) {
-      cpx<T>* p = ps + line * N;
-      cpx<T>* d = dv + line * N;
+      cpx<T>* p = ps + line * LS + slot;
+      cpx<T>* d = dv + line * LS + slot;
       // forward, zero carry: local d and the chunk's product of g
-      cpx<T> acc = {0, 0}, prod = {1, 0};
-      for (int i = i0; i < i1; ++i) {
+      cpx<T> acc = zero, prod = {1, 0};
+      // row i0 - 1 (the previous lane's last slot) and row i0; the loads stay inside the
+      // block's LDS and the selects act on values
+      cpx<T> pm = p[lane > 0 && cnt > 0 ? -Sp + S - 1 : 0];
+      if (!(i0 > 0 && cnt > 0)) pm = zero;
+      cpx<T> pc = p[0];
+#pragma unroll 4
+      for (int j = 0; j < cnt; ++j) {
+        const int i = i0 + j;
+        // the next row: this chunk's, or the next lane's first (row N is none: zero)
+        cpx<T> pn = p[j + 1 < cnt ? j + 1 : Sp];
+        if (i + 1 >= N) pn = zero;
         const cpx<T> fi = f[i];
         const cpx<T> gi = scl(fi, (T)0.5);
-        const cpx<T> pm = i > 0 ? p[i - 1] : cpx<T>{0, 0};
-        const cpx<T> pn = i + 1 < N ? p[i + 1] : cpx<T>{0, 0};
-        const cpx<T> pc = p[i];
         acc = fi * ((pm + pn) - (pc + pc)) + gi * acc;
         prod = gi * prod;
-        d[i] = acc;
+        d[j] = acc;
+        pm = pc;
+        pc = pn;
       }
       // inclusive scan of the maps c -> prod c + acc over the lanes
       cpx<T> P = prod, B = acc;
@@ -490,16 +667,18 @@ __global__ void __launch_bounds__(kThreads) kg_cn_lines(cpx<T>* __restrict__ dat
         }
       }
       cpx<T> carry = shfl_up_c(B, 1);   // d at the end of the previous chunk
-      if (lane == 0) carry = cpx<T>{0, 0};
-      for (int i = i0; i < i1; ++i) {
-        carry = scl(f[i], (T)0.5) * carry;
-        d[i] = d[i] + carry;
+      if (lane == 0) carry = zero;
+#pragma unroll 4
+      for (int j = 0; j < cnt; ++j) {
+        carry = scl(f[i0 + j], (T)0.5) * carry;
+        d[j] = d[j] + carry;
       }
       // backward, zero carry from the right: local e (kept in d)
-      acc = cpx<T>{0, 0};
-      for (int i = i1 - 1; i >= i0; --i) {
-        acc = d[i] + scl(f[i], (T)0.5) * acc;
-        d[i] = acc;
+      acc = zero;
+#pragma unroll 4
+      for (int j = cnt - 1; j >= 0; --j) {
+        acc = d[j] + scl(f[i0 + j], (T)0.5) * acc;
+        d[j] = acc;
       }
       P = prod;
       B = acc;
@@ -511,20 +690,23 @@ __global__ void __launch_bounds__(kThreads) kg_cn_lines(cpx<T>* __restrict__ dat
         }
       }
       carry = shfl_down_c(B, 1);         // e at the start of the next chunk
-      if (lane == 63) carry = cpx<T>{0, 0};
-      for (int i = i1 - 1; i >= i0; --i) {
-        carry = scl(f[i], (T)0.5) * carry;
-        p[i] = p[i] + (d[i] + carry);
+      if (lane == 63) carry = zero;
+#pragma unroll 4
+      for (int j = cnt - 1; j >= 0; --j) {
+        carry = scl(f[i0 + j], (T)0.5) * carry;
+        p[j] = p[j] + (d[j] + carry);
       }
     }
     __syncthreads();
   }
   if constexpr (MODE != 0) {
     for (int line = wave; line < nl; line += kWaves) {
-      const cpx<T>* p = ps + line * N;
-      for (int i = i0; i < i1; ++i) {
-        s0 += abs2_d(p[i]);
-        if (i + 1 < N) s1 += absdiff2_d(p[i + 1], p[i]);
+      const cpx<T>* p = ps + line * LS + slot;
+      for (int j = 0; j < cnt; ++j) {
+        const cpx<T> pc = p[j];
+        s0 += abs2_d(pc);
+        const cpx<T> pn = p[j + 1 < cnt ? j + 1 : Sp];
+        if (i0 + j + 1 < N) s1 += absdiff2_d(pn, pc);
       }
     }
     double s[2] = {s0, s1};
@@ -536,9 +718,263 @@ __global__ void __launch_bounds__(kThreads) kg_cn_lines(cpx<T>* __restrict__ dat
   }
   if constexpr (MODE != 2) {
     for (int t = threadIdx.x; t < tot; t += kThreads) {
-      const int line = contig ? t / N : t % nl;
-      const int e = contig ? t - line * N : t / nl;
-      data[g.addr(l0 + line, e)] = ps[line * N + e];
+      const int2 le = g.tile_index(t);
+      if (le.x < nl) {
+        const int c = (int)fdiv((uint32_t)le.y, fs);
+        data[g.addr(l0 + le.x, le.y)] = ps[le.x * LS + c * Sp + (le.y - c * S)];
+      }
+    }
+  }
+}
+
+// Crank-Nicolson sweep of a tile of lines of at most kTileMaxN points: the recurrences,
+// lane chunks and scans of kg_cn_lines, one wave per line, with the chunk's recurrence
+// values in registers (S <= kTileS rows per lane) and the factor table in LDS (the same
+// padded layout as the lines).  Tiles of strided lines take 16 (FP32) or 8 (FP64)
+// adjacent lines, 128-byte runs.
+// MODE 0: solve; 1: solve with the new-state sums part[2b], part[2b+1]; 2: those sums of
+// the stored state, no solve.
+// NLM = MODE_IMAG or MODE_REAL (x lines only: G = 1, so = n0, se = 1): the nonlinear
+// sub-step of kg_nonlinear applied to each value as it is loaded, with its seven sums of
+// the incoming state in pnl[7b ...]; NLM < 0: none.
+constexpr int kTileS = 16;
+constexpr int kTileMaxN = 64 * kTileS;
+constexpr int kTileMaxWaves = 16;
+// waves per tile block: 16 FP32, 8 FP64 (whose recurrence values need up to 256 VGPRs)
+template <typename T>
+constexpr int tile_max_waves() { return sizeof(T) == 4 ? 16 : 8; }
+
+struct GNl {  // the nonlinear sub-step's inputs for the fused x sweep
+  const void* V;
+  const void* phi;
+  const double* scale;
+  GStep sc;
+  int n0, n1, n2;
+  double* part;
+};
+
+template <typename T, int MODE, int NLM>
+__global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* __restrict__ data,
+                                                                GLines g, FDiv fs,
+                                                                const cpx<T>* __restrict__ f,
+                                                                double* __restrict__ part,
+                                                                GNl nlz) {
+  extern __shared__ __align__(16) char lds_raw[];
+  __shared__ double red[7 * kTileMaxWaves];
+  const int N = g.n;
+  const int S = (N + 63) / 64, Sp = S | 1, LS = cn_line_slots(N);
+  const int l0 = blockIdx.x * g.nl;
+  const int nl = min(g.nl, g.nlines - l0);
+  const int nt = blockDim.x, nw = nt >> 6;
+  const int tot = g.nl * N;  // the full tile's indexing; lines past nl are skipped
+  cpx<T>* ps = reinterpret_cast<cpx<T>*>(lds_raw);   // nl lines of psi (then u)
+  cpx<T>* fl = ps + (size_t)g.nl * LS;                // the factor table, one line
+  // values per thread per load round: the whole tile in one round where registers allow
+  constexpr int U = sizeof(T) == 4 && NLM < 0 ? 2 * kGenU : kGenU;
+  constexpr int UF = 4;  // factor-table values per thread fetched ahead of the tile
+  double q7[7] = {0, 0, 0, 0, 0, 0, 0};
+  [[maybe_unused]] T ts = (T)1;
+  if constexpr (NLM >= 0) ts = (T)(*nlz.scale);
+  // the factor table's first UF nt values are loaded with the tile and stored after it
+  cpx<T> fpre[UF];
+  if constexpr (MODE != 2) {
+#pragma unroll
+    for (int u = 0; u < UF; ++u) {
+      const int t = threadIdx.x + u * nt;
+      fpre[u] = f[t < N ? t : 0];
+    }
+  }
+  for (int t0 = threadIdx.x; t0 < tot; t0 += U * nt) {
+    T vr[U], vi[U];
+    [[maybe_unused]] T vv[U], ph[U];
+    int at[U], ee[U], ll[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * nt;
+      const int2 le = g.tile_index(t);
+      const int line = le.x, e = le.y;
+      const int c = (int)fdiv((uint32_t)e, fs);
+      at[u] = (t < tot && line < nl) ? line * LS + c * Sp + (e - c * S) : -1;
+      ee[u] = e;
+      ll[u] = l0 + line;
+      const long long a = at[u] >= 0 ? g.addr(l0 + line, e) : 0;  // in range only
+      const cpx<T> v = data[a];
+      vr[u] = v.re;
+      vi[u] = v.im;
+      if constexpr (NLM >= 0) {
+        vv[u] = reinterpret_cast<const T*>(nlz.V)[a];
+        ph[u] = reinterpret_cast<const T*>(nlz.phi)[a];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (at[u] < 0) continue;
+      cpx<T> v{vr[u], vi[u]};
+      if constexpr (NLM >= 0) {
+        // psi <- scale psi exp(-eps dt (V + g_c n + g_dd Phi)) and the sums of scale psi
+        const GStep& sc = nlz.sc;
+        const cpx<T> pv = scl(v, ts);
+        const T n = pv.re * pv.re + pv.im * pv.im;
+        const double nd = (double)n;
+        const int k = (int)fdiv((uint32_t)ll[u], sc.f1), j = ll[u] - k * nlz.n1;
+        const double x = (ee[u] - nlz.n0 / 2) * sc.h0, y = (j - nlz.n1 / 2) * sc.h1,
+                     z = (k - nlz.n2 / 2) * sc.h2;
+        q7[0] += nd;
+        q7[1] += (double)vv[u] * nd;
+        q7[2] += nd * nd;
+        q7[3] += (double)ph[u] * nd;
+        q7[4] += x * x * nd;
+        q7[5] += y * y * nd;
+        q7[6] += z * z * nd;
+        const T th = (T)sc.dt * (vv[u] + (T)sc.gc * n + (T)sc.gdd * ph[u]);
+        cpx<T> fz;
+        if constexpr (NLM == MODE_IMAG) {
+          fz = cpx<T>{exp(-th), (T)0};
+        } else {
+          T sn, cs;
+          sincos_phase(th, sn, cs);
+          fz = cpx<T>{cs, -sn};
+        }
+        v = pv * fz;
+      }
+      ps[at[u]] = v;
+    }
+  }
+  if constexpr (MODE != 2) {
+#pragma unroll
+    for (int u = 0; u < UF; ++u) {
+      const int t = threadIdx.x + u * nt;
+      if (t < N) {
+        const int c = (int)fdiv((uint32_t)t, fs);
+        fl[c * Sp + (t - c * S)] = fpre[u];
+      }
+    }
+    for (int t = threadIdx.x + UF * nt; t < N; t += nt) {
+      const int c = (int)fdiv((uint32_t)t, fs);
+      fl[c * Sp + (t - c * S)] = f[t];
+    }
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i0 = lane * S;
+  const int cnt = min(S, N - i0);  // rows of this lane's chunk (<= 0: none)
+  const int slot = cnt > 0 ? lane * Sp : 0;  // lanes with no chunk point at the line start
+  const cpx<T> zero{0, 0};
+  double s0 = 0.0, s1 = 0.0;
+  for (int line = wave; line < nl; line += nw) {
+    cpx<T>* p = ps + line * LS + slot;
+    cpx<T> d[kTileS];
+    if constexpr (MODE != 2) {
+      const cpx<T>* fq = fl + slot;
+      // forward, zero carry: local d and the chunk's product of g
+      cpx<T> acc = zero, prod = {1, 0};
+      cpx<T> pm = p[lane > 0 && cnt > 0 ? -Sp + S - 1 : 0];   // row i0 - 1
+      if (!(i0 > 0 && cnt > 0)) pm = zero;
+      cpx<T> pc = p[0];
+#pragma unroll
+      for (int j = 0; j < kTileS; ++j) {
+        if (j < cnt) {
+          cpx<T> pn = p[j + 1 < cnt ? j + 1 : Sp];  // row N is none: zero
+          if (i0 + j + 1 >= N) pn = zero;
+          const cpx<T> fi = fq[j];
+          acc = fi * ((pm + pn) - (pc + pc)) + scl(fi, (T)0.5) * acc;
+          prod = scl(fi, (T)0.5) * prod;
+          d[j] = acc;
+          pm = pc;
+          pc = pn;
+        }
+      }
+      // inclusive scan of the maps c -> prod c + acc over the lanes
+      cpx<T> P = prod, B = acc;
+      for (int off = 1; off < 64; off <<= 1) {
+        const cpx<T> Pp = shfl_up_c(P, off), Bp = shfl_up_c(B, off);
+        if (lane >= off) {
+          B = P * Bp + B;
+          P = P * Pp;
+        }
+      }
+      cpx<T> carry = shfl_up_c(B, 1);   // d at the end of the previous chunk
+      if (lane == 0) carry = zero;
+#pragma unroll
+      for (int j = 0; j < kTileS; ++j) {
+        if (j < cnt) {
+          carry = scl(fq[j], (T)0.5) * carry;
+          d[j] = d[j] + carry;
+        }
+      }
+      // backward, zero carry from the right: local e (kept in d)
+      acc = zero;
+#pragma unroll
+      for (int j = kTileS - 1; j >= 0; --j) {
+        if (j < cnt) {
+          acc = d[j] + scl(fq[j], (T)0.5) * acc;
+          d[j] = acc;
+        }
+      }
+      P = prod;
+      B = acc;
+      for (int off = 1; off < 64; off <<= 1) {
+        const cpx<T> Pn = shfl_down_c(P, off), Bn = shfl_down_c(B, off);
+        if (lane + off < 64) {
+          B = P * Bn + B;
+          P = P * Pn;
+        }
+      }
+      carry = shfl_down_c(B, 1);         // e at the start of the next chunk
+      if (lane == 63) carry = zero;
+#pragma unroll
+      for (int j = kTileS - 1; j >= 0; --j) {
+        if (j < cnt) {
+          carry = scl(fq[j], (T)0.5) * carry;
+          d[j] = p[j] + (d[j] + carry);   // u
+          p[j] = d[j];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < kTileS; ++j)
+        if (j < cnt) d[j] = p[j];
+    }
+    if constexpr (MODE != 0) {
+      // sums of u (or of the stored state): |u|^2 and the differences, the last one with
+      // the next lane's first row
+      const cpx<T> unext = shfl_down_c(d[0], 1);
+      cpx<T> prev = zero;
+#pragma unroll
+      for (int j = 0; j < kTileS; ++j) {
+        if (j < cnt) {
+          s0 += abs2_d(d[j]);
+          if (j > 0) s1 += absdiff2_d(d[j], prev);
+          prev = d[j];
+        }
+      }
+      if (cnt > 0 && i0 + cnt < N) s1 += absdiff2_d(unext, prev);
+    }
+  }
+  if constexpr (MODE != 0) {
+    double sv[2] = {s0, s1};
+    gblock_sum<2>(sv, red);
+    if (threadIdx.x == 0) {
+      part[2 * blockIdx.x] = sv[0];
+      part[2 * blockIdx.x + 1] = sv[1];
+    }
+  }
+  if constexpr (NLM >= 0) {
+    __syncthreads();  // red is reused
+    gblock_sum<7>(q7, red);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int q = 0; q < 7; ++q) nlz.part[7 * (long long)blockIdx.x + q] = q7[q];
+    }
+  }
+  if constexpr (MODE != 2) {
+    __syncthreads();
+    for (int t = threadIdx.x; t < tot; t += nt) {
+      const int2 le = g.tile_index(t);
+      if (le.x < nl) {
+        const int c = (int)fdiv((uint32_t)le.y, fs);
+        data[g.addr(l0 + le.x, le.y)] = ps[le.x * LS + c * Sp + (le.y - c * S)];
+      }
     }
   }
 }

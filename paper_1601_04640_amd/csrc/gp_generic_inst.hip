@@ -16,11 +16,15 @@ constexpr int kEmax = (int)(65536 / (2 * sizeof(T))) / kGenThreads;
 static_assert(kEmax * kGenThreads == gen_max_line<T>(), "one block holds the longest line");
 
 namespace {
-// lines per block of a line-FFT pass: about 2048 values, at most what 64 KiB of LDS
-// holds, halved while the pass would have fewer than 512 blocks
-int lines_per_block(int n, int nlines) {
+constexpr int kCnLds = 163840;  // LDS limit of the CN sweeps (160 KiB)
+constexpr int kTileLds = kCnLds - 1024;  // dynamic LDS of the tile sweeps (static: 896 B)
+
+// lines per block of a line-FFT pass: about 2048 values (contiguous lines) or as many
+// lines as 64 KiB of LDS holds (strided lines: the longest contiguous runs), halved
+// while the pass would have fewer than 512 blocks
+int lines_per_block(int n, int nlines, bool strided) {
   const int cap = gen_max_line<T>() / n;
-  int nl = 2048 / n;
+  int nl = strided ? cap : 2048 / n;
   if (nl < 1) nl = 1;
   if (nl > cap) nl = cap;
   while (nl > 1 && (nlines + nl - 1) / nl < 512) nl /= 2;
@@ -58,13 +62,25 @@ hipError_t GLaunch<T>::prepare() {
     const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
   }
-  // the CN sweeps hold two buffers of up to 64 KiB
+  // the CN sweeps hold two padded buffers of up to 65 KiB
   const void* kc[] = {reinterpret_cast<const void*>(&kg_cn_lines<T, 0>),
                       reinterpret_cast<const void*>(&kg_cn_lines<T, 1>),
                       reinterpret_cast<const void*>(&kg_cn_lines<T, 2>)};
   for (const void* k : kc) {
     const hipError_t e =
-        hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 2 * lds);
+        hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kCnLds);
+    if (e != hipSuccess) return e;
+  }
+  // the tile sweeps: up to 16 padded lines and the factor table, beside 896 bytes of
+  // static reduction space
+  const void* kt[] = {reinterpret_cast<const void*>(&kg_cn_tile<T, 0, -1>),
+                      reinterpret_cast<const void*>(&kg_cn_tile<T, 1, -1>),
+                      reinterpret_cast<const void*>(&kg_cn_tile<T, 2, -1>),
+                      reinterpret_cast<const void*>(&kg_cn_tile<T, 0, MODE_IMAG>),
+                      reinterpret_cast<const void*>(&kg_cn_tile<T, 0, MODE_REAL>)};
+  for (const void* k : kt) {
+    const hipError_t e =
+        hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kTileLds);
     if (e != hipSuccess) return e;
   }
   done = true;
@@ -86,6 +102,10 @@ GXTile GLaunch<T>::xtile(int n0, int n1, int n2) {
   while (np > 1 && (long long)n2 * ((pairs + np - 1) / np) < 512) np /= 2;
   xt.np = np;
   xt.nbj = (pairs + np - 1) / np;
+  xt.fn0 = fdiv_make((uint32_t)n0);
+  xt.fnp = fdiv_make((uint32_t)np);
+  xt.f2np = fdiv_make((uint32_t)(2 * np));
+  xt.fnbj = fdiv_make((uint32_t)xt.nbj);
   return xt;
 }
 
@@ -96,15 +116,73 @@ int GLaunch<T>::x_blocks(int n0, int n1, int n2) {
 }
 
 template <>
-int GLaunch<T>::cn_lines_per_block(int n, int nlines) {
-  // two LDS buffers (psi and the recurrence values) of nl lines within 128 KiB; about
-  // 4096 values per block, halved while the sweep would have fewer than 512 blocks
-  const int cap = 2 * gen_max_line<T>() / (2 * n);
-  int nl = 4096 / n;
-  if (nl < 1) nl = 1;
+int GLaunch<T>::cn_lines_per_block(int n, int nlines, bool strided) {
+  // contiguous lines: at most 4096 values and 64 KiB of LDS per block (two blocks per
+  // CU), a whole number of waves' worth of lines; strided lines: 128-byte runs (16 FP32
+  // or 8 FP64 lines) within the LDS limit; both halved while the sweep would have fewer
+  // than 512 blocks (a line takes two padded buffers)
+  const int per_line = 2 * cn_line_slots(n) * (int)sizeof(cpx<T>);
+  const int cap = (strided ? kCnLds : 65536) / per_line;
+  int nl = strided ? 128 / (int)sizeof(cpx<T>) : 4096 / n;
   if (nl > cap) nl = cap;
+  if (nl < 1) nl = 1;
+  if (!strided && nl >= kWaves) nl -= nl % kWaves;
   while (nl > 1 && (nlines + nl - 1) / nl < 512) nl /= 2;
   return nl;
+}
+
+template <>
+int GLaunch<T>::cn_tile_lines(int n, int nlines, bool strided) {
+  // one wave per line; strided tiles: 64-byte runs (8 FP32 or 4 FP64 lines, kept), contiguous
+  // lines: at most 52 KiB of LDS (three blocks per CU); halved while the sweep would have
+  // fewer than 512 blocks; the tile and the factor table fit the LDS
+  const int per_line = cn_line_slots(n) * (int)sizeof(cpx<T>);
+  int nl = strided ? 64 / (int)sizeof(cpx<T>) : 53248 / per_line;
+  const int cap = kTileLds / per_line - 1;
+  if (nl > cap) nl = cap;
+  if (nl > tile_max_waves<T>()) nl = tile_max_waves<T>();
+  if (nl < 1) nl = 1;
+  while (nl > (strided ? 4 : 1) && (nlines + nl - 1) / nl < 512) nl /= 2;
+  return nl;
+}
+
+namespace {
+template <int MODE, int NLM>
+hipError_t launch_tile(hipStream_t st, cpx<T>* data, const GLines& g, FDiv fs,
+                       const cpx<T>* f, double* part, const GNl& nlz) {
+  const int blocks = (g.nlines + g.nl - 1) / g.nl;
+  const size_t lds = lds_of((g.nl + 1) * cn_line_slots(g.n));
+  if (lds > (size_t)kTileLds || g.nl > tile_max_waves<T>()) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((kg_cn_tile<T, MODE, NLM>), dim3(blocks), dim3(64 * g.nl), lds, st, data,
+                     g, fs, f, part, nlz);
+  return hipGetLastError();
+}
+
+GLines tile_lines(int n, int nlines, int nl, int G, long long so, long long si, long long se) {
+  GLines g{};
+  g.n = n;
+  g.nlines = nlines;
+  g.nl = nl;
+  g.G = G;
+  g.so = so;
+  g.si = si;
+  g.se = se;
+  g.fn = fdiv_make((uint32_t)n);
+  g.fnl = fdiv_make((uint32_t)nl);
+  g.fg = fdiv_make((uint32_t)G);
+  return g;
+}
+}  // namespace
+
+template <>
+hipError_t GLaunch<T>::cn_x_nonlinear(int mode, hipStream_t st, cpx<T>* psi, int n0, int lines,
+                                      const cpx<T>* f, const GNl& nlz) {
+  if (n0 > kTileMaxN || lines < 1) return hipErrorInvalidValue;
+  const GLines g = tile_lines(n0, lines, cn_tile_lines(n0, lines, false), 1, n0, 0, 1);
+  const FDiv fs = fdiv_make((uint32_t)((n0 + 63) / 64));
+  if (mode == MODE_IMAG) return launch_tile<0, MODE_IMAG>(st, psi, g, fs, f, nullptr, nlz);
+  if (mode == MODE_REAL) return launch_tile<0, MODE_REAL>(st, psi, g, fs, f, nullptr, nlz);
+  return hipErrorInvalidValue;
 }
 
 template <>
@@ -145,11 +223,14 @@ hipError_t GLaunch<T>::lines(int kind, hipStream_t st, cpx<T>* data, int n, int 
   GLines g{};
   g.n = n;
   g.nlines = nlines;
-  g.nl = lines_per_block(n, nlines);
+  g.nl = lines_per_block(n, nlines, se != 1);
   g.G = G;
   g.so = so;
   g.si = si;
   g.se = se;
+  g.fn = fdiv_make((uint32_t)n);
+  g.fnl = fdiv_make((uint32_t)g.nl);
+  g.fg = fdiv_make((uint32_t)G);
   const int blocks = (nlines + g.nl - 1) / g.nl;
   const size_t lds = lds_of(g.nl * n);
   const bool small = gen_plan_small(p);
@@ -197,7 +278,18 @@ hipError_t GLaunch<T>::cn_lines(int mode, hipStream_t st, cpx<T>* data, int n, i
                                 int G, long long so, long long si, long long se,
                                 const cpx<T>* f, double* part, cpx<T>* dscr) {
   if (n > gen_max_line<T>() || nlines < 1) return hipErrorInvalidValue;
-  if (cn_by_columns(se != 1, nlines)) {
+  if (n <= kTileMaxN) {
+    const GLines g = tile_lines(n, nlines, cn_tile_lines(n, nlines, se != 1), G, so, si, se);
+    const FDiv fs = fdiv_make((uint32_t)((n + 63) / 64));
+    const GNl none{};
+    switch (mode) {
+      case 0: return launch_tile<0, -1>(st, data, g, fs, f, part, none);
+      case 1: return launch_tile<1, -1>(st, data, g, fs, f, part, none);
+      case 2: return launch_tile<2, -1>(st, data, g, fs, f, part, none);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  if (cn_by_columns(n, se != 1, nlines)) {
     // consecutive lines adjacent (si = 1): one thread per line
     if (si != 1) return hipErrorInvalidValue;
     const int blocks = (nlines + kThreads - 1) / kThreads;
@@ -222,27 +314,32 @@ hipError_t GLaunch<T>::cn_lines(int mode, hipStream_t st, cpx<T>* data, int n, i
   GLines g{};
   g.n = n;
   g.nlines = nlines;
-  g.nl = cn_lines_per_block(n, nlines);
+  g.nl = cn_lines_per_block(n, nlines, se != 1);
   g.G = G;
   g.so = so;
   g.si = si;
   g.se = se;
+  g.fn = fdiv_make((uint32_t)n);
+  g.fnl = fdiv_make((uint32_t)g.nl);
+  g.fg = fdiv_make((uint32_t)G);
+  const FDiv fs = fdiv_make((uint32_t)((n + 63) / 64));
   const int blocks = (nlines + g.nl - 1) / g.nl;
-  // psi lines, then the recurrence values (at least the block reduction's 64 bytes)
-  const size_t one = lds_of(g.nl * n);
-  const size_t lds = one + (one < 64 ? 64 : one);
+  // psi lines, then the recurrence values, padded (a line takes cn_line_slots values;
+  // at least 64 of them, which holds the block reduction)
+  const size_t lds = 2 * lds_of(g.nl * cn_line_slots(n));
+  if (lds > (size_t)kCnLds) return hipErrorInvalidValue;
   switch (mode) {
     case 0:
       hipLaunchKernelGGL((kg_cn_lines<T, 0>), dim3(blocks), dim3(kThreads), lds, st, data, g,
-                         f, part);
+                         fs, f, part);
       break;
     case 1:
       hipLaunchKernelGGL((kg_cn_lines<T, 1>), dim3(blocks), dim3(kThreads), lds, st, data, g,
-                         f, part);
+                         fs, f, part);
       break;
     case 2:
       hipLaunchKernelGGL((kg_cn_lines<T, 2>), dim3(blocks), dim3(kThreads), lds, st, data, g,
-                         f, part);
+                         fs, f, part);
       break;
     default:
       return hipErrorInvalidValue;

@@ -25,25 +25,36 @@ inline bool gen_size_ok(int n) {
 
 template <typename T>
 struct GLaunch {
-  // raises the dynamic LDS limit of the LDS-FFT kernels to 64 KiB (once per process;
-  // called when a context is created, never inside a graph capture)
+  // raises the dynamic LDS limit of the LDS-FFT kernels to 64 KiB and of the CN sweeps to
+  // 160 KiB (once per process; called when a context is created, never inside a graph
+  // capture)
   static hipError_t prepare();
   // x passes: tile of the grid (line pairs per block) and its block count
   static GXTile xtile(int n0, int n1, int n2);
   static int x_blocks(int n0, int n1, int n2);
   // blocks of the nonlinear pass (partial-sum slots) and of a CN sweep over nlines lines
   static int nl_blocks(int n0, int n1, int n2) {
-    return gen_nl_blocks((long long)n0 * n1 * n2);
+    return x_fused(n0) ? cn_blocks(n0, n1 * n2, false) : gen_nl_blocks((long long)n0 * n1 * n2);
   }
-  static int cn_lines_per_block(int n, int nlines);
-  // strided sweeps with at least this many lines run one thread per line
+  static int cn_lines_per_block(int n, int nlines, bool strided);
+  // lines of up to kTileMaxN points run kg_cn_tile (nl lines per block, one wave each)
+  static int cn_tile_lines(int n, int nlines, bool strided);
+  // longer strided lines, with at least this many lines, run one thread per line
   static constexpr int kColLines = 32768;
-  static bool cn_by_columns(bool strided, int nlines) { return strided && nlines >= kColLines; }
+  static bool cn_by_columns(int n, bool strided, int nlines) {
+    return n > kTileMaxN && strided && nlines >= kColLines;
+  }
   static int cn_blocks(int n, int nlines, bool strided) {
-    if (cn_by_columns(strided, nlines)) return (nlines + kThreads - 1) / kThreads;
-    const int nl = cn_lines_per_block(n, nlines);
+    if (n <= kTileMaxN) {
+      const int nl = cn_tile_lines(n, nlines, strided);
+      return (nlines + nl - 1) / nl;
+    }
+    if (cn_by_columns(n, strided, nlines)) return (nlines + kThreads - 1) / kThreads;
+    const int nl = cn_lines_per_block(n, nlines, strided);
     return (nlines + nl - 1) / nl;
   }
+  // the x sweep carries the nonlinear sub-step when its lines fit a tile
+  static bool x_fused(int n0) { return n0 <= kTileMaxN; }
 
   static hipError_t r2c_x(hipStream_t st, const cpx<T>* psi, cpx<T>* spec, const GPlan& p,
                           const cpx<T>* tw, double* part, int n0, int n1, int n2);
@@ -63,13 +74,18 @@ struct GLaunch {
   static hipError_t cn_lines(int mode, hipStream_t st, cpx<T>* data, int n, int nlines, int G,
                              long long so, long long si, long long se, const cpx<T>* f,
                              double* part, cpx<T>* dscr);
+  // the x sweep (lines (j, k) of n0 <= kTileMaxN points) with the nonlinear sub-step of
+  // MODE_IMAG / MODE_REAL fused into its loads; nlz.part: the nl_blocks seven-sum slots
+  static hipError_t cn_x_nonlinear(int mode, hipStream_t st, cpx<T>* psi, int n0, int lines,
+                                   const cpx<T>* f, const GNl& nlz);
 };
 
 #define GP_DECLARE_GLAUNCH(T)                                                                  \
   template <> hipError_t GLaunch<T>::prepare();                                                \
   template <> GXTile GLaunch<T>::xtile(int, int, int);                                         \
   template <> int GLaunch<T>::x_blocks(int, int, int);                                         \
-  template <> int GLaunch<T>::cn_lines_per_block(int, int);                                    \
+  template <> int GLaunch<T>::cn_lines_per_block(int, int, bool);                              \
+  template <> int GLaunch<T>::cn_tile_lines(int, int, bool);                                   \
   template <> hipError_t GLaunch<T>::r2c_x(hipStream_t, const cpx<T>*, cpx<T>*, const GPlan&, \
                                            const cpx<T>*, double*, int, int, int);             \
   template <> hipError_t GLaunch<T>::c2r_x(hipStream_t, const cpx<T>*, T*, const GPlan&,      \
@@ -82,7 +98,9 @@ struct GLaunch {
                                                double*);                                       \
   template <> hipError_t GLaunch<T>::cn_lines(int, hipStream_t, cpx<T>*, int, int, int,       \
                                               long long, long long, long long, const cpx<T>*, \
-                                              double*, cpx<T>*);
+                                              double*, cpx<T>*);                               \
+  template <> hipError_t GLaunch<T>::cn_x_nonlinear(int, hipStream_t, cpx<T>*, int, int,     \
+                                                    const cpx<T>*, const GNl&);
 GP_DECLARE_GLAUNCH(float)
 GP_DECLARE_GLAUNCH(double)
 #undef GP_DECLARE_GLAUNCH
