@@ -60,6 +60,37 @@ constexpr int kGenMaxPrime = 31;
 // round rather than one per value.
 constexpr int kGenU = 8;
 
+// The FFT kernels of the radices 2..8 copy the twiddle table (N values) into LDS beside
+// their lines, so the stages read it at LDS latency.  The first values are fetched into
+// registers before the lines' loads are issued and stored after them (one memory latency
+// for both).  The kernels that also carry the radices 11..31 read the table from global
+// memory: their LDS-table build gave wrong FP32 convolutions for lines with a factor 17
+// or 19 (parity test), with no cause found in the source.
+template <typename T>
+constexpr int tw_pre() { return sizeof(T) == 4 ? 8 : 4; }
+template <typename T, bool SMALL, int UT>
+__device__ __forceinline__ void tw_fetch(cpx<T> (&v)[UT], const cpx<T>* __restrict__ tw, int N) {
+  if constexpr (!SMALL) return;
+#pragma unroll
+  for (int u = 0; u < UT; ++u) {
+    const int t = threadIdx.x + u * blockDim.x;
+    v[u] = tw[t < N ? t : 0];
+  }
+}
+// returns the table the stages read: twl (radices up to 8) or tw
+template <typename T, bool SMALL, int UT>
+__device__ __forceinline__ const cpx<T>* tw_store(cpx<T>* twl, const cpx<T> (&v)[UT],
+                                                  const cpx<T>* __restrict__ tw, int N) {
+  if constexpr (!SMALL) return tw;
+#pragma unroll
+  for (int u = 0; u < UT; ++u) {
+    const int t = threadIdx.x + u * blockDim.x;
+    if (t < N) twl[t] = v[u];
+  }
+  for (int t = threadIdx.x + UT * blockDim.x; t < N; t += blockDim.x) twl[t] = tw[t];
+  return twl;
+}
+
 // Radices of an N-point FFT: factors 8, 4, 2, then the odd primes up to 31; per stage
 // the divisors of its butterfly indexing (N / R butterflies per line, L = the product of
 // the earlier radices).
@@ -106,7 +137,7 @@ __device__ __forceinline__ void dft_prime(cpx<T>* x, const cpx<T>* w) {
 }
 
 template <typename T, bool INV>
-__device__ __forceinline__ cpx<T> twid(const cpx<T>* __restrict__ tw, long long k) {
+__device__ __forceinline__ cpx<T> twid(const cpx<T>* __restrict__ tw, int k) {
   const cpx<T> w = tw[k];
   return INV ? cpx<T>{w.re, -w.im} : w;
 }
@@ -127,7 +158,7 @@ __device__ __forceinline__ void gstage(cpx<T>* buf, int NL, int N, int L, FDiv f
   cpx<T> w[R];
   if constexpr (R == 7 || R > 8) {
 #pragma unroll
-    for (int k = 0; k < R; ++k) w[k] = twid<T, INV>(tw, (long long)k * (N / R));
+    for (int k = 0; k < R; ++k) w[k] = twid<T, INV>(tw, k * (N / R));
   }
   cpx<T> v[QM][R];
   int dst[QM];
@@ -144,7 +175,7 @@ __device__ __forceinline__ void gstage(cpx<T>* buf, int NL, int N, int L, FDiv f
       for (int r = 0; r < R; ++r) v[q][r] = x[i + r * NB];
       if (L > 1) {
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[q][r] = v[q][r] * twid<T, INV>(tw, (long long)r * k * tstride);
+        for (int r = 1; r < R; ++r) v[q][r] = v[q][r] * twid<T, INV>(tw, r * k * tstride);
       }
       if constexpr (R == 7 || R > 8) {
         dft_prime<T, R>(v[q], w);
@@ -209,6 +240,9 @@ struct GLines {
   int G;
   long long so, si, se;
   FDiv fn, fnl, fg;
+  // the lines are consecutive runs of n values (G = 1, so = n, se = 1): a block's tile is
+  // one contiguous range
+  __device__ __forceinline__ bool packed() const { return G == 1 && se == 1 && so == n; }
   __device__ __forceinline__ long long addr(int l, int e) const {
     const int hi = (int)fdiv((uint32_t)l, fg);
     return (long long)hi * so + (long long)(l - hi * G) * si + (long long)e * se;
@@ -258,17 +292,27 @@ __global__ void __launch_bounds__(kGenThreads) kg_lines(cpx<T>* __restrict__ dat
   const int N = g.n;
   const int nt = blockDim.x;
   const int tot = g.nl * N;  // the full tile's indexing; lines past nl are skipped
+  cpx<T>* twl = buf + tot;   // the twiddle table
+  cpx<T> twv[tw_pre<T>()];
+  tw_fetch<T, SMALL, tw_pre<T>()>(twv, tw, N);
+  const bool packed = g.packed();
+  cpx<T>* const run = data + (long long)l0 * N;  // the tile when packed
   for (int t0 = threadIdx.x; t0 < tot; t0 += kGenU * nt) {
     T vr[kGenU], vi[kGenU];  // separate parts: arrays of the aligned pair type stay in memory
     int at[kGenU];
 #pragma unroll
     for (int u = 0; u < kGenU; ++u) {
       const int t = t0 + u * nt;
-      const int2 le = g.tile_index(t);
-      const int line = le.x, e = le.y;
-      at[u] = (t < tot && line < nl) ? line * N + e : -1;
-      if (at[u] >= 0) {
-        const cpx<T> v = data[g.addr(l0 + line, e)];
+      if (packed) {
+        at[u] = t < nl * N ? t : -1;
+        const cpx<T> v = run[at[u] >= 0 ? t : 0];
+        vr[u] = v.re;
+        vi[u] = v.im;
+      } else {
+        const int2 le = g.tile_index(t);
+        const int line = le.x, e = le.y;
+        at[u] = (t < tot && line < nl) ? line * N + e : -1;
+        const cpx<T> v = data[at[u] >= 0 ? g.addr(l0 + line, e) : 0];
         vr[u] = v.re;
         vi[u] = v.im;
       }
@@ -277,36 +321,40 @@ __global__ void __launch_bounds__(kGenThreads) kg_lines(cpx<T>* __restrict__ dat
     for (int u = 0; u < kGenU; ++u)
       if (at[u] >= 0) buf[at[u]] = cpx<T>{vr[u], vi[u]};
   }
+  const cpx<T>* twu = tw_store<T, SMALL, tw_pre<T>()>(twl, twv, tw, N);
   __syncthreads();
   if constexpr (KIND == GL_CONV) {
-    gfft<T, false, EMAX, SMALL>(buf, nl, p, tw);
+    gfft<T, false, EMAX, SMALL>(buf, nl, p, twu);
     const double s = *scale;
     const T s2 = (T)(s * s);
-    const int totl = nl * N;
-    for (int t0 = threadIdx.x; t0 < totl; t0 += kGenU * nt) {
+    // the tile's order of the loads (element-major for strided lines): the table reads of
+    // adjacent lines are adjacent
+    for (int t0 = threadIdx.x; t0 < tot; t0 += kGenU * nt) {
       T kv[kGenU];
+      int at[kGenU];
 #pragma unroll
       for (int u = 0; u < kGenU; ++u) {
         const int t = t0 + u * nt;
-        if (t < totl) {
-          const int line = (int)fdiv((uint32_t)t, g.fn), e = t - line * N;
-          kv[u] = ktab[km.index(l0 + line, e)];
-        }
+        const int2 le = g.tile_index(t);
+        at[u] = (t < tot && le.x < nl) ? le.x * N + le.y : -1;
+        kv[u] = ktab[at[u] >= 0 ? km.index(l0 + le.x, le.y) : 0];
       }
 #pragma unroll
-      for (int u = 0; u < kGenU; ++u) {
-        const int t = t0 + u * nt;
-        if (t < totl) buf[t] = scl(buf[t], kv[u] * s2);
-      }
+      for (int u = 0; u < kGenU; ++u)
+        if (at[u] >= 0) buf[at[u]] = scl(buf[at[u]], kv[u] * s2);
     }
     __syncthreads();
-    gfft<T, true, EMAX, SMALL>(buf, nl, p, tw);
+    gfft<T, true, EMAX, SMALL>(buf, nl, p, twu);
   } else {
-    gfft<T, KIND == GL_INV, EMAX, SMALL>(buf, nl, p, tw);
+    gfft<T, KIND == GL_INV, EMAX, SMALL>(buf, nl, p, twu);
   }
-  for (int t = threadIdx.x; t < tot; t += nt) {
-    const int2 le = g.tile_index(t);
-    if (le.x < nl) data[g.addr(l0 + le.x, le.y)] = buf[le.x * N + le.y];
+  if (packed) {
+    for (int t = threadIdx.x; t < nl * N; t += nt) run[t] = buf[t];
+  } else {
+    for (int t = threadIdx.x; t < tot; t += nt) {
+      const int2 le = g.tile_index(t);
+      if (le.x < nl) data[g.addr(l0 + le.x, le.y)] = buf[le.x * N + le.y];
+    }
   }
 }
 
@@ -343,6 +391,10 @@ __global__ void __launch_bounds__(kGenThreads) kg_r2c_x(const cpx<T>* __restrict
   const int N = xt.n0, n1 = xt.n1;
   const int nt = blockDim.x;
   const int tot = npairs * N;
+  cpx<T>* twl = buf + xt.np * N;  // the twiddle table (a shorter prefetch: five loads a value)
+  constexpr int UT = tw_pre<T>() / 2;
+  cpx<T> twv[UT];
+  tw_fetch<T, SMALL, UT>(twv, tw, N);
   double dx = 0.0, dy = 0.0;  // reduced at the end, through the same LDS
   for (int t0 = threadIdx.x; t0 < tot; t0 += U * nt) {
     // |psi|^2 needs the two values; the differences their x and axis-1 neighbours
@@ -382,8 +434,9 @@ __global__ void __launch_bounds__(kGenThreads) kg_r2c_x(const cpx<T>* __restrict
       }
     }
   }
+  const cpx<T>* twu = tw_store<T, SMALL, UT>(twl, twv, tw, N);
   __syncthreads();
-  gfft<T, false, EMAX, SMALL>(buf, npairs, p, tw);
+  gfft<T, false, EMAX, SMALL>(buf, npairs, p, twu);
   const int H = N / 2 + 1;
   const int tot2 = H * 2 * xt.np;  // the full tile's indexing; pairs past npairs skipped
   for (int t = threadIdx.x; t < tot2; t += nt) {
@@ -424,6 +477,9 @@ __global__ void __launch_bounds__(kGenThreads) kg_c2r_x(const cpx<T>* __restrict
   const int H = N / 2 + 1;
   const int nt = blockDim.x;
   const int tot = H * xt.np;  // the full tile's indexing; pairs past npairs skipped
+  cpx<T>* twl = buf + xt.np * N;  // the twiddle table
+  cpx<T> twv[tw_pre<T>()];
+  tw_fetch<T, SMALL, tw_pre<T>()>(twv, tw, N);
   for (int t0 = threadIdx.x; t0 < tot; t0 += U * nt) {
     cpx<T> A[U], B[U];
     int kk[U], qq[U];
@@ -449,8 +505,9 @@ __global__ void __launch_bounds__(kGenThreads) kg_c2r_x(const cpx<T>* __restrict
       }
     }
   }
+  const cpx<T>* twu = tw_store<T, SMALL, tw_pre<T>()>(twl, twv, tw, N);
   __syncthreads();
-  gfft<T, true, EMAX, SMALL>(buf, npairs, p, tw);
+  gfft<T, true, EMAX, SMALL>(buf, npairs, p, twu);
   const int tot2 = npairs * N;
   for (int t = threadIdx.x; t < tot2; t += nt) {
     const int q = (int)fdiv((uint32_t)t, xt.fn0), i = t - q * N;
@@ -784,20 +841,36 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
       fpre[u] = f[t < N ? t : 0];
     }
   }
-  for (int t0 = threadIdx.x; t0 < tot; t0 += U * nt) {
+  // packed tiles are one contiguous range; in strided tiles (element-major, blockDim =
+  // 64 nl) thread tid keeps line tid mod nl and walks its elements 64 apart, so its line's
+  // base address is computed once
+  const bool packed = g.packed();
+  const int sl = threadIdx.x % g.nl, se0 = threadIdx.x / g.nl;
+  const long long sbase = !packed && sl < nl ? g.addr(l0 + sl, 0) : 0;
+  const long long pbase = (long long)l0 * N;
+  for (int t0 = threadIdx.x, r0 = 0; t0 < tot; t0 += U * nt, r0 += U) {
     T vr[U], vi[U];
     [[maybe_unused]] T vv[U], ph[U];
     int at[U], ee[U], ll[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int t = t0 + u * nt;
-      const int2 le = g.tile_index(t);
-      const int line = le.x, e = le.y;
+      int line, e;
+      long long a;
+      if (packed) {
+        line = (int)fdiv((uint32_t)t, g.fn);
+        e = t - line * N;
+        a = pbase + t;
+      } else {
+        line = sl;
+        e = se0 + 64 * (r0 + u);
+        a = sbase + (long long)e * g.se;
+      }
       const int c = (int)fdiv((uint32_t)e, fs);
       at[u] = (t < tot && line < nl) ? line * LS + c * Sp + (e - c * S) : -1;
       ee[u] = e;
       ll[u] = l0 + line;
-      const long long a = at[u] >= 0 ? g.addr(l0 + line, e) : 0;  // in range only
+      if (at[u] < 0) a = 0;  // in range only
       const cpx<T> v = data[a];
       vr[u] = v.re;
       vi[u] = v.im;
@@ -969,11 +1042,21 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
   }
   if constexpr (MODE != 2) {
     __syncthreads();
-    for (int t = threadIdx.x; t < tot; t += nt) {
-      const int2 le = g.tile_index(t);
-      if (le.x < nl) {
-        const int c = (int)fdiv((uint32_t)le.y, fs);
-        data[g.addr(l0 + le.x, le.y)] = ps[le.x * LS + c * Sp + (le.y - c * S)];
+    for (int t = threadIdx.x, r = 0; t < tot; t += nt, ++r) {
+      int line, e;
+      long long a;
+      if (packed) {
+        line = (int)fdiv((uint32_t)t, g.fn);
+        e = t - line * N;
+        a = pbase + t;
+      } else {
+        line = sl;
+        e = se0 + 64 * r;
+        a = sbase + (long long)e * g.se;
+      }
+      if (line < nl) {
+        const int c = (int)fdiv((uint32_t)e, fs);
+        data[a] = ps[line * LS + c * Sp + (e - c * S)];
       }
     }
   }

@@ -46,7 +46,8 @@ hipError_t GLaunch<T>::prepare() {
   static bool done = false;
   std::lock_guard<std::mutex> lock(mu);
   if (done) return hipSuccess;
-  const int lds = (int)lds_of(gen_max_line<T>());
+  // lines of up to gen_max_line values and the twiddle table
+  const int lds = (int)lds_of(2 * gen_max_line<T>());
   const void* ks[] = {
       reinterpret_cast<const void*>(&kg_lines<T, GL_FWD, kEmax, true>),
       reinterpret_cast<const void*>(&kg_lines<T, GL_INV, kEmax, true>),
@@ -62,7 +63,7 @@ hipError_t GLaunch<T>::prepare() {
     const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
   }
-  // the CN sweeps hold two padded buffers of up to 65 KiB
+  // the CN line sweeps hold two padded buffers of up to 65 KiB
   const void* kc[] = {reinterpret_cast<const void*>(&kg_cn_lines<T, 0>),
                       reinterpret_cast<const void*>(&kg_cn_lines<T, 1>),
                       reinterpret_cast<const void*>(&kg_cn_lines<T, 2>)};
@@ -190,8 +191,9 @@ hipError_t GLaunch<T>::r2c_x(hipStream_t st, const cpx<T>* psi, cpx<T>* spec, co
                              const cpx<T>* tw, double* part, int n0, int n1, int n2) {
   const GXTile xt = xtile(n0, n1, n2);
   if (xt.np * n0 > gen_max_line<T>()) return hipErrorInvalidValue;
-  // the block's reduction reuses the line buffer: at least 32 doubles
-  const size_t lds_r2c = lds_of(xt.np * n0) < 256 ? 256 : lds_of(xt.np * n0);
+  // the lines and the twiddle table; the block's reduction reuses the line buffer (at
+  // least 32 doubles)
+  const size_t lds_r2c = lds_of(xt.np * n0 + n0) < 256 ? 256 : lds_of(xt.np * n0 + n0);
   if (gen_plan_small(p))
     hipLaunchKernelGGL((kg_r2c_x<T, kEmax, true>), dim3(xt.nbj * n2), threads_for(xt.np * n0),
                        lds_r2c, st, psi, spec, xt, p, tw, part);
@@ -208,10 +210,10 @@ hipError_t GLaunch<T>::c2r_x(hipStream_t st, const cpx<T>* spec, T* phi, const G
   if (xt.np * n0 > gen_max_line<T>()) return hipErrorInvalidValue;
   if (gen_plan_small(p))
     hipLaunchKernelGGL((kg_c2r_x<T, kEmax, true>), dim3(xt.nbj * n2), threads_for(xt.np * n0),
-                       lds_of(xt.np * n0), st, spec, phi, xt, p, tw);
+                       lds_of(xt.np * n0 + n0), st, spec, phi, xt, p, tw);
   else
     hipLaunchKernelGGL((kg_c2r_x<T, kEmax, false>), dim3(xt.nbj * n2), threads_for(xt.np * n0),
-                       lds_of(xt.np * n0), st, spec, phi, xt, p, tw);
+                       lds_of(xt.np * n0 + n0), st, spec, phi, xt, p, tw);
   return hipGetLastError();
 }
 
@@ -232,7 +234,7 @@ hipError_t GLaunch<T>::lines(int kind, hipStream_t st, cpx<T>* data, int n, int 
   g.fnl = fdiv_make((uint32_t)g.nl);
   g.fg = fdiv_make((uint32_t)G);
   const int blocks = (nlines + g.nl - 1) / g.nl;
-  const size_t lds = lds_of(g.nl * n);
+  const size_t lds = lds_of(g.nl * n + n);  // the lines and the twiddle table
   const bool small = gen_plan_small(p);
   switch (kind * 2 + (small ? 1 : 0)) {
 #define GLINES(K, S)                                                                      \
