@@ -826,8 +826,8 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
   const int tot = g.nl * N;  // the full tile's indexing; lines past nl are skipped
   cpx<T>* ps = reinterpret_cast<cpx<T>*>(lds_raw);   // nl lines of psi (then u)
   cpx<T>* fl = ps + (size_t)g.nl * LS;                // the factor table, one line
-  // values per thread per load round: the whole tile in one round where registers allow
-  constexpr int U = sizeof(T) == 4 && NLM < 0 ? 2 * kGenU : kGenU;
+  // values per thread per load round
+  constexpr int U = kGenU;
   constexpr int UF = 4;  // factor-table values per thread fetched ahead of the tile
   double q7[7] = {0, 0, 0, 0, 0, 0, 0};
   [[maybe_unused]] T ts = (T)1;

@@ -135,10 +135,12 @@ int GLaunch<T>::cn_lines_per_block(int n, int nlines, bool strided) {
 template <>
 int GLaunch<T>::cn_tile_lines(int n, int nlines, bool strided) {
   // one wave per line; strided tiles: 64-byte runs (8 FP32 or 4 FP64 lines, kept), contiguous
-  // lines: at most 52 KiB of LDS (three blocks per CU); halved while the sweep would have
-  // fewer than 512 blocks; the tile and the factor table fit the LDS
+  // lines: 8 lines, at most 52 KiB of LDS (two blocks per CU at the kernels' register use);
+  // halved while the sweep would have fewer than 512 blocks; the tile and the factor table
+  // fit the LDS
   const int per_line = cn_line_slots(n) * (int)sizeof(cpx<T>);
   int nl = strided ? 64 / (int)sizeof(cpx<T>) : 53248 / per_line;
+  if (!strided && nl > 8) nl = 8;
   const int cap = kTileLds / per_line - 1;
   if (nl > cap) nl = cap;
   if (nl > tile_max_waves<T>()) nl = tile_max_waves<T>();
