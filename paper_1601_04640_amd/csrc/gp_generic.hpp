@@ -280,8 +280,12 @@ enum : int { GL_FWD = 0, GL_INV = 1, GL_CONV = 2 };
 
 // Line FFTs of the half spectrum.  KIND GL_CONV: forward FFT, product with
 // U(k) scale^2 / N (the table holds U/N), inverse FFT.
+// FP32: at most 64 VGPRs, so that two full 16-wave blocks share a CU
+template <typename T>
+constexpr int gen_waves_per_eu() { return sizeof(T) == 4 ? 8 : 1; }
+
 template <typename T, int KIND, int EMAX, bool SMALL>
-__global__ void __launch_bounds__(kGenThreads) kg_lines(cpx<T>* __restrict__ data, GLines g,
+__global__ void __launch_bounds__(kGenThreads, gen_waves_per_eu<T>()) kg_lines(cpx<T>* __restrict__ data, GLines g,
                                                      GPlan p, const cpx<T>* __restrict__ tw,
                                                      const T* __restrict__ ktab, GKtab km,
                                                      const double* __restrict__ scale) {
@@ -293,8 +297,9 @@ __global__ void __launch_bounds__(kGenThreads) kg_lines(cpx<T>* __restrict__ dat
   const int nt = blockDim.x;
   const int tot = g.nl * N;  // the full tile's indexing; lines past nl are skipped
   cpx<T>* twl = buf + tot;   // the twiddle table
-  cpx<T> twv[tw_pre<T>()];
-  tw_fetch<T, SMALL, tw_pre<T>()>(twv, tw, N);
+  constexpr int UT = tw_pre<T>() / 2;
+  cpx<T> twv[UT];
+  tw_fetch<T, SMALL, UT>(twv, tw, N);
   const bool packed = g.packed();
   cpx<T>* const run = data + (long long)l0 * N;  // the tile when packed
   for (int t0 = threadIdx.x; t0 < tot; t0 += kGenU * nt) {
@@ -321,7 +326,7 @@ __global__ void __launch_bounds__(kGenThreads) kg_lines(cpx<T>* __restrict__ dat
     for (int u = 0; u < kGenU; ++u)
       if (at[u] >= 0) buf[at[u]] = cpx<T>{vr[u], vi[u]};
   }
-  const cpx<T>* twu = tw_store<T, SMALL, tw_pre<T>()>(twl, twv, tw, N);
+  const cpx<T>* twu = tw_store<T, SMALL, UT>(twl, twv, tw, N);
   __syncthreads();
   if constexpr (KIND == GL_CONV) {
     gfft<T, false, EMAX, SMALL>(buf, nl, p, twu);
@@ -786,7 +791,7 @@ __global__ void __launch_bounds__(kThreads) kg_cn_lines(cpx<T>* __restrict__ dat
 
 // Crank-Nicolson sweep of a tile of lines of at most kTileMaxN points: the recurrences,
 // lane chunks and scans of kg_cn_lines, one wave per line, with the chunk's recurrence
-// values in registers (S <= kTileS rows per lane) and the factor table in LDS (the same
+// values in registers (S <= TS rows per lane: 8 or kTileS) and the factor table in LDS (the same
 // padded layout as the lines).  Tiles of strided lines take 16 (FP32) or 8 (FP64)
 // adjacent lines, 128-byte runs.
 // MODE 0: solve; 1: solve with the new-state sums part[2b], part[2b+1]; 2: those sums of
@@ -810,7 +815,7 @@ struct GNl {  // the nonlinear sub-step's inputs for the fused x sweep
   double* part;
 };
 
-template <typename T, int MODE, int NLM>
+template <typename T, int MODE, int NLM, int TS>
 __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* __restrict__ data,
                                                                 GLines g, FDiv fs,
                                                                 const cpx<T>* __restrict__ f,
@@ -826,8 +831,8 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
   const int tot = g.nl * N;  // the full tile's indexing; lines past nl are skipped
   cpx<T>* ps = reinterpret_cast<cpx<T>*>(lds_raw);   // nl lines of psi (then u)
   cpx<T>* fl = ps + (size_t)g.nl * LS;                // the factor table, one line
-  // values per thread per load round
-  constexpr int U = kGenU;
+  // values per thread per load round (FP64: half, for the registers)
+  constexpr int U = sizeof(T) == 4 ? kGenU : kGenU / 2;
   constexpr int UF = 4;  // factor-table values per thread fetched ahead of the tile
   double q7[7] = {0, 0, 0, 0, 0, 0, 0};
   [[maybe_unused]] T ts = (T)1;
@@ -936,7 +941,7 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
   double s0 = 0.0, s1 = 0.0;
   for (int line = wave; line < nl; line += nw) {
     cpx<T>* p = ps + line * LS + slot;
-    cpx<T> d[kTileS];
+    cpx<T> d[TS];
     if constexpr (MODE != 2) {
       const cpx<T>* fq = fl + slot;
       // forward, zero carry: local d and the chunk's product of g
@@ -945,7 +950,7 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
       if (!(i0 > 0 && cnt > 0)) pm = zero;
       cpx<T> pc = p[0];
 #pragma unroll
-      for (int j = 0; j < kTileS; ++j) {
+      for (int j = 0; j < TS; ++j) {
         if (j < cnt) {
           cpx<T> pn = p[j + 1 < cnt ? j + 1 : Sp];  // row N is none: zero
           if (i0 + j + 1 >= N) pn = zero;
@@ -969,7 +974,7 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
       cpx<T> carry = shfl_up_c(B, 1);   // d at the end of the previous chunk
       if (lane == 0) carry = zero;
 #pragma unroll
-      for (int j = 0; j < kTileS; ++j) {
+      for (int j = 0; j < TS; ++j) {
         if (j < cnt) {
           carry = scl(fq[j], (T)0.5) * carry;
           d[j] = d[j] + carry;
@@ -978,7 +983,7 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
       // backward, zero carry from the right: local e (kept in d)
       acc = zero;
 #pragma unroll
-      for (int j = kTileS - 1; j >= 0; --j) {
+      for (int j = TS - 1; j >= 0; --j) {
         if (j < cnt) {
           acc = d[j] + scl(fq[j], (T)0.5) * acc;
           d[j] = acc;
@@ -996,7 +1001,7 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
       carry = shfl_down_c(B, 1);         // e at the start of the next chunk
       if (lane == 63) carry = zero;
 #pragma unroll
-      for (int j = kTileS - 1; j >= 0; --j) {
+      for (int j = TS - 1; j >= 0; --j) {
         if (j < cnt) {
           carry = scl(fq[j], (T)0.5) * carry;
           d[j] = p[j] + (d[j] + carry);   // u
@@ -1005,7 +1010,7 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
       }
     } else {
 #pragma unroll
-      for (int j = 0; j < kTileS; ++j)
+      for (int j = 0; j < TS; ++j)
         if (j < cnt) d[j] = p[j];
     }
     if constexpr (MODE != 0) {
@@ -1014,7 +1019,7 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
       const cpx<T> unext = shfl_down_c(d[0], 1);
       cpx<T> prev = zero;
 #pragma unroll
-      for (int j = 0; j < kTileS; ++j) {
+      for (int j = 0; j < TS; ++j) {
         if (j < cnt) {
           s0 += abs2_d(d[j]);
           if (j > 0) s1 += absdiff2_d(d[j], prev);

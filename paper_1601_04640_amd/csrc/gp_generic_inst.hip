@@ -74,11 +74,16 @@ hipError_t GLaunch<T>::prepare() {
   }
   // the tile sweeps: up to 16 padded lines and the factor table, beside 896 bytes of
   // static reduction space
-  const void* kt[] = {reinterpret_cast<const void*>(&kg_cn_tile<T, 0, -1>),
-                      reinterpret_cast<const void*>(&kg_cn_tile<T, 1, -1>),
-                      reinterpret_cast<const void*>(&kg_cn_tile<T, 2, -1>),
-                      reinterpret_cast<const void*>(&kg_cn_tile<T, 0, MODE_IMAG>),
-                      reinterpret_cast<const void*>(&kg_cn_tile<T, 0, MODE_REAL>)};
+  const void* kt[] = {reinterpret_cast<const void*>(&kg_cn_tile<T, 0, -1, 8>),
+                      reinterpret_cast<const void*>(&kg_cn_tile<T, 1, -1, 8>),
+                      reinterpret_cast<const void*>(&kg_cn_tile<T, 2, -1, 8>),
+                      reinterpret_cast<const void*>(&kg_cn_tile<T, 0, MODE_IMAG, 8>),
+                      reinterpret_cast<const void*>(&kg_cn_tile<T, 0, MODE_REAL, 8>),
+                      reinterpret_cast<const void*>(&kg_cn_tile<T, 0, -1, kTileS>),
+                      reinterpret_cast<const void*>(&kg_cn_tile<T, 1, -1, kTileS>),
+                      reinterpret_cast<const void*>(&kg_cn_tile<T, 2, -1, kTileS>),
+                      reinterpret_cast<const void*>(&kg_cn_tile<T, 0, MODE_IMAG, kTileS>),
+                      reinterpret_cast<const void*>(&kg_cn_tile<T, 0, MODE_REAL, kTileS>)};
   for (const void* k : kt) {
     const hipError_t e =
         hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kTileLds);
@@ -155,9 +160,15 @@ hipError_t launch_tile(hipStream_t st, cpx<T>* data, const GLines& g, FDiv fs,
                        const cpx<T>* f, double* part, const GNl& nlz) {
   const int blocks = (g.nlines + g.nl - 1) / g.nl;
   const size_t lds = lds_of((g.nl + 1) * cn_line_slots(g.n));
-  if (lds > (size_t)kTileLds || g.nl > tile_max_waves<T>()) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((kg_cn_tile<T, MODE, NLM>), dim3(blocks), dim3(64 * g.nl), lds, st, data,
-                     g, fs, f, part, nlz);
+  if (lds > (size_t)kTileLds || g.nl > tile_max_waves<T>() || g.n > kTileMaxN)
+    return hipErrorInvalidValue;
+  // lines of up to 512 points: at most 8 rows per lane (fewer registers)
+  if (g.n <= 64 * 8)
+    hipLaunchKernelGGL((kg_cn_tile<T, MODE, NLM, 8>), dim3(blocks), dim3(64 * g.nl), lds, st,
+                       data, g, fs, f, part, nlz);
+  else
+    hipLaunchKernelGGL((kg_cn_tile<T, MODE, NLM, kTileS>), dim3(blocks), dim3(64 * g.nl), lds,
+                       st, data, g, fs, f, part, nlz);
   return hipGetLastError();
 }
 
