@@ -144,12 +144,16 @@ Layout make_layout(const gp_params* p, unsigned host = 0) {
     L.nb_col = p->geom == GP_3D
                    ? (fp64 ? GLaunch<double>::cn_blocks(L.n2, L.n0 * L.n1, true)
                            : GLaunch<float>::cn_blocks(L.n2, L.n0 * L.n1, true))
-                   : (fp64 ? GLaunch<double>::cn_blocks(L.n1, L.n0, true)
-                           : GLaunch<float>::cn_blocks(L.n1, L.n0, true));
-    // scratch of the one-thread-per-line sweeps (3D grids whose y or z sweep has many
-    // lines longer than a tile)
-    L.gscr = p->geom == GP_3D && (GLaunch<float>::cn_by_columns(L.n1, true, L.n0 * L.n2) ||
-                                  GLaunch<float>::cn_by_columns(L.n2, true, L.n0 * L.n1));
+                   : (fp64 ? GLaunch<double>::cn_blocks(
+                                     L.n1, L.n0, !GLaunch<double>::y2d_transposed(L.n1))
+                           : GLaunch<float>::cn_blocks(
+                                     L.n1, L.n0, !GLaunch<float>::y2d_transposed(L.n1)));
+    // a scratch grid for the one-thread-per-line sweeps (3D grids whose y or z sweep has
+    // many lines longer than a tile) and for the transposed 2D y sweep of long lines
+    L.gscr = p->geom == GP_3D
+                 ? (GLaunch<float>::cn_by_columns(L.n1, true, L.n0 * L.n2) ||
+                    GLaunch<float>::cn_by_columns(L.n2, true, L.n0 * L.n1))
+                 : GLaunch<float>::y2d_transposed(L.n1);
   } else {
     const int tj = tj_of(fp64, L.n0);
     L.nb_x = ((L.n1 + tj - 1) / tj) * L.n2;
@@ -443,6 +447,13 @@ struct Passes {
     if (axis == 0)  // lines (j, k2), contiguous
       return dev(GLaunch<T>::cn_lines(mode, c->st, psi(c), L.n0, L.n1 * L.n2, 1, L.n0, 0, 1,
                                       f, pc, dscr));
+    if (axis == 1 && c->p.geom != GP_3D && GLaunch<T>::y2d_transposed(L.n1)) {
+      // 2D lines longer than a tile: the sweep runs along the rows of the transposed state
+      // (scratch grid, n0 rows of n1) and the result is transposed back
+      GP_HIP(GLaunch<T>::transpose(c->st, psi(c), dscr, L.n1, L.n0));
+      GP_HIP(GLaunch<T>::cn_lines(mode, c->st, dscr, L.n1, L.n0, 1, L.n1, 0, 1, f, pc, nullptr));
+      return dev(GLaunch<T>::transpose(c->st, dscr, psi(c), L.n0, L.n1));
+    }
     if (axis == 1)  // lines (i, k2) along y: base k2 n0 n1 + i, stride n0
       return dev(GLaunch<T>::cn_lines(mode, c->st, psi(c), L.n1, L.n0 * L.n2, L.n0, plane, 1,
                                       L.n0, f, pc, dscr));

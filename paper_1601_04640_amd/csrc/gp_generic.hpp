@@ -11,15 +11,16 @@
 //   kg_lines        line FFTs of the half spectrum (forward, inverse, or forward + U(k)
 //                   product + inverse, the convolution along the last axis)
 //   kg_c2r_x        x complex-to-real FFT -> Phi (a real grid)
-//   kg_nonlinear    psi <- scale psi exp(-eps dt (V + g_c n + g_dd Phi)) in place, with the
-//                   norm / potential / contact / dipolar / rms sums
-//   kg_cn_lines     Crank-Nicolson sweep of lines held in LDS, one wave per line (a
-//                   chunked scan of the Thomas recurrences): x lines, and strided lines
-//                   when there are few of them; optionally with the norm and difference
-//                   sums of the new state
+//   kg_nonlinear    the norm / potential / contact / dipolar / rms sums of the stored
+//                   state (observables; it can also apply the sub-step in place)
+//   kg_cn_tile      Crank-Nicolson sweep of a tile of lines held in LDS, one or more
+//                   waves per line (a chunked scan of the Thomas recurrences with the
+//                   chunks' values in registers); the x sweep with the nonlinear
+//                   sub-step applied as it loads; optionally with the norm and
+//                   difference sums of the new state
 //   kg_cn_cols      the same sweep, one thread per strided line with the recurrence
-//                   values in a scratch grid: strided axes with many lines, where
-//                   consecutive threads read consecutive addresses
+//                   values in a scratch grid: strided axes of more than 1024 points with
+//                   many lines, where consecutive threads read consecutive addresses
 // The partial sums have the meaning the FP64 finalisation reads (gp_finalize.hpp).
 #pragma once
 #include "gp_device.hpp"
@@ -632,175 +633,40 @@ __device__ __forceinline__ cpx<T> shfl_down_c(cpx<T> v, int off) {
   return cpx<T>{__shfl_down(v.re, off, 64), __shfl_down(v.im, off, 64)};
 }
 
-// Crank-Nicolson sweep of lines held in LDS, one 64-lane wave per line.  In increment
-// form, with Delta_i = psi_(i-1) + psi_(i+1) - 2 psi_i and the factor table
-// f_i = 2 A m_i (Thomas factors m of (1 + 2A) u_i - A (u_(i-1) + u_(i+1)); f = 0 on the
-// two boundary rows), g_i = f_i / 2:
+// Crank-Nicolson sweeps of lines.  In increment form, with
+// Delta_i = psi_(i-1) + psi_(i+1) - 2 psi_i and the factor table f_i = 2 A m_i (Thomas
+// factors m of (1 + 2A) u_i - A (u_(i-1) + u_(i+1)); f = 0 on the two boundary rows),
+// g_i = f_i / 2:
 //   forward  d_i = f_i Delta_i + g_i d_(i-1)      backward  e_i = d_i + g_i e_(i+1)
 //   u_i = psi_i + e_i.
-// Both are first-order linear recurrences.  Lane q takes the chunk of S = ceil(N/64)
-// consecutive rows, runs the recurrence from a zero carry, and the lanes' chunks are
-// joined by a scan of the affine maps c -> (prod g) c + (local result) across the wave;
-// each lane then adds its carry times the running product of g.  The result equals the
-// sequential recurrence up to rounding order.
-// LDS layout of a line: lane q's rows sit at [q Sp, q Sp + S) with Sp = S | 1 (odd), so
-// the 64 lanes reading the j-th rows of their chunks touch distinct bank pairs; a line
-// takes ceil(N/S) Sp values (cn_line_slots; lanes past the last chunk own none), psi and
-// d one buffer each.
-// MODE 0: solve; 1: solve, then part[2b] = sum |u|^2, part[2b+1] = sum |u_(i+1) - u_i|^2
-// of the new state; 2: those sums of the stored state, no solve.
-__host__ __device__ inline int cn_line_slots(int n) {
-  const int S = (n + 63) / 64;
+// Both are first-order linear recurrences.  Each lane takes a chunk of S consecutive
+// rows, runs the recurrence from a zero carry, and the chunks are joined by a scan of the
+// affine maps c -> (prod g) c + (local result); each lane then adds its carry times the
+// running product of g.  The result equals the sequential recurrence up to rounding
+// order.
+// LDS layout of a line spread over `lanes` lanes (S = ceil(N/lanes)): lane q's rows sit
+// at [q Sp, q Sp + S) with Sp = S | 1 (odd), so lanes reading the j-th rows of their
+// chunks touch distinct bank pairs; a line takes ceil(N/S) Sp values (lanes past the
+// last chunk own none).
+__host__ __device__ inline int cn_line_slots(int n, int lanes = 64) {
+  const int S = (n + lanes - 1) / lanes;
   return ((n + S - 1) / S) * (S | 1);
 }
 
-template <typename T, int MODE>
-__global__ void __launch_bounds__(kThreads) kg_cn_lines(cpx<T>* __restrict__ data, GLines g,
-                                                        FDiv fs,
-                                                        const cpx<T>* __restrict__ f,
-                                                        double* __restrict__ part) {
-  extern __shared__ __align__(16) char lds_raw[];
-  const int N = g.n;
-  const int S = (N + 63) / 64, Sp = S | 1, LS = cn_line_slots(N);
-  const int l0 = blockIdx.x * g.nl;
-  const int nl = min(g.nl, g.nlines - l0);
-  const int tot = g.nl * N;  // the full tile's indexing; lines past nl are skipped
-  cpx<T>* ps = reinterpret_cast<cpx<T>*>(lds_raw);   // nl lines of psi (then u)
-  cpx<T>* dv = ps + (size_t)g.nl * LS;                // nl lines of d
-  for (int t0 = threadIdx.x; t0 < tot; t0 += kGenU * kThreads) {
-    T vr[kGenU], vi[kGenU];
-    int at[kGenU];
-#pragma unroll
-    for (int u = 0; u < kGenU; ++u) {
-      const int t = t0 + u * kThreads;
-      const int2 le = g.tile_index(t);
-      const int line = le.x, e = le.y;
-      const int c = (int)fdiv((uint32_t)e, fs);
-      at[u] = (t < tot && line < nl) ? line * LS + c * Sp + (e - c * S) : -1;
-      if (at[u] >= 0) {
-        const cpx<T> v = data[g.addr(l0 + line, e)];
-        vr[u] = v.re;
-        vi[u] = v.im;
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < kGenU; ++u)
-      if (at[u] >= 0) ps[at[u]] = cpx<T>{vr[u], vi[u]};
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int i0 = lane * S;
-  const int cnt = min(S, N - i0);  // rows of this lane's chunk (<= 0: none)
-  const int slot = cnt > 0 ? lane * Sp : 0;  // lanes with no chunk point at the line start
-  const cpx<T> zero{0, 0};
-  double s0 = 0.0, s1 = 0.0;
-  if constexpr (MODE != 2) {
-    for (int line = wave; line < nl; line += kWaves) {
-      cpx<T>* p = ps + line * LS + slot;
-      cpx<T>* d = dv + line * LS + slot;
-      // forward, zero carry: local d and the chunk's product of g
-      cpx<T> acc = zero, prod = {1, 0};
-      // row i0 - 1 (the previous lane's last slot) and row i0; the loads stay inside the
-      // block's LDS and the selects act on values
-      cpx<T> pm = p[lane > 0 && cnt > 0 ? -Sp + S - 1 : 0];
-      if (!(i0 > 0 && cnt > 0)) pm = zero;
-      cpx<T> pc = p[0];
-#pragma unroll 4
-      for (int j = 0; j < cnt; ++j) {
-        const int i = i0 + j;
-        // the next row: this chunk's, or the next lane's first (row N is none: zero)
-        cpx<T> pn = p[j + 1 < cnt ? j + 1 : Sp];
-        if (i + 1 >= N) pn = zero;
-        const cpx<T> fi = f[i];
-        const cpx<T> gi = scl(fi, (T)0.5);
-        acc = fi * ((pm + pn) - (pc + pc)) + gi * acc;
-        prod = gi * prod;
-        d[j] = acc;
-        pm = pc;
-        pc = pn;
-      }
-      // inclusive scan of the maps c -> prod c + acc over the lanes
-      cpx<T> P = prod, B = acc;
-      for (int off = 1; off < 64; off <<= 1) {
-        const cpx<T> Pp = shfl_up_c(P, off), Bp = shfl_up_c(B, off);
-        if (lane >= off) {
-          B = P * Bp + B;
-          P = P * Pp;
-        }
-      }
-      cpx<T> carry = shfl_up_c(B, 1);   // d at the end of the previous chunk
-      if (lane == 0) carry = zero;
-#pragma unroll 4
-      for (int j = 0; j < cnt; ++j) {
-        carry = scl(f[i0 + j], (T)0.5) * carry;
-        d[j] = d[j] + carry;
-      }
-      // backward, zero carry from the right: local e (kept in d)
-      acc = zero;
-#pragma unroll 4
-      for (int j = cnt - 1; j >= 0; --j) {
-        acc = d[j] + scl(f[i0 + j], (T)0.5) * acc;
-        d[j] = acc;
-      }
-      P = prod;
-      B = acc;
-      for (int off = 1; off < 64; off <<= 1) {
-        const cpx<T> Pn = shfl_down_c(P, off), Bn = shfl_down_c(B, off);
-        if (lane + off < 64) {
-          B = P * Bn + B;
-          P = P * Pn;
-        }
-      }
-      carry = shfl_down_c(B, 1);         // e at the start of the next chunk
-      if (lane == 63) carry = zero;
-#pragma unroll 4
-      for (int j = cnt - 1; j >= 0; --j) {
-        carry = scl(f[i0 + j], (T)0.5) * carry;
-        p[j] = p[j] + (d[j] + carry);
-      }
-    }
-    __syncthreads();
-  }
-  if constexpr (MODE != 0) {
-    for (int line = wave; line < nl; line += kWaves) {
-      const cpx<T>* p = ps + line * LS + slot;
-      for (int j = 0; j < cnt; ++j) {
-        const cpx<T> pc = p[j];
-        s0 += abs2_d(pc);
-        const cpx<T> pn = p[j + 1 < cnt ? j + 1 : Sp];
-        if (i0 + j + 1 < N) s1 += absdiff2_d(pn, pc);
-      }
-    }
-    double s[2] = {s0, s1};
-    block_sum<2>(s, reinterpret_cast<double*>(dv));   // d is no longer needed
-    if (threadIdx.x == 0) {
-      part[2 * blockIdx.x] = s[0];
-      part[2 * blockIdx.x + 1] = s[1];
-    }
-  }
-  if constexpr (MODE != 2) {
-    for (int t = threadIdx.x; t < tot; t += kThreads) {
-      const int2 le = g.tile_index(t);
-      if (le.x < nl) {
-        const int c = (int)fdiv((uint32_t)le.y, fs);
-        data[g.addr(l0 + le.x, le.y)] = ps[le.x * LS + c * Sp + (le.y - c * S)];
-      }
-    }
-  }
-}
-
-// Crank-Nicolson sweep of a tile of lines of at most kTileMaxN points: the recurrences,
-// lane chunks and scans of kg_cn_lines, one wave per line, with the chunk's recurrence
-// values in registers (S <= TS rows per lane: 8 or kTileS) and the factor table in LDS (the same
-// padded layout as the lines).  Tiles of strided lines take 16 (FP32) or 8 (FP64)
-// adjacent lines, 128-byte runs.
+// Crank-Nicolson sweep of a tile of lines: the recurrences and chunked scans above, with
+// wpl waves per line (64 wpl lanes; wpl = 1 for lines of up to 1024
+// points, up to 16 for 8192), the chunk's recurrence values in registers (S <= TS rows
+// per lane) and the factor table in LDS, laid out like the lines.  With wpl > 1 the waves'
+// affine maps are composed through LDS after the in-wave scans: the carry into wave w of
+// a line is the composition of the totals of waves 0..w-1 (forward) or w+1..wpl-1
+// (backward).  Strided tiles take adjacent lines (64-byte runs).
 // MODE 0: solve; 1: solve with the new-state sums part[2b], part[2b+1]; 2: those sums of
 // the stored state, no solve.
 // NLM = MODE_IMAG or MODE_REAL (x lines only: G = 1, so = n0, se = 1): the nonlinear
 // sub-step of kg_nonlinear applied to each value as it is loaded, with its seven sums of
 // the incoming state in pnl[7b ...]; NLM < 0: none.
 constexpr int kTileS = 16;
-constexpr int kTileMaxN = 64 * kTileS;
+constexpr int kTileMaxN = 64 * kTileS;   // longest line at one wave per line
 constexpr int kTileMaxWaves = 16;
 // waves per tile block: 16 FP32, 8 FP64 (whose recurrence values need up to 256 VGPRs)
 template <typename T>
@@ -817,17 +683,18 @@ struct GNl {  // the nonlinear sub-step's inputs for the fused x sweep
 
 template <typename T, int MODE, int NLM, int TS>
 __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* __restrict__ data,
-                                                                GLines g, FDiv fs,
+                                                                GLines g, int wpl, FDiv fs,
                                                                 const cpx<T>* __restrict__ f,
                                                                 double* __restrict__ part,
                                                                 GNl nlz) {
   extern __shared__ __align__(16) char lds_raw[];
   __shared__ double red[7 * kTileMaxWaves];
+  __shared__ cpx<T> wP[kTileMaxWaves], wB[kTileMaxWaves];  // the waves' composed maps
   const int N = g.n;
-  const int S = (N + 63) / 64, Sp = S | 1, LS = cn_line_slots(N);
+  const int S = (int)fs.d, Sp = S | 1, LS = cn_line_slots(N, 64 * wpl);
   const int l0 = blockIdx.x * g.nl;
   const int nl = min(g.nl, g.nlines - l0);
-  const int nt = blockDim.x, nw = nt >> 6;
+  const int nt = blockDim.x;
   const int tot = g.nl * N;  // the full tile's indexing; lines past nl are skipped
   cpx<T>* ps = reinterpret_cast<cpx<T>*>(lds_raw);   // nl lines of psi (then u)
   cpx<T>* fl = ps + (size_t)g.nl * LS;                // the factor table, one line
@@ -846,11 +713,11 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
       fpre[u] = f[t < N ? t : 0];
     }
   }
-  // packed tiles are one contiguous range; in strided tiles (element-major, blockDim =
-  // 64 nl) thread tid keeps line tid mod nl and walks its elements 64 apart, so its line's
-  // base address is computed once
+  // packed tiles are one contiguous range; in strided tiles (element-major, blockDim a
+  // multiple of nl) thread tid keeps line tid mod nl and walks its elements nt/nl apart,
+  // so its line's base address is computed once
   const bool packed = g.packed();
-  const int sl = threadIdx.x % g.nl, se0 = threadIdx.x / g.nl;
+  const int sl = threadIdx.x % g.nl, se0 = threadIdx.x / g.nl, sstep = nt / g.nl;
   const long long sbase = !packed && sl < nl ? g.addr(l0 + sl, 0) : 0;
   const long long pbase = (long long)l0 * N;
   for (int t0 = threadIdx.x, r0 = 0; t0 < tot; t0 += U * nt, r0 += U) {
@@ -868,7 +735,7 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
         a = pbase + t;
       } else {
         line = sl;
-        e = se0 + 64 * (r0 + u);
+        e = se0 + sstep * (r0 + u);
         a = sbase + (long long)e * g.se;
       }
       const int c = (int)fdiv((uint32_t)e, fs);
@@ -933,103 +800,126 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
     }
   }
   __syncthreads();
+  // wave w works on line w / wpl, lanes q = 64 (w mod wpl) + lane of it
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int i0 = lane * S;
-  const int cnt = min(S, N - i0);  // rows of this lane's chunk (<= 0: none)
-  const int slot = cnt > 0 ? lane * Sp : 0;  // lanes with no chunk point at the line start
+  const int line = wave / wpl, sub = wave - line * wpl;
+  const bool act = line < nl;
+  const int q = sub * 64 + lane;
+  const int i0 = q * S;
+  const int cnt = act ? min(S, N - i0) : 0;  // rows of this lane's chunk (<= 0: none)
+  const int slot = cnt > 0 ? q * Sp : 0;     // lanes with no chunk point at the line start
   const cpx<T> zero{0, 0};
   double s0 = 0.0, s1 = 0.0;
-  for (int line = wave; line < nl; line += nw) {
-    cpx<T>* p = ps + line * LS + slot;
-    cpx<T> d[TS];
-    if constexpr (MODE != 2) {
-      const cpx<T>* fq = fl + slot;
-      // forward, zero carry: local d and the chunk's product of g
-      cpx<T> acc = zero, prod = {1, 0};
-      cpx<T> pm = p[lane > 0 && cnt > 0 ? -Sp + S - 1 : 0];   // row i0 - 1
-      if (!(i0 > 0 && cnt > 0)) pm = zero;
-      cpx<T> pc = p[0];
+  cpx<T>* p = ps + (act ? line : 0) * LS + slot;
+  cpx<T> d[TS];
+  if constexpr (MODE != 2) {
+    const cpx<T>* fq = fl + slot;
+    // forward, zero carry: local d and the chunk's product of g
+    cpx<T> acc = zero, prod = {1, 0};
+    cpx<T> pm = p[q > 0 && cnt > 0 ? -Sp + S - 1 : 0];   // row i0 - 1
+    if (!(i0 > 0 && cnt > 0)) pm = zero;
+    cpx<T> pc = p[0];
 #pragma unroll
-      for (int j = 0; j < TS; ++j) {
-        if (j < cnt) {
-          cpx<T> pn = p[j + 1 < cnt ? j + 1 : Sp];  // row N is none: zero
-          if (i0 + j + 1 >= N) pn = zero;
-          const cpx<T> fi = fq[j];
-          acc = fi * ((pm + pn) - (pc + pc)) + scl(fi, (T)0.5) * acc;
-          prod = scl(fi, (T)0.5) * prod;
-          d[j] = acc;
-          pm = pc;
-          pc = pn;
-        }
+    for (int j = 0; j < TS; ++j) {
+      if (j < cnt) {
+        cpx<T> pn = p[j + 1 < cnt ? j + 1 : Sp];  // row N is none: zero
+        if (i0 + j + 1 >= N) pn = zero;
+        const cpx<T> fi = fq[j];
+        acc = fi * ((pm + pn) - (pc + pc)) + scl(fi, (T)0.5) * acc;
+        prod = scl(fi, (T)0.5) * prod;
+        d[j] = acc;
+        pm = pc;
+        pc = pn;
       }
-      // inclusive scan of the maps c -> prod c + acc over the lanes
-      cpx<T> P = prod, B = acc;
-      for (int off = 1; off < 64; off <<= 1) {
-        const cpx<T> Pp = shfl_up_c(P, off), Bp = shfl_up_c(B, off);
-        if (lane >= off) {
-          B = P * Bp + B;
-          P = P * Pp;
-        }
-      }
-      cpx<T> carry = shfl_up_c(B, 1);   // d at the end of the previous chunk
-      if (lane == 0) carry = zero;
-#pragma unroll
-      for (int j = 0; j < TS; ++j) {
-        if (j < cnt) {
-          carry = scl(fq[j], (T)0.5) * carry;
-          d[j] = d[j] + carry;
-        }
-      }
-      // backward, zero carry from the right: local e (kept in d)
-      acc = zero;
-#pragma unroll
-      for (int j = TS - 1; j >= 0; --j) {
-        if (j < cnt) {
-          acc = d[j] + scl(fq[j], (T)0.5) * acc;
-          d[j] = acc;
-        }
-      }
-      P = prod;
-      B = acc;
-      for (int off = 1; off < 64; off <<= 1) {
-        const cpx<T> Pn = shfl_down_c(P, off), Bn = shfl_down_c(B, off);
-        if (lane + off < 64) {
-          B = P * Bn + B;
-          P = P * Pn;
-        }
-      }
-      carry = shfl_down_c(B, 1);         // e at the start of the next chunk
-      if (lane == 63) carry = zero;
-#pragma unroll
-      for (int j = TS - 1; j >= 0; --j) {
-        if (j < cnt) {
-          carry = scl(fq[j], (T)0.5) * carry;
-          d[j] = p[j] + (d[j] + carry);   // u
-          p[j] = d[j];
-        }
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < TS; ++j)
-        if (j < cnt) d[j] = p[j];
     }
-    if constexpr (MODE != 0) {
-      // sums of u (or of the stored state): |u|^2 and the differences, the last one with
-      // the next lane's first row
-      const cpx<T> unext = shfl_down_c(d[0], 1);
-      cpx<T> prev = zero;
-#pragma unroll
-      for (int j = 0; j < TS; ++j) {
-        if (j < cnt) {
-          s0 += abs2_d(d[j]);
-          if (j > 0) s1 += absdiff2_d(d[j], prev);
-          prev = d[j];
-        }
+    // inclusive scan of the maps c -> prod c + acc over the wave's lanes
+    cpx<T> P = prod, B = acc;
+    for (int off = 1; off < 64; off <<= 1) {
+      const cpx<T> Pp = shfl_up_c(P, off), Bp = shfl_up_c(B, off);
+      if (lane >= off) {
+        B = P * Bp + B;
+        P = P * Pp;
       }
-      if (cnt > 0 && i0 + cnt < N) s1 += absdiff2_d(unext, prev);
     }
+    // d entering the wave: the earlier waves' totals composed in order
+    cpx<T> C = zero;
+    if (wpl > 1) {
+      if (lane == 63) {
+        wP[wave] = P;
+        wB[wave] = B;
+      }
+      __syncthreads();
+      for (int s2 = 0; s2 < sub; ++s2) C = wP[wave - sub + s2] * C + wB[wave - sub + s2];
+      __syncthreads();  // the totals are read before the backward pass writes its own
+    }
+    const cpx<T> Pu = shfl_up_c(P, 1), Bu = shfl_up_c(B, 1);
+    cpx<T> carry = lane == 0 ? C : Pu * C + Bu;   // d at the end of the previous chunk
+#pragma unroll
+    for (int j = 0; j < TS; ++j) {
+      if (j < cnt) {
+        carry = scl(fq[j], (T)0.5) * carry;
+        d[j] = d[j] + carry;
+      }
+    }
+    // backward, zero carry from the right: local e (kept in d)
+    acc = zero;
+#pragma unroll
+    for (int j = TS - 1; j >= 0; --j) {
+      if (j < cnt) {
+        acc = d[j] + scl(fq[j], (T)0.5) * acc;
+        d[j] = acc;
+      }
+    }
+    P = prod;
+    B = acc;
+    for (int off = 1; off < 64; off <<= 1) {
+      const cpx<T> Pn = shfl_down_c(P, off), Bn = shfl_down_c(B, off);
+      if (lane + off < 64) {
+        B = P * Bn + B;
+        P = P * Pn;
+      }
+    }
+    // e entering the wave from the right: the later waves' totals composed in order
+    cpx<T> E = zero;
+    if (wpl > 1) {
+      if (lane == 0) {
+        wP[wave] = P;
+        wB[wave] = B;
+      }
+      __syncthreads();
+      for (int s2 = wpl - 1; s2 > sub; --s2) E = wP[wave - sub + s2] * E + wB[wave - sub + s2];
+    }
+    const cpx<T> Pd = shfl_down_c(P, 1), Bd = shfl_down_c(B, 1);
+    carry = lane == 63 ? E : Pd * E + Bd;         // e at the start of the next chunk
+#pragma unroll
+    for (int j = TS - 1; j >= 0; --j) {
+      if (j < cnt) {
+        carry = scl(fq[j], (T)0.5) * carry;
+        d[j] = p[j] + (d[j] + carry);   // u
+        p[j] = d[j];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < TS; ++j)
+      if (j < cnt) d[j] = p[j];
   }
   if constexpr (MODE != 0) {
+    // sums of u (or of the stored state): |u|^2 and the differences, the last one with
+    // the next chunk's first row (the next lane's, or the next wave's lane 0 through LDS)
+    __syncthreads();
+    cpx<T> unext = shfl_down_c(d[0], 1);
+    if (lane == 63 && cnt > 0 && i0 + cnt < N) unext = p[Sp];
+    cpx<T> prev = zero;
+#pragma unroll
+    for (int j = 0; j < TS; ++j) {
+      if (j < cnt) {
+        s0 += abs2_d(d[j]);
+        if (j > 0) s1 += absdiff2_d(d[j], prev);
+        prev = d[j];
+      }
+    }
+    if (cnt > 0 && i0 + cnt < N) s1 += absdiff2_d(unext, prev);
     double sv[2] = {s0, s1};
     gblock_sum<2>(sv, red);
     if (threadIdx.x == 0) {
@@ -1042,33 +932,56 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
     gblock_sum<7>(q7, red);
     if (threadIdx.x == 0) {
 #pragma unroll
-      for (int q = 0; q < 7; ++q) nlz.part[7 * (long long)blockIdx.x + q] = q7[q];
+      for (int k = 0; k < 7; ++k) nlz.part[7 * (long long)blockIdx.x + k] = q7[k];
     }
   }
   if constexpr (MODE != 2) {
     __syncthreads();
     for (int t = threadIdx.x, r = 0; t < tot; t += nt, ++r) {
-      int line, e;
+      int ln, e;
       long long a;
       if (packed) {
-        line = (int)fdiv((uint32_t)t, g.fn);
-        e = t - line * N;
+        ln = (int)fdiv((uint32_t)t, g.fn);
+        e = t - ln * N;
         a = pbase + t;
       } else {
-        line = sl;
-        e = se0 + 64 * r;
+        ln = sl;
+        e = se0 + sstep * r;
         a = sbase + (long long)e * g.se;
       }
-      if (line < nl) {
+      if (ln < nl) {
         const int c = (int)fdiv((uint32_t)e, fs);
-        data[a] = ps[line * LS + c * Sp + (e - c * S)];
+        data[a] = ps[ln * LS + c * Sp + (e - c * S)];
       }
     }
   }
 }
 
-// Crank-Nicolson sweep of strided lines with many lines per sweep (3D y and z), one thread
-// per line (line l: element e at
+// Transpose of a rows x cols grid of complex values, out[c rows + r] = in[r cols + c],
+// through TT x TT LDS tiles padded by one column (reads and writes both along rows).
+template <typename T, int TT>
+__global__ void __launch_bounds__(kThreads) kg_transpose(const cpx<T>* __restrict__ in,
+                                                         cpx<T>* __restrict__ out, int rows,
+                                                         int cols) {
+  __shared__ cpx<T> tile[TT][TT + 1];
+  constexpr int RY = kThreads / TT;
+  const int c0 = blockIdx.x * TT, r0 = blockIdx.y * TT;
+  const int tx = threadIdx.x % TT, ty = threadIdx.x / TT;
+#pragma unroll
+  for (int k = ty; k < TT; k += RY) {
+    const int r = r0 + k, c = c0 + tx;
+    if (r < rows && c < cols) tile[k][tx] = in[(long long)r * cols + c];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = ty; k < TT; k += RY) {
+    const int c = c0 + k, r = r0 + tx;
+    if (r < rows && c < cols) out[(long long)c * rows + r] = tile[tx][k];
+  }
+}
+
+// Crank-Nicolson sweep of strided lines with many lines per sweep (3D y and z lines of
+// more than 1024 points), one thread per line (line l: element e at
 // (l / G) so + (l mod G) + e se, consecutive lines adjacent in memory).  In increment
 // form: with Delta_i = psi_(i-1) + psi_(i+1) - 2 psi_i and the factor table f_i = 2 A m_i
 // (Thomas factors m of (1 + 2A) u_i - A (u_(i-1) + u_(i+1)), zero on the boundary rows),

@@ -17,7 +17,7 @@ static_assert(kEmax * kGenThreads == gen_max_line<T>(), "one block holds the lon
 
 namespace {
 constexpr int kCnLds = 163840;  // LDS limit of the CN sweeps (160 KiB)
-constexpr int kTileLds = kCnLds - 1024;  // dynamic LDS of the tile sweeps (static: 896 B)
+constexpr int kTileLds = kCnLds - 2048;  // dynamic LDS of the tile sweeps (static: 1408 B)
 
 // lines per block of a line-FFT pass: about 2048 values (contiguous lines) or as many
 // lines as 64 KiB of LDS holds (strided lines: the longest contiguous runs), halved
@@ -63,17 +63,8 @@ hipError_t GLaunch<T>::prepare() {
     const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
   }
-  // the CN line sweeps hold two padded buffers of up to 65 KiB
-  const void* kc[] = {reinterpret_cast<const void*>(&kg_cn_lines<T, 0>),
-                      reinterpret_cast<const void*>(&kg_cn_lines<T, 1>),
-                      reinterpret_cast<const void*>(&kg_cn_lines<T, 2>)};
-  for (const void* k : kc) {
-    const hipError_t e =
-        hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kCnLds);
-    if (e != hipSuccess) return e;
-  }
-  // the tile sweeps: up to 16 padded lines and the factor table, beside 896 bytes of
-  // static reduction space
+  // the tile sweeps: up to 16 padded lines (or one line of 8192 FP32 / 4096 FP64 points)
+  // and the factor table, beside the static reduction and scan space
   const void* kt[] = {reinterpret_cast<const void*>(&kg_cn_tile<T, 0, -1, 8>),
                       reinterpret_cast<const void*>(&kg_cn_tile<T, 1, -1, 8>),
                       reinterpret_cast<const void*>(&kg_cn_tile<T, 2, -1, 8>),
@@ -122,53 +113,44 @@ int GLaunch<T>::x_blocks(int n0, int n1, int n2) {
 }
 
 template <>
-int GLaunch<T>::cn_lines_per_block(int n, int nlines, bool strided) {
-  // contiguous lines: at most 4096 values and 64 KiB of LDS per block (two blocks per
-  // CU), a whole number of waves' worth of lines; strided lines: 128-byte runs (16 FP32
-  // or 8 FP64 lines) within the LDS limit; both halved while the sweep would have fewer
-  // than 512 blocks (a line takes two padded buffers)
-  const int per_line = 2 * cn_line_slots(n) * (int)sizeof(cpx<T>);
-  const int cap = (strided ? kCnLds : 65536) / per_line;
-  int nl = strided ? 128 / (int)sizeof(cpx<T>) : 4096 / n;
-  if (nl > cap) nl = cap;
-  if (nl < 1) nl = 1;
-  if (!strided && nl >= kWaves) nl -= nl % kWaves;
-  while (nl > 1 && (nlines + nl - 1) / nl < 512) nl /= 2;
-  return nl;
-}
-
-template <>
 int GLaunch<T>::cn_tile_lines(int n, int nlines, bool strided) {
-  // one wave per line; strided tiles: 64-byte runs (8 FP32 or 4 FP64 lines, kept), contiguous
-  // lines: 8 lines, at most 52 KiB of LDS (two blocks per CU at the kernels' register use);
-  // halved while the sweep would have fewer than 512 blocks; the tile and the factor table
-  // fit the LDS
-  const int per_line = cn_line_slots(n) * (int)sizeof(cpx<T>);
+  // wpl waves per line; strided tiles: 64-byte runs (8 FP32 or 4 FP64 lines, kept),
+  // contiguous lines: 8 lines, at most 52 KiB of LDS (two blocks per CU at the kernels'
+  // register use); at most tile_max_waves waves per block; halved while the sweep would
+  // have fewer than 512 blocks; the tile and the factor table fit the LDS
+  const int wpl = cn_tile_wpl(n);
+  const int per_line = cn_line_slots(n, 64 * wpl) * (int)sizeof(cpx<T>);
   int nl = strided ? 64 / (int)sizeof(cpx<T>) : 53248 / per_line;
   if (!strided && nl > 8) nl = 8;
   const int cap = kTileLds / per_line - 1;
   if (nl > cap) nl = cap;
-  if (nl > tile_max_waves<T>()) nl = tile_max_waves<T>();
+  if (nl > tile_max_waves<T>() / wpl) nl = tile_max_waves<T>() / wpl;
   if (nl < 1) nl = 1;
   while (nl > (strided ? 4 : 1) && (nlines + nl - 1) / nl < 512) nl /= 2;
+  if (nl * wpl > tile_max_waves<T>()) nl = 1;
   return nl;
 }
 
 namespace {
+constexpr int kTransTile = 32;  // transpose tiles of 32 x 32 values, 256 threads
+
 template <int MODE, int NLM>
-hipError_t launch_tile(hipStream_t st, cpx<T>* data, const GLines& g, FDiv fs,
+hipError_t launch_tile(hipStream_t st, cpx<T>* data, const GLines& g, int wpl,
                        const cpx<T>* f, double* part, const GNl& nlz) {
   const int blocks = (g.nlines + g.nl - 1) / g.nl;
-  const size_t lds = lds_of((g.nl + 1) * cn_line_slots(g.n));
-  if (lds > (size_t)kTileLds || g.nl > tile_max_waves<T>() || g.n > kTileMaxN)
+  const int S = (g.n + 64 * wpl - 1) / (64 * wpl);
+  const size_t lds = lds_of((g.nl + 1) * cn_line_slots(g.n, 64 * wpl));
+  if (lds > (size_t)kTileLds || g.nl * wpl > tile_max_waves<T>() || S > kTileS)
     return hipErrorInvalidValue;
-  // lines of up to 512 points: at most 8 rows per lane (fewer registers)
-  if (g.n <= 64 * 8)
-    hipLaunchKernelGGL((kg_cn_tile<T, MODE, NLM, 8>), dim3(blocks), dim3(64 * g.nl), lds, st,
-                       data, g, fs, f, part, nlz);
+  const FDiv fs = fdiv_make((uint32_t)S);
+  const dim3 threads(64 * wpl * g.nl);
+  // at most 8 rows per lane: fewer registers
+  if (S <= 8)
+    hipLaunchKernelGGL((kg_cn_tile<T, MODE, NLM, 8>), dim3(blocks), threads, lds, st, data, g,
+                       wpl, fs, f, part, nlz);
   else
-    hipLaunchKernelGGL((kg_cn_tile<T, MODE, NLM, kTileS>), dim3(blocks), dim3(64 * g.nl), lds,
-                       st, data, g, fs, f, part, nlz);
+    hipLaunchKernelGGL((kg_cn_tile<T, MODE, NLM, kTileS>), dim3(blocks), threads, lds, st,
+                       data, g, wpl, fs, f, part, nlz);
   return hipGetLastError();
 }
 
@@ -189,13 +171,23 @@ GLines tile_lines(int n, int nlines, int nl, int G, long long so, long long si, 
 }  // namespace
 
 template <>
+hipError_t GLaunch<T>::transpose(hipStream_t st, const cpx<T>* in, cpx<T>* out, int rows,
+                                 int cols) {
+  if (rows < 1 || cols < 1) return hipErrorInvalidValue;
+  const dim3 grid((cols + kTransTile - 1) / kTransTile, (rows + kTransTile - 1) / kTransTile);
+  hipLaunchKernelGGL((kg_transpose<T, kTransTile>), grid, dim3(kThreads), 0, st, in, out,
+                     rows, cols);
+  return hipGetLastError();
+}
+
+template <>
 hipError_t GLaunch<T>::cn_x_nonlinear(int mode, hipStream_t st, cpx<T>* psi, int n0, int lines,
                                       const cpx<T>* f, const GNl& nlz) {
-  if (n0 > kTileMaxN || lines < 1) return hipErrorInvalidValue;
+  if (n0 > gen_max_line<T>() || lines < 1) return hipErrorInvalidValue;
   const GLines g = tile_lines(n0, lines, cn_tile_lines(n0, lines, false), 1, n0, 0, 1);
-  const FDiv fs = fdiv_make((uint32_t)((n0 + 63) / 64));
-  if (mode == MODE_IMAG) return launch_tile<0, MODE_IMAG>(st, psi, g, fs, f, nullptr, nlz);
-  if (mode == MODE_REAL) return launch_tile<0, MODE_REAL>(st, psi, g, fs, f, nullptr, nlz);
+  const int wpl = cn_tile_wpl(n0);
+  if (mode == MODE_IMAG) return launch_tile<0, MODE_IMAG>(st, psi, g, wpl, f, nullptr, nlz);
+  if (mode == MODE_REAL) return launch_tile<0, MODE_REAL>(st, psi, g, wpl, f, nullptr, nlz);
   return hipErrorInvalidValue;
 }
 
@@ -293,17 +285,6 @@ hipError_t GLaunch<T>::cn_lines(int mode, hipStream_t st, cpx<T>* data, int n, i
                                 int G, long long so, long long si, long long se,
                                 const cpx<T>* f, double* part, cpx<T>* dscr) {
   if (n > gen_max_line<T>() || nlines < 1) return hipErrorInvalidValue;
-  if (n <= kTileMaxN) {
-    const GLines g = tile_lines(n, nlines, cn_tile_lines(n, nlines, se != 1), G, so, si, se);
-    const FDiv fs = fdiv_make((uint32_t)((n + 63) / 64));
-    const GNl none{};
-    switch (mode) {
-      case 0: return launch_tile<0, -1>(st, data, g, fs, f, part, none);
-      case 1: return launch_tile<1, -1>(st, data, g, fs, f, part, none);
-      case 2: return launch_tile<2, -1>(st, data, g, fs, f, part, none);
-      default: return hipErrorInvalidValue;
-    }
-  }
   if (cn_by_columns(n, se != 1, nlines)) {
     // consecutive lines adjacent (si = 1): one thread per line
     if (si != 1) return hipErrorInvalidValue;
@@ -326,40 +307,15 @@ hipError_t GLaunch<T>::cn_lines(int mode, hipStream_t st, cpx<T>* data, int n, i
     }
     return hipGetLastError();
   }
-  GLines g{};
-  g.n = n;
-  g.nlines = nlines;
-  g.nl = cn_lines_per_block(n, nlines, se != 1);
-  g.G = G;
-  g.so = so;
-  g.si = si;
-  g.se = se;
-  g.fn = fdiv_make((uint32_t)n);
-  g.fnl = fdiv_make((uint32_t)g.nl);
-  g.fg = fdiv_make((uint32_t)G);
-  const FDiv fs = fdiv_make((uint32_t)((n + 63) / 64));
-  const int blocks = (nlines + g.nl - 1) / g.nl;
-  // psi lines, then the recurrence values, padded (a line takes cn_line_slots values;
-  // at least 64 of them, which holds the block reduction)
-  const size_t lds = 2 * lds_of(g.nl * cn_line_slots(n));
-  if (lds > (size_t)kCnLds) return hipErrorInvalidValue;
+  const GLines g = tile_lines(n, nlines, cn_tile_lines(n, nlines, se != 1), G, so, si, se);
+  const int wpl = cn_tile_wpl(n);
+  const GNl none{};
   switch (mode) {
-    case 0:
-      hipLaunchKernelGGL((kg_cn_lines<T, 0>), dim3(blocks), dim3(kThreads), lds, st, data, g,
-                         fs, f, part);
-      break;
-    case 1:
-      hipLaunchKernelGGL((kg_cn_lines<T, 1>), dim3(blocks), dim3(kThreads), lds, st, data, g,
-                         fs, f, part);
-      break;
-    case 2:
-      hipLaunchKernelGGL((kg_cn_lines<T, 2>), dim3(blocks), dim3(kThreads), lds, st, data, g,
-                         fs, f, part);
-      break;
-    default:
-      return hipErrorInvalidValue;
+    case 0: return launch_tile<0, -1>(st, data, g, wpl, f, part, none);
+    case 1: return launch_tile<1, -1>(st, data, g, wpl, f, part, none);
+    case 2: return launch_tile<2, -1>(st, data, g, wpl, f, part, none);
+    default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 }  // namespace gpdbec

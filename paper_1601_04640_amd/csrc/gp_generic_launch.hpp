@@ -25,8 +25,8 @@ inline bool gen_size_ok(int n) {
 
 template <typename T>
 struct GLaunch {
-  // raises the dynamic LDS limit of the LDS-FFT kernels to 64 KiB and of the CN sweeps to
-  // 160 KiB (once per process; called when a context is created, never inside a graph
+  // raises the dynamic LDS limit of the LDS-FFT kernels to 128 KiB and of the CN sweeps to
+  // 159 KiB (once per process; called when a context is created, never inside a graph
   // capture)
   static hipError_t prepare();
   // x passes: tile of the grid (line pairs per block) and its block count
@@ -36,25 +36,29 @@ struct GLaunch {
   static int nl_blocks(int n0, int n1, int n2) {
     return x_fused(n0) ? cn_blocks(n0, n1 * n2, false) : gen_nl_blocks((long long)n0 * n1 * n2);
   }
-  static int cn_lines_per_block(int n, int nlines, bool strided);
-  // lines of up to kTileMaxN points run kg_cn_tile (nl lines per block, one wave each)
+  // CN sweeps: kg_cn_tile with wpl waves per line (1 up to kTileMaxN points, then one
+  // lane per 8 rows) and cn_tile_lines lines per block, except strided sweeps of many
+  // lines longer than kTileMaxN, which run one thread per line (kg_cn_cols)
+  static int cn_tile_wpl(int n) {
+    int w = 1;
+    while (n > kTileMaxN && 64 * 8 * w < n) w *= 2;
+    return w;
+  }
   static int cn_tile_lines(int n, int nlines, bool strided);
-  // longer strided lines, with at least this many lines, run one thread per line
   static constexpr int kColLines = 32768;
   static bool cn_by_columns(int n, bool strided, int nlines) {
     return n > kTileMaxN && strided && nlines >= kColLines;
   }
   static int cn_blocks(int n, int nlines, bool strided) {
-    if (n <= kTileMaxN) {
-      const int nl = cn_tile_lines(n, nlines, strided);
-      return (nlines + nl - 1) / nl;
-    }
     if (cn_by_columns(n, strided, nlines)) return (nlines + kThreads - 1) / kThreads;
-    const int nl = cn_lines_per_block(n, nlines, strided);
+    const int nl = cn_tile_lines(n, nlines, strided);
     return (nlines + nl - 1) / nl;
   }
-  // the x sweep carries the nonlinear sub-step when its lines fit a tile
-  static bool x_fused(int n0) { return n0 <= kTileMaxN; }
+  // the x sweep carries the nonlinear sub-step (every supported length)
+  static bool x_fused(int n0) { return n0 <= gen_max_line<T>(); }
+  // 2D y sweeps of lines longer than kTileMaxN run on a transposed copy of the state
+  // (lines of the copy are contiguous), through the scratch grid
+  static bool y2d_transposed(int n1) { return n1 > kTileMaxN; }
 
   static hipError_t r2c_x(hipStream_t st, const cpx<T>* psi, cpx<T>* spec, const GPlan& p,
                           const cpx<T>* tw, double* part, int n0, int n1, int n2);
@@ -69,13 +73,16 @@ struct GLaunch {
                               const double* scale, const GStep& sc, int n0, int n1, int n2,
                               double* part);
   // CN sweep of nlines lines (addressing as `lines`); mode 0 solve, 1 solve + new-state
-  // sums, 2 sums of the stored state only
-  // (strided sweeps of many lines run kg_cn_cols, with dscr: a grid of scratch values)
+  // sums, 2 sums of the stored state only (strided sweeps of many long lines run
+  // kg_cn_cols, with dscr: a grid of scratch values)
   static hipError_t cn_lines(int mode, hipStream_t st, cpx<T>* data, int n, int nlines, int G,
                              long long so, long long si, long long se, const cpx<T>* f,
                              double* part, cpx<T>* dscr);
-  // the x sweep (lines (j, k) of n0 <= kTileMaxN points) with the nonlinear sub-step of
-  // MODE_IMAG / MODE_REAL fused into its loads; nlz.part: the nl_blocks seven-sum slots
+  // out[c rows + r] = in[r cols + c]: a rows x cols grid of complex values transposed
+  static hipError_t transpose(hipStream_t st, const cpx<T>* in, cpx<T>* out, int rows,
+                              int cols);
+  // the x sweep (lines (j, k) of n0 points) with the nonlinear sub-step of MODE_IMAG /
+  // MODE_REAL fused into its loads; nlz.part: the nl_blocks seven-sum slots
   static hipError_t cn_x_nonlinear(int mode, hipStream_t st, cpx<T>* psi, int n0, int lines,
                                    const cpx<T>* f, const GNl& nlz);
 };
@@ -84,7 +91,6 @@ struct GLaunch {
   template <> hipError_t GLaunch<T>::prepare();                                                \
   template <> GXTile GLaunch<T>::xtile(int, int, int);                                         \
   template <> int GLaunch<T>::x_blocks(int, int, int);                                         \
-  template <> int GLaunch<T>::cn_lines_per_block(int, int, bool);                              \
   template <> int GLaunch<T>::cn_tile_lines(int, int, bool);                                   \
   template <> hipError_t GLaunch<T>::r2c_x(hipStream_t, const cpx<T>*, cpx<T>*, const GPlan&, \
                                            const cpx<T>*, double*, int, int, int);             \
@@ -100,7 +106,8 @@ struct GLaunch {
                                               long long, long long, long long, const cpx<T>*, \
                                               double*, cpx<T>*);                               \
   template <> hipError_t GLaunch<T>::cn_x_nonlinear(int, hipStream_t, cpx<T>*, int, int,     \
-                                                    const cpx<T>*, const GNl&);
+                                                    const cpx<T>*, const GNl&);              \
+  template <> hipError_t GLaunch<T>::transpose(hipStream_t, const cpx<T>*, cpx<T>*, int, int);
 GP_DECLARE_GLAUNCH(float)
 GP_DECLARE_GLAUNCH(double)
 #undef GP_DECLARE_GLAUNCH

@@ -111,7 +111,8 @@ def test_random_field_start(prec, gpu_lib):
 
 @pytest.mark.parametrize("prec,n", [("fp32", 8192), ("fp64", 4096), ("fp64", 2 * 3 * 7 * 29)])
 def test_longest_lines(prec, n, gpu_lib):
-    """The longest x and y lines one block holds (and a 29-point radix) in 2D."""
+    """The longest x and y lines one block holds (and a 29-point radix) in 2D: x sweeps of
+    several waves per line, y sweeps on the transposed state."""
     from paper_1601_04640_amd.binding import Solver
     for nx, ny in ((n, 12), (12, n)):
         h = 25.6 / n
@@ -198,4 +199,31 @@ def test_every_specialised_length_in_every_role(n, prec, gpu_lib):
         s.set_psi(psi0)
         s.step_real(3)
         assert_psi_close(s.get_psi(), O.run(psi0, p, False, 3), bars(prec)[0], (n, role))
+        s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", [(12, 1100, 10), (10, 12, 1100), (1100, 10, 12)])
+def test_long_lines_3d(shape, prec, gpu_lib):
+    """3D lines longer than 1024 points (1100 = 2^2 5^2 11) along each axis: sweeps of
+    several waves per line over strided tiles of few lines, and the x sweep with the
+    nonlinear sub-step; imaginary and real time against the oracle."""
+    from paper_1601_04640_amd.binding import Solver
+    nx, ny, nz = shape
+    h = {a: (12.0 / n if n > 100 else 0.8) for a, n in zip("xyz", shape)}
+    w = dict(geom="3d", nx=nx, ny=ny, nz=nz, dx=h["x"], dy=h["y"], dz=h["z"], dt=0.001,
+             gamma=1.0, nu=1.2, lam=1.5, g=15.0, gdd=5.0, R=2.0)
+    banner("run-time-length sizes: long 3D lines", shape, prec)
+    p = oparams(w)
+    psi0 = I.random_complex(p.shape(), 507, p.dV())
+    for imag in (True, False):
+        s = Solver(w, prec=prec)
+        s.set_psi(psi0)
+        s.step_imag(3) if imag else s.step_real(3)
+        ref, hist = O.run(psi0, p, imag, 3, record=True)
+        ptol, etol = bars(prec)
+        assert_psi_close(s.get_psi(), ref, ptol, (shape, imag))
+        for k, (g_, r_) in enumerate(zip(s.history(3), hist)):
+            bad = obs_close(g_, r_, etol)
+            assert not bad, (shape, imag, k, bad)
         s.close()
