@@ -698,8 +698,9 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
   const int tot = g.nl * N;  // the full tile's indexing; lines past nl are skipped
   cpx<T>* ps = reinterpret_cast<cpx<T>*>(lds_raw);   // nl lines of psi (then u)
   cpx<T>* fl = ps + (size_t)g.nl * LS;                // the factor table, one line
-  // values per thread per load round (FP64: half, for the registers)
-  constexpr int U = sizeof(T) == 4 ? kGenU : kGenU / 2;
+  // values per thread per load round (FP64: half, a quarter with the nonlinear sub-step,
+  // for the registers)
+  constexpr int U = sizeof(T) == 4 ? kGenU : (NLM >= 0 ? kGenU / 4 : kGenU / 2);
   constexpr int UF = 4;  // factor-table values per thread fetched ahead of the tile
   double q7[7] = {0, 0, 0, 0, 0, 0, 0};
   [[maybe_unused]] T ts = (T)1;
