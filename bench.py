@@ -449,6 +449,48 @@ def adjoint_128(nsteps=200, K=20):
     return out
 
 
+def adjoint_2d_256(nsteps=400, K=50):
+    """The 256^2 adjoint workload's rate (overlap loss against the displaced target,
+    checkpoints every K; the trap (x^2 + 1.5^2 y^2)/2 plus its seeded perturbation):
+    forward with checkpoints, then backward, over nsteps real-time steps."""
+    import numpy as np
+    import torch
+    from paper_1601_04640_amd import inputs as I
+    from paper_1601_04640_amd.adjoint import evolve_real, overlap_loss
+    from paper_1601_04640_amd.binding import Solver
+    w = I.WORKLOADS["real2dxy_256"]
+    out = {}
+    y, x = I.grid_axes("2dxy", w["nx"], w["ny"], w["nz"], w["dx"], w["dy"], w["dz"])
+    Y, X = np.meshgrid(y, x, indexing="ij")
+    V = 0.5 * (X ** 2 + (w["nu"] * Y) ** 2) + I.trap_perturbation_real2dxy_256()
+    for prec in ("fp32", "fp64"):
+        s = Solver(w, prec=prec)
+        dev = "cuda:0"
+        psi0 = torch.from_numpy(I.psi0_real2dxy_256()).to(dev, s.cdtype)
+        target = torch.from_numpy(I.displaced_target(w, 1610, widths=(1.0 / np.sqrt(1.5), 1.0))
+                                  ).to(dev, s.cdtype)
+        dV = w["dx"] * w["dy"]
+
+        def run():
+            p0 = psi0.clone().requires_grad_(True)
+            Vt = torch.from_numpy(V).to(dev).requires_grad_(True)
+            gt = torch.tensor(w["g"], dtype=torch.float64, device=dev, requires_grad=True)
+            gdt = torch.tensor(w["gdd"], dtype=torch.float64, device=dev, requires_grad=True)
+            L = overlap_loss(evolve_real(s, p0, Vt, gt, gdt, nsteps, K), target, dV)
+            L.backward()
+            torch.cuda.synchronize()
+        run()
+        t0 = time.perf_counter()
+        run()
+        wall = time.perf_counter() - t0
+        s.close()
+        out[prec] = {"ms_per_step_forward_and_backward": wall * 1e3 / nsteps,
+                     "grid_point_steps_per_s": 256 ** 2 * nsteps / wall}
+    out["workload"] = (f"real2dxy_256 adjoint: {nsteps} real-time steps (of the workload's "
+                       f"4000), checkpoints every {K}")
+    return out
+
+
 # ---------------------------------------------------------------------- sweep
 SWEEP3 = (48, 50, 64, 80, 96, 100, 120, 128, 150, 160, 192, 200, 240, 250, 256, 300, 320, 360,
           384, 400, 450, 480, 500, 512, 540, 600)
@@ -586,6 +628,8 @@ def main():
         line["imag3d_64"] = imag3d_64(args.steps)
         log("128^3 adjoint")
         line["adjoint3d_128"] = adjoint_128()
+        log("256^2 adjoint")
+        line["adjoint2d_256"] = adjoint_2d_256()
         if not args.no_batch:
             line["batched_2d"] = time_batch(args.batch_steps, two_streams=args.two_streams)
             log(f"batched 2d: {line['batched_2d']['ms_per_step']:.4f} ms/step "
