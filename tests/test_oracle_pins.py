@@ -74,10 +74,13 @@ def test_rfft_matches_bruteforce_dft(n):
     assert np.max(np.abs(got - ref[: n // 2 + 1])) <= 1e-13 * max(1.0, math.log2(n)) * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("geom,shape", [("3d", (10, 6, 8)), ("2dxy", (6, 8)), ("2dxz", (10, 8))])
+@pytest.mark.parametrize("geom,shape", [("3d", (10, 6, 8)), ("2dxy", (6, 8)), ("2dxz", (10, 8)),
+                                        ("3d", (9, 7, 5)), ("2dxy", (7, 9)), ("2dxz", (9, 5))])
 def test_dipolar_potential_equals_direct_circulant_sum(geom, shape):
     """S2: Phi = F^-1[U F[n]] is the periodic real-space convolution with
-    K = F^-1[U]; checked against an explicit O(N^2) sum on tiny grids."""
+    K = F^-1[U]; checked against an explicit O(N^2) sum on tiny grids, even and odd (an
+    odd axis has no Nyquist index: K is real only if U pairs index m with n - m, which
+    a frequency map off by one at m = (n-1)/2 breaks)."""
     if geom == "3d":
         p = O.Params(geom=geom, nx=shape[2], ny=shape[1], nz=shape[0], dx=0.3, dy=0.45,
                      dz=0.25, R=0.7)
@@ -262,11 +265,13 @@ def relax(p, psi, nsteps):
 
 
 @pytest.mark.parametrize("dt", [0.004, 0.002])
-def test_noninteracting_2d_ground_energy_is_tridiagonal_eigenvalue_sum(dt):
+@pytest.mark.parametrize("nx,ny", [(40, 36), (41, 35)])
+def test_noninteracting_2d_ground_energy_is_tridiagonal_eigenvalue_sum(dt, nx, ny):
     """g = g_dd = 0: imaginary time converges to the discrete ground state; E differs
-    from the exact eigenvalue sum only by the O(dt^2) Lie-splitting offset."""
-    p = O.Params(geom="2dxy", nx=40, ny=36, dx=0.3, dy=0.35, dt=dt, gamma=1.0, nu=1.7, lam=4.0)
-    psi = I.gaussian("2dxy", 40, 36, 1, 0.3, 0.35, 0.3, widths=(0.8, 1.0), amp_noise=0.01, seed=1)
+    from the exact eigenvalue sum only by the O(dt^2) Lie-splitting offset (even and odd
+    grids: an odd grid centres the trap on its middle point)."""
+    p = O.Params(geom="2dxy", nx=nx, ny=ny, dx=0.3, dy=0.35, dt=dt, gamma=1.0, nu=1.7, lam=4.0)
+    psi = I.gaussian("2dxy", nx, ny, 1, 0.3, 0.35, 0.3, widths=(0.8, 1.0), amp_noise=0.01, seed=1)
     psi, ob = relax(p, psi, int(16.0 / dt))
     e0 = discrete_ground_energy(p)
     err = ob["energy"] - e0
