@@ -139,8 +139,10 @@ __global__ void k_kernel_table(T* ktab, KernelGeom kg) {
   const int kx = (int)(idx / ((size_t)m1n * m2n));
   const double pi = 3.14159265358979323846;
   const double qx = 2.0 * pi * kx / (kg.n0 * kg.h0);
-  const int m1 = (k1 < kg.n1 / 2) ? k1 : k1 - kg.n1;
-  const int m2 = (k2 < kg.n2 / 2) ? k2 : k2 - kg.n2;
+  // signed frequency of index k: k below n/2, k - n from n/2 on (odd n: every k <= n/2
+  // of the quadrant is a non-negative frequency)
+  const int m1 = (2 * k1 < kg.n1) ? k1 : k1 - kg.n1;
+  const int m2 = (2 * k2 < kg.n2) ? k2 : k2 - kg.n2;
   const double q1 = 2.0 * pi * m1 / (kg.n1 * kg.h1);
   const double q2 = (kg.n2 > 1) ? 2.0 * pi * m2 / (kg.n2 * kg.h2) : 0.0;
   double u;

@@ -471,16 +471,12 @@ struct Passes {
     GP_TRY(g_convolution(c, psi(c), &c->sc()->scale));
     GP_TRY(pass_begin(c, GP_PASS_C2R_NL_CNX));
     GP_HIP(GLaunch<T>::c2r_x(c->st, spec(c), phi, c->gplan[0], tw(c, 0), L.n0, L.n1, L.n2));
-    if (GLaunch<T>::x_fused(L.n0)) {
+    {
       // the nonlinear sub-step rides in the x sweep's loads
       const GNl nlz{Vp(c), phi, &c->sc()->scale, g_scalars(c), L.n0, L.n1, L.n2,
                     c->at<double>(L.o_pnl)};
       GP_HIP(GLaunch<T>::cn_x_nonlinear(mode, c->st, psi(c), L.n0, L.n1 * L.n2, cn(c, 0, k),
                                         nlz));
-    } else {
-      GP_HIP(GLaunch<T>::nonlinear(mode, c->st, psi(c), Vp(c), phi, &c->sc()->scale,
-                                   g_scalars(c), L.n0, L.n1, L.n2, c->at<double>(L.o_pnl)));
-      GP_TRY(g_sweep(c, 0, k, 0));
     }
     GP_TRY(pass_end(c, GP_PASS_C2R_NL_CNX));
     if (c->p.geom == GP_3D) {

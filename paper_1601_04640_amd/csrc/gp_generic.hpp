@@ -365,7 +365,8 @@ __global__ void __launch_bounds__(kGenThreads, gen_waves_per_eu<T>()) kg_lines(c
 }
 
 // Grid of the x passes: block b covers the line pairs (j, j+1), j = j0, j0 + 2, ...,
-// j0 + 2 np - 2 (j0 = 2 np (b mod nbj)) of the plane k = b / nbj.  Spectrum layout
+// j0 + 2 np - 2 (j0 = 2 np (b mod nbj)) of the plane k = b / nbj; with an odd n1 the
+// last pair of a plane has no line j + 1 (packed as a zero line).  Spectrum layout
 // spec[(kx n2 + k) n1 + j], kx = 0..n0/2.  fn0, fnp, f2np, fnbj: divisors by n0, np, 2 np
 // and nbj.
 struct GXTile {
@@ -374,7 +375,7 @@ struct GXTile {
   __device__ __forceinline__ void locate(int b, int* k, int* j0, int* npairs) const {
     *k = (int)fdiv((uint32_t)b, fnbj);
     *j0 = 2 * np * (b - *k * nbj);
-    const int left = (n1 - *j0) / 2;
+    const int left = (n1 - *j0 + 1) / 2;  // an odd n1 leaves a last pair of one line
     *npairs = left < np ? left : np;
   }
 };
@@ -408,6 +409,7 @@ __global__ void __launch_bounds__(kGenThreads) kg_r2c_x(const cpx<T>* __restrict
     double ddx[U], ddy[U];
     int jj[U];
     cpx<T> a0[U], a1[U], b0[U], b1[U], c1[U];
+    bool hh[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int t = t0 + u * nt;
@@ -417,17 +419,19 @@ __global__ void __launch_bounds__(kGenThreads) kg_r2c_x(const cpx<T>* __restrict
       // loads from in-range addresses only, selected afterwards (a select between a
       // load and a constant would be turned into a load through a stack slot)
       const bool ok = jj[u] >= 0;
+      const bool has1 = ok && jj[u] + 1 < n1;  // line j + 1 exists
+      hh[u] = has1;
       const long long a = ok ? ((long long)k * n1 + j0 + 2 * q) * N + i : 0;
       a0[u] = psi[a];
-      a1[u] = psi[a + N];
+      a1[u] = psi[has1 ? a + N : a];  // without line j + 1: line j again (no difference)
       b0[u] = psi[ok && i + 1 < N ? a + 1 : a];
-      b1[u] = psi[ok && i + 1 < N ? a + N + 1 : a + N];
-      c1[u] = psi[ok && jj[u] + 2 < n1 ? a + 2 * N : a + N];
+      b1[u] = psi[has1 && i + 1 < N ? a + N + 1 : (has1 ? a + N : a)];
+      c1[u] = psi[has1 && jj[u] + 2 < n1 ? a + 2 * N : (has1 ? a + N : a)];
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       n0v[u] = a0[u].re * a0[u].re + a0[u].im * a0[u].im;
-      n1v[u] = a1[u].re * a1[u].re + a1[u].im * a1[u].im;
+      n1v[u] = hh[u] ? a1[u].re * a1[u].re + a1[u].im * a1[u].im : (T)0;
       ddx[u] = absdiff2_d(b0[u], a0[u]) + absdiff2_d(b1[u], a1[u]);
       ddy[u] = absdiff2_d(a1[u], a0[u]) + absdiff2_d(c1[u], a1[u]);
     }
@@ -448,7 +452,7 @@ __global__ void __launch_bounds__(kGenThreads) kg_r2c_x(const cpx<T>* __restrict
   for (int t = threadIdx.x; t < tot2; t += nt) {
     const int kx = (int)fdiv((uint32_t)t, xt.f2np), r = t - kx * 2 * xt.np;
     const int q = r >> 1, which = r & 1;
-    if (q >= npairs) continue;
+    if (q >= npairs || j0 + 2 * q + which >= n1) continue;
     const cpx<T> zk = buf[q * N + kx];
     const cpx<T> zm = buf[q * N + (kx == 0 ? 0 : N - kx)];
     cpx<T> o;
@@ -495,11 +499,13 @@ __global__ void __launch_bounds__(kGenThreads) kg_c2r_x(const cpx<T>* __restrict
       kk[u] = (int)fdiv((uint32_t)t, xt.fnp);
       qq[u] = t - kk[u] * xt.np;
       if (t >= tot || qq[u] >= npairs) qq[u] = -1;
-      // in-range addresses only (see kg_r2c_x)
+      // in-range addresses only (see kg_r2c_x); no line j + 1: B = 0
       const long long a =
           qq[u] >= 0 ? ((long long)kk[u] * xt.n2 + k) * n1 + j0 + 2 * qq[u] : 0;
+      const bool has1 = qq[u] >= 0 && j0 + 2 * qq[u] + 1 < n1;
       A[u] = spec[a];
-      B[u] = spec[a + 1];
+      B[u] = spec[has1 ? a + 1 : a];
+      if (!has1) B[u] = cpx<T>{0, 0};
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -520,7 +526,7 @@ __global__ void __launch_bounds__(kGenThreads) kg_c2r_x(const cpx<T>* __restrict
     const long long a = ((long long)k * n1 + j0 + 2 * q) * N + i;
     const cpx<T> z = buf[t];
     phi[a] = z.re;
-    phi[a + N] = z.im;
+    if (j0 + 2 * q + 1 < n1) phi[a + N] = z.im;
   }
 }
 
@@ -529,13 +535,6 @@ struct GStep {
   double dt, gc, gdd, h0, h1, h2;
   FDiv f0, f1;
 };
-
-// Blocks of the nonlinear pass: a fixed count (each walks its share of the grid), so the
-// number of partial-sum slots is known when the workspace is laid out.
-__host__ __device__ inline int gen_nl_blocks(long long npts) {
-  long long b = (npts + 4095) / 4096;
-  return (int)(b < 1 ? 1 : (b > 2048 ? 2048 : b));
-}
 
 // Nonlinear sub-step in place: psi <- scale psi exp(-eps dt (V + g_c n + g_dd Phi)),
 // eps = 1 (MODE_IMAG) or i (MODE_REAL); MODE_OBSERVE only sums.  part[7 b ...]: sum n,

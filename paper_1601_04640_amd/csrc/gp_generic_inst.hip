@@ -90,7 +90,7 @@ GXTile GLaunch<T>::xtile(int n0, int n1, int n2) {
   xt.n0 = n0;
   xt.n1 = n1;
   xt.n2 = n2;
-  const int pairs = n1 / 2;
+  const int pairs = (n1 + 1) / 2;  // an odd n1: the last pair has one line
   int np = gen_max_line<T>() / n0;   // pairs whose packed lines fit in LDS
   if (np > 8) np = 8;                // 16 consecutive y lines: 128-byte spectrum runs (FP64)
   if (np > pairs) np = pairs;

@@ -15,12 +15,12 @@ constexpr int gen_max_line() {
   return (int)(65536 / (2 * sizeof(T)));
 }
 
-// An axis the run-time-length kernels accept: even, at least 4, at most gen_max_line,
-// and every prime factor at most 31.
+// An axis the run-time-length kernels accept: at least 4 points, at most gen_max_line,
+// every prime factor at most 31 (even or odd).
 template <typename T>
 inline bool gen_size_ok(int n) {
   GPlan p;
-  return n >= 4 && n % 2 == 0 && n <= gen_max_line<T>() && gen_plan(n, &p);
+  return n >= 4 && n <= gen_max_line<T>() && gen_plan(n, &p);
 }
 
 template <typename T>
@@ -33,9 +33,8 @@ struct GLaunch {
   static GXTile xtile(int n0, int n1, int n2);
   static int x_blocks(int n0, int n1, int n2);
   // blocks of the nonlinear pass (partial-sum slots) and of a CN sweep over nlines lines
-  static int nl_blocks(int n0, int n1, int n2) {
-    return x_fused(n0) ? cn_blocks(n0, n1 * n2, false) : gen_nl_blocks((long long)n0 * n1 * n2);
-  }
+  // (the x sweep's, which carries the nonlinear sub-step and its sums)
+  static int nl_blocks(int n0, int n1, int n2) { return cn_blocks(n0, n1 * n2, false); }
   // CN sweeps: kg_cn_tile with wpl waves per line (1 up to kTileMaxN points, then one
   // lane per 8 rows) and cn_tile_lines lines per block, except strided sweeps of many
   // lines longer than kTileMaxN, which run one thread per line (kg_cn_cols)
@@ -54,8 +53,6 @@ struct GLaunch {
     const int nl = cn_tile_lines(n, nlines, strided);
     return (nlines + nl - 1) / nl;
   }
-  // the x sweep carries the nonlinear sub-step (every supported length)
-  static bool x_fused(int n0) { return n0 <= gen_max_line<T>(); }
   // 2D y sweeps of lines longer than kTileMaxN run on a transposed copy of the state
   // (lines of the copy are contiguous), through the scratch grid
   static bool y2d_transposed(int n1) { return n1 > kTileMaxN; }
@@ -68,7 +65,8 @@ struct GLaunch {
   static hipError_t lines(int kind, hipStream_t st, cpx<T>* data, int n, int nlines, int G,
                           long long so, long long si, long long se, const GPlan& p,
                           const cpx<T>* tw, const T* ktab, GKtab km, const double* scale);
-  // mode: MODE_IMAG, MODE_REAL (update psi), MODE_OBSERVE (sums only)
+  // the nonlinear sub-step's sums of the stored state (mode MODE_OBSERVE; MODE_IMAG and
+  // MODE_REAL also apply it in place), over nl_blocks blocks
   static hipError_t nonlinear(int mode, hipStream_t st, cpx<T>* psi, const T* V, const T* phi,
                               const double* scale, const GStep& sc, int n0, int n1, int n2,
                               double* part);

@@ -47,9 +47,10 @@ def ws(**kw):
     return B.gp_workspace_bytes(B.make_params(**base))
 
 
-# odd, below 4, a prime factor above 31 (37, 41, 43, 47, 53), or a line past 64 KiB of
-# LDS (FP64: 4096 points)
-@pytest.mark.parametrize("n", [7, 9, 15, 2, 0, -8, 74, 82, 86, 94, 106, 2 * 37 * 3, 4098, 8192])
+# below 4, a prime factor above 31 (37, 41, 43, 47, 53), or a line past 64 KiB of LDS
+# (FP64: 4096 points)
+@pytest.mark.parametrize("n", [3, 2, 0, -8, 37, 74, 82, 86, 94, 106, 2 * 37 * 3, 3 * 37, 4098,
+                               8192])
 def test_unsupported_sizes_rejected(n):
     with pytest.raises(B.GPError) as e:
         ws(nx=n, prec="fp64")
@@ -70,25 +71,25 @@ def test_line_length_limit_depends_on_precision():
 
 
 # the specialised lengths, and lengths the run-time-length passes take (the paper's
-# grids 50, 540, 600, 1000 among them; radices 7, 11, 13, 31)
+# grids 50, 540, 600, 1000 among them; radices 7, 11, 13, 31; odd lengths)
 @pytest.mark.parametrize("n", [8, 10, 12, 16, 20, 24, 30, 32, 40, 48, 60, 64, 80, 96, 120,
                                128, 160, 192, 240, 256, 320, 384, 480, 512,
                                4, 6, 14, 22, 26, 36, 50, 54, 62, 90, 100, 540, 600, 1000,
-                               1024, 2048, 4096])
+                               1024, 2048, 4096, 5, 7, 9, 15, 45, 49, 99, 625, 1001, 4095])
 def test_supported_sizes_accepted(n):
     assert ws(nx=n, ny=8, nz=8, prec="fp64") > 0
 
 
 def test_supported_size_set_follows_the_factor_rule():
-    """Every even length 4..600 is accepted exactly when all its prime factors are at
-    most 31 (FP32 and FP64 agree below the FP64 line limit)."""
+    """Every length 4..600, even or odd, is accepted exactly when all its prime factors
+    are at most 31 (FP32 and FP64 agree below the FP64 line limit)."""
     def ok(n):
         m = n
         for p in (2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31):
             while m % p == 0:
                 m //= p
         return m == 1
-    for n in range(4, 601, 2):
+    for n in range(4, 601):
         for prec in ("fp32", "fp64"):
             try:
                 ws(geom="2dxy", nx=n, ny=8, prec=prec)

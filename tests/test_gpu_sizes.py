@@ -1,7 +1,7 @@
 """Axis lengths.  Those without compile-time specialised passes run the run-time-length
-kernels: every even length >= 4 whose prime factors are at most 31, up to 8192 (FP32) /
-4096 (FP64) points per line; and every specialised length is run in each role (x, y and
-z line).  The paper's programs take any grid and enlarge it silently for
+kernels: every length >= 4, even or odd, whose prime factors are at most 31, up to 8192
+(FP32) / 4096 (FP64) points per line; and every specialised length is run in each role
+(x, y and z line).  The paper's programs take any grid and enlarge it silently for
 the FFT ("Unusual features"); here each length runs as given.  Parity with the FP64
 oracle through the C ABI at the same bars as the specialised sizes: psi rel-L2 and
 element-wise <= 1e-10 / 2e-5, energy and mu <= 1e-12 / 1e-6."""
@@ -37,6 +37,17 @@ CASES = {
     # degenerate lengths: 4 and 6 points (two and four interior points)
     "3d_4x6x10": dict(geom="3d", nx=4, ny=6, nz=10, dx=1.0, dy=0.8, dz=0.6, dt=0.002,
                       gamma=1.0, nu=1.0, lam=1.0, g=5.0, gdd=2.0, R=2.0),
+    # odd lengths on every axis (45 = 3^2 5, 27 = 3^3, 35 = 5 7): the x passes' last line
+    # pair of a plane holds one line, and the odd spectra have no Nyquist row
+    "3d_45x27x35": dict(geom="3d", nx=45, ny=27, nz=35, dx=0.3, dy=0.35, dz=0.3, dt=0.002,
+                        gamma=1.0, nu=1.1, lam=1.6, g=20.0, gdd=8.0, R=4.0),
+    "2dxy_63x49": dict(geom="2dxy", nx=63, ny=49, nz=1, dx=0.2, dy=0.25, dz=1.0, dt=0.001,
+                       gamma=1.0, nu=1.3, lam=4.0, g=25.0, gdd=10.0, R=0.0),
+    # odd z in XZ (the x passes pair z lines); 5 points: three interior points
+    "2dxz_40x55": dict(geom="2dxz", nx=40, ny=1, nz=55, dx=0.25, dy=1.0, dz=0.2, dt=0.001,
+                       gamma=1.0, nu=4.0, lam=2.0, g=15.0, gdd=12.0, R=0.0),
+    "3d_5x9x7": dict(geom="3d", nx=5, ny=9, nz=7, dx=1.0, dy=0.7, dz=0.8, dt=0.002,
+                     gamma=1.0, nu=1.0, lam=1.2, g=5.0, gdd=2.0, R=2.0),
 }
 
 
