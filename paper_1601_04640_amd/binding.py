@@ -400,7 +400,7 @@ def gp_axis_kind(n: int, prec: str = "fp64") -> int:
 def supported_sizes(limit: int = 16384, prec: str = "fp64", kind=None) -> list:
     """Axis lengths gp_init accepts (kind 1 or 2, or only the given kind)."""
     out = []
-    for n in range(2, limit + 1, 2):
+    for n in range(2, limit + 1):
         k = gp_axis_kind(n, prec)
         if k and (kind is None or k == kind):
             out.append(n)
