@@ -17,6 +17,34 @@ __global__ void k_twiddles(cpx<T>* tw, int N) {
   tw[k] = cpx<T>{(T)c, (T)(-s)};
 }
 
+// Bluestein tables of an n-point axis with convolution length m, in FP64 rounded to T:
+// the chirp c_j = exp(-i pi j^2 / n), j < n (j^2 taken mod 2n), and the filter
+// F_k = (1/m) sum_q w_q exp(-2 pi i q k / m) of w_q = conj(c_q) (q < n), w_(m-q) = w_q
+// (0 < q < n), zero elsewhere; w is even, so F_k = (1/m) (1 + 2 sum_(q=1)^(n-1) conj(c_q)
+// cos(2 pi q k / m)).  One thread per k < m.
+template <typename T>
+__global__ void k_bluestein(cpx<T>* chirp, cpx<T>* filt, int n, int m) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) {
+    const long long r = ((long long)k * k) % (2LL * n);
+    double s, c;
+    sincospi((double)r / n, &s, &c);
+    chirp[k] = cpx<T>{(T)c, (T)(-s)};
+  }
+  if (k >= m) return;
+  double fr = 1.0, fi = 0.0;
+  for (int q = 1; q < n; ++q) {
+    const long long r = ((long long)q * q) % (2LL * n);
+    double s, c;
+    sincospi((double)r / n, &s, &c);            // conj(c_q) = c + i s
+    const long long u = ((long long)q * k) % m;
+    const double w = 2.0 * cospi(2.0 * (double)u / m);
+    fr += w * c;
+    fi += w * s;
+  }
+  filt[k] = cpx<T>{(T)(fr / m), (T)(fi / m)};
+}
+
 // Thomas factors of (1 + 2A) u_i - A (u_{i-1} + u_{i+1}) with Dirichlet ends, for
 // A = Ar (imaginary time) and A = i Ar (real time), evaluated sequentially in FP64:
 //   m_1 = 1/b,  m_i = 1/(b - a c_{i-1}),  c_i = a m_i,  g_i = -c_i = A m_i,

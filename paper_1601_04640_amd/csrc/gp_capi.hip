@@ -72,7 +72,7 @@ struct Layout {
   // one-thread-per-line sweeps need a grid of scratch values (o_gscr)
   bool generic, gscr;
   // byte offsets inside the workspace
-  size_t o_psi, o_V, o_spec, o_ktab, o_tw[3], o_cn[3][3], o_px[2], o_pnl, o_pcol, o_padj, o_sfield,
+  size_t o_psi, o_V, o_spec, o_ktab, o_tw[3], o_blue[3], o_cn[3][3], o_px[2], o_pnl, o_pcol, o_padj, o_sfield,
       o_scalars, o_ring, o_obs, o_io, o_stamps, o_stage, o_gscr, total;
 };
 
@@ -180,7 +180,11 @@ Layout make_layout(const gp_params* p, unsigned host = 0) {
   L.o_ktab = take((host & GP_HOST_KTAB) ? 0 : L.esz * L.nktab);
   const int ns[3] = {L.n0, L.n1, L.n2};
   for (int a = 0; a < 3; ++a) {
-    L.o_tw[a] = take(2 * L.esz * ns[a]);
+    // twiddles of the stage length (Bluestein's M for a run-time-length axis with a prime
+    // factor above 31), then that axis's chirp (n) and filter (M)
+    const int ms = L.generic ? gen_stride(ns[a]) : ns[a];
+    L.o_tw[a] = take(2 * L.esz * ms);
+    L.o_blue[a] = take(ms != ns[a] ? 2 * L.esz * (size_t)(ns[a] + ms) : 0);
     // factor table and scan weights per set (imaginary time, real time, adjoint)
     for (int t = 0; t < 3; ++t) L.o_cn[a][t] = take(2 * L.esz * (ns[a] + kScanWeights));
   }
@@ -760,8 +764,17 @@ struct Passes {
     const double hs[3] = {L.h0, L.h1, L.h2};
     const int naxes = (c->p.geom == GP_3D) ? 3 : 2;
     for (int a = 0; a < naxes; ++a) {
-      hipLaunchKernelGGL(k_twiddles<T>, dim3(blocks_for(ns[a])), dim3(kThreads), 0, c->st,
-                         c->at<cpx<T>>(L.o_tw[a]), ns[a]);
+      const int ms = L.generic ? c->gplan[a].m : ns[a];  // stage length
+      hipLaunchKernelGGL(k_twiddles<T>, dim3(blocks_for(ms)), dim3(kThreads), 0, c->st,
+                         c->at<cpx<T>>(L.o_tw[a]), ms);
+      if (L.generic && c->gplan[a].blue) {
+        cpx<T>* ch = c->at<cpx<T>>(L.o_blue[a]);
+        cpx<T>* fl = ch + ns[a];
+        hipLaunchKernelGGL(k_bluestein<T>, dim3(blocks_for(ms)), dim3(kThreads), 0, c->st, ch,
+                           fl, ns[a], ms);
+        c->gplan[a].chirp = ch;
+        c->gplan[a].filt = fl;
+      }
       const double Ar = c->p.dt / (4.0 * hs[a] * hs[a]);
       // lanes per line of the solve that sweeps this axis: x lines in the x pass, columns
       // in the strided sweeps

@@ -92,33 +92,70 @@ __device__ __forceinline__ const cpx<T>* tw_store(cpx<T>* twl, const cpx<T> (&v)
   return twl;
 }
 
-// Radices of an N-point FFT: factors 8, 4, 2, then the odd primes up to 31; per stage
-// the divisors of its butterfly indexing (N / R butterflies per line, L = the product of
-// the earlier radices).
+// Plan of an N-point FFT.  Lengths whose prime factors are at most 31 run Stockham
+// stages of radices 8, 4, 2, then the odd primes; per stage the divisors of its
+// butterfly indexing (M / R butterflies per line, L = the product of the earlier
+// radices).  Other lengths run Bluestein's algorithm (Bluestein, "A linear filtering
+// approach to the computation of discrete Fourier transform", 1970): with the chirp
+// c_j = exp(-i pi j^2 / N), the DFT is X_k = c_k sum_j (x_j c_j) conj(c_(k-j)), a
+// convolution evaluated by FFTs of a length M >= 2N - 1 whose factors are 2, 3, 5, 7; the
+// stages are then those of M.  A line occupies m values of LDS (m = M, or N).
 struct GPlan {
-  int n;
+  int n;      // transform length
+  int m;      // stage length and LDS line stride (N, or Bluestein's M)
+  int blue;   // Bluestein's algorithm
   int nst;
   int rad[kGenMaxStages];
   FDiv nb[kGenMaxStages], l[kGenMaxStages];
+  FDiv fm;                  // divisor by m
+  const void* chirp;        // Bluestein: c_j, j < N (cpx<T>, set with the tables)
+  const void* filt;         // Bluestein: FFT_M of conj(c) wrapped to M, over M (cpx<T>)
 };
 
-__host__ __device__ inline bool gen_plan(int n, GPlan* p) {
-  p->n = n;
+// Stockham stages of an m-point FFT; false if m has a prime factor above 31.
+__host__ __device__ inline bool gen_stages(int m, GPlan* p) {
   p->nst = 0;
-  int m = n;
+  int r_ = m;
   const int order[] = {8, 4, 2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31};
   int L = 1;
   for (int r : order) {
-    while (m % r == 0) {
+    while (r_ % r == 0) {
       if (p->nst >= kGenMaxStages) return false;
-      p->nb[p->nst] = fdiv_make((uint32_t)(n / r));
+      p->nb[p->nst] = fdiv_make((uint32_t)(m / r));
       p->l[p->nst] = fdiv_make((uint32_t)L);
       p->rad[p->nst++] = r;
       L *= r;
-      m /= r;
+      r_ /= r;
     }
   }
-  return m == 1;
+  return r_ == 1;
+}
+
+// Bluestein's convolution length for n: the smallest M >= 2n - 1 with factors 2, 3, 5, 7.
+__host__ __device__ inline int gen_blue_len(int n) {
+  for (int M = 2 * n - 1;; ++M) {
+    int r = M;
+    for (int q : {2, 3, 5, 7})
+      while (r % q == 0) r /= q;
+    if (r == 1) return M;
+  }
+}
+
+__host__ __device__ inline bool gen_plan(int n, GPlan* p) {
+  p->n = n;
+  p->chirp = nullptr;
+  p->filt = nullptr;
+  if (n >= 1 && gen_stages(n, p)) {
+    p->m = n;
+    p->blue = 0;
+  } else {
+    if (n < 2) return false;
+    p->m = gen_blue_len(n);
+    p->blue = 1;
+    if (!gen_stages(p->m, p)) return false;
+  }
+  p->fm = fdiv_make((uint32_t)p->m);
+  return true;
 }
 
 // ---------------------------------------------------------------- radix butterflies
@@ -202,21 +239,22 @@ __device__ __forceinline__ void gstage(cpx<T>* buf, int NL, int N, int L, FDiv f
 // only the radices 2, 3, 4, 5, 8 (lengths 2^a 3^b 5^c): the prime stages' registers
 // would otherwise be charged to every launch.
 template <typename T, bool INV, int EMAX, bool SMALL>
-__device__ inline void gfft(cpx<T>* buf, int NL, const GPlan& p, const cpx<T>* __restrict__ tw) {
+__device__ inline void gstages(cpx<T>* buf, int NL, const GPlan& p,
+                               const cpx<T>* __restrict__ tw) {
   int L = 1;
   for (int s = 0; s < p.nst; ++s) {
     const int R = p.rad[s];
     switch (R) {
 #define GSTAGE(RR)                                                   \
   case RR:                                                           \
-    gstage<T, RR, INV, (EMAX + RR - 1) / RR>(buf, NL, p.n, L, p.nb[s], p.l[s], tw); \
+    gstage<T, RR, INV, (EMAX + RR - 1) / RR>(buf, NL, p.m, L, p.nb[s], p.l[s], tw); \
     break;
       GSTAGE(2) GSTAGE(3) GSTAGE(4) GSTAGE(5) GSTAGE(7) GSTAGE(8)
 #undef GSTAGE
 #define GSTAGE(RR)                                                               \
   case RR:                                                                       \
     if constexpr (!SMALL)                                                        \
-      gstage<T, RR, INV, (EMAX + RR - 1) / RR>(buf, NL, p.n, L, p.nb[s], p.l[s], tw); \
+      gstage<T, RR, INV, (EMAX + RR - 1) / RR>(buf, NL, p.m, L, p.nb[s], p.l[s], tw); \
     break;
       GSTAGE(11) GSTAGE(13) GSTAGE(17) GSTAGE(19) GSTAGE(23) GSTAGE(29) GSTAGE(31)
 #undef GSTAGE
@@ -225,6 +263,49 @@ __device__ inline void gfft(cpx<T>* buf, int NL, const GPlan& p, const cpx<T>* _
     }
     L *= R;
   }
+}
+
+// The N-point transform of NL lines at LDS stride p.m (unnormalised; INV: exponent +).
+// BLUE (plans with p.blue; compiled separately, so the other kernels keep their
+// registers): a = x c (the conjugate input for INV), zero-padded to M; FFT_M; times the
+// filter (which carries 1/M); inverse FFT_M; times c (conjugated back for INV).  The
+// element loops read the chirp and the filter from global memory.
+template <typename T, bool INV, int EMAX, bool SMALL, bool BLUE>
+__device__ inline void gfft(cpx<T>* buf, int NL, const GPlan& p, const cpx<T>* __restrict__ tw) {
+  if constexpr (!BLUE) {
+    gstages<T, INV, EMAX, SMALL>(buf, NL, p, tw);
+    return;
+  }
+  const cpx<T>* __restrict__ ch = reinterpret_cast<const cpx<T>*>(p.chirp);
+  const cpx<T>* __restrict__ fl = reinterpret_cast<const cpx<T>*>(p.filt);
+  const int N = p.n, M = p.m, tot = NL * M;
+  for (int t = threadIdx.x; t < tot; t += blockDim.x) {
+    const int j = t - (int)fdiv((uint32_t)t, p.fm) * M;
+    cpx<T> v{0, 0};
+    if (j < N) {
+      v = buf[t];
+      if (INV) v = conjg(v);
+      v = v * ch[j];
+    }
+    buf[t] = v;
+  }
+  __syncthreads();
+  gstages<T, false, EMAX, SMALL>(buf, NL, p, tw);
+  for (int t = threadIdx.x; t < tot; t += blockDim.x) {
+    const int j = t - (int)fdiv((uint32_t)t, p.fm) * M;
+    buf[t] = buf[t] * fl[j];
+  }
+  __syncthreads();
+  gstages<T, true, EMAX, SMALL>(buf, NL, p, tw);
+  for (int t = threadIdx.x; t < tot; t += blockDim.x) {
+    const int j = t - (int)fdiv((uint32_t)t, p.fm) * M;
+    if (j < N) {
+      cpx<T> v = buf[t] * ch[j];
+      if (INV) v = conjg(v);
+      buf[t] = v;
+    }
+  }
+  __syncthreads();
 }
 
 // Whether a plan uses only the radices of the SMALL kernels.
@@ -281,12 +362,13 @@ enum : int { GL_FWD = 0, GL_INV = 1, GL_CONV = 2 };
 
 // Line FFTs of the half spectrum.  KIND GL_CONV: forward FFT, product with
 // U(k) scale^2 / N (the table holds U/N), inverse FFT.
-// FP32: at most 64 VGPRs, so that two full 16-wave blocks share a CU
-template <typename T>
-constexpr int gen_waves_per_eu() { return sizeof(T) == 4 ? 8 : 1; }
+// FP32: at most 64 VGPRs, so that two full 16-wave blocks share a CU (not asked of the
+// Bluestein variants, which would spill)
+template <typename T, bool BLUE>
+constexpr int gen_waves_per_eu() { return sizeof(T) == 4 && !BLUE ? 8 : 1; }
 
-template <typename T, int KIND, int EMAX, bool SMALL>
-__global__ void __launch_bounds__(kGenThreads, gen_waves_per_eu<T>()) kg_lines(cpx<T>* __restrict__ data, GLines g,
+template <typename T, int KIND, int EMAX, bool SMALL, bool BLUE = false>
+__global__ void __launch_bounds__(kGenThreads, (gen_waves_per_eu<T, BLUE>())) kg_lines(cpx<T>* __restrict__ data, GLines g,
                                                      GPlan p, const cpx<T>* __restrict__ tw,
                                                      const T* __restrict__ ktab, GKtab km,
                                                      const double* __restrict__ scale) {
@@ -295,13 +377,16 @@ __global__ void __launch_bounds__(kGenThreads, gen_waves_per_eu<T>()) kg_lines(c
   const int l0 = blockIdx.x * g.nl;
   const int nl = min(g.nl, g.nlines - l0);
   const int N = g.n;
+  const int LS = BLUE ? p.m : N;   // LDS line stride: N, or Bluestein's M
   const int nt = blockDim.x;
   const int tot = g.nl * N;  // the full tile's indexing; lines past nl are skipped
-  cpx<T>* twl = buf + tot;   // the twiddle table
+  cpx<T>* twl = buf + g.nl * LS;   // the twiddle table (of the stage length)
   constexpr int UT = tw_pre<T>() / 2;
   cpx<T> twv[UT];
-  tw_fetch<T, SMALL, UT>(twv, tw, N);
+  tw_fetch<T, SMALL, UT>(twv, tw, LS);
   const bool packed = g.packed();
+  // LDS slot of element t of a packed tile (line-major, lines at stride LS)
+  auto pslot = [&](int t) { return LS == N ? t : t + (int)fdiv((uint32_t)t, g.fn) * (LS - N); };
   cpx<T>* const run = data + (long long)l0 * N;  // the tile when packed
   for (int t0 = threadIdx.x; t0 < tot; t0 += kGenU * nt) {
     T vr[kGenU], vi[kGenU];  // separate parts: arrays of the aligned pair type stay in memory
@@ -310,14 +395,14 @@ __global__ void __launch_bounds__(kGenThreads, gen_waves_per_eu<T>()) kg_lines(c
     for (int u = 0; u < kGenU; ++u) {
       const int t = t0 + u * nt;
       if (packed) {
-        at[u] = t < nl * N ? t : -1;
+        at[u] = t < nl * N ? pslot(t) : -1;
         const cpx<T> v = run[at[u] >= 0 ? t : 0];
         vr[u] = v.re;
         vi[u] = v.im;
       } else {
         const int2 le = g.tile_index(t);
         const int line = le.x, e = le.y;
-        at[u] = (t < tot && line < nl) ? line * N + e : -1;
+        at[u] = (t < tot && line < nl) ? line * LS + e : -1;
         const cpx<T> v = data[at[u] >= 0 ? g.addr(l0 + line, e) : 0];
         vr[u] = v.re;
         vi[u] = v.im;
@@ -327,10 +412,10 @@ __global__ void __launch_bounds__(kGenThreads, gen_waves_per_eu<T>()) kg_lines(c
     for (int u = 0; u < kGenU; ++u)
       if (at[u] >= 0) buf[at[u]] = cpx<T>{vr[u], vi[u]};
   }
-  const cpx<T>* twu = tw_store<T, SMALL, UT>(twl, twv, tw, N);
+  const cpx<T>* twu = tw_store<T, SMALL, UT>(twl, twv, tw, LS);
   __syncthreads();
   if constexpr (KIND == GL_CONV) {
-    gfft<T, false, EMAX, SMALL>(buf, nl, p, twu);
+    gfft<T, false, EMAX, SMALL, BLUE>(buf, nl, p, twu);
     const double s = *scale;
     const T s2 = (T)(s * s);
     // the tile's order of the loads (element-major for strided lines): the table reads of
@@ -342,7 +427,7 @@ __global__ void __launch_bounds__(kGenThreads, gen_waves_per_eu<T>()) kg_lines(c
       for (int u = 0; u < kGenU; ++u) {
         const int t = t0 + u * nt;
         const int2 le = g.tile_index(t);
-        at[u] = (t < tot && le.x < nl) ? le.x * N + le.y : -1;
+        at[u] = (t < tot && le.x < nl) ? le.x * LS + le.y : -1;
         kv[u] = ktab[at[u] >= 0 ? km.index(l0 + le.x, le.y) : 0];
       }
 #pragma unroll
@@ -350,16 +435,16 @@ __global__ void __launch_bounds__(kGenThreads, gen_waves_per_eu<T>()) kg_lines(c
         if (at[u] >= 0) buf[at[u]] = scl(buf[at[u]], kv[u] * s2);
     }
     __syncthreads();
-    gfft<T, true, EMAX, SMALL>(buf, nl, p, twu);
+    gfft<T, true, EMAX, SMALL, BLUE>(buf, nl, p, twu);
   } else {
-    gfft<T, KIND == GL_INV, EMAX, SMALL>(buf, nl, p, twu);
+    gfft<T, KIND == GL_INV, EMAX, SMALL, BLUE>(buf, nl, p, twu);
   }
   if (packed) {
-    for (int t = threadIdx.x; t < nl * N; t += nt) run[t] = buf[t];
+    for (int t = threadIdx.x; t < nl * N; t += nt) run[t] = buf[pslot(t)];
   } else {
     for (int t = threadIdx.x; t < tot; t += nt) {
       const int2 le = g.tile_index(t);
-      if (le.x < nl) data[g.addr(l0 + le.x, le.y)] = buf[le.x * N + le.y];
+      if (le.x < nl) data[g.addr(l0 + le.x, le.y)] = buf[le.x * LS + le.y];
     }
   }
 }
@@ -384,7 +469,7 @@ struct GXTile {
 // and untangled: A_k = (Z_k + conj Z_(N-k))/2, B_k = (Z_k - conj Z_(N-k))/(2i).  The
 // difference sums of the stored state: part[2b] = sum |psi(i+1) - psi(i)|^2 along x,
 // part[2b+1] along axis 1 (both over the block's lines).
-template <typename T, int EMAX, bool SMALL>
+template <typename T, int EMAX, bool SMALL, bool BLUE = false>
 __global__ void __launch_bounds__(kGenThreads) kg_r2c_x(const cpx<T>* __restrict__ psi,
                                                      cpx<T>* __restrict__ spec, GXTile xt,
                                                      GPlan p, const cpx<T>* __restrict__ tw,
@@ -396,18 +481,19 @@ __global__ void __launch_bounds__(kGenThreads) kg_r2c_x(const cpx<T>* __restrict
   int k, j0, npairs;
   xt.locate(blockIdx.x, &k, &j0, &npairs);
   const int N = xt.n0, n1 = xt.n1;
+  const int LS = BLUE ? p.m : N;  // LDS line stride: N, or Bluestein's M
   const int nt = blockDim.x;
   const int tot = npairs * N;
-  cpx<T>* twl = buf + xt.np * N;  // the twiddle table (a shorter prefetch: five loads a value)
+  cpx<T>* twl = buf + xt.np * LS;  // the twiddle table (a shorter prefetch: five loads a value)
   constexpr int UT = tw_pre<T>() / 2;
   cpx<T> twv[UT];
-  tw_fetch<T, SMALL, UT>(twv, tw, N);
+  tw_fetch<T, SMALL, UT>(twv, tw, LS);
   double dx = 0.0, dy = 0.0;  // reduced at the end, through the same LDS
   for (int t0 = threadIdx.x; t0 < tot; t0 += U * nt) {
     // |psi|^2 needs the two values; the differences their x and axis-1 neighbours
     T n0v[U], n1v[U];
     double ddx[U], ddy[U];
-    int jj[U];
+    int jj[U], ss[U];
     cpx<T> a0[U], a1[U], b0[U], b1[U], c1[U];
     bool hh[U];
 #pragma unroll
@@ -416,6 +502,7 @@ __global__ void __launch_bounds__(kGenThreads) kg_r2c_x(const cpx<T>* __restrict
       const int q = (int)fdiv((uint32_t)t, xt.fn0);
       const int i = t - q * N;
       jj[u] = t < tot ? j0 + 2 * q : -1;
+      ss[u] = q * LS + i;
       // loads from in-range addresses only, selected afterwards (a select between a
       // load and a constant would be turned into a load through a stack slot)
       const bool ok = jj[u] >= 0;
@@ -438,23 +525,23 @@ __global__ void __launch_bounds__(kGenThreads) kg_r2c_x(const cpx<T>* __restrict
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (jj[u] >= 0) {
-        buf[t0 + u * nt] = cpx<T>{n0v[u], n1v[u]};
+        buf[ss[u]] = cpx<T>{n0v[u], n1v[u]};
         dx += ddx[u];
         dy += ddy[u];
       }
     }
   }
-  const cpx<T>* twu = tw_store<T, SMALL, UT>(twl, twv, tw, N);
+  const cpx<T>* twu = tw_store<T, SMALL, UT>(twl, twv, tw, LS);
   __syncthreads();
-  gfft<T, false, EMAX, SMALL>(buf, npairs, p, twu);
+  gfft<T, false, EMAX, SMALL, BLUE>(buf, npairs, p, twu);
   const int H = N / 2 + 1;
   const int tot2 = H * 2 * xt.np;  // the full tile's indexing; pairs past npairs skipped
   for (int t = threadIdx.x; t < tot2; t += nt) {
     const int kx = (int)fdiv((uint32_t)t, xt.f2np), r = t - kx * 2 * xt.np;
     const int q = r >> 1, which = r & 1;
     if (q >= npairs || j0 + 2 * q + which >= n1) continue;
-    const cpx<T> zk = buf[q * N + kx];
-    const cpx<T> zm = buf[q * N + (kx == 0 ? 0 : N - kx)];
+    const cpx<T> zk = buf[q * LS + kx];
+    const cpx<T> zm = buf[q * LS + (kx == 0 ? 0 : N - kx)];
     cpx<T> o;
     if (which == 0) {  // (Z_k + conj Z_(N-k)) / 2
       o = cpx<T>{(T)0.5 * (zk.re + zm.re), (T)0.5 * (zk.im - zm.im)};
@@ -474,7 +561,7 @@ __global__ void __launch_bounds__(kGenThreads) kg_r2c_x(const cpx<T>* __restrict
 
 // Inverse of kg_r2c_x for the half spectrum of two real lines: Z_k = A_k + i B_k for
 // k <= N/2 and Z_(N-k) = conj A_k + i conj B_k, inverse FFT, line j = Re, j+1 = Im.
-template <typename T, int EMAX, bool SMALL>
+template <typename T, int EMAX, bool SMALL, bool BLUE = false>
 __global__ void __launch_bounds__(kGenThreads) kg_c2r_x(const cpx<T>* __restrict__ spec,
                                                      T* __restrict__ phi, GXTile xt, GPlan p,
                                                      const cpx<T>* __restrict__ tw) {
@@ -484,12 +571,13 @@ __global__ void __launch_bounds__(kGenThreads) kg_c2r_x(const cpx<T>* __restrict
   int k, j0, npairs;
   xt.locate(blockIdx.x, &k, &j0, &npairs);
   const int N = xt.n0, n1 = xt.n1;
+  const int LS = BLUE ? p.m : N;  // LDS line stride: N, or Bluestein's M
   const int H = N / 2 + 1;
   const int nt = blockDim.x;
   const int tot = H * xt.np;  // the full tile's indexing; pairs past npairs skipped
-  cpx<T>* twl = buf + xt.np * N;  // the twiddle table
+  cpx<T>* twl = buf + xt.np * LS;  // the twiddle table
   cpx<T> twv[tw_pre<T>()];
-  tw_fetch<T, SMALL, tw_pre<T>()>(twv, tw, N);
+  tw_fetch<T, SMALL, tw_pre<T>()>(twv, tw, LS);
   for (int t0 = threadIdx.x; t0 < tot; t0 += U * nt) {
     cpx<T> A[U], B[U];
     int kk[U], qq[U];
@@ -511,20 +599,20 @@ __global__ void __launch_bounds__(kGenThreads) kg_c2r_x(const cpx<T>* __restrict
     for (int u = 0; u < U; ++u) {
       if (qq[u] >= 0) {
         const int kx = kk[u], q = qq[u];
-        buf[q * N + kx] = cpx<T>{A[u].re - B[u].im, A[u].im + B[u].re};
+        buf[q * LS + kx] = cpx<T>{A[u].re - B[u].im, A[u].im + B[u].re};
         if (kx > 0 && kx < N - kx)
-          buf[q * N + N - kx] = cpx<T>{A[u].re + B[u].im, B[u].re - A[u].im};
+          buf[q * LS + N - kx] = cpx<T>{A[u].re + B[u].im, B[u].re - A[u].im};
       }
     }
   }
-  const cpx<T>* twu = tw_store<T, SMALL, tw_pre<T>()>(twl, twv, tw, N);
+  const cpx<T>* twu = tw_store<T, SMALL, tw_pre<T>()>(twl, twv, tw, LS);
   __syncthreads();
-  gfft<T, true, EMAX, SMALL>(buf, npairs, p, twu);
+  gfft<T, true, EMAX, SMALL, BLUE>(buf, npairs, p, twu);
   const int tot2 = npairs * N;
   for (int t = threadIdx.x; t < tot2; t += nt) {
     const int q = (int)fdiv((uint32_t)t, xt.fn0), i = t - q * N;
     const long long a = ((long long)k * n1 + j0 + 2 * q) * N + i;
-    const cpx<T> z = buf[t];
+    const cpx<T> z = buf[q * LS + i];
     phi[a] = z.re;
     if (j0 + 2 * q + 1 < n1) phi[a + N] = z.im;
   }

@@ -23,8 +23,9 @@ constexpr int kTileLds = kCnLds - 2048;  // dynamic LDS of the tile sweeps (stat
 // lines as 64 KiB of LDS holds (strided lines: the longest contiguous runs), halved
 // while the pass would have fewer than 512 blocks
 int lines_per_block(int n, int nlines, bool strided) {
-  const int cap = gen_max_line<T>() / n;
-  int nl = strided ? cap : 2048 / n;
+  const int ls = gen_stride(n);  // LDS values per line
+  const int cap = gen_max_line<T>() / ls;
+  int nl = strided ? cap : 2048 / ls;
   if (nl < 1) nl = 1;
   if (nl > cap) nl = cap;
   while (nl > 1 && (nlines + nl - 1) / nl < 512) nl /= 2;
@@ -58,7 +59,12 @@ hipError_t GLaunch<T>::prepare() {
       reinterpret_cast<const void*>(&kg_lines<T, GL_INV, kEmax, false>),
       reinterpret_cast<const void*>(&kg_lines<T, GL_CONV, kEmax, false>),
       reinterpret_cast<const void*>(&kg_r2c_x<T, kEmax, false>),
-      reinterpret_cast<const void*>(&kg_c2r_x<T, kEmax, false>)};
+      reinterpret_cast<const void*>(&kg_c2r_x<T, kEmax, false>),
+      reinterpret_cast<const void*>(&kg_lines<T, GL_FWD, kEmax, true, true>),
+      reinterpret_cast<const void*>(&kg_lines<T, GL_INV, kEmax, true, true>),
+      reinterpret_cast<const void*>(&kg_lines<T, GL_CONV, kEmax, true, true>),
+      reinterpret_cast<const void*>(&kg_r2c_x<T, kEmax, true, true>),
+      reinterpret_cast<const void*>(&kg_c2r_x<T, kEmax, true, true>)};
   for (const void* k : ks) {
     const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
@@ -91,7 +97,7 @@ GXTile GLaunch<T>::xtile(int n0, int n1, int n2) {
   xt.n1 = n1;
   xt.n2 = n2;
   const int pairs = (n1 + 1) / 2;  // an odd n1: the last pair has one line
-  int np = gen_max_line<T>() / n0;   // pairs whose packed lines fit in LDS
+  int np = gen_max_line<T>() / gen_stride(n0);   // pairs whose packed lines fit in LDS
   if (np > 8) np = 8;                // 16 consecutive y lines: 128-byte spectrum runs (FP64)
   if (np > pairs) np = pairs;
   if (np < 1) np = 1;
@@ -195,15 +201,19 @@ template <>
 hipError_t GLaunch<T>::r2c_x(hipStream_t st, const cpx<T>* psi, cpx<T>* spec, const GPlan& p,
                              const cpx<T>* tw, double* part, int n0, int n1, int n2) {
   const GXTile xt = xtile(n0, n1, n2);
-  if (xt.np * n0 > gen_max_line<T>()) return hipErrorInvalidValue;
+  if (xt.np * p.m > gen_max_line<T>()) return hipErrorInvalidValue;
   // the lines and the twiddle table; the block's reduction reuses the line buffer (at
   // least 32 doubles)
-  const size_t lds_r2c = lds_of(xt.np * n0 + n0) < 256 ? 256 : lds_of(xt.np * n0 + n0);
-  if (gen_plan_small(p))
-    hipLaunchKernelGGL((kg_r2c_x<T, kEmax, true>), dim3(xt.nbj * n2), threads_for(xt.np * n0),
+  const int ls = p.m;
+  const size_t lds_r2c = lds_of(xt.np * ls + ls) < 256 ? 256 : lds_of(xt.np * ls + ls);
+  if (p.blue)  // Bluestein: stages of M, radices 2..8
+    hipLaunchKernelGGL((kg_r2c_x<T, kEmax, true, true>), dim3(xt.nbj * n2),
+                       threads_for(xt.np * ls), lds_r2c, st, psi, spec, xt, p, tw, part);
+  else if (gen_plan_small(p))
+    hipLaunchKernelGGL((kg_r2c_x<T, kEmax, true>), dim3(xt.nbj * n2), threads_for(xt.np * ls),
                        lds_r2c, st, psi, spec, xt, p, tw, part);
   else
-    hipLaunchKernelGGL((kg_r2c_x<T, kEmax, false>), dim3(xt.nbj * n2), threads_for(xt.np * n0),
+    hipLaunchKernelGGL((kg_r2c_x<T, kEmax, false>), dim3(xt.nbj * n2), threads_for(xt.np * ls),
                        lds_r2c, st, psi, spec, xt, p, tw, part);
   return hipGetLastError();
 }
@@ -212,13 +222,17 @@ template <>
 hipError_t GLaunch<T>::c2r_x(hipStream_t st, const cpx<T>* spec, T* phi, const GPlan& p,
                              const cpx<T>* tw, int n0, int n1, int n2) {
   const GXTile xt = xtile(n0, n1, n2);
-  if (xt.np * n0 > gen_max_line<T>()) return hipErrorInvalidValue;
-  if (gen_plan_small(p))
-    hipLaunchKernelGGL((kg_c2r_x<T, kEmax, true>), dim3(xt.nbj * n2), threads_for(xt.np * n0),
-                       lds_of(xt.np * n0 + n0), st, spec, phi, xt, p, tw);
+  if (xt.np * p.m > gen_max_line<T>()) return hipErrorInvalidValue;
+  if (p.blue)
+    hipLaunchKernelGGL((kg_c2r_x<T, kEmax, true, true>), dim3(xt.nbj * n2),
+                       threads_for(xt.np * p.m), lds_of(xt.np * p.m + p.m), st, spec, phi, xt, p,
+                       tw);
+  else if (gen_plan_small(p))
+    hipLaunchKernelGGL((kg_c2r_x<T, kEmax, true>), dim3(xt.nbj * n2), threads_for(xt.np * p.m),
+                       lds_of(xt.np * p.m + p.m), st, spec, phi, xt, p, tw);
   else
-    hipLaunchKernelGGL((kg_c2r_x<T, kEmax, false>), dim3(xt.nbj * n2), threads_for(xt.np * n0),
-                       lds_of(xt.np * n0 + n0), st, spec, phi, xt, p, tw);
+    hipLaunchKernelGGL((kg_c2r_x<T, kEmax, false>), dim3(xt.nbj * n2), threads_for(xt.np * p.m),
+                       lds_of(xt.np * p.m + p.m), st, spec, phi, xt, p, tw);
   return hipGetLastError();
 }
 
@@ -226,7 +240,7 @@ template <>
 hipError_t GLaunch<T>::lines(int kind, hipStream_t st, cpx<T>* data, int n, int nlines, int G,
                              long long so, long long si, long long se, const GPlan& p,
                              const cpx<T>* tw, const T* ktab, GKtab km, const double* scale) {
-  if (n > gen_max_line<T>() || nlines < 1) return hipErrorInvalidValue;
+  if (p.m > gen_max_line<T>() || nlines < 1) return hipErrorInvalidValue;
   GLines g{};
   g.n = n;
   g.nlines = nlines;
@@ -239,12 +253,26 @@ hipError_t GLaunch<T>::lines(int kind, hipStream_t st, cpx<T>* data, int n, int 
   g.fnl = fdiv_make((uint32_t)g.nl);
   g.fg = fdiv_make((uint32_t)G);
   const int blocks = (nlines + g.nl - 1) / g.nl;
-  const size_t lds = lds_of(g.nl * n + n);  // the lines and the twiddle table
+  const size_t lds = lds_of(g.nl * p.m + p.m);  // the lines and the twiddle table
   const bool small = gen_plan_small(p);
+  if (p.blue) {
+    switch (kind) {
+#define GLINESB(K)                                                                           \
+  case K:                                                                                    \
+    hipLaunchKernelGGL((kg_lines<T, K, kEmax, true, true>), dim3(blocks),                    \
+                       threads_for(g.nl * p.m), lds, st, data, g, p, tw, ktab, km, scale);   \
+    break;
+      GLINESB(GL_FWD) GLINESB(GL_INV) GLINESB(GL_CONV)
+#undef GLINESB
+      default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   switch (kind * 2 + (small ? 1 : 0)) {
 #define GLINES(K, S)                                                                      \
   case K * 2 + (S ? 1 : 0):                                                               \
-    hipLaunchKernelGGL((kg_lines<T, K, kEmax, S>), dim3(blocks), threads_for(g.nl * n), lds, st, \
+    hipLaunchKernelGGL((kg_lines<T, K, kEmax, S>), dim3(blocks), threads_for(g.nl * p.m), lds, st, \
                        data, g, p, tw, ktab, km, scale);                                  \
     break;
     GLINES(GL_FWD, true) GLINES(GL_FWD, false) GLINES(GL_INV, true) GLINES(GL_INV, false)

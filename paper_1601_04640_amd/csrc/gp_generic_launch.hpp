@@ -15,12 +15,18 @@ constexpr int gen_max_line() {
   return (int)(65536 / (2 * sizeof(T)));
 }
 
-// An axis the run-time-length kernels accept: at least 4 points, at most gen_max_line,
-// every prime factor at most 31 (even or odd).
+// An axis the run-time-length kernels accept: at least 4 points, with its FFT's LDS line
+// (N, or Bluestein's M for lengths with a prime factor above 31) at most gen_max_line.
 template <typename T>
 inline bool gen_size_ok(int n) {
   GPlan p;
-  return n >= 4 && n <= gen_max_line<T>() && gen_plan(n, &p);
+  return n >= 4 && n <= gen_max_line<T>() && gen_plan(n, &p) && p.m <= gen_max_line<T>();
+}
+
+// LDS line stride of an axis's FFT: N, or Bluestein's M.
+inline int gen_stride(int n) {
+  GPlan p;
+  return gen_plan(n, &p) ? p.m : n;
 }
 
 template <typename T>

@@ -47,10 +47,9 @@ def ws(**kw):
     return B.gp_workspace_bytes(B.make_params(**base))
 
 
-# below 4, a prime factor above 31 (37, 41, 43, 47, 53), or a line past 64 KiB of LDS
-# (FP64: 4096 points)
-@pytest.mark.parametrize("n", [3, 2, 0, -8, 37, 74, 82, 86, 94, 106, 2 * 37 * 3, 3 * 37, 4098,
-                               8192])
+# below 4, or an FFT line past 64 KiB of LDS (FP64: 4096 points; for a length with a prime
+# factor above 31, Bluestein's M >= 2N - 1: 2062 = 2 1031 needs M = 4125 -> 4200)
+@pytest.mark.parametrize("n", [3, 2, 0, -8, 2062, 4098, 8192])
 def test_unsupported_sizes_rejected(n):
     with pytest.raises(B.GPError) as e:
         ws(nx=n, prec="fp64")
@@ -62,6 +61,8 @@ def test_unsupported_sizes_rejected(n):
 
 def test_line_length_limit_depends_on_precision():
     assert ws(geom="2dxy", nx=8192, ny=8, prec="fp32") > 0
+    assert ws(geom="2dxy", nx=2062, ny=8, prec="fp32") > 0   # Bluestein M = 4200
+    assert B.gp_axis_kind(2062, "fp64") == 0 and B.gp_axis_kind(2039, "fp64") == 2
     with pytest.raises(B.GPError) as e:
         ws(geom="2dxy", nx=8192, ny=8, prec="fp64")
     assert e.value.status == B.GP_E_SIZE
@@ -75,29 +76,22 @@ def test_line_length_limit_depends_on_precision():
 @pytest.mark.parametrize("n", [8, 10, 12, 16, 20, 24, 30, 32, 40, 48, 60, 64, 80, 96, 120,
                                128, 160, 192, 240, 256, 320, 384, 480, 512,
                                4, 6, 14, 22, 26, 36, 50, 54, 62, 90, 100, 540, 600, 1000,
-                               1024, 2048, 4096, 5, 7, 9, 15, 45, 49, 99, 625, 1001, 4095])
+                               1024, 2048, 4096, 5, 7, 9, 15, 45, 49, 99, 625, 1001, 4095,
+                               37, 74, 111, 106, 1009, 2039])
 def test_supported_sizes_accepted(n):
     assert ws(nx=n, ny=8, nz=8, prec="fp64") > 0
 
 
-def test_supported_size_set_follows_the_factor_rule():
-    """Every length 4..600, even or odd, is accepted exactly when all its prime factors
-    are at most 31 (FP32 and FP64 agree below the FP64 line limit)."""
-    def ok(n):
-        m = n
-        for p in (2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31):
-            while m % p == 0:
-                m //= p
-        return m == 1
+def test_every_length_to_600_is_accepted():
+    """Every length 4..600, even or odd, runs: kind 1 exactly for the specialised lengths
+    (2^a 3^b 5^c, b, c <= 1, 8..512, even), kind 2 otherwise (prime factors up to 31 by
+    Stockham stages, larger ones by Bluestein's algorithm); FP32 and FP64 agree."""
+    spec = {8, 10, 12, 16, 20, 24, 30, 32, 40, 48, 60, 64, 80, 96, 120, 128, 160, 192, 240,
+            256, 320, 384, 480, 512}
     for n in range(4, 601):
         for prec in ("fp32", "fp64"):
-            try:
-                ws(geom="2dxy", nx=n, ny=8, prec=prec)
-                got = True
-            except B.GPError as e:
-                assert e.status == B.GP_E_SIZE
-                got = False
-            assert got == ok(n), (n, prec)
+            assert B.gp_axis_kind(n, prec) == (1 if n in spec else 2), (n, prec)
+        assert ws(geom="2dxy", nx=n, ny=8, prec="fp64") > 0
 
 
 @pytest.mark.parametrize("kw", [dict(dt=0.0), dict(dt=-1e-3), dict(dx=0.0), dict(dy=-0.1),

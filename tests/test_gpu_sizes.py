@@ -48,6 +48,16 @@ CASES = {
                        gamma=1.0, nu=4.0, lam=2.0, g=15.0, gdd=12.0, R=0.0),
     "3d_5x9x7": dict(geom="3d", nx=5, ny=9, nz=7, dx=1.0, dy=0.7, dz=0.8, dt=0.002,
                      gamma=1.0, nu=1.0, lam=1.2, g=5.0, gdd=2.0, R=2.0),
+    # prime factors above 31 on every axis, by Bluestein's algorithm (convolution lengths
+    # 75, 147 and 81): 37 and 41 prime, 74 = 2 37
+    "3d_37x74x41": dict(geom="3d", nx=37, ny=74, nz=41, dx=0.35, dy=0.2, dz=0.3, dt=0.002,
+                        gamma=1.0, nu=1.1, lam=1.5, g=20.0, gdd=8.0, R=4.0),
+    # 106 = 2 53 as x, 97 (prime) as the convolution axis
+    "2dxy_106x97": dict(geom="2dxy", nx=106, ny=97, nz=1, dx=0.15, dy=0.16, dz=1.0, dt=0.001,
+                        gamma=1.0, nu=1.2, lam=4.0, g=25.0, gdd=10.0, R=0.0),
+    # 1009 (prime) x lines in XZ
+    "2dxz_1009x24": dict(geom="2dxz", nx=1009, ny=1, nz=24, dx=0.02, dy=1.0, dz=0.4,
+                         dt=0.0005, gamma=1.0, nu=4.0, lam=1.5, g=15.0, gdd=10.0, R=0.0),
 }
 
 
@@ -120,9 +130,11 @@ def test_random_field_start(prec, gpu_lib):
         s.close()
 
 
-@pytest.mark.parametrize("prec,n", [("fp32", 8192), ("fp64", 4096), ("fp64", 2 * 3 * 7 * 29)])
+@pytest.mark.parametrize("prec,n", [("fp32", 8192), ("fp64", 4096), ("fp64", 2 * 3 * 7 * 29),
+                                    ("fp32", 4093), ("fp64", 2039)])
 def test_longest_lines(prec, n, gpu_lib):
-    """The longest x and y lines one block holds (and a 29-point radix) in 2D: x sweeps of
+    """The longest x and y lines one block holds (and a 29-point radix; and the longest
+    primes, by Bluestein's algorithm through 8192 / 4096-point FFTs) in 2D: x sweeps of
     several waves per line, y sweeps on the transposed state."""
     from paper_1601_04640_amd.binding import Solver
     for nx, ny in ((n, 12), (12, n)):
