@@ -374,7 +374,9 @@ __global__ void __launch_bounds__(kGenThreads, (gen_waves_per_eu<T, BLUE>())) kg
                                                      const double* __restrict__ scale) {
   extern __shared__ __align__(16) char lds_raw[];
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lds_raw);
-  const int l0 = blockIdx.x * g.nl;
+  // tiles numbered XCD-contiguously (blocks run on the XCDs round-robin): neighbouring
+  // tiles, which share 128-byte lines of strided data, share an L2
+  const int l0 = xcd_tile(blockIdx.x, gridDim.x) * g.nl;
   const int nl = min(g.nl, g.nlines - l0);
   const int N = g.n;
   const int LS = BLUE ? p.m : N;   // LDS line stride: N, or Bluestein's M
@@ -779,7 +781,9 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
   __shared__ cpx<T> wP[kTileMaxWaves], wB[kTileMaxWaves];  // the waves' composed maps
   const int N = g.n;
   const int S = (int)fs.d, Sp = S | 1, LS = cn_line_slots(N, 64 * wpl);
-  const int l0 = blockIdx.x * g.nl;
+  // tiles numbered XCD-contiguously (blocks run on the XCDs round-robin): neighbouring
+  // tiles, which share 128-byte lines of strided data, share an L2
+  const int l0 = xcd_tile(blockIdx.x, gridDim.x) * g.nl;
   const int nl = min(g.nl, g.nlines - l0);
   const int nt = blockDim.x;
   const int tot = g.nl * N;  // the full tile's indexing; lines past nl are skipped
