@@ -481,7 +481,7 @@ __global__ void __launch_bounds__(kGenThreads) kg_r2c_x(const cpx<T>* __restrict
   extern __shared__ __align__(16) char lds_raw[];
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lds_raw);
   int k, j0, npairs;
-  xt.locate(blockIdx.x, &k, &j0, &npairs);
+  xt.locate(xcd_tile(blockIdx.x, gridDim.x), &k, &j0, &npairs);  // XCD-contiguous tiles
   const int N = xt.n0, n1 = xt.n1;
   const int LS = BLUE ? p.m : N;  // LDS line stride: N, or Bluestein's M
   const int nt = blockDim.x;
@@ -571,7 +571,7 @@ __global__ void __launch_bounds__(kGenThreads) kg_c2r_x(const cpx<T>* __restrict
   extern __shared__ __align__(16) char lds_raw[];
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lds_raw);
   int k, j0, npairs;
-  xt.locate(blockIdx.x, &k, &j0, &npairs);
+  xt.locate(xcd_tile(blockIdx.x, gridDim.x), &k, &j0, &npairs);  // XCD-contiguous tiles
   const int N = xt.n0, n1 = xt.n1;
   const int LS = BLUE ? p.m : N;  // LDS line stride: N, or Bluestein's M
   const int H = N / 2 + 1;
