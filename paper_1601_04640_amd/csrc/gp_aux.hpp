@@ -321,4 +321,23 @@ __global__ void k_clear_u64(unsigned long long* p, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0ull;
 }
 
+// P_s = g_a ... g_b and Q_s = sum_m (g_a ... g_(m-1)) (g_a ... g_m) of segment s (rows
+// a = s n .. b = a + n - 1, g = f / 2 of the factor table), in FP64, one thread per
+// segment.
+template <typename T>
+__global__ void k_seg_tables(const cpx<T>* __restrict__ f, int n, int nseg, cpx<T>* pq) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nseg) return;
+  zd P{1.0, 0.0}, Q{0.0, 0.0};
+  for (int i = s * n; i < s * n + n; ++i) {
+    const zd g{0.5 * (double)f[i].re, 0.5 * (double)f[i].im};
+    const zd R = zmul(P, g);
+    const zd PR = zmul(P, R);
+    Q = zd{Q.re + PR.re, Q.im + PR.im};
+    P = R;
+  }
+  pq[2 * s] = cpx<T>{(T)P.re, (T)P.im};
+  pq[2 * s + 1] = cpx<T>{(T)Q.re, (T)Q.im};
+}
+
 }  // namespace gpdbec

@@ -41,10 +41,16 @@ bool fast_size(int n) {
   }
 }
 
-// Every axis length a context accepts: a specialised one, or one the run-time-length
-// passes take (even, >= 4, prime factors <= 31, one line within 64 KiB of LDS).
-bool size_ok(int n, bool fp64) {
-  return fast_size(n) || (fp64 ? gen_size_ok<double>(n) : gen_size_ok<float>(n));
+// Every axis length a context accepts: a specialised one, one the run-time-length passes
+// take (n >= 4, its FFT line within 64 KiB of LDS), or, in a 2D grid (plane), a longer one
+// with a four-step split and Crank-Nicolson segments.
+bool long_size(int n, bool fp64) {
+  GLong lp;
+  return fp64 ? gen_long_plan<double>(n, &lp) : gen_long_plan<float>(n, &lp);
+}
+bool size_ok(int n, bool fp64, bool plane = false) {
+  return fast_size(n) || (fp64 ? gen_size_ok<double>(n) : gen_size_ok<float>(n)) ||
+         (plane && long_size(n, fp64));
 }
 
 // The axes a geometry uses: (n0, n1, n2) with n2 = 1 in 2D.
@@ -71,9 +77,17 @@ struct Layout {
   // axes without a compile-time specialisation run the run-time-length passes; gscr: their
   // one-thread-per-line sweeps need a grid of scratch values (o_gscr)
   bool generic, gscr;
+  // 2D axes longer than one LDS line (x, y): four-step FFT and segmented sweeps; the
+  // intermediate grid of the x transforms and the transposed y sweep use o_gscr
+  bool lx, ly;
+  GLong lg[2];
+  GLX lxg;  // the long-x passes' geometry (host side; the plans' strides from lg)
   // byte offsets inside the workspace
   size_t o_psi, o_V, o_spec, o_ktab, o_tw[3], o_blue[3], o_cn[3][3], o_px[2], o_pnl, o_pcol, o_padj, o_sfield,
       o_scalars, o_ring, o_obs, o_io, o_stamps, o_stage, o_gscr, total;
+  // long axes: stage twiddles of the A- and B-point plans and W_N^m, their Bluestein
+  // tables, the segments' carry products per factor set, segment summaries and carries
+  size_t o_ltw[2][3], o_lblue[2][2], o_seg[2][3], o_ssum, o_scar;
 };
 
 struct Scalars {  // device-side scalars (one 256-byte block)
@@ -96,16 +110,16 @@ gp_status validate(const gp_params* p) {
       !isfinite(p->lambda) || !isfinite(p->cutoff_R))
     return GP_E_ARG;
   const bool fp64 = p->prec == GP_FP64;
-  if (!size_ok(p->nx, fp64)) return GP_E_SIZE;
+  if (!size_ok(p->nx, fp64, p->geom != GP_3D)) return GP_E_SIZE;
   if (p->geom == GP_3D) {
     if (!(p->dy > 0) || !(p->dz > 0)) return GP_E_ARG;
     if (!size_ok(p->ny, fp64) || !size_ok(p->nz, fp64)) return GP_E_SIZE;
   } else if (p->geom == GP_2D_XY) {
     if (!(p->dy > 0) || !(p->lambda > 0)) return GP_E_ARG;
-    if (!size_ok(p->ny, fp64)) return GP_E_SIZE;
+    if (!size_ok(p->nx, fp64, true) || !size_ok(p->ny, fp64, true)) return GP_E_SIZE;
   } else {
     if (!(p->dz > 0) || !(p->nu > 0)) return GP_E_ARG;
-    if (!size_ok(p->nz, fp64)) return GP_E_SIZE;
+    if (!size_ok(p->nx, fp64, true) || !size_ok(p->nz, fp64, true)) return GP_E_SIZE;
   }
   // the run-time-length passes address the grid with 32-bit line offsets
   int n0, n1, n2;
@@ -135,9 +149,28 @@ Layout make_layout(const gp_params* p, unsigned host = 0) {
   const int H = L.n0 / 2 + 1;
   L.nspec = (size_t)H * L.n1 * L.n2;
   L.generic = is_generic(p);
+  const int ns0[2] = {L.n0, L.n1};
+  bool lng[2] = {false, false};
+  for (int a = 0; a < 2 && p->geom != GP_3D; ++a)
+    lng[a] = fp64 ? gen_long_plan<double>(ns0[a], &L.lg[a])
+                  : gen_long_plan<float>(ns0[a], &L.lg[a]);
+  L.lx = lng[0];
+  L.ly = lng[1];
+  GPlan lpa[2], lpb[2];
+  for (int a = 0; a < 2; ++a)
+    if (lng[a]) {
+      gen_plan(L.lg[a].A, &lpa[a]);
+      gen_plan(L.lg[a].B, &lpb[a]);
+    }
+  if (L.lx) {
+    L.lxg = fp64 ? GLaunch<double>::lx_geom(L.n0, L.n1, L.lg[0], lpa[0], lpb[0])
+                 : GLaunch<float>::lx_geom(L.n0, L.n1, L.lg[0], lpa[0], lpb[0]);
+    L.nspec = (size_t)L.n1 * L.lxg.rs;   // rows of kept four-step slots
+  }
   if (L.generic) {
     L.nb_x = fp64 ? GLaunch<double>::x_blocks(L.n0, L.n1, L.n2)
                   : GLaunch<float>::x_blocks(L.n0, L.n1, L.n2);
+    if (L.lx) L.nb_x = GLaunch<float>::lx_blocks(L.lxg);
     L.nb_nl = fp64 ? GLaunch<double>::nl_blocks(L.n0, L.n1, L.n2)
                    : GLaunch<float>::nl_blocks(L.n0, L.n1, L.n2);
     // blocks of the last sweep (z in 3D, y in 2D), which the z observe shares
@@ -153,7 +186,11 @@ Layout make_layout(const gp_params* p, unsigned host = 0) {
     L.gscr = p->geom == GP_3D
                  ? (GLaunch<float>::cn_by_columns(L.n1, true, L.n0 * L.n2) ||
                     GLaunch<float>::cn_by_columns(L.n2, true, L.n0 * L.n1))
-                 : GLaunch<float>::y2d_transposed(L.n1);
+                 : (GLaunch<float>::y2d_transposed(L.n1) || L.lx);
+    // a long y axis: its sweep (the last in 2D) is segmented, on the transposed grid
+    if (L.ly)
+      L.nb_col = fp64 ? GLaunch<double>::seg_blocks(L.lg[1].sn, L.n0 * L.lg[1].nseg)
+                      : GLaunch<float>::seg_blocks(L.lg[1].sn, L.n0 * L.lg[1].nseg);
   } else {
     const int tj = tj_of(fp64, L.n0);
     L.nb_x = ((L.n1 + tj - 1) / tj) * L.n2;
@@ -175,16 +212,19 @@ Layout make_layout(const gp_params* p, unsigned host = 0) {
   L.o_psi = take(2 * L.esz * L.npts);
   L.o_V = take((host & GP_HOST_V) ? 0 : L.esz * L.npts);
   L.o_spec = take(2 * L.esz * L.nspec);
-  // kernel table: 3D holds the quadrant k1 <= n1/2, k2 <= n2/2 of the half spectrum
-  L.nktab = (p->geom == GP_3D) ? (size_t)H * (L.n1 / 2 + 1) * (L.n2 / 2 + 1) : L.nspec;
+  // kernel table: 3D holds the quadrant k1 <= n1/2, k2 <= n2/2 of the half spectrum; 2D
+  // every k1 of kx <= n0/2
+  L.nktab = (p->geom == GP_3D) ? (size_t)H * (L.n1 / 2 + 1) * (L.n2 / 2 + 1)
+                               : (size_t)H * L.n1;
   L.o_ktab = take((host & GP_HOST_KTAB) ? 0 : L.esz * L.nktab);
   const int ns[3] = {L.n0, L.n1, L.n2};
   for (int a = 0; a < 3; ++a) {
     // twiddles of the stage length (Bluestein's M for a run-time-length axis with a prime
     // factor above 31), then that axis's chirp (n) and filter (M)
-    const int ms = L.generic ? gen_stride(ns[a]) : ns[a];
+    const bool la = a < 2 && lng[a];
+    const int ms = la ? 0 : (L.generic ? gen_stride(ns[a]) : ns[a]);
     L.o_tw[a] = take(2 * L.esz * ms);
-    L.o_blue[a] = take(ms != ns[a] ? 2 * L.esz * (size_t)(ns[a] + ms) : 0);
+    L.o_blue[a] = take(!la && ms != ns[a] ? 2 * L.esz * (size_t)(ns[a] + ms) : 0);
     // factor table and scan weights per set (imaginary time, real time, adjoint)
     for (int t = 0; t < 3; ++t) L.o_cn[a][t] = take(2 * L.esz * (ns[a] + kScanWeights));
   }
@@ -210,6 +250,20 @@ Layout make_layout(const gp_params* p, unsigned host = 0) {
   L.o_stamps = take(16 * (size_t)L.nb_x);
   L.o_stage = take(sizeof(double) * kStageVals * kStageMax);
   L.o_gscr = take(L.generic && L.gscr ? 2 * L.esz * L.npts : 0);
+  size_t nsegl = 0;  // segment lines of the longer segmented sweep
+  for (int a = 0; a < 2; ++a) {
+    const GPlan* pl[2] = {&lpa[a], &lpb[a]};
+    for (int q = 0; q < 2; ++q) {
+      L.o_ltw[a][q] = take(lng[a] ? 2 * L.esz * pl[q]->m : 0);
+      L.o_lblue[a][q] =
+          take(lng[a] && pl[q]->blue ? 2 * L.esz * (size_t)(pl[q]->n + pl[q]->m) : 0);
+    }
+    L.o_ltw[a][2] = take(lng[a] ? 2 * L.esz * ns0[a] : 0);
+    for (int t = 0; t < 3; ++t) L.o_seg[a][t] = take(lng[a] ? 4 * L.esz * L.lg[a].nseg : 0);
+    if (lng[a]) nsegl = std::max(nsegl, (size_t)ns0[1 - a] * L.lg[a].nseg);
+  }
+  L.o_ssum = take(8 * L.esz * nsegl);
+  L.o_scar = take(8 * L.esz * nsegl);
   L.total = o;
   return L;
 }
@@ -251,6 +305,7 @@ struct gp_ctx {
   double gc;
   int clock_khz = 0;  // device wall clock (kernel-span timing)
   GPlan gplan[3] = {};  // radix plans of the run-time-length passes (axes 0, 1, 2)
+  GPlan lplan[2][2] = {};  // long 2D axes: plans of the A- and B-point transforms
   // device addresses of caller-owned pinned host memory holding V / the kernel table
   // (gp_init_ex with GP_HOST_V / GP_HOST_KTAB), else null
   char* hostV = nullptr;
@@ -399,12 +454,73 @@ struct Passes {
   // the z convolution and the inverse y FFT (2D: the y convolution), the x C2R into a
   // real Phi grid, the phase in place, then the x, y and z sweeps; the finalisation runs
   // after every step.
+  // long 2D axes: stage twiddles of the A- (q = 0) and B-point (q = 1) plans, W_N^m (q = 2)
+  static const cpx<T>* ltw(gp_ctx* c, int a, int q) { return c->at<cpx<T>>(c->L.o_ltw[a][q]); }
+  static cpx<T>* gscr(gp_ctx* c) { return c->at<cpx<T>>(c->L.o_gscr); }
+
+  // 2D convolution along y of a spectrum whose x axis or y axis is split (four-step):
+  // spectrum [kx][y] (x in one line) or rows [y][rs] of four-step slots (long x)
+  static gp_status g_conv_y_long(gp_ctx* c, const double* scale) {
+    const Layout& L = c->L;
+    const int H = L.n0 / 2 + 1;
+    GKtab km{0, L.n1, 1, fdiv_make((uint32_t)L.n1)};
+    if (L.lx) {
+      km.Ax = L.lg[0].A;
+      km.Bx = L.lg[0].B;
+      km.nx = L.n0;
+      km.fAx = fdiv_make((uint32_t)L.lg[0].A);
+    }
+    if (!L.ly) {  // long x only: columns p of the rows, the whole y line in LDS
+      km.m4 = 2;
+      const int rs = L.lxg.rs;
+      GP_PASS(c, GP_PASS_CONV_Y,
+              GLaunch<T>::lines(GL_CONV, c->st, spec(c), L.n1, rs, rs, 0, 1, rs, c->gplan[1],
+                                tw(c, 1), Kp(c), km, scale));
+      return GP_OK;
+    }
+    // y = a + Ay b: B-point transforms over b with the twiddle of column a, the A-point
+    // convolution over a (wavenumber By ka + kb), the inverse steps
+    const int Ay = L.lg[1].A, By = L.lg[1].B;
+    km.By = By;
+    km.fBy = fdiv_make((uint32_t)By);
+    const GPlan& pa = c->lplan[1][0];
+    const GPlan& pb = c->lplan[1][1];
+    GP_TRY(pass_begin(c, GP_PASS_CONV_Y));
+    if (!L.lx) {  // spectrum [kx][y]: lines (kx, a) of stride Ay; inner lines contiguous
+      km.m4 = 1;
+      GP_HIP(GLaunch<T>::lines(GL_FWD, c->st, spec(c), By, H * Ay, Ay, L.n1, 1, Ay, pb,
+                               ltw(c, 1, 1), nullptr, km, scale, ltw(c, 1, 2), 0));
+      GP_HIP(GLaunch<T>::lines(GL_CONV, c->st, spec(c), Ay, H * By, 1, Ay, 0, 1, pa,
+                               ltw(c, 1, 0), Kp(c), km, scale));
+      GP_HIP(GLaunch<T>::lines(GL_INV, c->st, spec(c), By, H * Ay, Ay, L.n1, 1, Ay, pb,
+                               ltw(c, 1, 1), nullptr, km, scale, ltw(c, 1, 2), 0));
+    } else {      // rows [y][rs]: lines (a, p) and (kb, p), consecutive p adjacent
+      km.m4 = 3;
+      const long long rs = L.lxg.rs;
+      GP_HIP(GLaunch<T>::lines(GL_FWD, c->st, spec(c), By, (int)(Ay * rs), (int)rs, rs, 1,
+                               Ay * rs, pb, ltw(c, 1, 1), nullptr, km, scale, ltw(c, 1, 2), 1));
+      GP_HIP(GLaunch<T>::lines(GL_CONV, c->st, spec(c), Ay, (int)(By * rs), (int)rs, Ay * rs, 1,
+                               rs, pa, ltw(c, 1, 0), Kp(c), km, scale));
+      GP_HIP(GLaunch<T>::lines(GL_INV, c->st, spec(c), By, (int)(Ay * rs), (int)rs, rs, 1,
+                               Ay * rs, pb, ltw(c, 1, 1), nullptr, km, scale, ltw(c, 1, 2), 1));
+    }
+    return pass_end(c, GP_PASS_CONV_Y);
+  }
+
   static gp_status g_convolution(gp_ctx* c, const cpx<T>* src, const double* scale) {
     const Layout& L = c->L;
     const int H = L.n0 / 2 + 1;
-    GP_PASS(c, GP_PASS_R2C_X,
-            GLaunch<T>::r2c_x(c->st, src, spec(c), c->gplan[0], tw(c, 0),
-                              c->at<double>(L.o_px[0]), L.n0, L.n1, L.n2));
+    if (L.lx) {
+      GP_PASS(c, GP_PASS_R2C_X,
+              GLaunch<T>::lx_r2c(c->st, src, gscr(c), spec(c), L.lxg, c->lplan[0][0],
+                                 c->lplan[0][1], ltw(c, 0, 0), ltw(c, 0, 1), ltw(c, 0, 2),
+                                 c->at<double>(L.o_px[0])));
+    } else {
+      GP_PASS(c, GP_PASS_R2C_X,
+              GLaunch<T>::r2c_x(c->st, src, spec(c), c->gplan[0], tw(c, 0),
+                                c->at<double>(L.o_px[0]), L.n0, L.n1, L.n2));
+    }
+    if (L.lx || L.ly) return g_conv_y_long(c, scale);
     const GKtab none{0, L.n1, L.n2, fdiv_make((uint32_t)L.n1)};
     if (c->p.geom == GP_3D) {
       // y lines l = kx n2 + k2 (contiguous); z lines l = kx n1 + k1 (stride n1)
@@ -432,12 +548,19 @@ struct Passes {
                  fdiv_make((uint32_t)c->L.n0), fdiv_make((uint32_t)c->L.n1)};
   }
 
+  // the x C2R of the convolved spectrum into phi
+  static gp_status g_c2r(gp_ctx* c, T* phi) {
+    const Layout& L = c->L;
+    if (L.lx)
+      return dev(GLaunch<T>::lx_c2r(c->st, spec(c), gscr(c), phi, L.lxg, c->lplan[0][0],
+                                    c->lplan[0][1], ltw(c, 0, 0), ltw(c, 0, 1), ltw(c, 0, 2)));
+    return dev(GLaunch<T>::c2r_x(c->st, spec(c), phi, c->gplan[0], tw(c, 0), L.n0, L.n1, L.n2));
+  }
+
   // Phi of src into phi (the convolution, then the x C2R)
   static gp_status g_phi(gp_ctx* c, const cpx<T>* src, const double* scale, T* phi) {
-    const Layout& L = c->L;
     GP_TRY(g_convolution(c, src, scale));
-    GP_HIP(GLaunch<T>::c2r_x(c->st, spec(c), phi, c->gplan[0], tw(c, 0), L.n0, L.n1, L.n2));
-    return GP_OK;
+    return g_c2r(c, phi);
   }
 
   // CN sweep of axis a (0: x, 1: y, 2: z) of the stored state; mode 0: solve, 1: solve
@@ -448,9 +571,21 @@ struct Passes {
     const cpx<T>* f = mode == 2 ? nullptr : cn(c, axis, k);
     const long long plane = (long long)L.n0 * L.n1;
     cpx<T>* dscr = c->at<cpx<T>>(L.o_gscr);
+    if (axis == 0 && L.lx)  // long x lines: segmented
+      return dev(GLaunch<T>::seg_sweep(mode, c->st, psi(c), L.lg[0].sn, L.lg[0].nseg, L.n1, f,
+                                       c->at<cpx<T>>(L.o_seg[0][k]), c->at<cpx<T>>(L.o_ssum),
+                                       c->at<cpx<T>>(L.o_scar), pc));
     if (axis == 0)  // lines (j, k2), contiguous
       return dev(GLaunch<T>::cn_lines(mode, c->st, psi(c), L.n0, L.n1 * L.n2, 1, L.n0, 0, 1,
                                       f, pc, dscr));
+    if (axis == 1 && L.ly) {
+      // long y lines: segmented, along the rows of the transposed state
+      GP_HIP(GLaunch<T>::transpose(c->st, psi(c), dscr, L.n1, L.n0));
+      GP_HIP(GLaunch<T>::seg_sweep(mode, c->st, dscr, L.lg[1].sn, L.lg[1].nseg, L.n0, f,
+                                   c->at<cpx<T>>(L.o_seg[1][k]), c->at<cpx<T>>(L.o_ssum),
+                                   c->at<cpx<T>>(L.o_scar), pc));
+      return dev(GLaunch<T>::transpose(c->st, dscr, psi(c), L.n0, L.n1));
+    }
     if (axis == 1 && c->p.geom != GP_3D && GLaunch<T>::y2d_transposed(L.n1)) {
       // 2D lines longer than a tile: the sweep runs along the rows of the transposed state
       // (scratch grid, n0 rows of n1) and the result is transposed back
@@ -474,8 +609,13 @@ struct Passes {
     GP_TRY(settle(c));
     GP_TRY(g_convolution(c, psi(c), &c->sc()->scale));
     GP_TRY(pass_begin(c, GP_PASS_C2R_NL_CNX));
-    GP_HIP(GLaunch<T>::c2r_x(c->st, spec(c), phi, c->gplan[0], tw(c, 0), L.n0, L.n1, L.n2));
-    {
+    GP_TRY(g_c2r(c, phi));
+    if (L.lx) {
+      // long x lines: the nonlinear sub-step in place, then the segmented sweep
+      GP_HIP(GLaunch<T>::nonlinear(mode, c->st, psi(c), Vp(c), phi, &c->sc()->scale,
+                                   g_scalars(c), L.n0, L.n1, L.n2, c->at<double>(L.o_pnl)));
+      GP_TRY(g_sweep(c, 0, k, 0));
+    } else {
       // the nonlinear sub-step rides in the x sweep's loads
       const GNl nlz{Vp(c), phi, &c->sc()->scale, g_scalars(c), L.n0, L.n1, L.n2,
                     c->at<double>(L.o_pnl)};
@@ -754,26 +894,46 @@ struct Passes {
 
   static gp_status init_tables(gp_ctx* c) {
     const Layout& L = c->L;
+    const bool lng[3] = {L.lx, L.ly, false};
     if (L.generic) {
       const int ns3[3] = {L.n0, L.n1, L.n2};
-      for (int a = 0; a < (c->p.geom == GP_3D ? 3 : 2); ++a)
-        if (!gen_plan(ns3[a], &c->gplan[a])) return GP_E_SIZE;
+      for (int a = 0; a < (c->p.geom == GP_3D ? 3 : 2); ++a) {
+        if (lng[a]) {
+          if (!gen_plan(L.lg[a].A, &c->lplan[a][0]) || !gen_plan(L.lg[a].B, &c->lplan[a][1]))
+            return GP_E_SIZE;
+        } else if (!gen_plan(ns3[a], &c->gplan[a])) {
+          return GP_E_SIZE;
+        }
+      }
       GP_HIP(GLaunch<T>::prepare());
     }
     const int ns[3] = {L.n0, L.n1, L.n2};
     const double hs[3] = {L.h0, L.h1, L.h2};
     const int naxes = (c->p.geom == GP_3D) ? 3 : 2;
+    // twiddles of a stage length m and, for a Bluestein plan, its chirp and filter
+    auto plan_tables = [&](GPlan& pl, size_t o_tw, size_t o_blue) {
+      hipLaunchKernelGGL(k_twiddles<T>, dim3(blocks_for(pl.m)), dim3(kThreads), 0, c->st,
+                         c->at<cpx<T>>(o_tw), pl.m);
+      if (pl.blue) {
+        cpx<T>* ch = c->at<cpx<T>>(o_blue);
+        cpx<T>* fl = ch + pl.n;
+        hipLaunchKernelGGL(k_bluestein<T>, dim3(blocks_for(pl.m)), dim3(kThreads), 0, c->st, ch,
+                           fl, pl.n, pl.m);
+        pl.chirp = ch;
+        pl.filt = fl;
+      }
+    };
     for (int a = 0; a < naxes; ++a) {
-      const int ms = L.generic ? c->gplan[a].m : ns[a];  // stage length
-      hipLaunchKernelGGL(k_twiddles<T>, dim3(blocks_for(ms)), dim3(kThreads), 0, c->st,
-                         c->at<cpx<T>>(L.o_tw[a]), ms);
-      if (L.generic && c->gplan[a].blue) {
-        cpx<T>* ch = c->at<cpx<T>>(L.o_blue[a]);
-        cpx<T>* fl = ch + ns[a];
-        hipLaunchKernelGGL(k_bluestein<T>, dim3(blocks_for(ms)), dim3(kThreads), 0, c->st, ch,
-                           fl, ns[a], ms);
-        c->gplan[a].chirp = ch;
-        c->gplan[a].filt = fl;
+      if (lng[a]) {
+        plan_tables(c->lplan[a][0], L.o_ltw[a][0], L.o_lblue[a][0]);
+        plan_tables(c->lplan[a][1], L.o_ltw[a][1], L.o_lblue[a][1]);
+        hipLaunchKernelGGL(k_twiddles<T>, dim3(blocks_for(ns[a])), dim3(kThreads), 0, c->st,
+                           c->at<cpx<T>>(L.o_ltw[a][2]), ns[a]);   // W_N^m
+      } else if (L.generic) {
+        plan_tables(c->gplan[a], L.o_tw[a], L.o_blue[a]);
+      } else {
+        hipLaunchKernelGGL(k_twiddles<T>, dim3(blocks_for(ns[a])), dim3(kThreads), 0, c->st,
+                           c->at<cpx<T>>(L.o_tw[a]), ns[a]);
       }
       const double Ar = c->p.dt / (4.0 * hs[a] * hs[a]);
       // lanes per line of the solve that sweeps this axis: x lines in the x pass, columns
@@ -783,6 +943,12 @@ struct Passes {
       hipLaunchKernelGGL(k_cn_tables<T>, dim3(1), dim3(64), 0, c->st,
                          c->at<cpx<T>>(L.o_cn[a][0]), c->at<cpx<T>>(L.o_cn[a][1]),
                          c->at<cpx<T>>(L.o_cn[a][2]), ns[a], Ar, P);
+      if (lng[a]) {  // the segments' carry products of each factor set
+        for (int t = 0; t < 3; ++t)
+          hipLaunchKernelGGL(k_seg_tables<T>, dim3(blocks_for(L.lg[a].nseg)), dim3(kThreads), 0,
+                             c->st, c->at<cpx<T>>(L.o_cn[a][t]), L.lg[a].sn, L.lg[a].nseg,
+                             c->at<cpx<T>>(L.o_seg[a][t]));
+      }
     }
     KernelGeom kg{};
     kg.geom = c->p.geom;
@@ -1508,7 +1674,7 @@ const char* gp_status_string(gp_status s) {
   switch (s) {
     case GP_OK: return "ok";
     case GP_E_ARG: return "invalid argument";
-    case GP_E_SIZE: return "unsupported grid size (an axis odd, < 4, with a prime factor above 31, or a line longer than 8192 FP32 / 4096 FP64 points)";
+    case GP_E_SIZE: return "unsupported grid size (an axis < 4, an FFT line longer than 8192 FP32 / 4096 FP64 points in 3D, or a longer 2D axis with no four-step split)";
     case GP_E_DEVICE: return "HIP runtime error";
     case GP_E_NONFINITE: return "wave function became non-finite";
     case GP_E_STATE: return "call out of order (set psi first)";
@@ -1893,7 +2059,8 @@ gp_status gp_batch_get_psi(gp_batch* b, int idx, void* psi, int on_device) {
 int gp_axis_kind(int n, int prec) {
   if (prec != GP_FP64 && prec != GP_FP32_MIXED) return 0;
   if (fast_size(n)) return 1;
-  return size_ok(n, prec == GP_FP64) ? 2 : 0;
+  if (size_ok(n, prec == GP_FP64)) return 2;
+  return long_size(n, prec == GP_FP64) ? 3 : 0;
 }
 
 gp_status gp_get_params(gp_ctx* c, gp_params* out) {

@@ -344,9 +344,30 @@ struct GLines {
 //   3D (q3): lines along z, l = kx n1 + k1, e = k2; quadrant table (U is even in k1, k2)
 //            ktab[(kx (n2/2+1) + min(k2, n2-k2)) (n1/2+1) + min(k1, n1-k1)]
 //   2D:      lines along axis 1, l = kx, e = k1; ktab[kx n1 + k1]
+// 2D grids with an axis split for the four-step FFT (m4 != 0; hi, lo: l / G and l mod G of
+// the line addressing): ktab[kx n1 + ky] with
+//   bit 1 of m4: kx from the slot p = lo of a long-x spectrum row, kx = Bx (p mod Ax) + p / Ax,
+//                folded to min(kx, nx - kx) (U is even in kx); else kx = hi / By (bit 0) or l
+//   bit 0 of m4: the line is the inner (A-point) FFT of a split y axis, ky = By e + kb with
+//                kb = hi (bit 1) or hi mod By; else ky = e
 struct GKtab {
   int q3, n1, n2;
   FDiv fn1;
+  int m4, Ax, Bx, nx, By;
+  FDiv fAx, fBy;
+  __device__ __forceinline__ long long index4(int l, int hi, int lo, int e) const {
+    int kx = l, ky = e;
+    if (m4 & 2) {
+      const int r = (int)fdiv((uint32_t)lo, fAx);
+      kx = Bx * (lo - r * Ax) + r;
+      if (kx > nx - kx) kx = nx - kx;
+      if (m4 & 1) ky = By * e + hi;
+    } else if (m4 & 1) {
+      kx = (int)fdiv((uint32_t)hi, fBy);
+      ky = By * e + (hi - kx * By);
+    }
+    return (long long)kx * n1 + ky;
+  }
   __device__ __forceinline__ long long index(int l, int e) const {
     if (q3) {
       const int kx = (int)fdiv((uint32_t)l, fn1), k1 = l - kx * n1;
@@ -367,11 +388,15 @@ enum : int { GL_FWD = 0, GL_INV = 1, GL_CONV = 2 };
 template <typename T, bool BLUE>
 constexpr int gen_waves_per_eu() { return sizeof(T) == 4 && !BLUE ? 8 : 1; }
 
+// The four-step FFT's outer passes (w4 != null): GL_FWD multiplies element k of line l by
+// w4[c k] after its transform, GL_INV by conj(w4[c k]) before it, with the line's column
+// c = l / G (w4hi) or l mod G; w4[m] = W_N^m of the split axis.
 template <typename T, int KIND, int EMAX, bool SMALL, bool BLUE = false>
 __global__ void __launch_bounds__(kGenThreads, (gen_waves_per_eu<T, BLUE>())) kg_lines(cpx<T>* __restrict__ data, GLines g,
                                                      GPlan p, const cpx<T>* __restrict__ tw,
                                                      const T* __restrict__ ktab, GKtab km,
-                                                     const double* __restrict__ scale) {
+                                                     const double* __restrict__ scale,
+                                                     const cpx<T>* __restrict__ w4, int w4hi) {
   extern __shared__ __align__(16) char lds_raw[];
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lds_raw);
   // tiles numbered XCD-contiguously (blocks run on the XCDs round-robin): neighbouring
@@ -416,6 +441,21 @@ __global__ void __launch_bounds__(kGenThreads, (gen_waves_per_eu<T, BLUE>())) kg
   }
   const cpx<T>* twu = tw_store<T, SMALL, UT>(twl, twv, tw, LS);
   __syncthreads();
+  // the four-step twiddle of line l, element e
+  auto w4_of = [&](int line, int e) {
+    const int l = l0 + line;
+    const int hi = (int)fdiv((uint32_t)l, g.fg);
+    return w4[(w4hi ? hi : l - hi * g.G) * e];
+  };
+  if constexpr (KIND == GL_INV) {
+    if (w4 != nullptr) {
+      for (int t = threadIdx.x; t < nl * N; t += nt) {
+        const int line = (int)fdiv((uint32_t)t, g.fn), e = t - line * N;
+        buf[line * LS + e] = buf[line * LS + e] * conjg(w4_of(line, e));
+      }
+      __syncthreads();
+    }
+  }
   if constexpr (KIND == GL_CONV) {
     gfft<T, false, EMAX, SMALL, BLUE>(buf, nl, p, twu);
     const double s = *scale;
@@ -430,7 +470,17 @@ __global__ void __launch_bounds__(kGenThreads, (gen_waves_per_eu<T, BLUE>())) kg
         const int t = t0 + u * nt;
         const int2 le = g.tile_index(t);
         at[u] = (t < tot && le.x < nl) ? le.x * LS + le.y : -1;
-        kv[u] = ktab[at[u] >= 0 ? km.index(l0 + le.x, le.y) : 0];
+        long long ki = 0;
+        if (at[u] >= 0) {
+          const int l = l0 + le.x;
+          if (km.m4) {
+            const int hi = (int)fdiv((uint32_t)l, g.fg);
+            ki = km.index4(l, hi, l - hi * g.G, le.y);
+          } else {
+            ki = km.index(l, le.y);
+          }
+        }
+        kv[u] = ktab[ki];
       }
 #pragma unroll
       for (int u = 0; u < kGenU; ++u)
@@ -440,6 +490,15 @@ __global__ void __launch_bounds__(kGenThreads, (gen_waves_per_eu<T, BLUE>())) kg
     gfft<T, true, EMAX, SMALL, BLUE>(buf, nl, p, twu);
   } else {
     gfft<T, KIND == GL_INV, EMAX, SMALL, BLUE>(buf, nl, p, twu);
+    if constexpr (KIND == GL_FWD) {
+      if (w4 != nullptr) {
+        for (int t = threadIdx.x; t < nl * N; t += nt) {
+          const int line = (int)fdiv((uint32_t)t, g.fn), e = t - line * N;
+          buf[line * LS + e] = buf[line * LS + e] * w4_of(line, e);
+        }
+        __syncthreads();
+      }
+    }
   }
   if (packed) {
     for (int t = threadIdx.x; t < nl * N; t += nt) run[t] = buf[pslot(t)];
@@ -761,6 +820,27 @@ constexpr int kTileMaxWaves = 16;
 template <typename T>
 constexpr int tile_max_waves() { return sizeof(T) == 4 ? 16 : 8; }
 
+// Lines longer than one tile are swept in segments of n rows (SEG): line l of the tile is
+// segment s = l mod nseg of the long line l / nseg, its factor rows f[s n ..].  The
+// recurrences are linear, so a segment's results follow from its own solve with zero
+// carries and two numbers from its neighbours: with C the true d entering the segment
+// (at its row -1) and E the true e entering from the right (at its row n),
+//   d_i = d0_i + R_i C,                        R_i = g_a ... g_i (a: the first row)
+//   e_a = e0_a + Q C + P E,                    P = R_(last row),
+//   Q = sum_m (g_a ... g_(m-1)) R_m            (P and Q are fixed by the factor table)
+// where d0, e0 are the zero-carry results.  MODE 3 (summary): the zero-carry solve, writing
+// per segment line sum[4l ..] = d0 at the last row, e0 at the first row, psi at the first
+// and the last row; the carries then run along each long line (k_seg_carry), and the
+// sweep proper (MODE 0 or 1) starts its scans from car[4l] = C, car[4l+1] = E, with
+// car[4l+2], car[4l+3] = psi of the rows before and after the segment (values before the
+// sweep: the neighbouring segments are rewritten by other blocks).
+struct GSeg {
+  int nseg;
+  FDiv fseg;
+  const void* car;
+  void* sum;
+};
+
 struct GNl {  // the nonlinear sub-step's inputs for the fused x sweep
   const void* V;
   const void* phi;
@@ -770,12 +850,14 @@ struct GNl {  // the nonlinear sub-step's inputs for the fused x sweep
   double* part;
 };
 
-template <typename T, int MODE, int NLM, int TS>
+template <typename T, int MODE, int NLM, int TS, bool SEG = false>
 __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* __restrict__ data,
                                                                 GLines g, int wpl, FDiv fs,
                                                                 const cpx<T>* __restrict__ f,
                                                                 double* __restrict__ part,
-                                                                GNl nlz) {
+                                                                GNl nlz, GSeg sg) {
+  static_assert(!SEG || NLM < 0, "segments carry no nonlinear sub-step");
+  static_assert(MODE != 3 || SEG, "the summary mode belongs to segmented sweeps");
   extern __shared__ __align__(16) char lds_raw[];
   __shared__ double red[7 * kTileMaxWaves];
   __shared__ cpx<T> wP[kTileMaxWaves], wB[kTileMaxWaves];  // the waves' composed maps
@@ -788,7 +870,7 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
   const int nt = blockDim.x;
   const int tot = g.nl * N;  // the full tile's indexing; lines past nl are skipped
   cpx<T>* ps = reinterpret_cast<cpx<T>*>(lds_raw);   // nl lines of psi (then u)
-  cpx<T>* fl = ps + (size_t)g.nl * LS;                // the factor table, one line
+  cpx<T>* fl = ps + (size_t)g.nl * LS;                // the factor table: one line (SEG: nl)
   // values per thread per load round (FP64: half, a quarter with the nonlinear sub-step,
   // for the registers)
   constexpr int U = sizeof(T) == 4 ? kGenU : (NLM >= 0 ? kGenU / 4 : kGenU / 2);
@@ -798,7 +880,7 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
   if constexpr (NLM >= 0) ts = (T)(*nlz.scale);
   // the factor table's first UF nt values are loaded with the tile and stored after it
   cpx<T> fpre[UF];
-  if constexpr (MODE != 2) {
+  if constexpr (MODE != 2 && !SEG) {
 #pragma unroll
     for (int u = 0; u < UF; ++u) {
       const int t = threadIdx.x + u * nt;
@@ -877,7 +959,16 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
       ps[at[u]] = v;
     }
   }
-  if constexpr (MODE != 2) {
+  if constexpr (SEG) {
+    // each line's own rows of the factor table
+    for (int t = threadIdx.x; t < nl * N; t += nt) {
+      const int ln = (int)fdiv((uint32_t)t, g.fn), e = t - ln * N;
+      const int l = l0 + ln;
+      const int sgi = l - (int)fdiv((uint32_t)l, sg.fseg) * sg.nseg;
+      const int c = (int)fdiv((uint32_t)e, fs);
+      fl[ln * LS + c * Sp + (e - c * S)] = f[(long long)sgi * N + e];
+    }
+  } else if constexpr (MODE != 2) {
 #pragma unroll
     for (int u = 0; u < UF; ++u) {
       const int t = threadIdx.x + u * nt;
@@ -904,18 +995,38 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
   double s0 = 0.0, s1 = 0.0;
   cpx<T>* p = ps + (act ? line : 0) * LS + slot;
   cpx<T> d[TS];
+  // segments: the line's index, its segment, the rows beside it and the carries entering
+  [[maybe_unused]] const int lg = l0 + (act ? line : 0);
+  [[maybe_unused]] int sgi = 0;
+  [[maybe_unused]] cpx<T> eL = zero, eR = zero, cC = zero, cE = zero;
+  if constexpr (SEG) {
+    sgi = lg - (int)fdiv((uint32_t)lg, sg.fseg) * sg.nseg;
+    if constexpr (MODE == 3) {
+      // before the sweep every value is the stored one: read the neighbours in place
+      const cpx<T> vl = data[sgi > 0 ? (long long)lg * N - 1 : 0];
+      const cpx<T> vr = data[sgi + 1 < sg.nseg ? (long long)(lg + 1) * N : 0];
+      if (act && sgi > 0) eL = vl;
+      if (act && sgi + 1 < sg.nseg) eR = vr;
+    } else {
+      const cpx<T>* car = reinterpret_cast<const cpx<T>*>(sg.car) + 4LL * lg;
+      cC = car[0];
+      cE = car[1];
+      eL = car[2];
+      eR = car[3];
+    }
+  }
   if constexpr (MODE != 2) {
-    const cpx<T>* fq = fl + slot;
+    const cpx<T>* fq = fl + (SEG ? (act ? line : 0) * LS : 0) + slot;
     // forward, zero carry: local d and the chunk's product of g
     cpx<T> acc = zero, prod = {1, 0};
     cpx<T> pm = p[q > 0 && cnt > 0 ? -Sp + S - 1 : 0];   // row i0 - 1
-    if (!(i0 > 0 && cnt > 0)) pm = zero;
+    if (!(i0 > 0 && cnt > 0)) pm = SEG ? eL : zero;      // a segment's row -1: its neighbour
     cpx<T> pc = p[0];
 #pragma unroll
     for (int j = 0; j < TS; ++j) {
       if (j < cnt) {
-        cpx<T> pn = p[j + 1 < cnt ? j + 1 : Sp];  // row N is none: zero
-        if (i0 + j + 1 >= N) pn = zero;
+        cpx<T> pn = p[j + 1 < cnt ? j + 1 : Sp];  // row N is none: zero (a segment's: eR)
+        if (i0 + j + 1 >= N) pn = SEG ? eR : zero;
         const cpx<T> fi = fq[j];
         acc = fi * ((pm + pn) - (pc + pc)) + scl(fi, (T)0.5) * acc;
         prod = scl(fi, (T)0.5) * prod;
@@ -933,8 +1044,9 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
         P = P * Pp;
       }
     }
-    // d entering the wave: the earlier waves' totals composed in order
-    cpx<T> C = zero;
+    // d entering the wave: the earlier waves' totals composed in order (on the segment's
+    // carry; zero in the summary)
+    cpx<T> C = (SEG && MODE != 3) ? cC : zero;
     if (wpl > 1) {
       if (lane == 63) {
         wP[wave] = P;
@@ -951,6 +1063,13 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
       if (j < cnt) {
         carry = scl(fq[j], (T)0.5) * carry;
         d[j] = d[j] + carry;
+        if constexpr (MODE == 3) {
+          if (i0 + j == N - 1) {  // the segment's last row: d0 and psi
+            cpx<T>* sm = reinterpret_cast<cpx<T>*>(sg.sum) + 4LL * lg;
+            sm[0] = d[j];
+            sm[3] = p[j];
+          }
+        }
       }
     }
     // backward, zero carry from the right: local e (kept in d)
@@ -972,7 +1091,7 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
       }
     }
     // e entering the wave from the right: the later waves' totals composed in order
-    cpx<T> E = zero;
+    cpx<T> E = (SEG && MODE != 3) ? cE : zero;
     if (wpl > 1) {
       if (lane == 0) {
         wP[wave] = P;
@@ -983,12 +1102,25 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
     }
     const cpx<T> Pd = shfl_down_c(P, 1), Bd = shfl_down_c(B, 1);
     carry = lane == 63 ? E : Pd * E + Bd;         // e at the start of the next chunk
+    if constexpr (MODE == 3) {
+      if (q == 0 && cnt > 0) {  // the segment's first row: e0 and psi
+        cpx<T>* sm = reinterpret_cast<cpx<T>*>(sg.sum) + 4LL * lg;
+        // d holds the chunk's local e; the carry reaches row 0 through the chunk's g
+        cpx<T> cr = carry;
 #pragma unroll
-    for (int j = TS - 1; j >= 0; --j) {
-      if (j < cnt) {
-        carry = scl(fq[j], (T)0.5) * carry;
-        d[j] = p[j] + (d[j] + carry);   // u
-        p[j] = d[j];
+        for (int j = TS - 1; j >= 0; --j)
+          if (j < cnt) cr = scl(fq[j], (T)0.5) * cr;
+        sm[1] = d[0] + cr;
+        sm[2] = p[0];
+      }
+    } else {
+#pragma unroll
+      for (int j = TS - 1; j >= 0; --j) {
+        if (j < cnt) {
+          carry = scl(fq[j], (T)0.5) * carry;
+          d[j] = p[j] + (d[j] + carry);   // u
+          p[j] = d[j];
+        }
       }
     }
   } else {
@@ -996,9 +1128,10 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
     for (int j = 0; j < TS; ++j)
       if (j < cnt) d[j] = p[j];
   }
-  if constexpr (MODE != 0) {
+  if constexpr (MODE == 1 || MODE == 2) {
     // sums of u (or of the stored state): |u|^2 and the differences, the last one with
-    // the next chunk's first row (the next lane's, or the next wave's lane 0 through LDS)
+    // the next chunk's first row (the next lane's, or the next wave's lane 0 through LDS;
+    // after a segment's last row: the next segment's first, psi + e there)
     __syncthreads();
     cpx<T> unext = shfl_down_c(d[0], 1);
     if (lane == 63 && cnt > 0 && i0 + cnt < N) unext = p[Sp];
@@ -1012,6 +1145,9 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
       }
     }
     if (cnt > 0 && i0 + cnt < N) s1 += absdiff2_d(unext, prev);
+    if constexpr (SEG) {
+      if (cnt > 0 && i0 + cnt == N && sgi + 1 < sg.nseg) s1 += absdiff2_d(eR + cE, prev);
+    }
     double sv[2] = {s0, s1};
     gblock_sum<2>(sv, red);
     if (threadIdx.x == 0) {
@@ -1027,7 +1163,7 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
       for (int k = 0; k < 7; ++k) nlz.part[7 * (long long)blockIdx.x + k] = q7[k];
     }
   }
-  if constexpr (MODE != 2) {
+  if constexpr (MODE == 0 || MODE == 1) {
     __syncthreads();
     for (int t = threadIdx.x, r = 0; t < tot; t += nt, ++r) {
       int ln, e;

@@ -1,4 +1,5 @@
 // Instantiations of the run-time-length pass kernels for one precision (GP_REAL).
+#include <algorithm>
 #include <mutex>
 
 #include "gp_generic.hpp"
@@ -64,7 +65,15 @@ hipError_t GLaunch<T>::prepare() {
       reinterpret_cast<const void*>(&kg_lines<T, GL_INV, kEmax, true, true>),
       reinterpret_cast<const void*>(&kg_lines<T, GL_CONV, kEmax, true, true>),
       reinterpret_cast<const void*>(&kg_r2c_x<T, kEmax, true, true>),
-      reinterpret_cast<const void*>(&kg_c2r_x<T, kEmax, true, true>)};
+      reinterpret_cast<const void*>(&kg_c2r_x<T, kEmax, true, true>),
+#define GLX_KERNELS(S, B)                                                        \
+  reinterpret_cast<const void*>(&kg_lx_cols_fwd<T, kEmax, S, B>),               \
+      reinterpret_cast<const void*>(&kg_lx_rows_fwd<T, kEmax, S, B>),           \
+      reinterpret_cast<const void*>(&kg_lx_rows_inv<T, kEmax, S, B>),           \
+      reinterpret_cast<const void*>(&kg_lx_cols_inv<T, kEmax, S, B>)
+      GLX_KERNELS(true, false), GLX_KERNELS(false, false), GLX_KERNELS(true, true)
+#undef GLX_KERNELS
+  };
   for (const void* k : ks) {
     const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
@@ -80,7 +89,13 @@ hipError_t GLaunch<T>::prepare() {
                       reinterpret_cast<const void*>(&kg_cn_tile<T, 1, -1, kTileS>),
                       reinterpret_cast<const void*>(&kg_cn_tile<T, 2, -1, kTileS>),
                       reinterpret_cast<const void*>(&kg_cn_tile<T, 0, MODE_IMAG, kTileS>),
-                      reinterpret_cast<const void*>(&kg_cn_tile<T, 0, MODE_REAL, kTileS>)};
+                      reinterpret_cast<const void*>(&kg_cn_tile<T, 0, MODE_REAL, kTileS>),
+                      reinterpret_cast<const void*>(&kg_cn_tile<T, 0, -1, 8, true>),
+                      reinterpret_cast<const void*>(&kg_cn_tile<T, 1, -1, 8, true>),
+                      reinterpret_cast<const void*>(&kg_cn_tile<T, 3, -1, 8, true>),
+                      reinterpret_cast<const void*>(&kg_cn_tile<T, 0, -1, kTileS, true>),
+                      reinterpret_cast<const void*>(&kg_cn_tile<T, 1, -1, kTileS, true>),
+                      reinterpret_cast<const void*>(&kg_cn_tile<T, 3, -1, kTileS, true>)};
   for (const void* k : kt) {
     const hipError_t e =
         hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kTileLds);
@@ -140,23 +155,24 @@ int GLaunch<T>::cn_tile_lines(int n, int nlines, bool strided) {
 namespace {
 constexpr int kTransTile = 32;  // transpose tiles of 32 x 32 values, 256 threads
 
-template <int MODE, int NLM>
+// SEG: segments of long lines (each line its own factor rows in LDS)
+template <int MODE, int NLM, bool SEG = false>
 hipError_t launch_tile(hipStream_t st, cpx<T>* data, const GLines& g, int wpl,
-                       const cpx<T>* f, double* part, const GNl& nlz) {
+                       const cpx<T>* f, double* part, const GNl& nlz, const GSeg& sg = GSeg{}) {
   const int blocks = (g.nlines + g.nl - 1) / g.nl;
   const int S = (g.n + 64 * wpl - 1) / (64 * wpl);
-  const size_t lds = lds_of((g.nl + 1) * cn_line_slots(g.n, 64 * wpl));
+  const size_t lds = lds_of((SEG ? 2 * g.nl : g.nl + 1) * cn_line_slots(g.n, 64 * wpl));
   if (lds > (size_t)kTileLds || g.nl * wpl > tile_max_waves<T>() || S > kTileS)
     return hipErrorInvalidValue;
   const FDiv fs = fdiv_make((uint32_t)S);
   const dim3 threads(64 * wpl * g.nl);
   // at most 8 rows per lane: fewer registers
   if (S <= 8)
-    hipLaunchKernelGGL((kg_cn_tile<T, MODE, NLM, 8>), dim3(blocks), threads, lds, st, data, g,
-                       wpl, fs, f, part, nlz);
+    hipLaunchKernelGGL((kg_cn_tile<T, MODE, NLM, 8, SEG>), dim3(blocks), threads, lds, st, data,
+                       g, wpl, fs, f, part, nlz, sg);
   else
-    hipLaunchKernelGGL((kg_cn_tile<T, MODE, NLM, kTileS>), dim3(blocks), threads, lds, st,
-                       data, g, wpl, fs, f, part, nlz);
+    hipLaunchKernelGGL((kg_cn_tile<T, MODE, NLM, kTileS, SEG>), dim3(blocks), threads, lds, st,
+                       data, g, wpl, fs, f, part, nlz, sg);
   return hipGetLastError();
 }
 
@@ -239,7 +255,8 @@ hipError_t GLaunch<T>::c2r_x(hipStream_t st, const cpx<T>* spec, T* phi, const G
 template <>
 hipError_t GLaunch<T>::lines(int kind, hipStream_t st, cpx<T>* data, int n, int nlines, int G,
                              long long so, long long si, long long se, const GPlan& p,
-                             const cpx<T>* tw, const T* ktab, GKtab km, const double* scale) {
+                             const cpx<T>* tw, const T* ktab, GKtab km, const double* scale,
+                             const cpx<T>* w4, int w4hi) {
   if (p.m > gen_max_line<T>() || nlines < 1) return hipErrorInvalidValue;
   GLines g{};
   g.n = n;
@@ -260,7 +277,8 @@ hipError_t GLaunch<T>::lines(int kind, hipStream_t st, cpx<T>* data, int n, int 
 #define GLINESB(K)                                                                           \
   case K:                                                                                    \
     hipLaunchKernelGGL((kg_lines<T, K, kEmax, true, true>), dim3(blocks),                    \
-                       threads_for(g.nl * p.m), lds, st, data, g, p, tw, ktab, km, scale);   \
+                       threads_for(g.nl * p.m), lds, st, data, g, p, tw, ktab, km, scale,    \
+                       w4, w4hi);                                                            \
     break;
       GLINESB(GL_FWD) GLINESB(GL_INV) GLINESB(GL_CONV)
 #undef GLINESB
@@ -273,7 +291,7 @@ hipError_t GLaunch<T>::lines(int kind, hipStream_t st, cpx<T>* data, int n, int 
 #define GLINES(K, S)                                                                      \
   case K * 2 + (S ? 1 : 0):                                                               \
     hipLaunchKernelGGL((kg_lines<T, K, kEmax, S>), dim3(blocks), threads_for(g.nl * p.m), lds, st, \
-                       data, g, p, tw, ktab, km, scale);                                  \
+                       data, g, p, tw, ktab, km, scale, w4, w4hi);                        \
     break;
     GLINES(GL_FWD, true) GLINES(GL_FWD, false) GLINES(GL_INV, true) GLINES(GL_INV, false)
     GLINES(GL_CONV, true) GLINES(GL_CONV, false)
@@ -344,6 +362,124 @@ hipError_t GLaunch<T>::cn_lines(int mode, hipStream_t st, cpx<T>* data, int n, i
     case 2: return launch_tile<2, -1>(st, data, g, wpl, f, part, none);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <>
+GLX GLaunch<T>::lx_geom(int n0, int n1, const GLong& lp, const GPlan& pa, const GPlan& pb) {
+  GLX x{};
+  x.N = n0;
+  x.A = lp.A;
+  x.B = lp.B;
+  x.Bh = lp.B / 2 + 1;
+  x.rs = x.Bh * lp.A;
+  x.n1 = n1;
+  x.np = (n1 + 1) / 2;
+  const int lim = gen_max_line<T>();
+  // column tiles of about 4096 values (ta consecutive columns: runs of ta values)
+  int ta = 4096 / pb.m;
+  if (ta > lim / pb.m) ta = lim / pb.m;
+  if (ta > lp.A) ta = lp.A;
+  if (ta < 1) ta = 1;
+  x.ta = ta;
+  x.nat = (lp.A + ta - 1) / ta;
+  // row items of about 4096 values
+  int ipf = 4096 / (2 * pa.m);
+  if (ipf > lim / (2 * pa.m)) ipf = lim / (2 * pa.m);
+  x.ipf = ipf < 1 ? 1 : ipf;
+  int ipi = 4096 / pa.m;
+  if (ipi > lim / pa.m) ipi = lim / pa.m;
+  x.ipi = ipi < 1 ? 1 : ipi;
+  x.fA = fdiv_make((uint32_t)lp.A);
+  x.fB = fdiv_make((uint32_t)lp.B);
+  x.fBh = fdiv_make((uint32_t)x.Bh);
+  x.fta = fdiv_make((uint32_t)ta);
+  x.fnat = fdiv_make((uint32_t)x.nat);
+  return x;
+}
+
+namespace {
+// one launch of a long-x kernel in the variant its plan needs (Bluestein, radices up to 8,
+// or all radices)
+#define GLX_LAUNCH(KERNEL, plan, grid, values, lds, ...)                                     \
+  do {                                                                                        \
+    if ((plan).blue)                                                                          \
+      hipLaunchKernelGGL((KERNEL<T, kEmax, true, true>), dim3(grid), threads_for(values), lds, \
+                         st, __VA_ARGS__);                                                    \
+    else if (gen_plan_small(plan))                                                            \
+      hipLaunchKernelGGL((KERNEL<T, kEmax, true, false>), dim3(grid), threads_for(values),    \
+                         lds, st, __VA_ARGS__);                                               \
+    else                                                                                      \
+      hipLaunchKernelGGL((KERNEL<T, kEmax, false, false>), dim3(grid), threads_for(values),   \
+                         lds, st, __VA_ARGS__);                                               \
+  } while (0)
+}  // namespace
+
+template <>
+hipError_t GLaunch<T>::lx_r2c(hipStream_t st, const cpx<T>* psi, cpx<T>* w, cpx<T>* spec,
+                              const GLX& x, const GPlan& pa, const GPlan& pb,
+                              const cpx<T>* twa, const cpx<T>* twb, const cpx<T>* w4,
+                              double* part) {
+  const int lim = gen_max_line<T>();
+  if (x.ta * pb.m > lim || 2 * x.ipf * pa.m > lim || pa.n != x.A || pb.n != x.B)
+    return hipErrorInvalidValue;
+  // the reduction reuses the line buffer (at least 32 doubles)
+  const size_t lds1 = std::max<size_t>(256, lds_of(x.ta * pb.m + pb.m));
+  GLX_LAUNCH(kg_lx_cols_fwd, pb, x.np * x.nat, x.ta * pb.m, lds1, psi, w, x, pb, twb, w4,
+             part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int items = x.np * x.Bh;
+  GLX_LAUNCH(kg_lx_rows_fwd, pa, (items + x.ipf - 1) / x.ipf, 2 * x.ipf * pa.m,
+             lds_of(2 * x.ipf * pa.m + pa.m), w, spec, x, pa, twa);
+  return hipGetLastError();
+}
+
+template <>
+hipError_t GLaunch<T>::lx_c2r(hipStream_t st, const cpx<T>* spec, cpx<T>* w, T* phi,
+                              const GLX& x, const GPlan& pa, const GPlan& pb,
+                              const cpx<T>* twa, const cpx<T>* twb, const cpx<T>* w4) {
+  const int lim = gen_max_line<T>();
+  if (x.ta * pb.m > lim || x.ipi * pa.m > lim || pa.n != x.A || pb.n != x.B)
+    return hipErrorInvalidValue;
+  const int items = x.np * x.B;
+  GLX_LAUNCH(kg_lx_rows_inv, pa, (items + x.ipi - 1) / x.ipi, x.ipi * pa.m,
+             lds_of(x.ipi * pa.m + pa.m), spec, w, x, pa, twa, w4);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  GLX_LAUNCH(kg_lx_cols_inv, pb, x.np * x.nat, x.ta * pb.m, lds_of(x.ta * pb.m + pb.m), w,
+             phi, x, pb, twb);
+  return hipGetLastError();
+}
+#undef GLX_LAUNCH
+
+template <>
+int GLaunch<T>::seg_lines(int sn, int nlines) {
+  // the tile sweep's lines per block, with room for one factor line per line
+  int nl = cn_tile_lines(sn, nlines, false);
+  const int per_line = cn_line_slots(sn, 64 * cn_tile_wpl(sn)) * (int)sizeof(cpx<T>);
+  while (nl > 1 && 2 * nl * per_line > kTileLds) --nl;
+  return nl;
+}
+
+template <>
+hipError_t GLaunch<T>::seg_sweep(int mode, hipStream_t st, cpx<T>* data, int sn, int nseg,
+                                 int nlong, const cpx<T>* f, const cpx<T>* pq, cpx<T>* sum,
+                                 cpx<T>* car, double* part) {
+  if (sn > gen_max_line<T>() || nseg < 2 || nlong < 1 || (mode != 0 && mode != 1))
+    return hipErrorInvalidValue;
+  const int nlines = nlong * nseg;
+  const GLines g = tile_lines(sn, nlines, seg_lines(sn, nlines), 1, sn, 0, 1);
+  const int wpl = cn_tile_wpl(sn);
+  const GNl none{};
+  const GSeg sg{nseg, fdiv_make((uint32_t)nseg), car, sum};
+  hipError_t e = launch_tile<3, -1, true>(st, data, g, wpl, f, nullptr, none, sg);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_seg_carry<T>, dim3((nlong + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                     st, sum, car, pq, nseg, nlong);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (mode == 0) return launch_tile<0, -1, true>(st, data, g, wpl, f, nullptr, none, sg);
+  return launch_tile<1, -1, true>(st, data, g, wpl, f, part, none, sg);
 }
 
 }  // namespace gpdbec

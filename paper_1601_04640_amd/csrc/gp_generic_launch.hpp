@@ -5,6 +5,7 @@
 #include <stddef.h>
 
 #include "gp_generic.hpp"
+#include "gp_long.hpp"
 
 namespace gpdbec {
 
@@ -21,6 +22,43 @@ template <typename T>
 inline bool gen_size_ok(int n) {
   GPlan p;
   return n >= 4 && n <= gen_max_line<T>() && gen_plan(n, &p) && p.m <= gen_max_line<T>();
+}
+
+// An axis of a 2D grid longer than one LDS line: the four-step FFT split n = A B (A >= B,
+// the smallest such A; both transforms within one LDS line, two rows of A for the
+// untangling of real lines) and the Crank-Nicolson segments (nseg segments of sn rows: the
+// largest divisor of n that one tile sweep holds, at least 64 rows).
+struct GLong {
+  int A, B;
+  int sn, nseg;
+};
+
+template <typename T>
+inline bool gen_long_plan(int n, GLong* lp) {
+  const int lim = gen_max_line<T>();
+  if (n <= lim) return false;
+  lp->A = lp->B = lp->sn = lp->nseg = 0;
+  int a = 1;
+  while ((long long)a * a < n) ++a;
+  for (; a <= lim; ++a) {
+    if (n % a) continue;
+    GPlan pa, pb;
+    const int b = n / a;
+    if (b >= 2 && gen_plan(a, &pa) && gen_plan(b, &pb) && 2 * pa.m <= lim && pb.m <= lim) {
+      lp->A = a;
+      lp->B = b;
+      break;
+    }
+  }
+  if (lp->A == 0) return false;
+  for (int s = lim; s >= 64; --s) {
+    if (n % s == 0 && n / s >= 2) {
+      lp->sn = s;
+      lp->nseg = n / s;
+      return true;
+    }
+  }
+  return false;
 }
 
 // LDS line stride of an axis's FFT: N, or Bluestein's M.
@@ -40,7 +78,13 @@ struct GLaunch {
   static int x_blocks(int n0, int n1, int n2);
   // blocks of the nonlinear pass (partial-sum slots) and of a CN sweep over nlines lines
   // (the x sweep's, which carries the nonlinear sub-step and its sums)
-  static int nl_blocks(int n0, int n1, int n2) { return cn_blocks(n0, n1 * n2, false); }
+  static int nl_blocks(int n0, int n1, int n2) {
+    if (n0 > gen_max_line<T>()) {  // a long x axis: the nonlinear pass runs on its own
+      const long long b = (long long)n0 * n1 * n2 / 4096;
+      return (int)(b < 256 ? 256 : (b > 16384 ? 16384 : b));
+    }
+    return cn_blocks(n0, n1 * n2, false);
+  }
   // CN sweeps: kg_cn_tile with wpl waves per line (1 up to kTileMaxN points, then one
   // lane per 8 rows) and cn_tile_lines lines per block, except strided sweeps of many
   // lines longer than kTileMaxN, which run one thread per line (kg_cn_cols)
@@ -67,10 +111,36 @@ struct GLaunch {
                           const cpx<T>* tw, double* part, int n0, int n1, int n2);
   static hipError_t c2r_x(hipStream_t st, const cpx<T>* spec, T* phi, const GPlan& p,
                           const cpx<T>* tw, int n0, int n1, int n2);
-  // kind: GL_FWD, GL_INV, GL_CONV (ktab, km, scale used by GL_CONV only)
+  // kind: GL_FWD, GL_INV, GL_CONV (ktab, km, scale used by GL_CONV only); w4: the
+  // four-step twiddle of the outer passes of a split axis (GL_FWD after, GL_INV before the
+  // transform; the line's column l / G if w4hi, else l mod G)
   static hipError_t lines(int kind, hipStream_t st, cpx<T>* data, int n, int nlines, int G,
                           long long so, long long si, long long se, const GPlan& p,
-                          const cpx<T>* tw, const T* ktab, GKtab km, const double* scale);
+                          const cpx<T>* tw, const T* ktab, GKtab km, const double* scale,
+                          const cpx<T>* w4 = nullptr, int w4hi = 0);
+  // long x axis (2D): geometry, blocks of the forward column pass (its x-partial slots),
+  // and the two passes each way: psi -> w (grid of ceil(n1/2) n0 values) -> spec, and
+  // spec -> w -> phi; pa, pb: plans of the A- and B-point transforms, twa, twb their
+  // stage twiddles, w4 = W_N^m
+  static GLX lx_geom(int n0, int n1, const GLong& lp, const GPlan& pa, const GPlan& pb);
+  static int lx_blocks(const GLX& x) { return x.np * x.nat; }
+  static hipError_t lx_r2c(hipStream_t st, const cpx<T>* psi, cpx<T>* w, cpx<T>* spec,
+                           const GLX& x, const GPlan& pa, const GPlan& pb, const cpx<T>* twa,
+                           const cpx<T>* twb, const cpx<T>* w4, double* part);
+  static hipError_t lx_c2r(hipStream_t st, const cpx<T>* spec, cpx<T>* w, T* phi,
+                           const GLX& x, const GPlan& pa, const GPlan& pb, const cpx<T>* twa,
+                           const cpx<T>* twb, const cpx<T>* w4);
+  // segmented CN sweep of nlong contiguous lines of nseg segments of sn rows (mode 0:
+  // solve, 1: solve with the new-state sums in part over seg_blocks blocks); f: the long
+  // line's factor table, pq: the segments' carry products; sum, car: 4 values per segment
+  static int seg_lines(int sn, int nlines);
+  static int seg_blocks(int sn, int nlines) {
+    const int nl = seg_lines(sn, nlines);
+    return (nlines + nl - 1) / nl;
+  }
+  static hipError_t seg_sweep(int mode, hipStream_t st, cpx<T>* data, int sn, int nseg,
+                              int nlong, const cpx<T>* f, const cpx<T>* pq, cpx<T>* sum,
+                              cpx<T>* car, double* part);
   // the nonlinear sub-step's sums of the stored state (mode MODE_OBSERVE; MODE_IMAG and
   // MODE_REAL also apply it in place), over nl_blocks blocks
   static hipError_t nonlinear(int mode, hipStream_t st, cpx<T>* psi, const T* V, const T* phi,
@@ -102,7 +172,20 @@ struct GLaunch {
                                            const cpx<T>*, int, int, int);                      \
   template <> hipError_t GLaunch<T>::lines(int, hipStream_t, cpx<T>*, int, int, int,          \
                                            long long, long long, long long, const GPlan&,     \
-                                           const cpx<T>*, const T*, GKtab, const double*);    \
+                                           const cpx<T>*, const T*, GKtab, const double*,     \
+                                           const cpx<T>*, int);                               \
+  template <> GLX GLaunch<T>::lx_geom(int, int, const GLong&, const GPlan&, const GPlan&);    \
+  template <> hipError_t GLaunch<T>::lx_r2c(hipStream_t, const cpx<T>*, cpx<T>*, cpx<T>*,    \
+                                            const GLX&, const GPlan&, const GPlan&,          \
+                                            const cpx<T>*, const cpx<T>*, const cpx<T>*,     \
+                                            double*);                                          \
+  template <> hipError_t GLaunch<T>::lx_c2r(hipStream_t, const cpx<T>*, cpx<T>*, T*,         \
+                                            const GLX&, const GPlan&, const GPlan&,          \
+                                            const cpx<T>*, const cpx<T>*, const cpx<T>*);    \
+  template <> int GLaunch<T>::seg_lines(int, int);                                             \
+  template <> hipError_t GLaunch<T>::seg_sweep(int, hipStream_t, cpx<T>*, int, int, int,      \
+                                               const cpx<T>*, const cpx<T>*, cpx<T>*,         \
+                                               cpx<T>*, double*);                              \
   template <> hipError_t GLaunch<T>::nonlinear(int, hipStream_t, cpx<T>*, const T*, const T*, \
                                                const double*, const GStep&, int, int, int,    \
                                                double*);                                       \

@@ -63,11 +63,35 @@ def test_line_length_limit_depends_on_precision():
     assert ws(geom="2dxy", nx=8192, ny=8, prec="fp32") > 0
     assert ws(geom="2dxy", nx=2062, ny=8, prec="fp32") > 0   # Bluestein M = 4200
     assert B.gp_axis_kind(2062, "fp64") == 0 and B.gp_axis_kind(2039, "fp64") == 2
+    assert B.gp_axis_kind(8192, "fp32") == 2 and B.gp_axis_kind(8192, "fp64") == 3
+    # past one LDS line a 3D axis is refused ...
+    for prec, n in (("fp64", 8192), ("fp32", 8194)):
+        with pytest.raises(B.GPError) as e:
+            ws(nx=n, prec=prec)
+        assert e.value.status == B.GP_E_SIZE
+
+
+# 2D axes longer than one LDS line (kind 3): a four-step split n = A B (both transforms
+# within one line) and Crank-Nicolson segments; the paper's 2D grids 13000^2 and 15000^2
+@pytest.mark.parametrize("prec,n", [("fp32", 8194), ("fp32", 9000), ("fp32", 13000),
+                                    ("fp32", 15000), ("fp32", 8284), ("fp64", 4098),
+                                    ("fp64", 8192), ("fp64", 15000), ("fp64", 4500)])
+def test_long_2d_axes_accepted(prec, n):
+    assert B.gp_axis_kind(n, prec) == 3
+    for geom in ("2dxy", "2dxz"):
+        assert ws(geom=geom, nx=n, ny=12, nz=12, prec=prec) > 0
+        assert ws(geom=geom, nx=12, ny=n, nz=n, prec=prec) > 0
+    assert ws(geom="2dxy", nx=n, ny=n, prec=prec) > 0
+
+
+# no split: primes, and 2 p with p a prime whose line (by Bluestein's algorithm) is too
+# long for two rows in LDS
+@pytest.mark.parametrize("prec,n", [("fp32", 8209), ("fp32", 2 * 4099), ("fp64", 4099),
+                                    ("fp64", 2 * 2053)])
+def test_long_axes_without_split_rejected(prec, n):
+    assert B.gp_axis_kind(n, prec) == 0
     with pytest.raises(B.GPError) as e:
-        ws(geom="2dxy", nx=8192, ny=8, prec="fp64")
-    assert e.value.status == B.GP_E_SIZE
-    with pytest.raises(B.GPError) as e:
-        ws(geom="2dxy", nx=8194, ny=8, prec="fp32")
+        ws(geom="2dxy", nx=n, ny=12, prec=prec)
     assert e.value.status == B.GP_E_SIZE
 
 

@@ -1,0 +1,119 @@
+"""2D axes longer than one LDS line (more than 8192 points in FP32, 4096 in FP64; kind 3 of
+gp_axis_kind): the x and y transforms by the four-step split n = A B through the
+workspace, and the Crank-Nicolson sweeps in segments joined by their carries.  Parity with
+the FP64 oracle through the C ABI at the bars of every other size: Phi rel-L2 1e-12 / 2e-6,
+psi rel-L2 and element-wise 1e-10 / 2e-5, energy and mu 1e-12 / 1e-6, on white-noise
+starts (every tile, segment and split column weighted)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1601_04640_amd import binding as B
+from paper_1601_04640_amd import inputs as I
+from tests.gpu_util import (FP32_E_TOL, FP32_PSI_TOL, FP64_E_TOL, FP64_PSI_TOL,
+                            assert_psi_close, banner, obs_close, oparams, rel_l2)
+
+pytestmark = pytest.mark.gpu
+
+
+def grid(geom, n0, n1, dt=0.0005):
+    """A 25.6-wide box along long axes, spacing 0.5 along short ones."""
+    h0 = 25.6 / n0 if n0 > 100 else 0.5
+    h1 = 25.6 / n1 if n1 > 100 else 0.5
+    w = dict(geom=geom, nx=n0, ny=1, nz=1, dx=h0, dy=1.0, dz=1.0, dt=dt, gamma=1.0, nu=1.0,
+             lam=4.0, g=10.0, gdd=5.0, R=0.0)
+    if geom == "2dxy":
+        w.update(ny=n1, dy=h1)
+    else:
+        w.update(nz=n1, dz=h1, nu=4.0, lam=1.0)
+    return w
+
+
+# (geometry, n0, n1, precisions); the split and segments each case exercises:
+CASES = {
+    # long x (A 100, B 90; FP32 2 segments of 4500, FP64 3 of 3000), even and odd line count
+    "2dxy_9000x12": ("2dxy", 9000, 12, ("fp32", "fp64")),
+    "2dxy_9000x13": ("2dxy", 9000, 13, ("fp32", "fp64")),
+    # long y (A 100, B 84; FP64 3 segments of 2800) in XZ
+    "2dxz_10x8400": ("2dxz", 10, 8400, ("fp32", "fp64")),
+    # radices 19 and 31 in the split (A 133 = 7 19, B 62 = 2 31)
+    "2dxy_8246x10": ("2dxy", 8246, 10, ("fp32",)),
+    # a prime factor above 31 in the split (A 109 by Bluestein's algorithm, B 76), x and y
+    "2dxy_8284x9": ("2dxy", 8284, 9, ("fp32",)),
+    "2dxy_12x8284": ("2dxy", 12, 8284, ("fp32",)),
+    # both axes long (FP64: A 70, B 60 along x; A 72, B 57 along y)
+    "2dxy_4200x4104": ("2dxy", 4200, 4104, ("fp64",)),
+    # FP64 lengths just past the line (4098 = 2 3 683: A 683 by Bluestein, B 6)
+    "2dxz_4098x16": ("2dxz", 4098, 16, ("fp64",)),
+}
+PARAMS = [(name, prec) for name, c in CASES.items() for prec in c[3]]
+
+
+def bars(prec):
+    return (FP64_PSI_TOL, FP64_E_TOL) if prec == "fp64" else (FP32_PSI_TOL, FP32_E_TOL)
+
+
+@pytest.mark.parametrize("name,prec", PARAMS)
+def test_long_axes_match_oracle(name, prec, gpu_lib):
+    from paper_1601_04640_amd.binding import Solver
+    geom, n0, n1, _ = CASES[name]
+    assert 3 in (B.gp_axis_kind(n0, prec), B.gp_axis_kind(n1, prec))
+    w = grid(geom, n0, n1)
+    banner("long axes", name, prec)
+    p = oparams(w)
+    psi0 = I.random_complex(p.shape(), 611, p.dV())
+    ptol, etol = bars(prec)
+    s = Solver(w, prec=prec)
+    s.set_psi(psi0)
+    got = s.dipolar_potential()
+    ref = O.dipolar_potential(np.abs(psi0) ** 2, p)
+    assert rel_l2(got, ref) <= (1e-12 if prec == "fp64" else 2e-6), rel_l2(got, ref)
+    assert not obs_close(s.energy(), O.observables(psi0, p), etol)
+    s.close()
+    for imag in (True, False):
+        s = Solver(w, prec=prec)
+        s.set_psi(psi0)
+        s.step_imag(3) if imag else s.step_real(3)
+        ref, hist = O.run(psi0, p, imag, 3, record=True)
+        assert_psi_close(s.get_psi(), ref, ptol, (name, imag))
+        for k, (g_, r_) in enumerate(zip(s.history(3), hist)):
+            bad = obs_close(g_, r_, etol)
+            assert not bad, (name, imag, k, bad)
+        s.close()
+
+
+def test_long_axes_fp32_both_long(gpu_lib):
+    """Both axes past the FP32 line (8200 = A 100 x B 82 with B by Bluestein's algorithm;
+    8232 = 98 x 84): Phi and two real-time steps."""
+    from paper_1601_04640_amd.binding import Solver
+    w = grid("2dxz", 8200, 8232)
+    banner("long axes: both long, fp32")
+    p = oparams(w)
+    psi0 = I.random_complex(p.shape(), 612, p.dV())
+    s = Solver(w, prec="fp32")
+    s.set_psi(psi0)
+    got = s.dipolar_potential()
+    ref = O.dipolar_potential(np.abs(psi0) ** 2, p)
+    assert rel_l2(got, ref) <= 2e-6, rel_l2(got, ref)
+    del got, ref
+    s.step_real(2)
+    assert_psi_close(s.get_psi(), O.run(psi0, p, False, 2), FP32_PSI_TOL)
+    s.close()
+
+
+def test_long_axes_graphs_and_direct_launches_agree(gpu_lib):
+    """Graph-replayed steps (8 at a time) give bitwise the steps launched one by one."""
+    from paper_1601_04640_amd.binding import Solver
+    w = grid("2dxy", 9000, 12)
+    banner("long axes: graph replay")
+    p = oparams(w)
+    psi0 = I.random_complex(p.shape(), 613, p.dV())
+    out = []
+    for graphs in (True, False):
+        s = Solver(w, prec="fp32")
+        s.use_graphs(graphs)
+        s.set_psi(psi0)
+        s.step_real(9)
+        out.append(s.get_psi())
+        s.close()
+    assert np.array_equal(out[0], out[1])
