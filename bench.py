@@ -494,7 +494,9 @@ def adjoint_2d_256(nsteps=400, K=50):
 # ---------------------------------------------------------------------- sweep
 SWEEP3 = (48, 50, 64, 80, 96, 100, 120, 128, 150, 160, 192, 200, 240, 250, 256, 300, 320, 360,
           384, 400, 450, 480, 500, 512, 540, 600)
-SWEEP2 = (256, 384, 512, 1000, 1024, 1500, 2000, 2048, 3000, 4000, 4096, 5000, 6000, 8000, 8192)
+SWEEP2 = (256, 384, 512, 1000, 1024, 1500, 2000, 2048, 3000, 4000, 4096, 5000, 6000, 8000, 8192,
+          10000, 12000, 13000, 15000)
+PASSES = {1: "specialised", 2: "run-time length", 3: "four-step, segmented"}
 
 
 def sweep(args):
@@ -502,7 +504,9 @@ def sweep(args):
     paper's Fig. 2 (3D cubes 50^3 -> 600^3, 2D squares from 1000^2): real-time steps of
     cubes and squares (trap (1,1,2), g 20, g_dd 6, R half the box in 3D; box 12.8),
     graph-replayed.  Lengths with specialised passes report the dominant pass's HBM
-    fraction; the run-time-length kernels (other lengths) report null there."""
+    fraction; the run-time-length kernels (other lengths) report null there.  2D squares
+    past one LDS line (8192 FP32, 4096 FP64) run the four-step transforms and segmented
+    sweeps, up to the paper's 15000^2."""
     import numpy as np
     import torch
     from paper_1601_04640_amd import binding as B
@@ -541,7 +545,7 @@ def sweep(args):
             byts = (step_bytes_3d(n, n, n, esz) if geom == "3d" else step_bytes_2d(n, n, esz))
             line = {"sweep": "grid size", "geom": geom, "n": n, "points": npts,
                     "dtype": "f64" if prec == "fp64" else "f32",
-                    "passes": "specialised" if kind == 1 else "run-time length",
+                    "passes": PASSES[kind],
                     "steps": steps, "value": npts * steps / wall, "unit": "grid-point-steps/s",
                     "ms_per_step": wall * 1e3 / steps, "step_algorithmic_bytes": byts,
                     "step_hbm_frac": round(byts / (wall / steps) / 1e9 / HBM_PEAK_GBS, 4),

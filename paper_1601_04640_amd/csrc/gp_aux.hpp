@@ -145,6 +145,9 @@ struct KernelGeom {
   double h0, h1, h2;
   double R;          // 3D cutoff radius (<= 0: none)
   double d;          // 2D transverse width
+  // 2D axes split for the four-step FFT (x: Ax Bx, y: Ay By; 0 when not split): the table
+  // is laid out like the spectrum, one value per slot (rows of rs slots for a split x)
+  int Ax, Bx, Ay, By, rs;
 };
 
 // ktab[(kx*n2 + k2)*n1 + k1] = U(k)/(n0 n1 n2), kx = 0..n0/2, in FP64 rounded to T.
@@ -155,16 +158,29 @@ template <typename T>
 __global__ void k_kernel_table(T* ktab, KernelGeom kg) {
   // 3D: U depends on k1 and k2 through their squares only, so the table holds the
   // quadrant k1 <= n1/2, k2 <= n2/2 (ktab[(kx (n2/2+1) + k2) (n1/2+1) + k1]); the z
-  // convolution reads index min(k, n - k).  2D: the full [kx][k1] table.
+  // convolution reads index min(k, n - k).  2D: the full [kx][k1] table, or with a split
+  // axis the spectrum's slots: a split x keeps rows y of rs slots p holding
+  // kx = Bx (p mod Ax) + p / Ax (U is even in kx: folded to n0 - kx past n0/2); a split y
+  // slot y = kb Ay + ka holds k1 = By ka + kb.
   const int H = kg.n0 / 2 + 1;
   const bool q3 = kg.geom == 0;
   const int m1n = q3 ? kg.n1 / 2 + 1 : kg.n1, m2n = q3 ? kg.n2 / 2 + 1 : kg.n2;
-  const size_t total = (size_t)H * m1n * m2n;
+  const size_t total = kg.Ax ? (size_t)kg.rs * kg.n1 : (size_t)H * m1n * m2n;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= total) return;
-  const int k1 = (int)(idx % m1n);
-  const int k2 = (int)((idx / m1n) % m2n);
-  const int kx = (int)(idx / ((size_t)m1n * m2n));
+  int k1, k2, kx;
+  if (kg.Ax) {
+    const int y = (int)(idx / kg.rs), p = (int)(idx % kg.rs);
+    kx = kg.Bx * (p % kg.Ax) + p / kg.Ax;
+    if (kx > kg.n0 - kx) kx = kg.n0 - kx;
+    k1 = y;
+    k2 = 0;
+  } else {
+    k1 = (int)(idx % m1n);
+    k2 = (int)((idx / m1n) % m2n);
+    kx = (int)(idx / ((size_t)m1n * m2n));
+  }
+  if (kg.Ay) k1 = kg.By * (k1 % kg.Ay) + k1 / kg.Ay;
   const double pi = 3.14159265358979323846;
   const double qx = 2.0 * pi * kx / (kg.n0 * kg.h0);
   // signed frequency of index k: k below n/2, k - n from n/2 on (odd n: every k <= n/2
@@ -321,22 +337,40 @@ __global__ void k_clear_u64(unsigned long long* p, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0ull;
 }
 
-// P_s = g_a ... g_b and Q_s = sum_m (g_a ... g_(m-1)) (g_a ... g_m) of segment s (rows
-// a = s n .. b = a + n - 1, g = f / 2 of the factor table), in FP64, one thread per
-// segment.
+// Fixed numbers of the Crank-Nicolson segments of a long line (segment s: rows a = s n ..
+// b = a + n - 1; g = f / 2 of the factor table), in FP64, one thread per segment.  The
+// zero-carry recurrences are linear in Delta:
+//   d0_b = sum_i w_i Delta_i,  w_i = f_i g_(i+1) ... g_b
+//   e0_a = sum_i u_i Delta_i,  u_i = f_i S_i,  S_i = G_(i-1) + g_(i+1) S_(i+1),  S_b = G_(b-1)
+// with G_(i-1) = g_a ... g_(i-1); the carries need P = g_a ... g_b and
+// Q = sum_m G_(m-1) G_m = g_a S_a.  pq[2s], pq[2s+1] = P, Q; wu[2i], wu[2i+1] = w_i, u_i
+// (G is parked in wu[2i+1] between the two passes).
 template <typename T>
-__global__ void k_seg_tables(const cpx<T>* __restrict__ f, int n, int nseg, cpx<T>* pq) {
+__global__ void k_seg_tables(const cpx<T>* __restrict__ f, int n, int nseg, cpx<T>* pq,
+                             cpx<T>* wu) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nseg) return;
-  zd P{1.0, 0.0}, Q{0.0, 0.0};
-  for (int i = s * n; i < s * n + n; ++i) {
-    const zd g{0.5 * (double)f[i].re, 0.5 * (double)f[i].im};
-    const zd R = zmul(P, g);
-    const zd PR = zmul(P, R);
-    Q = zd{Q.re + PR.re, Q.im + PR.im};
-    P = R;
+  const int a = s * n, b = a + n - 1;
+  auto gof = [&](int i) { return zd{0.5 * (double)f[i].re, 0.5 * (double)f[i].im}; };
+  zd G{1.0, 0.0};
+  for (int i = a; i <= b; ++i) {
+    wu[2 * i + 1] = cpx<T>{(T)G.re, (T)G.im};
+    G = zmul(G, gof(i));
   }
-  pq[2 * s] = cpx<T>{(T)P.re, (T)P.im};
+  zd S{0.0, 0.0}, R{1.0, 0.0};
+  for (int i = b; i >= a; --i) {
+    const zd Gm{(double)wu[2 * i + 1].re, (double)wu[2 * i + 1].im};
+    const zd gn = i < b ? gof(i + 1) : zd{0.0, 0.0};
+    const zd gS = zmul(gn, S);
+    S = zd{Gm.re + gS.re, Gm.im + gS.im};
+    const zd fi{(double)f[i].re, (double)f[i].im};
+    const zd w = zmul(fi, R), u = zmul(fi, S);
+    wu[2 * i] = cpx<T>{(T)w.re, (T)w.im};
+    wu[2 * i + 1] = cpx<T>{(T)u.re, (T)u.im};
+    R = zmul(R, gof(i));
+  }
+  const zd Q = zmul(gof(a), S);
+  pq[2 * s] = cpx<T>{(T)G.re, (T)G.im};
   pq[2 * s + 1] = cpx<T>{(T)Q.re, (T)Q.im};
 }
 

@@ -213,9 +213,8 @@ Layout make_layout(const gp_params* p, unsigned host = 0) {
   L.o_V = take((host & GP_HOST_V) ? 0 : L.esz * L.npts);
   L.o_spec = take(2 * L.esz * L.nspec);
   // kernel table: 3D holds the quadrant k1 <= n1/2, k2 <= n2/2 of the half spectrum; 2D
-  // every k1 of kx <= n0/2
-  L.nktab = (p->geom == GP_3D) ? (size_t)H * (L.n1 / 2 + 1) * (L.n2 / 2 + 1)
-                               : (size_t)H * L.n1;
+  // every k1 of kx <= n0/2, in the spectrum's slot order when an axis is split
+  L.nktab = (p->geom == GP_3D) ? (size_t)H * (L.n1 / 2 + 1) * (L.n2 / 2 + 1) : L.nspec;
   L.o_ktab = take((host & GP_HOST_KTAB) ? 0 : L.esz * L.nktab);
   const int ns[3] = {L.n0, L.n1, L.n2};
   for (int a = 0; a < 3; ++a) {
@@ -259,7 +258,9 @@ Layout make_layout(const gp_params* p, unsigned host = 0) {
           take(lng[a] && pl[q]->blue ? 2 * L.esz * (size_t)(pl[q]->n + pl[q]->m) : 0);
     }
     L.o_ltw[a][2] = take(lng[a] ? 2 * L.esz * ns0[a] : 0);
-    for (int t = 0; t < 3; ++t) L.o_seg[a][t] = take(lng[a] ? 4 * L.esz * L.lg[a].nseg : 0);
+    // per factor set: P, Q of each segment, then the summary weights w, u of each row
+    for (int t = 0; t < 3; ++t)
+      L.o_seg[a][t] = take(lng[a] ? 4 * L.esz * ((size_t)L.lg[a].nseg + ns0[a]) : 0);
     if (lng[a]) nsegl = std::max(nsegl, (size_t)ns0[1 - a] * L.lg[a].nseg);
   }
   L.o_ssum = take(8 * L.esz * nsegl);
@@ -463,15 +464,9 @@ struct Passes {
   static gp_status g_conv_y_long(gp_ctx* c, const double* scale) {
     const Layout& L = c->L;
     const int H = L.n0 / 2 + 1;
-    GKtab km{0, L.n1, 1, fdiv_make((uint32_t)L.n1)};
-    if (L.lx) {
-      km.Ax = L.lg[0].A;
-      km.Bx = L.lg[0].B;
-      km.nx = L.n0;
-      km.fAx = fdiv_make((uint32_t)L.lg[0].A);
-    }
+    // the kernel table is in the spectrum's slot order
+    GKtab km{0, L.n1, 1, fdiv_make((uint32_t)L.n1), 1};
     if (!L.ly) {  // long x only: columns p of the rows, the whole y line in LDS
-      km.m4 = 2;
       const int rs = L.lxg.rs;
       GP_PASS(c, GP_PASS_CONV_Y,
               GLaunch<T>::lines(GL_CONV, c->st, spec(c), L.n1, rs, rs, 0, 1, rs, c->gplan[1],
@@ -481,13 +476,10 @@ struct Passes {
     // y = a + Ay b: B-point transforms over b with the twiddle of column a, the A-point
     // convolution over a (wavenumber By ka + kb), the inverse steps
     const int Ay = L.lg[1].A, By = L.lg[1].B;
-    km.By = By;
-    km.fBy = fdiv_make((uint32_t)By);
     const GPlan& pa = c->lplan[1][0];
     const GPlan& pb = c->lplan[1][1];
     GP_TRY(pass_begin(c, GP_PASS_CONV_Y));
     if (!L.lx) {  // spectrum [kx][y]: lines (kx, a) of stride Ay; inner lines contiguous
-      km.m4 = 1;
       GP_HIP(GLaunch<T>::lines(GL_FWD, c->st, spec(c), By, H * Ay, Ay, L.n1, 1, Ay, pb,
                                ltw(c, 1, 1), nullptr, km, scale, ltw(c, 1, 2), 0));
       GP_HIP(GLaunch<T>::lines(GL_CONV, c->st, spec(c), Ay, H * By, 1, Ay, 0, 1, pa,
@@ -495,7 +487,6 @@ struct Passes {
       GP_HIP(GLaunch<T>::lines(GL_INV, c->st, spec(c), By, H * Ay, Ay, L.n1, 1, Ay, pb,
                                ltw(c, 1, 1), nullptr, km, scale, ltw(c, 1, 2), 0));
     } else {      // rows [y][rs]: lines (a, p) and (kb, p), consecutive p adjacent
-      km.m4 = 3;
       const long long rs = L.lxg.rs;
       GP_HIP(GLaunch<T>::lines(GL_FWD, c->st, spec(c), By, (int)(Ay * rs), (int)rs, rs, 1,
                                Ay * rs, pb, ltw(c, 1, 1), nullptr, km, scale, ltw(c, 1, 2), 1));
@@ -947,7 +938,8 @@ struct Passes {
         for (int t = 0; t < 3; ++t)
           hipLaunchKernelGGL(k_seg_tables<T>, dim3(blocks_for(L.lg[a].nseg)), dim3(kThreads), 0,
                              c->st, c->at<cpx<T>>(L.o_cn[a][t]), L.lg[a].sn, L.lg[a].nseg,
-                             c->at<cpx<T>>(L.o_seg[a][t]));
+                             c->at<cpx<T>>(L.o_seg[a][t]),
+                             c->at<cpx<T>>(L.o_seg[a][t]) + 2 * L.lg[a].nseg);
       }
     }
     KernelGeom kg{};
@@ -960,6 +952,15 @@ struct Passes {
     kg.h2 = L.h2;
     kg.R = c->p.cutoff_R;
     kg.d = (c->p.geom == GP_3D) ? 0.0 : d_perp(c->p);
+    if (L.lx) {
+      kg.Ax = L.lg[0].A;
+      kg.Bx = L.lg[0].B;
+      kg.rs = L.lxg.rs;
+    }
+    if (L.ly) {
+      kg.Ay = L.lg[1].A;
+      kg.By = L.lg[1].B;
+    }
     hipLaunchKernelGGL(k_kernel_table<T>, dim3(blocks_for(L.nktab)), dim3(kThreads), 0, c->st,
                        Kp(c), kg);
     double w0 = c->p.gamma, w1, w2 = 0.0;

@@ -344,30 +344,12 @@ struct GLines {
 //   3D (q3): lines along z, l = kx n1 + k1, e = k2; quadrant table (U is even in k1, k2)
 //            ktab[(kx (n2/2+1) + min(k2, n2-k2)) (n1/2+1) + min(k1, n1-k1)]
 //   2D:      lines along axis 1, l = kx, e = k1; ktab[kx n1 + k1]
-// 2D grids with an axis split for the four-step FFT (m4 != 0; hi, lo: l / G and l mod G of
-// the line addressing): ktab[kx n1 + ky] with
-//   bit 1 of m4: kx from the slot p = lo of a long-x spectrum row, kx = Bx (p mod Ax) + p / Ax,
-//                folded to min(kx, nx - kx) (U is even in kx); else kx = hi / By (bit 0) or l
-//   bit 0 of m4: the line is the inner (A-point) FFT of a split y axis, ky = By e + kb with
-//                kb = hi (bit 1) or hi mod By; else ky = e
+// 2D grids with a split axis (slot != 0): the table is laid out like the spectrum, and
+// an element's entry is at its own spectrum offset.
 struct GKtab {
   int q3, n1, n2;
   FDiv fn1;
-  int m4, Ax, Bx, nx, By;
-  FDiv fAx, fBy;
-  __device__ __forceinline__ long long index4(int l, int hi, int lo, int e) const {
-    int kx = l, ky = e;
-    if (m4 & 2) {
-      const int r = (int)fdiv((uint32_t)lo, fAx);
-      kx = Bx * (lo - r * Ax) + r;
-      if (kx > nx - kx) kx = nx - kx;
-      if (m4 & 1) ky = By * e + hi;
-    } else if (m4 & 1) {
-      kx = (int)fdiv((uint32_t)hi, fBy);
-      ky = By * e + (hi - kx * By);
-    }
-    return (long long)kx * n1 + ky;
-  }
+  int slot;
   __device__ __forceinline__ long long index(int l, int e) const {
     if (q3) {
       const int kx = (int)fdiv((uint32_t)l, fn1), k1 = l - kx * n1;
@@ -471,15 +453,7 @@ __global__ void __launch_bounds__(kGenThreads, (gen_waves_per_eu<T, BLUE>())) kg
         const int2 le = g.tile_index(t);
         at[u] = (t < tot && le.x < nl) ? le.x * LS + le.y : -1;
         long long ki = 0;
-        if (at[u] >= 0) {
-          const int l = l0 + le.x;
-          if (km.m4) {
-            const int hi = (int)fdiv((uint32_t)l, g.fg);
-            ki = km.index4(l, hi, l - hi * g.G, le.y);
-          } else {
-            ki = km.index(l, le.y);
-          }
-        }
+        if (at[u] >= 0) ki = km.slot ? g.addr(l0 + le.x, le.y) : km.index(l0 + le.x, le.y);
         kv[u] = ktab[ki];
       }
 #pragma unroll
@@ -821,24 +795,22 @@ template <typename T>
 constexpr int tile_max_waves() { return sizeof(T) == 4 ? 16 : 8; }
 
 // Lines longer than one tile are swept in segments of n rows (SEG): line l of the tile is
-// segment s = l mod nseg of the long line l / nseg, its factor rows f[s n ..].  The
-// recurrences are linear, so a segment's results follow from its own solve with zero
-// carries and two numbers from its neighbours: with C the true d entering the segment
-// (at its row -1) and E the true e entering from the right (at its row n),
-//   d_i = d0_i + R_i C,                        R_i = g_a ... g_i (a: the first row)
-//   e_a = e0_a + Q C + P E,                    P = R_(last row),
-//   Q = sum_m (g_a ... g_(m-1)) R_m            (P and Q are fixed by the factor table)
-// where d0, e0 are the zero-carry results.  MODE 3 (summary): the zero-carry solve, writing
-// per segment line sum[4l ..] = d0 at the last row, e0 at the first row, psi at the first
-// and the last row; the carries then run along each long line (k_seg_carry), and the
-// sweep proper (MODE 0 or 1) starts its scans from car[4l] = C, car[4l+1] = E, with
-// car[4l+2], car[4l+3] = psi of the rows before and after the segment (values before the
-// sweep: the neighbouring segments are rewritten by other blocks).
+// segment s = l mod nseg of the long line l / nseg, its factor rows f[s n ..] (read from
+// global memory).  The recurrences are linear, so a segment's results follow from its own
+// solve started from two carries: C, the true d entering the segment (at its row -1), and
+// E, the true e entering from the right (at its row n).  With d0, e0 the zero-carry
+// results and R_i = g_a ... g_i (a: the first row),
+//   d_i = d0_i + R_i C,   e_a = e0_a + Q C + P E,   P = R_(last row),
+//   Q = sum_m (g_a ... g_(m-1)) R_m
+// (P, Q fixed by the factor table).  The carries run along each long line from the
+// segments' summaries (k_seg_summary, k_seg_carry); the sweep starts its scans from
+// car[4l] = C and car[4l+1] = E, with car[4l+2], car[4l+3] = psi of the rows before and
+// after the segment (values before the sweep: the neighbouring segments are rewritten by
+// other blocks).
 struct GSeg {
   int nseg;
   FDiv fseg;
   const void* car;
-  void* sum;
 };
 
 struct GNl {  // the nonlinear sub-step's inputs for the fused x sweep
@@ -857,7 +829,6 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
                                                                 double* __restrict__ part,
                                                                 GNl nlz, GSeg sg) {
   static_assert(!SEG || NLM < 0, "segments carry no nonlinear sub-step");
-  static_assert(MODE != 3 || SEG, "the summary mode belongs to segmented sweeps");
   extern __shared__ __align__(16) char lds_raw[];
   __shared__ double red[7 * kTileMaxWaves];
   __shared__ cpx<T> wP[kTileMaxWaves], wB[kTileMaxWaves];  // the waves' composed maps
@@ -870,7 +841,7 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
   const int nt = blockDim.x;
   const int tot = g.nl * N;  // the full tile's indexing; lines past nl are skipped
   cpx<T>* ps = reinterpret_cast<cpx<T>*>(lds_raw);   // nl lines of psi (then u)
-  cpx<T>* fl = ps + (size_t)g.nl * LS;                // the factor table: one line (SEG: nl)
+  cpx<T>* fl = ps + (size_t)g.nl * LS;                // the factor table, one line (not SEG)
   // values per thread per load round (FP64: half, a quarter with the nonlinear sub-step,
   // for the registers)
   constexpr int U = sizeof(T) == 4 ? kGenU : (NLM >= 0 ? kGenU / 4 : kGenU / 2);
@@ -959,16 +930,9 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
       ps[at[u]] = v;
     }
   }
-  if constexpr (SEG) {
-    // each line's own rows of the factor table
-    for (int t = threadIdx.x; t < nl * N; t += nt) {
-      const int ln = (int)fdiv((uint32_t)t, g.fn), e = t - ln * N;
-      const int l = l0 + ln;
-      const int sgi = l - (int)fdiv((uint32_t)l, sg.fseg) * sg.nseg;
-      const int c = (int)fdiv((uint32_t)e, fs);
-      fl[ln * LS + c * Sp + (e - c * S)] = f[(long long)sgi * N + e];
-    }
-  } else if constexpr (MODE != 2) {
+  // segments read their factor rows from global memory (each lane its chunk's S rows,
+  // contiguous; the table is small and stays in L2), not through LDS
+  if constexpr (MODE != 2 && !SEG) {
 #pragma unroll
     for (int u = 0; u < UF; ++u) {
       const int t = threadIdx.x + u * nt;
@@ -1001,22 +965,14 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
   [[maybe_unused]] cpx<T> eL = zero, eR = zero, cC = zero, cE = zero;
   if constexpr (SEG) {
     sgi = lg - (int)fdiv((uint32_t)lg, sg.fseg) * sg.nseg;
-    if constexpr (MODE == 3) {
-      // before the sweep every value is the stored one: read the neighbours in place
-      const cpx<T> vl = data[sgi > 0 ? (long long)lg * N - 1 : 0];
-      const cpx<T> vr = data[sgi + 1 < sg.nseg ? (long long)(lg + 1) * N : 0];
-      if (act && sgi > 0) eL = vl;
-      if (act && sgi + 1 < sg.nseg) eR = vr;
-    } else {
-      const cpx<T>* car = reinterpret_cast<const cpx<T>*>(sg.car) + 4LL * lg;
-      cC = car[0];
-      cE = car[1];
-      eL = car[2];
-      eR = car[3];
-    }
+    const cpx<T>* car = reinterpret_cast<const cpx<T>*>(sg.car) + 4LL * lg;
+    cC = car[0];
+    cE = car[1];
+    eL = car[2];
+    eR = car[3];
   }
   if constexpr (MODE != 2) {
-    const cpx<T>* fq = fl + (SEG ? (act ? line : 0) * LS : 0) + slot;
+    const cpx<T>* fq = SEG ? f + (long long)sgi * N + (cnt > 0 ? i0 : 0) : fl + slot;
     // forward, zero carry: local d and the chunk's product of g
     cpx<T> acc = zero, prod = {1, 0};
     cpx<T> pm = p[q > 0 && cnt > 0 ? -Sp + S - 1 : 0];   // row i0 - 1
@@ -1044,9 +1000,9 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
         P = P * Pp;
       }
     }
-    // d entering the wave: the earlier waves' totals composed in order (on the segment's
-    // carry; zero in the summary)
-    cpx<T> C = (SEG && MODE != 3) ? cC : zero;
+    // d entering the wave: the earlier waves' totals composed in order (on a segment's
+    // carry)
+    cpx<T> C = SEG ? cC : zero;
     if (wpl > 1) {
       if (lane == 63) {
         wP[wave] = P;
@@ -1063,13 +1019,6 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
       if (j < cnt) {
         carry = scl(fq[j], (T)0.5) * carry;
         d[j] = d[j] + carry;
-        if constexpr (MODE == 3) {
-          if (i0 + j == N - 1) {  // the segment's last row: d0 and psi
-            cpx<T>* sm = reinterpret_cast<cpx<T>*>(sg.sum) + 4LL * lg;
-            sm[0] = d[j];
-            sm[3] = p[j];
-          }
-        }
       }
     }
     // backward, zero carry from the right: local e (kept in d)
@@ -1091,7 +1040,7 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
       }
     }
     // e entering the wave from the right: the later waves' totals composed in order
-    cpx<T> E = (SEG && MODE != 3) ? cE : zero;
+    cpx<T> E = SEG ? cE : zero;
     if (wpl > 1) {
       if (lane == 0) {
         wP[wave] = P;
@@ -1102,25 +1051,12 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
     }
     const cpx<T> Pd = shfl_down_c(P, 1), Bd = shfl_down_c(B, 1);
     carry = lane == 63 ? E : Pd * E + Bd;         // e at the start of the next chunk
-    if constexpr (MODE == 3) {
-      if (q == 0 && cnt > 0) {  // the segment's first row: e0 and psi
-        cpx<T>* sm = reinterpret_cast<cpx<T>*>(sg.sum) + 4LL * lg;
-        // d holds the chunk's local e; the carry reaches row 0 through the chunk's g
-        cpx<T> cr = carry;
 #pragma unroll
-        for (int j = TS - 1; j >= 0; --j)
-          if (j < cnt) cr = scl(fq[j], (T)0.5) * cr;
-        sm[1] = d[0] + cr;
-        sm[2] = p[0];
-      }
-    } else {
-#pragma unroll
-      for (int j = TS - 1; j >= 0; --j) {
-        if (j < cnt) {
-          carry = scl(fq[j], (T)0.5) * carry;
-          d[j] = p[j] + (d[j] + carry);   // u
-          p[j] = d[j];
-        }
+    for (int j = TS - 1; j >= 0; --j) {
+      if (j < cnt) {
+        carry = scl(fq[j], (T)0.5) * carry;
+        d[j] = p[j] + (d[j] + carry);   // u
+        p[j] = d[j];
       }
     }
   } else {
@@ -1128,7 +1064,7 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
     for (int j = 0; j < TS; ++j)
       if (j < cnt) d[j] = p[j];
   }
-  if constexpr (MODE == 1 || MODE == 2) {
+  if constexpr (MODE != 0) {
     // sums of u (or of the stored state): |u|^2 and the differences, the last one with
     // the next chunk's first row (the next lane's, or the next wave's lane 0 through LDS;
     // after a segment's last row: the next segment's first, psi + e there)
@@ -1163,7 +1099,7 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
       for (int k = 0; k < 7; ++k) nlz.part[7 * (long long)blockIdx.x + k] = q7[k];
     }
   }
-  if constexpr (MODE == 0 || MODE == 1) {
+  if constexpr (MODE != 2) {
     __syncthreads();
     for (int t = threadIdx.x, r = 0; t < tot; t += nt, ++r) {
       int ln, e;

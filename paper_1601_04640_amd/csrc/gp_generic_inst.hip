@@ -92,10 +92,8 @@ hipError_t GLaunch<T>::prepare() {
                       reinterpret_cast<const void*>(&kg_cn_tile<T, 0, MODE_REAL, kTileS>),
                       reinterpret_cast<const void*>(&kg_cn_tile<T, 0, -1, 8, true>),
                       reinterpret_cast<const void*>(&kg_cn_tile<T, 1, -1, 8, true>),
-                      reinterpret_cast<const void*>(&kg_cn_tile<T, 3, -1, 8, true>),
                       reinterpret_cast<const void*>(&kg_cn_tile<T, 0, -1, kTileS, true>),
-                      reinterpret_cast<const void*>(&kg_cn_tile<T, 1, -1, kTileS, true>),
-                      reinterpret_cast<const void*>(&kg_cn_tile<T, 3, -1, kTileS, true>)};
+                      reinterpret_cast<const void*>(&kg_cn_tile<T, 1, -1, kTileS, true>)};
   for (const void* k : kt) {
     const hipError_t e =
         hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kTileLds);
@@ -161,7 +159,7 @@ hipError_t launch_tile(hipStream_t st, cpx<T>* data, const GLines& g, int wpl,
                        const cpx<T>* f, double* part, const GNl& nlz, const GSeg& sg = GSeg{}) {
   const int blocks = (g.nlines + g.nl - 1) / g.nl;
   const int S = (g.n + 64 * wpl - 1) / (64 * wpl);
-  const size_t lds = lds_of((SEG ? 2 * g.nl : g.nl + 1) * cn_line_slots(g.n, 64 * wpl));
+  const size_t lds = lds_of((SEG ? g.nl : g.nl + 1) * cn_line_slots(g.n, 64 * wpl));
   if (lds > (size_t)kTileLds || g.nl * wpl > tile_max_waves<T>() || S > kTileS)
     return hipErrorInvalidValue;
   const FDiv fs = fdiv_make((uint32_t)S);
@@ -454,11 +452,8 @@ hipError_t GLaunch<T>::lx_c2r(hipStream_t st, const cpx<T>* spec, cpx<T>* w, T* 
 
 template <>
 int GLaunch<T>::seg_lines(int sn, int nlines) {
-  // the tile sweep's lines per block, with room for one factor line per line
-  int nl = cn_tile_lines(sn, nlines, false);
-  const int per_line = cn_line_slots(sn, 64 * cn_tile_wpl(sn)) * (int)sizeof(cpx<T>);
-  while (nl > 1 && 2 * nl * per_line > kTileLds) --nl;
-  return nl;
+  // the tile sweep's lines per block (segments keep no factor line in LDS)
+  return cn_tile_lines(sn, nlines, false);
 }
 
 template <>
@@ -471,8 +466,11 @@ hipError_t GLaunch<T>::seg_sweep(int mode, hipStream_t st, cpx<T>* data, int sn,
   const GLines g = tile_lines(sn, nlines, seg_lines(sn, nlines), 1, sn, 0, 1);
   const int wpl = cn_tile_wpl(sn);
   const GNl none{};
-  const GSeg sg{nseg, fdiv_make((uint32_t)nseg), car, sum};
-  hipError_t e = launch_tile<3, -1, true>(st, data, g, wpl, f, nullptr, none, sg);
+  const GSeg sg{nseg, fdiv_make((uint32_t)nseg), car};
+  constexpr int kWavesPerBlock = kThreads / 64;
+  hipLaunchKernelGGL(k_seg_summary<T>, dim3((nlines + kWavesPerBlock - 1) / kWavesPerBlock),
+                     dim3(kThreads), 0, st, data, sum, pq + 2 * nseg, sn, nseg, sg.fseg, nlines);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_seg_carry<T>, dim3((nlong + kThreads - 1) / kThreads), dim3(kThreads), 0,
                      st, sum, car, pq, nseg, nlong);

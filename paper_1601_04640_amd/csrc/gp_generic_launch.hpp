@@ -27,7 +27,8 @@ inline bool gen_size_ok(int n) {
 // An axis of a 2D grid longer than one LDS line: the four-step FFT split n = A B (A >= B,
 // the smallest such A; both transforms within one LDS line, two rows of A for the
 // untangling of real lines) and the Crank-Nicolson segments (nseg segments of sn rows: the
-// largest divisor of n that one tile sweep holds, at least 64 rows).
+// largest divisor of n from 64 to 512, one wave per segment with at most 8 rows per lane
+// and several segments per block; failing that the largest one tile sweep holds).
 struct GLong {
   int A, B;
   int sn, nseg;
@@ -51,11 +52,13 @@ inline bool gen_long_plan(int n, GLong* lp) {
     }
   }
   if (lp->A == 0) return false;
-  for (int s = lim; s >= 64; --s) {
-    if (n % s == 0 && n / s >= 2) {
-      lp->sn = s;
-      lp->nseg = n / s;
-      return true;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int s = pass == 0 ? 512 : lim; s >= 64; --s) {
+      if (n % s == 0 && n / s >= 2) {
+        lp->sn = s;
+        lp->nseg = n / s;
+        return true;
+      }
     }
   }
   return false;
@@ -132,7 +135,8 @@ struct GLaunch {
                            const cpx<T>* twb, const cpx<T>* w4);
   // segmented CN sweep of nlong contiguous lines of nseg segments of sn rows (mode 0:
   // solve, 1: solve with the new-state sums in part over seg_blocks blocks); f: the long
-  // line's factor table, pq: the segments' carry products; sum, car: 4 values per segment
+  // line's factor table, pq: the segments' carry products P, Q (2 nseg values) followed by
+  // the rows' summary weights (2 per row); sum, car: 4 values per segment
   static int seg_lines(int sn, int nlines);
   static int seg_blocks(int sn, int nlines) {
     const int nl = seg_lines(sn, nlines);

@@ -25,9 +25,9 @@
 //                    conjugates), inverse A-point FFTs, conjugate twiddle -> w
 //   kg_lx_cols_inv   inverse B-point column FFTs -> Phi of lines j (Re) and j + 1 (Im)
 //
-// Crank-Nicolson sweeps of long lines run in segments (kg_cn_tile with SEG, GSeg): a
-// summary sweep, k_seg_carry along each line, and the sweep proper (the segments' carry
-// products P and Q: k_seg_tables, with the other tables).
+// Crank-Nicolson sweeps of long lines run in segments: k_seg_summary (two weighted sums
+// per segment), k_seg_carry along each line, and the sweep proper (kg_cn_tile with SEG,
+// GSeg); the weights and the carry products P, Q come from k_seg_tables.
 #pragma once
 #include "gp_generic.hpp"
 
@@ -290,6 +290,68 @@ __global__ void __launch_bounds__(kGenThreads) kg_lx_cols_inv(const cpx<T>* __re
       phi[o] = z.re;
       if (has1) phi[o + N] = z.im;
     }
+  }
+}
+
+// Segment summaries by the fixed weights of k_seg_tables: sum[4l ..] = d0 at the last row
+// (sum_i w_i Delta_i), e0 at the first row (sum_i u_i Delta_i), psi at the first and the
+// last row, for the nlines = nlong nseg contiguous segment lines l = L nseg + s of sn rows
+// (Delta from the long line's neighbours; none past its ends).  One wave per segment line,
+// lanes over its rows.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_seg_summary(const cpx<T>* __restrict__ data,
+                                                          cpx<T>* __restrict__ sum,
+                                                          const cpx<T>* __restrict__ wu,
+                                                          int sn, int nseg, FDiv fseg,
+                                                          int nlines) {
+  constexpr int U = 4;
+  const int lane = threadIdx.x & 63;
+  const int l = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  if (l >= nlines) return;  // whole waves
+  const int s = l - (int)fdiv((uint32_t)l, fseg) * nseg;
+  const long long base = (long long)l * sn;
+  const int r0 = s * sn;                 // the segment's first row in its long line
+  const int N = nseg * sn;
+  T wr = 0, wi = 0, ur = 0, ui = 0;
+  for (int i0 = lane; i0 < sn; i0 += 64 * U) {
+    cpx<T> pm[U], pc[U], pn[U], w[U], u[U];
+    bool ok[U], hm[U], hn[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int i = i0 + 64 * q;
+      ok[q] = i < sn;
+      const int r = r0 + (ok[q] ? i : 0);
+      hm[q] = ok[q] && r > 0;
+      hn[q] = ok[q] && r + 1 < N;
+      const long long ad = base + (ok[q] ? i : 0);
+      pc[q] = data[ad];
+      pm[q] = data[hm[q] ? ad - 1 : ad];
+      pn[q] = data[hn[q] ? ad + 1 : ad];
+      w[q] = wu[2LL * r];
+      u[q] = wu[2LL * r + 1];
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      if (!ok[q]) continue;
+      const cpx<T> zero{0, 0};
+      const cpx<T> dl = (hm[q] ? pm[q] : zero) + (hn[q] ? pn[q] : zero) - (pc[q] + pc[q]);
+      wr += w[q].re * dl.re - w[q].im * dl.im;
+      wi += w[q].re * dl.im + w[q].im * dl.re;
+      ur += u[q].re * dl.re - u[q].im * dl.im;
+      ui += u[q].re * dl.im + u[q].im * dl.re;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    wr += __shfl_down(wr, off, 64);
+    wi += __shfl_down(wi, off, 64);
+    ur += __shfl_down(ur, off, 64);
+    ui += __shfl_down(ui, off, 64);
+  }
+  if (lane == 0) {
+    sum[4LL * l] = cpx<T>{wr, wi};
+    sum[4LL * l + 1] = cpx<T>{ur, ui};
+    sum[4LL * l + 2] = data[base];
+    sum[4LL * l + 3] = data[base + sn - 1];
   }
 }
 

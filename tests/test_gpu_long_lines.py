@@ -31,19 +31,22 @@ def grid(geom, n0, n1, dt=0.0005):
 
 # (geometry, n0, n1, precisions); the split and segments each case exercises:
 CASES = {
-    # long x (A 100, B 90; FP32 2 segments of 4500, FP64 3 of 3000), even and odd line count
+    # long x (A 100, B 90; 18 segments of 500), even and odd line count
     "2dxy_9000x12": ("2dxy", 9000, 12, ("fp32", "fp64")),
     "2dxy_9000x13": ("2dxy", 9000, 13, ("fp32", "fp64")),
-    # long y (A 100, B 84; FP64 3 segments of 2800) in XZ
+    # long y (A 100, B 84; 20 segments of 420) in XZ
     "2dxz_10x8400": ("2dxz", 10, 8400, ("fp32", "fp64")),
-    # radices 19 and 31 in the split (A 133 = 7 19, B 62 = 2 31)
+    # radices 19 and 31 in the split (A 133 = 7 19, B 62 = 2 31; 19 segments of 434)
     "2dxy_8246x10": ("2dxy", 8246, 10, ("fp32",)),
-    # a prime factor above 31 in the split (A 109 by Bluestein's algorithm, B 76), x and y
+    # a prime factor above 31 in the split (A 109 by Bluestein's algorithm, B 76; 19 segments
+    # of 436), x and y
     "2dxy_8284x9": ("2dxy", 8284, 9, ("fp32",)),
     "2dxy_12x8284": ("2dxy", 12, 8284, ("fp32",)),
-    # both axes long (FP64: A 70, B 60 along x; A 72, B 57 along y)
+    # both axes long (FP64: A 70, B 60 along x, 10 segments of 420; A 72, B 57 along y,
+    # 9 segments of 456)
     "2dxy_4200x4104": ("2dxy", 4200, 4104, ("fp64",)),
-    # FP64 lengths just past the line (4098 = 2 3 683: A 683 by Bluestein, B 6)
+    # FP64 lengths just past the line (4098 = 2 3 683: A 683 by Bluestein, B 6; two
+    # segments of 2049, 8 waves per segment line)
     "2dxz_4098x16": ("2dxz", 4098, 16, ("fp64",)),
 }
 PARAMS = [(name, prec) for name, c in CASES.items() for prec in c[3]]
@@ -83,8 +86,8 @@ def test_long_axes_match_oracle(name, prec, gpu_lib):
 
 
 def test_long_axes_fp32_both_long(gpu_lib):
-    """Both axes past the FP32 line (8200 = A 100 x B 82 with B by Bluestein's algorithm;
-    8232 = 98 x 84): Phi and two real-time steps."""
+    """Both axes past the FP32 line (8200 = A 100 x B 82 with B by Bluestein's algorithm,
+    20 segments of 410; 8232 = 98 x 84, 21 segments of 392): Phi and two real-time steps."""
     from paper_1601_04640_amd.binding import Solver
     w = grid("2dxz", 8200, 8232)
     banner("long axes: both long, fp32")
