@@ -51,9 +51,10 @@ extern "C" {
 typedef int gp_status;
 #define GP_OK            0
 #define GP_E_ARG        -1  /* bad pointer, non-positive dt/h, bad enum, workspace too small */
-#define GP_E_SIZE       -2  /* an axis is < 4, or its FFT line is longer than 8192 points
-                               (FP32) / 4096 (FP64): N, or for a length with a prime factor
-                               above 31 Bluestein's M >= 2N - 1; see gp_axis_kind */
+#define GP_E_SIZE       -2  /* an axis is < 4; or a 3D axis's FFT line is longer than 8192
+                               points (FP32) / 4096 (FP64): N, or for a length with a prime
+                               factor above 31 Bluestein's M >= 2N - 1; or a longer 2D axis
+                               has no four-step split; see gp_axis_kind */
 #define GP_E_DEVICE     -3  /* a HIP runtime call or kernel launch failed */
 #define GP_E_NONFINITE  -4  /* the wave function became NaN/Inf (or its norm underflowed to 0) */
 #define GP_E_STATE      -5  /* call out of order (e.g. stepping before gp_set_psi) */
@@ -101,11 +102,15 @@ gp_status gp_workspace_bytes(const gp_params* params, size_t* bytes);
  * passes (any other n >= 4, even or odd: prime factors up to 31 by Stockham stages,
  * larger ones by Bluestein's algorithm through an FFT of length M >= 2n - 1 whose factors
  * are 2, 3, 5, 7; the FFT line, n or M, up to 8192 points in GP_FP32_MIXED and 4096 in
- * GP_FP64), 0 = unsupported (GP_E_SIZE).  A grid with
- * any axis of kind 2 runs every pass with the run-time-length kernels, which take more
- * launches per step; gp_step_real_adjoint, the batched ensemble and the allocation-free
- * call need axes of kind 1.  (The paper's programs enlarge an unsuitable grid silently,
- * "Unusual features"; here every accepted size runs as given.) */
+ * GP_FP64), 3 = longer than one such line, in 2D grids only (the paper's 2D runs reach
+ * 15000^2): the FFT by the four-step split n = A B (A >= B the smallest such factor whose
+ * A- and B-point transforms fit the line, and two A-point rows fit it together) through
+ * the workspace, the Crank-Nicolson sweeps in segments of up to 512 rows joined by their
+ * carries; 0 = unsupported (GP_E_SIZE; for kind 3 a length with no such split, e.g. a
+ * prime).  A grid with any axis of kind 2 or 3 runs every pass with the run-time-length
+ * kernels, which take more launches per step; gp_step_real_adjoint, the batched ensemble
+ * and the allocation-free call need axes of kind 1.  (The paper's programs enlarge an
+ * unsuitable grid silently, "Unusual features"; here every accepted size runs as given.) */
 int gp_axis_kind(int n, int prec);
 
 /* Create a context ("Summary of revisions": the host initialises the variables, which

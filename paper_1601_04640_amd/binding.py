@@ -393,12 +393,14 @@ def gp_evolve(ctx: int, imag: bool, nsteps: int, every: int, fn=None) -> int:
 
 
 def gp_axis_kind(n: int, prec: str = "fp64") -> int:
-    """1: specialised passes, 2: run-time-length passes, 0: unsupported."""
+    """1: specialised passes, 2: run-time-length passes, 3: a 2D axis longer than one LDS
+    line (four-step transforms, segmented sweeps), 0: unsupported."""
     return load().gp_axis_kind(n, PREC[prec])
 
 
 def supported_sizes(limit: int = 16384, prec: str = "fp64", kind=None) -> list:
-    """Axis lengths gp_init accepts (kind 1 or 2, or only the given kind)."""
+    """Axis lengths gp_init accepts (kind 1, 2 or, in 2D grids, 3; or only the given
+    kind)."""
     out = []
     for n in range(2, limit + 1):
         k = gp_axis_kind(n, prec)

@@ -1,6 +1,8 @@
-// Pass kernels for axis lengths with no compile-time specialisation: any even length
-// whose prime factors are at most 31.  The line length, the FFT's radix plan and the
-// tile shapes are kernel arguments, so one set of kernels serves every such grid.
+// Pass kernels for axis lengths with no compile-time specialisation: any length of at
+// least 4 whose FFT line (the length, or Bluestein's M for a prime factor above 31) fits
+// one LDS buffer; longer 2D axes add the four-step passes of gp_long.hpp.  The line
+// length, the FFT's radix plan and the tile shapes are kernel arguments, so one set of
+// kernels serves every such grid.
 //
 // The step is the same split-step as the specialised passes ("Solution method": the
 // dipolar term by the convolution theorem, then the Crank-Nicolson sweeps; "Summary of
