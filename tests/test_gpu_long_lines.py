@@ -2,8 +2,11 @@
 gp_axis_kind): the x and y transforms by the four-step split n = A B through the
 workspace, and the Crank-Nicolson sweeps in segments joined by their carries.  Parity with
 the FP64 oracle through the C ABI at the bars of every other size: Phi rel-L2 1e-12 / 2e-6,
-psi rel-L2 and element-wise 1e-10 / 2e-5, energy and mu 1e-12 / 1e-6, on white-noise
-starts (every tile, segment and split column weighted)."""
+psi rel-L2 and element-wise 1e-10 / 2e-5, energy and mu 1e-12 / 1e-6.  Two starts: a
+noisy Gaussian, whose density sits at low wavenumbers where U(k) varies (a slot holding
+the wrong wavenumber shows there: for white noise U is nearly constant over most of the
+spectrum, so Phi would only check that the transforms invert each other), and white
+noise (every tile, segment and split column weighted)."""
 import numpy as np
 import pytest
 
@@ -56,6 +59,12 @@ def bars(prec):
     return (FP64_PSI_TOL, FP64_E_TOL) if prec == "fp64" else (FP32_PSI_TOL, FP32_E_TOL)
 
 
+def smooth_start(w, seed):
+    """Noisy Gaussian, widths 1.1 (axis 1) and 1.6 (x): most of the density at low k."""
+    return I.gaussian(w["geom"], w["nx"], w["ny"], w["nz"], w["dx"], w["dy"], w["dz"],
+                      widths=(1.1, 1.6), amp_noise=0.05, phase_noise=0.02, seed=seed)
+
+
 @pytest.mark.parametrize("name,prec", PARAMS)
 def test_long_axes_match_oracle(name, prec, gpu_lib):
     from paper_1601_04640_amd.binding import Solver
@@ -64,25 +73,27 @@ def test_long_axes_match_oracle(name, prec, gpu_lib):
     w = grid(geom, n0, n1)
     banner("long axes", name, prec)
     p = oparams(w)
-    psi0 = I.random_complex(p.shape(), 611, p.dV())
     ptol, etol = bars(prec)
-    s = Solver(w, prec=prec)
-    s.set_psi(psi0)
-    got = s.dipolar_potential()
-    ref = O.dipolar_potential(np.abs(psi0) ** 2, p)
-    assert rel_l2(got, ref) <= (1e-12 if prec == "fp64" else 2e-6), rel_l2(got, ref)
-    assert not obs_close(s.energy(), O.observables(psi0, p), etol)
-    s.close()
-    for imag in (True, False):
+    for kind, psi0 in (("gaussian", smooth_start(w, 611)),
+                       ("noise", I.random_complex(p.shape(), 611, p.dV()))):
         s = Solver(w, prec=prec)
         s.set_psi(psi0)
-        s.step_imag(3) if imag else s.step_real(3)
-        ref, hist = O.run(psi0, p, imag, 3, record=True)
-        assert_psi_close(s.get_psi(), ref, ptol, (name, imag))
-        for k, (g_, r_) in enumerate(zip(s.history(3), hist)):
-            bad = obs_close(g_, r_, etol)
-            assert not bad, (name, imag, k, bad)
+        got = s.dipolar_potential()
+        ref = O.dipolar_potential(np.abs(psi0) ** 2, p)
+        err = rel_l2(got, ref)
+        assert err <= (1e-12 if prec == "fp64" else 2e-6), (kind, err)
+        assert not obs_close(s.energy(), O.observables(psi0, p), etol), kind
         s.close()
+        for imag in (True, False):
+            s = Solver(w, prec=prec)
+            s.set_psi(psi0)
+            s.step_imag(3) if imag else s.step_real(3)
+            ref, hist = O.run(psi0, p, imag, 3, record=True)
+            assert_psi_close(s.get_psi(), ref, ptol, (name, kind, imag))
+            for k, (g_, r_) in enumerate(zip(s.history(3), hist)):
+                bad = obs_close(g_, r_, etol)
+                assert not bad, (name, kind, imag, k, bad)
+            s.close()
 
 
 def test_long_axes_fp32_both_long(gpu_lib):
@@ -92,13 +103,15 @@ def test_long_axes_fp32_both_long(gpu_lib):
     w = grid("2dxz", 8200, 8232)
     banner("long axes: both long, fp32")
     p = oparams(w)
-    psi0 = I.random_complex(p.shape(), 612, p.dV())
     s = Solver(w, prec="fp32")
+    psi0 = smooth_start(w, 612)
     s.set_psi(psi0)
     got = s.dipolar_potential()
     ref = O.dipolar_potential(np.abs(psi0) ** 2, p)
     assert rel_l2(got, ref) <= 2e-6, rel_l2(got, ref)
     del got, ref
+    psi0 = I.random_complex(p.shape(), 612, p.dV())
+    s.set_psi(psi0)
     s.step_real(2)
     assert_psi_close(s.get_psi(), O.run(psi0, p, False, 2), FP32_PSI_TOL)
     s.close()
@@ -120,3 +133,49 @@ def test_long_axes_graphs_and_direct_launches_agree(gpu_lib):
         out.append(s.get_psi())
         s.close()
     assert np.array_equal(out[0], out[1])
+
+
+def test_full_size_15000_plane_waves(gpu_lib):
+    """The sweep's largest grid, 15000^2 FP32 (x and y split 125 x 120, segments of 500),
+    in its own configuration.  The density is a constant plus plane waves reaching past
+    row 60 of the split (kx = 130, 250: columns ka 1 and 2) and, through their images
+    N - k, the rows rebuilt from conjugates; with the Dirichlet boundary zeroed it is
+    compared with the oracle's Phi of the whole grid.  Then four real-time steps of a
+    Gaussian conserve the norm."""
+    from paper_1601_04640_amd.binding import Solver
+    n = 15000
+    h = 12.8 / n
+    w = dict(geom="2dxy", nx=n, ny=n, nz=1, dx=h, dy=h, dz=1.0, dt=0.0005, gamma=1.0,
+             nu=1.0, lam=4.0, g=20.0, gdd=6.0, R=0.0)
+    banner("long axes: 15000^2 fp32 plane waves")
+    assert B.gp_axis_kind(n, "fp32") == 3
+    p = oparams(w)
+    i = np.arange(n)
+    rho = np.zeros((n, n))
+    for (kx, ky, a) in [(0, 0, 1.0), (3, 5, 0.3), (130, 17, 0.2), (250, 211, 0.15),
+                        (41, 0, 0.1)]:
+        cx, sx = np.cos(2 * np.pi * kx * i / n), np.sin(2 * np.pi * kx * i / n)
+        cy, sy = np.cos(2 * np.pi * ky * i / n), np.sin(2 * np.pi * ky * i / n)
+        rho += a * (np.outer(cy, cx) - np.outer(sy, sx))
+    psi = O.zero_boundary(np.sqrt(rho))
+    del rho
+    s = Solver(w, prec="fp32")
+    s.set_psi(psi)
+    got = s.dipolar_potential()
+    ref = O.dipolar_potential(np.abs(psi) ** 2, p)
+    del psi
+    err = rel_l2(got, ref)
+    mx = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+    print("15000^2 Phi: rel-L2", err, "max", mx, flush=True)
+    assert err <= 2e-6 and mx <= 2e-5, (err, mx)
+    del got, ref
+    x = (i - n // 2) * h
+    g1 = np.exp(-0.5 * x * x)
+    g1[0] = g1[-1] = 0.0
+    psi = np.outer(np.exp(-2.0 * x * x), g1).astype(np.complex64)
+    s.set_psi(psi)
+    del psi
+    s.step_real(4)
+    norms = [r["norm"] for r in s.history(4)]
+    assert all(abs(v - norms[0]) <= 1e-5 * norms[0] for v in norms), norms
+    s.close()
