@@ -134,8 +134,9 @@ def test_random_field_start(prec, gpu_lib):
                                     ("fp32", 4093), ("fp64", 2039)])
 def test_longest_lines(prec, n, gpu_lib):
     """The longest x and y lines one block holds (and a 29-point radix; and the longest
-    primes, by Bluestein's algorithm through 8192 / 4096-point FFTs) in 2D: x sweeps of
-    several waves per line, y sweeps on the transposed state."""
+    primes, by Bluestein's algorithm through 8192 / 4096-point FFTs) in 2D: Phi of a
+    smooth start, then real-time steps of white noise (x sweeps of several waves per
+    line, y sweeps on the transposed state)."""
     from paper_1601_04640_amd.binding import Solver
     for nx, ny in ((n, 12), (12, n)):
         h = 25.6 / n
@@ -144,8 +145,15 @@ def test_longest_lines(prec, n, gpu_lib):
                  g=10.0, gdd=5.0, R=0.0)
         banner("run-time-length sizes: longest line", prec, nx, ny)
         p = oparams(w)
-        psi0 = I.random_complex(p.shape(), 504, p.dV())
         s = Solver(w, prec=prec)
+        # Phi of a smooth start: its density sits where U(k) varies, so every wavenumber
+        # must land in its own slot (white noise mostly checks that the transforms invert)
+        smooth = I.gaussian("2dxy", nx, ny, 1, w["dx"], w["dy"], 1.0, widths=(1.1, 1.6),
+                            amp_noise=0.05, seed=506)
+        s.set_psi(smooth)
+        err = rel_l2(s.dipolar_potential(), O.dipolar_potential(np.abs(smooth) ** 2, p))
+        assert err <= (1e-12 if prec == "fp64" else 2e-6), (nx, ny, err)
+        psi0 = I.random_complex(p.shape(), 504, p.dV())
         s.set_psi(psi0)
         s.step_real(3)
         assert_psi_close(s.get_psi(), O.run(psi0, p, False, 3), bars(prec)[0], (nx, ny))
