@@ -157,10 +157,11 @@ Layout make_layout(const gp_params* p, unsigned host = 0) {
   L.lx = lng[0];
   L.ly = lng[1];
   GPlan lpa[2], lpb[2];
+  const int lim = fp64 ? gen_max_line<double>() : gen_max_line<float>();
   for (int a = 0; a < 2; ++a)
     if (lng[a]) {
-      gen_plan(L.lg[a].A, &lpa[a]);
-      gen_plan(L.lg[a].B, &lpb[a]);
+      gen_long_subplan(L.lg[a].A, lim / 2, &lpa[a]);
+      gen_long_subplan(L.lg[a].B, lim, &lpb[a]);
     }
   if (L.lx) {
     L.lxg = fp64 ? GLaunch<double>::lx_geom(L.n0, L.n1, L.lg[0], lpa[0], lpb[0])
@@ -890,7 +891,8 @@ struct Passes {
       const int ns3[3] = {L.n0, L.n1, L.n2};
       for (int a = 0; a < (c->p.geom == GP_3D ? 3 : 2); ++a) {
         if (lng[a]) {
-          if (!gen_plan(L.lg[a].A, &c->lplan[a][0]) || !gen_plan(L.lg[a].B, &c->lplan[a][1]))
+          if (!gen_long_subplan(L.lg[a].A, gen_max_line<T>() / 2, &c->lplan[a][0]) ||
+              !gen_long_subplan(L.lg[a].B, gen_max_line<T>(), &c->lplan[a][1]))
             return GP_E_SIZE;
         } else if (!gen_plan(ns3[a], &c->gplan[a])) {
           return GP_E_SIZE;

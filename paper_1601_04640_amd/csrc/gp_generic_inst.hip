@@ -20,11 +20,11 @@ namespace {
 constexpr int kCnLds = 163840;  // LDS limit of the CN sweeps (160 KiB)
 constexpr int kTileLds = kCnLds - 2048;  // dynamic LDS of the tile sweeps (static: 1408 B)
 
-// lines per block of a line-FFT pass: about 2048 values (contiguous lines) or as many
-// lines as 64 KiB of LDS holds (strided lines: the longest contiguous runs), halved
-// while the pass would have fewer than 512 blocks
-int lines_per_block(int n, int nlines, bool strided) {
-  const int ls = gen_stride(n);  // LDS values per line
+// lines per block of a line-FFT pass whose lines take ls values of LDS (the plan's
+// stride): about 2048 values (contiguous lines) or as many lines as 64 KiB of LDS holds
+// (strided lines: the longest contiguous runs), halved while the pass would have fewer
+// than 512 blocks
+int lines_per_block(int ls, int nlines, bool strided) {
   const int cap = gen_max_line<T>() / ls;
   int nl = strided ? cap : 2048 / ls;
   if (nl < 1) nl = 1;
@@ -259,7 +259,9 @@ hipError_t GLaunch<T>::lines(int kind, hipStream_t st, cpx<T>* data, int n, int 
   GLines g{};
   g.n = n;
   g.nlines = nlines;
-  g.nl = lines_per_block(n, nlines, se != 1);
+  g.nl = lines_per_block(p.m, nlines, se != 1);
+  // the stages hold at most kEmax values per thread of a 1024-thread block
+  if (g.nl * p.m > gen_max_line<T>() || p.n != n) return hipErrorInvalidValue;
   g.G = G;
   g.so = so;
   g.si = si;

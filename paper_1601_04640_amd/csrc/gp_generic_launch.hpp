@@ -34,6 +34,22 @@ struct GLong {
   int sn, nseg;
 };
 
+// Plan of a factor of a split axis: a factor with a prime above 7 runs Bluestein's
+// algorithm through a 2-3-5-7 length when that fits `lim` (the radix 11-31 kernels keep
+// values in scratch memory), else its own stages.
+inline bool gen_long_subplan(int n, int lim, GPlan* p) {
+  if (!gen_plan(n, p)) return false;
+  if (p->blue || gen_plan_small(*p)) return true;
+  GPlan q = *p;
+  q.m = gen_blue_len(n);
+  q.blue = 1;
+  if (q.m <= lim && gen_stages(q.m, &q)) {
+    q.fm = fdiv_make((uint32_t)q.m);
+    *p = q;
+  }
+  return true;
+}
+
 template <typename T>
 inline bool gen_long_plan(int n, GLong* lp) {
   const int lim = gen_max_line<T>();
@@ -45,7 +61,8 @@ inline bool gen_long_plan(int n, GLong* lp) {
     if (n % a) continue;
     GPlan pa, pb;
     const int b = n / a;
-    if (b >= 2 && gen_plan(a, &pa) && gen_plan(b, &pb) && 2 * pa.m <= lim && pb.m <= lim) {
+    if (b >= 2 && gen_long_subplan(a, lim / 2, &pa) && gen_long_subplan(b, lim, &pb) &&
+        2 * pa.m <= lim && pb.m <= lim) {
       lp->A = a;
       lp->B = b;
       break;

@@ -39,7 +39,8 @@ CASES = {
     "2dxy_9000x13": ("2dxy", 9000, 13, ("fp32", "fp64")),
     # long y (A 100, B 84; 20 segments of 420) in XZ
     "2dxz_10x8400": ("2dxz", 10, 8400, ("fp32", "fp64")),
-    # radices 19 and 31 in the split (A 133 = 7 19, B 62 = 2 31; 19 segments of 434)
+    # primes 19 and 31 in the split (A 133 = 7 19, B 62 = 2 31): both factors by
+    # Bluestein's algorithm (270- and 125-point stages; 19 segments of 434)
     "2dxy_8246x10": ("2dxy", 8246, 10, ("fp32",)),
     # a prime factor above 31 in the split (A 109 by Bluestein's algorithm, B 76; 19 segments
     # of 436), x and y
