@@ -187,11 +187,11 @@ Layout make_layout(const gp_params* p, unsigned host = 0) {
     L.gscr = p->geom == GP_3D
                  ? (GLaunch<float>::cn_by_columns(L.n1, true, L.n0 * L.n2) ||
                     GLaunch<float>::cn_by_columns(L.n2, true, L.n0 * L.n1))
-                 : (GLaunch<float>::y2d_transposed(L.n1) || L.lx);
-    // a long y axis: its sweep (the last in 2D) is segmented, on the transposed grid
+                 : ((GLaunch<float>::y2d_transposed(L.n1) && !L.ly) || L.lx);
+    // a long y axis: its sweep (the last in 2D) is segmented, over the strided columns
     if (L.ly)
-      L.nb_col = fp64 ? GLaunch<double>::seg_blocks(L.lg[1].sn, L.n0 * L.lg[1].nseg)
-                      : GLaunch<float>::seg_blocks(L.lg[1].sn, L.n0 * L.lg[1].nseg);
+      L.nb_col = fp64 ? GLaunch<double>::seg_blocks(L.lg[1].sn, L.n0 * L.lg[1].nseg, true)
+                      : GLaunch<float>::seg_blocks(L.lg[1].sn, L.n0 * L.lg[1].nseg, true);
   } else {
     const int tj = tj_of(fp64, L.n0);
     L.nb_x = ((L.n1 + tj - 1) / tj) * L.n2;
@@ -570,14 +570,10 @@ struct Passes {
     if (axis == 0)  // lines (j, k2), contiguous
       return dev(GLaunch<T>::cn_lines(mode, c->st, psi(c), L.n0, L.n1 * L.n2, 1, L.n0, 0, 1,
                                       f, pc, dscr));
-    if (axis == 1 && L.ly) {
-      // long y lines: segmented, along the rows of the transposed state
-      GP_HIP(GLaunch<T>::transpose(c->st, psi(c), dscr, L.n1, L.n0));
-      GP_HIP(GLaunch<T>::seg_sweep(mode, c->st, dscr, L.lg[1].sn, L.lg[1].nseg, L.n0, f,
-                                   c->at<cpx<T>>(L.o_seg[1][k]), c->at<cpx<T>>(L.o_ssum),
-                                   c->at<cpx<T>>(L.o_scar), pc));
-      return dev(GLaunch<T>::transpose(c->st, dscr, psi(c), L.n0, L.n1));
-    }
+    if (axis == 1 && L.ly)  // long y lines: segmented, in place over the strided columns
+      return dev(GLaunch<T>::seg_sweep(mode, c->st, psi(c), L.lg[1].sn, L.lg[1].nseg, L.n0, f,
+                                       c->at<cpx<T>>(L.o_seg[1][k]), c->at<cpx<T>>(L.o_ssum),
+                                       c->at<cpx<T>>(L.o_scar), pc, L.n0));
     if (axis == 1 && c->p.geom != GP_3D && GLaunch<T>::y2d_transposed(L.n1)) {
       // 2D lines longer than a tile: the sweep runs along the rows of the transposed state
       // (scratch grid, n0 rows of n1) and the result is transposed back

@@ -809,10 +809,15 @@ constexpr int tile_max_waves() { return sizeof(T) == 4 ? 16 : 8; }
 // car[4l] = C and car[4l+1] = E, with car[4l+2], car[4l+3] = psi of the rows before and
 // after the segment (values before the sweep: the neighbouring segments are rewritten by
 // other blocks).
+// Segment lines are numbered line-major, l = L nseg + s (contiguous long lines: the tile's
+// lines are consecutive segments), or segment-major, l = s nlong + L (cols: strided long
+// lines, so that a tile holds the same segment of adjacent lines; fseg then divides by
+// nlong).
 struct GSeg {
   int nseg;
   FDiv fseg;
   const void* car;
+  int cols;
 };
 
 struct GNl {  // the nonlinear sub-step's inputs for the fused x sweep
@@ -966,7 +971,8 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
   [[maybe_unused]] int sgi = 0;
   [[maybe_unused]] cpx<T> eL = zero, eR = zero, cC = zero, cE = zero;
   if constexpr (SEG) {
-    sgi = lg - (int)fdiv((uint32_t)lg, sg.fseg) * sg.nseg;
+    const int q = (int)fdiv((uint32_t)lg, sg.fseg);
+    sgi = sg.cols ? q : lg - q * sg.nseg;
     const cpx<T>* car = reinterpret_cast<const cpx<T>*>(sg.car) + 4LL * lg;
     cC = car[0];
     cE = car[1];

@@ -453,29 +453,41 @@ hipError_t GLaunch<T>::lx_c2r(hipStream_t st, const cpx<T>* spec, cpx<T>* w, T* 
 #undef GLX_LAUNCH
 
 template <>
-int GLaunch<T>::seg_lines(int sn, int nlines) {
-  // the tile sweep's lines per block (segments keep no factor line in LDS)
-  return cn_tile_lines(sn, nlines, false);
+int GLaunch<T>::seg_lines(int sn, int nlines, bool cols) {
+  // the tile sweep's lines per block (segments keep no factor line in LDS); strided
+  // segments take the strided tiles of adjacent lines
+  return cn_tile_lines(sn, nlines, cols);
 }
 
 template <>
 hipError_t GLaunch<T>::seg_sweep(int mode, hipStream_t st, cpx<T>* data, int sn, int nseg,
                                  int nlong, const cpx<T>* f, const cpx<T>* pq, cpx<T>* sum,
-                                 cpx<T>* car, double* part) {
-  if (sn > gen_max_line<T>() || nseg < 2 || nlong < 1 || (mode != 0 && mode != 1))
+                                 cpx<T>* car, double* part, long long ld) {
+  if (sn > gen_max_line<T>() || nseg < 2 || nlong < 1 || (mode != 0 && mode != 1) ||
+      (ld != 0 && ld < nlong))
     return hipErrorInvalidValue;
+  const bool cols = ld != 0;
   const int nlines = nlong * nseg;
-  const GLines g = tile_lines(sn, nlines, seg_lines(sn, nlines), 1, sn, 0, 1);
+  // contiguous: line l = L nseg + s at l sn; strided: l = s nlong + L at s sn ld + L
+  const GLines g = cols ? tile_lines(sn, nlines, seg_lines(sn, nlines, true), nlong, sn * ld,
+                                     1, ld)
+                        : tile_lines(sn, nlines, seg_lines(sn, nlines), 1, sn, 0, 1);
   const int wpl = cn_tile_wpl(sn);
   const GNl none{};
-  const GSeg sg{nseg, fdiv_make((uint32_t)nseg), car};
-  constexpr int kWavesPerBlock = kThreads / 64;
-  hipLaunchKernelGGL(k_seg_summary<T>, dim3((nlines + kWavesPerBlock - 1) / kWavesPerBlock),
-                     dim3(kThreads), 0, st, data, sum, pq + 2 * nseg, sn, nseg, sg.fseg, nlines);
+  const GSeg sg{nseg, fdiv_make((uint32_t)(cols ? nlong : nseg)), car, cols ? 1 : 0};
+  const cpx<T>* wu = pq + 2 * nseg;
+  if (cols) {
+    hipLaunchKernelGGL(k_seg_summary_cols<T>, dim3((nlines + kThreads - 1) / kThreads),
+                       dim3(kThreads), 0, st, data, sum, wu, sn, nseg, nlong, ld);
+  } else {
+    constexpr int kWavesPerBlock = kThreads / 64;
+    hipLaunchKernelGGL(k_seg_summary<T>, dim3((nlines + kWavesPerBlock - 1) / kWavesPerBlock),
+                       dim3(kThreads), 0, st, data, sum, wu, sn, nseg, sg.fseg, nlines);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_seg_carry<T>, dim3((nlong + kThreads - 1) / kThreads), dim3(kThreads), 0,
-                     st, sum, car, pq, nseg, nlong);
+                     st, sum, car, pq, nseg, nlong, cols ? 1 : 0);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (mode == 0) return launch_tile<0, -1, true>(st, data, g, wpl, f, nullptr, none, sg);

@@ -154,14 +154,16 @@ struct GLaunch {
   // solve, 1: solve with the new-state sums in part over seg_blocks blocks); f: the long
   // line's factor table, pq: the segments' carry products P, Q (2 nseg values) followed by
   // the rows' summary weights (2 per row); sum, car: 4 values per segment
-  static int seg_lines(int sn, int nlines);
-  static int seg_blocks(int sn, int nlines) {
-    const int nl = seg_lines(sn, nlines);
+  // ld = 0: contiguous long lines (line L at L nseg sn); ld > 0: strided long lines,
+  // line L at L, row r at r ld (consecutive lines adjacent), swept in place
+  static int seg_lines(int sn, int nlines, bool cols = false);
+  static int seg_blocks(int sn, int nlines, bool cols = false) {
+    const int nl = seg_lines(sn, nlines, cols);
     return (nlines + nl - 1) / nl;
   }
   static hipError_t seg_sweep(int mode, hipStream_t st, cpx<T>* data, int sn, int nseg,
                               int nlong, const cpx<T>* f, const cpx<T>* pq, cpx<T>* sum,
-                              cpx<T>* car, double* part);
+                              cpx<T>* car, double* part, long long ld = 0);
   // the nonlinear sub-step's sums of the stored state (mode MODE_OBSERVE; MODE_IMAG and
   // MODE_REAL also apply it in place), over nl_blocks blocks
   static hipError_t nonlinear(int mode, hipStream_t st, cpx<T>* psi, const T* V, const T* phi,
@@ -203,10 +205,10 @@ struct GLaunch {
   template <> hipError_t GLaunch<T>::lx_c2r(hipStream_t, const cpx<T>*, cpx<T>*, T*,         \
                                             const GLX&, const GPlan&, const GPlan&,          \
                                             const cpx<T>*, const cpx<T>*, const cpx<T>*);    \
-  template <> int GLaunch<T>::seg_lines(int, int);                                             \
+  template <> int GLaunch<T>::seg_lines(int, int, bool);                                       \
   template <> hipError_t GLaunch<T>::seg_sweep(int, hipStream_t, cpx<T>*, int, int, int,      \
                                                const cpx<T>*, const cpx<T>*, cpx<T>*,         \
-                                               cpx<T>*, double*);                              \
+                                               cpx<T>*, double*, long long);                   \
   template <> hipError_t GLaunch<T>::nonlinear(int, hipStream_t, cpx<T>*, const T*, const T*, \
                                                const double*, const GStep&, int, int, int,    \
                                                double*);                                       \

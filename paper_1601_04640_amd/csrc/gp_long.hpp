@@ -355,31 +355,89 @@ __global__ void __launch_bounds__(kThreads) k_seg_summary(const cpx<T>* __restri
   }
 }
 
-// Carries along each long line (one thread per line of nseg segments, segment lines
-// l = L nseg + s): C_0 = 0, C_(s+1) = P_s C_s + d0_s; E_nseg = 0, E_s = e0_s + Q_s C_s +
-// P_s E_(s+1); car[4l ..] = C_s, E_(s+1), psi before the segment, psi after it.
+// The same summaries for strided long lines (segment-major numbering l = s nlong + L, row
+// r of line L at L + r ld): one thread per segment line walking its rows, adjacent
+// threads on adjacent lines (coalesced).
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_seg_summary_cols(const cpx<T>* __restrict__ data,
+                                                               cpx<T>* __restrict__ sum,
+                                                               const cpx<T>* __restrict__ wu,
+                                                               int sn, int nseg, int nlong,
+                                                               long long ld) {
+  constexpr int U = 8;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= nseg * nlong) return;
+  const int s = gid / nlong, L = gid - s * nlong;
+  const int r0 = s * sn;
+  const long long base = (long long)L + (long long)r0 * ld;
+  // rows r0 - 1 and r0 (the long line's row -1 is none); in-range loads, values selected
+  // afterwards, real and imaginary parts apart (no arrays of the aligned pair type)
+  const cpx<T> first = data[base];
+  const cpx<T> before = data[s > 0 ? base - ld : base];
+  cpx<T> pm{s > 0 ? before.re : (T)0, s > 0 ? before.im : (T)0}, pc = first;
+  T wr = 0, wi = 0, ur = 0, ui = 0;
+  const int N = nseg * sn;
+  for (int e0 = 0; e0 < sn; e0 += U) {
+    T nr[U], ni[U];
+    bool ok[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = r0 + e0 + u + 1;  // the next row of each of the U rows
+      ok[u] = e0 + u < sn && r < N;
+      const cpx<T> v = data[ok[u] ? base + (long long)(e0 + u + 1) * ld : base];
+      nr[u] = v.re;
+      ni[u] = v.im;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (e0 + u < sn) {
+        const int r = r0 + e0 + u;
+        const cpx<T> nxu{ok[u] ? nr[u] : (T)0, ok[u] ? ni[u] : (T)0};
+        const cpx<T> dl = (pm + nxu) - (pc + pc);
+        const cpx<T> w = wu[2LL * r], uu = wu[2LL * r + 1];
+        wr += w.re * dl.re - w.im * dl.im;
+        wi += w.re * dl.im + w.im * dl.re;
+        ur += uu.re * dl.re - uu.im * dl.im;
+        ui += uu.re * dl.im + uu.im * dl.re;
+        pm = pc;
+        pc = nxu;
+      }
+    }
+  }
+  sum[4LL * gid] = cpx<T>{wr, wi};
+  sum[4LL * gid + 1] = cpx<T>{ur, ui};
+  sum[4LL * gid + 2] = first;
+  sum[4LL * gid + 3] = data[base + (long long)(sn - 1) * ld];
+}
+
+// Carries along each long line (one thread per line of nseg segments; segment lines
+// l = L nseg + s, or s nlong + L with cols): C_0 = 0, C_(s+1) = P_s C_s + d0_s;
+// E_nseg = 0, E_s = e0_s + Q_s C_s + P_s E_(s+1); car[4l ..] = C_s, E_(s+1), psi before the
+// segment, psi after it.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_seg_carry(const cpx<T>* __restrict__ sum,
                                                         cpx<T>* __restrict__ car,
                                                         const cpx<T>* __restrict__ pq,
-                                                        int nseg, int nlong) {
+                                                        int nseg, int nlong, int cols) {
   const int L = blockIdx.x * blockDim.x + threadIdx.x;
   if (L >= nlong) return;
-  const long long l0 = (long long)L * nseg;
+  // segment s of line L: l0 + s dl
+  const long long l0 = cols ? (long long)L : (long long)L * nseg;
+  const long long dl = cols ? (long long)nlong : 1;
   cpx<T> C{0, 0};
   for (int s = 0; s < nseg; ++s) {
-    const long long l = l0 + s;
+    const long long l = l0 + s * dl;
     car[4 * l] = C;
     // in-range loads, values selected afterwards
-    const cpx<T> before = sum[4 * (s > 0 ? l - 1 : l) + 3];
-    const cpx<T> after = sum[4 * (s + 1 < nseg ? l + 1 : l) + 2];
+    const cpx<T> before = sum[4 * (s > 0 ? l - dl : l) + 3];
+    const cpx<T> after = sum[4 * (s + 1 < nseg ? l + dl : l) + 2];
     car[4 * l + 2] = cpx<T>{s > 0 ? before.re : (T)0, s > 0 ? before.im : (T)0};
     car[4 * l + 3] = cpx<T>{s + 1 < nseg ? after.re : (T)0, s + 1 < nseg ? after.im : (T)0};
     C = pq[2 * s] * C + sum[4 * l];
   }
   cpx<T> E{0, 0};
   for (int s = nseg - 1; s >= 0; --s) {
-    const long long l = l0 + s;
+    const long long l = l0 + s * dl;
     car[4 * l + 1] = E;
     E = sum[4 * l + 1] + pq[2 * s + 1] * car[4 * l] + pq[2 * s] * E;
   }
