@@ -78,8 +78,10 @@ struct Layout {
   // one-thread-per-line sweeps need a grid of scratch values (o_gscr)
   bool generic, gscr;
   // 2D axes longer than one LDS line (x, y): four-step FFT and segmented sweeps; the
-  // intermediate grid of the x transforms and the transposed y sweep use o_gscr
-  bool lx, ly;
+  // intermediate grid of the x transforms uses o_gscr.  sy: the 2D y sweep runs in
+  // segments over the strided columns (a long y axis, or one-line y axes past a tile
+  // with a segment length dividing them; others run on a transposed copy in o_gscr)
+  bool lx, ly, sy;
   GLong lg[2];
   GLX lxg;  // the long-x passes' geometry (host side; the plans' strides from lg)
   // byte offsets inside the workspace
@@ -156,6 +158,18 @@ Layout make_layout(const gp_params* p, unsigned host = 0) {
                   : gen_long_plan<float>(ns0[a], &L.lg[a]);
   L.lx = lng[0];
   L.ly = lng[1];
+  // one-line y axes past a tile: segmented when there are enough column segments to fill
+  // the GPU (the summary walks each with one thread; fewer ran slower than the transposed
+  // sweep: 1500^2 FP32 0.12 -> 0.22 ms, while 8192^2 went 3.07 -> 2.75 ms)
+  if (!L.ly && p->geom != GP_3D && L.generic && L.n1 > kTileMaxN) {
+    GLong sg{};
+    if (gen_seg_split(L.n1, &sg.sn, &sg.nseg) &&
+        (long long)L.n0 * sg.nseg >= (fp64 ? 16384 : 40960)) {
+      L.lg[1] = sg;
+      L.sy = true;
+    }
+  }
+  L.sy = L.sy || L.ly;
   GPlan lpa[2], lpb[2];
   const int lim = fp64 ? gen_max_line<double>() : gen_max_line<float>();
   for (int a = 0; a < 2; ++a)
@@ -187,9 +201,9 @@ Layout make_layout(const gp_params* p, unsigned host = 0) {
     L.gscr = p->geom == GP_3D
                  ? (GLaunch<float>::cn_by_columns(L.n1, true, L.n0 * L.n2) ||
                     GLaunch<float>::cn_by_columns(L.n2, true, L.n0 * L.n1))
-                 : ((GLaunch<float>::y2d_transposed(L.n1) && !L.ly) || L.lx);
-    // a long y axis: its sweep (the last in 2D) is segmented, over the strided columns
-    if (L.ly)
+                 : ((GLaunch<float>::y2d_transposed(L.n1) && !L.sy) || L.lx);
+    // a segmented y sweep (the last in 2D) runs over the strided columns
+    if (L.sy)
       L.nb_col = fp64 ? GLaunch<double>::seg_blocks(L.lg[1].sn, L.n0 * L.lg[1].nseg, true)
                       : GLaunch<float>::seg_blocks(L.lg[1].sn, L.n0 * L.lg[1].nseg, true);
   } else {
@@ -260,9 +274,10 @@ Layout make_layout(const gp_params* p, unsigned host = 0) {
     }
     L.o_ltw[a][2] = take(lng[a] ? 2 * L.esz * ns0[a] : 0);
     // per factor set: P, Q of each segment, then the summary weights w, u of each row
+    const bool seg = a == 0 ? L.lx : L.sy;  // this axis's sweep runs in segments
     for (int t = 0; t < 3; ++t)
-      L.o_seg[a][t] = take(lng[a] ? 4 * L.esz * ((size_t)L.lg[a].nseg + ns0[a]) : 0);
-    if (lng[a]) nsegl = std::max(nsegl, (size_t)ns0[1 - a] * L.lg[a].nseg);
+      L.o_seg[a][t] = take(seg ? 4 * L.esz * ((size_t)L.lg[a].nseg + ns0[a]) : 0);
+    if (seg) nsegl = std::max(nsegl, (size_t)ns0[1 - a] * L.lg[a].nseg);
   }
   L.o_ssum = take(8 * L.esz * nsegl);
   L.o_scar = take(8 * L.esz * nsegl);
@@ -570,7 +585,7 @@ struct Passes {
     if (axis == 0)  // lines (j, k2), contiguous
       return dev(GLaunch<T>::cn_lines(mode, c->st, psi(c), L.n0, L.n1 * L.n2, 1, L.n0, 0, 1,
                                       f, pc, dscr));
-    if (axis == 1 && L.ly)  // long y lines: segmented, in place over the strided columns
+    if (axis == 1 && L.sy)  // segmented, in place over the strided columns
       return dev(GLaunch<T>::seg_sweep(mode, c->st, psi(c), L.lg[1].sn, L.lg[1].nseg, L.n0, f,
                                        c->at<cpx<T>>(L.o_seg[1][k]), c->at<cpx<T>>(L.o_ssum),
                                        c->at<cpx<T>>(L.o_scar), pc, L.n0));
@@ -932,7 +947,7 @@ struct Passes {
       hipLaunchKernelGGL(k_cn_tables<T>, dim3(1), dim3(64), 0, c->st,
                          c->at<cpx<T>>(L.o_cn[a][0]), c->at<cpx<T>>(L.o_cn[a][1]),
                          c->at<cpx<T>>(L.o_cn[a][2]), ns[a], Ar, P);
-      if (lng[a]) {  // the segments' carry products of each factor set
+      if (a == 0 ? L.lx : (a == 1 && L.sy)) {  // the segments' fixed numbers per factor set
         for (int t = 0; t < 3; ++t)
           hipLaunchKernelGGL(k_seg_tables<T>, dim3(blocks_for(L.lg[a].nseg)), dim3(kThreads), 0,
                              c->st, c->at<cpx<T>>(L.o_cn[a][t]), L.lg[a].sn, L.lg[a].nseg,

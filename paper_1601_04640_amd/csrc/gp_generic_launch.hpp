@@ -50,6 +50,19 @@ inline bool gen_long_subplan(int n, int lim, GPlan* p) {
   return true;
 }
 
+// Crank-Nicolson segments of a line: the largest divisor of n from 64 to 512 with at
+// least two segments (one wave per segment, at most 8 rows per lane).
+inline bool gen_seg_split(int n, int* sn, int* nseg) {
+  for (int s = 512; s >= 64; --s) {
+    if (n % s == 0 && n / s >= 2) {
+      *sn = s;
+      *nseg = n / s;
+      return true;
+    }
+  }
+  return false;
+}
+
 template <typename T>
 inline bool gen_long_plan(int n, GLong* lp) {
   const int lim = gen_max_line<T>();
@@ -69,13 +82,12 @@ inline bool gen_long_plan(int n, GLong* lp) {
     }
   }
   if (lp->A == 0) return false;
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int s = pass == 0 ? 512 : lim; s >= 64; --s) {
-      if (n % s == 0 && n / s >= 2) {
-        lp->sn = s;
-        lp->nseg = n / s;
-        return true;
-      }
+  if (gen_seg_split(n, &lp->sn, &lp->nseg)) return true;
+  for (int s = lim; s >= 64; --s) {
+    if (n % s == 0 && n / s >= 2) {
+      lp->sn = s;
+      lp->nseg = n / s;
+      return true;
     }
   }
   return false;

@@ -180,3 +180,31 @@ def test_full_size_15000_plane_waves(gpu_lib):
     norms = [r["norm"] for r in s.history(4)]
     assert all(abs(v - norms[0]) <= 1e-5 * norms[0] for v in norms), norms
     s.close()
+
+
+@pytest.mark.parametrize("prec,geom,n0,n1", [("fp32", "2dxy", 2560, 8192),
+                                             ("fp64", "2dxz", 2048, 4000)])
+def test_segmented_y_sweep_of_one_line_axes(prec, geom, n0, n1, gpu_lib):
+    """A y axis that one LDS line holds but a tile does not (8192 = 16 x 512, FP32;
+    4000 = 8 x 500, FP64), with enough columns for the segmented sweep in place over the
+    strided columns (n0 x segments >= 40960 FP32 / 16384 FP64) instead of the transposed
+    state: Phi, then imaginary and real steps against the oracle."""
+    from paper_1601_04640_amd.binding import Solver
+    assert B.gp_axis_kind(n1, prec) == 2
+    w = grid(geom, n0, n1)
+    banner("segmented y of a one-line axis", prec, geom, n0, n1)
+    p = oparams(w)
+    ptol, etol = bars(prec)
+    psi0 = smooth_start(w, 614)
+    for imag in (True, False):
+        s = Solver(w, prec=prec)
+        s.set_psi(psi0)
+        if imag:
+            err = rel_l2(s.dipolar_potential(), O.dipolar_potential(np.abs(psi0) ** 2, p))
+            assert err <= (1e-12 if prec == "fp64" else 2e-6), err
+        s.step_imag(2) if imag else s.step_real(2)
+        ref, hist = O.run(psi0, p, imag, 2, record=True)
+        assert_psi_close(s.get_psi(), ref, ptol, imag)
+        for k, (g_, r_) in enumerate(zip(s.history(2), hist)):
+            assert not obs_close(g_, r_, etol), (imag, k)
+        s.close()
