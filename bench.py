@@ -188,7 +188,8 @@ def time_gpu(workload, prec, psi_start, steps, warmup, solver_params=None, host=
     # the start state is kept on the device: resetting it between runs is a device copy,
     # so the GPU does not sit idle (and clock down) behind a host transfer just before a
     # timed region
-    psi_dev = torch.from_numpy(psi_start).to(s.device, s.cdtype)
+    psi_dev = (psi_start.to(s.device, s.cdtype) if torch.is_tensor(psi_start)
+               else torch.from_numpy(psi_start).to(s.device, s.cdtype))
     s.set_psi(psi_dev)
     s.step_real(max(warmup, GRAPH_STEPS + 1))
     s.set_psi(psi_dev)
@@ -492,10 +493,12 @@ def adjoint_2d_256(nsteps=400, K=50):
 
 
 # ---------------------------------------------------------------------- sweep
+# to the paper's 600^3 and 15000^2, then to the largest grids the run-time-length passes
+# address (fewer than 2^31 points: 1280^3, 46000^2)
 SWEEP3 = (48, 50, 64, 80, 96, 100, 120, 128, 150, 160, 192, 200, 240, 250, 256, 300, 320, 360,
-          384, 400, 450, 480, 500, 512, 540, 600)
+          384, 400, 450, 480, 500, 512, 540, 600, 700, 800, 1000, 1280)
 SWEEP2 = (256, 384, 512, 1000, 1024, 1500, 2000, 2048, 3000, 4000, 4096, 5000, 6000, 8000, 8192,
-          10000, 12000, 13000, 15000)
+          10000, 12000, 13000, 15000, 20000, 30000, 40000, 46000)
 PASSES = {1: "specialised", 2: "run-time length", 3: "four-step, segmented"}
 
 
@@ -506,15 +509,16 @@ def sweep(args):
     graph-replayed.  Lengths with specialised passes report the dominant pass's HBM
     fraction; the run-time-length kernels (other lengths) report null there.  2D squares
     past one LDS line (8192 FP32, 4096 FP64) run the four-step transforms and segmented
-    sweeps, up to the paper's 15000^2."""
-    import numpy as np
+    sweeps.  Past the paper's 600^3 and 15000^2 the sweep goes on to the largest grids the
+    run-time-length passes address (1280^3, 46000^2), as far as the GPU's memory holds
+    them."""
     import torch
     from paper_1601_04640_amd import binding as B
     cases = []
     if 3 in args.sweep_dims:
-        cases += [("3d", n) for n in SWEEP3 if n <= args.sweep_max3]
+        cases += [("3d", n) for n in SWEEP3 if args.sweep_min <= n <= args.sweep_max3]
     if 2 in args.sweep_dims:
-        cases += [("2dxy", n) for n in SWEEP2 if n <= args.sweep_max2]
+        cases += [("2dxy", n) for n in SWEEP2 if args.sweep_min <= n <= args.sweep_max2]
     for geom, n in cases:
         for prec in args.sweep_prec:
             esz = 8 if prec == "fp64" else 4
@@ -525,20 +529,25 @@ def sweep(args):
             w = dict(geom=geom, nx=n, ny=n, nz=n if geom == "3d" else 1, dx=h, dy=h, dz=h,
                      dt=0.0005, gamma=1.0, nu=1.0, lam=2.0 if geom == "3d" else 4.0, g=20.0,
                      gdd=6.0, R=6.4 if geom == "3d" else 0.0)
+            npts = n ** (3 if geom == "3d" else 2)
             need = B.gp_workspace_bytes(B.make_params(**{**w, "prec": prec}))
-            if need > 0.8 * torch.cuda.mem_get_info()[0]:
+            if need + 4 * esz * npts > 0.85 * torch.cuda.mem_get_info()[0]:
                 continue
-            x = ((np.arange(n) - n // 2) * h).astype(np.float64)
-            g1 = np.exp(-0.5 * x * x)
+            # the separable Gaussian start, built on the device in the step's precision and
+            # normalised from its factors (no host grid for the largest cases)
+            rd = torch.float64 if prec == "fp64" else torch.float32
+            x = (torch.arange(n, dtype=torch.float64, device="cuda") - n // 2) * h
+            g1 = torch.exp(-0.5 * x * x)
             g1[0] = g1[-1] = 0.0
             if geom == "3d":
-                gz = np.exp(-0.5 * 2.0 * x * x)
+                gz = torch.exp(-0.5 * 2.0 * x * x)
                 gz[0] = gz[-1] = 0.0
-                psi = (gz[:, None, None] * g1[None, :, None] * g1[None, None, :]).astype(np.complex128)
+                norm = torch.sqrt((gz * gz).sum() * (g1 * g1).sum() ** 2 * h ** 3)
+                gz, g1 = (gz / norm).to(rd), g1.to(rd)
+                psi = (gz[:, None, None] * g1[None, :, None]) * g1[None, None, :]
             else:
-                psi = (g1[:, None] * g1[None, :]).astype(np.complex128)
-            psi /= np.sqrt(np.sum(np.abs(psi) ** 2) * h ** (3 if geom == "3d" else 2))
-            npts = psi.size
+                norm = torch.sqrt((g1 * g1).sum() ** 2 * h ** 2)
+                psi = (g1 / norm).to(rd)[:, None] * g1.to(rd)[None, :]
             steps = max(GRAPH_STEPS, min(400, int(2e9 / npts) // GRAPH_STEPS * GRAPH_STEPS))
             r = time_gpu(None, prec, psi, steps, GRAPH_STEPS + 1, solver_params=w)
             wall = r["graph"]["wall"]
@@ -551,7 +560,7 @@ def sweep(args):
                     "step_hbm_frac": round(byts / (wall / steps) / 1e9 / HBM_PEAK_GBS, 4),
                     "dominant_kernel_frac": roofline(r, esz)["frac"] if kind == 1 else None}
             print(json.dumps(line), flush=True)
-            del psi
+            del psi, x, g1
             torch.cuda.empty_cache()
 
 
@@ -571,8 +580,9 @@ def main():
     ap.add_argument("--sweep", action="store_true", help="throughput against grid size")
     ap.add_argument("--sweep-dims", type=int, nargs="*", default=[3, 2])
     ap.add_argument("--sweep-prec", nargs="*", default=["fp32", "fp64"])
-    ap.add_argument("--sweep-max3", type=int, default=600)
-    ap.add_argument("--sweep-max2", type=int, default=16384)
+    ap.add_argument("--sweep-max3", type=int, default=1280)
+    ap.add_argument("--sweep-max2", type=int, default=46000)
+    ap.add_argument("--sweep-min", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); sharding "

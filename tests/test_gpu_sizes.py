@@ -258,3 +258,34 @@ def test_long_lines_3d(shape, prec, gpu_lib):
             bad = obs_close(g_, r_, etol)
             assert not bad, (shape, imag, k, bad)
         s.close()
+
+
+@pytest.mark.parametrize("prec,shape", [("fp64", (64, 1100, 512)), ("fp32", (64, 512, 1100))])
+def test_long_lines_3d_by_columns(prec, shape, gpu_lib):
+    """3D y or z lines longer than 1024 points with at least 32768 of them (64 x 512): the
+    sweep runs one thread per line with the forward values in the scratch grid
+    (kg_cn_cols); 1100 = 2^2 5^2 11.  Phi of a smooth start, then an imaginary and a
+    real step against the oracle, with the record and the energy of the new state (the
+    observables' z sums run the same kernel)."""
+    from paper_1601_04640_amd.binding import Solver
+    nx, ny, nz = shape
+    h = {a: 12.0 / n for a, n in zip("xyz", shape)}
+    w = dict(geom="3d", nx=nx, ny=ny, nz=nz, dx=h["x"], dy=h["y"], dz=h["z"], dt=0.001,
+             gamma=1.0, nu=1.2, lam=1.5, g=15.0, gdd=5.0, R=2.0)
+    banner("run-time-length sizes: 3D long lines by columns", shape, prec)
+    p = oparams(w)
+    psi0 = I.gaussian("3d", nx, ny, nz, h["x"], h["y"], h["z"], widths=(1.2, 1.0, 0.9),
+                      amp_noise=0.05, phase_noise=0.02, seed=508)
+    ptol, etol = bars(prec)
+    for imag in (True, False):
+        s = Solver(w, prec=prec)
+        s.set_psi(psi0)
+        if imag:
+            err = rel_l2(s.dipolar_potential(), O.dipolar_potential(np.abs(psi0) ** 2, p))
+            assert err <= (1e-12 if prec == "fp64" else 2e-6), err
+        s.step_imag(1) if imag else s.step_real(1)
+        ref, hist = O.run(psi0, p, imag, 1, record=True)
+        assert_psi_close(s.get_psi(), ref, ptol, (shape, imag))
+        assert not obs_close(s.history(1)[0], hist[0], etol), (shape, imag)
+        assert not obs_close(s.energy(), O.observables(ref, p), etol), (shape, imag)
+        s.close()
