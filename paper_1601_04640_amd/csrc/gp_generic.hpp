@@ -829,7 +829,17 @@ struct GNl {  // the nonlinear sub-step's inputs for the fused x sweep
   double* part;
 };
 
-template <typename T, int MODE, int NLM, int TS, bool SEG = false>
+// LDS writes of a wave made visible to the wave's other lanes (no block barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// WI (contiguous lines, one wave per line): each wave loads, solves and stores its own
+// line, lanes along it (coalesced), with the factor rows read from global memory, so the
+// waves of a block run independently up to the final reduction of the sums.
+template <typename T, int MODE, int NLM, int TS, bool SEG = false, bool WI = false>
 __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* __restrict__ data,
                                                                 GLines g, int wpl, FDiv fs,
                                                                 const cpx<T>* __restrict__ f,
@@ -858,7 +868,7 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
   if constexpr (NLM >= 0) ts = (T)(*nlz.scale);
   // the factor table's first UF nt values are loaded with the tile and stored after it
   cpx<T> fpre[UF];
-  if constexpr (MODE != 2 && !SEG) {
+  if constexpr (MODE != 2 && !SEG && !WI) {
 #pragma unroll
     for (int u = 0; u < UF; ++u) {
       const int t = threadIdx.x + u * nt;
@@ -872,16 +882,25 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
   const int sl = threadIdx.x % g.nl, se0 = threadIdx.x / g.nl, sstep = nt / g.nl;
   const long long sbase = !packed && sl < nl ? g.addr(l0 + sl, 0) : 0;
   const long long pbase = (long long)l0 * N;
-  for (int t0 = threadIdx.x, r0 = 0; t0 < tot; t0 += U * nt, r0 += U) {
+  // WI: wave wv walks its own line wv, lanes 64 apart
+  const int wv = threadIdx.x >> 6;
+  const int tstart = WI ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
+  const int tstep = WI ? 64 : nt;
+  const int tlim = WI ? N : tot;
+  for (int t0 = tstart, r0 = 0; t0 < tlim; t0 += U * tstep, r0 += U) {
     T vr[U], vi[U];
     [[maybe_unused]] T vv[U], ph[U];
     int at[U], ee[U], ll[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int t = t0 + u * nt;
+      const int t = t0 + u * tstep;
       int line, e;
       long long a;
-      if (packed) {
+      if (WI) {
+        line = wv;
+        e = t;
+        a = pbase + (long long)line * N + t;
+      } else if (packed) {
         line = (int)fdiv((uint32_t)t, g.fn);
         e = t - line * N;
         a = pbase + t;
@@ -891,7 +910,7 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
         a = sbase + (long long)e * g.se;
       }
       const int c = (int)fdiv((uint32_t)e, fs);
-      at[u] = (t < tot && line < nl) ? line * LS + c * Sp + (e - c * S) : -1;
+      at[u] = (t < tlim && line < nl) ? line * LS + c * Sp + (e - c * S) : -1;
       ee[u] = e;
       ll[u] = l0 + line;
       if (at[u] < 0) a = 0;  // in range only
@@ -937,9 +956,9 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
       ps[at[u]] = v;
     }
   }
-  // segments read their factor rows from global memory (each lane its chunk's S rows,
-  // contiguous; the table is small and stays in L2), not through LDS
-  if constexpr (MODE != 2 && !SEG) {
+  // segments and WI tiles read their factor rows from global memory (each lane its
+  // chunk's S rows, contiguous; the table is small and stays in L2), not through LDS
+  if constexpr (MODE != 2 && !SEG && !WI) {
 #pragma unroll
     for (int u = 0; u < UF; ++u) {
       const int t = threadIdx.x + u * nt;
@@ -953,7 +972,7 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
       fl[c * Sp + (t - c * S)] = f[t];
     }
   }
-  __syncthreads();
+  if constexpr (WI) wave_sync(); else __syncthreads();
   // wave w works on line w / wpl, lanes q = 64 (w mod wpl) + lane of it
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int line = wave / wpl, sub = wave - line * wpl;
@@ -980,7 +999,8 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
     eR = car[3];
   }
   if constexpr (MODE != 2) {
-    const cpx<T>* fq = SEG ? f + (long long)sgi * N + (cnt > 0 ? i0 : 0) : fl + slot;
+    const cpx<T>* fq =
+        (SEG || WI) ? f + (long long)sgi * N + (cnt > 0 ? i0 : 0) : fl + slot;
     // forward, zero carry: local d and the chunk's product of g
     cpx<T> acc = zero, prod = {1, 0};
     cpx<T> pm = p[q > 0 && cnt > 0 ? -Sp + S - 1 : 0];   // row i0 - 1
@@ -1076,7 +1096,7 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
     // sums of u (or of the stored state): |u|^2 and the differences, the last one with
     // the next chunk's first row (the next lane's, or the next wave's lane 0 through LDS;
     // after a segment's last row: the next segment's first, psi + e there)
-    __syncthreads();
+    if constexpr (WI) wave_sync(); else __syncthreads();
     cpx<T> unext = shfl_down_c(d[0], 1);
     if (lane == 63 && cnt > 0 && i0 + cnt < N) unext = p[Sp];
     cpx<T> prev = zero;
@@ -1107,7 +1127,15 @@ __global__ void __launch_bounds__(64 * tile_max_waves<T>()) kg_cn_tile(cpx<T>* _
       for (int k = 0; k < 7; ++k) nlz.part[7 * (long long)blockIdx.x + k] = q7[k];
     }
   }
-  if constexpr (MODE != 2) {
+  if constexpr (MODE != 2 && WI) {
+    wave_sync();
+    if (wv < nl) {
+      for (int t = (int)(threadIdx.x & 63); t < N; t += 64) {
+        const int c = (int)fdiv((uint32_t)t, fs);
+        data[pbase + (long long)wv * N + t] = ps[wv * LS + c * Sp + (t - c * S)];
+      }
+    }
+  } else if constexpr (MODE != 2) {
     __syncthreads();
     for (int t = threadIdx.x, r = 0; t < tot; t += nt, ++r) {
       int ln, e;

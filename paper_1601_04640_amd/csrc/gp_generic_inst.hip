@@ -80,20 +80,20 @@ hipError_t GLaunch<T>::prepare() {
   }
   // the tile sweeps: up to 16 padded lines (or one line of 8192 FP32 / 4096 FP64 points)
   // and the factor table, beside the static reduction and scan space
-  const void* kt[] = {reinterpret_cast<const void*>(&kg_cn_tile<T, 0, -1, 8>),
-                      reinterpret_cast<const void*>(&kg_cn_tile<T, 1, -1, 8>),
-                      reinterpret_cast<const void*>(&kg_cn_tile<T, 2, -1, 8>),
-                      reinterpret_cast<const void*>(&kg_cn_tile<T, 0, MODE_IMAG, 8>),
-                      reinterpret_cast<const void*>(&kg_cn_tile<T, 0, MODE_REAL, 8>),
-                      reinterpret_cast<const void*>(&kg_cn_tile<T, 0, -1, kTileS>),
-                      reinterpret_cast<const void*>(&kg_cn_tile<T, 1, -1, kTileS>),
-                      reinterpret_cast<const void*>(&kg_cn_tile<T, 2, -1, kTileS>),
-                      reinterpret_cast<const void*>(&kg_cn_tile<T, 0, MODE_IMAG, kTileS>),
-                      reinterpret_cast<const void*>(&kg_cn_tile<T, 0, MODE_REAL, kTileS>),
-                      reinterpret_cast<const void*>(&kg_cn_tile<T, 0, -1, 8, true>),
-                      reinterpret_cast<const void*>(&kg_cn_tile<T, 1, -1, 8, true>),
-                      reinterpret_cast<const void*>(&kg_cn_tile<T, 0, -1, kTileS, true>),
-                      reinterpret_cast<const void*>(&kg_cn_tile<T, 1, -1, kTileS, true>)};
+#define GP_TILE_K(M, NL, TSV, SG, WIV) reinterpret_cast<const void*>(&kg_cn_tile<T, M, NL, TSV, SG, WIV>)
+#define GP_TILE_TS(M, NL, SG, WIV) GP_TILE_K(M, NL, 8, SG, WIV), GP_TILE_K(M, NL, kTileS, SG, WIV)
+#define GP_TILE_ALL(WIV)                                                                    \
+  GP_TILE_TS(0, -1, false, WIV), GP_TILE_TS(1, -1, false, WIV), GP_TILE_TS(2, -1, false, WIV), \
+      GP_TILE_TS(0, MODE_IMAG, false, WIV), GP_TILE_TS(0, MODE_REAL, false, WIV),           \
+      GP_TILE_TS(0, -1, true, WIV), GP_TILE_TS(1, -1, true, WIV)
+  const void* kt[] = {GP_TILE_ALL(false), GP_TILE_K(0, -1, kTileS, false, true),
+                      GP_TILE_K(1, -1, kTileS, false, true), GP_TILE_K(2, -1, kTileS, false, true),
+                      GP_TILE_K(0, MODE_IMAG, kTileS, false, true),
+                      GP_TILE_K(0, MODE_REAL, kTileS, false, true),
+                      GP_TILE_K(0, -1, kTileS, true, true), GP_TILE_K(1, -1, kTileS, true, true)};
+#undef GP_TILE_ALL
+#undef GP_TILE_TS
+#undef GP_TILE_K
   for (const void* k : kt) {
     const hipError_t e =
         hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kTileLds);
@@ -153,24 +153,33 @@ int GLaunch<T>::cn_tile_lines(int n, int nlines, bool strided) {
 namespace {
 constexpr int kTransTile = 32;  // transpose tiles of 32 x 32 values, 256 threads
 
-// SEG: segments of long lines (each line its own factor rows in LDS)
+// SEG: segments of long lines (factor rows from global memory).  Contiguous FP64 lines
+// of one wave with more than 8 rows per lane run the wave-independent variant (WI: no
+// factor line in LDS either; it frees registers of the 16-row bodies: 600^3 FP64 step
+// 16.1 -> 14.4 ms, while FP32 and the 8-row bodies ran 2-5 % slower with it).
 template <int MODE, int NLM, bool SEG = false>
 hipError_t launch_tile(hipStream_t st, cpx<T>* data, const GLines& g, int wpl,
                        const cpx<T>* f, double* part, const GNl& nlz, const GSeg& sg = GSeg{}) {
   const int blocks = (g.nlines + g.nl - 1) / g.nl;
   const int S = (g.n + 64 * wpl - 1) / (64 * wpl);
-  const size_t lds = lds_of((SEG ? g.nl : g.nl + 1) * cn_line_slots(g.n, 64 * wpl));
+  const bool wi =
+      sizeof(T) == 8 && S > 8 && wpl == 1 && g.G == 1 && g.se == 1 && g.so == g.n;
+  const size_t lds = lds_of((SEG || wi ? g.nl : g.nl + 1) * cn_line_slots(g.n, 64 * wpl));
   if (lds > (size_t)kTileLds || g.nl * wpl > tile_max_waves<T>() || S > kTileS)
     return hipErrorInvalidValue;
   const FDiv fs = fdiv_make((uint32_t)S);
   const dim3 threads(64 * wpl * g.nl);
   // at most 8 rows per lane: fewer registers
+#define GP_TILE(TSV, WIV)                                                                   \
+  hipLaunchKernelGGL((kg_cn_tile<T, MODE, NLM, TSV, SEG, WIV>), dim3(blocks), threads, lds, st, \
+                     data, g, wpl, fs, f, part, nlz, sg)
   if (S <= 8)
-    hipLaunchKernelGGL((kg_cn_tile<T, MODE, NLM, 8, SEG>), dim3(blocks), threads, lds, st, data,
-                       g, wpl, fs, f, part, nlz, sg);
+    GP_TILE(8, false);
+  else if (wi)
+    GP_TILE(kTileS, true);
   else
-    hipLaunchKernelGGL((kg_cn_tile<T, MODE, NLM, kTileS, SEG>), dim3(blocks), threads, lds, st,
-                       data, g, wpl, fs, f, part, nlz, sg);
+    GP_TILE(kTileS, false);
+#undef GP_TILE
   return hipGetLastError();
 }
 
