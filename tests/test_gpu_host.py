@@ -22,6 +22,12 @@ CASES = {
     # run-time-length axes
     "3d_50x54x36": dict(geom="3d", nx=50, ny=54, nz=36, dx=0.3, dy=0.28, dz=0.4, dt=0.002,
                         gamma=1.0, nu=1.2, lam=2.0, g=25.0, gdd=8.0, R=4.0),
+    # 2D axes past one LDS line (four-step transforms, segmented sweeps): the kernel table
+    # in the spectrum's slot order, read from host memory
+    "2dxy_9000x12": dict(geom="2dxy", nx=9000, ny=12, nz=1, dx=25.6 / 9000, dy=0.5, dz=1.0,
+                         dt=0.0005, gamma=1.0, nu=1.0, lam=4.0, g=10.0, gdd=5.0, R=0.0),
+    "2dxz_10x8400": dict(geom="2dxz", nx=10, ny=1, nz=8400, dx=0.5, dy=1.0, dz=25.6 / 8400,
+                         dt=0.0005, gamma=1.0, nu=4.0, lam=1.0, g=10.0, gdd=5.0, R=0.0),
 }
 
 

@@ -21,6 +21,12 @@ CASES = {
                         gamma=1.0, nu=1.3, lam=2.0, g=15.0, gdd=5.0, R=3.5),
     "2dxz_40x48": dict(geom="2dxz", nx=40, ny=1, nz=48, dx=0.3, dy=1.0, dz=0.25, dt=0.002,
                        gamma=1.0, nu=4.0, lam=1.5, g=12.0, gdd=8.0, R=0.0),
+    # an x axis past one LDS line (four-step transforms, segmented sweeps), on a 256-wide
+    # box: at the spacing of a 25.6-wide box (2.8e-3) FP32 energies sit at the 1e-6 bar on
+    # one-line grids too (the kinetic differences subtract neighbours that agree to three
+    # digits), and this test is about the hand-off
+    "2dxy_9000x12": dict(geom="2dxy", nx=9000, ny=12, nz=1, dx=256.0 / 9000, dy=0.5, dz=1.0,
+                         dt=0.002, gamma=1.0, nu=1.0, lam=4.0, g=12.0, gdd=8.0, R=0.0),
 }
 N_IMAG, N_REAL, EVERY = 30, 24, 8           # records at 0, 8, 16, 24 (and 30 in imag time)
 
