@@ -72,8 +72,16 @@ struct Tiles {
   static constexpr int TC = S == 1 ? 8 : TC0;
   static constexpr int PC = kThreads / TC;
   // columns per tile of the z convolution: 16, or 8 when a 16-column tile would take more
-  // than GP_TV_SPLIT_BYTES of LDS (more resident blocks per CU)
-  static constexpr int TV = ((size_t)N * 17 * 2 * sizeof(T) > (size_t)GP_TV_SPLIT_BYTES) ? 8 : 16;
+  // than GP_TV_SPLIT_BYTES of LDS (more resident blocks per CU).  256-point columns are
+  // always 16 per tile: each thread keeps 16 points in registers (two 16-point stages
+  // around one LDS exchange per direction).  In FP64 (CONV_SPLIT) the exchange moves the
+  // real parts and then the imaginary parts through one real-valued buffer: 38.9 KB of
+  // LDS instead of 73.7 KB, so that 16-column tiles (256-byte row runs) keep three
+  // blocks per CU (registers bound them there) instead of two.
+  static constexpr bool CONV_REG = (N == 256);
+  static constexpr bool CONV_SPLIT = CONV_REG && sizeof(T) == 8;
+  static constexpr int TV =
+      (CONV_REG || (size_t)N * 17 * 2 * sizeof(T) <= (size_t)GP_TV_SPLIT_BYTES) ? 16 : 8;
   // contiguous lines per block of the line FFT passes
   static constexpr int LB0 = (GP_LB_POINTS / N) < 1 ? 1 : (GP_LB_POINTS / N);
   static constexpr int LB = S == 1 ? ((2 * GP_LB_POINTS / N) < 1 ? 1 : (2 * GP_LB_POINTS / N))
@@ -192,7 +200,9 @@ constexpr size_t lds_bytes() {
     return Tiles<T, N>::FFT16 ? a16(16 * (N + N / 16) * C) + a16(N * C)
                               : a16(LB * (N + 1) * C) + a16(N * C);
   if (PASS == P_CONV_LINE) return a16(LB * (N + 1) * C) + a16(N * C);
-  if (PASS == P_CONV_COL) return a16(N * (Tiles<T, N>::TV + 1) * C) + a16(N * C);
+  if (PASS == P_CONV_COL)
+    return a16(N * (Tiles<T, N>::TV + 1) * (Tiles<T, N>::CONV_SPLIT ? sizeof(T) : C)) +
+           a16(N * C);
   if (PASS == P_C2R_STEP) return X::mx(X::mx(X::Z, X::PS), X::RED8) + X::W + X::MT;
   if (PASS == P_ADJ_X) return X::Z + X::PS + X::W + X::MT + X::RED;
   if (PASS == P_C2R_OBS) return X::mx(X::Z, X::RED8) + X::W;
@@ -491,6 +501,35 @@ __device__ __forceinline__ void conv_line_body(cpx<T>* __restrict__ data,
 }
 
 // ------------------------------------------------------------------ conv_col
+// The LDS exchange of the register path: register m of thread (column c, group g) is
+// row g R + m of its column on the way in and row g + R m on the way out.  SPLIT sends
+// the real parts and then the imaginary parts through one real-valued buffer (half the
+// LDS, two more barriers).  The caller fences earlier reads of the buffer.
+template <typename T, int R, int RS, bool SPLIT>
+__device__ __forceinline__ void col_exchange(cpx<T> (&v)[R], char* buf, int c, int g) {
+  if constexpr (SPLIT) {
+    T* Br = reinterpret_cast<T*>(buf);
+#pragma unroll
+    for (int m = 0; m < R; ++m) Br[(g * R + m) * RS + c] = v[m].re;
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[m].re = Br[(g + R * m) * RS + c];
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < R; ++m) Br[(g * R + m) * RS + c] = v[m].im;
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[m].im = Br[(g + R * m) * RS + c];
+  } else {
+    cpx<T>* B = reinterpret_cast<cpx<T>*>(buf);
+#pragma unroll
+    for (int m = 0; m < R; ++m) B[(g * R + m) * RS + c] = v[m];
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[m] = B[(g + R * m) * RS + c];
+  }
+}
+
 // 3D z pass on the spectrum: lines along k2 (stride n1) inside each kx plane; a tile is
 // TC consecutive k1 of one kx plane.  tiles: ceil(n1/TC) * H.
 template <typename T, int N2>
@@ -500,10 +539,12 @@ __device__ __forceinline__ void conv_col_body(cpx<T>* __restrict__ spec,
                                               const cpx<T>* __restrict__ tw2, int n1, int bid,
                                               char* lds) {
   constexpr int TC = Tiles<T, N2>::TV, RS = TC + 1;
+  constexpr bool SPLIT = Tiles<T, N2>::CONV_SPLIT;
   using IT = Iters<N2 * TC>;
   Carve cv{lds};
-  cpx<T>* B = cv.take<cpx<T>>(N2 * RS);
+  char* buf = cv.take<char>(N2 * RS * (SPLIT ? sizeof(T) : sizeof(cpx<T>)));
   cpx<T>* W = cv.take<cpx<T>>(N2);
+  cpx<T>* B = reinterpret_cast<cpx<T>*>(buf);
   const int tid = thread_idx();
   const int nt = (n1 + TC - 1) / TC;
   const int kx = bid / nt;
@@ -512,6 +553,19 @@ __device__ __forceinline__ void conv_col_body(cpx<T>* __restrict__ spec,
   // the kernel table holds the quadrant k1 <= n1/2, k2 <= N2/2 (U is even in both)
   const int H1 = n1 / 2 + 1;
   const T* kq = ktab + (size_t)kx * (N2 / 2 + 1) * H1;
+  using FFT = LdsFFT<T, N2, TC, 1, RS, true>;
+  constexpr int R = IT::N;
+  constexpr bool REG = FFT::P.n == 2 && FFT::P.r[0] == R && FFT::P.r[1] == R &&
+                      kThreads / TC == R && IT::N * kThreads == N2 * TC;
+  static_assert(REG || !SPLIT, "the split exchange exists only on the register path");
+  // kernel value of element `it` of this thread (row u / TC, column u % TC)
+  auto kernel_value = [&](int it) -> T {
+    const int u = tid + it * kThreads;
+    const int c = u % TC, r = u / TC;
+    const int k1 = c0 + c;
+    const int k1r = min(k1, n1 - k1), k2r = min(r, N2 - r);
+    return (IT::valid(u) && k1 < n1) ? at32(kq, (unsigned)(k2r * H1 + k1r)) : (T)0;
+  };
   cpx<T> v[IT::N];
   T kv[IT::N];
 #pragma unroll
@@ -519,11 +573,8 @@ __device__ __forceinline__ void conv_col_body(cpx<T>* __restrict__ spec,
     const int u = tid + it * kThreads;
     const int c = u % TC, r = u / TC;
     const bool in = IT::valid(u) && c0 + c < n1;
-    const unsigned g = (unsigned)(r * n1 + c);
-    const int k1 = c0 + c;
-    const int k1r = min(k1, n1 - k1), k2r = min(r, N2 - r);
-    v[it] = in ? at32(spec + plane + c0, g) : cpx<T>{0, 0};
-    kv[it] = in ? at32(kq, (unsigned)(k2r * H1 + k1r)) : (T)0;
+    v[it] = in ? at32(spec + plane + c0, (unsigned)(r * n1 + c)) : cpx<T>{0, 0};
+    kv[it] = kernel_value(it);
   }
   for (int i = tid; i < N2; i += kThreads) W[i] = tw2[i];
   {
@@ -532,10 +583,7 @@ __device__ __forceinline__ void conv_col_body(cpx<T>* __restrict__ spec,
 #pragma unroll
     for (int it = 0; it < IT::N; ++it) kv[it] *= s2;
   }
-  using FFT = LdsFFT<T, N2, TC, 1, RS, true>;
-  constexpr int R = IT::N;
-  if constexpr (FFT::P.n == 2 && FFT::P.r[0] == R && FFT::P.r[1] == R && kThreads / TC == R &&
-                IT::N * kThreads == N2 * TC) {
+  if constexpr (REG) {
     // N2 = R * R with R points per thread at stride R (rows g + R m of column c): the
     // first forward stage works on the loaded registers, the second leaves spectrum
     // index g + R m in register m, where the kernel multiply and the first inverse stage
@@ -543,27 +591,17 @@ __device__ __forceinline__ void conv_col_body(cpx<T>* __restrict__ spec,
     // Two LDS exchanges per tile.
     const int c = tid % TC, g = tid / TC;
     dft<T, R, false>(v);
+    col_exchange<T, R, RS, SPLIT>(v, buf, c, g);
 #pragma unroll
-    for (int m = 0; m < R; ++m) B[(g * R + m) * RS + c] = v[m];
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < R; ++m) {
-      const cpx<T> e = B[(g + R * m) * RS + c];
-      v[m] = (m == 0) ? e : e * W[g * m];
-    }
+    for (int m = 1; m < R; ++m) v[m] = v[m] * W[g * m];
     dft<T, R, false>(v);
 #pragma unroll
     for (int m = 0; m < R; ++m) v[m] = scl(v[m], kv[m]);
     dft<T, R, true>(v);
     __syncthreads();  // every forward read of the buffer is done
+    col_exchange<T, R, RS, SPLIT>(v, buf, c, g);
 #pragma unroll
-    for (int m = 0; m < R; ++m) B[(g * R + m) * RS + c] = v[m];
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < R; ++m) {
-      const cpx<T> e = B[(g + R * m) * RS + c];
-      v[m] = (m == 0) ? e : e * conjg(W[g * m]);
-    }
+    for (int m = 1; m < R; ++m) v[m] = v[m] * conjg(W[g * m]);
     dft<T, R, true>(v);
 #pragma unroll
     for (int m = 0; m < R; ++m)
