@@ -29,10 +29,13 @@ CASES = {
                        gamma=1.0, nu=4.0, lam=2.5, g=20.0, gdd=15.0, R=0.0),
     "2dxy_120x96": dict(geom="2dxy", nx=120, ny=96, nz=1, dx=0.15, dy=0.15, dz=1.0, dt=0.001,
                         gamma=1.0, nu=1.2, lam=4.0, g=40.0, gdd=20.0, R=0.0),
-    # 256-point z lines: the FP32 z convolution runs as two 16-point stages held in
-    # registers; ny = 20 leaves a ragged 4-column tile
+    # 256-point z lines: the z convolution runs as two 16-point stages held in registers
+    # (FP64: real and imaginary parts exchanged in turn); ny = 20 leaves a ragged
+    # 4-column tile, ny = 10 a single tile of 10 of its 16 columns
     "3d_12x20x256": dict(geom="3d", nx=12, ny=20, nz=256, dx=0.5, dy=0.45, dz=0.04,
                          dt=0.0005, gamma=1.0, nu=1.0, lam=1.0, g=15.0, gdd=6.0, R=2.0),
+    "3d_16x10x256": dict(geom="3d", nx=16, ny=10, nz=256, dx=0.5, dy=0.55, dz=0.04,
+                         dt=0.0005, gamma=1.0, nu=1.2, lam=1.0, g=12.0, gdd=5.0, R=2.2),
     # 256-point y lines: the FP32 y FFT runs 16 x 16 with one LDS exchange; 7 x 20 = 140
     # lines leave a ragged last block of 16
     "3d_12x256x20": dict(geom="3d", nx=12, ny=256, nz=20, dx=0.5, dy=0.04, dz=0.45,
