@@ -74,6 +74,7 @@ struct Layout {
   size_t npts, nspec, nktab;  // grid points, half-spectrum values, kernel-table values
   size_t esz;           // bytes of one real value
   int nb_x, nb_nl, nb_col, nb_colobs;
+  int nb_r2c;           // tiles of the single-grid R2C pass (nb_x unless its tiles are wider)
   // axes without a compile-time specialisation run the run-time-length passes; gscr: their
   // one-thread-per-line sweeps need a grid of scratch values (o_gscr)
   bool generic, gscr;
@@ -131,6 +132,7 @@ gp_status validate(const gp_params* p) {
 }
 
 int tj_of(bool fp64, int n) { return fp64 ? Launch<double>::tj(n) : Launch<float>::tj(n); }
+int tjw_of(bool fp64, int n) { return fp64 ? Launch<double>::tjw(n) : Launch<float>::tjw(n); }
 int tc_of(bool fp64, int n) { return fp64 ? Launch<double>::tc(n) : Launch<float>::tc(n); }
 int tv_of(bool fp64, int n) { return fp64 ? Launch<double>::tv(n) : Launch<float>::tv(n); }
 
@@ -186,6 +188,7 @@ Layout make_layout(const gp_params* p, unsigned host = 0) {
     L.nb_x = fp64 ? GLaunch<double>::x_blocks(L.n0, L.n1, L.n2)
                   : GLaunch<float>::x_blocks(L.n0, L.n1, L.n2);
     if (L.lx) L.nb_x = GLaunch<float>::lx_blocks(L.lxg);
+    L.nb_r2c = L.nb_x;
     L.nb_nl = fp64 ? GLaunch<double>::nl_blocks(L.n0, L.n1, L.n2)
                    : GLaunch<float>::nl_blocks(L.n0, L.n1, L.n2);
     // blocks of the last sweep (z in 3D, y in 2D), which the z observe shares
@@ -207,9 +210,10 @@ Layout make_layout(const gp_params* p, unsigned host = 0) {
       L.nb_col = fp64 ? GLaunch<double>::seg_blocks(L.lg[1].sn, L.n0 * L.lg[1].nseg, true)
                       : GLaunch<float>::seg_blocks(L.lg[1].sn, L.n0 * L.lg[1].nseg, true);
   } else {
-    const int tj = tj_of(fp64, L.n0);
+    const int tj = tj_of(fp64, L.n0), tjw = tjw_of(fp64, L.n0);
     L.nb_x = ((L.n1 + tj - 1) / tj) * L.n2;
     L.nb_nl = L.nb_x;   // the x pass writes both
+    L.nb_r2c = ((L.n1 + tjw - 1) / tjw) * L.n2;
     if (p->geom == GP_3D) {
       const int tcz = tc_of(fp64, L.n2);
       L.nb_col = ((L.n0 + tcz - 1) / tcz) * L.n1;   // z sweep / z observe
@@ -410,7 +414,7 @@ StepScalars step_scalars(const gp_ctx* c) {
 FinArgs fin_args(const gp_ctx* c, int sel) {
   FinArgs a{};
   a.p_x = c->at<double>(c->L.o_px[sel]);
-  a.nb_x = c->L.nb_x;
+  a.nb_x = c->L.nb_r2c;
   a.p_nl = c->at<double>(c->L.o_pnl);
   a.nb_nl = c->L.nb_nl;
   a.p_col = c->at<double>(c->L.o_pcol);
@@ -431,7 +435,7 @@ FinArgs fin_args(const gp_ctx* c, int sel) {
   a.ring_cap = kRingCap;
   a.obs = c->at<double>(c->L.o_obs);
   // many partials: a first stage of up to kStageMax blocks sums slices of ~512 values
-  const long long nvals = 2LL * c->L.nb_x + 7LL * c->L.nb_nl + 2LL * c->L.nb_col;
+  const long long nvals = 2LL * c->L.nb_r2c + 7LL * c->L.nb_nl + 2LL * c->L.nb_col;
   a.stage = c->at<double>(c->L.o_stage);
   a.nstage = nvals > kStageThreshold
                  ? (int)std::min<long long>(kStageMax, (nvals + kStageSlice - 1) / kStageSlice)
@@ -694,11 +698,11 @@ struct Passes {
     const Layout& L = c->L;
     double* px = c->at<double>(L.o_px[c->px_sel]);
     if (fold) {
-      GP_HIP(Launch<T>::r2c_x_fin(L.n0, L.nb_x, c->st, src, spec(c), tw(c, 0), px, L.n1, L.n2,
+      GP_HIP(Launch<T>::r2c_x_fin(L.n0, L.nb_r2c, c->st, src, spec(c), tw(c, 0), px, L.n1, L.n2,
                                   *fold, fin_mode, fold->nstage > 0 ? fold->nstage : 1));
     } else {
       GP_PASS(c, GP_PASS_R2C_X,
-              Launch<T>::r2c_x(L.n0, L.nb_x, c->st, src, spec(c), tw(c, 0), px, L.n1, L.n2));
+              Launch<T>::r2c_x(L.n0, L.nb_r2c, c->st, src, spec(c), tw(c, 0), px, L.n1, L.n2));
     }
     return spectrum_passes(c, scale, fold && fold->nstage > 0 ? fold : nullptr, fin_mode);
   }
@@ -847,7 +851,7 @@ struct Passes {
     const int tcy = tc_of(c->fp64, L.n1);
     switch (pass) {
       case GP_PASS_R2C_X:
-        return dev(Launch<T>::r2c_x(L.n0, L.nb_x, c->st, psi(c), spec(c),
+        return dev(Launch<T>::r2c_x(L.n0, L.nb_r2c, c->st, psi(c), spec(c),
                                     tw(c, 0), c->at<double>(L.o_px[c->px_sel]), L.n1, L.n2));
       case GP_PASS_C2R_NL_CNX:
         return dev(Launch<T>::c2r_nl_cnx(L.n0, MODE_REAL, L.nb_x, c->st, psi(c),

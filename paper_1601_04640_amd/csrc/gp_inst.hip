@@ -273,6 +273,17 @@ int Launch<T>::tj(int n) {
   return 0;
 }
 template <>
+int Launch<T>::tjw(int n) {
+  switch (n) {
+#define X(N) \
+  case N:    \
+    return Tiles<T, N>::TJW;
+    GP_FOR_SIZES(X)
+#undef X
+  }
+  return 0;
+}
+template <>
 int Launch<T>::tc(int n) {
   switch (n) {
 #define X(N) \

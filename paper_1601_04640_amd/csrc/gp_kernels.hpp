@@ -50,6 +50,9 @@ namespace gpdbec {
 #ifndef GP_TV_SPLIT_BYTES
 #define GP_TV_SPLIT_BYTES 65536
 #endif
+#ifndef GP_R2C_WIDE
+#define GP_R2C_WIDE 1
+#endif
 
 // S selects a tile-shape variant (the batched ensemble's autotuner chooses per pass and
 // size class; the single-grid passes use S = 0):
@@ -64,6 +67,9 @@ struct Tiles {
   // half the serial chunk of the CN solve, twice the tiles)
   static constexpr int TJ0 = (N >= GP_TJ_SPLIT_N) ? 8 : 16;
   static constexpr int TJ = S == 1 ? 8 : TJ0;
+  // x lines per tile of the single-grid R2C pass: FP64 256-point lines go 16 to a tile
+  // (spectrum rows written in 256-byte runs) where the other x passes keep 8
+  static constexpr int TJW = (GP_R2C_WIDE && sizeof(T) == 8 && N == 256 && S == 0) ? 16 : TJ;
   static constexpr int PX = kThreads / TJ;          // lanes per x line in the CN solve
   // columns per tile: 16, or 8 (32 lanes per line) when the 16-lane chunk would exceed
   // GP_TC_SPLIT_* elements
@@ -187,7 +193,7 @@ struct CT {
 
 // -------------------------------------------------------------------- LDS sizes
 enum : int { P_R2C = 0, P_R2C_REAL, P_FFT_LINE, P_CONV_LINE, P_CONV_COL, P_C2R_STEP, P_C2R_OBS,
-             P_CN_COL, P_ADJ_X, P_ADJ_FIN };
+             P_CN_COL, P_ADJ_X, P_ADJ_FIN, P_R2C_W };
 template <typename T, int N, int PASS, int S = 0>
 constexpr size_t lds_bytes() {
   using X = XT<T, N, S>;
@@ -195,6 +201,8 @@ constexpr size_t lds_bytes() {
   constexpr size_t C = sizeof(cpx<T>);
   constexpr int LB = Tiles<T, N, S>::LB, TC = Tiles<T, N, S>::TC;
   if (PASS == P_R2C) return X::Z + X::W + X::RED;
+  if (PASS == P_R2C_W)
+    return a16(Tiles<T, N, S>::TJW / 2 * X::LSZ * C) + X::W + X::RED;
   if (PASS == P_R2C_REAL) return X::Z + X::W;
   if (PASS == P_FFT_LINE)
     return Tiles<T, N>::FFT16 ? a16(16 * (N + N / 16) * C) + a16(N * C)
@@ -213,17 +221,20 @@ constexpr size_t lds_bytes() {
 
 // ================================================================ pass bodies
 // ---------------------------------------------------------------- r2c_x
-// tiles: ceil(n1/TJ) * n2.  Spectrum of the stored |psi|^2 (unscaled: the convolution
+// tiles: ceil(n1/TJ) * n2 (TJ = Tiles::TJW in the single-grid pass, Tiles::TJ in the
+// batched one).  Spectrum of the stored |psi|^2 (unscaled: the convolution
 // applies scale^2).  partials[bid*2 + {0,1}] = sum |dx psi|^2, sum |dy psi|^2 of the
 // stored psi (unscaled), the y difference reaching one line past the tile.
-template <typename T, int N0, int S = 0>
+// WIDE: the single-grid pass, with Tiles::TJW lines per tile.
+template <typename T, int N0, int S = 0, bool WIDE = false>
 __device__ __forceinline__ void r2c_x_body(const cpx<T>* __restrict__ psi,
                                            cpx<T>* __restrict__ spec,
                                            const cpx<T>* __restrict__ tw0,
                                            double* __restrict__ partials, int n1, int n2, int bid,
                                            char* lds) {
   using X = XT<T, N0, S>;
-  constexpr int TJ = X::TJ, NP = X::NP, H = X::H, LSZ = X::LSZ;
+  constexpr int TJ = WIDE ? Tiles<T, N0, S>::TJW : X::TJ, NP = TJ / 2, H = X::H,
+                LSZ = X::LSZ;
   using IT = Iters<TJ * N0>;
   Carve cv{lds};
   cpx<T>* Z = cv.take<cpx<T>>(NP * LSZ);
@@ -235,34 +246,67 @@ __device__ __forceinline__ void r2c_x_body(const cpx<T>* __restrict__ psi,
   const int j0 = (bid % nt1) * TJ;
   const cpx<T>* plane = psi + (size_t)k2 * n1 * N0;
   // all loads first: the point, its x neighbour and its y neighbour (mostly cache hits)
-  cpx<T> a[IT::N], bx[IT::N], by[IT::N];
-  if constexpr (N0 == kThreads && sizeof(T) == 8) {
+  constexpr bool LANE_X = N0 == kThreads && sizeof(T) == 8;
+  cpx<T> a[IT::N], bx[LANE_X ? 1 : IT::N], by[LANE_X ? 1 : IT::N];
+  // per-thread partials in T (at most 16 points), FP64 above
+  T ps[2] = {0, 0};
+  if constexpr (LANE_X) {
     // lane = x index, register it = line j0 + it: the y neighbour is the next register
     // (one halo line loaded past the tile), the x neighbour the next lane (a wave shift;
-    // the last lane of each wave loads its own).  In FP64 this frees the registers that
-    // held the neighbours (3 -> 4 waves per SIMD); FP32 is faster with the plain loads.
+    // the last lane of each wave loads its own, or reads it from LDS in 16-line tiles).
+    // In FP64 this frees the registers that held the neighbours (8-line tiles: 3 -> 4
+    // waves per SIMD); FP32 is faster with the plain loads.
     const cpx<T> z = {0, 0};
     const int i = tid;
     const bool last_lane = (tid & 63) == 63;
+    // 16-line tiles keep rows past the grid as loaded (clamped) and mask what they feed,
+    // and take the last lane's x neighbour from the next wave's first lane through LDS
+    // (the twiddle buffer, filled afterwards) instead of loading it again
+    constexpr bool EDGE_LDS = IT::N > 8;
 #pragma unroll
     for (int it = 0; it < IT::N; ++it) {
       const int j = j0 + it;
       const int jc = min(j, n1 - 1);
       const cpx<T> l0 = at32(plane, (unsigned)(jc * N0 + i));
-      a[it] = j < n1 ? l0 : z;
+      a[it] = (EDGE_LDS || j < n1) ? l0 : z;
     }
     const cpx<T> halo = at32(plane, (unsigned)(min(j0 + IT::N, n1 - 1) * N0 + i));
+    const int wv = tid >> 6;
+    if constexpr (EDGE_LDS) {
+      if ((tid & 63) == 0) {
+#pragma unroll
+        for (int it = 0; it < IT::N; ++it) W[wv * IT::N + it] = a[it];
+      }
+      __syncthreads();
+    }
 #pragma unroll
     for (int it = 0; it < IT::N; ++it) {
       const int j = j0 + it;
       const bool in = j < n1;
       // min(j + 1, n1 - 1): the next line if there is one, else the point itself
       const cpx<T> nxt = (it + 1 < IT::N) ? a[it + 1 < IT::N ? it + 1 : it] : halo;
-      by[it] = in ? csel(j + 1 <= n1 - 1, nxt, a[it]) : z;
+      const cpx<T> byv = in ? csel(j + 1 <= n1 - 1, nxt, a[it]) : z;
       const cpx<T> sh = dpp<DPP_WAVE_SHL1>(a[it]);
       cpx<T> nb = sh;
-      if (last_lane && i < N0 - 1) nb = at32(plane, (unsigned)(min(j, n1 - 1) * N0 + i + 1));
-      bx[it] = in ? csel(i < N0 - 1, nb, a[it]) : z;
+      if (last_lane && i < N0 - 1) {
+        // (rows past the grid are zeroed below whatever nb holds)
+        if constexpr (EDGE_LDS) nb = W[(wv + 1) * IT::N + it];
+        else nb = at32(plane, (unsigned)(min(j, n1 - 1) * N0 + i + 1));
+      }
+      const cpx<T> bxv = in ? csel(i < N0 - 1, nb, a[it]) : z;
+      // the differences, partial sums and density of register it (line it, point i),
+      // in the order of the general path below
+      const cpx<T> dx = bxv - a[it], dy = byv - a[it];
+      const T sx = dx.re * dx.re + dx.im * dx.im, sy = dy.re * dy.re + dy.im * dy.im;
+      const T n2v = a[it].re * a[it].re + a[it].im * a[it].im;
+      ps[0] += EDGE_LDS ? (in ? sx : (T)0) : sx;
+      ps[1] += EDGE_LDS ? (in ? sy : (T)0) : sy;
+      const T nv = EDGE_LDS ? (in ? n2v : (T)0) : n2v;
+      cpx<T>& zc = Z[(it >> 1) * LSZ + i];
+      if (it & 1) zc.im = nv;
+      else zc.re = nv;
+      // 16-line tiles: a scheduling fence between registers
+      if constexpr (EDGE_LDS) __builtin_amdgcn_sched_barrier(0);
     }
   } else {
 #pragma unroll
@@ -282,11 +326,10 @@ __device__ __forceinline__ void r2c_x_body(const cpx<T>* __restrict__ psi,
     by[it] = in ? l2 : z;
   }
   }
+  if constexpr (LANE_X && IT::N > 8) __syncthreads();  // the edge values are read
   for (int i = tid; i < N0; i += kThreads) W[i] = tw0[i];
-  // per-thread partials in T (at most 16 points), FP64 above
-  T ps[2] = {0, 0};
 #pragma unroll
-  for (int it = 0; it < IT::N; ++it) {
+  for (int it = 0; it < (LANE_X ? 0 : IT::N); ++it) {
     const int u = tid + it * kThreads;
     if (!IT::valid(u)) continue;
     const int jl = u / N0, i = u % N0;
@@ -1017,8 +1060,9 @@ __global__ __launch_bounds__(kThreads) void k_r2c_x(const cpx<T>* __restrict__ p
                                                     cpx<T>* __restrict__ spec,
                                                     const cpx<T>* __restrict__ tw0,
                                                     double* __restrict__ partials, int n1, int n2) {
-  GP_LDS(T, N0, P_R2C);
-  r2c_x_body<T, N0>(psi, spec, tw0, partials, n1, n2, xcd_tile(blockIdx.x, gridDim.x), lds);
+  GP_LDS(T, N0, P_R2C_W);
+  r2c_x_body<T, N0, 0, true>(psi, spec, tw0, partials, n1, n2, xcd_tile(blockIdx.x, gridDim.x),
+                             lds);
 }
 
 // The x R2C of a step with the previous step's finalisation folded in: that finalisation
@@ -1034,7 +1078,7 @@ __global__ __launch_bounds__(kThreads) void k_r2c_x_fin(const cpx<T>* __restrict
                                                         double* __restrict__ partials, int n1,
                                                         int n2, FinArgs fa, int nfin,
                                                         int nlead) {
-  GP_LDS(T, N0, P_R2C);
+  GP_LDS(T, N0, P_R2C_W);
   const int b = blockIdx.x;
   if (b < nlead) {
     if (b < nfin) {
@@ -1043,8 +1087,8 @@ __global__ __launch_bounds__(kThreads) void k_r2c_x_fin(const cpx<T>* __restrict
     }
     return;
   }
-  r2c_x_body<T, N0>(psi, spec, tw0, partials, n1, n2, xcd_tile(b - nlead, gridDim.x - nlead),
-                    lds);
+  r2c_x_body<T, N0, 0, true>(psi, spec, tw0, partials, n1, n2,
+                             xcd_tile(b - nlead, gridDim.x - nlead), lds);
 }
 
 template <typename T, int N0>

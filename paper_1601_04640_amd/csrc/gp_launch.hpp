@@ -22,6 +22,7 @@ template <typename T>
 struct Launch {
   // tile geometry of the pass kernels for line length n
   static int tj(int n);  // x lines per block
+  static int tjw(int n); // x lines per block of the single-grid R2C pass
   static int tc(int n);  // columns per block (strided passes)
   static int tv(int n);  // columns per block (z convolution)
   static int lb(int n);  // contiguous lines per block
@@ -66,6 +67,7 @@ struct Launch {
 // The members are defined (explicitly specialised) per precision in gp_inst.hip.
 #define GP_DECLARE_LAUNCH(T)                                                                  \
   template <> int Launch<T>::tj(int);                                                         \
+  template <> int Launch<T>::tjw(int);                                                        \
   template <> int Launch<T>::tc(int);                                                         \
   template <> int Launch<T>::tv(int);                                                         \
   template <> int Launch<T>::lb(int);                                                         \
