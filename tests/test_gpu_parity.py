@@ -36,6 +36,10 @@ CASES = {
                          dt=0.0005, gamma=1.0, nu=1.0, lam=1.0, g=15.0, gdd=6.0, R=2.0),
     "3d_16x10x256": dict(geom="3d", nx=16, ny=10, nz=256, dx=0.5, dy=0.55, dz=0.04,
                          dt=0.0005, gamma=1.0, nu=1.2, lam=1.0, g=12.0, gdd=5.0, R=2.2),
+    # 256-point x lines: FP64 R2C tiles of 16 lines (ny = 20: one full, one of 4), with
+    # their own count of x-difference partials in the energy
+    "3d_256x20x12": dict(geom="3d", nx=256, ny=20, nz=12, dx=0.05, dy=0.5, dz=0.55,
+                         dt=0.0005, gamma=1.0, nu=1.0, lam=1.2, g=15.0, gdd=6.0, R=2.0),
     # 256-point y lines: the FP32 y FFT runs 16 x 16 with one LDS exchange; 7 x 20 = 140
     # lines leave a ragged last block of 16
     "3d_12x256x20": dict(geom="3d", nx=12, ny=256, nz=20, dx=0.5, dy=0.04, dz=0.45,
